@@ -1,0 +1,244 @@
+/*
+ * fvx -- repeated-block finite-volume operators as sparse-times-multivector
+ * products on MI355X (gfx950).
+ *
+ * The operators follow the staggered symmetry-preserving finite-volume
+ * discretisation of Section 3 (Eq. 9): the integrated divergence M, the face
+ * volumes Omega_s, the gradient G = -Omega_s^{-1} M^T and the Laplacian
+ * L = M G.  A 2D base mesh is extruded into k planes.  The 3D Laplacian then
+ * has the repeated-block form  L = I_k (x) A_b + C  (Section 2, Eq. 1, and the
+ * k stacked systems of Section 3.1, Eq. 10): one base block A_b, identical on
+ * every plane, plus C, the faces between neighbouring planes (periodic along
+ * the repeated direction) when the planes are coupled.  Every product with
+ * these operators is one sparse-times-multivector product (SpMM, Algorithm 1)
+ * over the k columns.
+ *
+ * CONVENTIONS
+ *  - Every call returns an int status: 0 = FVX_OK, > 0 = warning, < 0 = error
+ *    (see fvx_status).  No call aborts, exits or throws.  The text of the last
+ *    error on the calling thread is returned by fvx_last_error().
+ *  - "host" pointers point to CPU memory, "device" pointers to GPU memory on
+ *    the current HIP device.  The caller owns all memory it passes in.
+ *  - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *    Operator applications are asynchronous on that stream.
+ *  - Multivectors are row-major "array of structures" (the AoS layout of
+ *    Algorithm 1): row r holds the k values of that cell (or face) for the k
+ *    planes contiguously, at elements [r*ld, r*ld + k).  ld >= k is fixed per
+ *    operator (fvx_op_shape); columns k..ld-1 are padding, never read for
+ *    results and never written.  Base pointers must be 16-byte aligned.
+ *  - Cell vectors have n_b rows; in-plane face vectors have F_b rows; the
+ *    faces between planes (plane l to plane (l+1) mod k) form a cell-shaped
+ *    vector with n_b rows whose column l is the face above plane l.
+ *  - Plane-major vectors (the stacked vector of Section 2) hold cell c of
+ *    plane l at l*n + c; fvx_pack / fvx_unpack convert.
+ */
+#ifndef FVX_H
+#define FVX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Status codes, precisions, options                                   */
+/* ------------------------------------------------------------------ */
+typedef enum fvx_status {
+    FVX_OK = 0,
+    FVX_NOT_CONVERGED = 1,   /* warning: X holds the last iterate, stats are filled */
+    FVX_E_ARG = -1,          /* null pointer, size or enum out of range, misaligned */
+    FVX_E_MESH = -2,         /* mesh index out of range, non-positive area/length/distance */
+    FVX_E_NOMEM = -3,        /* caller buffer smaller than the size query returned */
+    FVX_E_HIP = -4,          /* a HIP runtime call failed (text in fvx_last_error) */
+    FVX_E_BREAKDOWN = -5,    /* CG breakdown: p.Ap <= 0 with nonzero residual, or non-finite */
+    FVX_E_NONFINITE = -6,    /* NaN/Inf in the right-hand side or initial guess */
+    FVX_E_UNSUPPORTED = -7   /* valid request this build does not provide */
+} fvx_status;
+
+enum { FVX_F64 = 0, FVX_F32 = 1, FVX_MIXED = 2 };
+enum { FVX_COUPLING_NONE = 0, FVX_COUPLING_PERIODIC_Z = 1 };
+enum { FVX_WALL_NEUMANN = 0, FVX_WALL_DIRICHLET = 1 };
+enum { FVX_GUESS_ZERO = 0, FVX_GUESS_GIVEN = 1 };
+
+typedef struct fvx_mesh fvx_mesh;   /* host-side base mesh (face graph) */
+typedef struct fvx_op fvx_op;       /* operator: base block on the device + launch tiles */
+
+/* Returns a static string naming a status code. */
+const char *fvx_status_str(int status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *fvx_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int fvx_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Base meshes (host).  A base mesh is a 2D finite-volume face graph:  */
+/* cells with an area, interior faces with their two cells (normal     */
+/* from c1 to c2), length and centre-to-centre distance, and wall      */
+/* faces with their cell, length and centre-to-wall distance.          */
+/* ------------------------------------------------------------------ */
+
+/* Structured base: nx uniform cells on [x0, x0+Lx]; ny cells on [y0, y1]
+ * clustered towards both ends by y_j = y0 + (y1-y0)(1 + tanh(s(2j/ny-1))/tanh s)/2
+ * (s = stretch; s = 0 is uniform), the hyperbolic-tangent refinement of the
+ * channel case (Section 4.1).  Non-periodic sides are walls.  Cell (i, j) is
+ * c = j*nx + i.  Interior faces are numbered x-normal faces first (j outer, i
+ * inner, face between (i, j) and (i+1 mod nx, j)), then y-normal faces (j
+ * outer, i inner, face between (i, j) and (i, j+1 mod ny)).
+ * Errors: FVX_E_ARG for nx, ny < 1 or an empty extent. */
+int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y1,
+                       double stretch, int periodic_x, int periodic_y, fvx_mesh **out);
+
+/* Triangle base (cells = triangles, e.g. a Delaunay mesh around a body).
+ * xy: host [n_pts][2]; tri: host [n_tri][3] vertex indices.  Cell area and
+ * centroid from the vertices; face length = edge length; face distance =
+ * |n . (centroid_c2 - centroid_c1)| with n the unit edge normal (two-point
+ * flux).  Interior faces are the edges shared by two triangles, in ascending
+ * order of (lower vertex, higher vertex), with c1 the lower triangle index;
+ * edges of one triangle are walls.  Errors: FVX_E_MESH for a vertex index out
+ * of range, a degenerate triangle or an edge shared by more than two. */
+int fvx_mesh_triangles(int n_pts, const double *xy, int n_tri, const int32_t *tri,
+                       fvx_mesh **out);
+
+/* General face graph.  All arrays are host memory and are copied.
+ * area [n_cells] > 0; c1, c2 [n_faces] in [0, n_cells); len, dist > 0;
+ * wcell [n_walls], wlen, wdist > 0 (may be NULL when n_walls == 0).
+ * cx, cy [n_cells] optional cell centres (NULL allowed). */
+int fvx_mesh_from_faces(int n_cells, const double *area, const double *cx, const double *cy,
+                        int n_faces, const int32_t *c1, const int32_t *c2,
+                        const double *len, const double *dist,
+                        int n_walls, const int32_t *wcell, const double *wlen,
+                        const double *wdist, fvx_mesh **out);
+
+/* Sizes of a mesh (any pointer may be NULL). */
+int fvx_mesh_info(const fvx_mesh *m, int64_t *n_cells, int64_t *n_faces, int64_t *n_walls);
+/* Copies the cell centres (host arrays of n_cells). */
+int fvx_mesh_centroids(const fvx_mesh *m, double *cx, double *cy);
+/* Copies the face graph (host arrays sized by fvx_mesh_info; NULL skips). */
+int fvx_mesh_faces(const fvx_mesh *m, double *area, int32_t *c1, int32_t *c2,
+                   double *len, double *dist);
+int fvx_mesh_destroy(fvx_mesh *m);
+
+/* ------------------------------------------------------------------ */
+/* Operators                                                           */
+/* ------------------------------------------------------------------ */
+typedef struct fvx_op_desc {
+    int32_t k;          /* number of repeated planes (columns), >= 1 */
+    int32_t coupling;   /* FVX_COUPLING_NONE: k independent systems (Section 3.1);
+                           FVX_COUPLING_PERIODIC_Z: faces between planes l and
+                           l+1 mod k (area = cell area, distance = dz) */
+    double dz;          /* plane spacing (> 0); in-plane face area = len * dz */
+    int32_t wall_bc;    /* FVX_WALL_NEUMANN: zero-flux walls (L singular, null
+                           space = constants); FVX_WALL_DIRICHLET: p = 0 on walls */
+    int32_t with_f32;   /* nonzero: also store FP32 copies (FVX_F32 and FVX_MIXED) */
+    int32_t reserved[4];
+} fvx_op_desc;
+
+/* Launch tile of the SpMM kernels: vec = elements per lane per load (FP64:
+ * 1 or 2, FP32: 1, 2 or 4); lanes_per_row = lanes sharing one matrix row
+ * (power of two, 1..64); block = threads per workgroup (64..1024, multiple of
+ * 64); xcd_remap = nonzero maps consecutive row tiles to the same XCD. */
+typedef struct fvx_tile {
+    int32_t vec, lanes_per_row, block, xcd_remap;
+} fvx_tile;
+
+/* Device bytes the operator needs (query before fvx_op_create). */
+int fvx_op_bytes(const fvx_mesh *m, const fvx_op_desc *d, size_t *bytes);
+
+/* Builds the operator.  dev_mem: device buffer of at least fvx_op_bytes bytes,
+ * owned by the caller and kept alive until fvx_op_destroy.  The host builds
+ * A_b, the plane-coupling weights, M_b and G_b once (their storage does not
+ * grow with k) and copies them on `stream`; the call returns after the copy.
+ * The op is immutable afterwards except for its tiles (fvx_op_set_tile). */
+int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t bytes,
+                  void *stream, fvx_op **out);
+int fvx_op_destroy(fvx_op *op);
+
+/* n_b cells, F_b in-plane faces, k planes, ld row stride of multivectors;
+ * nnz_b = nnz(A_b).  Any pointer may be NULL. */
+int fvx_op_shape(const fvx_op *op, int64_t *n_b, int64_t *F_b, int32_t *k, int32_t *ld,
+                 int64_t *nnz_b);
+/* 1 if L has the constant null space (solves project to zero mean). */
+int fvx_op_singular(const fvx_op *op);
+
+int fvx_op_get_tile(const fvx_op *op, int dtype, fvx_tile *tile);
+/* Sets the SpMM tile for one precision.  FVX_E_ARG if the tile is invalid
+ * for this operator (vec must divide ld, alignment, ranges above). */
+int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile);
+
+/* Laplacian SpMM (Algorithm 1 with the plane coupling):
+ *   Y[i][l] = s_l ( sum_j A_b[i][j] X[j][l] + w_i (X[i][l+1 mod k] + X[i][l-1 mod k]) )
+ * dtype FVX_F64 (double X, Y) or FVX_F32 (float X, Y; needs with_f32).
+ * X, Y: device [n_b][ld], must not overlap.  colscale: device double [k], the
+ * per-column output scale c of Algorithm 1, or NULL (s_l = 1). */
+int fvx_lap(const fvx_op *op, int dtype, const void *X, void *Y, const double *colscale,
+            void *stream);
+
+/* Divergence SpMM, integrated over cells (M u of Eq. 9a):
+ *   D[i][l] = sum_{faces f of i} (+-) len_f dz Uf[f][l] + A_i (Wz[i][l] - Wz[i][l-1 mod k])
+ * with + when i is the face's c1.  Uf: device [F_b][ld]; Wz: device [n_b][ld]
+ * (faces between planes; ignored and may be NULL when there are none);
+ * D: device [n_b][ld]. */
+int fvx_div(const fvx_op *op, int dtype, const void *Uf, const void *Wz, void *D, void *stream);
+
+/* Gradient SpMM, G = -Omega_s^{-1} M^T (Eq. 9b):
+ *   Gf[f][l] = (P[c2][l] - P[c1][l]) / dist_f,   Gz[i][l] = (P[i][l+1 mod k] - P[i][l]) / dz
+ * P: device [n_b][ld]; Gf: device [F_b][ld]; Gz: device [n_b][ld] (may be
+ * NULL when there are no faces between planes). */
+int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream);
+
+/* Plane-major <-> row-major conversion on the device.  n_rows = n_b or F_b.
+ * src/dst: device; pack reads [k][n_rows] and writes [n_rows][ld]. */
+int fvx_pack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream);
+int fvx_unpack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Poisson solve  L x = b  (CG on the SPD operator -L)                  */
+/* ------------------------------------------------------------------ */
+typedef struct fvx_solve_opts {
+    double rtol;          /* stop when ||b - L x|| <= rtol ||b|| (b after projection) */
+    int32_t max_iter;     /* CG iteration cap (inner iterations summed for MIXED) */
+    int32_t precision;    /* FVX_F64, or FVX_MIXED: FP32 SpMM and vectors inside CG,
+                             FP64 dot products and scalars, FP64 outer defect correction */
+    double inner_rtol;    /* MIXED: inner CG tolerance relative to the outer residual */
+    int32_t max_outer;    /* MIXED: cap on outer corrections */
+    int32_t guess;        /* FVX_GUESS_ZERO or FVX_GUESS_GIVEN (X holds x0) */
+    int32_t poll_every;   /* iterations between host reads of the device flag (>= 1) */
+    int32_t reserved[5];
+} fvx_solve_opts;
+
+typedef struct fvx_solve_stats {
+    int32_t status;       /* same as the return value */
+    int32_t iters;        /* CG iterations (max over columns when planes are independent) */
+    int32_t outer;        /* MIXED: outer corrections */
+    int32_t rhs_projected;/* 1 if b had a nonzero plain mean that was removed */
+    double relres_rec;    /* recursive residual / ||b|| at exit (max over columns) */
+    double relres_true;   /* ||b - L x|| / ||b|| recomputed in FP64 (max over columns) */
+    double r0_over_b;     /* ||b - L x0|| / ||b|| (max over columns) */
+    double bnorm;         /* ||b|| after projection (max over columns) */
+    double seconds;       /* wall time of the call */
+} fvx_solve_stats;
+
+/* Fills opts with defaults: rtol 1e-8, max_iter 100000, FP64, inner_rtol 1e-4,
+ * max_outer 50, zero guess, poll_every 64. */
+int fvx_solve_opts_default(fvx_solve_opts *opts);
+
+/* Device workspace bytes for fvx_poisson_solve. */
+int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *opts, size_t *bytes);
+
+/* Solves L x = b.  B, X: device double [n_b][ld].  With coupled planes the
+ * system is one CG with global scalars; with independent planes
+ * (FVX_COUPLING_NONE) each column runs its own CG (its own alpha, beta and
+ * stopping test) inside the shared SpMM, as k independent systems.  When L is
+ * singular, b is projected to zero plain mean (per column for independent
+ * planes) and x is returned with zero mean.  ws: device workspace of at least
+ * fvx_solve_bytes bytes.  Synchronises `stream` before returning.  Returns
+ * FVX_NOT_CONVERGED when the cap is hit, FVX_E_BREAKDOWN, FVX_E_NONFINITE. */
+int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *opts,
+                      void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVX_H */

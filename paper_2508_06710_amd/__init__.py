@@ -1,0 +1,258 @@
+"""Python binding of libfvx: repeated-block finite-volume operators on MI355X.
+
+Argument marshalling only.  Every operator application and solve runs in the
+HIP kernels of libfvx.so; torch supplies device memory and the current
+stream.  See include/fvx.h for the operations, layouts and error behaviour.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
+                   PERIODIC_Z, FvxError, SolveOpts, SolveStats, Tile, check, lib)
+
+__all__ = ["Mesh", "Operator", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
+           "NEUMANN", "DIRICHLET", "lib"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Mesh:
+    """A 2D finite-volume base mesh (host object)."""
+
+    def __init__(self, handle: C.c_void_p, keep=()):
+        self._h = handle
+        self._keep = keep
+
+    @classmethod
+    def cartesian(cls, nx, ny, x0=0.0, Lx=1.0, y0=0.0, y1=1.0, stretch=0.0, periodic_x=True,
+                  periodic_y=False):
+        h = C.c_void_p()
+        check(lib().fvx_mesh_cartesian(nx, ny, x0, Lx, y0, y1, stretch, int(periodic_x),
+                                       int(periodic_y), C.byref(h)), "fvx_mesh_cartesian")
+        return cls(h)
+
+    @classmethod
+    def from_spec(cls, spec):
+        """From an ``inputs.CartSpec`` or ``inputs.TriSpec``."""
+        if hasattr(spec, "triangles"):
+            return cls.triangles(spec.points, spec.triangles)
+        return cls.cartesian(spec.nx, spec.ny, spec.x0, spec.Lx, spec.y0, spec.y1, spec.stretch,
+                             spec.periodic_x, spec.periodic_y)
+
+    @classmethod
+    def triangles(cls, points, tris):
+        xy = np.ascontiguousarray(points, dtype=np.float64)
+        tri = np.ascontiguousarray(tris, dtype=np.int32)
+        h = C.c_void_p()
+        check(lib().fvx_mesh_triangles(len(xy), _np_ptr(xy), len(tri), _np_ptr(tri), C.byref(h)),
+              "fvx_mesh_triangles")
+        return cls(h)
+
+    @classmethod
+    def from_faces(cls, area, c1, c2, length, dist, wcell=None, wlen=None, wdist=None,
+                   cx=None, cy=None):
+        a = np.ascontiguousarray(area, np.float64)
+        f1, f2 = np.ascontiguousarray(c1, np.int32), np.ascontiguousarray(c2, np.int32)
+        ln, ds = np.ascontiguousarray(length, np.float64), np.ascontiguousarray(dist, np.float64)
+        nw = 0 if wcell is None else len(wcell)
+        wc = None if wcell is None else np.ascontiguousarray(wcell, np.int32)
+        wl = None if wlen is None else np.ascontiguousarray(wlen, np.float64)
+        wd = None if wdist is None else np.ascontiguousarray(wdist, np.float64)
+        cxa = None if cx is None else np.ascontiguousarray(cx, np.float64)
+        cya = None if cy is None else np.ascontiguousarray(cy, np.float64)
+        h = C.c_void_p()
+        check(lib().fvx_mesh_from_faces(len(a), _np_ptr(a), _np_ptr(cxa), _np_ptr(cya), len(f1),
+                                        _np_ptr(f1), _np_ptr(f2), _np_ptr(ln), _np_ptr(ds), nw,
+                                        _np_ptr(wc), _np_ptr(wl), _np_ptr(wd), C.byref(h)),
+              "fvx_mesh_from_faces")
+        return cls(h)
+
+    def info(self):
+        n = [C.c_int64() for _ in range(3)]
+        check(lib().fvx_mesh_info(self._h, *[C.byref(v) for v in n]), "fvx_mesh_info")
+        return tuple(v.value for v in n)
+
+    @property
+    def n_cells(self):
+        return self.info()[0]
+
+    @property
+    def n_faces(self):
+        return self.info()[1]
+
+    def centroids(self):
+        n = self.n_cells
+        cx, cy = np.zeros(n), np.zeros(n)
+        check(lib().fvx_mesh_centroids(self._h, _np_ptr(cx), _np_ptr(cy)), "fvx_mesh_centroids")
+        return cx, cy
+
+    def faces(self):
+        nc, nf, _ = self.info()
+        area = np.zeros(nc)
+        c1, c2 = np.zeros(nf, np.int32), np.zeros(nf, np.int32)
+        ln, ds = np.zeros(nf), np.zeros(nf)
+        check(lib().fvx_mesh_faces(self._h, _np_ptr(area), _np_ptr(c1), _np_ptr(c2), _np_ptr(ln),
+                                   _np_ptr(ds)), "fvx_mesh_faces")
+        return area, c1, c2, ln, ds
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib().fvx_mesh_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+
+_DT = {F64: "float64", F32: "float32"}
+
+
+class Operator:
+    """Repeated-block operator L = I_k (x) A_b + C (plus M_b, G_b) on the device."""
+
+    def __init__(self, mesh: Mesh, k: int, dz: float, coupling: int = PERIODIC_Z,
+                 wall_bc: int = NEUMANN, with_f32: bool = True, device=None, stream=None):
+        torch = _torch()
+        self.mesh = mesh
+        self.device = torch.device(device if device is not None else "cuda")
+        d = _lib.OpDesc()
+        d.k, d.coupling, d.dz, d.wall_bc, d.with_f32 = int(k), int(coupling), float(dz), int(wall_bc), int(with_f32)
+        self._desc = d
+        nbytes = C.c_size_t()
+        check(lib().fvx_op_bytes(mesh._h, C.byref(d), C.byref(nbytes)), "fvx_op_bytes")
+        self._mem = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(lib().fvx_op_create(mesh._h, C.byref(d), _ptr(self._mem), nbytes.value, _stream(stream),
+                                  C.byref(h)), "fvx_op_create")
+        self._h = h
+        nb, fb, kk, ld, nnz = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+        check(lib().fvx_op_shape(h, C.byref(nb), C.byref(fb), C.byref(kk), C.byref(ld), C.byref(nnz)),
+              "fvx_op_shape")
+        self.n_b, self.F_b, self.k, self.ld, self.nnz_b = nb.value, fb.value, kk.value, ld.value, nnz.value
+        self.coupling, self.dz, self.wall_bc = int(coupling), float(dz), int(wall_bc)
+        self.zfaces = coupling == PERIODIC_Z and k >= 2
+        self.singular = bool(lib().fvx_op_singular(h))
+        self.op_bytes = int(nbytes.value)
+        self._ws = {}
+
+    # ---- buffers -------------------------------------------------------
+    def empty(self, rows: int | None = None, dtype=F64):
+        torch = _torch()
+        n = self.n_b if rows is None else rows
+        return torch.empty((max(n, 1), self.ld), dtype=getattr(torch, _DT[dtype]), device=self.device)
+
+    def zeros(self, rows: int | None = None, dtype=F64):
+        t = self.empty(rows, dtype)
+        t.zero_()
+        return t
+
+    def to_rows(self, plane_major, rows: int | None = None, dtype=F64):
+        """Plane-major host or device vector [k * n] -> device [n][ld] (via fvx_pack)."""
+        torch = _torch()
+        n = self.n_b if rows is None else rows
+        src = torch.as_tensor(plane_major, dtype=getattr(torch, _DT[dtype])).to(self.device).contiguous()
+        dst = self.zeros(n, dtype)
+        check(lib().fvx_pack(self._h, dtype, n, _ptr(src), _ptr(dst), _stream()), "fvx_pack")
+        return dst
+
+    def to_planes(self, rows_t, rows: int | None = None, dtype=F64):
+        """Device [n][ld] -> plane-major numpy vector [k * n] (via fvx_unpack)."""
+        torch = _torch()
+        n = self.n_b if rows is None else rows
+        dst = torch.empty(self.k * n, dtype=getattr(torch, _DT[dtype]), device=self.device)
+        check(lib().fvx_unpack(self._h, dtype, n, _ptr(rows_t), _ptr(dst), _stream()), "fvx_unpack")
+        torch.cuda.synchronize(self.device)
+        return dst.cpu().numpy()
+
+    # ---- tiles ----------------------------------------------------------
+    def get_tile(self, dtype=F64):
+        t = Tile()
+        check(lib().fvx_op_get_tile(self._h, dtype, C.byref(t)), "fvx_op_get_tile")
+        return t.as_tuple()
+
+    def set_tile(self, vec, lanes_per_row, block=256, xcd_remap=1, dtype=F64):
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap))
+        check(lib().fvx_op_set_tile(self._h, dtype, C.byref(t)), "fvx_op_set_tile")
+
+    # ---- operators --------------------------------------------------------
+    def lap(self, X, Y=None, colscale=None, dtype=None, stream=None):
+        dt = dtype if dtype is not None else (F32 if str(X.dtype).endswith("float32") else F64)
+        Y = self.empty(dtype=dt) if Y is None else Y
+        check(lib().fvx_lap(self._h, dt, _ptr(X), _ptr(Y), _ptr(colscale), _stream(stream)), "fvx_lap")
+        return Y
+
+    def div(self, Uf, Wz=None, D=None, dtype=None, stream=None):
+        dt = dtype if dtype is not None else (F32 if str(Uf.dtype).endswith("float32") else F64)
+        D = self.empty(dtype=dt) if D is None else D
+        check(lib().fvx_div(self._h, dt, _ptr(Uf), _ptr(Wz), _ptr(D), _stream(stream)), "fvx_div")
+        return D
+
+    def grad(self, P, Gf=None, Gz=None, dtype=None, stream=None):
+        dt = dtype if dtype is not None else (F32 if str(P.dtype).endswith("float32") else F64)
+        Gf = self.empty(self.F_b, dt) if Gf is None else Gf
+        if Gz is None and self.zfaces:
+            Gz = self.empty(dtype=dt)
+        check(lib().fvx_grad(self._h, dt, _ptr(P), _ptr(Gf), _ptr(Gz), _stream(stream)), "fvx_grad")
+        return Gf, Gz
+
+    # ---- solves -----------------------------------------------------------
+    def solve_opts(self, rtol=1e-8, max_iter=100000, precision=F64, inner_rtol=1e-4, max_outer=50,
+                   guess=GUESS_ZERO, poll_every=64):
+        o = SolveOpts()
+        check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
+        o.rtol, o.max_iter, o.precision = float(rtol), int(max_iter), int(precision)
+        o.inner_rtol, o.max_outer, o.guess, o.poll_every = float(inner_rtol), int(max_outer), int(guess), int(poll_every)
+        return o
+
+    def workspace(self, opts):
+        torch = _torch()
+        nbytes = C.c_size_t()
+        check(lib().fvx_solve_bytes(self._h, C.byref(opts), C.byref(nbytes)), "fvx_solve_bytes")
+        key = int(opts.precision)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes.value:
+            ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def solve(self, B, X=None, stream=None, allow_not_converged=False, **kw):
+        """Solves L x = b (B, X: device [n_b][ld] float64).  Returns (X, stats dict)."""
+        opts = self.solve_opts(**kw)
+        if X is None:
+            X = self.zeros()
+        ws = self.workspace(opts)
+        st = SolveStats()
+        rc = lib().fvx_poisson_solve(self._h, _ptr(B), _ptr(X), C.byref(opts), _ptr(ws), ws.numel(),
+                                     C.byref(st), _stream(stream))
+        allow = (0, 1) if allow_not_converged else (0,)
+        check(rc, "fvx_poisson_solve", allow)
+        return X, st.as_dict()
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                lib().fvx_op_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None

@@ -1,0 +1,148 @@
+// Internal declarations shared by the host builder, the HIP kernels and the
+// C-ABI entry points of libfvx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fvx.h"
+
+// ---------------------------------------------------------------------------
+// Host-side objects behind the opaque handles
+// ---------------------------------------------------------------------------
+
+struct fvx_mesh {
+    int n_cells = 0, n_faces = 0, n_walls = 0;
+    std::vector<double> area, cx, cy;
+    std::vector<int32_t> c1, c2;
+    std::vector<double> len, dist;
+    std::vector<int32_t> wcell;
+    std::vector<double> wlen, wdist;
+};
+
+namespace fvx {
+
+// Device arrays of one precision.  All sizes are fixed by the base mesh; none
+// grows with the number of planes k.
+template <typename T>
+struct OpDev {
+    // Laplacian base block A_b: diagonal plus off-diagonal neighbours in
+    // column-major ELL ([W][n_b]: entry e of row i at e*n_b + i; padding
+    // entries point at the row itself with value 0).
+    const T *diag = nullptr;
+    const int32_t *ell_col = nullptr;
+    const T *ell_val = nullptr;
+    const T *w = nullptr;        // [n_b] plane-coupling weight area_i / dz
+    // Divergence M_b: cell -> face incidence, column-major ELL [Wd][n_b],
+    // coefficient +-len_f*dz (+ when the cell is the face's c1).
+    const int32_t *cf_face = nullptr;
+    const T *cf_coef = nullptr;
+    const T *area = nullptr;     // [n_b] cell area (flux through faces between planes)
+    // Gradient: per face its cells and 1/dist.
+    const int32_t *f_c1 = nullptr, *f_c2 = nullptr;
+    const T *f_invd = nullptr;
+    T inv_dz = 0;
+};
+
+}  // namespace fvx
+
+struct fvx_op {
+    int64_t n_b = 0, F_b = 0, nnz_b = 0;
+    int32_t k = 0, ld = 0, coupling = 0;
+    bool zfaces = false;    // faces between planes exist (periodic coupling, k >= 2)
+    bool singular = true;   // L has the constant null space
+    bool percol = false;    // columns are independent systems
+    double dz = 0;
+    int W = 0, Wd = 0;      // ELL widths (Laplacian off-diagonals, cell->face)
+    bool has_f32 = false;
+    int device = 0;
+    fvx::OpDev<double> d64;
+    fvx::OpDev<float> d32;
+    fvx_tile tile[2];
+};
+
+namespace fvx {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &s) : std::runtime_error(s), code(c) {}
+};
+
+void set_last_error(const std::string &s);
+
+// Runs f and converts exceptions into status codes; records the message.
+int guard(const std::function<int()> &f);
+
+#define FVX_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::fvx::Error(FVX_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FVX_REQUIRE(cond, code, msg)                     \
+    do {                                                 \
+        if (!(cond)) throw ::fvx::Error((code), (msg));  \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Row stride of multivectors for k planes: k itself when k <= 2 or a multiple
+// of 4, else k rounded up to a multiple of 4 (so 16-byte vector loads stay
+// aligned for both precisions).
+inline int32_t ld_for_k(int32_t k) { return (k <= 2 || k % 4 == 0) ? k : (k + 3) / 4 * 4; }
+
+fvx_tile default_tile(const fvx_op *op, int dtype);
+void check_tile(const fvx_op *op, int dtype, const fvx_tile &t);
+
+// ---------------------------------------------------------------------------
+// Launchers (spmm.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_lap(const fvx_op *op, const T *X, T *Y, const double *colscale, hipStream_t s);
+template <typename T>
+void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s);
+template <typename T>
+void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s);
+template <typename T>
+void launch_pack(const fvx_op *op, int64_t n_rows, const T *src, T *dst, bool to_rows, hipStream_t s);
+
+template <typename T>
+const OpDev<T> &dev(const fvx_op *op);
+template <>
+inline const OpDev<double> &dev<double>(const fvx_op *op) { return op->d64; }
+template <>
+inline const OpDev<float> &dev<float>(const fvx_op *op) { return op->d32; }
+
+template <typename T>
+inline int dtype_of();
+template <>
+inline int dtype_of<double>() { return FVX_F64; }
+template <>
+inline int dtype_of<float>() { return FVX_F32; }
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Number of thread blocks of a row-tiled launch: each block walks a contiguous
+// range of row tiles.  Blocks are capped so per-block reduction partials stay
+// small; plain SpMMs use a large cap.
+struct RowGrid {
+    int64_t n_rows;
+    int rows_per_tile;   // rows one block covers per step = block / lanes_per_row
+    int64_t tiles_per_block;
+    int n_blocks;
+};
+RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks);
+
+}  // namespace fvx

@@ -1,0 +1,141 @@
+// Device-side building blocks shared by the HIP translation units: vector
+// loads, the XCD-aware tile order, and the per-row SpMM bodies.
+#pragma once
+
+#include "common.h"
+
+namespace fvx {
+
+template <typename T, int V>
+using vec_t = T __attribute__((ext_vector_type(V)));
+
+template <typename T, int V>
+__device__ __forceinline__ vec_t<T, V> ldv(const T *p) {
+    return *reinterpret_cast<const vec_t<T, V> *>(p);
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid) {
+    if (valid >= V) {
+        *reinterpret_cast<vec_t<T, V> *>(p) = v;
+    } else {
+#pragma unroll
+        for (int t = 0; t < V; ++t)
+            if (t < valid) p[t] = v[t];
+    }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remapping hardware block b to a logical tile index so that the blocks
+// of one XCD take one contiguous range of rows keeps the neighbour rows a
+// block gathers in the L2 that already holds them.  A bijection on [0, n).
+__device__ __forceinline__ int64_t logical_block(int remap) {
+    const int b = blockIdx.x, n = gridDim.x;
+    if (!remap || n < 8) return b;
+    const int xcd = b & 7, local = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return xcd < r ? int64_t(xcd) * (q + 1) + local : int64_t(r) * (q + 1) + int64_t(xcd - r) * q + local;
+}
+
+// Values of the neighbouring planes of this lane's V columns, l-1 and l+1
+// (mod k), taken from the row-group lanes that hold them when all k columns
+// of the row sit in one pass of the group (lanes_per_row * V >= k).
+template <typename T, int V>
+struct PlaneNeighbours {
+    T left0;   // value of column c0 - 1 (mod k)
+    T rightV;  // value of column c0 + V (or column 0 past the last column)
+};
+
+template <typename T, int V>
+__device__ __forceinline__ PlaneNeighbours<T, V> plane_neighbours(const vec_t<T, V> &xo, int sub, int lpr, int k) {
+    const int last = (k - 1) / V;  // lane of the row group holding column k-1
+    const int src_r = sub == last ? 0 : sub + 1;
+    const int src_l = sub == 0 ? last : sub - 1;
+    const T prov_l = sub == last ? xo[(k - 1) % V] : xo[V - 1];
+    PlaneNeighbours<T, V> n;
+    n.rightV = __shfl(xo[0], src_r, lpr);
+    n.left0 = __shfl(prov_l, src_l, lpr);
+    return n;
+}
+
+// Column l-1 (mod k) and l+1 (mod k) of element t of this lane.
+template <typename T, int V>
+__device__ __forceinline__ T left_of(const vec_t<T, V> &xo, const PlaneNeighbours<T, V> &n, int t) {
+    return t > 0 ? xo[t > 0 ? t - 1 : 0] : n.left0;
+}
+template <typename T, int V>
+__device__ __forceinline__ T right_of(const vec_t<T, V> &xo, const PlaneNeighbours<T, V> &n, int t, int l,
+                                      int k) {
+    return (l == k - 1 || t + 1 >= V) ? n.rightV : xo[t + 1 < V ? t + 1 : 0];
+}
+
+// One row and one V-wide column chunk of the Laplacian SpMM:
+//   acc = diag_i x_i + sum_e a_ie x_{j(e)} + w_i (x_i[l+1] + x_i[l-1])
+// The row's matrix entries are loaded once and applied to all V columns of
+// the lane (and, across the lanes of the row group, to all k columns).
+// xo returns this row's own V values (used by fused dot products).
+template <typename T, int V, bool Z>
+__device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b,
+                                               int k, int ld, int W, int64_t row, int c0, int sub, int lpr,
+                                               bool single, vec_t<T, V> &xo) {
+    using vt = vec_t<T, V>;
+    xo = ldv<T, V>(X + row * ld + c0);
+    vt acc = A.diag[row] * xo;
+    for (int e = 0; e < W; ++e) {
+        const int64_t j = A.ell_col[e * n_b + row];
+        const T v = A.ell_val[e * n_b + row];
+        acc += v * ldv<T, V>(X + j * ld + c0);
+    }
+    if constexpr (Z) {
+        const T wr = A.w[row];
+        if (single) {
+            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, k);
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int l = c0 + t;
+                acc[t] += wr * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
+            }
+        } else {
+            const T *xr = X + row * ld;
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int l = c0 + t;
+                if (l < k) acc[t] += wr * (xr[l == 0 ? k - 1 : l - 1] + xr[l == k - 1 ? 0 : l + 1]);
+            }
+        }
+    }
+    return acc;
+}
+
+// Launch arguments of a row-tiled kernel (lanes_per_row lanes per row,
+// tiles of rows_per_tile rows, tiles_per_block consecutive tiles per block).
+template <typename T>
+struct RowArgs {
+    OpDev<T> A;
+    int64_t n_b, n_rows;
+    int k, ld, W, Wd, lpr, rows_per_tile, remap;
+    int64_t tiles_per_block;
+    int64_t F_b;
+};
+
+template <typename T>
+inline RowArgs<T> row_args(const fvx_op *op, int64_t n_rows, RowGrid &g, const fvx_tile &t,
+                           int max_blocks = 1 << 22) {
+    g = row_grid(n_rows, t, max_blocks);
+    RowArgs<T> a;
+    a.A = dev<T>(op);
+    a.n_b = op->n_b;
+    a.n_rows = n_rows;
+    a.k = op->k;
+    a.ld = op->ld;
+    a.W = op->W;
+    a.Wd = op->Wd;
+    a.lpr = t.lanes_per_row;
+    a.rows_per_tile = g.rows_per_tile;
+    a.remap = t.xcd_remap;
+    a.tiles_per_block = g.tiles_per_block;
+    a.F_b = op->F_b;
+    return a;
+}
+
+}  // namespace fvx

@@ -1,0 +1,284 @@
+// Base meshes: 2D finite-volume face graphs (host side), plus the library's
+// error handling.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+
+#include "common.h"
+
+namespace fvx {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &s) { g_last_error = s; }
+
+int guard(const std::function<int()> &f) {
+    try {
+        int rc = f();
+        if (rc >= 0) g_last_error.clear();
+        return rc;
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return FVX_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return FVX_E_ARG;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return FVX_E_ARG;
+    }
+}
+
+static void validate(const fvx_mesh &m) {
+    FVX_REQUIRE(m.n_cells >= 1, FVX_E_MESH, "mesh has no cells");
+    for (int c = 0; c < m.n_cells; ++c)
+        FVX_REQUIRE(m.area[c] > 0.0 && std::isfinite(m.area[c]), FVX_E_MESH,
+                    "cell " + std::to_string(c) + " has non-positive area");
+    for (int f = 0; f < m.n_faces; ++f) {
+        FVX_REQUIRE(m.c1[f] >= 0 && m.c1[f] < m.n_cells && m.c2[f] >= 0 && m.c2[f] < m.n_cells,
+                    FVX_E_MESH, "face " + std::to_string(f) + " cell index out of range");
+        FVX_REQUIRE(m.len[f] > 0.0 && m.dist[f] > 0.0 && std::isfinite(m.len[f]) &&
+                        std::isfinite(m.dist[f]),
+                    FVX_E_MESH, "face " + std::to_string(f) + " has non-positive length or distance");
+    }
+    for (int w = 0; w < m.n_walls; ++w) {
+        FVX_REQUIRE(m.wcell[w] >= 0 && m.wcell[w] < m.n_cells, FVX_E_MESH,
+                    "wall " + std::to_string(w) + " cell index out of range");
+        FVX_REQUIRE(m.wlen[w] > 0.0 && m.wdist[w] > 0.0, FVX_E_MESH,
+                    "wall " + std::to_string(w) + " has non-positive length or distance");
+    }
+}
+
+}  // namespace fvx
+
+using fvx::Error;
+using fvx::guard;
+
+extern "C" {
+
+const char *fvx_status_str(int s) {
+    switch (s) {
+        case FVX_OK: return "ok";
+        case FVX_NOT_CONVERGED: return "not converged";
+        case FVX_E_ARG: return "invalid argument";
+        case FVX_E_MESH: return "invalid mesh";
+        case FVX_E_NOMEM: return "buffer too small";
+        case FVX_E_HIP: return "HIP runtime error";
+        case FVX_E_BREAKDOWN: return "CG breakdown";
+        case FVX_E_NONFINITE: return "non-finite input";
+        case FVX_E_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char *fvx_last_error(void) { return fvx::g_last_error.c_str(); }
+
+int fvx_version(void) { return 10000; }
+
+int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y1, double stretch,
+                       int periodic_x, int periodic_y, fvx_mesh **out) {
+    return guard([&] {
+        FVX_REQUIRE(out, FVX_E_ARG, "out is NULL");
+        FVX_REQUIRE(nx >= 1 && ny >= 1, FVX_E_ARG, "nx and ny must be >= 1");
+        FVX_REQUIRE(Lx > 0 && y1 > y0 && std::isfinite(stretch) && stretch >= 0, FVX_E_ARG,
+                    "empty extent or bad stretch");
+        auto m = new fvx_mesh();
+        std::vector<double> xf(nx + 1), yf(ny + 1);
+        for (int i = 0; i <= nx; ++i) xf[i] = x0 + Lx * double(i) / double(nx);
+        for (int j = 0; j <= ny; ++j) {
+            double t = double(j) / double(ny);
+            yf[j] = stretch == 0.0
+                        ? y0 + (y1 - y0) * t
+                        : y0 + (y1 - y0) * 0.5 * (1.0 + std::tanh(stretch * (2.0 * t - 1.0)) / std::tanh(stretch));
+        }
+        const int nc = nx * ny;
+        m->n_cells = nc;
+        m->area.resize(nc);
+        m->cx.resize(nc);
+        m->cy.resize(nc);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int c = j * nx + i;
+                m->area[c] = (xf[i + 1] - xf[i]) * (yf[j + 1] - yf[j]);
+                m->cx[c] = 0.5 * (xf[i] + xf[i + 1]);
+                m->cy[c] = 0.5 * (yf[j] + yf[j + 1]);
+            }
+        auto add_face = [&](int a, int b, double l, double d) {
+            m->c1.push_back(a);
+            m->c2.push_back(b);
+            m->len.push_back(l);
+            m->dist.push_back(d);
+        };
+        auto half = [](const std::vector<double> &f, int i) { return 0.5 * (f[i + 1] - f[i]); };
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                if (i == nx - 1 && !periodic_x) continue;
+                const int ip = (i + 1) % nx;
+                add_face(j * nx + i, j * nx + ip, yf[j + 1] - yf[j], half(xf, i) + half(xf, ip));
+            }
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                if (j == ny - 1 && !periodic_y) continue;
+                const int jp = (j + 1) % ny;
+                add_face(j * nx + i, jp * nx + i, xf[i + 1] - xf[i], half(yf, j) + half(yf, jp));
+            }
+        m->n_faces = int(m->c1.size());
+        auto add_wall = [&](int c, double l, double d) {
+            m->wcell.push_back(c);
+            m->wlen.push_back(l);
+            m->wdist.push_back(d);
+        };
+        if (!periodic_x)
+            for (int j = 0; j < ny; ++j) {
+                add_wall(j * nx, yf[j + 1] - yf[j], half(xf, 0));
+                add_wall(j * nx + nx - 1, yf[j + 1] - yf[j], half(xf, nx - 1));
+            }
+        if (!periodic_y)
+            for (int i = 0; i < nx; ++i) {
+                add_wall(i, xf[i + 1] - xf[i], half(yf, 0));
+                add_wall((ny - 1) * nx + i, xf[i + 1] - xf[i], half(yf, ny - 1));
+            }
+        m->n_walls = int(m->wcell.size());
+        *out = m;
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_triangles(int n_pts, const double *xy, int n_tri, const int32_t *tri, fvx_mesh **out) {
+    return guard([&] {
+        FVX_REQUIRE(out && xy && tri, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(n_pts >= 3 && n_tri >= 1, FVX_E_ARG, "need >= 3 points and >= 1 triangle");
+        auto m = std::make_unique<fvx_mesh>();
+        m->n_cells = n_tri;
+        m->area.resize(n_tri);
+        m->cx.resize(n_tri);
+        m->cy.resize(n_tri);
+        for (int t = 0; t < n_tri; ++t) {
+            for (int s = 0; s < 3; ++s)
+                FVX_REQUIRE(tri[3 * t + s] >= 0 && tri[3 * t + s] < n_pts, FVX_E_MESH,
+                            "triangle " + std::to_string(t) + " vertex out of range");
+            const double *a = xy + 2 * tri[3 * t], *b = xy + 2 * tri[3 * t + 1], *c = xy + 2 * tri[3 * t + 2];
+            const double cr = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+            m->area[t] = 0.5 * std::fabs(cr);
+            FVX_REQUIRE(m->area[t] > 0.0, FVX_E_MESH, "degenerate triangle " + std::to_string(t));
+            m->cx[t] = (a[0] + b[0] + c[0]) / 3.0;
+            m->cy[t] = (a[1] + b[1] + c[1]) / 3.0;
+        }
+        // Edge key (lo, hi, triangle); sorting groups the two sides of a face.
+        std::vector<std::tuple<int, int, int>> e;
+        e.reserve(size_t(3) * n_tri);
+        for (int t = 0; t < n_tri; ++t)
+            for (int s = 0; s < 3; ++s) {
+                int u = tri[3 * t + s], v = tri[3 * t + (s + 1) % 3];
+                FVX_REQUIRE(u != v, FVX_E_MESH, "repeated vertex in triangle " + std::to_string(t));
+                e.emplace_back(std::min(u, v), std::max(u, v), t);
+            }
+        std::sort(e.begin(), e.end());
+        for (size_t i = 0; i < e.size();) {
+            size_t j = i;
+            while (j < e.size() && std::get<0>(e[j]) == std::get<0>(e[i]) &&
+                   std::get<1>(e[j]) == std::get<1>(e[i]))
+                ++j;
+            FVX_REQUIRE(j - i <= 2, FVX_E_MESH, "edge shared by more than two triangles");
+            const double *pa = xy + 2 * std::get<0>(e[i]), *pb = xy + 2 * std::get<1>(e[i]);
+            const double tx = pb[0] - pa[0], ty = pb[1] - pa[1];
+            const double l = std::sqrt(tx * tx + ty * ty);
+            const double nxv = ty / l, nyv = -tx / l;
+            const int ta = std::get<2>(e[i]);
+            if (j - i == 2) {
+                const int tb = std::get<2>(e[i + 1]);
+                const double d = std::fabs(nxv * (m->cx[tb] - m->cx[ta]) + nyv * (m->cy[tb] - m->cy[ta]));
+                FVX_REQUIRE(d > 0.0, FVX_E_MESH, "zero centroid distance across a face");
+                m->c1.push_back(ta);
+                m->c2.push_back(tb);
+                m->len.push_back(l);
+                m->dist.push_back(d);
+            } else {
+                m->wcell.push_back(ta);
+                m->wlen.push_back(l);
+                m->wdist.push_back(std::fabs(nxv * (m->cx[ta] - pa[0]) + nyv * (m->cy[ta] - pa[1])));
+            }
+            i = j;
+        }
+        m->n_faces = int(m->c1.size());
+        m->n_walls = int(m->wcell.size());
+        *out = m.release();
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_from_faces(int n_cells, const double *area, const double *cx, const double *cy,
+                        int n_faces, const int32_t *c1, const int32_t *c2, const double *len,
+                        const double *dist, int n_walls, const int32_t *wcell, const double *wlen,
+                        const double *wdist, fvx_mesh **out) {
+    return guard([&] {
+        FVX_REQUIRE(out && area, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(n_cells >= 1 && n_faces >= 0 && n_walls >= 0, FVX_E_ARG, "bad sizes");
+        FVX_REQUIRE(n_faces == 0 || (c1 && c2 && len && dist), FVX_E_ARG, "NULL face array");
+        FVX_REQUIRE(n_walls == 0 || (wcell && wlen && wdist), FVX_E_ARG, "NULL wall array");
+        auto m = std::make_unique<fvx_mesh>();
+        m->n_cells = n_cells;
+        m->n_faces = n_faces;
+        m->n_walls = n_walls;
+        m->area.assign(area, area + n_cells);
+        m->cx = cx ? std::vector<double>(cx, cx + n_cells) : std::vector<double>(n_cells, 0.0);
+        m->cy = cy ? std::vector<double>(cy, cy + n_cells) : std::vector<double>(n_cells, 0.0);
+        if (n_faces) {
+            m->c1.assign(c1, c1 + n_faces);
+            m->c2.assign(c2, c2 + n_faces);
+            m->len.assign(len, len + n_faces);
+            m->dist.assign(dist, dist + n_faces);
+        }
+        if (n_walls) {
+            m->wcell.assign(wcell, wcell + n_walls);
+            m->wlen.assign(wlen, wlen + n_walls);
+            m->wdist.assign(wdist, wdist + n_walls);
+        }
+        fvx::validate(*m);
+        *out = m.release();
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_info(const fvx_mesh *m, int64_t *n_cells, int64_t *n_faces, int64_t *n_walls) {
+    return guard([&] {
+        FVX_REQUIRE(m, FVX_E_ARG, "mesh is NULL");
+        if (n_cells) *n_cells = m->n_cells;
+        if (n_faces) *n_faces = m->n_faces;
+        if (n_walls) *n_walls = m->n_walls;
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_centroids(const fvx_mesh *m, double *cx, double *cy) {
+    return guard([&] {
+        FVX_REQUIRE(m, FVX_E_ARG, "mesh is NULL");
+        if (cx) std::memcpy(cx, m->cx.data(), sizeof(double) * m->n_cells);
+        if (cy) std::memcpy(cy, m->cy.data(), sizeof(double) * m->n_cells);
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_faces(const fvx_mesh *m, double *area, int32_t *c1, int32_t *c2, double *len,
+                   double *dist) {
+    return guard([&] {
+        FVX_REQUIRE(m, FVX_E_ARG, "mesh is NULL");
+        if (area) std::memcpy(area, m->area.data(), sizeof(double) * m->n_cells);
+        if (c1 && m->n_faces) std::memcpy(c1, m->c1.data(), sizeof(int32_t) * m->n_faces);
+        if (c2 && m->n_faces) std::memcpy(c2, m->c2.data(), sizeof(int32_t) * m->n_faces);
+        if (len && m->n_faces) std::memcpy(len, m->len.data(), sizeof(double) * m->n_faces);
+        if (dist && m->n_faces) std::memcpy(dist, m->dist.data(), sizeof(double) * m->n_faces);
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_destroy(fvx_mesh *m) {
+    delete m;
+    return FVX_OK;
+}
+
+}  // extern "C"

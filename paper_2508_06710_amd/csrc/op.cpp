@@ -1,0 +1,346 @@
+// Host operator builder: base mesh + k -> the base block A_b, the plane
+// coupling weights, the divergence incidence M_b and the gradient G_b, stored
+// once on the device (Section 3.1: operators are stored as for one system,
+// only the fields grow with the number of planes).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "common.h"
+
+namespace fvx {
+
+namespace {
+
+// Host image of the operator in FP64, before it is laid out on the device.
+struct HostOp {
+    int64_t n_b = 0, F_b = 0, nnz_b = 0;
+    int W = 0, Wd = 0;
+    std::vector<double> diag, w, ell_val, area, cf_coef, f_invd;
+    std::vector<int32_t> ell_col, cf_face, f_c1, f_c2;
+    // FP32 copies: diagonal rebuilt in FP32 so that rows sum to zero up to
+    // FP32 rounding of that sum.
+    std::vector<float> diag32;
+};
+
+HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
+    HostOp h;
+    const int64_t nb = m.n_cells;
+    h.n_b = nb;
+    h.F_b = m.n_faces;
+    const bool zf = d.coupling == FVX_COUPLING_PERIODIC_Z && d.k >= 2;
+    const double dz = d.dz;
+
+    // Off-diagonal neighbours per row, duplicates (two faces between the same
+    // cells, as on a two-cell periodic ring) merged.
+    std::vector<std::map<int32_t, double>> nbr(nb);
+    h.diag.assign(nb, 0.0);
+    for (int f = 0; f < m.n_faces; ++f) {
+        const int a = m.c1[f], b = m.c2[f];
+        if (a == b) continue;  // a face from a cell to itself carries no net flux
+        const double coef = m.len[f] * dz / m.dist[f];
+        nbr[a][b] += coef;
+        nbr[b][a] += coef;
+        h.diag[a] -= coef;
+        h.diag[b] -= coef;
+    }
+    h.w.assign(nb, 0.0);
+    if (zf)
+        for (int64_t c = 0; c < nb; ++c) {
+            h.w[c] = m.area[c] / dz;
+            h.diag[c] -= h.w[c];
+            h.diag[c] -= h.w[c];
+        }
+    std::vector<double> wall(nb, 0.0);
+    if (d.wall_bc == FVX_WALL_DIRICHLET)
+        for (int i = 0; i < m.n_walls; ++i) {
+            const double t = m.wlen[i] * dz / m.wdist[i];
+            wall[m.wcell[i]] -= t;
+            h.diag[m.wcell[i]] -= t;
+        }
+
+    h.W = 0;
+    for (int64_t i = 0; i < nb; ++i) h.W = std::max<int>(h.W, int(nbr[i].size()));
+    h.ell_col.assign(size_t(h.W) * nb, 0);
+    h.ell_val.assign(size_t(h.W) * nb, 0.0);
+    h.diag32.assign(nb, 0.0f);
+    h.nnz_b = nb;
+    for (int64_t i = 0; i < nb; ++i) {
+        int e = 0;
+        float s32 = 0.0f;
+        for (const auto &kv : nbr[i]) {
+            h.ell_col[size_t(e) * nb + i] = kv.first;
+            h.ell_val[size_t(e) * nb + i] = kv.second;
+            s32 += float(kv.second);
+            ++e;
+        }
+        h.nnz_b += e;
+        for (; e < h.W; ++e) {
+            h.ell_col[size_t(e) * nb + i] = int32_t(i);
+            h.ell_val[size_t(e) * nb + i] = 0.0;
+        }
+        if (zf) {
+            s32 += float(h.w[i]);
+            s32 += float(h.w[i]);
+        }
+        h.diag32[i] = -s32 + float(wall[i]);
+    }
+
+    // Divergence: cell -> face incidence.
+    std::vector<std::vector<std::pair<int32_t, double>>> inc(nb);
+    for (int f = 0; f < m.n_faces; ++f) {
+        const int a = m.c1[f], b = m.c2[f];
+        if (a == b) continue;
+        const double s = m.len[f] * dz;
+        inc[a].push_back({f, +s});
+        inc[b].push_back({f, -s});
+    }
+    h.Wd = 0;
+    for (int64_t i = 0; i < nb; ++i) h.Wd = std::max<int>(h.Wd, int(inc[i].size()));
+    h.cf_face.assign(size_t(h.Wd) * nb, 0);
+    h.cf_coef.assign(size_t(h.Wd) * nb, 0.0);
+    for (int64_t i = 0; i < nb; ++i)
+        for (size_t e = 0; e < inc[i].size(); ++e) {
+            h.cf_face[e * nb + i] = inc[i][e].first;
+            h.cf_coef[e * nb + i] = inc[i][e].second;
+        }
+    h.area = m.area;
+    h.f_c1 = m.c1;
+    h.f_c2 = m.c2;
+    h.f_invd.resize(m.n_faces);
+    for (int f = 0; f < m.n_faces; ++f) h.f_invd[f] = 1.0 / m.dist[f];
+    return h;
+}
+
+// Byte layout of the device image; every array starts on a 256-byte boundary.
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    }
+};
+
+struct Offsets {
+    size_t ell_col, cf_face, f_c1, f_c2;
+    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2];
+    size_t total;
+};
+
+Offsets layout(const HostOp &h, bool f32) {
+    Layout L;
+    Offsets o{};
+    const size_t nb = size_t(h.n_b), fb = size_t(h.F_b);
+    o.ell_col = L.take(sizeof(int32_t) * h.W * nb);
+    o.cf_face = L.take(sizeof(int32_t) * h.Wd * nb);
+    o.f_c1 = L.take(sizeof(int32_t) * fb);
+    o.f_c2 = L.take(sizeof(int32_t) * fb);
+    for (int p = 0; p < (f32 ? 2 : 1); ++p) {
+        const size_t v = p == 0 ? 8 : 4;
+        o.diag[p] = L.take(v * nb);
+        o.ell_val[p] = L.take(v * h.W * nb);
+        o.w[p] = L.take(v * nb);
+        o.cf_coef[p] = L.take(v * h.Wd * nb);
+        o.area[p] = L.take(v * nb);
+        o.f_invd[p] = L.take(v * fb);
+    }
+    o.total = L.off;
+    return o;
+}
+
+void check_desc(const fvx_mesh *m, const fvx_op_desc *d) {
+    FVX_REQUIRE(m && d, FVX_E_ARG, "NULL mesh or descriptor");
+    FVX_REQUIRE(d->k >= 1, FVX_E_ARG, "k must be >= 1");
+    FVX_REQUIRE(d->coupling == FVX_COUPLING_NONE || d->coupling == FVX_COUPLING_PERIODIC_Z,
+                FVX_E_ARG, "unknown coupling");
+    FVX_REQUIRE(d->dz > 0 && std::isfinite(d->dz), FVX_E_ARG, "dz must be > 0");
+    FVX_REQUIRE(d->wall_bc == FVX_WALL_NEUMANN || d->wall_bc == FVX_WALL_DIRICHLET, FVX_E_ARG,
+                "unknown wall_bc");
+    FVX_REQUIRE(m->n_cells < (1 << 30) && m->n_faces < (1 << 30), FVX_E_ARG, "mesh too large for int32 indices");
+}
+
+template <typename T>
+std::vector<T> cast(const std::vector<double> &v) {
+    return std::vector<T>(v.begin(), v.end());
+}
+
+}  // namespace
+
+fvx_tile default_tile(const fvx_op *op, int dtype) {
+    fvx_tile t{};
+    const int vmax = dtype == FVX_F32 ? 4 : 2;
+    int v = 1;
+    for (int c = vmax; c >= 1; c >>= 1)
+        if (op->ld % c == 0) {
+            v = c;
+            break;
+        }
+    t.vec = v;
+    t.lanes_per_row = std::min(64, next_pow2(int(ceil_div(op->k, v))));
+    t.block = 256;
+    t.xcd_remap = 1;
+    return t;
+}
+
+void check_tile(const fvx_op *op, int dtype, const fvx_tile &t) {
+    const int vmax = dtype == FVX_F32 ? 4 : 2;
+    FVX_REQUIRE(t.vec == 1 || t.vec == 2 || t.vec == 4, FVX_E_ARG, "tile.vec must be 1, 2 or 4");
+    FVX_REQUIRE(t.vec <= vmax, FVX_E_ARG, "tile.vec exceeds 16 bytes for this precision");
+    FVX_REQUIRE(op->ld % t.vec == 0, FVX_E_ARG, "tile.vec must divide ld");
+    FVX_REQUIRE(t.lanes_per_row >= 1 && t.lanes_per_row <= 64 &&
+                    (t.lanes_per_row & (t.lanes_per_row - 1)) == 0,
+                FVX_E_ARG, "tile.lanes_per_row must be a power of two in 1..64");
+    FVX_REQUIRE(t.block >= 64 && t.block <= 1024 && t.block % 64 == 0, FVX_E_ARG,
+                "tile.block must be a multiple of 64 in 64..1024");
+}
+
+RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks) {
+    RowGrid g;
+    g.n_rows = n_rows;
+    g.rows_per_tile = t.block / t.lanes_per_row;
+    const int64_t tiles = std::max<int64_t>(1, ceil_div(n_rows, g.rows_per_tile));
+    const int64_t nb = std::min<int64_t>(tiles, max_blocks);
+    g.tiles_per_block = ceil_div(tiles, nb);
+    g.n_blocks = int(ceil_div(tiles, g.tiles_per_block));
+    return g;
+}
+
+}  // namespace fvx
+
+using fvx::guard;
+
+extern "C" {
+
+int fvx_op_bytes(const fvx_mesh *m, const fvx_op_desc *d, size_t *bytes) {
+    return guard([&] {
+        fvx::check_desc(m, d);
+        FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
+        auto h = fvx::build_host(*m, *d);
+        *bytes = fvx::layout(h, d->with_f32 != 0).total;
+        return FVX_OK;
+    });
+}
+
+int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t bytes, void *stream,
+                  fvx_op **out) {
+    return guard([&] {
+        fvx::check_desc(m, d);
+        FVX_REQUIRE(out && dev_mem, FVX_E_ARG, "NULL output or device buffer");
+        FVX_REQUIRE(reinterpret_cast<uintptr_t>(dev_mem) % 256 == 0, FVX_E_ARG,
+                    "device buffer must be 256-byte aligned");
+        const bool f32 = d->with_f32 != 0;
+        auto h = fvx::build_host(*m, *d);
+        auto o = fvx::layout(h, f32);
+        FVX_REQUIRE(bytes >= o.total, FVX_E_NOMEM,
+                    "operator buffer too small: need " + std::to_string(o.total));
+        hipStream_t s = fvx::as_stream(stream);
+        char *base = static_cast<char *>(dev_mem);
+        auto put = [&](size_t off, const void *src, size_t n) {
+            if (n) FVX_HIP(hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s));
+        };
+        const size_t nb = size_t(h.n_b), fb = size_t(h.F_b);
+        put(o.ell_col, h.ell_col.data(), 4 * h.ell_col.size());
+        put(o.cf_face, h.cf_face.data(), 4 * h.cf_face.size());
+        put(o.f_c1, h.f_c1.data(), 4 * fb);
+        put(o.f_c2, h.f_c2.data(), 4 * fb);
+        put(o.diag[0], h.diag.data(), 8 * nb);
+        put(o.ell_val[0], h.ell_val.data(), 8 * h.ell_val.size());
+        put(o.w[0], h.w.data(), 8 * nb);
+        put(o.cf_coef[0], h.cf_coef.data(), 8 * h.cf_coef.size());
+        put(o.area[0], h.area.data(), 8 * nb);
+        put(o.f_invd[0], h.f_invd.data(), 8 * fb);
+        std::vector<float> ev32, w32, cf32, ar32, fi32;
+        if (f32) {
+            ev32 = fvx::cast<float>(h.ell_val);
+            w32 = fvx::cast<float>(h.w);
+            cf32 = fvx::cast<float>(h.cf_coef);
+            ar32 = fvx::cast<float>(h.area);
+            fi32 = fvx::cast<float>(h.f_invd);
+            put(o.diag[1], h.diag32.data(), 4 * nb);
+            put(o.ell_val[1], ev32.data(), 4 * ev32.size());
+            put(o.w[1], w32.data(), 4 * nb);
+            put(o.cf_coef[1], cf32.data(), 4 * cf32.size());
+            put(o.area[1], ar32.data(), 4 * nb);
+            put(o.f_invd[1], fi32.data(), 4 * fb);
+        }
+        FVX_HIP(hipStreamSynchronize(s));
+
+        auto op = std::make_unique<fvx_op>();
+        op->n_b = h.n_b;
+        op->F_b = h.F_b;
+        op->nnz_b = h.nnz_b;
+        op->k = d->k;
+        op->ld = fvx::ld_for_k(d->k);
+        op->coupling = d->coupling;
+        op->zfaces = d->coupling == FVX_COUPLING_PERIODIC_Z && d->k >= 2;
+        op->singular = !(d->wall_bc == FVX_WALL_DIRICHLET && m->n_walls > 0);
+        op->percol = d->coupling == FVX_COUPLING_NONE && d->k > 1;
+        op->dz = d->dz;
+        op->W = h.W;
+        op->Wd = h.Wd;
+        op->has_f32 = f32;
+        FVX_HIP(hipGetDevice(&op->device));
+        auto fill = [&](auto &D, int p, auto tag) {
+            using T = decltype(tag);
+            D.diag = reinterpret_cast<const T *>(base + o.diag[p]);
+            D.ell_col = reinterpret_cast<const int32_t *>(base + o.ell_col);
+            D.ell_val = reinterpret_cast<const T *>(base + o.ell_val[p]);
+            D.w = reinterpret_cast<const T *>(base + o.w[p]);
+            D.cf_face = reinterpret_cast<const int32_t *>(base + o.cf_face);
+            D.cf_coef = reinterpret_cast<const T *>(base + o.cf_coef[p]);
+            D.area = reinterpret_cast<const T *>(base + o.area[p]);
+            D.f_c1 = reinterpret_cast<const int32_t *>(base + o.f_c1);
+            D.f_c2 = reinterpret_cast<const int32_t *>(base + o.f_c2);
+            D.f_invd = reinterpret_cast<const T *>(base + o.f_invd[p]);
+            D.inv_dz = T(1.0 / d->dz);
+        };
+        fill(op->d64, 0, double{});
+        if (f32) fill(op->d32, 1, float{});
+        op->tile[0] = fvx::default_tile(op.get(), FVX_F64);
+        op->tile[1] = fvx::default_tile(op.get(), FVX_F32);
+        *out = op.release();
+        return FVX_OK;
+    });
+}
+
+int fvx_op_destroy(fvx_op *op) {
+    delete op;
+    return FVX_OK;
+}
+
+int fvx_op_shape(const fvx_op *op, int64_t *n_b, int64_t *F_b, int32_t *k, int32_t *ld, int64_t *nnz_b) {
+    return guard([&] {
+        FVX_REQUIRE(op, FVX_E_ARG, "op is NULL");
+        if (n_b) *n_b = op->n_b;
+        if (F_b) *F_b = op->F_b;
+        if (k) *k = op->k;
+        if (ld) *ld = op->ld;
+        if (nnz_b) *nnz_b = op->nnz_b;
+        return FVX_OK;
+    });
+}
+
+int fvx_op_singular(const fvx_op *op) { return op && op->singular ? 1 : 0; }
+
+int fvx_op_get_tile(const fvx_op *op, int dtype, fvx_tile *tile) {
+    return guard([&] {
+        FVX_REQUIRE(op && tile, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(dtype == FVX_F64 || dtype == FVX_F32, FVX_E_ARG, "dtype must be F64 or F32");
+        *tile = op->tile[dtype];
+        return FVX_OK;
+    });
+}
+
+int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile) {
+    return guard([&] {
+        FVX_REQUIRE(op && tile, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(dtype == FVX_F64 || dtype == FVX_F32, FVX_E_ARG, "dtype must be F64 or F32");
+        fvx::check_tile(op, dtype, *tile);
+        op->tile[dtype] = *tile;
+        return FVX_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+// SpMM kernels for the repeated-block operators: Laplacian, divergence,
+// gradient, and the plane-major <-> row-major conversion.
+//
+// Work mapping (gfx950, wave64): a row group of `lanes_per_row` lanes owns
+// one matrix row; each lane owns `vec` consecutive columns (one 16-byte load
+// for FP64 x2 / FP32 x4), so a row group covers lanes_per_row * vec of the k
+// columns per pass.  The row's matrix entries are read once per row group
+// and applied to every column it holds -- the reuse that Section 2 (Eq. 1,
+// Algorithm 1) turns SpMV into SpMM for.  Multivector rows are k-contiguous,
+// so the lanes of a row group issue one coalesced load per neighbour row.
+#include "kernels.h"
+
+namespace fvx {
+namespace {
+
+// Y = (I_k (x) A_b + C) X, optionally scaled per column.
+template <typename T, int V, bool Z>
+__global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+                                              const double *__restrict__ cs) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const bool single = lpr * V >= a.k;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+            vec_t<T, V> xo;
+            vec_t<T, V> acc = lap_row<T, V, Z>(a.A, X, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, xo);
+            if (cs) {
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    if (c0 + q < a.k) acc[q] *= T(cs[c0 + q]);
+            }
+            stv_masked<T, V>(Y + row * a.ld + c0, acc, a.k - c0);
+        }
+    }
+}
+
+// D = M U: integrated divergence of in-plane face fluxes plus the fluxes
+// through the faces between planes.
+template <typename T, int V, bool Z>
+__global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict__ U, const T *__restrict__ Wz,
+                                              T *__restrict__ D) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const bool single = lpr * V >= a.k;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+            vec_t<T, V> acc = 0;
+            for (int e = 0; e < a.Wd; ++e) {
+                const int64_t f = a.A.cf_face[e * a.n_b + row];
+                const T c = a.A.cf_coef[e * a.n_b + row];
+                acc += c * ldv<T, V>(U + f * a.ld + c0);
+            }
+            if constexpr (Z) {
+                const T ar = a.A.area[row];
+                const vec_t<T, V> wo = ldv<T, V>(Wz + row * a.ld + c0);
+                if (single) {
+                    const auto nb = plane_neighbours<T, V>(wo, sub, lpr, a.k);
+#pragma unroll
+                    for (int q = 0; q < V; ++q) acc[q] += ar * (wo[q] - left_of<T, V>(wo, nb, q));
+                } else {
+                    const T *wr = Wz + row * a.ld;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const int l = c0 + q;
+                        if (l < a.k) acc[q] += ar * (wo[q] - wr[l == 0 ? a.k - 1 : l - 1]);
+                    }
+                }
+            }
+            stv_masked<T, V>(D + row * a.ld + c0, acc, a.k - c0);
+        }
+    }
+}
+
+// Gf = G_b P on in-plane faces (rows [0, F_b)), Gz on the faces between
+// planes (rows [F_b, F_b + n_b)).
+template <typename T, int V, bool Z>
+__global__ __launch_bounds__(1024) void k_grad(RowArgs<T> a, const T *__restrict__ P, T *__restrict__ Gf,
+                                               T *__restrict__ Gz) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const bool single = lpr * V >= a.k;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        if (row < a.F_b) {
+            const int64_t c1 = a.A.f_c1[row], c2 = a.A.f_c2[row];
+            const T inv = a.A.f_invd[row];
+            for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+                const vec_t<T, V> g = (ldv<T, V>(P + c2 * a.ld + c0) - ldv<T, V>(P + c1 * a.ld + c0)) * inv;
+                stv_masked<T, V>(Gf + row * a.ld + c0, g, a.k - c0);
+            }
+        } else if constexpr (Z) {
+            const int64_t i = row - a.F_b;
+            const T inv = a.A.inv_dz;
+            for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+                const vec_t<T, V> po = ldv<T, V>(P + i * a.ld + c0);
+                vec_t<T, V> g;
+                if (single) {
+                    const auto nb = plane_neighbours<T, V>(po, sub, lpr, a.k);
+#pragma unroll
+                    for (int q = 0; q < V; ++q) g[q] = (right_of<T, V>(po, nb, q, c0 + q, a.k) - po[q]) * inv;
+                } else {
+                    const T *pr = P + i * a.ld;
+#pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const int l = c0 + q;
+                        g[q] = l < a.k ? (pr[l == a.k - 1 ? 0 : l + 1] - po[q]) * inv : T(0);
+                    }
+                }
+                stv_masked<T, V>(Gz + i * a.ld + c0, g, a.k - c0);
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_pack(int64_t n_rows, int k, int ld, const T *__restrict__ src, T *__restrict__ dst,
+                       int to_rows) {
+    const int64_t n = n_rows * k;
+    for (int64_t idx = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; idx < n;
+         idx += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = idx / k;
+        const int l = int(idx - r * k);
+        if (to_rows)
+            dst[r * ld + l] = src[int64_t(l) * n_rows + r];
+        else
+            dst[int64_t(l) * n_rows + r] = src[r * ld + l];
+    }
+}
+
+// Picks the kernel instance for (vec, planes coupled); vec * sizeof(T) <= 16.
+template <typename T, typename F>
+void by_vec(int vec, bool z, F &&f) {
+    auto go = [&](auto vtag) {
+        constexpr int V = decltype(vtag)::value;
+        if constexpr (V * sizeof(T) <= 16) {
+            if (z)
+                f(std::integral_constant<int, V>{}, std::true_type{});
+            else
+                f(std::integral_constant<int, V>{}, std::false_type{});
+        } else {
+            throw Error(FVX_E_ARG, "vector width too large for this precision");
+        }
+    };
+    switch (vec) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        default: throw Error(FVX_E_ARG, "bad vector width");
+    }
+}
+
+void check_ptr(const void *p, const char *what) {
+    FVX_REQUIRE(p, FVX_E_ARG, std::string(what) + " is NULL");
+    FVX_REQUIRE(reinterpret_cast<uintptr_t>(p) % 16 == 0, FVX_E_ARG, std::string(what) + " is not 16-byte aligned");
+}
+
+void check_dtype(const fvx_op *op, int dtype) {
+    FVX_REQUIRE(op, FVX_E_ARG, "op is NULL");
+    FVX_REQUIRE(dtype == FVX_F64 || dtype == FVX_F32, FVX_E_ARG, "dtype must be FVX_F64 or FVX_F32");
+    FVX_REQUIRE(dtype == FVX_F64 || op->has_f32, FVX_E_ARG, "operator was built without FP32 copies");
+}
+
+}  // namespace
+
+template <typename T>
+void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_t s) {
+    RowGrid g;
+    const fvx_tile &t = op->tile[dtype_of<T>()];
+    auto a = row_args<T>(op, op->n_b, g, t);
+    by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
+        hipLaunchKernelGGL((k_lap<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
+                           s, a, X, Y, cs);
+    });
+    FVX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s) {
+    RowGrid g;
+    const fvx_tile &t = op->tile[dtype_of<T>()];
+    auto a = row_args<T>(op, op->n_b, g, t);
+    by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
+        hipLaunchKernelGGL((k_div<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
+                           s, a, U, Wz, D);
+    });
+    FVX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s) {
+    RowGrid g;
+    const int64_t rows = op->F_b + (op->zfaces ? op->n_b : 0);
+    const fvx_tile &t = op->tile[dtype_of<T>()];
+    auto a = row_args<T>(op, rows, g, t);
+    by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
+        hipLaunchKernelGGL((k_grad<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
+                           s, a, P, Gf, Gz);
+    });
+    FVX_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_pack(const fvx_op *op, int64_t n_rows, const T *src, T *dst, bool to_rows, hipStream_t s) {
+    const int64_t n = n_rows * op->k;
+    const int blocks = int(std::min<int64_t>(std::max<int64_t>(1, ceil_div(n, 256)), 65536));
+    hipLaunchKernelGGL((k_pack<T>), dim3(blocks), dim3(256), 0, s, n_rows, op->k, op->ld, src, dst, int(to_rows));
+    FVX_HIP(hipGetLastError());
+}
+
+template void launch_lap<double>(const fvx_op *, const double *, double *, const double *, hipStream_t);
+template void launch_lap<float>(const fvx_op *, const float *, float *, const double *, hipStream_t);
+template void launch_div<double>(const fvx_op *, const double *, const double *, double *, hipStream_t);
+template void launch_div<float>(const fvx_op *, const float *, const float *, float *, hipStream_t);
+template void launch_grad<double>(const fvx_op *, const double *, double *, double *, hipStream_t);
+template void launch_grad<float>(const fvx_op *, const float *, float *, float *, hipStream_t);
+template void launch_pack<double>(const fvx_op *, int64_t, const double *, double *, bool, hipStream_t);
+template void launch_pack<float>(const fvx_op *, int64_t, const float *, float *, bool, hipStream_t);
+
+}  // namespace fvx
+
+using fvx::guard;
+
+extern "C" {
+
+int fvx_lap(const fvx_op *op, int dtype, const void *X, void *Y, const double *colscale, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        fvx::check_ptr(X, "X");
+        fvx::check_ptr(Y, "Y");
+        FVX_REQUIRE(X != Y, FVX_E_ARG, "X and Y must not overlap");
+        if (dtype == FVX_F64)
+            fvx::launch_lap<double>(op, static_cast<const double *>(X), static_cast<double *>(Y), colscale,
+                                    fvx::as_stream(stream));
+        else
+            fvx::launch_lap<float>(op, static_cast<const float *>(X), static_cast<float *>(Y), colscale,
+                                   fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_div(const fvx_op *op, int dtype, const void *Uf, const void *Wz, void *D, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        if (op->F_b > 0) fvx::check_ptr(Uf, "Uf");
+        if (op->zfaces) fvx::check_ptr(Wz, "Wz");
+        fvx::check_ptr(D, "D");
+        if (dtype == FVX_F64)
+            fvx::launch_div<double>(op, static_cast<const double *>(Uf), static_cast<const double *>(Wz),
+                                    static_cast<double *>(D), fvx::as_stream(stream));
+        else
+            fvx::launch_div<float>(op, static_cast<const float *>(Uf), static_cast<const float *>(Wz),
+                                   static_cast<float *>(D), fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        fvx::check_ptr(P, "P");
+        if (op->F_b > 0) fvx::check_ptr(Gf, "Gf");
+        if (op->zfaces) fvx::check_ptr(Gz, "Gz");
+        if (op->F_b == 0 && !op->zfaces) return FVX_OK;
+        if (dtype == FVX_F64)
+            fvx::launch_grad<double>(op, static_cast<const double *>(P), static_cast<double *>(Gf),
+                                     static_cast<double *>(Gz), fvx::as_stream(stream));
+        else
+            fvx::launch_grad<float>(op, static_cast<const float *>(P), static_cast<float *>(Gf),
+                                    static_cast<float *>(Gz), fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_pack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        FVX_REQUIRE(src && dst && n_rows >= 0, FVX_E_ARG, "NULL buffer or negative rows");
+        if (n_rows == 0) return FVX_OK;
+        if (dtype == FVX_F64)
+            fvx::launch_pack<double>(op, n_rows, static_cast<const double *>(src), static_cast<double *>(dst), true,
+                                     fvx::as_stream(stream));
+        else
+            fvx::launch_pack<float>(op, n_rows, static_cast<const float *>(src), static_cast<float *>(dst), true,
+                                    fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_unpack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        FVX_REQUIRE(src && dst && n_rows >= 0, FVX_E_ARG, "NULL buffer or negative rows");
+        if (n_rows == 0) return FVX_OK;
+        if (dtype == FVX_F64)
+            fvx::launch_pack<double>(op, n_rows, static_cast<const double *>(src), static_cast<double *>(dst), false,
+                                     fvx::as_stream(stream));
+        else
+            fvx::launch_pack<float>(op, n_rows, static_cast<const float *>(src), static_cast<float *>(dst), false,
+                                    fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+}  // extern "C"

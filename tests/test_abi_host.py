@@ -1,0 +1,100 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/fvx.h, and its host-only logic (mesh builders, size
+queries, argument validation) agrees with the oracle.  No GPU calls."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            txt = open(os.path.join(inc, f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(fvx_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def fvx():
+    import paper_2508_06710_amd as fvx
+    fvx.lib()
+    return fvx
+
+
+def test_exports_every_declared_symbol(fvx):
+    from paper_2508_06710_amd import _lib
+    names = _declared()
+    assert len(names) >= 20
+    L = fvx.lib()
+    for n in names:
+        assert hasattr(L, n), f"{n} missing from libfvx.so"
+        assert n in _lib.SIGNATURES, f"{n} has no ctypes signature"
+
+
+def test_status_strings(fvx):
+    L = fvx.lib()
+    assert L.fvx_status_str(0) == b"ok"
+    assert L.fvx_status_str(-5) == b"CG breakdown"
+    assert L.fvx_version() >= 10000
+
+
+@pytest.mark.parametrize("spec", [inputs.channel_base(7, 5), inputs.convection_base(4, 6),
+                                  inputs.CartSpec(3, 4, 1.0, 0.0, 2.0, 0.7, True, True)])
+def test_cartesian_mesh_matches_oracle_geometry(fvx, orc, spec):
+    m = fvx.Mesh.from_spec(spec)
+    g = orc.cart_geometry(spec)
+    area, c1, c2, ln, ds = m.faces()
+    cx, cy = m.centroids()
+    assert np.array_equal(c1, g.c1) and np.array_equal(c2, g.c2)
+    for a, b in ((area, g.area), (ln, g.len), (ds, g.dist), (cx, g.cx), (cy, g.cy)):
+        assert np.allclose(a, b, rtol=4e-16, atol=1e-300)
+
+
+def test_triangle_mesh_matches_oracle_geometry(fvx, orc):
+    t = inputs.unit_square_triangles(5)
+    m = fvx.Mesh.from_spec(t)
+    g = orc.tri_geometry(t)
+    area, c1, c2, ln, ds = m.faces()
+    assert np.array_equal(c1, g.c1) and np.array_equal(c2, g.c2)
+    assert np.allclose(area, g.area, rtol=1e-15) and np.allclose(ln, g.len, rtol=1e-15)
+    assert np.allclose(ds, g.dist, rtol=1e-13)
+
+
+def test_mesh_errors(fvx):
+    from paper_2508_06710_amd._lib import E_ARG, E_MESH
+    L = fvx.lib()
+    h = C.c_void_p()
+    assert L.fvx_mesh_cartesian(0, 4, 0.0, 1.0, 0.0, 1.0, 0.0, 1, 0, C.byref(h)) == E_ARG
+    assert b"nx" in L.fvx_last_error()
+    xy = np.array([[0, 0], [1, 0], [0, 1.0]])
+    tri = np.array([[0, 1, 5]], np.int32)
+    assert L.fvx_mesh_triangles(3, xy.ctypes.data, 1, tri.ctypes.data, C.byref(h)) == E_MESH
+    with pytest.raises(fvx.FvxError):
+        fvx.Mesh.from_faces([1.0, -1.0], [0], [1], [1.0], [1.0])
+
+
+def test_op_bytes_independent_of_k(fvx):
+    """Operator storage is that of the base block only (fields grow with k, operators do not)."""
+    from paper_2508_06710_amd import _lib
+    m = fvx.Mesh.from_spec(inputs.channel_base(32, 16))
+    sizes = []
+    for k in (1, 4, 64, 128):
+        d = _lib.OpDesc()
+        d.k, d.coupling, d.dz, d.wall_bc, d.with_f32 = k, 1, 0.1, 0, 1
+        n = C.c_size_t()
+        assert fvx.lib().fvx_op_bytes(m._h, C.byref(d), C.byref(n)) == 0
+        sizes.append(n.value)
+    assert len(set(sizes)) == 1
+    d.k = 0
+    assert fvx.lib().fvx_op_bytes(m._h, C.byref(d), C.byref(n)) == _lib.E_ARG

@@ -1,0 +1,181 @@
+"""GPU parity of the SpMM operators (lap, div, grad) against the oracle's
+assembled 3D matrices, element by element, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from helpers import Case, componentwise, fp32_bound_factor
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+# (label, spec) -- ragged sizes that do not fill whole tiles, walls on all
+# sides, unstructured triangles, and the 64x64 stretched channel base.
+BASES = {
+    "chan13x9": inputs.channel_base(13, 9),
+    "box7x11": inputs.convection_base(7, 11),
+    "tri6": inputs.unit_square_triangles(6),
+    "chan64": inputs.channel_base(64, 64),
+}
+
+
+def _lap_check(c: Case, seed=0, dtype=None, colscale=None):
+    fvx = c.fvx
+    x = inputs.uniform(seed, 0, c.m3.N)
+    if dtype == fvx.F32:
+        x = x.astype(np.float32).astype(np.float64)
+        X = c.op.to_rows(x, dtype=fvx.F32)
+        y = c.op.to_planes(c.op.lap(X, colscale=colscale), dtype=fvx.F32).astype(np.float64)
+    else:
+        X = c.op.to_rows(x)
+        y = c.op.to_planes(c.op.lap(X, colscale=colscale))
+    from oracle import spmv
+    ref = spmv(c.L, x)
+    if colscale is not None:
+        s = colscale.cpu().numpy()
+        ref = ref * np.repeat(s, c.m3.n_b)
+        A = c.L.multiply(np.repeat(np.abs(s), c.m3.n_b)[:, None]).tocsr()
+    else:
+        A = c.L
+    return y, ref, A, x
+
+
+@pytest.mark.parametrize("base", list(BASES))
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 16, 64])
+def test_lap_f64_periodic(base, k):
+    c = Case(BASES[base], k)
+    y, ref, A, x = _lap_check(c, seed=k)
+    assert componentwise(y, ref, A, x) <= TOL64
+    assert np.linalg.norm(y - ref) <= TOL64 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("base", ["chan13x9", "tri6"])
+@pytest.mark.parametrize("k", [1, 4, 7])
+def test_lap_f64_independent_planes_colscale(base, k):
+    c = Case(BASES[base], k, coupling=0)
+    cs = torch.tensor(inputs.uniform(9, 0, k, 0.5, 2.0), dtype=torch.float64, device="cuda")
+    for scale in (None, cs):
+        y, ref, A, x = _lap_check(c, seed=1, colscale=scale)
+        assert componentwise(y, ref, A, x) <= TOL64
+
+
+@pytest.mark.parametrize("k", [2, 5, 16])
+def test_lap_dirichlet(k):
+    c = Case(BASES["box7x11"], k, dirichlet=True)
+    y, ref, A, x = _lap_check(c, seed=3)
+    assert componentwise(y, ref, A, x) <= TOL64
+
+
+@pytest.mark.parametrize("k", [128, 130])
+def test_lap_wide_k(k):
+    c = Case(BASES["chan13x9"], k)
+    y, ref, A, x = _lap_check(c, seed=4)
+    assert componentwise(y, ref, A, x) <= TOL64
+
+
+@pytest.mark.parametrize("k", [8, 16, 64])
+def test_every_tile_gives_the_same_product(k):
+    """Tiles are interchangeable: each valid tile reproduces the oracle, and
+    single-pass and multi-pass row groups agree."""
+    c = Case(BASES["chan13x9"], k)
+    fvx = c.fvx
+    outs = []
+    for vec in (1, 2):
+        for lpr in (1, 2, 4, 8, 16, 32, 64):
+            for block in (64, 256, 1024):
+                if block < lpr:
+                    continue
+                for remap in (0, 1):
+                    c.op.set_tile(vec, lpr, block, remap, fvx.F64)
+                    y, ref, A, x = _lap_check(c, seed=5)
+                    assert componentwise(y, ref, A, x) <= TOL64, (vec, lpr, block, remap)
+                    outs.append(y)
+    with pytest.raises(fvx.FvxError):
+        c.op.set_tile(4, 8, 256, 1, fvx.F64)  # 32-byte vectors are not offered
+    with pytest.raises(fvx.FvxError):
+        c.op.set_tile(2, 3, 256, 1, fvx.F64)  # lanes per row must be a power of two
+
+
+@pytest.mark.parametrize("base", list(BASES))
+@pytest.mark.parametrize("k", [1, 3, 8, 64])
+def test_lap_f32_within_rounding_bound(base, k):
+    c = Case(BASES[base], k)
+    y, ref, A, x = _lap_check(c, seed=6, dtype=c.fvx.F32)
+    bound = abs(A) @ np.abs(x)
+    err = np.abs(y - ref)
+    fac = fp32_bound_factor(A)
+    assert np.all(err <= fac * bound + 1e-30), float(np.max(err / (fac * bound + 1e-300)))
+
+
+def _faces_vec(c, seed):
+    """Random face velocities, plane-major over the oracle's 3D face numbering."""
+    return inputs.normal(seed, 0, c.m3.F3)
+
+
+def _split_faces(c, u):
+    kF = c.k * c.m3.g.n_faces
+    return u[:kF], u[kF:]
+
+
+@pytest.mark.parametrize("base", list(BASES))
+@pytest.mark.parametrize("k,coupling", [(1, 1), (2, 1), (3, 1), (8, 1), (64, 1), (4, 0)])
+def test_div_and_grad(base, k, coupling):
+    c = Case(BASES[base], k, coupling=coupling)
+    fvx = c.fvx
+    from oracle import spmv
+    u = _faces_vec(c, 11)
+    uf, wz = _split_faces(c, u)
+    Uf = c.op.to_rows(uf, rows=c.op.F_b)
+    Wz = c.op.to_rows(wz) if c.op.zfaces else None
+    D = c.op.to_planes(c.op.div(Uf, Wz))
+    assert componentwise(D, spmv(c.M, u), c.M, u) <= TOL64
+
+    p = inputs.uniform(12, 0, c.m3.N)
+    Gf, Gz = c.op.grad(c.op.to_rows(p))
+    g = c.op.to_planes(Gf, rows=c.op.F_b)
+    if c.op.zfaces:
+        g = np.concatenate([g, c.op.to_planes(Gz)])
+    assert componentwise(g, spmv(c.G, p), c.G, p) <= TOL64
+
+    # FP32 versions within a rounding bound.
+    U32 = c.op.to_rows(uf.astype(np.float32), rows=c.op.F_b, dtype=fvx.F32)
+    W32 = c.op.to_rows(wz.astype(np.float32), dtype=fvx.F32) if c.op.zfaces else None
+    D32 = c.op.to_planes(c.op.div(U32, W32), dtype=fvx.F32).astype(np.float64)
+    u32 = np.concatenate([uf.astype(np.float32), wz.astype(np.float32)]).astype(np.float64)
+    ref32 = spmv(c.M, u32)
+    assert np.all(np.abs(D32 - ref32) <= 16 * 2.0 ** -24 * (abs(c.M) @ np.abs(u32)) + 1e-30)
+
+
+def test_lap_equals_div_of_grad():
+    """L = M G through the GPU operators themselves."""
+    c = Case(BASES["chan13x9"], 6)
+    p = c.op.to_rows(inputs.uniform(13, 0, c.m3.N))
+    Gf, Gz = c.op.grad(p)
+    D = c.op.to_planes(c.op.div(Gf, Gz))
+    Lp = c.op.to_planes(c.op.lap(p))
+    assert np.max(np.abs(D - Lp)) <= 1e-12 * np.max(np.abs(Lp))
+
+
+def test_small_channel_full_size():
+    """The 64x64 base with 8 periodic planes (32,768 cells), all elements."""
+    c = Case(inputs.channel_base(64, 64), 8, math.pi / 8)
+    y, ref, A, x = _lap_check(c, seed=0)
+    assert componentwise(y, ref, A, x) <= TOL64
+    assert np.linalg.norm(y - ref) <= TOL64 * np.linalg.norm(ref)
+
+
+def test_bad_arguments_are_rejected():
+    c = Case(BASES["chan13x9"], 4)
+    fvx = c.fvx
+    X = c.op.empty()
+    with pytest.raises(fvx.FvxError):
+        c.op.lap(X, X)                      # in place
+    with pytest.raises(fvx.FvxError):
+        c.op.lap(X[:, 1:], dtype=fvx.F64)  # misaligned
+    c2 = Case(BASES["chan13x9"], 4, with_f32=False)
+    with pytest.raises(fvx.FvxError):
+        c2.op.lap(c2.op.empty(dtype=fvx.F32), dtype=fvx.F32)

@@ -1,0 +1,141 @@
+"""GPU Poisson solves against the oracle.
+
+Solution vectors of two correct solves may differ by about cond(L) * rtol,
+so parity is defined through residuals recomputed with the ORACLE's matrix,
+brute-force dense solves on tiny meshes, the oracle CG's iteration count,
+and bitwise repeatability of the deterministic reductions."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from helpers import Case
+
+pytestmark = pytest.mark.gpu
+
+
+def _true_relres(c, x, b):
+    """Per group ||bp - L x|| / ||bp|| with the oracle's assembled matrix."""
+    ng = c.m3.n_groups()
+    bp = oracle.project_mean(b, ng)
+    r = bp - oracle.spmv(c.L, x)
+    if c.coupling == 0 and c.k > 1:
+        return [np.linalg.norm(rr) / np.linalg.norm(bb) for rr, bb in
+                zip(r.reshape(c.k, -1), bp.reshape(c.k, -1))]
+    return [np.linalg.norm(r) / np.linalg.norm(bp)]
+
+
+def _solve(c, b, **kw):
+    X, st = c.op.solve(c.op.to_rows(b), **kw)
+    return c.op.to_planes(X), st
+
+
+@pytest.mark.parametrize("spec,k,coupling", [
+    (inputs.channel_base(64, 64), 8, 1),        # the 64x64 stretched channel, 8 planes
+    (inputs.channel_base(13, 9), 1, 1),
+    (inputs.channel_base(13, 9), 2, 1),
+    (inputs.channel_base(13, 9), 5, 0),
+    (inputs.convection_base(12, 20), 16, 1),
+    (inputs.unit_square_triangles(8), 4, 1),
+])
+def test_true_residual_and_iterations_match_oracle(spec, k, coupling):
+    c = Case(spec, k, coupling=coupling)
+    b = inputs.rhs_uniform(0, c.m3.N)
+    for rtol in (1e-8, 1e-10):
+        x, st = _solve(c, b, rtol=rtol)
+        assert st["status"] == 0
+        rel = _true_relres(c, x, b)
+        assert max(rel) <= rtol * 1.05, rel
+        assert abs(st["relres_true"] - max(rel)) <= 1e-3 * rtol + 1e-14
+        ref = oracle.cg(c.m3, c.L, b, rtol)
+        it_ref = max(ref.iters)
+        assert abs(st["iters"] - it_ref) <= max(2, math.ceil(0.01 * it_ref)), (st["iters"], it_ref)
+        # zero plain mean on exit (singular operator)
+        for g in x.reshape(c.m3.n_groups(), -1):
+            assert abs(g.mean()) <= 1e-13 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("k,coupling,dirichlet", [(1, 1, False), (2, 1, False), (3, 1, False),
+                                                  (4, 0, False), (3, 1, True)])
+def test_tiny_mesh_matches_dense_direct_solve(k, coupling, dirichlet):
+    c = Case(inputs.channel_base(6, 5, 0.5), k, 0.6, coupling, dirichlet)
+    b = inputs.rhs_uniform(3, c.m3.N)
+    x, st = _solve(c, b, rtol=1e-15, max_iter=500, allow_not_converged=True)
+    ng = c.m3.n_groups()
+    xd = oracle.dense_solve(c.m3.dense_lap(), oracle.project_mean(b, ng), ng)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+def test_finite_termination_special_case():
+    """A uniform 4-cell periodic ring x 4 periodic planes has four distinct
+    nonzero eigenvalues: CG ends within 4 iterations."""
+    c = Case(inputs.CartSpec(4, 1, 4.0, 0.0, 1.0, 0.0, True, False), 4, 1.0)
+    b = inputs.rhs_uniform(11, c.m3.N)
+    x, st = _solve(c, b, rtol=1e-13, max_iter=50)
+    assert st["iters"] <= 4 and st["relres_true"] < 1e-13
+
+
+def test_bitwise_repeatable():
+    c = Case(inputs.channel_base(48, 40), 16)
+    b = c.op.to_rows(inputs.rhs_uniform(2, c.m3.N))
+    X1, s1 = c.op.solve(b, rtol=1e-9)
+    X2, s2 = c.op.solve(b, rtol=1e-9)
+    assert torch.equal(X1, X2) and s1["iters"] == s2["iters"]
+
+
+def test_initial_guess_and_projection_flags():
+    c = Case(inputs.channel_base(20, 16), 4)
+    b = inputs.rhs_uniform(4, c.m3.N) + 3.0  # nonzero mean: projected
+    x, st = _solve(c, b, rtol=1e-10)
+    assert st["rhs_projected"] == 1
+    X0 = c.op.to_rows(x)
+    _, st2 = c.op.solve(c.op.to_rows(b), X=X0, guess=1, rtol=1e-10)
+    assert st2["iters"] <= 1 and st2["r0_over_b"] <= 1.1e-10
+    # a constant right-hand side projects to zero: x = 0 without iterating
+    x0, st0 = _solve(c, np.ones(c.m3.N), rtol=1e-10)
+    assert st0["iters"] == 0 and np.all(x0 == 0)
+
+
+def test_failure_paths():
+    c = Case(inputs.channel_base(16, 12), 4)
+    fvx = c.fvx
+    b = inputs.rhs_uniform(5, c.m3.N)
+    _, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, max_iter=1, allow_not_converged=True)
+    assert st["status"] == fvx._lib.NOT_CONVERGED and st["iters"] == 1
+    bad = b.copy()
+    bad[7] = np.nan
+    with pytest.raises(fvx.FvxError) as e:
+        c.op.solve(c.op.to_rows(bad), rtol=1e-8)
+    assert e.value.code == fvx._lib.E_NONFINITE
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    from paper_2508_06710_amd import _lib
+    import ctypes as C
+    opts = c.op.solve_opts()
+    st = _lib.SolveStats()
+    B = c.op.to_rows(b)
+    X = c.op.zeros()
+    rc = _lib.lib().fvx_poisson_solve(c.op._h, C.c_void_p(B.data_ptr()), C.c_void_p(X.data_ptr()),
+                                      C.byref(opts), C.c_void_p(small.data_ptr()), 16, C.byref(st), None)
+    assert rc == _lib.E_NOMEM
+
+
+@pytest.mark.parametrize("spec,k,coupling", [
+    (inputs.channel_base(64, 64), 8, 1),
+    (inputs.channel_base(13, 9), 6, 0),
+    (inputs.unit_square_triangles(10), 8, 1),
+])
+def test_mixed_precision_reaches_fp64_residual(spec, k, coupling):
+    c = Case(spec, k, coupling=coupling)
+    fvx = c.fvx
+    b = inputs.rhs_uniform(7, c.m3.N)
+    x, st = _solve(c, b, rtol=1e-10, precision=fvx.MIXED, inner_rtol=1e-4)
+    assert st["status"] == 0 and st["outer"] >= 2
+    rel = _true_relres(c, x, b)
+    assert max(rel) <= 1e-10 * 1.05, rel
+    xr, _ = _solve(c, b, rtol=1e-13)
+    err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+    print(f"mixed vs fp64 solution: rel err {err:.2e}, inner iters {st['iters']}, outer {st['outer']}")
+    assert err <= 1e-6
