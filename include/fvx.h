@@ -188,6 +188,10 @@ int fvx_div(const fvx_op *op, int dtype, const void *Uf, const void *Wz, void *D
  * NULL when there are no faces between planes). */
 int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream);
 
+/* Gradient update  Gf += alpha * (G_b P),  Gz += alpha * (G_z P)  -- e.g. the
+ * projection step u <- u - G p with alpha = -1.  Arguments as fvx_grad. */
+int fvx_grad_axpy(const fvx_op *op, int dtype, double alpha, const void *P, void *Gf, void *Gz, void *stream);
+
 /* Plane-major <-> row-major conversion on the device.  n_rows = n_b or F_b.
  * src/dst: device; pack reads [k][n_rows] and writes [n_rows][ld]. */
 int fvx_pack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream);
@@ -237,6 +241,38 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *opts, size_t *bytes)
  * FVX_NOT_CONVERGED when the cap is hit, FVX_E_BREAKDOWN, FVX_E_NONFINITE. */
 int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *opts,
                       void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Comparators for measurement                                         */
+/* ------------------------------------------------------------------ */
+
+/* The assembled 3D Laplacian with no block reuse: I_k (x) A_b + C expanded
+ * into one CSR matrix over plane-major rows l*n_b + c (columns ascending,
+ * duplicate entries merged).  Host arrays: ptr [k*n_b + 1], col and val
+ * [*nnz].  Call with ptr = col = val = NULL to query *nnz.  FVX_E_ARG when the
+ * expansion does not fit int32 indices. */
+int fvx_expand_csr(const fvx_mesh *m, const fvx_op_desc *d, int64_t *nnz, int32_t *ptr, int32_t *col,
+                   double *val);
+
+/* y = A x for an assembled CSR matrix (one row per thread; device arrays,
+ * int32 row pointers and column indices, FP64 values): the plain SpMV that
+ * the repeated-block SpMM replaces. */
+int fvx_csr_spmv(int64_t n_rows, const int32_t *ptr, const int32_t *col, const double *val,
+                 const double *x, double *y, void *stream);
+
+/* Textbook FP64 CG on an assembled CSR matrix (SPD -A form as fvx_poisson_solve)
+ * with separate kernels for the SpMV, each dot product, each axpy and the
+ * search-direction update.  B, X: device double [n].  singular != 0
+ * projects b (and x on exit) to zero plain mean.  Options and statistics as
+ * fvx_poisson_solve (precision must be FVX_F64). */
+int fvx_csr_solve_bytes(int64_t n_rows, size_t *bytes);
+int fvx_csr_poisson_solve(int64_t n_rows, const int32_t *ptr, const int32_t *col, const double *val,
+                          const double *B, double *X, int singular, const fvx_solve_opts *opts,
+                          void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
+
+/* Streaming device copy of `bytes` (multiple of 16, 16-byte aligned buffers):
+ * the achievable-bandwidth reference of the roofline. */
+int fvx_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,7 @@ def lib():
         L.orc_spmv.argtypes = [l64, _lp, _ip, _dp, _dp, _dp]
         L.orc_spmv.restype = None
         L.orc_cg.argtypes = [l64, l64, _lp, _ip, _dp, _dp, _dp, i, d, i, i, P(_CGStats)]
+        L.orc_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -237,12 +238,17 @@ class Mesh3D:
         return (np.arange(self.k) + 0.5) * self.dz
 
 
-def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
+def threads() -> int:
+    """Number of host threads the oracle's OpenMP loops use."""
+    return int(lib().orc_threads())
+
+
+def spmv(A: sp.csr_matrix, x: np.ndarray, out: np.ndarray | None = None) -> np.ndarray:
     """y = A x by the oracle's row-sequential CSR loop."""
     A = A.tocsr()
     x = np.ascontiguousarray(x, dtype=np.float64)
-    y = np.zeros(A.shape[0])
-    lib().orc_spmv(A.shape[0], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+    y = np.empty(A.shape[0]) if out is None else out
+    lib().orc_spmv(A.shape[0], A.indptr.astype(np.int64, copy=False), A.indices.astype(np.int32, copy=False),
                    np.ascontiguousarray(A.data), x, y)
     return y
 

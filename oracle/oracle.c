@@ -17,6 +17,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ERR_ARG (-1)
 #define ERR_MESH (-2)
@@ -657,4 +660,14 @@ int orc_cg(int64_t row0, int64_t n, const int64_t *ptr, const int32_t *col, cons
     st->relres_true = sqrt(s) / bnorm;
     free(b); free(r); free(p); free(q);
     return st->status == -5 ? -5 : 0;
+}
+
+/* Threads the OpenMP loops above use (1 without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -92,6 +92,8 @@ int orc_cg(int64_t row0, int64_t n, const int64_t *ptr, const int32_t *col, cons
            const double *b, double *x, int x_given, double tol, int max_iter, int singular,
            orc_cg_stats *st);
 
+int orc_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

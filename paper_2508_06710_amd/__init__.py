@@ -128,6 +128,20 @@ class Mesh:
 _DT = {F64: "float64", F32: "float32"}
 
 
+def expand_csr(mesh: Mesh, k: int, dz: float, coupling: int = PERIODIC_Z, wall_bc: int = NEUMANN):
+    """Host: the assembled 3D Laplacian I_k (x) A_b + C as CSR arrays (ptr, col, val)."""
+    d = _lib.OpDesc()
+    d.k, d.coupling, d.dz, d.wall_bc, d.with_f32 = int(k), int(coupling), float(dz), int(wall_bc), 0
+    nnz = C.c_int64()
+    check(lib().fvx_expand_csr(mesh._h, C.byref(d), C.byref(nnz), None, None, None), "fvx_expand_csr")
+    ptr = np.zeros(k * mesh.n_cells + 1, np.int32)
+    col = np.zeros(max(nnz.value, 1), np.int32)
+    val = np.zeros(max(nnz.value, 1))
+    check(lib().fvx_expand_csr(mesh._h, C.byref(d), C.byref(nnz), _np_ptr(ptr), _np_ptr(col), _np_ptr(val)),
+          "fvx_expand_csr")
+    return ptr, col[:nnz.value], val[:nnz.value]
+
+
 class Operator:
     """Repeated-block operator L = I_k (x) A_b + C (plus M_b, G_b) on the device."""
 
@@ -208,6 +222,13 @@ class Operator:
         check(lib().fvx_div(self._h, dt, _ptr(Uf), _ptr(Wz), _ptr(D), _stream(stream)), "fvx_div")
         return D
 
+    def grad_axpy(self, alpha, P, Gf, Gz=None, dtype=None, stream=None):
+        """Gf += alpha * G P (and Gz on the faces between planes)."""
+        dt = dtype if dtype is not None else (F32 if str(P.dtype).endswith("float32") else F64)
+        check(lib().fvx_grad_axpy(self._h, dt, float(alpha), _ptr(P), _ptr(Gf), _ptr(Gz), _stream(stream)),
+              "fvx_grad_axpy")
+        return Gf, Gz
+
     def grad(self, P, Gf=None, Gz=None, dtype=None, stream=None):
         dt = dtype if dtype is not None else (F32 if str(P.dtype).endswith("float32") else F64)
         Gf = self.empty(self.F_b, dt) if Gf is None else Gf
@@ -256,3 +277,49 @@ class Operator:
             except Exception:
                 pass
             self._h = None
+
+
+class CsrMatrix:
+    """An assembled CSR matrix on the device (the no-block-reuse comparator)."""
+
+    def __init__(self, ptr, col, val, device=None):
+        torch = _torch()
+        dev = torch.device(device if device is not None else "cuda")
+        self.n = len(ptr) - 1
+        self.nnz = len(col)
+        self.ptr = torch.as_tensor(np.ascontiguousarray(ptr, np.int32)).to(dev)
+        self.col = torch.as_tensor(np.ascontiguousarray(col, np.int32)).to(dev)
+        self.val = torch.as_tensor(np.ascontiguousarray(val, np.float64)).to(dev)
+        self.device = dev
+        self._ws = None
+
+    def spmv(self, x, y=None, stream=None):
+        torch = _torch()
+        y = torch.empty(self.n, dtype=torch.float64, device=self.device) if y is None else y
+        check(lib().fvx_csr_spmv(self.n, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(x), _ptr(y),
+                                 _stream(stream)), "fvx_csr_spmv")
+        return y
+
+    def solve(self, b, x=None, singular=True, stream=None, allow_not_converged=False, rtol=1e-8,
+              max_iter=100000, guess=GUESS_ZERO, poll_every=64):
+        torch = _torch()
+        o = SolveOpts()
+        check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
+        o.rtol, o.max_iter, o.guess, o.poll_every = float(rtol), int(max_iter), int(guess), int(poll_every)
+        nbytes = C.c_size_t()
+        check(lib().fvx_csr_solve_bytes(self.n, C.byref(nbytes)), "fvx_csr_solve_bytes")
+        if self._ws is None or self._ws.numel() < nbytes.value:
+            self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        x = torch.zeros(self.n, dtype=torch.float64, device=self.device) if x is None else x
+        st = SolveStats()
+        rc = lib().fvx_csr_poisson_solve(self.n, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(b), _ptr(x),
+                                         int(singular), C.byref(o), _ptr(self._ws), self._ws.numel(), C.byref(st),
+                                         _stream(stream))
+        check(rc, "fvx_csr_poisson_solve", (0, 1) if allow_not_converged else (0,))
+        return x, st.as_dict()
+
+
+def copy(dst, src, nbytes=None, stream=None):
+    """Device streaming copy (the bandwidth reference kernel)."""
+    n = dst.numel() * dst.element_size() if nbytes is None else nbytes
+    check(lib().fvx_copy(_ptr(dst), _ptr(src), n, _stream(stream)), "fvx_copy")

@@ -78,12 +78,19 @@ SIGNATURES = {
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "fvx_grad_axpy": (C.c_int, [_vp, C.c_int, C.c_double, _vp, _vp, _vp, _vp]),
     "fvx_pack": (C.c_int, [_vp, C.c_int, _i64, _vp, _vp, _vp]),
     "fvx_unpack": (C.c_int, [_vp, C.c_int, _i64, _vp, _vp, _vp]),
     "fvx_solve_opts_default": (C.c_int, [_P(SolveOpts)]),
     "fvx_solve_bytes": (C.c_int, [_vp, _P(SolveOpts), _P(C.c_size_t)]),
     "fvx_poisson_solve": (C.c_int, [_vp, _vp, _vp, _P(SolveOpts), _vp, C.c_size_t,
                                     _P(SolveStats), _vp]),
+    "fvx_expand_csr": (C.c_int, [_vp, _P(OpDesc), _P(_i64), _vp, _vp, _vp]),
+    "fvx_csr_spmv": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fvx_csr_solve_bytes": (C.c_int, [_i64, _P(C.c_size_t)]),
+    "fvx_csr_poisson_solve": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
+                                        C.c_size_t, _P(SolveStats), _vp]),
+    "fvx_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
 }
 
 _lib = None

@@ -114,7 +114,8 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *colscale, hipS
 template <typename T>
 void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s);
 template <typename T>
-void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s);
+void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s, double alpha = 1.0,
+                 bool acc = false);
 template <typename T>
 void launch_pack(const fvx_op *op, int64_t n_rows, const T *src, T *dst, bool to_rows, hipStream_t s);
 
@@ -144,5 +145,10 @@ struct RowGrid {
     int n_blocks;
 };
 RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks);
+
+// Assembled 3D Laplacian (plane-major rows l*n_b + c) expanded from the base
+// block and the plane coupling: the "no block reuse" form of the operator.
+void expand_csr(const fvx_mesh &m, const fvx_op_desc &d, std::vector<int32_t> &ptr, std::vector<int32_t> &col,
+                std::vector<double> &val);
 
 }  // namespace fvx

@@ -69,22 +69,45 @@ __device__ __forceinline__ T right_of(const vec_t<T, V> &xo, const PlaneNeighbou
     return (l == k - 1 || t + 1 >= V) ? n.rightV : xo[t + 1 < V ? t + 1 : 0];
 }
 
+// Row loaders: how a lap SpMM reads its input multivector.  PlainLoad reads
+// X; DirLoad forms the CG search direction r + beta p on the fly (beta per
+// column), so the SpMM and the direction update share one pass.
+template <typename T, int V>
+struct PlainLoad {
+    const T *__restrict__ X;
+    int ld;
+    __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const { return ldv<T, V>(X + row * ld + c0); }
+    __device__ __forceinline__ T scalar(int64_t row, int l) const { return X[row * ld + l]; }
+};
+
+template <typename T, int V>
+struct DirLoad {
+    const T *__restrict__ R;
+    const T *__restrict__ P;
+    int ld;
+    vec_t<T, V> beta;  // beta of this lane's V columns (equal entries when global)
+    __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const {
+        return ldv<T, V>(R + row * ld + c0) + beta * ldv<T, V>(P + row * ld + c0);
+    }
+    __device__ __forceinline__ T scalar(int64_t row, int l) const { return R[row * ld + l] + beta[0] * P[row * ld + l]; }
+};
+
 // One row and one V-wide column chunk of the Laplacian SpMM:
 //   acc = diag_i x_i + sum_e a_ie x_{j(e)} + w_i (x_i[l+1] + x_i[l-1])
 // The row's matrix entries are loaded once and applied to all V columns of
 // the lane (and, across the lanes of the row group, to all k columns).
-// xo returns this row's own V values (used by fused dot products).
-template <typename T, int V, bool Z>
-__device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b,
-                                               int k, int ld, int W, int64_t row, int c0, int sub, int lpr,
-                                               bool single, vec_t<T, V> &xo) {
+// xo returns this row's own V input values (used by fused dot products).
+template <typename T, int V, bool Z, class Ld>
+__device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &in, int64_t n_b, int k, int W,
+                                                  int64_t row, int c0, int sub, int lpr, bool single,
+                                                  vec_t<T, V> &xo) {
     using vt = vec_t<T, V>;
-    xo = ldv<T, V>(X + row * ld + c0);
+    xo = in.vec(row, c0);
     vt acc = A.diag[row] * xo;
     for (int e = 0; e < W; ++e) {
         const int64_t j = A.ell_col[e * n_b + row];
         const T v = A.ell_val[e * n_b + row];
-        acc += v * ldv<T, V>(X + j * ld + c0);
+        acc += v * in.vec(j, c0);
     }
     if constexpr (Z) {
         const T wr = A.w[row];
@@ -96,15 +119,21 @@ __device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__res
                 acc[t] += wr * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
             }
         } else {
-            const T *xr = X + row * ld;
 #pragma unroll
             for (int t = 0; t < V; ++t) {
                 const int l = c0 + t;
-                if (l < k) acc[t] += wr * (xr[l == 0 ? k - 1 : l - 1] + xr[l == k - 1 ? 0 : l + 1]);
+                if (l < k) acc[t] += wr * (in.scalar(row, l == 0 ? k - 1 : l - 1) + in.scalar(row, l == k - 1 ? 0 : l + 1));
             }
         }
     }
     return acc;
+}
+
+template <typename T, int V, bool Z>
+__device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b, int k,
+                                               int ld, int W, int64_t row, int c0, int sub, int lpr, bool single,
+                                               vec_t<T, V> &xo) {
+    return lap_row_ld<T, V, Z>(A, PlainLoad<T, V>{X, ld}, n_b, k, W, row, c0, sub, lpr, single, xo);
 }
 
 // Launch arguments of a row-tiled kernel (lanes_per_row lanes per row,

@@ -207,6 +207,46 @@ RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks) {
     return g;
 }
 
+void expand_csr(const fvx_mesh &m, const fvx_op_desc &d, std::vector<int32_t> &ptr, std::vector<int32_t> &col,
+                std::vector<double> &val) {
+    check_desc(&m, &d);
+    const HostOp h = build_host(m, d);
+    const int64_t nb = h.n_b, N = nb * int64_t(d.k);
+    FVX_REQUIRE(N < (int64_t(1) << 31), FVX_E_ARG, "expanded matrix too large for int32 indices");
+    const bool zf = d.coupling == FVX_COUPLING_PERIODIC_Z && d.k >= 2;
+    ptr.assign(size_t(N) + 1, 0);
+    col.clear();
+    val.clear();
+    std::vector<std::pair<int32_t, double>> row;
+    for (int l = 0; l < d.k; ++l) {
+        const int64_t off = int64_t(l) * nb;
+        for (int64_t i = 0; i < nb; ++i) {
+            row.clear();
+            row.push_back({int32_t(off + i), h.diag[i]});
+            for (int e = 0; e < h.W; ++e) {
+                const int32_t j = h.ell_col[size_t(e) * nb + i];
+                if (j == i) continue;  // padding
+                row.push_back({int32_t(off + j), h.ell_val[size_t(e) * nb + i]});
+            }
+            if (zf) {
+                row.push_back({int32_t(((l + 1) % d.k) * nb + i), h.w[i]});
+                row.push_back({int32_t(((l - 1 + d.k) % d.k) * nb + i), h.w[i]});
+            }
+            std::sort(row.begin(), row.end(), [](auto &a, auto &b) { return a.first < b.first; });
+            for (size_t e = 0; e < row.size(); ++e) {
+                if (!col.empty() && int64_t(col.size()) > ptr[off + i] && col.back() == row[e].first)
+                    val.back() += row[e].second;
+                else {
+                    col.push_back(row[e].first);
+                    val.push_back(row[e].second);
+                }
+            }
+            FVX_REQUIRE(col.size() < (size_t(1) << 31), FVX_E_ARG, "expanded matrix too large for int32 indices");
+            ptr[off + i + 1] = int32_t(col.size());
+        }
+    }
+}
+
 }  // namespace fvx
 
 using fvx::guard;
@@ -339,6 +379,21 @@ int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile) {
         FVX_REQUIRE(dtype == FVX_F64 || dtype == FVX_F32, FVX_E_ARG, "dtype must be F64 or F32");
         fvx::check_tile(op, dtype, *tile);
         op->tile[dtype] = *tile;
+        return FVX_OK;
+    });
+}
+
+int fvx_expand_csr(const fvx_mesh *m, const fvx_op_desc *d, int64_t *nnz, int32_t *ptr, int32_t *col,
+                   double *val) {
+    return guard([&] {
+        FVX_REQUIRE(m && d && nnz, FVX_E_ARG, "NULL argument");
+        std::vector<int32_t> p, c;
+        std::vector<double> v;
+        fvx::expand_csr(*m, *d, p, c, v);
+        *nnz = int64_t(c.size());
+        if (ptr) std::memcpy(ptr, p.data(), sizeof(int32_t) * p.size());
+        if (col) std::memcpy(col, c.data(), sizeof(int32_t) * c.size());
+        if (val) std::memcpy(val, v.data(), sizeof(double) * v.size());
         return FVX_OK;
     });
 }

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict_
 // planes (rows [F_b, F_b + n_b)).
 template <typename T, int V, bool Z>
 __global__ __launch_bounds__(1024) void k_grad(RowArgs<T> a, const T *__restrict__ P, T *__restrict__ Gf,
-                                               T *__restrict__ Gz) {
+                                               T *__restrict__ Gz, T alpha, int acc) {
     const int lpr = a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
@@ -96,7 +96,8 @@ __global__ __launch_bounds__(1024) void k_grad(RowArgs<T> a, const T *__restrict
             const int64_t c1 = a.A.f_c1[row], c2 = a.A.f_c2[row];
             const T inv = a.A.f_invd[row];
             for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
-                const vec_t<T, V> g = (ldv<T, V>(P + c2 * a.ld + c0) - ldv<T, V>(P + c1 * a.ld + c0)) * inv;
+                vec_t<T, V> g = (ldv<T, V>(P + c2 * a.ld + c0) - ldv<T, V>(P + c1 * a.ld + c0)) * inv;
+                if (acc) g = ldv<T, V>(Gf + row * a.ld + c0) + alpha * g;
                 stv_masked<T, V>(Gf + row * a.ld + c0, g, a.k - c0);
             }
         } else if constexpr (Z) {
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(1024) void k_grad(RowArgs<T> a, const T *__restrict
                         g[q] = l < a.k ? (pr[l == a.k - 1 ? 0 : l + 1] - po[q]) * inv : T(0);
                     }
                 }
+                if (acc) g = ldv<T, V>(Gz + i * a.ld + c0) + alpha * g;
                 stv_masked<T, V>(Gz + i * a.ld + c0, g, a.k - c0);
             }
         }
@@ -198,14 +200,14 @@ void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s) 
 }
 
 template <typename T>
-void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s) {
+void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s, double alpha, bool acc) {
     RowGrid g;
     const int64_t rows = op->F_b + (op->zfaces ? op->n_b : 0);
     const fvx_tile &t = op->tile[dtype_of<T>()];
     auto a = row_args<T>(op, rows, g, t);
     by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
         hipLaunchKernelGGL((k_grad<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
-                           s, a, P, Gf, Gz);
+                           s, a, P, Gf, Gz, T(alpha), int(acc));
     });
     FVX_HIP(hipGetLastError());
 }
@@ -222,8 +224,8 @@ template void launch_lap<double>(const fvx_op *, const double *, double *, const
 template void launch_lap<float>(const fvx_op *, const float *, float *, const double *, hipStream_t);
 template void launch_div<double>(const fvx_op *, const double *, const double *, double *, hipStream_t);
 template void launch_div<float>(const fvx_op *, const float *, const float *, float *, hipStream_t);
-template void launch_grad<double>(const fvx_op *, const double *, double *, double *, hipStream_t);
-template void launch_grad<float>(const fvx_op *, const float *, float *, float *, hipStream_t);
+template void launch_grad<double>(const fvx_op *, const double *, double *, double *, hipStream_t, double, bool);
+template void launch_grad<float>(const fvx_op *, const float *, float *, float *, hipStream_t, double, bool);
 template void launch_pack<double>(const fvx_op *, int64_t, const double *, double *, bool, hipStream_t);
 template void launch_pack<float>(const fvx_op *, int64_t, const float *, float *, bool, hipStream_t);
 
@@ -265,7 +267,8 @@ int fvx_div(const fvx_op *op, int dtype, const void *Uf, const void *Wz, void *D
     });
 }
 
-int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream) {
+static int grad_impl(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream, double alpha,
+                     bool acc) {
     return guard([&] {
         fvx::check_dtype(op, dtype);
         fvx::check_ptr(P, "P");
@@ -274,12 +277,20 @@ int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, voi
         if (op->F_b == 0 && !op->zfaces) return FVX_OK;
         if (dtype == FVX_F64)
             fvx::launch_grad<double>(op, static_cast<const double *>(P), static_cast<double *>(Gf),
-                                     static_cast<double *>(Gz), fvx::as_stream(stream));
+                                     static_cast<double *>(Gz), fvx::as_stream(stream), alpha, acc);
         else
             fvx::launch_grad<float>(op, static_cast<const float *>(P), static_cast<float *>(Gf),
-                                    static_cast<float *>(Gz), fvx::as_stream(stream));
+                                    static_cast<float *>(Gz), fvx::as_stream(stream), alpha, acc);
         return FVX_OK;
     });
+}
+
+int fvx_grad(const fvx_op *op, int dtype, const void *P, void *Gf, void *Gz, void *stream) {
+    return grad_impl(op, dtype, P, Gf, Gz, stream, 1.0, false);
+}
+
+int fvx_grad_axpy(const fvx_op *op, int dtype, double alpha, const void *P, void *Gf, void *Gz, void *stream) {
+    return grad_impl(op, dtype, P, Gf, Gz, stream, alpha, true);
 }
 
 int fvx_pack(const fvx_op *op, int dtype, int64_t n_rows, const void *src, void *dst, void *stream) {

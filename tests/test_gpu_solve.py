@@ -139,3 +139,34 @@ def test_mixed_precision_reaches_fp64_residual(spec, k, coupling):
     err = np.linalg.norm(x - xr) / np.linalg.norm(xr)
     print(f"mixed vs fp64 solution: rel err {err:.2e}, inner iters {st['iters']}, outer {st['outer']}")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("spec,k", [(inputs.channel_base(64, 64), 8), (inputs.unit_square_triangles(8), 3)])
+def test_assembled_csr_comparator(spec, k):
+    """The no-block-reuse comparator: its SpMV reproduces the oracle product and
+    its textbook CG reaches the tolerance with the oracle's iteration count."""
+    c = Case(spec, k)
+    fvx = c.fvx
+    ptr, col, val = fvx.expand_csr(c.op.mesh, k, c.dz, fvx.PERIODIC_Z)
+    A = fvx.CsrMatrix(ptr, col, val)
+    x = inputs.uniform(21, 0, c.m3.N)
+    y = A.spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+    from helpers import componentwise
+    assert componentwise(y, oracle.spmv(c.L, x), c.L, x) <= 1e-12
+    b = inputs.rhs_uniform(22, c.m3.N)
+    xs, st = A.solve(torch.as_tensor(b).cuda(), rtol=1e-10)
+    xs = xs.cpu().numpy()
+    assert max(_true_relres(c, xs, b)) <= 1.05e-10
+    ref = oracle.cg(c.m3, c.L, b, 1e-10)
+    assert abs(st["iters"] - ref.iters[0]) <= max(2, math.ceil(0.01 * ref.iters[0]))
+    assert abs(xs.mean()) <= 1e-13 * np.abs(xs).max()
+
+
+def test_copy_kernel():
+    fvx = __import__("paper_2508_06710_amd")
+    src = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    fvx.copy(dst, src)
+    assert torch.equal(dst, src)
+    with pytest.raises(fvx.FvxError):
+        fvx.copy(dst[1:], src[1:], 8 * 100)
