@@ -138,9 +138,13 @@ typedef struct fvx_op_desc {
 /* Launch tile of the SpMM kernels: vec = elements per lane per load (FP64:
  * 1 or 2, FP32: 1, 2 or 4); lanes_per_row = lanes sharing one matrix row
  * (power of two, 1..64); block = threads per workgroup (64..1024, multiple of
- * 64); xcd_remap = nonzero maps consecutive row tiles to the same XCD. */
+ * 64); xcd_remap = nonzero maps consecutive row tiles to the same XCD;
+ * max_blocks = cap on workgroups (each then walks several consecutive row
+ * tiles), 0 = one tile per workgroup; rows = rows a row group keeps in
+ * flight at once (1 or 2); nt_store = nonzero writes the SpMM output with
+ * non-temporal stores (it is not re-read by the same kernel). */
 typedef struct fvx_tile {
-    int32_t vec, lanes_per_row, block, xcd_remap;
+    int32_t vec, lanes_per_row, block, xcd_remap, max_blocks, rows, nt_store;
 } fvx_tile;
 
 /* Device bytes the operator needs (query before fvx_op_create). */
@@ -166,6 +170,21 @@ int fvx_op_get_tile(const fvx_op *op, int dtype, fvx_tile *tile);
 /* Sets the SpMM tile for one precision.  FVX_E_ARG if the tile is invalid
  * for this operator (vec must divide ld, alignment, ranges above). */
 int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile);
+
+/* Autotuner.  Times the Laplacian SpMM of precision dtype on the device for a
+ * set of candidate tiles (vector width, lanes per row, workgroup size, XCD
+ * remap, workgroup cap) and sets the fastest on the op.  scratch: device
+ * buffer for input/output pairs, at least 2 * n_b * ld * sizeof(element)
+ * bytes; the more pairs fit, the colder the caches (pairs rotate).  results:
+ * optional host array of max_results (tile, microseconds per launch) records,
+ * *n_results receives the count tried.  Every candidate computes the same
+ * product (the tiles are interchangeable); only the timing differs. */
+typedef struct fvx_tune_result {
+    fvx_tile tile;
+    double us;
+} fvx_tune_result;
+int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_bytes, int reps, void *stream,
+             fvx_tune_result *results, int max_results, int *n_results);
 
 /* Laplacian SpMM (Algorithm 1 with the plane coupling):
  *   Y[i][l] = s_l ( sum_j A_b[i][j] X[j][l] + w_i (X[i][l+1 mod k] + X[i][l-1 mod k]) )

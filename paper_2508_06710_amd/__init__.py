@@ -205,9 +205,24 @@ class Operator:
         check(lib().fvx_op_get_tile(self._h, dtype, C.byref(t)), "fvx_op_get_tile")
         return t.as_tuple()
 
-    def set_tile(self, vec, lanes_per_row, block=256, xcd_remap=1, dtype=F64):
-        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap))
+    def set_tile(self, vec, lanes_per_row, block=256, xcd_remap=1, max_blocks=0, rows=1, nt_store=0, dtype=F64):
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), int(rows),
+                 int(nt_store))
         check(lib().fvx_op_set_tile(self._h, dtype, C.byref(t)), "fvx_op_set_tile")
+
+    def tune(self, dtype=F64, scratch_bytes=None, reps=3, max_results=512, stream=None):
+        """Times candidate SpMM tiles on the device and keeps the fastest.
+        Returns [(tile tuple, us per launch), ...] in the order tried."""
+        torch = _torch()
+        esize = 8 if dtype == F64 else 4
+        pair = 2 * self.n_b * self.ld * esize
+        nbytes = max(pair, int(scratch_bytes) if scratch_bytes else pair)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        res = (_lib.TuneResult * max_results)()
+        n = C.c_int()
+        check(lib().fvx_tune(self._h, dtype, _ptr(scratch), nbytes, int(reps), _stream(stream), res, max_results,
+                             C.byref(n)), "fvx_tune")
+        return [(res[i].tile.as_tuple(), res[i].us) for i in range(min(n.value, max_results))]
 
     # ---- operators --------------------------------------------------------
     def lap(self, X, Y=None, colscale=None, dtype=None, stream=None):

@@ -27,10 +27,16 @@ class OpDesc(C.Structure):
 
 class Tile(C.Structure):
     _fields_ = [("vec", C.c_int32), ("lanes_per_row", C.c_int32), ("block", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("max_blocks", C.c_int32), ("rows", C.c_int32),
+                ("nt_store", C.c_int32)]
 
     def as_tuple(self):
-        return (self.vec, self.lanes_per_row, self.block, self.xcd_remap)
+        return (self.vec, self.lanes_per_row, self.block, self.xcd_remap, self.max_blocks, self.rows,
+                self.nt_store)
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("tile", Tile), ("us", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -75,6 +81,7 @@ SIGNATURES = {
     "fvx_op_singular": (C.c_int, [_vp]),
     "fvx_op_get_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
     "fvx_op_set_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
+    "fvx_tune": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.c_int, _vp, _vp, C.c_int, _P(C.c_int)]),
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, 
 
 // A: direction update fused with the SpMM.  rr: partial sums of r.r after the
 // previous iteration (or after init, with bb the b.b sums, when it == 0).
-template <typename T, int V, bool Z>
+template <typename T, int V, bool Z, int WT>
 __global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int it, Src rr, Src bb,
                                                       const T *__restrict__ r, const T *__restrict__ p_old,
                                                       T *__restrict__ p_new, T *__restrict__ q) {
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int
 #pragma unroll
         for (int u = 0; u < V; ++u) in.beta[u] = T(s_beta[d.percol ? (c0 + u < a.k ? c0 + u : 0) : 0]);
         vec_t<T, V> pn;
-        const vec_t<T, V> acc = lap_row_ld<T, V, Z>(a.A, in, a.n_b, a.k, a.W, row, c0, sub, lpr, single, pn);
+        const vec_t<T, V> acc = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, row, c0, sub, lpr, single, pn);
         stv_masked<T, V>(p_new + row * a.ld + c0, pn, a.k - c0);
         stv_masked<T, V>(q + row * a.ld + c0, acc, a.k - c0);
 #pragma unroll
@@ -548,12 +548,15 @@ void run_cg(const fvx_op *op, CgDev d, const T *b, T *x, T *bp, T *r, T *p0, T *
         while (true) {
             const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
             for (int i = 0; i < batch; ++i, ++it) {
-                if (op->zfaces)
-                    hipLaunchKernelGGL((k_cg_a<T, V, true>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r, pold, pnew,
-                                       q);
-                else
-                    hipLaunchKernelGGL((k_cg_a<T, V, false>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r, pold, pnew,
-                                       q);
+                by_width(op->W, [&](auto Wt) {
+                    constexpr int WT = decltype(Wt)::value;
+                    if (op->zfaces)
+                        hipLaunchKernelGGL((k_cg_a<T, V, true, WT>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r,
+                                           pold, pnew, q);
+                    else
+                        hipLaunchKernelGGL((k_cg_a<T, V, false, WT>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r,
+                                           pold, pnew, q);
+                });
                 const Src pq = fold_or_direct(d, d.part_a, 1, nb, 0, d.tot + 2 * d.G, s);
                 hipLaunchKernelGGL((k_cg_b<T, V>), c.grid, c.block, 0, s, c.a, d, it, pq, x, r, pnew, q);
                 rr = fold_or_direct(d, d.part_b, 1, nb, 0, d.tot, s);
@@ -672,6 +675,9 @@ int solve_mixed(const fvx_op *op, const double *B, double *X, const fvx_solve_op
             if (!std::isfinite(t0[g]) || !std::isfinite(t0[G + g])) status = FVX_E_NONFINITE;
         }
         if (h.st.status < 0) status = h.st.status;
+        // The final projection reads ||b||^2 per group on the device.
+        FVX_HIP(hipMemcpyAsync(D.bnorm2, h.bnorm2.data(), 8 * G, hipMemcpyHostToDevice, s));
+        FVX_HIP(hipStreamSynchronize(s));
         if (status < 0) return;
         std::vector<double> gmean(G), gact(G);
         for (outer = 0;; ++outer) {

@@ -103,6 +103,29 @@ inline int next_pow2(int v) {
 // aligned for both precisions).
 inline int32_t ld_for_k(int32_t k) { return (k <= 2 || k % 4 == 0) ? k : (k + 3) / 4 * 4; }
 
+// ELL widths the kernels are compiled for (all gathers of a row issue before
+// the first multiply-add); rows are padded to the next of them.  Wider rows
+// use a loop over a run-time width.
+inline int ell_width(int w) {
+    if (w == 0) return 0;  // no neighbours: nothing to gather, nothing to pad
+    for (int c : {3, 4, 6, 8})
+        if (w <= c) return c;
+    return w;
+}
+
+// Calls f(std::integral_constant<int, W>) for a compiled width, or with 0
+// (run-time width) otherwise.
+template <typename F>
+void by_width(int w, F &&f) {
+    switch (w) {
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        default: f(std::integral_constant<int, 0>{}); break;
+    }
+}
+
 fvx_tile default_tile(const fvx_op *op, int dtype);
 void check_tile(const fvx_op *op, int dtype, const fvx_tile &t);
 

@@ -15,9 +15,12 @@ __device__ __forceinline__ vec_t<T, V> ldv(const T *p) {
 }
 
 template <typename T, int V>
-__device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid) {
+__device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid, bool nt = false) {
     if (valid >= V) {
-        *reinterpret_cast<vec_t<T, V> *>(p) = v;
+        if (nt)
+            __builtin_nontemporal_store(v, reinterpret_cast<vec_t<T, V> *>(p));
+        else
+            *reinterpret_cast<vec_t<T, V> *>(p) = v;
     } else {
 #pragma unroll
         for (int t = 0; t < V; ++t)
@@ -97,17 +100,37 @@ struct DirLoad {
 // The row's matrix entries are loaded once and applied to all V columns of
 // the lane (and, across the lanes of the row group, to all k columns).
 // xo returns this row's own V input values (used by fused dot products).
-template <typename T, int V, bool Z, class Ld>
+template <typename T, int V, bool Z, int WT, class Ld>
 __device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &in, int64_t n_b, int k, int W,
                                                   int64_t row, int c0, int sub, int lpr, bool single,
                                                   vec_t<T, V> &xo) {
     using vt = vec_t<T, V>;
-    xo = in.vec(row, c0);
-    vt acc = A.diag[row] * xo;
-    for (int e = 0; e < W; ++e) {
-        const int64_t j = A.ell_col[e * n_b + row];
-        const T v = A.ell_val[e * n_b + row];
-        acc += v * in.vec(j, c0);
+    vt acc;
+    if constexpr (WT > 0) {
+        // Compiled width: every column index and value, then every gather, is
+        // in flight before the first multiply-add.
+        int32_t col[WT];
+        T val[WT];
+#pragma unroll
+        for (int e = 0; e < WT; ++e) {
+            col[e] = A.ell_col[e * n_b + row];
+            val[e] = A.ell_val[e * n_b + row];
+        }
+        xo = in.vec(row, c0);
+        vt xj[WT];
+#pragma unroll
+        for (int e = 0; e < WT; ++e) xj[e] = in.vec(col[e], c0);
+        acc = A.diag[row] * xo;
+#pragma unroll
+        for (int e = 0; e < WT; ++e) acc += val[e] * xj[e];
+    } else {
+        xo = in.vec(row, c0);
+        acc = A.diag[row] * xo;
+        for (int e = 0; e < W; ++e) {
+            const int64_t j = A.ell_col[e * n_b + row];
+            const T v = A.ell_val[e * n_b + row];
+            acc += v * in.vec(j, c0);
+        }
     }
     if constexpr (Z) {
         const T wr = A.w[row];
@@ -129,11 +152,11 @@ __device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &i
     return acc;
 }
 
-template <typename T, int V, bool Z>
+template <typename T, int V, bool Z, int WT>
 __device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b, int k,
                                                int ld, int W, int64_t row, int c0, int sub, int lpr, bool single,
                                                vec_t<T, V> &xo) {
-    return lap_row_ld<T, V, Z>(A, PlainLoad<T, V>{X, ld}, n_b, k, W, row, c0, sub, lpr, single, xo);
+    return lap_row_ld<T, V, Z, WT>(A, PlainLoad<T, V>{X, ld}, n_b, k, W, row, c0, sub, lpr, single, xo);
 }
 
 // Launch arguments of a row-tiled kernel (lanes_per_row lanes per row,
@@ -142,7 +165,7 @@ template <typename T>
 struct RowArgs {
     OpDev<T> A;
     int64_t n_b, n_rows;
-    int k, ld, W, Wd, lpr, rows_per_tile, remap;
+    int k, ld, W, Wd, lpr, rows_per_tile, remap, nt;
     int64_t tiles_per_block;
     int64_t F_b;
 };
@@ -150,6 +173,7 @@ struct RowArgs {
 template <typename T>
 inline RowArgs<T> row_args(const fvx_op *op, int64_t n_rows, RowGrid &g, const fvx_tile &t,
                            int max_blocks = 1 << 22) {
+    if (t.max_blocks > 0) max_blocks = std::min(max_blocks, t.max_blocks);
     g = row_grid(n_rows, t, max_blocks);
     RowArgs<T> a;
     a.A = dev<T>(op);
@@ -162,6 +186,7 @@ inline RowArgs<T> row_args(const fvx_op *op, int64_t n_rows, RowGrid &g, const f
     a.lpr = t.lanes_per_row;
     a.rows_per_tile = g.rows_per_tile;
     a.remap = t.xcd_remap;
+    a.nt = t.nt_store;
     a.tiles_per_block = g.tiles_per_block;
     a.F_b = op->F_b;
     return a;

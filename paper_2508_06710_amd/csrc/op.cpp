@@ -62,6 +62,7 @@ HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
 
     h.W = 0;
     for (int64_t i = 0; i < nb; ++i) h.W = std::max<int>(h.W, int(nbr[i].size()));
+    h.W = ell_width(h.W);
     h.ell_col.assign(size_t(h.W) * nb, 0);
     h.ell_val.assign(size_t(h.W) * nb, 0.0);
     h.diag32.assign(nb, 0.0f);
@@ -98,6 +99,7 @@ HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
     }
     h.Wd = 0;
     for (int64_t i = 0; i < nb; ++i) h.Wd = std::max<int>(h.Wd, int(inc[i].size()));
+    h.Wd = ell_width(h.Wd);
     h.cf_face.assign(size_t(h.Wd) * nb, 0);
     h.cf_coef.assign(size_t(h.Wd) * nb, 0.0);
     for (int64_t i = 0; i < nb; ++i)
@@ -181,6 +183,9 @@ fvx_tile default_tile(const fvx_op *op, int dtype) {
     t.lanes_per_row = std::min(64, next_pow2(int(ceil_div(op->k, v))));
     t.block = 256;
     t.xcd_remap = 1;
+    t.max_blocks = 0;
+    t.rows = 1;
+    t.nt_store = 0;
     return t;
 }
 
@@ -194,6 +199,10 @@ void check_tile(const fvx_op *op, int dtype, const fvx_tile &t) {
                 FVX_E_ARG, "tile.lanes_per_row must be a power of two in 1..64");
     FVX_REQUIRE(t.block >= 64 && t.block <= 1024 && t.block % 64 == 0, FVX_E_ARG,
                 "tile.block must be a multiple of 64 in 64..1024");
+    FVX_REQUIRE(t.block >= t.lanes_per_row, FVX_E_ARG, "tile.block must hold one row group");
+    FVX_REQUIRE(t.max_blocks >= 0, FVX_E_ARG, "tile.max_blocks must be >= 0");
+    FVX_REQUIRE(t.rows == 1 || t.rows == 2, FVX_E_ARG, "tile.rows must be 1 or 2");
+    FVX_REQUIRE(t.nt_store == 0 || t.nt_store == 1, FVX_E_ARG, "tile.nt_store must be 0 or 1");
 }
 
 RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks) {

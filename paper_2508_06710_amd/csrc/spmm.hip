@@ -13,8 +13,11 @@
 namespace fvx {
 namespace {
 
-// Y = (I_k (x) A_b + C) X, optionally scaled per column.
-template <typename T, int V, bool Z>
+// Y = (I_k (x) A_b + C) X, optionally scaled per column.  With R = 2 a row
+// group works on two rows at once (rows of consecutive tiles): both rows'
+// loads are in flight before either row's multiply-adds.  The second row of
+// the last pair is clamped to a valid row and its result is not stored.
+template <typename T, int V, bool Z, int WT, int R>
 __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                               const double *__restrict__ cs) {
     const int lpr = a.lpr;
@@ -22,25 +25,42 @@ __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict_
     const int grp = threadIdx.x / lpr;
     const bool single = lpr * V >= a.k;
     const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
-    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
-        const int64_t row = t * a.rows_per_tile + grp;
-        if (row >= a.n_rows) break;
-        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
-            vec_t<T, V> xo;
-            vec_t<T, V> acc = lap_row<T, V, Z>(a.A, X, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, xo);
-            if (cs) {
+    const int64_t t_end = t0 + a.tiles_per_block;
+    for (int64_t t = t0; t < t_end; t += R) {
+        int64_t row[R];
+        bool ok[R];
 #pragma unroll
-                for (int q = 0; q < V; ++q)
-                    if (c0 + q < a.k) acc[q] *= T(cs[c0 + q]);
+        for (int r = 0; r < R; ++r) {
+            row[r] = (t + r) * a.rows_per_tile + grp;
+            ok[r] = t + r < t_end && row[r] < a.n_rows;
+        }
+        if (!ok[0]) break;
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            if (!ok[r]) row[r] = row[0];
+        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+            vec_t<T, V> acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                vec_t<T, V> xo;
+                acc[r] = lap_row<T, V, Z, WT>(a.A, X, a.n_b, a.k, a.ld, a.W, row[r], c0, sub, lpr, single, xo);
             }
-            stv_masked<T, V>(Y + row * a.ld + c0, acc, a.k - c0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (cs) {
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+                        if (c0 + q < a.k) acc[r][q] *= T(cs[c0 + q]);
+                }
+                if (ok[r]) stv_masked<T, V>(Y + row[r] * a.ld + c0, acc[r], a.k - c0, a.nt != 0);
+            }
         }
     }
 }
 
 // D = M U: integrated divergence of in-plane face fluxes plus the fluxes
 // through the faces between planes.
-template <typename T, int V, bool Z>
+template <typename T, int V, bool Z, int WT>
 __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict__ U, const T *__restrict__ Wz,
                                               T *__restrict__ D) {
     const int lpr = a.lpr;
@@ -53,10 +73,25 @@ __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict_
         if (row >= a.n_rows) break;
         for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
             vec_t<T, V> acc = 0;
-            for (int e = 0; e < a.Wd; ++e) {
-                const int64_t f = a.A.cf_face[e * a.n_b + row];
-                const T c = a.A.cf_coef[e * a.n_b + row];
-                acc += c * ldv<T, V>(U + f * a.ld + c0);
+            if constexpr (WT > 0) {
+                int32_t f[WT];
+                T cf[WT];
+#pragma unroll
+                for (int e = 0; e < WT; ++e) {
+                    f[e] = a.A.cf_face[e * a.n_b + row];
+                    cf[e] = a.A.cf_coef[e * a.n_b + row];
+                }
+                vec_t<T, V> u[WT];
+#pragma unroll
+                for (int e = 0; e < WT; ++e) u[e] = ldv<T, V>(U + int64_t(f[e]) * a.ld + c0);
+#pragma unroll
+                for (int e = 0; e < WT; ++e) acc += cf[e] * u[e];
+            } else {
+                for (int e = 0; e < a.Wd; ++e) {
+                    const int64_t f = a.A.cf_face[e * a.n_b + row];
+                    const T c = a.A.cf_coef[e * a.n_b + row];
+                    acc += c * ldv<T, V>(U + f * a.ld + c0);
+                }
             }
             if constexpr (Z) {
                 const T ar = a.A.area[row];
@@ -181,8 +216,14 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
     const fvx_tile &t = op->tile[dtype_of<T>()];
     auto a = row_args<T>(op, op->n_b, g, t);
     by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
-        hipLaunchKernelGGL((k_lap<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
-                           s, a, X, Y, cs);
+        by_width(op->W, [&](auto Wt) {
+            constexpr int v = decltype(V)::value, wt = decltype(Wt)::value;
+            constexpr bool z = decltype(Z)::value;
+            if (t.rows == 2)
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, 2>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+            else
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, 1>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+        });
     });
     FVX_HIP(hipGetLastError());
 }
@@ -193,8 +234,10 @@ void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s) 
     const fvx_tile &t = op->tile[dtype_of<T>()];
     auto a = row_args<T>(op, op->n_b, g, t);
     by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
-        hipLaunchKernelGGL((k_div<T, decltype(V)::value, decltype(Z)::value>), dim3(g.n_blocks), dim3(t.block), 0,
-                           s, a, U, Wz, D);
+        by_width(op->Wd, [&](auto Wt) {
+            hipLaunchKernelGGL((k_div<T, decltype(V)::value, decltype(Z)::value, decltype(Wt)::value>),
+                               dim3(g.n_blocks), dim3(t.block), 0, s, a, U, Wz, D);
+        });
     });
     FVX_HIP(hipGetLastError());
 }

@@ -90,14 +90,21 @@ def test_every_tile_gives_the_same_product(k):
                 if block < lpr:
                     continue
                 for remap in (0, 1):
-                    c.op.set_tile(vec, lpr, block, remap, fvx.F64)
-                    y, ref, A, x = _lap_check(c, seed=5)
-                    assert componentwise(y, ref, A, x) <= TOL64, (vec, lpr, block, remap)
-                    outs.append(y)
+                    for rows in (1, 2):
+                        cap = (0, 3, 7)[(lpr + block + rows) % 3]  # also caps that leave a ragged last pair
+                        nt = (remap + rows) % 2
+                        c.op.set_tile(vec, lpr, block, remap, cap, rows, nt, dtype=fvx.F64)
+                        y, ref, A, x = _lap_check(c, seed=5)
+                        assert componentwise(y, ref, A, x) <= TOL64, (vec, lpr, block, remap, cap, rows, nt)
+                        outs.append(y)
+    # same order of operations per element in every tile: bit-identical results
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
     with pytest.raises(fvx.FvxError):
-        c.op.set_tile(4, 8, 256, 1, fvx.F64)  # 32-byte vectors are not offered
+        c.op.set_tile(4, 8, 256, 1, dtype=fvx.F64)  # 32-byte vectors are not offered
     with pytest.raises(fvx.FvxError):
-        c.op.set_tile(2, 3, 256, 1, fvx.F64)  # lanes per row must be a power of two
+        c.op.set_tile(2, 3, 256, 1, dtype=fvx.F64)  # lanes per row must be a power of two
+    with pytest.raises(fvx.FvxError):
+        c.op.set_tile(2, 8, 256, 1, 0, 3, dtype=fvx.F64)  # rows in flight: 1 or 2
 
 
 @pytest.mark.parametrize("base", list(BASES))

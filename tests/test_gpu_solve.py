@@ -170,3 +170,19 @@ def test_copy_kernel():
     assert torch.equal(dst, src)
     with pytest.raises(fvx.FvxError):
         fvx.copy(dst[1:], src[1:], 8 * 100)
+
+
+def test_mixed_precision_does_not_depend_on_workspace_contents():
+    """Regression: the mixed solve must not read stale per-column norms from a
+    reused workspace (a zeroed and a garbage-filled workspace give the same x)."""
+    c = Case(inputs.channel_base(13, 9), 6, coupling=0)
+    fvx = c.fvx
+    b = c.op.to_rows(inputs.rhs_uniform(8, c.m3.N))
+    opts = dict(rtol=1e-10, precision=fvx.MIXED)
+    ws = c.op.workspace(c.op.solve_opts(**opts))
+    ws.zero_()
+    X1, _ = c.op.solve(b, **opts)
+    ws.fill_(0x7F)
+    X2, _ = c.op.solve(b, **opts)
+    assert torch.equal(X1, X2)
+    assert max(_true_relres(c, c.op.to_planes(X1), c.op.to_planes(b))) <= 1.05e-10
