@@ -140,11 +140,13 @@ typedef struct fvx_op_desc {
  * (power of two, 1..64); block = threads per workgroup (64..1024, multiple of
  * 64); xcd_remap = nonzero maps consecutive row tiles to the same XCD;
  * max_blocks = cap on workgroups (each then walks several consecutive row
- * tiles), 0 = one tile per workgroup; rows = rows a row group keeps in
- * flight at once (1 or 2); nt_store = nonzero writes the SpMM output with
- * non-temporal stores (it is not re-read by the same kernel). */
+ * tiles), 0 = one tile per workgroup; stage_lds = nonzero stages each tile's
+ * base-block rows (column indices, values, diagonal, coupling weight) in LDS
+ * with coalesced loads, shared by all lanes of a row (needs at most 64 rows
+ * per tile, i.e. block / lanes_per_row <= 64); nt_store = nonzero writes the
+ * SpMM output with non-temporal stores (not re-read by the same kernel). */
 typedef struct fvx_tile {
-    int32_t vec, lanes_per_row, block, xcd_remap, max_blocks, rows, nt_store;
+    int32_t vec, lanes_per_row, block, xcd_remap, max_blocks, stage_lds, nt_store;
 } fvx_tile;
 
 /* Device bytes the operator needs (query before fvx_op_create). */
@@ -193,6 +195,11 @@ int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_bytes, int rep
  * per-column output scale c of Algorithm 1, or NULL (s_l = 1). */
 int fvx_lap(const fvx_op *op, int dtype, const void *X, void *Y, const double *colscale,
             void *stream);
+
+/* n Laplacian SpMMs back to back on one stream, Y[i] = L X[i] (e.g. the k
+ * stacked fields of several time levels).  X, Y: host arrays of n device
+ * pointers, each as in fvx_lap. */
+int fvx_lap_many(const fvx_op *op, int dtype, int n, const void *const *X, void *const *Y, void *stream);
 
 /* Divergence SpMM, integrated over cells (M u of Eq. 9a):
  *   D[i][l] = sum_{faces f of i} (+-) len_f dz Uf[f][l] + A_i (Wz[i][l] - Wz[i][l-1 mod k])

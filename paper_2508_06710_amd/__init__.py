@@ -205,8 +205,9 @@ class Operator:
         check(lib().fvx_op_get_tile(self._h, dtype, C.byref(t)), "fvx_op_get_tile")
         return t.as_tuple()
 
-    def set_tile(self, vec, lanes_per_row, block=256, xcd_remap=1, max_blocks=0, rows=1, nt_store=0, dtype=F64):
-        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), int(rows),
+    def set_tile(self, vec, lanes_per_row, block=256, xcd_remap=1, max_blocks=0, stage_lds=0, nt_store=0,
+                 dtype=F64):
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), int(stage_lds),
                  int(nt_store))
         check(lib().fvx_op_set_tile(self._h, dtype, C.byref(t)), "fvx_op_set_tile")
 
@@ -230,6 +231,40 @@ class Operator:
         Y = self.empty(dtype=dt) if Y is None else Y
         check(lib().fvx_lap(self._h, dt, _ptr(X), _ptr(Y), _ptr(colscale), _stream(stream)), "fvx_lap")
         return Y
+
+    def lap_many(self, Xs, Ys, dtype=None, stream=None):
+        """Y[i] = L X[i] for every pair, launched back to back from C."""
+        dt = dtype if dtype is not None else (F32 if str(Xs[0].dtype).endswith("float32") else F64)
+        n = len(Xs)
+        xa = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
+        ya = (C.c_void_p * n)(*[y.data_ptr() for y in Ys])
+        check(lib().fvx_lap_many(self._h, dt, n, xa, ya, _stream(stream)), "fvx_lap_many")
+        return Ys
+
+    def tune_cached(self, dtype=F64, cache_path=None, scratch_bytes=int(1.1 * 2 ** 30), reps=2):
+        """Autotuned tile, cached in a JSON file keyed by (device architecture,
+        precision, k, ld, base rows, ELL width class).  Returns (tile, source)."""
+        import json
+        import os
+        torch = _torch()
+        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
+        key = f"{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}|nnz_b={self.nnz_b}"
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        if key in cache:
+            self.set_tile(*cache[key]["tile"], dtype=dtype)
+            return tuple(cache[key]["tile"]), "cache"
+        res = self.tune(dtype=dtype, scratch_bytes=scratch_bytes, reps=reps)
+        best = self.get_tile(dtype)
+        if cache_path:
+            cache[key] = {"tile": list(best), "us": min(r[1] for r in res), "candidates": len(res)}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return best, "tuned"
 
     def div(self, Uf, Wz=None, D=None, dtype=None, stream=None):
         dt = dtype if dtype is not None else (F32 if str(Uf.dtype).endswith("float32") else F64)

@@ -27,11 +27,11 @@ class OpDesc(C.Structure):
 
 class Tile(C.Structure):
     _fields_ = [("vec", C.c_int32), ("lanes_per_row", C.c_int32), ("block", C.c_int32),
-                ("xcd_remap", C.c_int32), ("max_blocks", C.c_int32), ("rows", C.c_int32),
+                ("xcd_remap", C.c_int32), ("max_blocks", C.c_int32), ("stage_lds", C.c_int32),
                 ("nt_store", C.c_int32)]
 
     def as_tuple(self):
-        return (self.vec, self.lanes_per_row, self.block, self.xcd_remap, self.max_blocks, self.rows,
+        return (self.vec, self.lanes_per_row, self.block, self.xcd_remap, self.max_blocks, self.stage_lds,
                 self.nt_store)
 
 
@@ -83,6 +83,7 @@ SIGNATURES = {
     "fvx_op_set_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
     "fvx_tune": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.c_int, _vp, _vp, C.c_int, _P(C.c_int)]),
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "fvx_lap_many": (C.c_int, [_vp, C.c_int, C.c_int, _P(_vp), _P(_vp), _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_grad_axpy": (C.c_int, [_vp, C.c_int, C.c_double, _vp, _vp, _vp, _vp]),

@@ -92,6 +92,8 @@ int guard(const std::function<int()> &f);
     } while (0)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kMaxStageRows = 64;  // rows per tile whose base-block rows fit the LDS stage
 inline int next_pow2(int v) {
     int p = 1;
     while (p < v) p <<= 1;

@@ -95,42 +95,126 @@ struct DirLoad {
     __device__ __forceinline__ T scalar(int64_t row, int l) const { return R[row * ld + l] + beta[0] * P[row * ld + l]; }
 };
 
-// One row and one V-wide column chunk of the Laplacian SpMM:
+// One base-block row: its WT off-diagonal column indices and values (padding
+// entries point at the row itself with value 0), diagonal, and coupling weight.
+template <typename T, int WT>
+struct RowMeta {
+    int32_t col[WT > 0 ? WT : 1];
+    T val[WT > 0 ? WT : 1];
+    T diag, w;
+};
+
+template <typename T, int WT, bool Z>
+__device__ __forceinline__ RowMeta<T, WT> meta_global(const OpDev<T> &A, int64_t n_b, int64_t row) {
+    RowMeta<T, WT> m;
+#pragma unroll
+    for (int e = 0; e < WT; ++e) {
+        m.col[e] = A.ell_col[e * n_b + row];
+        m.val[e] = A.ell_val[e * n_b + row];
+    }
+    m.diag = A.diag[row];
+    m.w = Z ? A.w[row] : T(0);
+    return m;
+}
+
+// LDS stage of one tile's base-block rows: [rows][WT] columns, [rows][WT]
+// values, [rows] diagonal, [rows] coupling weight.
+__host__ __device__ constexpr size_t stage_col_bytes(int rows, int wt) {
+    return (size_t(rows) * wt * sizeof(int32_t) + 15) / 16 * 16;
+}
+template <typename T, int WT>
+__host__ __device__ constexpr size_t stage_bytes(int rows) {
+    return stage_col_bytes(rows, WT) + size_t(rows) * (WT + 2) * sizeof(T);
+}
+
+// All threads of the block: copy the rows [row0, row0 + rows) of the base
+// block (ELL stride n_b) into the stage with coalesced loads; rows at or past
+// n_valid get the padding pattern (column 0, value 0).
+template <typename T, int WT, bool Z>
+__device__ __forceinline__ void stage_rows(const OpDev<T> &A, int64_t n_b, int64_t n_valid, int64_t row0, int rows,
+                                           char *smem) {
+    int32_t *s_col = reinterpret_cast<int32_t *>(smem);
+    T *s_val = reinterpret_cast<T *>(smem + stage_col_bytes(rows, WT));
+    T *s_dw = s_val + size_t(rows) * WT;
+    for (int i = threadIdx.x; i < rows * WT; i += blockDim.x) {
+        const int e = i / rows, r = i - e * rows;
+        const int64_t row = row0 + r;
+        const bool ok = row < n_valid;
+        s_col[r * WT + e] = ok ? A.ell_col[e * n_b + row] : 0;
+        s_val[r * WT + e] = ok ? A.ell_val[e * n_b + row] : T(0);
+    }
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        const int64_t row = row0 + r;
+        const bool ok = row < n_valid;
+        s_dw[2 * r] = ok ? A.diag[row] : T(0);
+        s_dw[2 * r + 1] = (ok && Z) ? A.w[row] : T(0);
+    }
+}
+
+template <typename T, int WT>
+__device__ __forceinline__ RowMeta<T, WT> meta_staged(const char *smem, int rows, int r) {
+    const int32_t *s_col = reinterpret_cast<const int32_t *>(smem);
+    const T *s_val = reinterpret_cast<const T *>(smem + stage_col_bytes(rows, WT));
+    const T *s_dw = s_val + size_t(rows) * WT;
+    RowMeta<T, WT> m;
+#pragma unroll
+    for (int e = 0; e < WT; ++e) {
+        m.col[e] = s_col[r * WT + e];
+        m.val[e] = s_val[r * WT + e];
+    }
+    m.diag = s_dw[2 * r];
+    m.w = s_dw[2 * r + 1];
+    return m;
+}
+
+// One row and one V-wide column chunk of the Laplacian SpMM from the row's
+// base-block entries (compiled width WT > 0):
 //   acc = diag_i x_i + sum_e a_ie x_{j(e)} + w_i (x_i[l+1] + x_i[l-1])
-// The row's matrix entries are loaded once and applied to all V columns of
-// the lane (and, across the lanes of the row group, to all k columns).
+// Every gather is in flight before the first multiply-add.  The row's entries
+// serve all V columns of the lane (and, across the row group, all k columns).
 // xo returns this row's own V input values (used by fused dot products).
 template <typename T, int V, bool Z, int WT, class Ld>
-__device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &in, int64_t n_b, int k, int W,
-                                                  int64_t row, int c0, int sub, int lpr, bool single,
-                                                  vec_t<T, V> &xo) {
+__device__ __forceinline__ vec_t<T, V> lap_row_meta(const RowMeta<T, WT> &m, const Ld &in, int k, int64_t row,
+                                                    int c0, int sub, int lpr, bool single, vec_t<T, V> &xo) {
     using vt = vec_t<T, V>;
-    vt acc;
-    if constexpr (WT > 0) {
-        // Compiled width: every column index and value, then every gather, is
-        // in flight before the first multiply-add.
-        int32_t col[WT];
-        T val[WT];
+    xo = in.vec(row, c0);
+    vt xj[WT];
 #pragma unroll
-        for (int e = 0; e < WT; ++e) {
-            col[e] = A.ell_col[e * n_b + row];
-            val[e] = A.ell_val[e * n_b + row];
+    for (int e = 0; e < WT; ++e) xj[e] = in.vec(m.col[e], c0);
+    vt acc = m.diag * xo;
+#pragma unroll
+    for (int e = 0; e < WT; ++e) acc += m.val[e] * xj[e];
+    if constexpr (Z) {
+        if (single) {
+            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, k);
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int l = c0 + t;
+                acc[t] += m.w * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                const int l = c0 + t;
+                if (l < k) acc[t] += m.w * (in.scalar(row, l == 0 ? k - 1 : l - 1) + in.scalar(row, l == k - 1 ? 0 : l + 1));
+            }
         }
-        xo = in.vec(row, c0);
-        vt xj[WT];
-#pragma unroll
-        for (int e = 0; e < WT; ++e) xj[e] = in.vec(col[e], c0);
-        acc = A.diag[row] * xo;
-#pragma unroll
-        for (int e = 0; e < WT; ++e) acc += val[e] * xj[e];
-    } else {
-        xo = in.vec(row, c0);
-        acc = A.diag[row] * xo;
-        for (int e = 0; e < W; ++e) {
-            const int64_t j = A.ell_col[e * n_b + row];
-            const T v = A.ell_val[e * n_b + row];
-            acc += v * in.vec(j, c0);
-        }
+    }
+    return acc;
+}
+
+// Same product for a run-time ELL width (rows wider than the compiled widths).
+template <typename T, int V, bool Z, class Ld>
+__device__ __forceinline__ vec_t<T, V> lap_row_dyn(const OpDev<T> &A, const Ld &in, int64_t n_b, int k, int W,
+                                                   int64_t row, int c0, int sub, int lpr, bool single,
+                                                   vec_t<T, V> &xo) {
+    using vt = vec_t<T, V>;
+    xo = in.vec(row, c0);
+    vt acc = A.diag[row] * xo;
+    for (int e = 0; e < W; ++e) {
+        const int64_t j = A.ell_col[e * n_b + row];
+        const T v = A.ell_val[e * n_b + row];
+        acc += v * in.vec(j, c0);
     }
     if constexpr (Z) {
         const T wr = A.w[row];
@@ -150,6 +234,17 @@ __device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &i
         }
     }
     return acc;
+}
+
+// Dispatch on compiled width: global row entries or run-time width.
+template <typename T, int V, bool Z, int WT, class Ld>
+__device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &in, int64_t n_b, int k, int W,
+                                                  int64_t row, int c0, int sub, int lpr, bool single,
+                                                  vec_t<T, V> &xo) {
+    if constexpr (WT > 0)
+        return lap_row_meta<T, V, Z, WT>(meta_global<T, WT, Z>(A, n_b, row), in, k, row, c0, sub, lpr, single, xo);
+    else
+        return lap_row_dyn<T, V, Z>(A, in, n_b, k, W, row, c0, sub, lpr, single, xo);
 }
 
 template <typename T, int V, bool Z, int WT>

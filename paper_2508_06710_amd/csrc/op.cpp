@@ -184,7 +184,7 @@ fvx_tile default_tile(const fvx_op *op, int dtype) {
     t.block = 256;
     t.xcd_remap = 1;
     t.max_blocks = 0;
-    t.rows = 1;
+    t.stage_lds = 0;
     t.nt_store = 0;
     return t;
 }
@@ -201,7 +201,9 @@ void check_tile(const fvx_op *op, int dtype, const fvx_tile &t) {
                 "tile.block must be a multiple of 64 in 64..1024");
     FVX_REQUIRE(t.block >= t.lanes_per_row, FVX_E_ARG, "tile.block must hold one row group");
     FVX_REQUIRE(t.max_blocks >= 0, FVX_E_ARG, "tile.max_blocks must be >= 0");
-    FVX_REQUIRE(t.rows == 1 || t.rows == 2, FVX_E_ARG, "tile.rows must be 1 or 2");
+    FVX_REQUIRE(t.stage_lds == 0 || t.stage_lds == 1, FVX_E_ARG, "tile.stage_lds must be 0 or 1");
+    FVX_REQUIRE(!t.stage_lds || t.block / t.lanes_per_row <= kMaxStageRows, FVX_E_ARG,
+                "tile.stage_lds needs at most 64 rows per tile");
     FVX_REQUIRE(t.nt_store == 0 || t.nt_store == 1, FVX_E_ARG, "tile.nt_store must be 0 or 1");
 }
 

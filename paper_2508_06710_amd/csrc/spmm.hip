@@ -13,47 +13,42 @@
 namespace fvx {
 namespace {
 
-// Y = (I_k (x) A_b + C) X, optionally scaled per column.  With R = 2 a row
-// group works on two rows at once (rows of consecutive tiles): both rows'
-// loads are in flight before either row's multiply-adds.  The second row of
-// the last pair is clamped to a valid row and its result is not stored.
-template <typename T, int V, bool Z, int WT, int R>
+// Y = (I_k (x) A_b + C) X, optionally scaled per column.  With S, each tile's
+// base-block rows are first staged in LDS by the whole workgroup (coalesced
+// loads) and every lane of a row reads them from there.
+template <typename T, int V, bool Z, int WT, bool S>
 __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                               const double *__restrict__ cs) {
+    extern __shared__ __align__(16) char smem[];
     const int lpr = a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const bool single = lpr * V >= a.k;
     const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
-    const int64_t t_end = t0 + a.tiles_per_block;
-    for (int64_t t = t0; t < t_end; t += R) {
-        int64_t row[R];
-        bool ok[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            row[r] = (t + r) * a.rows_per_tile + grp;
-            ok[r] = t + r < t_end && row[r] < a.n_rows;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row0 = t * a.rows_per_tile, row = row0 + grp;
+        if constexpr (S) {
+            if (row0 >= a.n_rows) break;  // uniform across the workgroup
+            __syncthreads();              // the previous tile's readers are done
+            stage_rows<T, WT, Z>(a.A, a.n_b, a.n_rows, row0, a.rows_per_tile, smem);
+            __syncthreads();
+            if (row >= a.n_rows) continue;
+        } else {
+            if (row >= a.n_rows) break;
         }
-        if (!ok[0]) break;
-#pragma unroll
-        for (int r = 1; r < R; ++r)
-            if (!ok[r]) row[r] = row[0];
         for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
-            vec_t<T, V> acc[R];
+            vec_t<T, V> xo, acc;
+            if constexpr (S)
+                acc = lap_row_meta<T, V, Z, WT>(meta_staged<T, WT>(smem, a.rows_per_tile, grp), PlainLoad<T, V>{X, a.ld},
+                                                a.k, row, c0, sub, lpr, single, xo);
+            else
+                acc = lap_row<T, V, Z, WT>(a.A, X, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, xo);
+            if (cs) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                vec_t<T, V> xo;
-                acc[r] = lap_row<T, V, Z, WT>(a.A, X, a.n_b, a.k, a.ld, a.W, row[r], c0, sub, lpr, single, xo);
+                for (int q = 0; q < V; ++q)
+                    if (c0 + q < a.k) acc[q] *= T(cs[c0 + q]);
             }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (cs) {
-#pragma unroll
-                    for (int q = 0; q < V; ++q)
-                        if (c0 + q < a.k) acc[r][q] *= T(cs[c0 + q]);
-                }
-                if (ok[r]) stv_masked<T, V>(Y + row[r] * a.ld + c0, acc[r], a.k - c0, a.nt != 0);
-            }
+            stv_masked<T, V>(Y + row * a.ld + c0, acc, a.k - c0, a.nt != 0);
         }
     }
 }
@@ -219,10 +214,13 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
         by_width(op->W, [&](auto Wt) {
             constexpr int v = decltype(V)::value, wt = decltype(Wt)::value;
             constexpr bool z = decltype(Z)::value;
-            if (t.rows == 2)
-                hipLaunchKernelGGL((k_lap<T, v, z, wt, 2>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+            constexpr bool can_stage = wt > 0;
+            const size_t shm = stage_bytes<T, wt>(g.rows_per_tile);
+            if (can_stage && t.stage_lds)
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, can_stage>), dim3(g.n_blocks), dim3(t.block), shm, s, a, X, Y,
+                                   cs);
             else
-                hipLaunchKernelGGL((k_lap<T, v, z, wt, 1>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
         });
     });
     FVX_HIP(hipGetLastError());
@@ -290,6 +288,26 @@ int fvx_lap(const fvx_op *op, int dtype, const void *X, void *Y, const double *c
         else
             fvx::launch_lap<float>(op, static_cast<const float *>(X), static_cast<float *>(Y), colscale,
                                    fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_lap_many(const fvx_op *op, int dtype, int n, const void *const *X, void *const *Y, void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        FVX_REQUIRE(n >= 0 && (n == 0 || (X && Y)), FVX_E_ARG, "bad pointer arrays");
+        for (int i = 0; i < n; ++i) {
+            fvx::check_ptr(X[i], "X[i]");
+            fvx::check_ptr(Y[i], "Y[i]");
+            FVX_REQUIRE(X[i] != Y[i], FVX_E_ARG, "X[i] and Y[i] must not overlap");
+        }
+        hipStream_t s = fvx::as_stream(stream);
+        for (int i = 0; i < n; ++i) {
+            if (dtype == FVX_F64)
+                fvx::launch_lap<double>(op, static_cast<const double *>(X[i]), static_cast<double *>(Y[i]), nullptr, s);
+            else
+                fvx::launch_lap<float>(op, static_cast<const float *>(X[i]), static_cast<float *>(Y[i]), nullptr, s);
+        }
         return FVX_OK;
     });
 }

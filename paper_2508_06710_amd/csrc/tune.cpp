@@ -17,15 +17,17 @@ std::vector<fvx_tile> candidates(const fvx_op *op, int dtype) {
         if (op->ld % vec) continue;
         const int base = std::min(64, next_pow2(int(ceil_div(op->k, vec))));
         for (int lpr = base; lpr >= 1 && lpr >= base / 4; lpr >>= 1)
-            for (int block : {64, 128, 256, 512, 1024}) {
+            for (int block : {64, 128, 256, 512}) {
                 if (block < lpr) continue;
-                for (int cap : {0, 1024, 2048, 4096})
+                for (int cap : {0, 2048})
                     for (int remap : {1, 0})
-                        for (int rows : {1, 2})
+                        for (int stage : {0, 1}) {
+                            if (stage && block / lpr > kMaxStageRows) continue;
                             for (int nt : {0, 1}) {
-                                fvx_tile t{vec, lpr, block, remap, cap, rows, nt};
+                                fvx_tile t{vec, lpr, block, remap, cap, stage, nt};
                                 out.push_back(t);
                             }
+                        }
             }
     }
     return out;

@@ -90,12 +90,14 @@ def test_every_tile_gives_the_same_product(k):
                 if block < lpr:
                     continue
                 for remap in (0, 1):
-                    for rows in (1, 2):
-                        cap = (0, 3, 7)[(lpr + block + rows) % 3]  # also caps that leave a ragged last pair
-                        nt = (remap + rows) % 2
-                        c.op.set_tile(vec, lpr, block, remap, cap, rows, nt, dtype=fvx.F64)
+                    for stage in (0, 1):
+                        if stage and block // lpr > 64:
+                            continue
+                        cap = (0, 3, 7)[(lpr + block + stage) % 3]  # caps give several tiles per block
+                        nt = (remap + stage) % 2
+                        c.op.set_tile(vec, lpr, block, remap, cap, stage, nt, dtype=fvx.F64)
                         y, ref, A, x = _lap_check(c, seed=5)
-                        assert componentwise(y, ref, A, x) <= TOL64, (vec, lpr, block, remap, cap, rows, nt)
+                        assert componentwise(y, ref, A, x) <= TOL64, (vec, lpr, block, remap, cap, stage, nt)
                         outs.append(y)
     # same order of operations per element in every tile: bit-identical results
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
@@ -104,7 +106,9 @@ def test_every_tile_gives_the_same_product(k):
     with pytest.raises(fvx.FvxError):
         c.op.set_tile(2, 3, 256, 1, dtype=fvx.F64)  # lanes per row must be a power of two
     with pytest.raises(fvx.FvxError):
-        c.op.set_tile(2, 8, 256, 1, 0, 3, dtype=fvx.F64)  # rows in flight: 1 or 2
+        c.op.set_tile(2, 8, 256, 1, 0, 2, dtype=fvx.F64)  # stage_lds is 0 or 1
+    with pytest.raises(fvx.FvxError):
+        c.op.set_tile(2, 1, 256, 1, 0, 1, dtype=fvx.F64)  # 256 rows per tile do not fit the stage
 
 
 @pytest.mark.parametrize("base", list(BASES))
