@@ -268,6 +268,20 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *opts, size_t *bytes)
 int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *opts,
                       void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
 
+/* Many independent solves (uneven meshes and k) advanced together: every
+ * CG phase of all problems still iterating is one launch (per group of
+ * problems sharing a kernel instance: block size, vector width, coupling and
+ * ELL width), each workgroup running one block of one problem's grid.  Each
+ * problem takes exactly the steps and decisions of fvx_poisson_solve on its
+ * own, so its result is bitwise identical to that solve with the same tiles.
+ * ops, B, X: host arrays of n pointers (B[i], X[i] as in fvx_poisson_solve).
+ * stats: host array of n records (or NULL).  Returns FVX_OK when all
+ * converged, else the most severe status (errors before warnings). */
+int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts *opts, size_t *bytes);
+int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const *B, double *const *X,
+                            const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
+                            void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Comparators for measurement                                         */
 /* ------------------------------------------------------------------ */

@@ -329,6 +329,25 @@ class Operator:
             self._h = None
 
 
+def solve_batch(ops, Bs, Xs=None, stream=None, allow_not_converged=False, **kw):
+    """Solves L_i x_i = b_i for several operators at once (fvx_poisson_solve_batch).
+    Returns (list of X, list of stats dicts)."""
+    torch = _torch()
+    n = len(ops)
+    opts = ops[0].solve_opts(**kw)
+    Xs = [op.zeros() for op in ops] if Xs is None else Xs
+    oa = (C.c_void_p * n)(*[op._h.value for op in ops])
+    ba = (C.c_void_p * n)(*[b.data_ptr() for b in Bs])
+    xa = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
+    nbytes = C.c_size_t()
+    check(lib().fvx_solve_batch_bytes(n, oa, C.byref(opts), C.byref(nbytes)), "fvx_solve_batch_bytes")
+    ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=ops[0].device)
+    st = (SolveStats * n)()
+    rc = lib().fvx_poisson_solve_batch(n, oa, ba, xa, C.byref(opts), _ptr(ws), ws.numel(), st, _stream(stream))
+    check(rc, "fvx_poisson_solve_batch", (0, 1) if allow_not_converged else (0,))
+    return Xs, [st[i].as_dict() for i in range(n)]
+
+
 class CsrMatrix:
     """An assembled CSR matrix on the device (the no-block-reuse comparator)."""
 

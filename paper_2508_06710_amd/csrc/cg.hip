@@ -25,11 +25,22 @@
 namespace fvx {
 namespace {
 
+// A kernel body runs one virtual block vb.blk of a grid of vb.nblk blocks.
+// A single-problem launch maps hardware blocks onto virtual blocks (XCD-aware
+// order); a batched launch maps them onto (problem, virtual block) items.  The
+// arithmetic of a virtual block does not depend on which launch runs it.
+struct VB {
+    int64_t blk;
+    int nblk;
+};
+
+__device__ __forceinline__ VB vb_single(int remap) { return VB{logical_block(remap), int(gridDim.x)}; }
+
 #define ROW_PROLOGUE                                 \
     const int lpr = a.lpr;                           \
     const int sub = threadIdx.x & (lpr - 1);         \
     const int grp = threadIdx.x / lpr;               \
-    const int64_t blk = logical_block(a.remap);      \
+    const int64_t blk = vb.blk;                      \
     const int64_t t0 = blk * a.tiles_per_block;
 
 #define FOR_ROWS                                                         \
@@ -48,8 +59,7 @@ struct Src {
 
 // Partial sums of a vector per group (for plain means).
 template <typename T, int V>
-__global__ __launch_bounds__(kMaxCgBlock) void k_sum(RowArgs<T> a, CgDev d, const T *__restrict__ v,
-                                                     double *__restrict__ part) {
+__device__ void b_sum(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__restrict__ v, double *__restrict__ part) {
     __shared__ double lds[kMaxCgBlock * kMaxV];
     ROW_PROLOGUE
     double c[1][V] = {};
@@ -60,17 +70,22 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_sum(RowArgs<T> a, CgDev d, cons
             if (c0 + u < a.k) c[0][u] += double(vv[u]);
     }
     END_ROWS
-    write_partials<1, V>(c, sub, lpr, d.G, d.percol, part, blk, gridDim.x, lds);
+    write_partials<1, V>(c, sub, lpr, d.G, d.percol, part, blk, vb.nblk, lds);
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kMaxCgBlock) void k_sum(RowArgs<T> a, CgDev d, const T *__restrict__ v,
+                                                     double *__restrict__ part) {
+    b_sum<T, V>(a, d, vb_single(a.remap), v, part);
 }
 
 // Start: mean (if singular) from partials; bp = b - mean; r = L x0 - bp (x0
 // given, L x0 in q) or -bp; x = 0 for the zero guess; partials of r.r and
 // b.b into part_b.
 template <typename T, int V>
-__global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, Src mean_src, int singular,
-                                                         const T *__restrict__ b, T *__restrict__ bp,
-                                                         T *__restrict__ x, T *__restrict__ r,
-                                                         const T *__restrict__ q, int given) {
+__device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_src, int singular,
+                          const T *__restrict__ b, T *__restrict__ bp, T *__restrict__ x, T *__restrict__ r,
+                          const T *__restrict__ q, int given) {
     __shared__ double lds[kMaxCgBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     ROW_PROLOGUE
@@ -111,15 +126,22 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, 
         if (!given) stv_masked<T, V>(x + o, vec_t<T, V>(0), a.k - c0);
     }
     END_ROWS
-    write_partials<2, V>(c, sub, lpr, G, d.percol, d.part_b, blk, gridDim.x, lds);
+    write_partials<2, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, Src mean_src, int singular,
+                                                         const T *__restrict__ b, T *__restrict__ bp,
+                                                         T *__restrict__ x, T *__restrict__ r,
+                                                         const T *__restrict__ q, int given) {
+    b_cg_init<T, V>(a, d, vb_single(a.remap), mean_src, singular, b, bp, x, r, q, given);
 }
 
 // A: direction update fused with the SpMM.  rr: partial sums of r.r after the
 // previous iteration (or after init, with bb the b.b sums, when it == 0).
 template <typename T, int V, bool Z, int WT>
-__global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int it, Src rr, Src bb,
-                                                      const T *__restrict__ r, const T *__restrict__ p_old,
-                                                      T *__restrict__ p_new, T *__restrict__ q) {
+__device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, const T *__restrict__ r,
+                       const T *__restrict__ p_old, T *__restrict__ p_new, T *__restrict__ q) {
     if (d.st->done) return;
     __shared__ double lds[kMaxCgBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
@@ -199,14 +221,20 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int
             if (c0 + u < a.k) c[0][u] += double(pn[u]) * double(acc[u]);
     }
     END_ROWS
-    write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, gridDim.x, lds);
+    write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, vb.nblk, lds);
+}
+
+template <typename T, int V, bool Z, int WT>
+__global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int it, Src rr, Src bb,
+                                                      const T *__restrict__ r, const T *__restrict__ p_old,
+                                                      T *__restrict__ p_new, T *__restrict__ q) {
+    b_cg_a<T, V, Z, WT>(a, d, vb_single(a.remap), it, rr, bb, r, p_old, p_new, q);
 }
 
 // B: alpha from the p.q partials; x += alpha p; r += alpha q; partial r.r.
 template <typename T, int V>
-__global__ __launch_bounds__(kMaxCgBlock) void k_cg_b(RowArgs<T> a, CgDev d, int it, Src pq, T *__restrict__ x,
-                                                      T *__restrict__ r, const T *__restrict__ p,
-                                                      const T *__restrict__ q) {
+__device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
+                       T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q) {
     if (d.st->done) return;
     __shared__ double lds[kMaxCgBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
@@ -254,7 +282,14 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_b(RowArgs<T> a, CgDev d, int
         stv_masked<T, V>(r + o, rv, a.k - c0);
     }
     END_ROWS
-    write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b, blk, gridDim.x, lds);
+    write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kMaxCgBlock) void k_cg_b(RowArgs<T> a, CgDev d, int it, Src pq, T *__restrict__ x,
+                                                      T *__restrict__ r, const T *__restrict__ p,
+                                                      const T *__restrict__ q) {
+    b_cg_b<T, V>(a, d, vb_single(a.remap), it, pq, x, r, p, q);
 }
 
 // End: x -= mean(x) (singular L; mean from partials), x = 0 where b vanished.
@@ -263,6 +298,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_fix_x(RowArgs<T> a, CgDev d, Sr
                                                        T *__restrict__ x) {
     __shared__ double lds[kMaxCgBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
+    const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     const int G = d.G;
     if (project) {
@@ -290,6 +326,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_resid(RowArgs<T> a, CgDev d, co
                                                        const T *__restrict__ q, T *__restrict__ r,
                                                        double *__restrict__ part) {
     __shared__ double lds[kMaxCgBlock * kMaxV];
+    const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     double c[2][V] = {};
     FOR_ROWS {
@@ -304,7 +341,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_resid(RowArgs<T> a, CgDev d, co
         if (r) stv_masked<T, V>(r + o, rv, a.k - c0);
     }
     END_ROWS
-    write_partials<2, V>(c, sub, lpr, d.G, d.percol, part, blk, gridDim.x, lds);
+    write_partials<2, V>(c, sub, lpr, d.G, d.percol, part, blk, vb.nblk, lds);
 }
 
 // Mixed precision: inner right-hand side b32 = r - mean_g for groups still
@@ -313,6 +350,7 @@ template <int V>
 __global__ __launch_bounds__(kMaxCgBlock) void k_to_inner(RowArgs<double> a, CgDev d, const double *__restrict__ r,
                                                           const double *__restrict__ gmean,
                                                           const double *__restrict__ gact, float *__restrict__ b32) {
+    const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     (void)blk;
     FOR_ROWS {
@@ -332,6 +370,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_to_inner(RowArgs<double> a, CgD
 template <int V>
 __global__ __launch_bounds__(kMaxCgBlock) void k_add_inner(RowArgs<double> a, double *__restrict__ x,
                                                            const float *__restrict__ d32) {
+    const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     (void)blk;
     FOR_ROWS {
@@ -343,6 +382,58 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_add_inner(RowArgs<double> a, do
         stv_masked<double, V>(x + o, xv, a.k - c0);
     }
     END_ROWS
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: one grid covers several problems.  Each problem owns a
+// contiguous range of hardware blocks starting at a multiple of 8 (so the
+// XCD-aware order holds inside the range) and runs exactly the virtual blocks
+// of its single-problem grid.  Blocks past a problem's range (alignment
+// padding) return at once.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct BItem {
+    RowArgs<T> a;
+    CgDev d;
+    const T *b;
+    T *x, *bp, *r, *p0, *p1, *q;
+    Src rr, bb, pq;
+    int nblk, first;
+};
+
+template <typename T>
+__device__ __forceinline__ int find_item(const BItem<T> *items, int n) {
+    int p = 0;
+    while (p + 1 < n && int(blockIdx.x) >= items[p + 1].first) ++p;
+    return p;
+}
+
+// p' of iteration it: p0 on even iterations, p1 on odd ones; the previous
+// direction is r at it = 0 (p' = r + 0 r) and the other buffer afterwards.
+template <typename T, int V, bool Z, int WT>
+__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restrict__ items, int n, int it) {
+    const BItem<T> &I = items[find_item(items, n)];
+    const int local = int(blockIdx.x) - I.first;
+    if (local >= I.nblk) return;
+    const RowArgs<T> a = I.a;
+    const CgDev d = I.d;
+    const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
+    T *pold = it == 0 ? I.r : ((it & 1) ? I.p0 : I.p1);
+    T *pnew = (it & 1) ? I.p1 : I.p0;
+    b_cg_a<T, V, Z, WT>(a, d, vb, it, I.rr, I.bb, I.r, pold, pnew, I.q);
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n, int it) {
+    const BItem<T> &I = items[find_item(items, n)];
+    const int local = int(blockIdx.x) - I.first;
+    if (local >= I.nblk) return;
+    const RowArgs<T> a = I.a;
+    const CgDev d = I.d;
+    const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
+    T *pnew = (it & 1) ? I.p1 : I.p0;
+    b_cg_b<T, V>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,53 +612,148 @@ std::vector<double> host_totals(const CgDev &d, const double *part, int nq, int 
     return h;
 }
 
-// One CG solve in precision T.  b, x, bp, r, p0, p1, q are [n_b][ld] arrays
-// of T; x holds the guess when `given`.  Returns once the device flag is set.
+// One CG of a batch: the problem's operator, its CG state and its vectors.
 template <typename T>
-void run_cg(const fvx_op *op, CgDev d, const T *b, T *x, T *bp, T *r, T *p0, T *p1, T *q, bool given,
-            double rtol, int max_iter, int poll, hipStream_t s) {
-    Ctx<T> c(op);
-    d.rtol2 = rtol * rtol;
-    reset_state(d, max_iter, s);
-    const int nb = c.g.n_blocks;
-    by_v<T>(c.t.vec, [&](auto Vt) {
-        constexpr int V = decltype(Vt)::value;
-        Src mean{nullptr, 0};
-        if (op->singular) {
-            hipLaunchKernelGGL((k_sum<T, V>), c.grid, c.block, 0, s, c.a, d, b, d.part_a);
-            mean = fold_or_direct(d, d.part_a, 1, nb, 0, d.tot + 3 * d.G, s);
-        }
-        if (given) launch_lap<T>(op, x, q, nullptr, s);
-        hipLaunchKernelGGL((k_cg_init<T, V>), c.grid, c.block, 0, s, c.a, d, mean, int(op->singular), b, bp, x, r,
-                           q, int(given));
-        Src rr = fold_or_direct(d, d.part_b, 2, nb, 0, d.tot, s);
-        const Src bb = d.percol ? Src{d.tot + d.G, 1} : Src{d.part_b + size_t(nb) * d.G, nb};
-        FVX_HIP(hipGetLastError());
-        T *pold = r, *pnew = p0;  // iteration 0 forms p = r + 0 * r
-        int it = 0;
-        while (true) {
-            const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
-            for (int i = 0; i < batch; ++i, ++it) {
-                by_width(op->W, [&](auto Wt) {
-                    constexpr int WT = decltype(Wt)::value;
-                    if (op->zfaces)
-                        hipLaunchKernelGGL((k_cg_a<T, V, true, WT>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r,
-                                           pold, pnew, q);
-                    else
-                        hipLaunchKernelGGL((k_cg_a<T, V, false, WT>), c.grid, c.block, 0, s, c.a, d, it, rr, bb, r,
-                                           pold, pnew, q);
-                });
-                const Src pq = fold_or_direct(d, d.part_a, 1, nb, 0, d.tot + 2 * d.G, s);
-                hipLaunchKernelGGL((k_cg_b<T, V>), c.grid, c.block, 0, s, c.a, d, it, pq, x, r, pnew, q);
-                rr = fold_or_direct(d, d.part_b, 1, nb, 0, d.tot, s);
-                pold = pnew;
-                pnew = (pnew == p0) ? p1 : p0;
+struct CgJob {
+    const fvx_op *op;
+    CgDev d;
+    const T *b;
+    T *x, *bp, *r, *p0, *p1, *q;
+    bool given;
+    double rtol;
+    int max_iter;
+};
+
+// Batched launches group jobs whose kernels share one instance: block size,
+// vector width, plane coupling and ELL width.
+struct GroupKey {
+    int block, vec, z, w;
+    bool operator==(const GroupKey &o) const { return block == o.block && vec == o.vec && z == o.z && w == o.w; }
+};
+
+// Runs the CGs of all jobs.  Each job starts exactly as a single solve would
+// (its own launches), then every iteration is one batched launch per phase and
+// group.  items_dev: device array for the launch descriptors (>= jobs.size()).
+template <typename T>
+void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int poll, hipStream_t s) {
+    if (jobs.empty()) return;
+    std::vector<BItem<T>> items(jobs.size());
+    std::vector<GroupKey> keys(jobs.size());
+    int max_iter = 0;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        CgJob<T> &J = jobs[j];
+        Ctx<T> c(J.op);
+        J.d.rtol2 = J.rtol * J.rtol;
+        reset_state(J.d, J.max_iter, s);
+        max_iter = std::max(max_iter, J.max_iter);
+        const CgDev &d = J.d;
+        const int nb = c.g.n_blocks;
+        BItem<T> &I = items[j];
+        by_v<T>(c.t.vec, [&](auto Vt) {
+            constexpr int V = decltype(Vt)::value;
+            Src mean{nullptr, 0};
+            if (J.op->singular) {
+                hipLaunchKernelGGL((k_sum<T, V>), c.grid, c.block, 0, s, c.a, d, J.b, d.part_a);
+                mean = fold_or_direct(d, d.part_a, 1, nb, 0, d.tot + 3 * d.G, s);
             }
+            if (J.given) launch_lap<T>(J.op, J.x, J.q, nullptr, s);
+            hipLaunchKernelGGL((k_cg_init<T, V>), c.grid, c.block, 0, s, c.a, d, mean, int(J.op->singular), J.b, J.bp,
+                               J.x, J.r, J.q, int(J.given));
+            I.rr = fold_or_direct(d, d.part_b, 2, nb, 0, d.tot, s);
             FVX_HIP(hipGetLastError());
-            if (read_done(d, s)) break;
-            if (it > max_iter) break;  // the device flag is set by then
+        });
+        I.a = c.a;
+        I.d = d;
+        I.b = J.b;
+        I.x = J.x;
+        I.bp = J.bp;
+        I.r = J.r;
+        I.p0 = J.p0;
+        I.p1 = J.p1;
+        I.q = J.q;
+        I.bb = d.percol ? Src{d.tot + d.G, 1} : Src{d.part_b + size_t(nb) * d.G, nb};
+        I.pq = d.percol ? Src{d.tot + 2 * d.G, 1} : Src{d.part_a, nb};
+        I.nblk = nb;
+        keys[j] = GroupKey{c.t.block, c.t.vec, int(J.op->zfaces), J.op->W};
+    }
+    // Order jobs by group, give each a block range aligned to 8, upload.
+    std::vector<int> order(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) order[j] = int(j);
+    std::vector<GroupKey> gk;
+    std::vector<std::vector<int>> members;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        size_t g = 0;
+        while (g < gk.size() && !(gk[g] == keys[j])) ++g;
+        if (g == gk.size()) {
+            gk.push_back(keys[j]);
+            members.emplace_back();
         }
-    });
+        members[g].push_back(int(j));
+    }
+    struct Launch {
+        GroupKey key;
+        int offset, n, blocks;
+        std::vector<int> jobs;
+    };
+    std::vector<Launch> launches;
+    std::vector<BItem<T>> packed;
+    for (size_t g = 0; g < gk.size(); ++g) {
+        Launch L{gk[g], int(packed.size()), 0, 0, members[g]};
+        int first = 0;
+        for (int j : members[g]) {
+            BItem<T> I = items[j];
+            I.first = first;
+            first += int(ceil_div(I.nblk, 8) * 8);
+            packed.push_back(I);
+        }
+        L.n = int(members[g].size());
+        L.blocks = first;
+        launches.push_back(L);
+    }
+    FVX_HIP(hipMemcpyAsync(items_dev, packed.data(), sizeof(BItem<T>) * packed.size(), hipMemcpyHostToDevice, s));
+    FVX_HIP(hipStreamSynchronize(s));
+    auto fold_percol = [&](const Launch &L, bool after_a) {
+        for (int j : L.jobs) {
+            const CgDev &d = jobs[j].d;
+            if (!d.percol) continue;
+            if (after_a)
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_a, items[j].nblk, d.G, d.tot + 2 * d.G);
+            else
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_b, items[j].nblk, d.G, d.tot);
+        }
+    };
+    int it = 0;
+    while (true) {
+        const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
+        for (int i = 0; i < batch; ++i, ++it) {
+            for (const Launch &L : launches) {
+                const BItem<T> *dev = items_dev + L.offset;
+                by_v<T>(L.key.vec, [&](auto Vt) {
+                    constexpr int V = decltype(Vt)::value;
+                    by_width(L.key.w, [&](auto Wt) {
+                        constexpr int WT = decltype(Wt)::value;
+                        if (L.key.z)
+                            hipLaunchKernelGGL((kb_cg_a<T, V, true, WT>), dim3(L.blocks), dim3(L.key.block), 0, s, dev,
+                                               L.n, it);
+                        else
+                            hipLaunchKernelGGL((kb_cg_a<T, V, false, WT>), dim3(L.blocks), dim3(L.key.block), 0, s,
+                                               dev, L.n, it);
+                    });
+                    fold_percol(L, true);
+                    hipLaunchKernelGGL((kb_cg_b<T, V>), dim3(L.blocks), dim3(L.key.block), 0, s, dev, L.n, it);
+                    fold_percol(L, false);
+                });
+            }
+        }
+        FVX_HIP(hipGetLastError());
+        bool all_done = true;
+        std::vector<int32_t> done(jobs.size(), 0);
+        for (size_t j = 0; j < jobs.size(); ++j)
+            FVX_HIP(hipMemcpyAsync(&done[j], &jobs[j].d.st->done, 4, hipMemcpyDeviceToHost, s));
+        FVX_HIP(hipStreamSynchronize(s));
+        for (auto v : done) all_done &= v != 0;
+        if (all_done || it > max_iter) break;
+    }
 }
 
 // x projection (singular L) and the FP64 true residual per group; returns
@@ -628,105 +814,205 @@ void check_opts(const fvx_op *op, const fvx_solve_opts *o) {
         FVX_REQUIRE(op->k <= 128, FVX_E_UNSUPPORTED, "independent-plane solves support k <= 128");
 }
 
-int solve_f64(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *o, Workspace &w,
-              fvx_solve_stats *stats, hipStream_t s) {
-    run_cg<double>(op, w.outer, B, X, w.bp, w.r, w.p0, w.p1, w.q, o->guess == FVX_GUESS_GIVEN, o->rtol,
-                   o->max_iter, o->poll_every, s);
-    auto h = read_state(w.outer, s);
-    const auto res2 = finish_f64(op, w.outer, X, w.bp, w.q, s);
-    const int status = h.st.status;
-    fill_stats(stats, h, res2, status);
-    if (stats) stats->outer = 0;
-    return status;
+// One problem of a (possibly single-problem) solve.
+struct Problem {
+    const fvx_op *op;
+    const double *B;
+    double *X;
+    Workspace w;
+    HostScalars h;
+    std::vector<double> res2;
+    int status = FVX_OK, total_inner = 0, outer = 0;
+    bool outer_active = true;
+};
+
+void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<double> *items, hipStream_t s) {
+    std::vector<CgJob<double>> jobs;
+    for (auto &p : P)
+        jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
+                                     o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter});
+    run_cg_batch<double>(jobs, items, o->poll_every, s);
+    for (auto &p : P) {
+        p.h = read_state(p.w.outer, s);
+        p.res2 = finish_f64(p.op, p.w.outer, p.X, p.w.bp, p.w.q, s);
+        p.status = p.h.st.status;
+    }
 }
 
-int solve_mixed(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *o, Workspace &w,
-                fvx_solve_stats *stats, hipStream_t s) {
-    CgDev D = w.outer;
-    Ctx<double> c(op);
-    const int nb = c.g.n_blocks, G = D.G;
-    reset_state(D, o->max_iter, s);
-    int total_inner = 0, outer = 0, status = FVX_OK;
-    HostScalars h;
-    h.bnorm2.assign(G, 0.0);
-    h.r0.assign(G, 0.0);
-    h.rho_last.assign(G, 0.0);
-    h.iters.assign(G, 0);
-    std::vector<double> res2(G, 0.0);
-    by_v<double>(c.t.vec, [&](auto Vt) {
-        constexpr int V = decltype(Vt)::value;
-        // bp = B - mean(B) and b.b per group (x = 0 unless a guess is given).
-        Src mean{nullptr, 0};
-        if (op->singular) {
-            hipLaunchKernelGGL((k_sum<double, V>), c.grid, c.block, 0, s, c.a, D, B, D.part_a);
-            mean = fold_or_direct(D, D.part_a, 1, nb, 0, D.tot + 3 * G, s);
-        }
-        const bool given = o->guess == FVX_GUESS_GIVEN;
-        if (given) launch_lap<double>(op, X, w.q, nullptr, s);
-        hipLaunchKernelGGL((k_cg_init<double, V>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), B, w.bp, X,
-                           w.r, w.q, int(given));
-        FVX_HIP(hipGetLastError());
+// Mixed precision for every problem: FP64 outer defect correction with an
+// FP32-SpMM inner CG (FP64 dot products and scalars).  Each problem takes the
+// same steps and decisions as when solved alone; the inner CGs of all problems
+// still iterating run as one batch.
+void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<float> *items, hipStream_t s) {
+    for (auto &p : P) {
+        CgDev D = p.w.outer;
+        const fvx_op *op = p.op;
+        Ctx<double> c(op);
+        const int nb = c.g.n_blocks, G = D.G;
+        reset_state(D, o->max_iter, s);
+        p.h.bnorm2.assign(G, 0.0);
+        p.h.r0.assign(G, 0.0);
+        p.h.rho_last.assign(G, 0.0);
+        p.h.iters.assign(G, 0);
+        by_v<double>(c.t.vec, [&](auto Vt) {
+            constexpr int V = decltype(Vt)::value;
+            Src mean{nullptr, 0};
+            if (op->singular) {
+                hipLaunchKernelGGL((k_sum<double, V>), c.grid, c.block, 0, s, c.a, D, p.B, D.part_a);
+                mean = fold_or_direct(D, D.part_a, 1, nb, 0, D.tot + 3 * G, s);
+            }
+            const bool given = o->guess == FVX_GUESS_GIVEN;
+            if (given) launch_lap<double>(op, p.X, p.w.q, nullptr, s);
+            hipLaunchKernelGGL((k_cg_init<double, V>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), p.B,
+                               p.w.bp, p.X, p.w.r, p.w.q, int(given));
+            FVX_HIP(hipGetLastError());
+        });
         const auto t0 = host_totals(D, D.part_b, 2, nb, s);
-        const HostScalars hs = read_state(D, s);
-        h.st = hs.st;
+        p.h.st = read_state(D, s).st;
         for (int g = 0; g < G; ++g) {
-            h.bnorm2[g] = t0[G + g];
-            h.r0[g] = t0[g];
-            if (!std::isfinite(t0[g]) || !std::isfinite(t0[G + g])) status = FVX_E_NONFINITE;
+            p.h.bnorm2[g] = t0[G + g];
+            p.h.r0[g] = t0[g];
+            if (!std::isfinite(t0[g]) || !std::isfinite(t0[G + g])) p.status = FVX_E_NONFINITE;
         }
-        if (h.st.status < 0) status = h.st.status;
+        if (p.h.st.status < 0) p.status = p.h.st.status;
         // The final projection reads ||b||^2 per group on the device.
-        FVX_HIP(hipMemcpyAsync(D.bnorm2, h.bnorm2.data(), 8 * G, hipMemcpyHostToDevice, s));
+        FVX_HIP(hipMemcpyAsync(D.bnorm2, p.h.bnorm2.data(), 8 * G, hipMemcpyHostToDevice, s));
         FVX_HIP(hipStreamSynchronize(s));
-        if (status < 0) return;
-        std::vector<double> gmean(G), gact(G);
-        for (outer = 0;; ++outer) {
-            // FP64 outer residual r = bp - L x, its norm and plain mean per group.
-            launch_lap<double>(op, X, w.q, nullptr, s);
-            hipLaunchKernelGGL((k_resid<double, V>), c.grid, c.block, 0, s, c.a, D, w.bp, w.q, w.r, D.part_b);
-            FVX_HIP(hipGetLastError());
-            const auto t = host_totals(D, D.part_b, 2, nb, s);
+        if (p.status < 0) p.outer_active = false;
+    }
+    while (true) {
+        // FP64 outer residual r = bp - L x, its norm and plain mean per group.
+        std::vector<CgJob<float>> jobs;
+        std::vector<Problem *> in_jobs;
+        for (auto &p : P) {
+            if (!p.outer_active) continue;
+            CgDev D = p.w.outer;
+            const fvx_op *op = p.op;
+            Ctx<double> c(op);
+            const int nb = c.g.n_blocks, G = D.G;
+            std::vector<double> gmean(G), gact(G);
             bool any = false;
-            for (int g = 0; g < G; ++g) {
-                h.rho_last[g] = t[g];
-                const bool act = h.bnorm2[g] > 0.0 && t[g] > o->rtol * o->rtol * h.bnorm2[g];
-                gact[g] = act ? 1.0 : 0.0;
-                gmean[g] = op->singular ? t[G + g] / double(D.count) : 0.0;
-                any |= act;
-                if (!std::isfinite(t[g])) status = FVX_E_NONFINITE;
-            }
-            if (status < 0 || !any) break;
-            if (outer >= o->max_outer || total_inner >= o->max_iter) {
-                status = FVX_NOT_CONVERGED;
-                break;
-            }
-            FVX_HIP(hipMemcpyAsync(w.gmean, gmean.data(), 8 * G, hipMemcpyHostToDevice, s));
-            FVX_HIP(hipMemcpyAsync(w.gact, gact.data(), 8 * G, hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL((k_to_inner<V>), c.grid, c.block, 0, s, c.a, D, w.r, w.gmean, w.gact, w.b32);
-            FVX_HIP(hipGetLastError());
-            const int budget = std::max(1, o->max_iter - total_inner);
-            run_cg<float>(op, w.inner, w.b32, w.x32, w.bp32, w.r32, w.p32a, w.p32b, w.q32, false, o->inner_rtol,
-                          budget, o->poll_every, s);
-            const auto hi = read_state(w.inner, s);
+            by_v<double>(c.t.vec, [&](auto Vt) {
+                constexpr int V = decltype(Vt)::value;
+                launch_lap<double>(op, p.X, p.w.q, nullptr, s);
+                hipLaunchKernelGGL((k_resid<double, V>), c.grid, c.block, 0, s, c.a, D, p.w.bp, p.w.q, p.w.r,
+                                   D.part_b);
+                FVX_HIP(hipGetLastError());
+                const auto t = host_totals(D, D.part_b, 2, nb, s);
+                for (int g = 0; g < G; ++g) {
+                    p.h.rho_last[g] = t[g];
+                    const bool act = p.h.bnorm2[g] > 0.0 && t[g] > o->rtol * o->rtol * p.h.bnorm2[g];
+                    gact[g] = act ? 1.0 : 0.0;
+                    gmean[g] = op->singular ? t[G + g] / double(D.count) : 0.0;
+                    any |= act;
+                    if (!std::isfinite(t[g])) p.status = FVX_E_NONFINITE;
+                }
+                if (p.status < 0 || !any) {
+                    p.outer_active = false;
+                    return;
+                }
+                if (p.outer >= o->max_outer || p.total_inner >= o->max_iter) {
+                    p.status = FVX_NOT_CONVERGED;
+                    p.outer_active = false;
+                    return;
+                }
+                FVX_HIP(hipMemcpyAsync(p.w.gmean, gmean.data(), 8 * G, hipMemcpyHostToDevice, s));
+                FVX_HIP(hipMemcpyAsync(p.w.gact, gact.data(), 8 * G, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL((k_to_inner<V>), c.grid, c.block, 0, s, c.a, D, p.w.r, p.w.gmean, p.w.gact, p.w.b32);
+                FVX_HIP(hipGetLastError());
+                FVX_HIP(hipStreamSynchronize(s));  // gmean/gact host buffers are reused next pass
+            });
+            if (!p.outer_active) continue;
+            const int budget = std::max(1, o->max_iter - p.total_inner);
+            jobs.push_back(CgJob<float>{op, p.w.inner, p.w.b32, p.w.x32, p.w.bp32, p.w.r32, p.w.p32a, p.w.p32b,
+                                        p.w.q32, false, o->inner_rtol, budget});
+            in_jobs.push_back(&p);
+        }
+        if (jobs.empty()) break;
+        run_cg_batch<float>(jobs, items, o->poll_every, s);
+        for (Problem *pp : in_jobs) {
+            Problem &p = *pp;
+            const auto hi = read_state(p.w.inner, s);
             int it = 0;
             for (auto v : hi.iters) it = std::max(it, v);
-            total_inner += it;
+            p.total_inner += it;
             if (hi.st.status < 0) {
-                status = hi.st.status;
-                break;
+                p.status = hi.st.status;
+                p.outer_active = false;
+                continue;
             }
-            hipLaunchKernelGGL((k_add_inner<V>), c.grid, c.block, 0, s, c.a, X, w.x32);
+            Ctx<double> c(p.op);
+            by_v<double>(c.t.vec, [&](auto Vt) {
+                constexpr int V = decltype(Vt)::value;
+                hipLaunchKernelGGL((k_add_inner<V>), c.grid, c.block, 0, s, c.a, p.X, p.w.x32);
+            });
             FVX_HIP(hipGetLastError());
+            ++p.outer;
         }
-    });
-    res2 = finish_f64(op, D, X, w.bp, w.q, s);
-    h.st.status = status;
-    fill_stats(stats, h, res2, status);
-    if (stats) {
-        stats->iters = total_inner;
-        stats->outer = outer;
     }
-    return status;
+    for (auto &p : P) {
+        p.res2 = finish_f64(p.op, p.w.outer, p.X, p.w.bp, p.w.q, s);
+        p.h.st.status = p.status;
+    }
+}
+
+// Workspace of a batch: the item descriptors, then each problem's workspace.
+struct BatchLayout {
+    size_t items64, items32, total;
+    std::vector<size_t> offs;
+};
+
+BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed) {
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += (b + 255) / 256 * 256;
+        return o;
+    };
+    L.items64 = take(sizeof(BItem<double>) * size_t(n));
+    L.items32 = take(sizeof(BItem<float>) * size_t(n));
+    for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed).bytes));
+    L.total = off;
+    return L;
+}
+
+int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double *const *X, const fvx_solve_opts *o,
+                void *ws, size_t ws_bytes, fvx_solve_stats *stats, hipStream_t s) {
+    FVX_REQUIRE(n >= 1 && ops && B && X && ws, FVX_E_ARG, "NULL argument or empty batch");
+    FVX_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, FVX_E_ARG, "ws must be 256-byte aligned");
+    for (int i = 0; i < n; ++i) {
+        check_opts(ops[i], o);
+        FVX_REQUIRE(B[i] && X[i], FVX_E_ARG, "NULL B[i] or X[i]");
+        FVX_REQUIRE(reinterpret_cast<uintptr_t>(B[i]) % 16 == 0 && reinterpret_cast<uintptr_t>(X[i]) % 16 == 0,
+                    FVX_E_ARG, "B[i] and X[i] must be 16-byte aligned");
+    }
+    const bool mixed = o->precision == FVX_MIXED;
+    const BatchLayout L = batch_layout(n, ops, mixed);
+    FVX_REQUIRE(ws_bytes >= L.total, FVX_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
+    char *base = static_cast<char *>(ws);
+    std::vector<Problem> P(n);
+    for (int i = 0; i < n; ++i) {
+        P[i].op = ops[i];
+        P[i].B = B[i];
+        P[i].X = X[i];
+        P[i].w = carve(base + L.offs[i], ops[i], mixed);
+    }
+    if (mixed)
+        solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32), s);
+    else
+        solve_f64_batch(P, o, reinterpret_cast<BItem<double> *>(base + L.items64), s);
+    int worst = FVX_OK;
+    for (int i = 0; i < n; ++i) {
+        fill_stats(stats ? &stats[i] : nullptr, P[i].h, P[i].res2, P[i].status);
+        if (stats) {
+            stats[i].outer = mixed ? P[i].outer : 0;
+            if (mixed) stats[i].iters = P[i].total_inner;
+        }
+        if (P[i].status < 0 && (worst >= 0 || P[i].status < worst)) worst = P[i].status;
+        if (P[i].status > 0 && worst == FVX_OK) worst = P[i].status;
+    }
+    return worst;
 }
 
 }  // namespace
@@ -753,7 +1039,8 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *o, size_t *bytes) {
     return guard([&] {
         fvx::check_opts(op, o);
         FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
-        *bytes = fvx::carve(nullptr, op, o->precision == FVX_MIXED).bytes;
+        const fvx_op *ops[1] = {op};
+        *bytes = fvx::batch_layout(1, ops, o->precision == FVX_MIXED).total;
         return FVX_OK;
     });
 }
@@ -762,19 +1049,33 @@ int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_so
                       size_t ws_bytes, fvx_solve_stats *stats, void *stream) {
     return guard([&] {
         const auto t0 = std::chrono::steady_clock::now();
-        fvx::check_opts(op, o);
-        FVX_REQUIRE(B && X && ws, FVX_E_ARG, "NULL B, X or workspace");
-        FVX_REQUIRE(reinterpret_cast<uintptr_t>(B) % 16 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
-                        reinterpret_cast<uintptr_t>(ws) % 256 == 0,
-                    FVX_E_ARG, "B and X must be 16-byte aligned and ws 256-byte aligned");
-        const bool mixed = o->precision == FVX_MIXED;
-        auto w = fvx::carve(ws, op, mixed);
-        FVX_REQUIRE(ws_bytes >= w.bytes, FVX_E_NOMEM, "workspace too small: need " + std::to_string(w.bytes));
-        hipStream_t s = fvx::as_stream(stream);
-        const int rc = mixed ? fvx::solve_mixed(op, B, X, o, w, stats, s) : fvx::solve_f64(op, B, X, o, w, stats, s);
-        if (stats)
-            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const fvx_op *ops[1] = {op};
+        const double *Bs[1] = {B};
+        double *Xs[1] = {X};
+        const int rc = fvx::solve_batch(1, ops, Bs, Xs, o, ws, ws_bytes, stats, fvx::as_stream(stream));
+        if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc < 0) throw fvx::Error(rc, fvx_status_str(rc));
+        return rc;
+    });
+}
+
+int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts *o, size_t *bytes) {
+    return guard([&] {
+        FVX_REQUIRE(n >= 1 && ops && bytes, FVX_E_ARG, "bad argument");
+        for (int i = 0; i < n; ++i) fvx::check_opts(ops[i], o);
+        *bytes = fvx::batch_layout(n, ops, o->precision == FVX_MIXED).total;
+        return FVX_OK;
+    });
+}
+
+int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const *B, double *const *X,
+                            const fvx_solve_opts *o, void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream) {
+    return guard([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = fvx::solve_batch(n, ops, B, X, o, ws, ws_bytes, stats, fvx::as_stream(stream));
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats)
+            for (int i = 0; i < n; ++i) stats[i].seconds = sec;
         return rc;
     });
 }

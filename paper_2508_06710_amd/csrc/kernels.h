@@ -32,13 +32,14 @@ __device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid
 // L2).  Remapping hardware block b to a logical tile index so that the blocks
 // of one XCD take one contiguous range of rows keeps the neighbour rows a
 // block gathers in the L2 that already holds them.  A bijection on [0, n).
-__device__ __forceinline__ int64_t logical_block(int remap) {
-    const int b = blockIdx.x, n = gridDim.x;
+__device__ __forceinline__ int64_t logical_block_of(int b, int n, int remap) {
     if (!remap || n < 8) return b;
     const int xcd = b & 7, local = b >> 3;
     const int q = n >> 3, r = n & 7;
     return xcd < r ? int64_t(xcd) * (q + 1) + local : int64_t(r) * (q + 1) + int64_t(xcd - r) * q + local;
 }
+
+__device__ __forceinline__ int64_t logical_block(int remap) { return logical_block_of(blockIdx.x, gridDim.x, remap); }
 
 // Values of the neighbouring planes of this lane's V columns, l-1 and l+1
 // (mod k), taken from the row-group lanes that hold them when all k columns
