@@ -64,6 +64,7 @@ enum { FVX_GUESS_ZERO = 0, FVX_GUESS_GIVEN = 1 };
 
 typedef struct fvx_mesh fvx_mesh;   /* host-side base mesh (face graph) */
 typedef struct fvx_op fvx_op;       /* operator: base block on the device + launch tiles */
+typedef struct fvx_net fvx_net;     /* learned initial-guess network (device parameters) */
 
 /* Returns a static string naming a status code. */
 const char *fvx_status_str(int status);
@@ -281,6 +282,86 @@ int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts 
 int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const *B, double *const *X,
                             const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
                             void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned initial guess                                                */
+/* ------------------------------------------------------------------ */
+/* Not part of the paper's method: a small convolutional network that
+ * predicts the initial guess of the pressure Poisson solve of the projection
+ * step (Section 3, Eq. 9: L = M G with the Kronecker-repeated blocks of
+ * Section 2) from the right-hand side and the previous pressure, with the
+ * residual deciding whether the prediction is used.
+ *
+ * Network: four 3x3x3 convolutions 2 -> 32 -> 32 -> 32 -> 1 with ReLU after
+ * the first three, FP32 weights and FP32 accumulation, on the grid of a
+ * Cartesian base (fvx_mesh_cartesian, nx x ny cells) extruded into nz = k
+ * planes.  Padding: periodic in x and z, edge-replicated in y.
+ * Tensors (device, float): samples [ns][2][nz][ny][nx] (channel 0 = f / s,
+ * channel 1 = p_prev / s), outputs and targets [ns][nz][ny][nx], where
+ * f = (b - mean b) / (cell volume) is the source density (mean removed only
+ * for singular operators), s its rms over the cells (1 if zero).  The guess
+ * is x0 = s * (out - mean out) (mean removed only for singular operators).
+ * Parameters (host float, fvx_net_n_params() values): per layer its weights
+ * [co][ci][tap], tap = (dz*3 + dy)*3 + dx reading the input at offsets
+ * (dz-1, dy-1, dx-1), followed by its biases [co].
+ * Training: loss = mean over ns*cells of (out - target)^2; Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8) with bias correction.  Deterministic.
+ * Calls are asynchronous on `stream` unless stated.  Errors: FVX_E_ARG for
+ * NULL pointers, sample counts outside [1, batch] or an operator that is not
+ * this grid; FVX_E_NOMEM for a short buffer. */
+int fvx_net_n_params(void);
+
+/* Device bytes of a network for an nx x ny x nz grid that trains on up to
+ * `batch` samples per step (parameters, Adam moments, activations, gradient
+ * scratch). */
+int fvx_net_bytes(int nx, int ny, int nz, int batch, size_t *bytes);
+
+/* Creates the network in caller-owned device memory dev_mem (256-byte
+ * aligned, >= fvx_net_bytes; must outlive the handle).  init: host
+ * parameters, or NULL for zeros.  Synchronises `stream`. */
+int fvx_net_create(int nx, int ny, int nz, int batch, const float *init, void *dev_mem, size_t bytes,
+                   void *stream, fvx_net **out);
+int fvx_net_destroy(fvx_net *net);
+
+/* Copies the parameters and/or the last gradients to host arrays (either may
+ * be NULL).  Synchronous. */
+int fvx_net_get_params(const fvx_net *net, float *params, float *grads);
+
+/* Replaces the parameters and clears the Adam state.  Synchronises `stream`. */
+int fvx_net_set_params(fvx_net *net, const float *params, void *stream);
+
+/* out = net(in) for ns samples (device arrays as above). */
+int fvx_net_forward(fvx_net *net, int ns, const float *in, float *out, void *stream);
+
+/* Gradients of the loss of ns samples with respect to every parameter (kept
+ * in the network; read with fvx_net_get_params), no update.  *loss (may be
+ * NULL) = the loss before the step.  Synchronises `stream`. */
+int fvx_net_gradients(fvx_net *net, int ns, const float *in, const float *target, double *loss, void *stream);
+
+/* One Adam step with learning rate lr on ns samples.  Synchronises `stream`. */
+int fvx_net_train_step(fvx_net *net, int ns, const float *in, const float *target, float lr, double *loss,
+                       void *stream);
+
+/* One training sample from solver vectors (device double [n_b][ld]): B the
+ * right-hand side, Pprev the previous pressure (NULL = none), Xstar the
+ * solution (NULL with target = NULL: input only).  in: device float
+ * [2][nz][ny][nx]; target: device float [nz][ny][nx] = Xstar / s. */
+int fvx_net_prepare(fvx_net *net, const fvx_op *op, const double *B, const double *Pprev, const double *Xstar,
+                    float *in, float *target, void *stream);
+
+/* X0 (device double [n_b][ld], columns < k written) = the network's guess
+ * for right-hand side B and previous pressure Pprev (NULL = none). */
+int fvx_net_guess(fvx_net *net, const fvx_op *op, const double *B, const double *Pprev, double *X0, void *stream);
+
+/* fvx_poisson_solve started from the network's guess when it is better than
+ * zero: the guess is kept when ||b - L x0|| < ||b|| (b after projection,
+ * FP64, max over CG groups) and is finite; otherwise X is solved from a zero
+ * guess exactly as fvx_poisson_solve with FVX_GUESS_ZERO (opts->guess is
+ * ignored).  *fallback (may be NULL) = 1 when the zero guess was used.
+ * ws as fvx_poisson_solve; stats->seconds includes the inference. */
+int fvx_poisson_solve_net(const fvx_op *op, fvx_net *net, const double *B, const double *Pprev, double *X,
+                          const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
+                          int *fallback, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Comparators for measurement                                         */

@@ -290,3 +290,39 @@ def batch_problems():
             idx = bi * len(ks) + ki
             out.append(dict(base=channel_base(nx, ny), k=k, dz=PI / k, seed=100 + idx))
     return out
+
+
+# --------------------------------------------------------------------------
+# Learned initial guess: training and evaluation data, initial weights
+# --------------------------------------------------------------------------
+
+NET_LAYERS = ((2, 32), (32, 32), (32, 32), (32, 1))  # (c_in, c_out) of the 3x3x3 layers
+
+
+def net_init(seed: int = 6) -> np.ndarray:
+    """Kaiming-uniform weights (bound sqrt(6 / fan_in), fan_in = 27 c_in) and
+    zero biases, flat [W[o][c][tap], b[o]] per layer, float32."""
+    parts = []
+    for li, (ci, co) in enumerate(NET_LAYERS):
+        bound = math.sqrt(6.0 / (27 * ci))
+        parts.append(uniform(seed, 200 + li, co * ci * 27, -bound, bound))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def guess_trajectory(seed: int, traj: int, n_steps: int, n_modes: int = 16,
+                     omega_std: float = 0.1) -> list:
+    """Mode sets of one trajectory: phases drift by omega ~ N(0, omega_std)
+    per mode and step."""
+    modes = fourier_modes(seed, 1000 + 10 * traj, n_modes)
+    om = omega_std * normal(seed, 1000 + 10 * traj + 5, 2 * n_modes)
+    return [modes.advanced(t * om[:n_modes], t * om[n_modes:]) for t in range(n_steps)]
+
+
+def integrated_rhs(modes: FourierModes, cx: np.ndarray, cy: np.ndarray, area: np.ndarray,
+                   k: int, dz: float) -> np.ndarray:
+    """Plane-major right-hand side: the mode sum at the cell centres times the
+    cell volume (plane l centred at z = (l + 1/2) dz)."""
+    z = (np.arange(k) + 0.5) * dz
+    f = modes.evaluate(np.asarray(cx)[None, :], np.asarray(cy)[None, :], z[:, None])
+    return (f * np.asarray(area)[None, :] * dz).ravel()

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
                    PERIODIC_Z, FvxError, SolveOpts, SolveStats, Tile, check, lib)
 
-__all__ = ["Mesh", "Operator", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
+__all__ = ["Mesh", "Operator", "GuessNet", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
            "NEUMANN", "DIRICHLET", "lib"]
 
 
@@ -386,6 +386,109 @@ class CsrMatrix:
                                          _stream(stream))
         check(rc, "fvx_csr_poisson_solve", (0, 1) if allow_not_converged else (0,))
         return x, st.as_dict()
+
+
+class GuessNet:
+    """Learned initial guess (fvx_net_*): a 4-layer 3x3x3 conv net on the grid
+    of a Cartesian base nx x ny extruded into nz planes, with device buffers
+    for training batches of up to ``batch`` samples."""
+
+    def __init__(self, nx, ny, nz, batch=16, params=None, device=None, stream=None):
+        torch = _torch()
+        self.nx, self.ny, self.nz, self.batch = int(nx), int(ny), int(nz), int(batch)
+        self.device = torch.device(device if device is not None else "cuda")
+        self.cells = self.nx * self.ny * self.nz
+        nbytes = C.c_size_t()
+        check(lib().fvx_net_bytes(self.nx, self.ny, self.nz, self.batch, C.byref(nbytes)), "fvx_net_bytes")
+        self._mem = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p is not None and p.size != self.n_params():
+            raise ValueError(f"expected {self.n_params()} parameters, got {p.size}")
+        h = C.c_void_p()
+        check(lib().fvx_net_create(self.nx, self.ny, self.nz, self.batch, _np_ptr(p), _ptr(self._mem),
+                                   nbytes.value, _stream(stream), C.byref(h)), "fvx_net_create")
+        self._h = h
+
+    @staticmethod
+    def n_params():
+        return int(lib().fvx_net_n_params())
+
+    def samples(self, ns, channels=2):
+        """Uninitialised device float32 buffer [ns][channels][nz][ny][nx]."""
+        torch = _torch()
+        return torch.empty((ns, channels, self.nz, self.ny, self.nx), dtype=torch.float32, device=self.device)
+
+    def params(self):
+        p = np.zeros(self.n_params(), np.float32)
+        check(lib().fvx_net_get_params(self._h, _np_ptr(p), None), "fvx_net_get_params")
+        return p
+
+    def grads(self):
+        g = np.zeros(self.n_params(), np.float32)
+        check(lib().fvx_net_get_params(self._h, None, _np_ptr(g)), "fvx_net_get_params")
+        return g
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.n_params():
+            raise ValueError(f"expected {self.n_params()} parameters, got {p.size}")
+        check(lib().fvx_net_set_params(self._h, _np_ptr(p), _stream(stream)), "fvx_net_set_params")
+
+    def forward(self, inp, out=None, stream=None):
+        ns = int(inp.shape[0])
+        out = self.samples(ns, 1) if out is None else out
+        check(lib().fvx_net_forward(self._h, ns, _ptr(inp), _ptr(out), _stream(stream)), "fvx_net_forward")
+        return out
+
+    def gradients(self, inp, target, stream=None):
+        loss = C.c_double()
+        check(lib().fvx_net_gradients(self._h, int(inp.shape[0]), _ptr(inp), _ptr(target), C.byref(loss),
+                                      _stream(stream)), "fvx_net_gradients")
+        return loss.value
+
+    def train_step(self, inp, target, lr=1e-3, stream=None):
+        loss = C.c_double()
+        check(lib().fvx_net_train_step(self._h, int(inp.shape[0]), _ptr(inp), _ptr(target), float(lr),
+                                       C.byref(loss), _stream(stream)), "fvx_net_train_step")
+        return loss.value
+
+    def prepare(self, op, B, Pprev=None, Xstar=None, inp=None, target=None, stream=None):
+        """One sample's input (and target when Xstar is given) from solver vectors."""
+        inp = self.samples(1, 2)[0] if inp is None else inp
+        if Xstar is not None and target is None:
+            target = self.samples(1, 1)[0]
+        check(lib().fvx_net_prepare(self._h, op._h, _ptr(B), _ptr(Pprev), _ptr(Xstar), _ptr(inp),
+                                    _ptr(target if Xstar is not None else None), _stream(stream)),
+              "fvx_net_prepare")
+        return inp, target
+
+    def guess(self, op, B, Pprev=None, X0=None, stream=None):
+        X0 = op.zeros() if X0 is None else X0
+        check(lib().fvx_net_guess(self._h, op._h, _ptr(B), _ptr(Pprev), _ptr(X0), _stream(stream)),
+              "fvx_net_guess")
+        return X0
+
+    def solve(self, op, B, Pprev=None, X=None, stream=None, allow_not_converged=False, **kw):
+        """fvx_poisson_solve_net: returns (X, stats dict with 'fallback')."""
+        opts = op.solve_opts(**kw)
+        X = op.zeros() if X is None else X
+        ws = op.workspace(opts)
+        st = SolveStats()
+        fb = C.c_int(0)
+        rc = lib().fvx_poisson_solve_net(op._h, self._h, _ptr(B), _ptr(Pprev), _ptr(X), C.byref(opts), _ptr(ws),
+                                         ws.numel(), C.byref(st), C.byref(fb), _stream(stream))
+        check(rc, "fvx_poisson_solve_net", (0, 1) if allow_not_converged else (0,))
+        d = st.as_dict()
+        d["fallback"] = int(fb.value)
+        return X, d
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                lib().fvx_net_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None
 
 
 def copy(dst, src, nbytes=None, stream=None):

@@ -102,6 +102,19 @@ SIGNATURES = {
     "fvx_csr_poisson_solve": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
                                         C.c_size_t, _P(SolveStats), _vp]),
     "fvx_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "fvx_net_n_params": (C.c_int, []),
+    "fvx_net_bytes": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _P(C.c_size_t)]),
+    "fvx_net_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _P(_vp)]),
+    "fvx_net_destroy": (C.c_int, [_vp]),
+    "fvx_net_get_params": (C.c_int, [_vp, _vp, _vp]),
+    "fvx_net_set_params": (C.c_int, [_vp, _vp, _vp]),
+    "fvx_net_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "fvx_net_gradients": (C.c_int, [_vp, C.c_int, _vp, _vp, _P(C.c_double), _vp]),
+    "fvx_net_train_step": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_float, _P(C.c_double), _vp]),
+    "fvx_net_prepare": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fvx_net_guess": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "fvx_poisson_solve_net": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _vp, C.c_size_t, _P(SolveStats),
+                                        _P(C.c_int), _vp]),
 }
 
 _lib = None

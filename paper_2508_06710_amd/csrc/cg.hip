@@ -402,11 +402,19 @@ struct BItem {
     int nblk, first;
 };
 
+// The item whose block range holds this block: the last one with first <=
+// blockIdx.x (items ascend by first, items[0].first = 0).
 template <typename T>
 __device__ __forceinline__ int find_item(const BItem<T> *items, int n) {
-    int p = 0;
-    while (p + 1 < n && int(blockIdx.x) >= items[p + 1].first) ++p;
-    return p;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (items[mid].first <= int(blockIdx.x))
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 // p' of iteration it: p0 on even iterations, p1 on odd ones; the previous
@@ -434,6 +442,13 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *pnew = (it & 1) ? I.p1 : I.p0;
     b_cg_b<T, V>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
+}
+
+// flags[i] = done flag of item i's CG (one read back per poll for the batch).
+template <typename T>
+__global__ __launch_bounds__(256) void kb_done(const BItem<T> *__restrict__ items, int n, int32_t *__restrict__ flags) {
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        flags[i] = items[i].d.st->done;
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +650,7 @@ struct GroupKey {
 // (its own launches), then every iteration is one batched launch per phase and
 // group.  items_dev: device array for the launch descriptors (>= jobs.size()).
 template <typename T>
-void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int poll, hipStream_t s) {
+void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *flags_dev, int poll, hipStream_t s) {
     if (jobs.empty()) return;
     std::vector<BItem<T>> items(jobs.size());
     std::vector<GroupKey> keys(jobs.size());
@@ -748,8 +763,10 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int poll, hi
         FVX_HIP(hipGetLastError());
         bool all_done = true;
         std::vector<int32_t> done(jobs.size(), 0);
-        for (size_t j = 0; j < jobs.size(); ++j)
-            FVX_HIP(hipMemcpyAsync(&done[j], &jobs[j].d.st->done, 4, hipMemcpyDeviceToHost, s));
+        const int nj = int(jobs.size());
+        hipLaunchKernelGGL(kb_done<T>, dim3(unsigned(ceil_div(nj, 256))), dim3(256), 0, s, items_dev, nj, flags_dev);
+        FVX_HIP(hipGetLastError());
+        FVX_HIP(hipMemcpyAsync(done.data(), flags_dev, 4 * size_t(nj), hipMemcpyDeviceToHost, s));
         FVX_HIP(hipStreamSynchronize(s));
         for (auto v : done) all_done &= v != 0;
         if (all_done || it > max_iter) break;
@@ -826,12 +843,13 @@ struct Problem {
     bool outer_active = true;
 };
 
-void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<double> *items, hipStream_t s) {
+void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<double> *items, int32_t *flags,
+                     hipStream_t s) {
     std::vector<CgJob<double>> jobs;
     for (auto &p : P)
         jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
                                      o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter});
-    run_cg_batch<double>(jobs, items, o->poll_every, s);
+    run_cg_batch<double>(jobs, items, flags, o->poll_every, s);
     for (auto &p : P) {
         p.h = read_state(p.w.outer, s);
         p.res2 = finish_f64(p.op, p.w.outer, p.X, p.w.bp, p.w.q, s);
@@ -843,7 +861,8 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
 // FP32-SpMM inner CG (FP64 dot products and scalars).  Each problem takes the
 // same steps and decisions as when solved alone; the inner CGs of all problems
 // still iterating run as one batch.
-void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<float> *items, hipStream_t s) {
+void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<float> *items, int32_t *flags,
+                       hipStream_t s) {
     for (auto &p : P) {
         CgDev D = p.w.outer;
         const fvx_op *op = p.op;
@@ -929,7 +948,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;
-        run_cg_batch<float>(jobs, items, o->poll_every, s);
+        run_cg_batch<float>(jobs, items, flags, o->poll_every, s);
         for (Problem *pp : in_jobs) {
             Problem &p = *pp;
             const auto hi = read_state(p.w.inner, s);
@@ -958,7 +977,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
 
 // Workspace of a batch: the item descriptors, then each problem's workspace.
 struct BatchLayout {
-    size_t items64, items32, total;
+    size_t items64, items32, flags, total;
     std::vector<size_t> offs;
 };
 
@@ -972,6 +991,7 @@ BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed) {
     };
     L.items64 = take(sizeof(BItem<double>) * size_t(n));
     L.items32 = take(sizeof(BItem<float>) * size_t(n));
+    L.flags = take(sizeof(int32_t) * size_t(n));
     for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed).bytes));
     L.total = off;
     return L;
@@ -999,9 +1019,11 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
         P[i].w = carve(base + L.offs[i], ops[i], mixed);
     }
     if (mixed)
-        solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32), s);
+        solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32),
+                          reinterpret_cast<int32_t *>(base + L.flags), s);
     else
-        solve_f64_batch(P, o, reinterpret_cast<BItem<double> *>(base + L.items64), s);
+        solve_f64_batch(P, o, reinterpret_cast<BItem<double> *>(base + L.items64),
+                        reinterpret_cast<int32_t *>(base + L.flags), s);
     int worst = FVX_OK;
     for (int i = 0; i < n; ++i) {
         fill_stats(stats ? &stats[i] : nullptr, P[i].h, P[i].res2, P[i].status);
@@ -1016,6 +1038,39 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
 }
 
 }  // namespace
+
+double guess_residual_ratio(const fvx_op *op, const double *B, const double *X, void *ws, hipStream_t s) {
+    const Workspace w = carve(ws, op, false);
+    const CgDev D = w.outer;
+    const Ctx<double> c(op);
+    const int nb = c.g.n_blocks;
+    reset_state(D, 1, s);
+    by_v<double>(c.t.vec, [&](auto Vt) {
+        constexpr int V = decltype(Vt)::value;
+        Src mean{nullptr, 0};
+        if (op->singular) {
+            hipLaunchKernelGGL((k_sum<double, V>), c.grid, c.block, 0, s, c.a, D, B, D.part_a);
+            mean = fold_or_direct(D, D.part_a, 1, nb, 0, D.tot + 3 * D.G, s);
+        }
+        launch_lap<double>(op, X, w.q, nullptr, s);
+        // given = 1: x is only read.
+        hipLaunchKernelGGL((k_cg_init<double, V>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), B, w.bp,
+                           const_cast<double *>(X), w.r, w.q, 1);
+        FVX_HIP(hipGetLastError());
+    });
+    const auto t = host_totals(D, D.part_b, 2, nb, s);
+    double worst = 0.0;
+    for (int g = 0; g < D.G; ++g) {
+        const double rr = t[g], bb = t[D.G + g];
+        if (!std::isfinite(rr) || !std::isfinite(bb)) return INFINITY;
+        if (bb > 0.0)
+            worst = std::max(worst, std::sqrt(rr / bb));
+        else if (rr > 0.0)
+            return INFINITY;
+    }
+    return worst;
+}
+
 }  // namespace fvx
 
 using fvx::guard;

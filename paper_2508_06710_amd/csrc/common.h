@@ -19,6 +19,7 @@
 
 struct fvx_mesh {
     int n_cells = 0, n_faces = 0, n_walls = 0;
+    int grid_nx = 0, grid_ny = 0;  // Cartesian builder: cell (i, j) is j*nx + i; 0 otherwise
     std::vector<double> area, cx, cy;
     std::vector<int32_t> c1, c2;
     std::vector<double> len, dist;
@@ -61,6 +62,7 @@ struct fvx_op {
     double dz = 0;
     int W = 0, Wd = 0;      // ELL widths (Laplacian off-diagonals, cell->face)
     bool has_f32 = false;
+    int grid_nx = 0, grid_ny = 0;  // structured base (Cartesian builder), else 0
     int device = 0;
     fvx::OpDev<double> d64;
     fvx::OpDev<float> d32;
@@ -175,5 +177,11 @@ RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks);
 // block and the plane coupling: the "no block reuse" form of the operator.
 void expand_csr(const fvx_mesh &m, const fvx_op_desc &d, std::vector<int32_t> &ptr, std::vector<int32_t> &col,
                 std::vector<double> &val);
+
+// max over the CG groups of ||bp - L x|| / ||bp|| (bp: b after the solver's
+// projection) for a given x, in FP64; +inf when a value is not finite or a
+// group has bp = 0 but a nonzero residual.  ws: a solve workspace of op.
+// Synchronises s.
+double guess_residual_ratio(const fvx_op *op, const double *B, const double *X, void *ws, hipStream_t s);
 
 }  // namespace fvx

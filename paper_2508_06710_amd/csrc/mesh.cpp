@@ -97,6 +97,8 @@ int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y
         }
         const int nc = nx * ny;
         m->n_cells = nc;
+        m->grid_nx = nx;
+        m->grid_ny = ny;
         m->area.resize(nc);
         m->cx.resize(nc);
         m->cy.resize(nc);

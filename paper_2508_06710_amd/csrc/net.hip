@@ -1,0 +1,749 @@
+// Learned initial guess for the Poisson solve: a 4-layer 3x3x3 convolutional
+// network (2 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three
+// layers, FP32 weights and accumulation) on the structured grid of a
+// Cartesian base (nx x ny cells, cell j*nx + i) extruded into nz planes.
+// Padding is periodic in x and z and replicates the edge cell in y (zero
+// gradient at the walls).
+//
+// Activations are stored [sample][channel][z][y][x] (x fastest).  The
+// parameters of layer l are its weights [co][ci][tap], tap = (dz*3 + dy)*3 +
+// dx reading the input at (z + dz - 1, y + dy - 1, x + dx - 1), then its
+// biases [co]; layers follow each other in one array.  Weight gradients are
+// per-block partials summed in a fixed order, so training is deterministic.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+struct fvx_net {
+    int nx = 0, ny = 0, nz = 0, batch = 0, cells = 0;
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+    float *act[5] = {};   // act[0]: input (2 ch), act[1..3]: 32 ch after ReLU, act[4]: output (1 ch)
+    float *g0 = nullptr, *g1 = nullptr;  // gradient ping-pong buffers (32 ch)
+    float *part = nullptr;               // weight-gradient partials
+    float *lossp = nullptr;              // loss partials
+    double *scal = nullptr;              // [0] mean of b removed, [1] scale s
+    int step = 0;                        // Adam steps taken
+};
+
+namespace fvx {
+namespace net {
+
+constexpr int kC = 32;
+constexpr int kTaps = 27;
+constexpr int kLayers = 4;
+constexpr int kCin[kLayers] = {2, kC, kC, kC};
+constexpr int kCout[kLayers] = {kC, kC, kC, 1};
+constexpr int kBlock = 256;
+constexpr int kChunk = 8;        // channels of weights staged in LDS at a time
+constexpr int kPosBlocks = 256;  // position ranges of the weight-gradient reduction
+constexpr int kTile = 64;        // positions staged per pass of the weight gradient
+constexpr int kLossBlocks = 256;
+
+constexpr int64_t w_size(int l) { return int64_t(kCout[l]) * kCin[l] * kTaps; }
+constexpr int64_t layer_offset(int l) { return l == 0 ? 0 : layer_offset(l - 1) + w_size(l - 1) + kCout[l - 1]; }
+constexpr int64_t n_params() { return layer_offset(kLayers); }
+constexpr int64_t part_floats() { return int64_t(kPosBlocks) * (int64_t(kC) * kTaps * kC + kC); }
+
+struct Grid {
+    int X, Y, Z, cells;
+};
+
+// Offsets of the three input neighbours along each axis of cell (x, y, z).
+struct Taps {
+    int x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ Taps fwd_taps(const Grid &g, int x, int y, int z) {
+    Taps t;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        t.x[d] = wrap(x + d - 1, g.X);
+        t.y[d] = min(max(y + d - 1, 0), g.Y - 1) * g.X;
+        t.z[d] = wrap(z + d - 1, g.Z) * g.X * g.Y;
+    }
+    return t;
+}
+
+// Output cells o that read input cell (x, y, z) through tap offset d along
+// each axis: one in x and z (periodic); in y the row y - d + 1 when it
+// exists (ya) plus, at the walls, the row whose clamped read lands on y (yb).
+struct AdjTaps {
+    int x[3], z[3], ya[3], yb[3];
+};
+
+__device__ __forceinline__ AdjTaps adj_taps(const Grid &g, int x, int y, int z) {
+    AdjTaps t;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        t.x[d] = wrap(x - d + 1, g.X);
+        t.z[d] = wrap(z - d + 1, g.Z) * g.X * g.Y;
+        const int oy = y - d + 1;
+        t.ya[d] = (oy >= 0 && oy < g.Y) ? oy * g.X : -1;
+        t.yb[d] = -1;
+    }
+    if (y == 0) t.yb[0] = 0;                      // o_y = 0 reads row -1, clamped to 0
+    if (y == g.Y - 1) t.yb[2] = (g.Y - 1) * g.X;  // o_y = Y-1 reads row Y, clamped to Y-1
+    return t;
+}
+
+// Position (sample n, cell) of flat index pos < ns*cells and its coordinates.
+struct Pos {
+    int n, cell, x, y, z;
+};
+
+__device__ __forceinline__ Pos pos_of(const Grid &g, int pos) {
+    Pos p;
+    p.n = pos / g.cells;
+    p.cell = pos - p.n * g.cells;
+    const int xy = g.X * g.Y;
+    p.z = p.cell / xy;
+    const int r = p.cell - p.z * xy;
+    p.y = r / g.X;
+    p.x = r - p.y * g.X;
+    return p;
+}
+
+// out[n][co][cell] = bias[co] + sum_{ci,tap} W[co][ci][tap] in[n][ci][src(cell, tap)],
+// optionally through a ReLU.  Each thread computes all CO outputs of CPT
+// cells spaced `per` apart; the weights of kChunk input channels at a time
+// are staged in LDS as [ci][tap][co] and read as wave-wide broadcasts.
+template <int CO, int CPT>
+__global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, const float *__restrict__ in,
+                                                     const float *__restrict__ W, const float *__restrict__ bias,
+                                                     float *__restrict__ out, int relu) {
+    __shared__ __align__(16) float w_s[kChunk * kTaps * CO];
+    const int total = g.cells * ns;
+    const int per = (total + CPT - 1) / CPT;
+    const int gid = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    int base[CPT], obase[CPT];
+    bool live[CPT];
+    Taps t[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int pos = gid + c * per;
+        live[c] = gid < per && pos < total;
+        const Pos p = pos_of(g, live[c] ? pos : 0);
+        t[c] = fwd_taps(g, p.x, p.y, p.z);
+        base[c] = p.n * CI * g.cells;
+        obase[c] = p.n * CO * g.cells + p.cell;
+    }
+    float acc[CPT][CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) acc[c][co] = bias[co];
+    for (int c0 = 0; c0 < CI; c0 += kChunk) {
+        const int nc = min(kChunk, CI - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc * kTaps * CO; i += blockDim.x) {
+            const int co = i % CO, rest = i / CO, tap = rest % kTaps, ci = rest / kTaps;
+            w_s[i] = W[(co * CI + c0 + ci) * kTaps + tap];
+        }
+        __syncthreads();
+        for (int ci = 0; ci < nc; ++ci) {
+            const int coff = (c0 + ci) * g.cells;
+#pragma unroll
+            for (int tap = 0; tap < kTaps; ++tap) {
+                const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+                float a[CPT];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) a[c] = in[base[c] + coff + t[c].z[dz] + t[c].y[dy] + t[c].x[dx]];
+                const float *w = w_s + (ci * kTaps + tap) * CO;
+#pragma unroll
+                for (int co = 0; co < CO; ++co)
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) acc[c][co] += w[co] * a[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        if (!live[c]) continue;
+#pragma unroll
+        for (int co = 0; co < CO; ++co) out[obase[c] + co * g.cells] = relu ? fmaxf(acc[c][co], 0.0f) : acc[c][co];
+    }
+}
+
+// Gradient with respect to a 32-channel layer input:
+// din[n][ci][p] = sum_{co,tap} W[co][ci][tap] sum_{o reads p at tap} dout[n][co][o],
+// multiplied by the ReLU derivative (act_in > 0) of the layer that produced
+// the input.  Weights staged as [co][tap][ci].
+template <int CPT>
+__global__ __launch_bounds__(kBlock) void k_conv_bwd_data(Grid g, int ns, int CO, const float *__restrict__ dout,
+                                                          const float *__restrict__ W,
+                                                          const float *__restrict__ act_in, float *__restrict__ din) {
+    constexpr int CI = kC;
+    __shared__ __align__(16) float w_s[kChunk * kTaps * CI];
+    const int total = g.cells * ns;
+    const int per = (total + CPT - 1) / CPT;
+    const int gid = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    int dbase[CPT], ibase[CPT];
+    bool live[CPT];
+    AdjTaps t[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int pos = gid + c * per;
+        live[c] = gid < per && pos < total;
+        const Pos p = pos_of(g, live[c] ? pos : 0);
+        t[c] = adj_taps(g, p.x, p.y, p.z);
+        dbase[c] = p.n * CO * g.cells;
+        ibase[c] = p.n * CI * g.cells + p.cell;
+    }
+    float acc[CPT][CI];
+#pragma unroll
+    for (int ci = 0; ci < CI; ++ci)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) acc[c][ci] = 0.0f;
+    for (int c0 = 0; c0 < CO; c0 += kChunk) {
+        const int nc = min(kChunk, CO - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nc * kTaps * CI; i += blockDim.x) {
+            const int ci = i % CI, rest = i / CI, tap = rest % kTaps, co = rest / kTaps;
+            w_s[i] = W[((c0 + co) * CI + ci) * kTaps + tap];
+        }
+        __syncthreads();
+        for (int co = 0; co < nc; ++co) {
+            const int coff = (c0 + co) * g.cells;
+#pragma unroll
+            for (int tap = 0; tap < kTaps; ++tap) {
+                const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+                float s[CPT];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const float *d = dout + dbase[c] + coff + t[c].z[dz] + t[c].x[dx];
+                    // Both reads are in bounds (offset 0 stands in for a missing row) and
+                    // selected without a branch, which keeps the unrolled taps in registers.
+                    const float va = d[max(t[c].ya[dy], 0)], vb = d[max(t[c].yb[dy], 0)];
+                    s[c] = (t[c].ya[dy] >= 0 ? va : 0.0f) + (t[c].yb[dy] >= 0 ? vb : 0.0f);
+                }
+                const float *w = w_s + (co * kTaps + tap) * CI;
+#pragma unroll
+                for (int ci = 0; ci < CI; ++ci)
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) acc[c][ci] += w[ci] * s[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        if (!live[c]) continue;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int o = ibase[c] + ci * g.cells;
+            din[o] = act_in[o] > 0.0f ? acc[c][ci] : 0.0f;
+        }
+    }
+}
+
+// Weight and bias gradient partials over the positions [p0, p0 + per) of
+// block x: thread j of block y owns the (ci, tap) pair y*blockDim + j and
+// accumulates sum_pos dout[co][pos] * in[ci][src(pos, tap)] for every co.
+// part[bx][(ci*27 + tap)*CO + co]; the biases at part[bx][CI*27*CO + co].
+template <int CO>
+__global__ __launch_bounds__(kBlock) void k_conv_bwd_w(Grid g, int ns, int CI, const float *__restrict__ dout,
+                                                       const float *__restrict__ in, int per,
+                                                       float *__restrict__ part) {
+    __shared__ __align__(16) float d_s[kTile * CO];  // [j][co]
+    __shared__ int p_s[kTile * 4];                    // input base, x, y, z of position j
+    const int total = g.cells * ns;
+    const int p0 = int(blockIdx.x) * per, p1 = min(total, p0 + per);
+    const int npair = CI * kTaps;
+    const int pair = int(blockIdx.y) * blockDim.x + threadIdx.x;
+    const bool mine = pair < npair;
+    const int ci = mine ? pair / kTaps : 0, tap = mine ? pair % kTaps : 0;
+    const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+    const bool do_bias = blockIdx.y == 0 && threadIdx.x < CO;
+    float acc[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) acc[co] = 0.0f;
+    float bacc = 0.0f;
+    for (int t0 = p0; t0 < p1; t0 += kTile) {
+        const int nt = min(kTile, p1 - t0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < kTile * CO; i += blockDim.x) {
+            const int j = i % kTile, co = i / kTile;
+            float v = 0.0f;
+            if (j < nt) {
+                const Pos p = pos_of(g, t0 + j);
+                v = dout[(p.n * CO + co) * g.cells + p.cell];
+            }
+            d_s[j * CO + co] = v;
+        }
+        for (int j = threadIdx.x; j < nt; j += blockDim.x) {
+            const Pos p = pos_of(g, t0 + j);
+            p_s[4 * j] = p.n * CI * g.cells;
+            p_s[4 * j + 1] = p.x;
+            p_s[4 * j + 2] = p.y;
+            p_s[4 * j + 3] = p.z;
+        }
+        __syncthreads();
+        if (mine) {
+            const float *src = in + ci * g.cells;
+            for (int j = 0; j < nt; ++j) {
+                const int xs = wrap(p_s[4 * j + 1] + dx - 1, g.X);
+                const int ys = min(max(p_s[4 * j + 2] + dy - 1, 0), g.Y - 1);
+                const int zs = wrap(p_s[4 * j + 3] + dz - 1, g.Z);
+                const float a = src[p_s[4 * j] + (zs * g.Y + ys) * g.X + xs];
+                const float *d = d_s + j * CO;
+#pragma unroll
+                for (int co = 0; co < CO; ++co) acc[co] += d[co] * a;
+            }
+        }
+        if (do_bias)
+            for (int j = 0; j < nt; ++j) bacc += d_s[j * CO + threadIdx.x];
+    }
+    float *out = part + size_t(blockIdx.x) * (size_t(npair) * CO + CO);
+    if (mine)
+#pragma unroll
+        for (int co = 0; co < CO; ++co) out[pair * CO + co] = acc[co];
+    if (do_bias) out[npair * CO + threadIdx.x] = bacc;
+}
+
+// Gradients of one layer (weights [co][ci][tap], biases) = sum over the
+// position blocks of the partials, in block order.
+__global__ __launch_bounds__(kBlock) void k_fold_w(const float *__restrict__ part, int nblk, int CI, int CO,
+                                                   float *__restrict__ gw, float *__restrict__ gb) {
+    const int npair = CI * kTaps;
+    const int stride = npair * CO + CO;
+    for (int v = int(blockIdx.x) * blockDim.x + threadIdx.x; v < stride; v += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int b = 0; b < nblk; ++b) s += part[size_t(b) * stride + v];
+        if (v < npair * CO) {
+            const int pr = v / CO, co = v % CO;
+            gw[(co * CI + pr / kTaps) * kTaps + pr % kTaps] = s;
+        } else {
+            gb[v - npair * CO] = s;
+        }
+    }
+}
+
+// Mean-squared error over n values: d = 2 (out - t) / n and per-block
+// partial sums of (out - t)^2.
+__global__ __launch_bounds__(kBlock) void k_mse(const float *__restrict__ out, const float *__restrict__ t, int n,
+                                                float *__restrict__ d, float *__restrict__ part) {
+    __shared__ float s[kBlock];
+    float acc = 0.0f;
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float e = out[i] - t[i];
+        d[i] = 2.0f * e / float(n);
+        acc += e * e;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Adam with bias correction (Kingma and Ba, 2015); c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ __launch_bounds__(kBlock) void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                                                 float *__restrict__ m, float *__restrict__ v, int n, float lr,
+                                                 float b1, float b2, float eps, float c1, float c2) {
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(float *__restrict__ p, int n) {
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+__device__ double block_sum(double v, double *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Scales of one sample (one block): s[0] = plain mean of b (0 unless the
+// operator is singular), s[1] = rms over the cells of the source density
+// f = (b - s[0]) / (area * dz), or 1 when it is zero.  B: AoS [n_b][ld].
+__global__ __launch_bounds__(1024) void k_scale(Grid g, const double *__restrict__ B, int ld,
+                                                const double *__restrict__ area, double inv_dz, int singular,
+                                                double *__restrict__ s) {
+    __shared__ double red[1024];
+    const int k = g.Z;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) a += B[(i / k) * ld + i % k];
+    const double sum = block_sum(a, red);
+    const double mean = singular ? sum / double(g.cells) : 0.0;
+    a = 0.0;
+    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) {
+        const int c = i / k;
+        const double f = (B[c * ld + i % k] - mean) / area[c] * inv_dz;
+        a += f * f;
+    }
+    const double rms = sqrt(block_sum(a, red) / double(g.cells));
+    if (threadIdx.x == 0) {
+        s[0] = mean;
+        s[1] = rms > 0.0 ? rms : 1.0;
+    }
+}
+
+// Network input of one sample: in[0][cell] = f / s, in[1][cell] = p_prev / s
+// (0 without a previous pressure); the optional target is x* / s.
+__global__ __launch_bounds__(kBlock) void k_prepare(Grid g, const double *__restrict__ B,
+                                                    const double *__restrict__ P, const double *__restrict__ Xs, int ld,
+                                                    const double *__restrict__ area, double inv_dz,
+                                                    const double *__restrict__ s, float *__restrict__ in,
+                                                    float *__restrict__ target) {
+    const int nb = g.X * g.Y;
+    const double mean = s[0], sc = s[1];
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < g.cells; i += gridDim.x * blockDim.x) {
+        const int c = i % nb, z = i / nb;
+        const int o = c * ld + z;
+        in[i] = float((B[o] - mean) / area[c] * inv_dz / sc);
+        in[g.cells + i] = P ? float(P[o] / sc) : 0.0f;
+        if (target) target[i] = float(Xs[o] / sc);
+    }
+}
+
+// x0 = s * (out - mean(out)) (mean removed only for a singular operator),
+// written into the AoS [n_b][ld] vector X (one block).
+__global__ __launch_bounds__(1024) void k_guess_out(Grid g, const float *__restrict__ out,
+                                                    const double *__restrict__ s, int singular,
+                                                    double *__restrict__ X, int ld) {
+    __shared__ double red[1024];
+    const int nb = g.X * g.Y;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) a += double(out[i]);
+    const double sum = block_sum(a, red);
+    const double mean = singular ? sum / double(g.cells) : 0.0;
+    const double sc = s[1];
+    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) X[(i % nb) * ld + i / nb] = sc * (double(out[i]) - mean);
+}
+
+Grid grid_of(const fvx_net *n) { return Grid{n->nx, n->ny, n->nz, n->cells}; }
+
+template <int CO, int CPT>
+void conv_fwd(const Grid &g, int ns, int CI, const float *in, const float *W, const float *b, float *out, int relu,
+              hipStream_t s) {
+    const int64_t threads = ceil_div(int64_t(g.cells) * ns, CPT);
+    hipLaunchKernelGGL((k_conv_fwd<CO, CPT>), dim3(unsigned(ceil_div(threads, kBlock))), dim3(kBlock), 0, s, g, ns,
+                       CI, in, W, b, out, relu);
+}
+
+void forward(fvx_net *net, int ns, const float *in, hipStream_t s) {
+    const Grid g = grid_of(net);
+    const float *src = in;
+    for (int l = 0; l < kLayers; ++l) {
+        const float *W = net->params + layer_offset(l);
+        const float *b = W + w_size(l);
+        if (kCout[l] == kC)
+            conv_fwd<kC, 2>(g, ns, kCin[l], src, W, b, net->act[l + 1], 1, s);
+        else
+            conv_fwd<1, 4>(g, ns, kCin[l], src, W, b, net->act[l + 1], 0, s);
+        src = net->act[l + 1];
+    }
+    FVX_HIP(hipGetLastError());
+}
+
+// Forward pass, loss and all parameter gradients (into net->grads); returns
+// the mean-squared error after synchronising the stream.
+double backward(fvx_net *n, int ns, const float *in, const float *target, hipStream_t s) {
+    const Grid g = grid_of(n);
+    forward(n, ns, in, s);
+    const int nout = g.cells * ns;
+    hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kBlock), 0, s, n->act[4], target, nout, n->g0, n->lossp);
+    FVX_HIP(hipGetLastError());
+    float *dcur = n->g0, *dnext = n->g1;
+    const int per = int(ceil_div(nout, kPosBlocks));
+    const int nblk = int(ceil_div(nout, per));
+    const int64_t threads2 = ceil_div(nout, 2);
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const int CI = kCin[l], CO = kCout[l];
+        const float *W = n->params + layer_offset(l);
+        float *gw = n->grads + layer_offset(l), *gb = gw + w_size(l);
+        const float *lin = l == 0 ? in : n->act[l];
+        const dim3 wgrid(unsigned(nblk), unsigned(ceil_div(CI * kTaps, kBlock)));
+        if (CO == kC)
+            hipLaunchKernelGGL((k_conv_bwd_w<kC>), wgrid, dim3(kBlock), 0, s, g, ns, CI, dcur, lin, per, n->part);
+        else
+            hipLaunchKernelGGL((k_conv_bwd_w<1>), wgrid, dim3(kBlock), 0, s, g, ns, CI, dcur, lin, per, n->part);
+        hipLaunchKernelGGL(k_fold_w, dim3(64), dim3(kBlock), 0, s, n->part, nblk, CI, CO, gw, gb);
+        if (l > 0) {
+            hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(unsigned(ceil_div(threads2, kBlock))), dim3(kBlock), 0, s,
+                               g, ns, CO, dcur, W, n->act[l], dnext);
+            std::swap(dcur, dnext);
+        }
+        FVX_HIP(hipGetLastError());
+    }
+    std::vector<float> lp(kLossBlocks);
+    FVX_HIP(hipMemcpyAsync(lp.data(), n->lossp, 4 * kLossBlocks, hipMemcpyDeviceToHost, s));
+    FVX_HIP(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (float v : lp) sum += double(v);
+    return sum / double(nout);
+}
+
+struct Layout {
+    size_t params, grads, m, v, act[5], g0, g1, part, lossp, scal, total;
+};
+
+Layout layout(int nx, int ny, int nz, int batch) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off += (b + 255) / 256 * 256;
+        return o;
+    };
+    const size_t cells = size_t(nx) * ny * nz, np = size_t(n_params()), B = size_t(batch);
+    L.params = take(4 * np);
+    L.grads = take(4 * np);
+    L.m = take(4 * np);
+    L.v = take(4 * np);
+    L.act[0] = take(4 * B * 2 * cells);
+    for (int l = 1; l <= 3; ++l) L.act[l] = take(4 * B * kC * cells);
+    L.act[4] = take(4 * B * cells);
+    L.g0 = take(4 * B * kC * cells);
+    L.g1 = take(4 * B * kC * cells);
+    L.part = take(4 * size_t(part_floats()));
+    L.lossp = take(4 * kLossBlocks);
+    L.scal = take(8 * 2);
+    L.total = off;
+    return L;
+}
+
+void check_dims(int nx, int ny, int nz, int batch) {
+    FVX_REQUIRE(nx >= 1 && ny >= 1 && nz >= 1 && batch >= 1, FVX_E_ARG, "net dimensions must be >= 1");
+    FVX_REQUIRE(int64_t(nx) * ny * nz * batch * kC < (int64_t(1) << 31), FVX_E_ARG,
+                "net too large for 32-bit activation indices (nx*ny*nz*batch*32 >= 2^31)");
+}
+
+void check_net(const fvx_net *n) { FVX_REQUIRE(n, FVX_E_ARG, "net is NULL"); }
+
+void check_samples(const fvx_net *n, int ns) {
+    FVX_REQUIRE(ns >= 1 && ns <= n->batch, FVX_E_ARG, "sample count must be in [1, batch]");
+}
+
+void check_op(const fvx_net *n, const fvx_op *op) {
+    FVX_REQUIRE(op, FVX_E_ARG, "op is NULL");
+    FVX_REQUIRE(op->grid_nx == n->nx && op->grid_ny == n->ny && op->k == n->nz, FVX_E_ARG,
+                "operator is not the net's grid (Cartesian base nx x ny, k = nz)");
+}
+
+void zero(float *p, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(64), dim3(kBlock), 0, s, p, int(n));
+    FVX_HIP(hipGetLastError());
+}
+
+void guess(fvx_net *n, const fvx_op *op, const double *B, const double *Pprev, double *X0, hipStream_t s) {
+    const Grid g = grid_of(n);
+    hipLaunchKernelGGL(k_scale, dim3(1), dim3(1024), 0, s, g, B, op->ld, op->d64.area, 1.0 / op->dz,
+                       int(op->singular), n->scal);
+    hipLaunchKernelGGL(k_prepare, dim3(unsigned(std::min<int64_t>(1024, ceil_div(g.cells, kBlock)))), dim3(kBlock), 0,
+                       s, g, B, Pprev, (const double *)nullptr, op->ld, op->d64.area, 1.0 / op->dz, n->scal,
+                       n->act[0], (float *)nullptr);
+    forward(n, 1, n->act[0], s);
+    hipLaunchKernelGGL(k_guess_out, dim3(1), dim3(1024), 0, s, g, n->act[4], n->scal, int(op->singular), X0, op->ld);
+    FVX_HIP(hipGetLastError());
+}
+
+}  // namespace net
+}  // namespace fvx
+
+using fvx::guard;
+namespace N = fvx::net;
+
+extern "C" {
+
+int fvx_net_n_params(void) { return int(N::n_params()); }
+
+int fvx_net_bytes(int nx, int ny, int nz, int batch, size_t *bytes) {
+    return guard([&] {
+        N::check_dims(nx, ny, nz, batch);
+        FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
+        *bytes = N::layout(nx, ny, nz, batch).total;
+        return FVX_OK;
+    });
+}
+
+int fvx_net_create(int nx, int ny, int nz, int batch, const float *init, void *dev_mem, size_t bytes, void *stream,
+                   fvx_net **out) {
+    return guard([&] {
+        N::check_dims(nx, ny, nz, batch);
+        FVX_REQUIRE(out && dev_mem, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(reinterpret_cast<uintptr_t>(dev_mem) % 256 == 0, FVX_E_ARG, "dev_mem must be 256-byte aligned");
+        const N::Layout L = N::layout(nx, ny, nz, batch);
+        FVX_REQUIRE(bytes >= L.total, FVX_E_NOMEM, "net buffer too small: need " + std::to_string(L.total));
+        auto n = std::make_unique<fvx_net>();
+        char *b = static_cast<char *>(dev_mem);
+        n->nx = nx;
+        n->ny = ny;
+        n->nz = nz;
+        n->batch = batch;
+        n->cells = nx * ny * nz;
+        auto f = [&](size_t off) { return reinterpret_cast<float *>(b + off); };
+        n->params = f(L.params);
+        n->grads = f(L.grads);
+        n->m = f(L.m);
+        n->v = f(L.v);
+        for (int l = 0; l < 5; ++l) n->act[l] = f(L.act[l]);
+        n->g0 = f(L.g0);
+        n->g1 = f(L.g1);
+        n->part = f(L.part);
+        n->lossp = f(L.lossp);
+        n->scal = reinterpret_cast<double *>(b + L.scal);
+        hipStream_t s = fvx::as_stream(stream);
+        const int64_t np = N::n_params();
+        if (init)
+            FVX_HIP(hipMemcpyAsync(n->params, init, 4 * size_t(np), hipMemcpyHostToDevice, s));
+        else
+            N::zero(n->params, np, s);
+        N::zero(n->grads, np, s);
+        N::zero(n->m, np, s);
+        N::zero(n->v, np, s);
+        FVX_HIP(hipStreamSynchronize(s));
+        *out = n.release();
+        return FVX_OK;
+    });
+}
+
+int fvx_net_destroy(fvx_net *n) {
+    delete n;
+    return FVX_OK;
+}
+
+int fvx_net_get_params(const fvx_net *n, float *params, float *grads) {
+    return guard([&] {
+        N::check_net(n);
+        const size_t np = size_t(N::n_params());
+        if (params) FVX_HIP(hipMemcpy(params, n->params, 4 * np, hipMemcpyDeviceToHost));
+        if (grads) FVX_HIP(hipMemcpy(grads, n->grads, 4 * np, hipMemcpyDeviceToHost));
+        return FVX_OK;
+    });
+}
+
+int fvx_net_set_params(fvx_net *n, const float *params, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        FVX_REQUIRE(params, FVX_E_ARG, "params is NULL");
+        hipStream_t s = fvx::as_stream(stream);
+        const int64_t np = N::n_params();
+        FVX_HIP(hipMemcpyAsync(n->params, params, 4 * size_t(np), hipMemcpyHostToDevice, s));
+        N::zero(n->m, np, s);
+        N::zero(n->v, np, s);
+        FVX_HIP(hipStreamSynchronize(s));
+        n->step = 0;
+        return FVX_OK;
+    });
+}
+
+int fvx_net_forward(fvx_net *n, int ns, const float *in, float *out, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        N::check_samples(n, ns);
+        FVX_REQUIRE(in && out, FVX_E_ARG, "NULL input or output");
+        hipStream_t s = fvx::as_stream(stream);
+        N::forward(n, ns, in, s);
+        FVX_HIP(hipMemcpyAsync(out, n->act[4], 4 * size_t(ns) * n->cells, hipMemcpyDeviceToDevice, s));
+        return FVX_OK;
+    });
+}
+
+int fvx_net_gradients(fvx_net *n, int ns, const float *in, const float *target, double *loss, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        N::check_samples(n, ns);
+        FVX_REQUIRE(in && target, FVX_E_ARG, "NULL input or target");
+        const double l = N::backward(n, ns, in, target, fvx::as_stream(stream));
+        if (loss) *loss = l;
+        return FVX_OK;
+    });
+}
+
+int fvx_net_train_step(fvx_net *n, int ns, const float *in, const float *target, float lr, double *loss,
+                       void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        N::check_samples(n, ns);
+        FVX_REQUIRE(in && target, FVX_E_ARG, "NULL input or target");
+        FVX_REQUIRE(lr > 0.0f && std::isfinite(lr), FVX_E_ARG, "lr must be positive");
+        hipStream_t s = fvx::as_stream(stream);
+        const double l = N::backward(n, ns, in, target, s);
+        n->step += 1;
+        const double b1 = 0.9, b2 = 0.999;
+        const float c1 = float(1.0 - std::pow(b1, n->step)), c2 = float(1.0 - std::pow(b2, n->step));
+        hipLaunchKernelGGL(N::k_adam, dim3(64), dim3(N::kBlock), 0, s, n->params, n->grads, n->m, n->v,
+                           int(N::n_params()), lr, float(b1), float(b2), 1e-8f, c1, c2);
+        FVX_HIP(hipGetLastError());
+        if (loss) *loss = l;
+        return FVX_OK;
+    });
+}
+
+int fvx_net_prepare(fvx_net *n, const fvx_op *op, const double *B, const double *Pprev, const double *Xstar,
+                    float *in, float *target, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        N::check_op(n, op);
+        FVX_REQUIRE(B && in && (target == nullptr) == (Xstar == nullptr), FVX_E_ARG,
+                    "NULL B or input, or only one of target and Xstar");
+        hipStream_t s = fvx::as_stream(stream);
+        const N::Grid g = N::grid_of(n);
+        hipLaunchKernelGGL(N::k_scale, dim3(1), dim3(1024), 0, s, g, B, op->ld, op->d64.area, 1.0 / op->dz,
+                           int(op->singular), n->scal);
+        hipLaunchKernelGGL(N::k_prepare, dim3(unsigned(std::min<int64_t>(1024, fvx::ceil_div(g.cells, N::kBlock)))),
+                           dim3(N::kBlock), 0, s, g, B, Pprev, Xstar, op->ld, op->d64.area, 1.0 / op->dz, n->scal,
+                           in, target);
+        FVX_HIP(hipGetLastError());
+        return FVX_OK;
+    });
+}
+
+int fvx_net_guess(fvx_net *n, const fvx_op *op, const double *B, const double *Pprev, double *X0, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        N::check_op(n, op);
+        FVX_REQUIRE(B && X0, FVX_E_ARG, "NULL argument");
+        N::guess(n, op, B, Pprev, X0, fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_poisson_solve_net(const fvx_op *op, fvx_net *n, const double *B, const double *Pprev, double *X,
+                          const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
+                          int *fallback, void *stream) {
+    const auto t0 = std::chrono::steady_clock::now();
+    fvx_solve_opts o{};
+    const int rc = guard([&]() -> int {
+        N::check_net(n);
+        N::check_op(n, op);
+        FVX_REQUIRE(B && X && opts && ws, FVX_E_ARG, "NULL argument");
+        size_t need = 0;
+        const int q = fvx_solve_bytes(op, opts, &need);
+        if (q != FVX_OK) return q;
+        FVX_REQUIRE(ws_bytes >= need, FVX_E_NOMEM, "workspace too small: need " + std::to_string(need));
+        FVX_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, FVX_E_ARG, "ws must be 256-byte aligned");
+        hipStream_t s = fvx::as_stream(stream);
+        N::guess(n, op, B, Pprev, X, s);
+        const double ratio = fvx::guess_residual_ratio(op, B, X, ws, s);
+        o = *opts;
+        o.guess = ratio < 1.0 ? FVX_GUESS_GIVEN : FVX_GUESS_ZERO;
+        if (fallback) *fallback = o.guess == FVX_GUESS_ZERO;
+        return FVX_OK;
+    });
+    if (rc != FVX_OK) return rc;
+    const int st = fvx_poisson_solve(op, B, X, &o, ws, ws_bytes, stats, stream);
+    if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+}  // extern "C"

@@ -332,6 +332,8 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         op->W = h.W;
         op->Wd = h.Wd;
         op->has_f32 = f32;
+        op->grid_nx = m->grid_nx;
+        op->grid_ny = m->grid_ny;
         FVX_HIP(hipGetDevice(&op->device));
         auto fill = [&](auto &D, int p, auto tag) {
             using T = decltype(tag);
