@@ -214,10 +214,15 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--counters", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-airfoil", action="store_true")
+    ap.add_argument("--no-guess", action="store_true")
+    ap.add_argument("--guess-epochs", type=int, default=20)
+    ap.add_argument("--guess-lr", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding is a design, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path runs on a single device)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -233,6 +238,7 @@ def main():
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
+        args.no_batch = args.no_airfoil = args.no_guess = True
 
     rtol = 1e-8
     log("building the channel operator")
@@ -330,6 +336,16 @@ def main():
         out.update(extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D))
         if out.get("copy_ceiling_GBs"):
             out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GBs"]
+
+    if not args.no_batch:
+        out["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
+        torch.cuda.empty_cache()
+    if not args.no_airfoil:
+        out["airfoil"] = airfoil_leg(fvx, inputs, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_guess:
+        out["learned_guess"] = guess_leg(fvx, inputs, torch, np, args.guess_epochs, args.guess_lr, rtol)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("timing the CPU oracle")
@@ -429,6 +445,196 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
                        "relres_true": stm["relres_true"]}
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
+
+
+def batch_leg(fvx, inputs, torch, np, rtol):
+    """24 uneven problems (4 channel bases x k in {4..128}) solved together in
+    mixed precision to rtol, against the same problems solved one by one and
+    against plain FP64 SpMV-CG on their assembled matrices."""
+    probs = inputs.batch_problems()
+    ops, Bs, tiles = [], [], []
+    for p in probs:
+        mesh = fvx.Mesh.from_spec(p["base"])
+        op = fvx.Operator(mesh, p["k"], p["dz"], fvx.PERIODIC_Z, with_f32=True)
+        tiles.append((tune(op, fvx), tune(op, fvx, fvx.F32)))
+        Bs.append(op.to_rows(inputs.rhs_uniform(p["seed"], op.n_b * op.k)))
+        ops.append((op, mesh))
+    opl = [o for o, _ in ops]
+    cells = sum(o.n_b * o.k for o in opl)
+    log(f"batch: {len(opl)} problems, {cells} cells")
+    fvx.solve_batch(opl, Bs, rtol=rtol, precision=fvx.MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs, sts = fvx.solve_batch(opl, Bs, rtol=rtol, precision=fvx.MIXED)
+    batch_s = time.perf_counter() - t0
+    singles, csr = [], []
+    for (op, mesh), B in zip(ops, Bs):
+        op.solve(B, rtol=rtol, precision=fvx.MIXED)
+        t0 = time.perf_counter()
+        op.solve(B, rtol=rtol, precision=fvx.MIXED)
+        singles.append(time.perf_counter() - t0)
+        ptr, col, val = fvx.expand_csr(mesh, op.k, op.dz, fvx.PERIODIC_Z)
+        A = fvx.CsrMatrix(ptr, col, val)
+        b = torch.as_tensor(op.to_planes(B)).cuda()
+        A.solve(b, rtol=rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = A.solve(b, rtol=rtol)
+        csr.append(time.perf_counter() - t0)
+        del A, b
+    out = {
+        "problems": [{"base": f"{p['base'].nx}x{p['base'].ny}", "k": p["k"], "cells": o.n_b * o.k,
+                      "tile_f64": list(t[0]), "tile_f32": list(t[1]), "inner_iters": s["iters"],
+                      "outer": s["outer"], "relres_true": s["relres_true"], "single_s": ts, "csr3d_fp64_s": tc}
+                     for p, o, t, s, ts, tc in zip(probs, opl, tiles, sts, singles, csr)],
+        "cells": cells,
+        "batch_s": batch_s,
+        "sum_single_s": float(sum(singles)),
+        "sum_csr3d_fp64_s": float(sum(csr)),
+        "max_relres_true": max(s["relres_true"] for s in sts),
+        "rtol": rtol,
+    }
+    log(f"batch {batch_s:.3f} s, singles {out['sum_single_s']:.3f} s, csr3d {out['sum_csr3d_fp64_s']:.3f} s")
+    return out
+
+
+def airfoil_leg(fvx, inputs, torch, np):
+    """Extruded NACA-0012 Delaunay mesh (k = 32): SpMM bandwidth in both
+    precisions and the mixed-precision solve to 1e-10 against the FP64 solve
+    and plain FP64 SpMV-CG."""
+    rtol = 1e-10
+    spec = inputs.naca_delaunay(seed=1)
+    mesh = fvx.Mesh.from_spec(spec)
+    k, dz = inputs.AIRFOIL_K, inputs.AIRFOIL_DZ
+    op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=True)
+    res = {"cells_base": op.n_b, "k": k, "cells": op.n_b * k, "nnz_b": op.nnz_b}
+    for dt, name, v in ((fvx.F64, "f64", 8), (fvx.F32, "f32", 4)):
+        tile = tune(op, fvx, dt)
+        x = op.to_rows(inputs.uniform(0, 0, op.n_b * k), dtype=dt)
+        per = 2 * op.n_b * op.ld * v
+        R = max(2, math.ceil(COLD_BYTES / per))
+        X = [x.clone() for _ in range(R)]
+        Y = [torch.empty_like(x) for _ in range(R)]
+        lap_sweep(op, X[:2], Y[:2], torch)
+        t = lap_sweep(op, X, Y, torch, reps=2)
+        Bk = spmm_bytes(op.nnz_b, op.n_b, k, v)
+        res[f"spmm_{name}"] = {"tile": list(tile), "us": t * 1e3, "GBs": Bk / (t * 1e-3) / 1e9,
+                               "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del X, Y
+    B = op.to_rows(inputs.rhs_uniform(3, op.n_b * k))
+    for prec, name in ((fvx.MIXED, "mixed"), (fvx.F64, "f64")):
+        op.solve(B, rtol=rtol, precision=prec)
+        t0 = time.perf_counter()
+        _, st = op.solve(B, rtol=rtol, precision=prec)
+        res[f"solve_{name}"] = {"s": time.perf_counter() - t0, "iters": st["iters"], "outer": st["outer"],
+                                "relres_true": st["relres_true"]}
+    ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z)
+    A = fvx.CsrMatrix(ptr, col, val)
+    b = torch.as_tensor(op.to_planes(B)).cuda()
+    A.solve(b, rtol=rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = A.solve(b, rtol=rtol)
+    res["solve_csr3d_fp64"] = {"s": time.perf_counter() - t0, "iters": st["iters"],
+                               "relres_true": st["relres_true"]}
+    log(f"airfoil {op.n_b}x{k}: mixed {res['solve_mixed']['s']:.3f} s, f64 {res['solve_f64']['s']:.3f} s, "
+        f"csr3d {res['solve_csr3d_fp64']['s']:.3f} s")
+    return res
+
+
+def guess_leg(fvx, inputs, torch, np, epochs, lr, rtol=1e-8):
+    """Learned initial guess on the 64 x 64 x 8 channel: 2000 (rhs, solution)
+    pairs from the library's own CG (20 trajectories of 100 steps of drifting
+    Fourier modes, seed 4), Adam training, then 100 held-out pairs (seed 5,
+    5 trajectories of 20 steps) solved to rtol from a zero guess, from the
+    previous pressure, and from the network's guess."""
+    cfg = inputs.SMALL_CHANNEL
+    spec, k, dz = cfg["base"], cfg["k"], cfg["dz"]
+    mesh = fvx.Mesh.from_spec(spec)
+    op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=False)
+    tune(op, fvx)
+    cx, cy = mesh.centroids()
+    area = mesh.faces()[0]
+
+    def pairs(seed, n_traj, n_steps):
+        rhs = [[op.to_rows(inputs.integrated_rhs(m, cx, cy, area, k, dz))
+                for m in inputs.guess_trajectory(seed, r, n_steps)] for r in range(n_traj)]
+        flat = [b for tr in rhs for b in tr]
+        sol = []
+        for i in range(0, len(flat), 250):
+            chunk = flat[i:i + 250]
+            X, _ = fvx.solve_batch([op] * len(chunk), chunk, rtol=1e-10)
+            sol += X
+        it = iter(sol)
+        return [[(b, next(it)) for b in tr] for tr in rhs]
+
+    t0 = time.perf_counter()
+    train = pairs(4, 20, 100)
+    t_gen = time.perf_counter() - t0
+    net = fvx.GuessNet(spec.nx, spec.ny, k, batch=16, params=inputs.net_init(6))
+    n = sum(len(tr) for tr in train)
+    inp = torch.empty((n, 2, k, spec.ny, spec.nx), dtype=torch.float32, device="cuda")
+    tgt = torch.empty((n, 1, k, spec.ny, spec.nx), dtype=torch.float32, device="cuda")
+    i = 0
+    for tr in train:
+        for t, (b, x) in enumerate(tr):
+            net.prepare(op, b, tr[t - 1][1] if t > 0 else None, x, inp[i], tgt[i])
+            i += 1
+    del train
+    torch.cuda.synchronize()
+    log(f"guess: {n} training pairs in {t_gen:.1f} s")
+    losses = []
+    t0 = time.perf_counter()
+    steps = 0
+    for e in range(epochs):
+        perm = torch.as_tensor(np.argsort(inputs.u64(4, 500 + e, n)), device="cuda")
+        tot = 0.0
+        for j in range(0, n - 15, 16):
+            idx = perm[j:j + 16]
+            tot += net.train_step(inp.index_select(0, idx), tgt.index_select(0, idx), lr)
+            steps += 1
+        losses.append(tot / (n // 16))
+        log(f"guess: epoch {e + 1}/{epochs} loss {losses[-1]:.4e}")
+    t_train = time.perf_counter() - t0
+    del inp, tgt
+    test = pairs(5, 5, 20)
+    rec = {"zero": [], "prev": [], "net": []}
+    used = {fvx.GUESS_NET: 0, fvx.GUESS_GIVEN: 0, fvx.GUESS_ZERO: 0}
+    for tr in test:
+        for t, (b, _) in enumerate(tr):
+            prev = tr[t - 1][1] if t > 0 else None
+            _, st = op.solve(b, rtol=rtol)
+            rec["zero"].append((st["iters"], st["seconds"], st["relres_true"]))
+            X = prev.clone() if prev is not None else op.zeros()
+            _, st = op.solve(b, X, rtol=rtol, guess=fvx.GUESS_GIVEN)
+            rec["prev"].append((st["iters"], st["seconds"], st["relres_true"]))
+            _, st = net.solve(op, b, prev, rtol=rtol)
+            rec["net"].append((st["iters"], st["seconds"], st["relres_true"]))
+            used[st["source"]] += 1
+    # inference alone
+    b0, p0 = test[0][1][0], test[0][0][1]
+    X0 = op.zeros()
+    net.guess(op, b0, p0, X0)
+    tm = Timer(torch)
+    with tm:
+        for _ in range(20):
+            net.guess(op, b0, p0, X0)
+    infer_ms = tm.ms() / 20
+    summ = {m: {"mean_iters": float(np.mean([r[0] for r in v])),
+                "mean_ms_to_1e-8": 1e3 * float(np.mean([r[1] for r in v])),
+                "max_relres_true": float(max(r[2] for r in v))} for m, v in rec.items()}
+    cells = op.n_b * k
+    out = {"grid": f"{spec.nx}x{spec.ny}x{k}", "train_pairs": n, "epochs": epochs, "train_steps": steps,
+           "batch": 16, "lr": lr, "pair_generation_s": t_gen, "train_s": t_train, "epoch_losses": losses,
+           "train_ms_per_step": 1e3 * t_train / max(1, steps), "loss_first_epoch": losses[0] if losses else None,
+           "loss_last_epoch": losses[-1] if losses else None, "eval_pairs": len(rec["net"]),
+           "guess_chosen": {"net": used[fvx.GUESS_NET], "prev_pressure": used[fvx.GUESS_GIVEN],
+                            "zero": used[fvx.GUESS_ZERO]}, "inference_ms": infer_ms,
+           "inference_TFLOPs": 2 * cells * 27 * (2 * 32 + 32 * 32 * 2 + 32) / (infer_ms * 1e-3) / 1e12,
+           "zero_guess": summ["zero"], "prev_pressure_guess": summ["prev"], "net_guess": summ["net"]}
+    log(f"guess: iters zero {summ['zero']['mean_iters']:.0f}, prev {summ['prev']['mean_iters']:.0f}, "
+        f"net {summ['net']['mean_iters']:.0f} (chosen {used}); infer {infer_ms:.3f} ms")
+    return out
 
 
 if __name__ == "__main__":

@@ -61,6 +61,8 @@ enum { FVX_F64 = 0, FVX_F32 = 1, FVX_MIXED = 2 };
 enum { FVX_COUPLING_NONE = 0, FVX_COUPLING_PERIODIC_Z = 1 };
 enum { FVX_WALL_NEUMANN = 0, FVX_WALL_DIRICHLET = 1 };
 enum { FVX_GUESS_ZERO = 0, FVX_GUESS_GIVEN = 1 };
+/* Reported by fvx_poisson_solve_net only: the network's guess was used. */
+enum { FVX_GUESS_NET = 2 };
 
 typedef struct fvx_mesh fvx_mesh;   /* host-side base mesh (face graph) */
 typedef struct fvx_op fvx_op;       /* operator: base block on the device + launch tiles */
@@ -174,11 +176,15 @@ int fvx_op_get_tile(const fvx_op *op, int dtype, fvx_tile *tile);
  * for this operator (vec must divide ld, alignment, ranges above). */
 int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile);
 
-/* Autotuner.  Times the Laplacian SpMM of precision dtype on the device for a
- * set of candidate tiles (vector width, lanes per row, workgroup size, XCD
- * remap, workgroup cap) and sets the fastest on the op.  scratch: device
- * buffer for input/output pairs, at least 2 * n_b * ld * sizeof(element)
- * bytes; the more pairs fit, the colder the caches (pairs rotate).  results:
+/* Autotuner.  Times the Laplacian SpMM of precision dtype on the device for
+ * candidate tiles and sets the fastest on the op, in two stages: every row
+ * mapping (vector width, lanes per row, workgroup size) with default launch
+ * options, then every launch option (XCD remap, workgroup cap, LDS staging,
+ * non-temporal stores) around the best mapping.  Each candidate is timed with
+ * HIP events over `reps` sweeps of up to 512 launches on rotating pairs.
+ * scratch: device buffer for input/output pairs, at least
+ * 2 * n_b * ld * sizeof(element) bytes; the more pairs fit, the colder the
+ * caches (zero-filled here before timing).  results:
  * optional host array of max_results (tile, microseconds per launch) records,
  * *n_results receives the count tried.  Every candidate computes the same
  * product (the tiles are interchangeable); only the timing differs. */
@@ -232,7 +238,9 @@ typedef struct fvx_solve_opts {
     int32_t max_iter;     /* CG iteration cap (inner iterations summed for MIXED) */
     int32_t precision;    /* FVX_F64, or FVX_MIXED: FP32 SpMM and vectors inside CG,
                              FP64 dot products and scalars, FP64 outer defect correction */
-    double inner_rtol;    /* MIXED: inner CG tolerance relative to the outer residual */
+    double inner_rtol;    /* MIXED: inner CG tolerance relative to the outer residual; a
+                             correction that needs less (outer residual within
+                             1/(2 inner_rtol) of rtol ||b||) stops at half its need */
     int32_t max_outer;    /* MIXED: cap on outer corrections */
     int32_t guess;        /* FVX_GUESS_ZERO or FVX_GUESS_GIVEN (X holds x0) */
     int32_t poll_every;   /* iterations between host reads of the device flag (>= 1) */
@@ -293,7 +301,8 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  * residual deciding whether the prediction is used.
  *
  * Network: four 3x3x3 convolutions 2 -> 32 -> 32 -> 32 -> 1 with ReLU after
- * the first three, FP32 weights and FP32 accumulation, on the grid of a
+ * the first three and the input's channel 1 added to the output (the network
+ * refines the previous pressure), FP32 weights and FP32 accumulation, on the grid of a
  * Cartesian base (fvx_mesh_cartesian, nx x ny cells) extruded into nz = k
  * planes.  Padding: periodic in x and z, edge-replicated in y.
  * Tensors (device, float): samples [ns][2][nz][ny][nx] (channel 0 = f / s,
@@ -338,9 +347,19 @@ int fvx_net_forward(fvx_net *net, int ns, const float *in, float *out, void *str
  * NULL) = the loss before the step.  Synchronises `stream`. */
 int fvx_net_gradients(fvx_net *net, int ns, const float *in, const float *target, double *loss, void *stream);
 
-/* One Adam step with learning rate lr on ns samples.  Synchronises `stream`. */
+/* One Adam step with learning rate lr on ns samples (fvx_net_gradients then
+ * fvx_net_apply_adam).  Synchronises `stream`. */
 int fvx_net_train_step(fvx_net *net, int ns, const float *in, const float *target, float lr, double *loss,
                        void *stream);
+
+/* The network's gradient buffer: device float [fvx_net_n_params()], written
+ * by fvx_net_gradients and read by fvx_net_apply_adam.  A caller may combine
+ * gradients in place between the two (sum over micro-batches, or an
+ * all-reduce across data-parallel replicas).  NULL for a NULL net. */
+float *fvx_net_grads(fvx_net *net);
+
+/* One Adam step with learning rate lr from the gradient buffer as it is. */
+int fvx_net_apply_adam(fvx_net *net, float lr, void *stream);
 
 /* One training sample from solver vectors (device double [n_b][ld]): B the
  * right-hand side, Pprev the previous pressure (NULL = none), Xstar the
@@ -353,15 +372,18 @@ int fvx_net_prepare(fvx_net *net, const fvx_op *op, const double *B, const doubl
  * for right-hand side B and previous pressure Pprev (NULL = none). */
 int fvx_net_guess(fvx_net *net, const fvx_op *op, const double *B, const double *Pprev, double *X0, void *stream);
 
-/* fvx_poisson_solve started from the network's guess when it is better than
- * zero: the guess is kept when ||b - L x0|| < ||b|| (b after projection,
- * FP64, max over CG groups) and is finite; otherwise X is solved from a zero
- * guess exactly as fvx_poisson_solve with FVX_GUESS_ZERO (opts->guess is
- * ignored).  *fallback (may be NULL) = 1 when the zero guess was used.
- * ws as fvx_poisson_solve; stats->seconds includes the inference. */
+/* fvx_poisson_solve started from the best of three initial guesses, judged
+ * by the FP64 residual ||b - L x0|| / ||b|| (b after projection, max over CG
+ * groups): the network's guess (if finite), the previous pressure Pprev (if
+ * not NULL) and zero (ratio 1).  Ties keep the earlier candidate in that
+ * order.  With zero chosen the solve is exactly fvx_poisson_solve with
+ * FVX_GUESS_ZERO; opts->guess is ignored.  *source (may be NULL) =
+ * FVX_GUESS_NET, FVX_GUESS_GIVEN (the previous pressure) or FVX_GUESS_ZERO.
+ * Pprev must not overlap X.  ws as fvx_poisson_solve; stats->seconds
+ * includes the inference and the residual checks. */
 int fvx_poisson_solve_net(const fvx_op *op, fvx_net *net, const double *B, const double *Pprev, double *X,
                           const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
-                          int *fallback, void *stream);
+                          int *source, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Comparators for measurement                                         */

@@ -299,13 +299,18 @@ def batch_problems():
 NET_LAYERS = ((2, 32), (32, 32), (32, 32), (32, 1))  # (c_in, c_out) of the 3x3x3 layers
 
 
-def net_init(seed: int = 6) -> np.ndarray:
+def net_init(seed: int = 6, zero_output_layer: bool = True) -> np.ndarray:
     """Kaiming-uniform weights (bound sqrt(6 / fan_in), fan_in = 27 c_in) and
-    zero biases, flat [W[o][c][tap], b[o]] per layer, float32."""
+    zero biases, flat [W[o][c][tap], b[o]] per layer, float32.  The output
+    layer starts at zero by default, so that the untrained network returns
+    its previous-pressure input."""
     parts = []
     for li, (ci, co) in enumerate(NET_LAYERS):
         bound = math.sqrt(6.0 / (27 * ci))
-        parts.append(uniform(seed, 200 + li, co * ci * 27, -bound, bound))
+        w = uniform(seed, 200 + li, co * ci * 27, -bound, bound)
+        if zero_output_layer and li == len(NET_LAYERS) - 1:
+            w = np.zeros_like(w)
+        parts.append(w)
         parts.append(np.zeros(co))
     return np.concatenate(parts).astype(np.float32)
 

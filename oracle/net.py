@@ -13,7 +13,9 @@ computes, written out plainly:
   z and x, a copy of the edge cell in y.
 * ``conv(a, W, b)[n, o, z, y, x] = b[o] + sum_{c, dz, dy, dx}
   W[o, c, dz, dy, dx] * pad(a)[n, c, z + dz, y + dy, x + dx]``.
-* Four layers 2 -> 32 -> 32 -> 32 -> 1, ReLU after the first three.
+* Four layers 2 -> 32 -> 32 -> 32 -> 1, ReLU after the first three; the
+  output adds the input's channel 1 (the scaled previous pressure), so the
+  layers learn a correction to the previous pressure.
 * Loss = mean of (out - target)^2; gradients by the chain rule, with the
   adjoint of ``pad`` folding each halo cell back onto the cell it copies.
 * Adam (Kingma and Ba, 2015) with bias correction.
@@ -102,6 +104,7 @@ def forward(params, inp: np.ndarray):
     for (W, b), (_, _, relu) in zip(unpack(params), LAYERS):
         h = conv(acts[-1], W, b)
         acts.append(np.maximum(h, 0.0) if relu else h)
+    acts[-1] = acts[-1] + acts[0][:, 1:2]
     return acts
 
 

@@ -11,7 +11,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
+from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
                    PERIODIC_Z, FvxError, SolveOpts, SolveStats, Tile, check, lib)
 
 __all__ = ["Mesh", "Operator", "GuessNet", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
@@ -452,6 +452,17 @@ class GuessNet:
                                        C.byref(loss), _stream(stream)), "fvx_net_train_step")
         return loss.value
 
+    def grads_tensor(self):
+        """The device gradient buffer (fvx_net_grads) as a float32 tensor view."""
+        torch = _torch()
+        ptr = lib().fvx_net_grads(self._h)
+        off = ptr - self._mem.data_ptr()
+        n = self.n_params()
+        return self._mem[off:off + 4 * n].view(torch.float32)
+
+    def apply_adam(self, lr=1e-3, stream=None):
+        check(lib().fvx_net_apply_adam(self._h, float(lr), _stream(stream)), "fvx_net_apply_adam")
+
     def prepare(self, op, B, Pprev=None, Xstar=None, inp=None, target=None, stream=None):
         """One sample's input (and target when Xstar is given) from solver vectors."""
         inp = self.samples(1, 2)[0] if inp is None else inp
@@ -469,7 +480,8 @@ class GuessNet:
         return X0
 
     def solve(self, op, B, Pprev=None, X=None, stream=None, allow_not_converged=False, **kw):
-        """fvx_poisson_solve_net: returns (X, stats dict with 'fallback')."""
+        """fvx_poisson_solve_net: returns (X, stats dict with 'source', the guess
+        used: GUESS_NET, GUESS_GIVEN (previous pressure) or GUESS_ZERO)."""
         opts = op.solve_opts(**kw)
         X = op.zeros() if X is None else X
         ws = op.workspace(opts)
@@ -479,7 +491,7 @@ class GuessNet:
                                          ws.numel(), C.byref(st), C.byref(fb), _stream(stream))
         check(rc, "fvx_poisson_solve_net", (0, 1) if allow_not_converged else (0,))
         d = st.as_dict()
-        d["fallback"] = int(fb.value)
+        d["source"] = int(fb.value)
         return X, d
 
     def __del__(self):

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfvx.so")
 F64, F32, MIXED = 0, 1, 2
 NONE, PERIODIC_Z = 0, 1
 NEUMANN, DIRICHLET = 0, 1
-GUESS_ZERO, GUESS_GIVEN = 0, 1
+GUESS_ZERO, GUESS_GIVEN, GUESS_NET = 0, 1, 2
 
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
@@ -111,6 +111,8 @@ SIGNATURES = {
     "fvx_net_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "fvx_net_gradients": (C.c_int, [_vp, C.c_int, _vp, _vp, _P(C.c_double), _vp]),
     "fvx_net_train_step": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_float, _P(C.c_double), _vp]),
+    "fvx_net_grads": (_vp, [_vp]),
+    "fvx_net_apply_adam": (C.c_int, [_vp, C.c_float, _vp]),
     "fvx_net_prepare": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fvx_net_guess": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fvx_poisson_solve_net": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _P(SolveOpts), _vp, C.c_size_t, _P(SolveStats),

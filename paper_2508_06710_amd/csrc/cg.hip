@@ -911,6 +911,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             const int nb = c.g.n_blocks, G = D.G;
             std::vector<double> gmean(G), gact(G);
             bool any = false;
+            double need = 0.5;  // inner reduction the outer target still needs
             by_v<double>(c.t.vec, [&](auto Vt) {
                 constexpr int V = decltype(Vt)::value;
                 launch_lap<double>(op, p.X, p.w.q, nullptr, s);
@@ -922,6 +923,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
                     p.h.rho_last[g] = t[g];
                     const bool act = p.h.bnorm2[g] > 0.0 && t[g] > o->rtol * o->rtol * p.h.bnorm2[g];
                     gact[g] = act ? 1.0 : 0.0;
+                    if (act) need = std::min(need, 0.5 * o->rtol * std::sqrt(p.h.bnorm2[g] / t[g]));
                     gmean[g] = op->singular ? t[G + g] / double(D.count) : 0.0;
                     any |= act;
                     if (!std::isfinite(t[g])) p.status = FVX_E_NONFINITE;
@@ -943,8 +945,11 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             });
             if (!p.outer_active) continue;
             const int budget = std::max(1, o->max_iter - p.total_inner);
+            // The inner tolerance is inner_rtol, loosened in a last correction
+            // to half of what separates the outer residual from its target.
+            const double inner_rtol = std::max(o->inner_rtol, need);
             jobs.push_back(CgJob<float>{op, p.w.inner, p.w.b32, p.w.x32, p.w.bp32, p.w.r32, p.w.p32a, p.w.p32b,
-                                        p.w.q32, false, o->inner_rtol, budget});
+                                        p.w.q32, false, inner_rtol, budget});
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;

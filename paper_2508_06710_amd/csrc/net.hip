@@ -1,6 +1,7 @@
 // Learned initial guess for the Poisson solve: a 4-layer 3x3x3 convolutional
 // network (2 -> 32 -> 32 -> 32 -> 1 channels, ReLU after the first three
-// layers, FP32 weights and accumulation) on the structured grid of a
+// layers, the input's previous-pressure channel added to the output, FP32
+// weights and accumulation) on the structured grid of a
 // Cartesian base (nx x ny cells, cell j*nx + i) extruded into nz planes.
 // Padding is periodic in x and z and replicates the edge cell in y (zero
 // gradient at the walls).
@@ -108,18 +109,21 @@ __device__ __forceinline__ Pos pos_of(const Grid &g, int pos) {
 }
 
 // out[n][co][cell] = bias[co] + sum_{ci,tap} W[co][ci][tap] in[n][ci][src(cell, tap)],
-// optionally through a ReLU.  Each thread computes all CO outputs of CPT
+// optionally through a ReLU, plus skip[n * skip_stride + cell] when skip is
+// given (the output layer adds the network input's previous-pressure
+// channel).  Each thread computes all CO outputs of CPT
 // cells spaced `per` apart; the weights of kChunk input channels at a time
 // are staged in LDS as [ci][tap][co] and read as wave-wide broadcasts.
 template <int CO, int CPT>
 __global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, const float *__restrict__ in,
                                                      const float *__restrict__ W, const float *__restrict__ bias,
-                                                     float *__restrict__ out, int relu) {
+                                                     float *__restrict__ out, int relu,
+                                                     const float *__restrict__ skip, int skip_stride) {
     __shared__ __align__(16) float w_s[kChunk * kTaps * CO];
     const int total = g.cells * ns;
     const int per = (total + CPT - 1) / CPT;
     const int gid = int(blockIdx.x) * blockDim.x + threadIdx.x;
-    int base[CPT], obase[CPT];
+    int base[CPT], obase[CPT], sidx[CPT];
     bool live[CPT];
     Taps t[CPT];
 #pragma unroll
@@ -130,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, con
         t[c] = fwd_taps(g, p.x, p.y, p.z);
         base[c] = p.n * CI * g.cells;
         obase[c] = p.n * CO * g.cells + p.cell;
+        sidx[c] = p.n * skip_stride + p.cell;
     }
     float acc[CPT][CO];
 #pragma unroll
@@ -164,7 +169,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, con
     for (int c = 0; c < CPT; ++c) {
         if (!live[c]) continue;
 #pragma unroll
-        for (int co = 0; co < CO; ++co) out[obase[c] + co * g.cells] = relu ? fmaxf(acc[c][co], 0.0f) : acc[c][co];
+        for (int co = 0; co < CO; ++co) {
+            float v = relu ? fmaxf(acc[c][co], 0.0f) : acc[c][co];
+            if (skip) v += skip[sidx[c]];
+            out[obase[c] + co * g.cells] = v;
+        }
     }
 }
 
@@ -433,10 +442,10 @@ Grid grid_of(const fvx_net *n) { return Grid{n->nx, n->ny, n->nz, n->cells}; }
 
 template <int CO, int CPT>
 void conv_fwd(const Grid &g, int ns, int CI, const float *in, const float *W, const float *b, float *out, int relu,
-              hipStream_t s) {
+              const float *skip, hipStream_t s) {
     const int64_t threads = ceil_div(int64_t(g.cells) * ns, CPT);
     hipLaunchKernelGGL((k_conv_fwd<CO, CPT>), dim3(unsigned(ceil_div(threads, kBlock))), dim3(kBlock), 0, s, g, ns,
-                       CI, in, W, b, out, relu);
+                       CI, in, W, b, out, relu, skip, 2 * g.cells);
 }
 
 void forward(fvx_net *net, int ns, const float *in, hipStream_t s) {
@@ -446,9 +455,9 @@ void forward(fvx_net *net, int ns, const float *in, hipStream_t s) {
         const float *W = net->params + layer_offset(l);
         const float *b = W + w_size(l);
         if (kCout[l] == kC)
-            conv_fwd<kC, 2>(g, ns, kCin[l], src, W, b, net->act[l + 1], 1, s);
+            conv_fwd<kC, 2>(g, ns, kCin[l], src, W, b, net->act[l + 1], 1, nullptr, s);
         else
-            conv_fwd<1, 4>(g, ns, kCin[l], src, W, b, net->act[l + 1], 0, s);
+            conv_fwd<1, 4>(g, ns, kCin[l], src, W, b, net->act[l + 1], 0, in + g.cells, s);
         src = net->act[l + 1];
     }
     FVX_HIP(hipGetLastError());
@@ -669,6 +678,15 @@ int fvx_net_gradients(fvx_net *n, int ns, const float *in, const float *target, 
     });
 }
 
+static void apply_adam(fvx_net *n, float lr, hipStream_t s) {
+    n->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = float(1.0 - std::pow(b1, n->step)), c2 = float(1.0 - std::pow(b2, n->step));
+    hipLaunchKernelGGL(N::k_adam, dim3(64), dim3(N::kBlock), 0, s, n->params, n->grads, n->m, n->v,
+                       int(N::n_params()), lr, float(b1), float(b2), 1e-8f, c1, c2);
+    FVX_HIP(hipGetLastError());
+}
+
 int fvx_net_train_step(fvx_net *n, int ns, const float *in, const float *target, float lr, double *loss,
                        void *stream) {
     return guard([&] {
@@ -678,13 +696,19 @@ int fvx_net_train_step(fvx_net *n, int ns, const float *in, const float *target,
         FVX_REQUIRE(lr > 0.0f && std::isfinite(lr), FVX_E_ARG, "lr must be positive");
         hipStream_t s = fvx::as_stream(stream);
         const double l = N::backward(n, ns, in, target, s);
-        n->step += 1;
-        const double b1 = 0.9, b2 = 0.999;
-        const float c1 = float(1.0 - std::pow(b1, n->step)), c2 = float(1.0 - std::pow(b2, n->step));
-        hipLaunchKernelGGL(N::k_adam, dim3(64), dim3(N::kBlock), 0, s, n->params, n->grads, n->m, n->v,
-                           int(N::n_params()), lr, float(b1), float(b2), 1e-8f, c1, c2);
-        FVX_HIP(hipGetLastError());
+        apply_adam(n, lr, s);
         if (loss) *loss = l;
+        return FVX_OK;
+    });
+}
+
+float *fvx_net_grads(fvx_net *n) { return n ? n->grads : nullptr; }
+
+int fvx_net_apply_adam(fvx_net *n, float lr, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        FVX_REQUIRE(lr > 0.0f && std::isfinite(lr), FVX_E_ARG, "lr must be positive");
+        apply_adam(n, lr, fvx::as_stream(stream));
         return FVX_OK;
     });
 }
@@ -720,7 +744,7 @@ int fvx_net_guess(fvx_net *n, const fvx_op *op, const double *B, const double *P
 
 int fvx_poisson_solve_net(const fvx_op *op, fvx_net *n, const double *B, const double *Pprev, double *X,
                           const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
-                          int *fallback, void *stream) {
+                          int *source, void *stream) {
     const auto t0 = std::chrono::steady_clock::now();
     fvx_solve_opts o{};
     const int rc = guard([&]() -> int {
@@ -734,10 +758,26 @@ int fvx_poisson_solve_net(const fvx_op *op, fvx_net *n, const double *B, const d
         FVX_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, FVX_E_ARG, "ws must be 256-byte aligned");
         hipStream_t s = fvx::as_stream(stream);
         N::guess(n, op, B, Pprev, X, s);
-        const double ratio = fvx::guess_residual_ratio(op, B, X, ws, s);
+        // Candidates judged by their residual: the network's guess, the
+        // previous pressure, and zero (ratio 1).
+        double best = fvx::guess_residual_ratio(op, B, X, ws, s);
+        int src = FVX_GUESS_NET;
+        if (!(best < 1.0)) {
+            best = 1.0;
+            src = FVX_GUESS_ZERO;
+        }
+        if (Pprev) {
+            const double rp = fvx::guess_residual_ratio(op, B, Pprev, ws, s);
+            if (rp < best) {
+                best = rp;
+                src = FVX_GUESS_GIVEN;
+                FVX_HIP(hipMemcpyAsync(X, Pprev, sizeof(double) * size_t(op->n_b) * op->ld, hipMemcpyDeviceToDevice,
+                                       s));
+            }
+        }
         o = *opts;
-        o.guess = ratio < 1.0 ? FVX_GUESS_GIVEN : FVX_GUESS_ZERO;
-        if (fallback) *fallback = o.guess == FVX_GUESS_ZERO;
+        o.guess = src == FVX_GUESS_ZERO ? FVX_GUESS_ZERO : FVX_GUESS_GIVEN;
+        if (source) *source = src;
         return FVX_OK;
     });
     if (rc != FVX_OK) return rc;

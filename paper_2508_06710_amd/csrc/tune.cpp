@@ -1,7 +1,8 @@
 // Autotuner for the SpMM launch tile: times candidate tiles of the Laplacian
 // SpMM on the device (HIP events around a sweep over rotating input/output
-// pairs) and keeps the fastest.  All candidates compute the same product; the
-// choice only affects speed.
+// pairs) and keeps the fastest, in two stages: the row mapping first, then
+// the launch options around it.  All candidates compute the same product;
+// the choice only affects speed.
 #include <algorithm>
 #include <cmath>
 
@@ -10,7 +11,9 @@
 namespace fvx {
 namespace {
 
-std::vector<fvx_tile> candidates(const fvx_op *op, int dtype) {
+// Stage 1: the row mapping (vector width, lanes per row, block size) with
+// the launch options at their defaults.
+std::vector<fvx_tile> shape_candidates(const fvx_op *op, int dtype) {
     std::vector<fvx_tile> out;
     const int vmax = dtype == FVX_F32 ? 4 : 2;
     for (int vec = vmax; vec >= 1; vec >>= 1) {
@@ -19,17 +22,25 @@ std::vector<fvx_tile> candidates(const fvx_op *op, int dtype) {
         for (int lpr = base; lpr >= 1 && lpr >= base / 4; lpr >>= 1)
             for (int block : {64, 128, 256, 512}) {
                 if (block < lpr) continue;
-                for (int cap : {0, 2048})
-                    for (int remap : {1, 0})
-                        for (int stage : {0, 1}) {
-                            if (stage && block / lpr > kMaxStageRows) continue;
-                            for (int nt : {0, 1}) {
-                                fvx_tile t{vec, lpr, block, remap, cap, stage, nt};
-                                out.push_back(t);
-                            }
-                        }
+                out.push_back(fvx_tile{vec, lpr, block, 1, 0, 0, 0});
             }
     }
+    return out;
+}
+
+// Stage 2: the launch options (grid cap, XCD remap, LDS staging of the row
+// metadata, non-temporal stores) around the best row mapping.
+std::vector<fvx_tile> option_candidates(const fvx_tile &b) {
+    std::vector<fvx_tile> out;
+    for (int cap : {0, 2048})
+        for (int remap : {1, 0})
+            for (int stage : {0, 1}) {
+                if (stage && b.block / b.lanes_per_row > kMaxStageRows) continue;
+                for (int nt : {0, 1}) {
+                    if (cap == 0 && remap == 1 && stage == 0 && nt == 0) continue;  // timed in stage 1
+                    out.push_back(fvx_tile{b.vec, b.lanes_per_row, b.block, remap, cap, stage, nt});
+                }
+            }
     return out;
 }
 
@@ -63,7 +74,9 @@ extern "C" int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_byt
         const size_t nv = size_t(op->n_b) * op->ld;
         const size_t pair_bytes = 2 * nv * es;
         FVX_REQUIRE(scratch_bytes >= pair_bytes, FVX_E_NOMEM, "scratch holds no input/output pair");
-        const int pairs = int(std::min<size_t>(scratch_bytes / pair_bytes, 4096));
+        // Enough pairs that a sweep streams from HBM for large operators; a
+        // few hundred launches for small ones (whose data stay in cache in use).
+        const int pairs = int(std::min<size_t>(scratch_bytes / pair_bytes, 512));
         reps = std::max(1, reps);
         hipStream_t s = fvx::as_stream(stream);
         // Inputs: zero-filled scratch is a valid, finite multivector.
@@ -75,8 +88,8 @@ extern "C" int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_byt
         fvx_tile best = keep;
         double best_us = 1e30;
         int n = 0;
-        try {
-            for (const fvx_tile &t : fvx::candidates(op, dtype)) {
+        auto try_all = [&](const std::vector<fvx_tile> &cands) {
+            for (const fvx_tile &t : cands) {
                 const double us = dtype == FVX_F64
                                       ? fvx::time_tile<double>(op, dtype, t, static_cast<double *>(scratch), pairs, nv,
                                                                reps, s, e0, e1)
@@ -89,6 +102,10 @@ extern "C" int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_byt
                     best = t;
                 }
             }
+        };
+        try {
+            try_all(fvx::shape_candidates(op, dtype));
+            try_all(fvx::option_candidates(best));
         } catch (...) {
             op->tile[dtype] = keep;
             hipEventDestroy(e0);

@@ -111,6 +111,25 @@ def test_every_tile_gives_the_same_product(k):
         c.op.set_tile(2, 1, 256, 1, 0, 1, dtype=fvx.F64)  # 256 rows per tile do not fit the stage
 
 
+@pytest.mark.parametrize("k,dtype", [(16, 0), (5, 1), (64, 1)])
+def test_tuner_keeps_the_fastest_candidate(k, dtype):
+    """The autotuner's two stages: every row mapping with default options,
+    then the options around the stage-1 winner; the op keeps the fastest
+    candidate, and the tuned product is the oracle's (tiles only change speed)."""
+    c = Case(inputs.channel_base(40, 24), k)
+    fvx = c.fvx
+    res = c.op.tune(dtype, scratch_bytes=32 << 20, reps=1)
+    tiles = [t for t, _ in res]
+    assert len(set(tiles)) == len(tiles)
+    stage1 = [t for t in tiles if t[3:] == (1, 0, 0, 0)]
+    first = min(((us, t) for t, us in res if t in stage1))[1]
+    assert all(t[:3] == first[:3] for t in tiles[len(stage1):])
+    assert c.op.get_tile(dtype) == min(res, key=lambda r: r[1])[0]
+    y, ref, A, x = _lap_check(c, seed=7, dtype=dtype)
+    tol = TOL64 if dtype == fvx.F64 else float(np.max(fp32_bound_factor(A)))
+    assert componentwise(y, ref, A, x) <= tol
+
+
 @pytest.mark.parametrize("base", list(BASES))
 @pytest.mark.parametrize("k", [1, 3, 8, 64])
 def test_lap_f32_within_rounding_bound(base, k):

@@ -29,7 +29,7 @@ def _torch_net(params, inp):
         x = F.conv3d(_torch_pad(x), W, b)
         if relu:
             x = torch.relu(x)
-    return x
+    return x + inp[:, 1:2]
 
 
 def _torch_params(flat):
@@ -38,7 +38,7 @@ def _torch_params(flat):
 
 
 def _params(scale_bias=0.1):
-    p = inputs.net_init(6).astype(np.float64)
+    p = inputs.net_init(6, zero_output_layer=False).astype(np.float64)
     # nonzero biases so that the bias paths are exercised
     o = 0
     for ci, co, _ in onet.LAYERS:
@@ -173,3 +173,10 @@ def test_prepare_and_guess_scaling():
 def test_n_params_matches_layer_shapes():
     assert onet.n_params() == 2 * 32 * 27 + 32 + 2 * (32 * 32 * 27 + 32) + 32 * 27 + 1
     assert inputs.net_init(6).size == onet.n_params()
+
+
+def test_untrained_network_returns_the_previous_pressure():
+    # zero output layer: out = input channel 1 exactly
+    inp = _rand((2, 2, 3, 4, 5), 30)
+    out = onet.forward(inputs.net_init(6).astype(np.float64), inp)[-1]
+    assert np.array_equal(out[:, 0], inp[:, 1])
