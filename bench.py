@@ -153,6 +153,29 @@ def counters_mode(fvx, inputs, torch):
     log(f"counters run done: lap bytes/launch {spmm_bytes(op.nnz_b, op.n_b, op.k)}, copy bytes {nbytes}")
 
 
+def net_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 kernel traces of the learned-guess kernels on
+    the 64 x 64 x 8 channel: 10 inferences (one sample) and 5 training steps
+    (16 samples)."""
+    cfg = inputs.SMALL_CHANNEL
+    spec, k, dz = cfg["base"], cfg["k"], cfg["dz"]
+    mesh = fvx.Mesh.from_spec(spec)
+    op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=False)
+    net = fvx.GuessNet(spec.nx, spec.ny, k, batch=16, params=inputs.net_init(6, zero_output_layer=False))
+    b = op.to_rows(inputs.rhs_uniform(1, op.n_b * k))
+    X0 = op.zeros()
+    for _ in range(10):
+        net.guess(op, b, b, X0)
+    x = torch.as_tensor(inputs.uniform(2, 0, 16 * 2 * op.n_b * k).astype("float32")).cuda()
+    t = torch.as_tensor(inputs.uniform(2, 1, 16 * op.n_b * k).astype("float32")).cuda()
+    x = x.view(16, 2, k, spec.ny, spec.nx)
+    t = t.view(16, 1, k, spec.ny, spec.nx)
+    for _ in range(5):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    log("net profile run done")
+
+
 def cpu_baseline(inputs, oracle, b_plane, k, rtol):
     """The oracle as it stands, on the host cores: its assembled-3D CSR SpMV
     (timed repeatedly) and its textbook CG to rtol on the same right-hand side."""
@@ -214,6 +237,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--counters", action="store_true")
+    ap.add_argument("--profile-net", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-airfoil", action="store_true")
     ap.add_argument("--no-guess", action="store_true")
@@ -235,6 +259,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_mode(fvx, inputs, torch)
+        return
+    if args.profile_net:
+        net_profile_mode(fvx, inputs, torch)
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
@@ -424,6 +451,7 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
         log(f"k={k}: spmm {rec['spmm_us']:.2f} us ({rec['spmm_GBs']:.0f} GB/s), csr3d {rec['csr3d_us']:.2f} us, "
             f"P_k {rec['P_k']}")
     res["k_sweep"] = sweep
+    res["large_sweep"] = large_sweep(fvx, inputs, torch, np)
 
     # Plain FP64 SpMV-CG on the assembled matrix, same right-hand side.
     ptr, col, val = fvx.expand_csr(mesh, op.k, op.dz, fvx.PERIODIC_Z)
@@ -445,6 +473,48 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
                        "relres_true": stm["relres_true"]}
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
+
+
+def large_sweep(fvx, inputs, torch, np):
+    """Lap SpMM bandwidth on the convection-shaped 160 x 320 base at larger
+    plane counts (FP64 and FP32, tuned tiles), beside a streaming copy of the
+    same bytes per launch: how close the SpMM gets to the roofline once a
+    launch moves hundreds of MB."""
+    spec = inputs.convection_base(160, 320)
+    mesh = fvx.Mesh.from_spec(spec)
+    out = []
+    for k in (16, 64, 256):
+        op = fvx.Operator(mesh, k, math.pi / k, fvx.PERIODIC_Z, with_f32=True)
+        for dt, name, v in ((fvx.F64, "f64", 8), (fvx.F32, "f32", 4)):
+            tile = tune(op, fvx, dt)
+            x = op.to_rows(inputs.uniform(0, 0, op.n_b * k), dtype=dt)
+            per = 2 * op.n_b * op.ld * v
+            R = max(3, math.ceil(COLD_BYTES / per))
+            X = [x.clone() for _ in range(R)]
+            Y = [torch.empty_like(x) for _ in range(R)]
+            lap_sweep(op, X[:2], Y[:2], torch)
+            t = lap_sweep(op, X, Y, torch, reps=2)
+            Bk = spmm_bytes(op.nnz_b, op.n_b, k, v)
+            nbytes = op.n_b * op.ld * v
+            fvx.copy(Y[0], X[0], nbytes)
+            tc = Timer(torch)
+            with tc:
+                for _ in range(2):
+                    for xx, yy in zip(X, Y):
+                        fvx.copy(yy, xx, nbytes)
+            t_copy = tc.ms() / (2 * R)
+            rec = {"k": k, "dtype": name, "tile": list(tile), "cells": op.n_b * k, "bytes_per_launch": Bk,
+                   "spmm_us": t * 1e3, "spmm_GBs": Bk / (t * 1e-3) / 1e9,
+                   "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "copy_GBs_same_size": 2 * nbytes / (t_copy * 1e-3) / 1e9,
+                   "frac_of_copy": (Bk / t) / (2 * nbytes / t_copy)}
+            out.append(rec)
+            log(f"large k={k} {name}: {rec['spmm_GBs']:.0f} GB/s ({100 * rec['frac_hbm']:.0f}% of 8 TB/s), "
+                f"copy {rec['copy_GBs_same_size']:.0f} GB/s")
+            del X, Y, x
+        del op
+        torch.cuda.empty_cache()
+    return out
 
 
 def batch_leg(fvx, inputs, torch, np, rtol):

@@ -108,6 +108,35 @@ def forward(params, inp: np.ndarray):
     return acts
 
 
+def forward_at(params, inp: np.ndarray, n: int, z: int, y: int, x: int) -> float:
+    """Output of the network at one cell of sample n, evaluated from that
+    cell's receptive field alone, cell by cell: the value read at tap offset
+    (dz, dy, dx) of cell (z, y, x) is the cell ((z + dz - 1) mod Z,
+    clamp(y + dy - 1), (x + dx - 1) mod X).  For sampled checks of large
+    grids."""
+    layers = unpack(params)
+    a = np.asarray(inp, dtype=np.float64)
+    Z, Y, X = a.shape[2:]
+
+    def src(c, dz, dy, dx):
+        return ((c[0] + dz - 1) % Z, min(max(c[1] + dy - 1, 0), Y - 1), (c[2] + dx - 1) % X)
+
+    taps = [(dz, dy, dx) for dz in range(3) for dy in range(3) for dx in range(3)]
+    need = [{(z, y, x)}]
+    for _ in range(len(layers)):
+        need.append({src(c, *t) for c in need[-1] for t in taps})
+    vals = {c: a[n, :, c[0], c[1], c[2]] for c in need[-1]}
+    for li, ((W, b), (_, _, relu)) in enumerate(zip(layers, LAYERS)):
+        new = {}
+        for c in need[len(layers) - 1 - li]:
+            acc = b.copy()
+            for t in taps:
+                acc = acc + W[:, :, t[0], t[1], t[2]] @ vals[src(c, *t)]
+            new[c] = np.maximum(acc, 0.0) if relu else acc
+        vals = new
+    return float(vals[(z, y, x)][0] + a[n, 1, z, y, x])
+
+
 def loss_and_grads(params, inp: np.ndarray, target: np.ndarray):
     """(loss, flat gradient) of mean((out - target)^2)."""
     layers = unpack(params)

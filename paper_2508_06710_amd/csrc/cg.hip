@@ -224,13 +224,6 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, vb.nblk, lds);
 }
 
-template <typename T, int V, bool Z, int WT>
-__global__ __launch_bounds__(kMaxCgBlock) void k_cg_a(RowArgs<T> a, CgDev d, int it, Src rr, Src bb,
-                                                      const T *__restrict__ r, const T *__restrict__ p_old,
-                                                      T *__restrict__ p_new, T *__restrict__ q) {
-    b_cg_a<T, V, Z, WT>(a, d, vb_single(a.remap), it, rr, bb, r, p_old, p_new, q);
-}
-
 // B: alpha from the p.q partials; x += alpha p; r += alpha q; partial r.r.
 template <typename T, int V>
 __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
@@ -285,12 +278,6 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
 }
 
-template <typename T, int V>
-__global__ __launch_bounds__(kMaxCgBlock) void k_cg_b(RowArgs<T> a, CgDev d, int it, Src pq, T *__restrict__ x,
-                                                      T *__restrict__ r, const T *__restrict__ p,
-                                                      const T *__restrict__ q) {
-    b_cg_b<T, V>(a, d, vb_single(a.remap), it, pq, x, r, p, q);
-}
 
 // End: x -= mean(x) (singular L; mean from partials), x = 0 where b vanished.
 template <typename T, int V>

@@ -177,6 +177,82 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, con
     }
 }
 
+typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
+
+// The 32-output-channel layers as an implicit GEMM on the matrix cores
+// (v_mfma_f32_32x32x2_f32, FP32 in and out):
+//   D[co][cell] = bias[co] + sum_{tap, ci} W[co][ci][tap] in[ci][src(cell, tap)]
+// with M = 32 output channels, N = 32 cells per MFMA column block (NB blocks
+// per wave) and K = 27 * CI taken two input channels at a time.  Operand
+// layouts of the 32x32x2 instruction: lane l supplies A[l % 32][l / 32] and
+// B[l / 32][l % 32]; accumulator register r of lane l is
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  The weights of one z-offset of
+// the stencil (9 taps) at a time are staged in LDS as [tap][ci][co], so the
+// A operand is a conflict-free LDS read; B is a gather of 32 consecutive
+// cells per channel.  ReLU on output.
+template <int CI, int NB>
+__global__ __launch_bounds__(kBlock) void k_conv_fwd_mfma(Grid g, int ns, const float *__restrict__ in,
+                                                          const float *__restrict__ W,
+                                                          const float *__restrict__ bias, float *__restrict__ out) {
+    constexpr int CO = kC;
+    __shared__ __align__(16) float w_s[9 * CI * CO];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 31, hi = lane >> 5;
+    const int total = g.cells * ns;
+    const int first = (int(blockIdx.x) * (kBlock / 64) + wave) * (32 * NB);
+    int base[NB], cell[NB], nn[NB];
+    bool live[NB];
+    Taps t[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int pos = first + 32 * b + lo;
+        live[b] = pos < total;
+        const Pos p = pos_of(g, live[b] ? pos : 0);
+        t[b] = fwd_taps(g, p.x, p.y, p.z);
+        base[b] = p.n * CI * g.cells + hi * g.cells;
+        cell[b] = p.cell;
+        nn[b] = p.n;
+    }
+    mfma_acc16 acc[NB];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float bv = bias[8 * (r / 4) + 4 * hi + (r % 4)];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b][r] = bv;
+    }
+    for (int dz = 0; dz < 3; ++dz) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 9 * CI * CO; i += blockDim.x) {
+            const int co = i % CO, rest = i / CO, ci = rest % CI, tl = rest / CI;
+            w_s[i] = W[(co * CI + ci) * kTaps + dz * 9 + tl];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tl = 0; tl < 9; ++tl) {
+            const int dy = tl / 3, dx = tl % 3;
+            int off[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) off[b] = base[b] + t[b].z[dz] + t[b].y[dy] + t[b].x[dx];
+#pragma unroll
+            for (int c = 0; c < CI; c += 2) {
+                const float a = w_s[(tl * CI + c + hi) * CO + lo];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float bx = in[off[b] + c * g.cells];
+                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bx, acc[b], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!live[b]) continue;
+        float *o = out + nn[b] * CO * g.cells + cell[b];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[(8 * (r / 4) + 4 * hi + (r % 4)) * g.cells] = fmaxf(acc[b][r], 0.0f);
+    }
+}
+
 // Gradient with respect to a 32-channel layer input:
 // din[n][ci][p] = sum_{co,tap} W[co][ci][tap] sum_{o reads p at tap} dout[n][co][o],
 // multiplied by the ReLU derivative (act_in > 0) of the layer that produced
@@ -244,6 +320,82 @@ __global__ __launch_bounds__(kBlock) void k_conv_bwd_data(Grid g, int ns, int CO
         for (int ci = 0; ci < CI; ++ci) {
             const int o = ibase[c] + ci * g.cells;
             din[o] = act_in[o] > 0.0f ? acc[c][ci] : 0.0f;
+        }
+    }
+}
+
+// The same gradient for a 32-channel output gradient on the matrix cores:
+//   D[ci][p] = sum_{tap, co} W[co][ci][tap] adj(dout[co])(p, tap)
+// M = 32 input channels, N = 32 positions per column block, K = 27 * 32 two
+// output channels at a time; operand and accumulator layouts as in
+// k_conv_fwd_mfma, weights staged per z-offset as [tap][co][ci].
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_conv_bwd_data_mfma(Grid g, int ns, const float *__restrict__ dout,
+                                                               const float *__restrict__ W,
+                                                               const float *__restrict__ act_in,
+                                                               float *__restrict__ din) {
+    constexpr int CI = kC, CO = kC;
+    __shared__ __align__(16) float w_s[9 * CO * CI];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 31, hi = lane >> 5;
+    const int total = g.cells * ns;
+    const int first = (int(blockIdx.x) * (kBlock / 64) + wave) * (32 * NB);
+    int dbase[NB], ibase[NB];
+    bool live[NB];
+    AdjTaps t[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int pos = first + 32 * b + lo;
+        live[b] = pos < total;
+        const Pos p = pos_of(g, live[b] ? pos : 0);
+        t[b] = adj_taps(g, p.x, p.y, p.z);
+        dbase[b] = p.n * CO * g.cells + hi * g.cells;
+        ibase[b] = p.n * CI * g.cells + p.cell;
+    }
+    mfma_acc16 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
+    for (int dz = 0; dz < 3; ++dz) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 9 * CO * CI; i += blockDim.x) {
+            const int ci = i % CI, rest = i / CI, co = rest % CO, tl = rest / CO;
+            w_s[i] = W[(co * CI + ci) * kTaps + dz * 9 + tl];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tl = 0; tl < 9; ++tl) {
+            const int dy = tl / 3, dx = tl % 3;
+            const float *d[NB];
+            int ya[NB], yb[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                d[b] = dout + dbase[b] + t[b].z[dz] + t[b].x[dx];
+                ya[b] = t[b].ya[dy];
+                yb[b] = t[b].yb[dy];
+            }
+#pragma unroll
+            for (int c = 0; c < CO; c += 2) {
+                const float a = w_s[(tl * CO + c + hi) * CI + lo];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    // both reads in bounds (offset 0 stands in for a missing row), selected without a branch
+                    const float *dc = d[b] + c * g.cells;
+                    const float va = dc[max(ya[b], 0)], vb = dc[max(yb[b], 0)];
+                    const float bx = (ya[b] >= 0 ? va : 0.0f) + (yb[b] >= 0 ? vb : 0.0f);
+                    acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bx, acc[b], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (!live[b]) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = ibase[b] + (8 * (r / 4) + 4 * hi + (r % 4)) * g.cells;
+            din[o] = act_in[o] > 0.0f ? acc[b][r] : 0.0f;
         }
     }
 }
@@ -448,16 +600,36 @@ void conv_fwd(const Grid &g, int ns, int CI, const float *in, const float *W, co
                        CI, in, W, b, out, relu, skip, 2 * g.cells);
 }
 
+// 32-output-channel layer on the matrix cores: one wave per 32 * NB cells,
+// four waves per workgroup; two column blocks per wave once there are
+// enough cells for every CU to hold several workgroups.
+template <int CI>
+void conv_fwd_mfma(const Grid &g, int ns, const float *in, const float *W, const float *b, float *out,
+                   hipStream_t s) {
+    const int64_t total = int64_t(g.cells) * ns;
+    if (total >= int64_t(2048) * 256) {
+        const unsigned blocks = unsigned(ceil_div(total, (kBlock / 64) * 64));
+        hipLaunchKernelGGL((k_conv_fwd_mfma<CI, 2>), dim3(blocks), dim3(kBlock), 0, s, g, ns, in, W, b, out);
+    } else {
+        const unsigned blocks = unsigned(ceil_div(total, (kBlock / 64) * 32));
+        hipLaunchKernelGGL((k_conv_fwd_mfma<CI, 1>), dim3(blocks), dim3(kBlock), 0, s, g, ns, in, W, b, out);
+    }
+}
+
 void forward(fvx_net *net, int ns, const float *in, hipStream_t s) {
     const Grid g = grid_of(net);
     const float *src = in;
     for (int l = 0; l < kLayers; ++l) {
         const float *W = net->params + layer_offset(l);
         const float *b = W + w_size(l);
-        if (kCout[l] == kC)
-            conv_fwd<kC, 2>(g, ns, kCin[l], src, W, b, net->act[l + 1], 1, nullptr, s);
-        else
+        if (kCout[l] == kC) {
+            if (kCin[l] == 2)
+                conv_fwd_mfma<2>(g, ns, src, W, b, net->act[l + 1], s);
+            else
+                conv_fwd_mfma<kC>(g, ns, src, W, b, net->act[l + 1], s);
+        } else {
             conv_fwd<1, 4>(g, ns, kCin[l], src, W, b, net->act[l + 1], 0, in + g.cells, s);
+        }
         src = net->act[l + 1];
     }
     FVX_HIP(hipGetLastError());
@@ -487,8 +659,14 @@ double backward(fvx_net *n, int ns, const float *in, const float *target, hipStr
             hipLaunchKernelGGL((k_conv_bwd_w<1>), wgrid, dim3(kBlock), 0, s, g, ns, CI, dcur, lin, per, n->part);
         hipLaunchKernelGGL(k_fold_w, dim3(64), dim3(kBlock), 0, s, n->part, nblk, CI, CO, gw, gb);
         if (l > 0) {
-            hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(unsigned(ceil_div(threads2, kBlock))), dim3(kBlock), 0, s,
-                               g, ns, CO, dcur, W, n->act[l], dnext);
+            if (CO == kC) {
+                // one column block per wave: two would keep too many gathers in registers
+                hipLaunchKernelGGL((k_conv_bwd_data_mfma<1>), dim3(unsigned(ceil_div(nout, 128))), dim3(kBlock), 0, s,
+                                   g, ns, dcur, W, n->act[l], dnext);
+            } else {
+                hipLaunchKernelGGL((k_conv_bwd_data<2>), dim3(unsigned(ceil_div(threads2, kBlock))), dim3(kBlock), 0,
+                                   s, g, ns, CO, dcur, W, n->act[l], dnext);
+            }
             std::swap(dcur, dnext);
         }
         FVX_HIP(hipGetLastError());

@@ -82,6 +82,29 @@ def test_forward_matches_oracle(nx, ny, nz, ns):
         assert _rel(out[n], ref[n]) <= FWD_TOL, n
 
 
+def test_forward_full_size_batch_sampled():
+    """The training batch of the 64 x 64 x 8 channel (16 samples, two MFMA
+    column blocks per wave): outputs at sampled cells against the oracle's
+    receptive-field evaluation."""
+    nx, ny, nz, ns = 64, 64, 8, 16
+    p = _params()
+    x = _samples(ns, nz, ny, nx, 12)
+    net = _net(nx, ny, nz, ns, p)
+    out = net.forward(_dev(x)).cpu().numpy()
+    pick = inputs.u64(13, 0, 4 * 24).reshape(24, 4)
+    got, ref = [], []
+    for n_, z, y, xx in pick:
+        n_, z, y, xx = int(n_ % ns), int(z % nz), int(y % ny), int(xx % nx)
+        got.append(out[n_, 0, z, y, xx])
+        ref.append(onet.forward_at(p.astype(np.float64), x.astype(np.float64), n_, z, y, xx))
+    got, ref = np.array(got, np.float64), np.array(ref)
+    # edges of the grid are always sampled too
+    for n_, z, y, xx in ((0, 0, 0, 0), (ns - 1, nz - 1, ny - 1, nx - 1), (3, 0, ny - 1, 0)):
+        got = np.append(got, out[n_, 0, z, y, xx])
+        ref = np.append(ref, onet.forward_at(p.astype(np.float64), x.astype(np.float64), n_, z, y, xx))
+    assert np.max(np.abs(got - ref)) <= FWD_TOL * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("nx,ny,nz,ns", GRIDS[:4])
 def test_gradients_match_oracle(nx, ny, nz, ns):
     p = _params()

@@ -180,3 +180,16 @@ def test_untrained_network_returns_the_previous_pressure():
     inp = _rand((2, 2, 3, 4, 5), 30)
     out = onet.forward(inputs.net_init(6).astype(np.float64), inp)[-1]
     assert np.array_equal(out[:, 0], inp[:, 1])
+
+
+@pytest.mark.parametrize("shape", [(3, 5, 6), (1, 2, 3)])
+def test_forward_at_one_cell_equals_whole_grid_forward(shape):
+    p = _params()
+    inp = _rand((2,) + (2,) + shape, 31)
+    full = onet.forward(p, inp)[-1]
+    Z, Y, X = shape
+    for n in range(2):
+        for z in range(Z):
+            for y in range(Y):
+                for x in range(X):
+                    assert abs(onet.forward_at(p, inp, n, z, y, x) - full[n, 0, z, y, x]) <= 1e-12
