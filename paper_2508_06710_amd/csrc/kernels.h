@@ -14,10 +14,14 @@ __device__ __forceinline__ vec_t<T, V> ldv(const T *p) {
     return *reinterpret_cast<const vec_t<T, V> *>(p);
 }
 
-template <typename T, int V>
-__device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid, bool nt = false) {
+// Store of the first `valid` of V values; NT marks full-vector stores
+// non-temporal (the output is not read again by this kernel).  NT is a
+// compile-time choice: a run-time flag lets the compiler merge the two stores
+// and drop the hint.
+template <typename T, int V, bool NT = false>
+__device__ __forceinline__ void stv_masked(T *p, const vec_t<T, V> &v, int valid) {
     if (valid >= V) {
-        if (nt)
+        if constexpr (NT)
             __builtin_nontemporal_store(v, reinterpret_cast<vec_t<T, V> *>(p));
         else
             *reinterpret_cast<vec_t<T, V> *>(p) = v;
@@ -60,6 +64,27 @@ __device__ __forceinline__ PlaneNeighbours<T, V> plane_neighbours(const vec_t<T,
     n.rightV = __shfl(xo[0], src_r, lpr);
     n.left0 = __shfl(prov_l, src_l, lpr);
     return n;
+}
+
+// The same two values when the row group covers the k columns in several
+// passes (lanes_per_row * V < k): from the neighbouring lanes of this pass,
+// and from memory for the lanes at the edges of the pass.  Lanes past column
+// k in the last pass are inactive; no active lane uses their values.
+template <typename T, int V, class Ld>
+__device__ __forceinline__ PlaneNeighbours<T, V> plane_neighbours_pass(const vec_t<T, V> &xo, const Ld &in,
+                                                                       int64_t row, int c0, int sub, int lpr, int k) {
+    const T l = __shfl(xo[V - 1], sub == 0 ? lpr - 1 : sub - 1, lpr);
+    const T r = __shfl(xo[0], sub == lpr - 1 ? 0 : sub + 1, lpr);
+    PlaneNeighbours<T, V> n;
+    n.left0 = sub == 0 ? in.scalar(row, c0 == 0 ? k - 1 : c0 - 1) : l;
+    n.rightV = (sub == lpr - 1 || c0 + V >= k) ? in.scalar(row, c0 + V >= k ? 0 : c0 + V) : r;
+    return n;
+}
+
+template <typename T, int V, class Ld>
+__device__ __forceinline__ PlaneNeighbours<T, V> neighbours_of(const vec_t<T, V> &xo, const Ld &in, int64_t row,
+                                                               int c0, int sub, int lpr, int k, bool single) {
+    return single ? plane_neighbours<T, V>(xo, sub, lpr, k) : plane_neighbours_pass<T, V>(xo, in, row, c0, sub, lpr, k);
 }
 
 // Column l-1 (mod k) and l+1 (mod k) of element t of this lane.
@@ -186,19 +211,11 @@ __device__ __forceinline__ vec_t<T, V> lap_row_meta(const RowMeta<T, WT> &m, con
 #pragma unroll
     for (int e = 0; e < WT; ++e) acc += m.val[e] * xj[e];
     if constexpr (Z) {
-        if (single) {
-            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, k);
+        const auto nb = neighbours_of<T, V>(xo, in, row, c0, sub, lpr, k, single);
 #pragma unroll
-            for (int t = 0; t < V; ++t) {
-                const int l = c0 + t;
-                acc[t] += m.w * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < V; ++t) {
-                const int l = c0 + t;
-                if (l < k) acc[t] += m.w * (in.scalar(row, l == 0 ? k - 1 : l - 1) + in.scalar(row, l == k - 1 ? 0 : l + 1));
-            }
+        for (int t = 0; t < V; ++t) {
+            const int l = c0 + t;
+            acc[t] += m.w * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
         }
     }
     return acc;
@@ -219,19 +236,11 @@ __device__ __forceinline__ vec_t<T, V> lap_row_dyn(const OpDev<T> &A, const Ld &
     }
     if constexpr (Z) {
         const T wr = A.w[row];
-        if (single) {
-            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, k);
+        const auto nb = neighbours_of<T, V>(xo, in, row, c0, sub, lpr, k, single);
 #pragma unroll
-            for (int t = 0; t < V; ++t) {
-                const int l = c0 + t;
-                acc[t] += wr * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < V; ++t) {
-                const int l = c0 + t;
-                if (l < k) acc[t] += wr * (in.scalar(row, l == 0 ? k - 1 : l - 1) + in.scalar(row, l == k - 1 ? 0 : l + 1));
-            }
+        for (int t = 0; t < V; ++t) {
+            const int l = c0 + t;
+            acc[t] += wr * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
         }
     }
     return acc;

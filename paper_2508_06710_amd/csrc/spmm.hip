@@ -16,7 +16,7 @@ namespace {
 // Y = (I_k (x) A_b + C) X, optionally scaled per column.  With S, each tile's
 // base-block rows are first staged in LDS by the whole workgroup (coalesced
 // loads) and every lane of a row reads them from there.
-template <typename T, int V, bool Z, int WT, bool S>
+template <typename T, int V, bool Z, int WT, bool S, bool NT>
 __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                               const double *__restrict__ cs) {
     extern __shared__ __align__(16) char smem[];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict_
                 for (int q = 0; q < V; ++q)
                     if (c0 + q < a.k) acc[q] *= T(cs[c0 + q]);
             }
-            stv_masked<T, V>(Y + row * a.ld + c0, acc, a.k - c0, a.nt != 0);
+            stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
         }
     }
 }
@@ -91,18 +91,9 @@ __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict_
             if constexpr (Z) {
                 const T ar = a.A.area[row];
                 const vec_t<T, V> wo = ldv<T, V>(Wz + row * a.ld + c0);
-                if (single) {
-                    const auto nb = plane_neighbours<T, V>(wo, sub, lpr, a.k);
+                const auto nb = neighbours_of<T, V>(wo, PlainLoad<T, V>{Wz, a.ld}, row, c0, sub, lpr, a.k, single);
 #pragma unroll
-                    for (int q = 0; q < V; ++q) acc[q] += ar * (wo[q] - left_of<T, V>(wo, nb, q));
-                } else {
-                    const T *wr = Wz + row * a.ld;
-#pragma unroll
-                    for (int q = 0; q < V; ++q) {
-                        const int l = c0 + q;
-                        if (l < a.k) acc[q] += ar * (wo[q] - wr[l == 0 ? a.k - 1 : l - 1]);
-                    }
-                }
+                for (int q = 0; q < V; ++q) acc[q] += ar * (wo[q] - left_of<T, V>(wo, nb, q));
             }
             stv_masked<T, V>(D + row * a.ld + c0, acc, a.k - c0);
         }
@@ -136,18 +127,9 @@ __global__ __launch_bounds__(1024) void k_grad(RowArgs<T> a, const T *__restrict
             for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
                 const vec_t<T, V> po = ldv<T, V>(P + i * a.ld + c0);
                 vec_t<T, V> g;
-                if (single) {
-                    const auto nb = plane_neighbours<T, V>(po, sub, lpr, a.k);
+                const auto nb = neighbours_of<T, V>(po, PlainLoad<T, V>{P, a.ld}, i, c0, sub, lpr, a.k, single);
 #pragma unroll
-                    for (int q = 0; q < V; ++q) g[q] = (right_of<T, V>(po, nb, q, c0 + q, a.k) - po[q]) * inv;
-                } else {
-                    const T *pr = P + i * a.ld;
-#pragma unroll
-                    for (int q = 0; q < V; ++q) {
-                        const int l = c0 + q;
-                        g[q] = l < a.k ? (pr[l == a.k - 1 ? 0 : l + 1] - po[q]) * inv : T(0);
-                    }
-                }
+                for (int q = 0; q < V; ++q) g[q] = (right_of<T, V>(po, nb, q, c0 + q, a.k) - po[q]) * inv;
                 if (acc) g = ldv<T, V>(Gz + i * a.ld + c0) + alpha * g;
                 stv_masked<T, V>(Gz + i * a.ld + c0, g, a.k - c0);
             }
@@ -216,11 +198,19 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
             constexpr bool z = decltype(Z)::value;
             constexpr bool can_stage = wt > 0;
             const size_t shm = stage_bytes<T, wt>(g.rows_per_tile);
-            if (can_stage && t.stage_lds)
-                hipLaunchKernelGGL((k_lap<T, v, z, wt, can_stage>), dim3(g.n_blocks), dim3(t.block), shm, s, a, X, Y,
+            const bool st = can_stage && t.stage_lds;
+            if (st && t.nt_store)
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, can_stage, true>), dim3(g.n_blocks), dim3(t.block), shm, s, a,
+                                   X, Y, cs);
+            else if (st)
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, can_stage, false>), dim3(g.n_blocks), dim3(t.block), shm, s, a,
+                                   X, Y, cs);
+            else if (t.nt_store)
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, false, true>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y,
                                    cs);
             else
-                hipLaunchKernelGGL((k_lap<T, v, z, wt, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+                hipLaunchKernelGGL((k_lap<T, v, z, wt, false, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y,
+                                   cs);
         });
     });
     FVX_HIP(hipGetLastError());

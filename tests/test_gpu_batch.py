@@ -58,3 +58,29 @@ def test_batch_reports_per_problem_status():
     Bs = [c.op.to_rows(inputs.rhs_uniform(7 + i, c.m3.N)) for i, c in enumerate(cases)]
     _, stats = fvx.solve_batch([c.op for c in cases], Bs, rtol=1e-12, max_iter=3, allow_not_converged=True)
     assert all(s["status"] == 1 and s["iters"] == 3 for s in stats)
+
+
+def test_many_small_problems_in_one_batch():
+    """300 problems (more than one block of done flags per poll, and a binary
+    search over many block ranges): each converges with the oracle's residual
+    and equals its single solve bitwise."""
+    spec = inputs.channel_base(6, 5)
+    cases = [Case(spec, 2 + (i % 5), math.pi / (2 + (i % 5)), with_f32=False) for i in range(5)]
+    import paper_2508_06710_amd as fvx
+    ops, Bs, bs, cs = [], [], [], []
+    for i in range(300):
+        c = cases[i % 5]
+        b = inputs.rhs_uniform(400 + i, c.op.n_b * c.k)
+        ops.append(c.op)
+        Bs.append(c.op.to_rows(b))
+        bs.append(b)
+        cs.append(c)
+    Xs, sts = fvx.solve_batch(ops, Bs, rtol=1e-10)
+    for i in (0, 1, 2, 3, 4, 150, 299):
+        c, b = cs[i], bs[i]
+        X1, st1 = c.op.solve(Bs[i], rtol=1e-10)
+        assert torch.equal(Xs[i], X1) and sts[i]["iters"] == st1["iters"]
+        bp = oracle.project_mean(b, 1)
+        x = c.op.to_planes(Xs[i])
+        assert np.linalg.norm(bp - oracle.spmv(c.L, x)) <= 1.0001e-10 * np.linalg.norm(bp)
+    assert all(s["status"] == 0 for s in sts)

@@ -180,6 +180,27 @@ def test_div_and_grad(base, k, coupling):
     assert np.all(np.abs(D32 - ref32) <= 16 * 2.0 ** -24 * (abs(c.M) @ np.abs(u32)) + 1e-30)
 
 
+@pytest.mark.parametrize("k,vec,lpr", [(64, 2, 4), (7, 1, 2), (130, 2, 16), (9, 2, 1)])
+def test_multi_pass_row_groups(k, vec, lpr):
+    """Row groups that cover the k columns in several passes take the plane
+    neighbours at the pass edges from memory: lap, div and grad against the
+    oracle with such tiles."""
+    c = Case(BASES["chan13x9"], k)
+    fvx = c.fvx
+    from oracle import spmv
+    c.op.set_tile(vec, lpr, 64, 1, dtype=fvx.F64)
+    y, ref, A, x = _lap_check(c, seed=21)
+    assert componentwise(y, ref, A, x) <= TOL64
+    u = _faces_vec(c, 22)
+    uf, wz = _split_faces(c, u)
+    D = c.op.to_planes(c.op.div(c.op.to_rows(uf, rows=c.op.F_b), c.op.to_rows(wz)))
+    assert componentwise(D, spmv(c.M, u), c.M, u) <= TOL64
+    p = inputs.uniform(23, 0, c.m3.N)
+    Gf, Gz = c.op.grad(c.op.to_rows(p))
+    g = np.concatenate([c.op.to_planes(Gf, rows=c.op.F_b), c.op.to_planes(Gz)])
+    assert componentwise(g, spmv(c.G, p), c.G, p) <= TOL64
+
+
 def test_lap_equals_div_of_grad():
     """L = M G through the GPU operators themselves."""
     c = Case(BASES["chan13x9"], 6)
