@@ -118,6 +118,14 @@ def tune(op, fvx, dtype=None):
     return tile
 
 
+def tune_cg(op, fvx, dtype=None):
+    """Autotuned CG tile for this operator (outside every timed region)."""
+    dt = fvx.F64 if dtype is None else dtype
+    tile, src = op.tune_cg_cached(dtype=dt, cache_path=os.environ.get("FVX_TUNE_CACHE"))
+    log(f"cg tile k={op.k} {'f64' if dt == fvx.F64 else 'f32'}: {tile} ({src})")
+    return tile
+
+
 def build_case(fvx, inputs, k):
     spec = inputs.channel_base(*BASE)
     mesh = fvx.Mesh.from_spec(spec)
@@ -151,6 +159,23 @@ def counters_mode(fvx, inputs, torch):
         fvx.copy(dst[i % 2], src)
     torch.cuda.synchronize()
     log(f"counters run done: lap bytes/launch {spmm_bytes(op.nnz_b, op.n_b, op.k)}, copy bytes {nbytes}")
+
+
+def mixed_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 kernel traces of the mixed-precision solve on
+    the channel workload: one warm-up and one timed solve to 1e-8 of the
+    projection right-hand side."""
+    spec, mesh, op = build_case(fvx, inputs, K_MAIN)
+    tune(op, fvx)
+    tune(op, fvx, fvx.F32)
+    tune_cg(op, fvx)
+    tune_cg(op, fvx, fvx.F32)
+    u = inputs.normal(2, 0, op.F_b * op.k + op.n_b * op.k)
+    D = op.div(op.to_rows(u[:op.F_b * op.k], rows=op.F_b), op.to_rows(u[op.F_b * op.k:]))
+    for _ in range(2):
+        _, st = op.solve(D, rtol=1e-8, precision=fvx.MIXED)
+    torch.cuda.synchronize()
+    log(f"mixed profile run done: {st['iters']} inner iterations, {st['outer']} corrections, {st['seconds']:.4f} s")
 
 
 def net_profile_mode(fvx, inputs, torch):
@@ -238,6 +263,7 @@ def main():
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--counters", action="store_true")
     ap.add_argument("--profile-net", action="store_true")
+    ap.add_argument("--profile-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-airfoil", action="store_true")
     ap.add_argument("--no-guess", action="store_true")
@@ -263,6 +289,9 @@ def main():
     if args.profile_net:
         net_profile_mode(fvx, inputs, torch)
         return
+    if args.profile_mixed:
+        mixed_profile_mode(fvx, inputs, torch)
+        return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
         args.no_batch = args.no_airfoil = args.no_guess = True
@@ -272,6 +301,7 @@ def main():
     spec, mesh, op = build_case(fvx, inputs, K_MAIN)
     tile = tune(op, fvx)
     tune(op, fvx, fvx.F32)
+    cg_tiles = {"f64": list(tune_cg(op, fvx)), "f32": list(tune_cg(op, fvx, fvx.F32))}
     n_b, k, N = op.n_b, op.k, op.n_b * op.k
     Bk = spmm_bytes(op.nnz_b, n_b, k)
     Fk = spmm_flops(op.nnz_b, n_b, k)
@@ -353,7 +383,7 @@ def main():
                      "launch_us": lap_ms * 1e3, "fp64_tflops": Fk / (lap_ms * 1e-3) / 1e12,
                      "fp64_peak_tflops": FP64_PEAK_TFLOPS, "intensity_flop_per_byte": Fk / Bk,
                      "source_sha": sha},
-        "poisson": {"s_to_1e-8": solve_s, "iters": st["iters"], "relres_true": st["relres_true"],
+        "poisson": {"s_to_1e-8": solve_s, "iters": st["iters"], "relres_true": st["relres_true"], "cg_tiles": cg_tiles,
                     "ms_per_iter": solve_s * 1e3 / max(1, st["iters"]),
                     "div_after_over_before": div_ratio},
         "phases_ms": {p: float(np.mean([r[p] for r in recs])) for p in ("div_ms", "solve_ms", "grad_ms", "lap_ms")},
@@ -526,7 +556,7 @@ def batch_leg(fvx, inputs, torch, np, rtol):
     for p in probs:
         mesh = fvx.Mesh.from_spec(p["base"])
         op = fvx.Operator(mesh, p["k"], p["dz"], fvx.PERIODIC_Z, with_f32=True)
-        tiles.append((tune(op, fvx), tune(op, fvx, fvx.F32)))
+        tiles.append((tune(op, fvx), tune(op, fvx, fvx.F32), tune_cg(op, fvx), tune_cg(op, fvx, fvx.F32)))
         Bs.append(op.to_rows(inputs.rhs_uniform(p["seed"], op.n_b * op.k)))
         ops.append((op, mesh))
     opl = [o for o, _ in ops]
@@ -554,7 +584,8 @@ def batch_leg(fvx, inputs, torch, np, rtol):
         del A, b
     out = {
         "problems": [{"base": f"{p['base'].nx}x{p['base'].ny}", "k": p["k"], "cells": o.n_b * o.k,
-                      "tile_f64": list(t[0]), "tile_f32": list(t[1]), "inner_iters": s["iters"],
+                      "tile_f64": list(t[0]), "tile_f32": list(t[1]), "cg_tile_f64": list(t[2]),
+                      "cg_tile_f32": list(t[3]), "inner_iters": s["iters"],
                       "outer": s["outer"], "relres_true": s["relres_true"], "single_s": ts, "csr3d_fp64_s": tc}
                      for p, o, t, s, ts, tc in zip(probs, opl, tiles, sts, singles, csr)],
         "cells": cells,
@@ -591,6 +622,7 @@ def airfoil_leg(fvx, inputs, torch, np):
         res[f"spmm_{name}"] = {"tile": list(tile), "us": t * 1e3, "GBs": Bk / (t * 1e-3) / 1e9,
                                "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del X, Y
+    res["cg_tile_f64"], res["cg_tile_f32"] = list(tune_cg(op, fvx)), list(tune_cg(op, fvx, fvx.F32))
     B = op.to_rows(inputs.rhs_uniform(3, op.n_b * k))
     for prec, name in ((fvx.MIXED, "mixed"), (fvx.F64, "f64")):
         op.solve(B, rtol=rtol, precision=prec)
@@ -623,6 +655,7 @@ def guess_leg(fvx, inputs, torch, np, epochs, lr, rtol=1e-8):
     mesh = fvx.Mesh.from_spec(spec)
     op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=False)
     tune(op, fvx)
+    tune_cg(op, fvx)
     cx, cy = mesh.centroids()
     area = mesh.faces()[0]
 

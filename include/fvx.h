@@ -195,6 +195,29 @@ typedef struct fvx_tune_result {
 int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_bytes, int reps, void *stream,
              fvx_tune_result *results, int max_results, int *n_results);
 
+/* Launch tile of the CG kernels (the fused direction+SpMM kernel and the
+ * update kernel) per precision, separate from the SpMM tile: their partial
+ * reductions make them sensitive to the workgroup size and the grid cap.
+ * get: the tile in use (the one set or tuned, else the default: the SpMM
+ * tile's vector width, 256 threads, XCD remap, at most 1024 workgroups),
+ * with lanes per row widened so that one pass covers all k columns.
+ * set: validated like fvx_op_set_tile, block at most 512 (256 with
+ * independent planes); block 0 or tile NULL restores the default.
+ * The solution of a solve depends on the CG tile only through the order of
+ * its FP64 partial sums. */
+int fvx_op_get_cg_tile(const fvx_op *op, int dtype, fvx_tile *tile);
+int fvx_op_set_cg_tile(fvx_op *op, int dtype, const fvx_tile *tile);
+
+/* CG autotuner: times `iters` CG iterations (FVX_F64: the FP64 solve; FVX_F32:
+ * the FP32 inner CG of the mixed solve) of a fixed right-hand side for each
+ * candidate (workgroup size 128/256/512, XCD remap on/off, grid cap
+ * 512/1024/2048) and sets the fastest as the op's CG tile.  ws: device
+ * workspace of fvx_tune_cg_bytes (256-byte aligned).  Synchronises
+ * `stream`.  results/n_results as fvx_tune (microseconds per iteration). */
+int fvx_tune_cg_bytes(const fvx_op *op, int dtype, size_t *bytes);
+int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, void *stream,
+                fvx_tune_result *results, int max_results, int *n_results);
+
 /* Laplacian SpMM (Algorithm 1 with the plane coupling):
  *   Y[i][l] = s_l ( sum_j A_b[i][j] X[j][l] + w_i (X[i][l+1 mod k] + X[i][l-1 mod k]) )
  * dtype FVX_F64 (double X, Y) or FVX_F32 (float X, Y; needs with_f32).

@@ -225,6 +225,56 @@ class Operator:
                              C.byref(n)), "fvx_tune")
         return [(res[i].tile.as_tuple(), res[i].us) for i in range(min(n.value, max_results))]
 
+    def get_cg_tile(self, dtype=F64):
+        t = Tile()
+        check(lib().fvx_op_get_cg_tile(self._h, dtype, C.byref(t)), "fvx_op_get_cg_tile")
+        return t.as_tuple()
+
+    def set_cg_tile(self, vec=0, lanes_per_row=1, block=0, xcd_remap=1, max_blocks=0, dtype=F64):
+        """CG launch tile (block 0 restores the default)."""
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), 0, 0)
+        check(lib().fvx_op_set_cg_tile(self._h, dtype, C.byref(t)), "fvx_op_set_cg_tile")
+
+    def tune_cg(self, dtype=F64, iters=40, max_results=64, stream=None):
+        """Times CG iterations for candidate CG tiles and keeps the fastest.
+        Returns [(tile tuple, us per iteration), ...] in the order tried."""
+        torch = _torch()
+        nbytes = C.c_size_t()
+        check(lib().fvx_tune_cg_bytes(self._h, dtype, C.byref(nbytes)), "fvx_tune_cg_bytes")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        res = (_lib.TuneResult * max_results)()
+        n = C.c_int()
+        check(lib().fvx_tune_cg(self._h, dtype, _ptr(ws), nbytes.value, int(iters), _stream(stream), res,
+                                max_results, C.byref(n)), "fvx_tune_cg")
+        return [(res[i].tile.as_tuple(), res[i].us) for i in range(min(n.value, max_results))]
+
+    def tune_cg_cached(self, dtype=F64, cache_path=None, iters=40):
+        """CG tile from a JSON cache (same keys as tune_cached, prefixed 'cg|'),
+        tuned and stored when absent.  Returns (tile, source)."""
+        import json
+        import os
+        torch = _torch()
+        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
+        key = (f"cg|{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}"
+               f"|nnz_b={self.nnz_b}|coupling={self.coupling}")
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        if key in cache:
+            t = cache[key]["tile"]
+            self.set_cg_tile(t[0], t[1], t[2], t[3], t[4], dtype=dtype)
+            return tuple(t), "cache"
+        res = self.tune_cg(dtype=dtype, iters=iters)
+        best = self.get_cg_tile(dtype)
+        if cache_path:
+            cache[key] = {"tile": list(best), "us_per_iter": min(r[1] for r in res), "candidates": len(res)}
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return best, "tuned"
+
     # ---- operators --------------------------------------------------------
     def lap(self, X, Y=None, colscale=None, dtype=None, stream=None):
         dt = dtype if dtype is not None else (F32 if str(X.dtype).endswith("float32") else F64)

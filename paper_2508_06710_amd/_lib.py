@@ -82,6 +82,10 @@ SIGNATURES = {
     "fvx_op_get_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
     "fvx_op_set_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
     "fvx_tune": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.c_int, _vp, _vp, C.c_int, _P(C.c_int)]),
+    "fvx_op_get_cg_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
+    "fvx_op_set_cg_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
+    "fvx_tune_cg_bytes": (C.c_int, [_vp, C.c_int, _P(C.c_size_t)]),
+    "fvx_tune_cg": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.c_int, _vp, _vp, C.c_int, _P(C.c_int)]),
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_lap_many": (C.c_int, [_vp, C.c_int, C.c_int, _P(_vp), _P(_vp), _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),

@@ -60,7 +60,7 @@ struct Src {
 // Partial sums of a vector per group (for plain means).
 template <typename T, int V>
 __device__ void b_sum(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__restrict__ v, double *__restrict__ part) {
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     ROW_PROLOGUE
     double c[1][V] = {};
     FOR_ROWS {
@@ -86,7 +86,7 @@ template <typename T, int V>
 __device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_src, int singular,
                           const T *__restrict__ b, T *__restrict__ bp, T *__restrict__ x, T *__restrict__ r,
                           const T *__restrict__ q, int given) {
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     ROW_PROLOGUE
     const int G = d.G;
@@ -143,7 +143,7 @@ template <typename T, int V, bool Z, int WT>
 __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, const T *__restrict__ r,
                        const T *__restrict__ p_old, T *__restrict__ p_new, T *__restrict__ q) {
     if (d.st->done) return;
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     __shared__ double tbb[kMaxGroups];
     __shared__ double s_beta[kMaxGroups];
@@ -229,7 +229,7 @@ template <typename T, int V>
 __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
                        T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q) {
     if (d.st->done) return;
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     __shared__ int s_bad;
     ROW_PROLOGUE
@@ -283,7 +283,7 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
 template <typename T, int V>
 __global__ __launch_bounds__(kMaxCgBlock) void k_fix_x(RowArgs<T> a, CgDev d, Src mean_src, int project,
                                                        T *__restrict__ x) {
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
@@ -312,7 +312,7 @@ template <typename T, int V>
 __global__ __launch_bounds__(kMaxCgBlock) void k_resid(RowArgs<T> a, CgDev d, const T *__restrict__ bp,
                                                        const T *__restrict__ q, T *__restrict__ r,
                                                        double *__restrict__ part) {
-    __shared__ double lds[kMaxCgBlock * kMaxV];
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
     const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     double c[2][V] = {};
@@ -431,6 +431,13 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     b_cg_b<T, V>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
 }
 
+// A fixed, nonzero right-hand side for timing CG tiles: a hash of the index
+// in [-0.5, 0.5) (its mean is projected away like any other).
+__global__ __launch_bounds__(256) void k_fill_pattern(double *__restrict__ b, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        b[i] = double((uint64_t(i) * 2654435761ull) % 1000ull) / 1000.0 - 0.5;
+}
+
 // flags[i] = done flag of item i's CG (one read back per poll for the batch).
 template <typename T>
 __global__ __launch_bounds__(256) void kb_done(const BItem<T> *__restrict__ items, int n, int32_t *__restrict__ flags) {
@@ -454,23 +461,34 @@ struct Carve {
 };
 
 int groups_of(const fvx_op *op) { return op->percol ? op->k : 1; }
-int max_blocks_for(const fvx_op *op) { return op->percol ? 256 : 1024; }
+int max_blocks_for(const fvx_op *op) { return op->percol ? 256 : 2048; }
 
-// CG launch tile for precision T: the op's tile, widened so that one pass of
-// a row group covers all k columns when per-column reductions need it, with
-// at most kMaxCgBlock threads.
+// CG launch tile for precision T: the tile set by the CG autotuner, else a
+// default (the SpMM tile's vector width, 256 threads, XCD remap, a grid of at
+// most 1024 blocks); lanes per row widened so that one pass of a row group
+// covers all k columns, at most kMaxCgBlock threads (kMaxPercolBlock for
+// independent planes).
 template <typename T>
 fvx_tile cg_tile(const fvx_op *op) {
-    fvx_tile t = op->tile[dtype_of<T>()];
+    const int dt = dtype_of<T>();
+    fvx_tile t = op->cg_tile[dt];
+    if (t.block <= 0) {
+        t = op->tile[dt];
+        t.block = 256;
+        t.xcd_remap = 1;
+        t.max_blocks = 1024;
+        t.stage_lds = 0;
+        t.nt_store = 0;
+    }
     if (t.lanes_per_row * t.vec < op->k) t.lanes_per_row = std::min(64, next_pow2(int(ceil_div(op->k, t.vec))));
     if (op->percol && t.lanes_per_row * t.vec < op->k) {
-        const fvx_tile d = default_tile(op, dtype_of<T>());
+        const fvx_tile d = default_tile(op, dt);
         t.vec = d.vec;
         t.lanes_per_row = d.lanes_per_row;
     }
     FVX_REQUIRE(!op->percol || t.lanes_per_row * t.vec >= op->k, FVX_E_UNSUPPORTED,
                 "independent-plane solve: k exceeds one pass of a row group");
-    t.block = std::max(std::min(t.block, kMaxCgBlock), t.lanes_per_row);
+    t.block = std::max(std::min(t.block, op->percol ? kMaxPercolBlock : kMaxCgBlock), t.lanes_per_row);
     return t;
 }
 
@@ -1124,6 +1142,128 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
         if (stats)
             for (int i = 0; i < n; ++i) stats[i].seconds = sec;
         return rc;
+    });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int fvx_op_get_cg_tile(const fvx_op *op, int dtype, fvx_tile *tile) {
+    return guard([&] {
+        FVX_REQUIRE(op && tile, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(dtype == FVX_F64 || (dtype == FVX_F32 && op->has_f32), FVX_E_ARG, "bad dtype for this op");
+        *tile = dtype == FVX_F64 ? fvx::cg_tile<double>(op) : fvx::cg_tile<float>(op);
+        return FVX_OK;
+    });
+}
+
+int fvx_op_set_cg_tile(fvx_op *op, int dtype, const fvx_tile *tile) {
+    return guard([&] {
+        FVX_REQUIRE(op, FVX_E_ARG, "op is NULL");
+        FVX_REQUIRE(dtype == FVX_F64 || (dtype == FVX_F32 && op->has_f32), FVX_E_ARG, "bad dtype for this op");
+        if (!tile || tile->block == 0) {
+            op->cg_tile[dtype] = fvx_tile{};
+            return FVX_OK;
+        }
+        fvx::check_tile(op, dtype, *tile);
+        FVX_REQUIRE(tile->block <= (op->percol ? fvx::kMaxPercolBlock : fvx::kMaxCgBlock), FVX_E_ARG,
+                    "CG tile block too large (512, or 256 for independent planes)");
+        op->cg_tile[dtype] = *tile;
+        return FVX_OK;
+    });
+}
+
+int fvx_tune_cg_bytes(const fvx_op *op, int dtype, size_t *bytes) {
+    return guard([&]() -> int {
+        FVX_REQUIRE(op && bytes, FVX_E_ARG, "NULL argument");
+        fvx_solve_opts o{};
+        fvx_solve_opts_default(&o);
+        o.precision = dtype == FVX_F32 ? FVX_MIXED : FVX_F64;
+        size_t ws = 0;
+        const int rc = fvx_solve_bytes(op, &o, &ws);
+        if (rc != FVX_OK) return rc;
+        const size_t v = (sizeof(double) * size_t(op->n_b) * op->ld + 255) / 256 * 256;
+        *bytes = (ws + 255) / 256 * 256 + 2 * v;
+        return FVX_OK;
+    });
+}
+
+int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, void *stream,
+                fvx_tune_result *results, int max_results, int *n_results) {
+    return guard([&]() -> int {
+        FVX_REQUIRE(op && ws, FVX_E_ARG, "NULL op or workspace");
+        FVX_REQUIRE(dtype == FVX_F64 || (dtype == FVX_F32 && op->has_f32), FVX_E_ARG, "bad dtype for this op");
+        FVX_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, FVX_E_ARG, "ws must be 256-byte aligned");
+        iters = std::max(8, iters);
+        size_t need = 0;
+        const int q = fvx_tune_cg_bytes(op, dtype, &need);
+        if (q != FVX_OK) return q;
+        FVX_REQUIRE(ws_bytes >= need, FVX_E_NOMEM, "workspace too small: need " + std::to_string(need));
+        fvx_solve_opts o{};
+        fvx_solve_opts_default(&o);
+        o.precision = dtype == FVX_F32 ? FVX_MIXED : FVX_F64;
+        o.rtol = 1e-300;  // never met: every timed solve runs `iters` CG iterations
+        o.inner_rtol = 1e-300;
+        o.max_outer = 1;
+        o.max_iter = iters;
+        o.poll_every = iters;
+        size_t sws = 0;
+        fvx_solve_bytes(op, &o, &sws);
+        sws = (sws + 255) / 256 * 256;
+        const size_t v = (sizeof(double) * size_t(op->n_b) * op->ld + 255) / 256 * 256;
+        double *B = reinterpret_cast<double *>(static_cast<char *>(ws) + sws);
+        double *X = reinterpret_cast<double *>(static_cast<char *>(ws) + sws + v);
+        hipStream_t s = fvx::as_stream(stream);
+        const int64_t n = int64_t(op->n_b) * op->ld;
+        hipLaunchKernelGGL(fvx::k_fill_pattern, dim3(1024), dim3(256), 0, s, B, n);
+        FVX_HIP(hipGetLastError());
+        // Candidates: the widest vector, one pass per row group, and the block
+        // size, XCD remap and grid cap that the CG kernels are sensitive to.
+        const fvx_tile base = fvx::default_tile(op, dtype);
+        std::vector<fvx_tile> cands;
+        for (int block : {128, 256, 512}) {
+            if (op->percol && block > fvx::kMaxPercolBlock) continue;
+            if (block < base.lanes_per_row) continue;
+            for (int remap : {1, 0})
+                for (int cap : {1024, 512, 2048}) {
+                    if (op->percol && cap != 1024) continue;  // independent planes: grids of at most 256 blocks
+                    fvx_tile t = base;
+                    t.block = block;
+                    t.xcd_remap = remap;
+                    t.max_blocks = cap;
+                    cands.push_back(t);
+                }
+        }
+        if (cands.empty()) cands.push_back(base);
+        const fvx_tile keep = op->cg_tile[dtype];
+        fvx_tile best = cands[0];
+        double best_us = 1e300;
+        int count = 0;
+        try {
+            for (const fvx_tile &t : cands) {
+                op->cg_tile[dtype] = t;
+                fvx_solve_stats st{};
+                double us = 1e300;
+                for (int rep = 0; rep < 3; ++rep) {
+                    const int rc = fvx_poisson_solve(op, B, X, &o, ws, sws, &st, stream);
+                    FVX_REQUIRE(rc >= 0, rc, "CG tile timing solve failed");
+                    if (rep > 0) us = std::min(us, 1e6 * st.seconds / double(std::max(1, st.iters)));
+                }
+                if (results && count < max_results) results[count] = fvx_tune_result{t, us};
+                ++count;
+                if (us < best_us) {
+                    best_us = us;
+                    best = t;
+                }
+            }
+        } catch (...) {
+            op->cg_tile[dtype] = keep;
+            throw;
+        }
+        op->cg_tile[dtype] = best;
+        if (n_results) *n_results = count;
+        return FVX_OK;
     });
 }
 

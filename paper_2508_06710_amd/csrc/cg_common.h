@@ -13,7 +13,8 @@
 
 namespace fvx {
 
-constexpr int kMaxCgBlock = 256;
+constexpr int kMaxCgBlock = 512;     // launch bound of the CG kernels
+constexpr int kMaxPercolBlock = 256;  // independent planes: per-column partials staged in LDS
 constexpr int kMaxV = 4;
 constexpr int kMaxGroups = 256;
 

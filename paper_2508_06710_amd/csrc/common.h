@@ -67,6 +67,7 @@ struct fvx_op {
     fvx::OpDev<double> d64;
     fvx::OpDev<float> d32;
     fvx_tile tile[2];
+    fvx_tile cg_tile[2] = {};  // CG launch tile per precision (block 0: not set)
 };
 
 namespace fvx {

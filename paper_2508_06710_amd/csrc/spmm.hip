@@ -53,6 +53,61 @@ __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict_
     }
 }
 
+// The same product when a row group covers the k columns in exactly P
+// passes (k = P * lanes_per_row * V): the row's entries are read once, and
+// every pass's own-row and neighbour-row loads are issued before the first
+// multiply-add, so a lane keeps P times more bytes in flight.  The plane
+// neighbours at pass edges come from the neighbouring pass's registers.  The
+// operations per element are those of lap_row_meta, in the same order.
+template <typename T, int V, bool Z, int WT, bool NT, int P>
+__global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+                                                     const double *__restrict__ cs) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        const RowMeta<T, WT> m = meta_global<T, WT, Z>(a.A, a.n_b, row);
+        vec_t<T, V> xo[P], xj[P][WT];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int c0 = (p * lpr + sub) * V;
+            xo[p] = ldv<T, V>(X + row * a.ld + c0);
+#pragma unroll
+            for (int e = 0; e < WT; ++e) xj[p][e] = ldv<T, V>(X + int64_t(m.col[e]) * a.ld + c0);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int c0 = (p * lpr + sub) * V;
+            vec_t<T, V> acc = m.diag * xo[p];
+#pragma unroll
+            for (int e = 0; e < WT; ++e) acc += m.val[e] * xj[p][e];
+            if constexpr (Z) {
+                // column c0 - 1: lane sub - 1 of this pass, or the last lane of the
+                // previous pass (of the last pass for column k - 1); column c0 + V:
+                // lane sub + 1, or lane 0 of the next pass (of pass 0 for column 0)
+                const T l_same = __shfl(xo[p][V - 1], sub == 0 ? 0 : sub - 1, lpr);
+                const T l_prev = __shfl(xo[p > 0 ? p - 1 : P - 1][V - 1], lpr - 1, lpr);
+                const T r_same = __shfl(xo[p][0], sub == lpr - 1 ? 0 : sub + 1, lpr);
+                const T r_next = __shfl(xo[p + 1 < P ? p + 1 : 0][0], 0, lpr);
+                PlaneNeighbours<T, V> nb;
+                nb.left0 = sub > 0 ? l_same : l_prev;
+                nb.rightV = sub < lpr - 1 ? r_same : r_next;
+#pragma unroll
+                for (int q = 0; q < V; ++q)
+                    acc[q] += m.w * (left_of<T, V>(xo[p], nb, q) + right_of<T, V>(xo[p], nb, q, c0 + q, a.k));
+            }
+            if (cs) {
+#pragma unroll
+                for (int q = 0; q < V; ++q) acc[q] *= T(cs[c0 + q]);
+            }
+            stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
+        }
+    }
+}
+
 // D = M U: integrated divergence of in-plane face fluxes plus the fluxes
 // through the faces between planes.
 template <typename T, int V, bool Z, int WT>
@@ -199,6 +254,26 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
             constexpr bool can_stage = wt > 0;
             const size_t shm = stage_bytes<T, wt>(g.rows_per_tile);
             const bool st = can_stage && t.stage_lds;
+            const int span = t.lanes_per_row * v;
+            const int passes = op->k % span == 0 ? op->k / span : 0;
+            if constexpr (wt > 0) {
+                if (!st && (passes == 2 || passes == 4) && t.block <= 512) {  // its launch bound
+                    auto go = [&](auto Pt) {
+                        constexpr int P = decltype(Pt)::value;
+                        if (t.nt_store)
+                            hipLaunchKernelGGL((k_lap_passes<T, v, z, wt, true, P>), dim3(g.n_blocks), dim3(t.block), 0,
+                                               s, a, X, Y, cs);
+                        else
+                            hipLaunchKernelGGL((k_lap_passes<T, v, z, wt, false, P>), dim3(g.n_blocks), dim3(t.block),
+                                               0, s, a, X, Y, cs);
+                    };
+                    if (passes == 2)
+                        go(std::integral_constant<int, 2>{});
+                    else
+                        go(std::integral_constant<int, 4>{});
+                    return;
+                }
+            }
             if (st && t.nt_store)
                 hipLaunchKernelGGL((k_lap<T, v, z, wt, can_stage, true>), dim3(g.n_blocks), dim3(t.block), shm, s, a,
                                    X, Y, cs);

@@ -186,3 +186,31 @@ def test_mixed_precision_does_not_depend_on_workspace_contents():
     X2, _ = c.op.solve(b, **opts)
     assert torch.equal(X1, X2)
     assert max(_true_relres(c, c.op.to_planes(X1), c.op.to_planes(b))) <= 1.05e-10
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_cg_tiles_and_tuner(precision):
+    """Every CG tile solves to the tolerance by the oracle's residual; the CG
+    autotuner keeps its fastest candidate; block 0 restores the default."""
+    c = Case(inputs.channel_base(40, 24), 16, with_f32=True)
+    fvx = c.fvx
+    dt = fvx.F64 if precision == "f64" else fvx.F32
+    prec = fvx.F64 if precision == "f64" else fvx.MIXED
+    b = inputs.rhs_uniform(77, c.op.n_b * c.k)
+    B = c.op.to_rows(b)
+    vec = c.op.get_cg_tile(dt)[0]
+    for block, remap, cap in ((128, 0, 512), (512, 1, 2048), (256, 1, 0)):
+        c.op.set_cg_tile(vec, 1, block, remap, cap, dtype=dt)
+        got = c.op.get_cg_tile(dt)
+        assert got[2] == block and got[1] * got[0] >= c.k  # lanes widened to one pass
+        X, st = c.op.solve(B, rtol=1e-10, precision=prec)
+        assert max(_true_relres(c, c.op.to_planes(X), b)) <= 1e-10 * 1.0001
+    res = c.op.tune_cg(dt, iters=16)
+    assert len(res) >= 6
+    assert c.op.get_cg_tile(dt) == min(res, key=lambda r: r[1])[0]
+    X, st = c.op.solve(B, rtol=1e-10, precision=prec)
+    assert max(_true_relres(c, c.op.to_planes(X), b)) <= 1e-10 * 1.0001
+    c.op.set_cg_tile(block=0, dtype=dt)
+    assert c.op.get_cg_tile(dt)[2] == 256
+    with pytest.raises(fvx.FvxError):
+        c.op.set_cg_tile(vec, 8, 1024, 1, 0, dtype=dt)
