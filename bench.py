@@ -55,6 +55,16 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def lap_kernel_name(tile, k):
+    """The lap SpMM kernel a tile selects (vec, lanes, block, remap, cap, stage, nt)."""
+    vec, lpr, block, _, _, stage, nt = tile
+    span = vec * lpr
+    passes = k // span if k % span == 0 else 0
+    if passes in (2, 4) and not stage and block <= 512:
+        return f"k_lap_passes<double,{vec},true,4,{bool(nt)},{passes}>"
+    return f"k_lap<double,{vec},true,4,{bool(stage)},{bool(nt)}>"
+
+
 def spmm_bytes(nnz_b, n_b, k, v=8):
     """Algorithmic bytes of one Laplacian SpMM: the base block once (values,
     int32 column indices, int32 row pointers), the coupling weights once, X
@@ -379,7 +389,7 @@ def main():
                    "rtol": rtol},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_lap<double,V,true,4,S>", "tile": list(tile), "bytes_per_launch": Bk,
+                     "kernel": lap_kernel_name(tile, k), "tile": list(tile), "bytes_per_launch": Bk,
                      "launch_us": lap_ms * 1e3, "fp64_tflops": Fk / (lap_ms * 1e-3) / 1e12,
                      "fp64_peak_tflops": FP64_PEAK_TFLOPS, "intensity_flop_per_byte": Fk / Bk,
                      "source_sha": sha},
