@@ -139,6 +139,11 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_06710_amd.build` "
                               "(or __graft_entry__.build()); there is no fallback implementation")
+        # torch first: its wheel carries its own HIP runtime (same soname as
+        # /opt/rocm's).  Loaded after the library, it would bring a second
+        # runtime into the process, and device memory from one is unknown to
+        # the other; loaded before, the library binds to torch's runtime.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -114,3 +114,17 @@ def test_kronecker_expansion_matches_oracle_assembly(fvx, orc, spec, k, coupling
     assert np.array_equal(ptr, L.indptr) and np.array_equal(col, L.indices)
     ulp = np.spacing(np.abs(L.data))
     assert np.all(np.abs(val - L.data) <= 2 * ulp + 1e-300 * 0), float(np.max(np.abs(val - L.data) / ulp))
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """torch's wheel carries its own HIP runtime; loading the library must not
+    bring a second one into the process (device memory from one runtime is
+    unknown to the other).  No device call is made."""
+    import subprocess
+    import sys
+    code = ("import paper_2508_06710_amd as f; f.lib(); import torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
