@@ -147,7 +147,11 @@ typedef struct fvx_op_desc {
  * base-block rows (column indices, values, diagonal, coupling weight) in LDS
  * with coalesced loads, shared by all lanes of a row (needs at most 64 rows
  * per tile, i.e. block / lanes_per_row <= 64); nt_store = nonzero writes the
- * SpMM output with non-temporal stores (not re-read by the same kernel). */
+ * Laplacian SpMM's output with non-temporal stores (not re-read by the same
+ * kernel).  When one row group covers the k columns in exactly 2 or 4 passes
+ * (k = passes * lanes_per_row * vec, no LDS staging, block <= 512), every
+ * pass's loads are issued before the arithmetic.  All tiles give bitwise the
+ * same product. */
 typedef struct fvx_tile {
     int32_t vec, lanes_per_row, block, xcd_remap, max_blocks, stage_lds, nt_store;
 } fvx_tile;

@@ -270,7 +270,7 @@ template <typename T>
 struct RowArgs {
     OpDev<T> A;
     int64_t n_b, n_rows;
-    int k, ld, W, Wd, lpr, rows_per_tile, remap, nt;
+    int k, ld, W, Wd, lpr, rows_per_tile, remap;
     int64_t tiles_per_block;
     int64_t F_b;
 };
@@ -291,7 +291,6 @@ inline RowArgs<T> row_args(const fvx_op *op, int64_t n_rows, RowGrid &g, const f
     a.lpr = t.lanes_per_row;
     a.rows_per_tile = g.rows_per_tile;
     a.remap = t.xcd_remap;
-    a.nt = t.nt_store;
     a.tiles_per_block = g.tiles_per_block;
     a.F_b = op->F_b;
     return a;
