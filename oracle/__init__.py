@@ -70,6 +70,9 @@ def lib():
         L.orc_spmv.restype = None
         L.orc_cg.argtypes = [l64, l64, _lp, _ip, _dp, _dp, _dp, i, d, i, i, P(_CGStats)]
         L.orc_threads.argtypes = []
+        L.orc_stencil_max_nnz.argtypes = [i, i, i, i]
+        L.orc_stencil_max_nnz.restype = l64
+        L.orc_assemble_stencil.argtypes = [i, i, d, d, d, d, d, i, i, i, d, i, _lp, _ip, _dp, P(l64)]
         _lib = L
     return _lib
 
@@ -236,6 +239,23 @@ class Mesh3D:
 
     def z_centres(self) -> np.ndarray:
         return (np.arange(self.k) + 0.5) * self.dz
+
+
+def stencil_lap(spec, k: int, dz: float, stencil: int) -> sp.csr_matrix:
+    """The 13- or 27-point operator of a Cartesian base ``spec`` repeated in k
+    periodic planes (see ``orc_assemble_stencil`` in oracle.c), plane-major."""
+    L = lib()
+    n = spec.nx * spec.ny * k
+    cap = int(L.orc_stencil_max_nnz(spec.nx, spec.ny, k, stencil))
+    ptr = np.zeros(n + 1, np.int64)
+    col = np.zeros(cap, np.int32)
+    val = np.zeros(cap)
+    nnz = C.c_int64()
+    _check(L.orc_assemble_stencil(spec.nx, spec.ny, spec.x0, spec.Lx, spec.y0, spec.y1, spec.stretch,
+                                  int(spec.periodic_x), int(spec.periodic_y), k, float(dz), int(stencil),
+                                  ptr, col, val, C.byref(nnz)), "assemble_stencil")
+    m = nnz.value
+    return sp.csr_matrix((val[:m], col[:m], ptr), shape=(n, n))
 
 
 def threads() -> int:

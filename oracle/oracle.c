@@ -671,3 +671,190 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+
+/* ---- higher-order structured operators (13- and 27-point) --------------
+ *
+ * The paper tests its SpMM with 7-, 13- and 27-point Laplacian stencils
+ * (Section 4.1, the discretisation figure): first neighbours; first and
+ * second neighbours along each axis; all 26 neighbours.  Here they are
+ * written for a Cartesian base (the same face coordinates as
+ * orc_cart_geometry) repeated in k periodic planes of spacing dz, with the
+ * unknowns at the cell centres:
+ *
+ *  27-point: minus the tensor-product (trilinear finite-element) stiffness on
+ *    the centre nodes, A = -(Kx My Mz + Mx Ky Mz + Mx My Kz).  Along one axis,
+ *    every element joins two consecutive centres a, b at distance s and adds
+ *    [1 -1; -1 1]/s to K and [2 1; 1 2] s/6 to M at (a, b).  A periodic axis
+ *    closes the loop with an element across the period; a wall axis has none
+ *    beyond its end centres (zero flux).
+ *  13-point: A = (4/3) L1 - (1/6) L2.  L1 is the 7-point finite-volume form:
+ *    off-diagonal len*dz/dist between face neighbours (len the face length,
+ *    dist the centre distance) and area/dz between neighbouring planes.  L2
+ *    has the same form between second neighbours along each axis (the face
+ *    length over the distance of the two centres, area/(2 dz) between planes
+ *    l and l +- 2).  Each has diagonal minus its off-diagonal row sum.  On a
+ *    uniform grid this is the cell volume times the fourth-order central
+ *    difference (-1/12, 4/3, -5/2, 4/3, -1/12)/h^2 along each axis.
+ *
+ * Rows and columns are 3D cells l*n_b + j*nx + i.  Entries that meet at one
+ * column (short periodic axes) are summed.
+ */
+typedef struct {
+    int n, periodic;
+    double *c;        /* centres */
+    double period;    /* length of the period (periodic axes) */
+} axis1d;
+
+static int make_axis(axis1d *a, int n, int periodic, const double *faces)
+{
+    a->n = n;
+    a->periodic = periodic;
+    a->c = malloc(sizeof(double) * (size_t)n);
+    if (!a->c) return ERR_NOMEM;
+    for (int i = 0; i < n; ++i) a->c[i] = 0.5 * (faces[i] + faces[i + 1]);
+    a->period = faces[n] - faces[0];
+    return 0;
+}
+
+/* centre distance from node i to node i + d (d = 1, 2), walking forward */
+static double fwd_dist(const axis1d *a, int i, int d)
+{
+    double s = 0.0;
+    for (int q = 0; q < d; ++q) {
+        int u = (i + q) % a->n, v = (i + q + 1) % a->n;
+        s += (u + 1 < a->n) ? a->c[v] - a->c[u] : a->c[v] + a->period - a->c[u];
+    }
+    return s;
+}
+
+/* dense 1D stiffness K and mass M (n x n, row-major) of an axis */
+static int axis_km(const axis1d *a, double **K, double **M)
+{
+    int n = a->n;
+    *K = calloc((size_t)n * n, sizeof(double));
+    *M = calloc((size_t)n * n, sizeof(double));
+    if (!*K || !*M) return ERR_NOMEM;
+    int ne = a->periodic ? n : n - 1;
+    for (int e = 0; e < ne; ++e) {
+        int u = e, v = (e + 1) % n;
+        double s = fwd_dist(a, e, 1);
+        (*K)[u * n + u] += 1.0 / s;  (*K)[v * n + v] += 1.0 / s;
+        (*K)[u * n + v] -= 1.0 / s;  (*K)[v * n + u] -= 1.0 / s;
+        (*M)[u * n + u] += s / 3.0;  (*M)[v * n + v] += s / 3.0;
+        (*M)[u * n + v] += s / 6.0;  (*M)[v * n + u] += s / 6.0;
+    }
+    return 0;
+}
+
+/* distinct indices among i-1, i, i+1 on an axis (periodic wrap or bounded) */
+static int near3(const axis1d *a, int i, int *out)
+{
+    int m = 0;
+    for (int d = -1; d <= 1; ++d) {
+        int v = i + d;
+        if (a->periodic) v = ((v % a->n) + a->n) % a->n;
+        else if (v < 0 || v >= a->n) continue;
+        int dup = 0;
+        for (int q = 0; q < m; ++q) dup |= out[q] == v;
+        if (!dup) out[m++] = v;
+    }
+    return m;
+}
+
+int64_t orc_stencil_max_nnz(int nx, int ny, int k, int stencil)
+{
+    int64_t n3 = (int64_t)nx * ny * k;
+    return n3 * (stencil == 27 ? 27 : 14);
+}
+
+int orc_assemble_stencil(int nx, int ny, double x0, double Lx, double y0, double y1, double stretch,
+                         int periodic_x, int periodic_y, int k, double dz, int stencil,
+                         int64_t *ptr, int32_t *col, double *val, int64_t *nnz)
+{
+    if (nx < 1 || ny < 1 || k < 1 || !(dz > 0.0) || !(Lx > 0.0) || !(y1 > y0)) return ERR_ARG;
+    if (stencil != 13 && stencil != 27) return ERR_ARG;
+    double *xf = malloc(sizeof(double) * (nx + 1)), *yf = malloc(sizeof(double) * (ny + 1));
+    double *zf = malloc(sizeof(double) * (k + 1));
+    if (!xf || !yf || !zf) { free(xf); free(yf); free(zf); return ERR_NOMEM; }
+    for (int i = 0; i <= nx; ++i) xf[i] = x0 + Lx * (double)i / (double)nx;
+    for (int j = 0; j <= ny; ++j) yf[j] = stretched(j, ny, y0, y1, stretch);
+    for (int l = 0; l <= k; ++l) zf[l] = dz * l;
+    axis1d ax, ay, az;
+    int e = make_axis(&ax, nx, periodic_x, xf);
+    if (!e) e = make_axis(&ay, ny, periodic_y, yf);
+    if (!e) e = make_axis(&az, k, 1, zf);
+    if (e) return e;
+    const int64_t nb = (int64_t)nx * ny, n3 = nb * k;
+    int64_t cap = orc_stencil_max_nnz(nx, ny, k, stencil);
+    trip_o *T = malloc(sizeof(trip_o) * (size_t)cap);
+    if (!T) return ERR_NOMEM;
+    int64_t t = 0;
+#define PUT(R, C, V) do { T[t].t = (trip){(R), (int32_t)(C), (V)}; T[t].order = t; ++t; } while (0)
+    if (stencil == 27) {
+        double *Kx, *Mx, *Ky, *My, *Kz, *Mz;
+        e = axis_km(&ax, &Kx, &Mx);
+        if (!e) e = axis_km(&ay, &Ky, &My);
+        if (!e) e = axis_km(&az, &Kz, &Mz);
+        if (e) { free(T); return e; }
+        for (int l = 0; l < k; ++l)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int64_t r = (int64_t)l * nb + (int64_t)j * nx + i;
+                    int ni[3], nj[3], nl[3];
+                    int mi = near3(&ax, i, ni), mj = near3(&ay, j, nj), ml = near3(&az, l, nl);
+                    for (int a = 0; a < ml; ++a)
+                        for (int b = 0; b < mj; ++b)
+                            for (int c = 0; c < mi; ++c) {
+                                int I = ni[c], J = nj[b], Lz = nl[a];
+                                double v = Kx[i * nx + I] * My[j * ny + J] * Mz[l * k + Lz]
+                                         + Mx[i * nx + I] * Ky[j * ny + J] * Mz[l * k + Lz]
+                                         + Mx[i * nx + I] * My[j * ny + J] * Kz[l * k + Lz];
+                                PUT(r, (int64_t)Lz * nb + (int64_t)J * nx + I, -v);
+                            }
+                }
+        free(Kx); free(Mx); free(Ky); free(My); free(Kz); free(Mz);
+    } else {
+        for (int l = 0; l < k; ++l)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int64_t r = (int64_t)l * nb + (int64_t)j * nx + i;
+                    double hx = xf[i + 1] - xf[i], hy = yf[j + 1] - yf[j];
+                    double area = hx * hy, diag = 0.0;
+                    for (int d = 1; d <= 2; ++d) {
+                        double w = d == 1 ? 4.0 / 3.0 : -1.0 / 6.0;
+                        for (int sgn = -1; sgn <= 1; sgn += 2) {
+                            /* x */
+                            int I = i + sgn * d;
+                            if (periodic_x || (I >= 0 && I < nx)) {
+                                int Iw = ((I % nx) + nx) % nx;
+                                double dist = sgn > 0 ? fwd_dist(&ax, i, d) : fwd_dist(&ax, Iw, d);
+                                double cf = w * hy * dz / dist;
+                                PUT(r, (int64_t)l * nb + (int64_t)j * nx + Iw, cf);
+                                diag -= cf;
+                            }
+                            /* y */
+                            int J = j + sgn * d;
+                            if (periodic_y || (J >= 0 && J < ny)) {
+                                int Jw = ((J % ny) + ny) % ny;
+                                double dist = sgn > 0 ? fwd_dist(&ay, j, d) : fwd_dist(&ay, Jw, d);
+                                double cf = w * hx * dz / dist;
+                                PUT(r, (int64_t)l * nb + (int64_t)Jw * nx + i, cf);
+                                diag -= cf;
+                            }
+                            /* z (periodic planes) */
+                            int Lz = (((l + sgn * d) % k) + k) % k;
+                            double cf = w * area / (d * dz);
+                            PUT(r, (int64_t)Lz * nb + (int64_t)j * nx + i, cf);
+                            diag -= cf;
+                        }
+                    }
+                    PUT(r, r, diag);
+                }
+    }
+#undef PUT
+    free(xf); free(yf); free(zf); free(ax.c); free(ay.c); free(az.c);
+    int rc = to_csr(T, t, n3, ptr, col, val, nnz);
+    free(T);
+    return rc;
+}

@@ -62,6 +62,14 @@ int orc_assemble_grad(const orc_mesh3d *m, int64_t *ptr, int32_t *col, double *v
 int orc_face_volumes(const orc_mesh3d *m, double *omega_s);
 int orc_cell_volumes(const orc_mesh3d *m, double *omega_c);
 
+/* ---- higher-order structured operators (13- and 27-point) -------------- */
+/* A Cartesian base (as orc_cart_geometry) repeated in k periodic planes;
+ * stencil 13 or 27 (definitions in oracle.c).  CSR as orc_assemble_lap. */
+int64_t orc_stencil_max_nnz(int nx, int ny, int k, int stencil);
+int orc_assemble_stencil(int nx, int ny, double x0, double Lx, double y0, double y1, double stretch,
+                         int periodic_x, int periodic_y, int k, double dz, int stencil,
+                         int64_t *ptr, int32_t *col, double *val, int64_t *nnz);
+
 /* ---- dense brute force (tiny meshes) ---------------------------------- */
 int orc_dense_lap(const orc_mesh3d *m, double *L);   /* N x N row-major */
 int orc_dense_div(const orc_mesh3d *m, double *M);   /* N x F3 */
