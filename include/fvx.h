@@ -135,7 +135,19 @@ typedef struct fvx_op_desc {
     int32_t wall_bc;    /* FVX_WALL_NEUMANN: zero-flux walls (L singular, null
                            space = constants); FVX_WALL_DIRICHLET: p = 0 on walls */
     int32_t with_f32;   /* nonzero: also store FP32 copies (FVX_F32 and FVX_MIXED) */
-    int32_t reserved[4];
+    int32_t stencil;    /* Laplacian: 0 or 7 = the finite-volume operator of the face
+                           graph (Section 3, Eq. 9); 13 or 27 = the higher-order
+                           structured stencils of Section 4.1 on a Cartesian base
+                           (fvx_mesh_cartesian), coupling PERIODIC_Z, zero-flux walls,
+                           k <= 128:
+                             27: minus the trilinear-element (Q1) stiffness on the
+                                 cell centres, -(Kx My Mz + Mx Ky Mz + Mx My Kz);
+                             13: (4/3) L1 - (1/6) L2, L1 the 7-point finite-volume
+                                 form and L2 the same form between second neighbours
+                                 along each axis (area/(2 dz) between planes l, l+-2):
+                                 the fourth-order central difference on uniform grids.
+                           div/grad stay the face-graph operators; solves need 7. */
+    int32_t reserved[3];
 } fvx_op_desc;
 
 /* Launch tile of the SpMM kernels: vec = elements per lane per load (FP64:

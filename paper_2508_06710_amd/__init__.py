@@ -128,10 +128,11 @@ class Mesh:
 _DT = {F64: "float64", F32: "float32"}
 
 
-def expand_csr(mesh: Mesh, k: int, dz: float, coupling: int = PERIODIC_Z, wall_bc: int = NEUMANN):
+def expand_csr(mesh: Mesh, k: int, dz: float, coupling: int = PERIODIC_Z, wall_bc: int = NEUMANN, stencil: int = 7):
     """Host: the assembled 3D Laplacian I_k (x) A_b + C as CSR arrays (ptr, col, val)."""
     d = _lib.OpDesc()
     d.k, d.coupling, d.dz, d.wall_bc, d.with_f32 = int(k), int(coupling), float(dz), int(wall_bc), 0
+    d.stencil = int(stencil)
     nnz = C.c_int64()
     check(lib().fvx_expand_csr(mesh._h, C.byref(d), C.byref(nnz), None, None, None), "fvx_expand_csr")
     ptr = np.zeros(k * mesh.n_cells + 1, np.int32)
@@ -146,12 +147,14 @@ class Operator:
     """Repeated-block operator L = I_k (x) A_b + C (plus M_b, G_b) on the device."""
 
     def __init__(self, mesh: Mesh, k: int, dz: float, coupling: int = PERIODIC_Z,
-                 wall_bc: int = NEUMANN, with_f32: bool = True, device=None, stream=None):
+                 wall_bc: int = NEUMANN, with_f32: bool = True, device=None, stream=None, stencil: int = 7):
         torch = _torch()
         self.mesh = mesh
         self.device = torch.device(device if device is not None else "cuda")
         d = _lib.OpDesc()
         d.k, d.coupling, d.dz, d.wall_bc, d.with_f32 = int(k), int(coupling), float(dz), int(wall_bc), int(with_f32)
+        d.stencil = int(stencil)
+        self.stencil = int(stencil) if stencil in (13, 27) else 7
         self._desc = d
         nbytes = C.c_size_t()
         check(lib().fvx_op_bytes(mesh._h, C.byref(d), C.byref(nbytes)), "fvx_op_bytes")

@@ -22,7 +22,8 @@ E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2,
 
 class OpDesc(C.Structure):
     _fields_ = [("k", C.c_int32), ("coupling", C.c_int32), ("dz", C.c_double),
-                ("wall_bc", C.c_int32), ("with_f32", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("wall_bc", C.c_int32), ("with_f32", C.c_int32), ("stencil", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Tile(C.Structure):

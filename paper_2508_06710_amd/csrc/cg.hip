@@ -821,6 +821,7 @@ void fill_stats(fvx_solve_stats *st, const HostScalars &h, const std::vector<dou
 
 void check_opts(const fvx_op *op, const fvx_solve_opts *o) {
     FVX_REQUIRE(op && o, FVX_E_ARG, "NULL op or options");
+    FVX_REQUIRE(op->stencil == 7, FVX_E_UNSUPPORTED, "solves use the 7-point finite-volume operator");
     FVX_REQUIRE(o->rtol > 0 && o->rtol < 1, FVX_E_ARG, "rtol must be in (0, 1)");
     FVX_REQUIRE(o->max_iter >= 1, FVX_E_ARG, "max_iter must be >= 1");
     FVX_REQUIRE(o->precision == FVX_F64 || o->precision == FVX_MIXED, FVX_E_ARG,

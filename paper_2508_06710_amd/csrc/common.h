@@ -20,6 +20,8 @@
 struct fvx_mesh {
     int n_cells = 0, n_faces = 0, n_walls = 0;
     int grid_nx = 0, grid_ny = 0;  // Cartesian builder: cell (i, j) is j*nx + i; 0 otherwise
+    std::vector<double> xf, yf;    // Cartesian builder: face coordinates along x and y
+    bool periodic_x = false, periodic_y = false;
     std::vector<double> area, cx, cy;
     std::vector<int32_t> c1, c2;
     std::vector<double> len, dist;
@@ -49,6 +51,11 @@ struct OpDev {
     const int32_t *f_c1 = nullptr, *f_c2 = nullptr;
     const T *f_invd = nullptr;
     T inv_dz = 0;
+    // Structured 13/27-point operators: per ELL entry the coefficient of the
+    // neighbour's planes l +- 1 (27-point), and the row's own planes l +- 2
+    // coefficient (13-point); NULL otherwise.
+    const T *ell_v1 = nullptr;
+    const T *w2 = nullptr;
 };
 
 }  // namespace fvx
@@ -63,6 +70,7 @@ struct fvx_op {
     int W = 0, Wd = 0;      // ELL widths (Laplacian off-diagonals, cell->face)
     bool has_f32 = false;
     int grid_nx = 0, grid_ny = 0;  // structured base (Cartesian builder), else 0
+    int stencil = 7;                // 7: finite-volume face graph; 13, 27: structured operators
     int device = 0;
     fvx::OpDev<double> d64;
     fvx::OpDev<float> d32;

@@ -264,6 +264,69 @@ __device__ __forceinline__ vec_t<T, V> lap_row(const OpDev<T> &A, const T *__res
     return lap_row_ld<T, V, Z, WT>(A, PlainLoad<T, V>{X, ld}, n_b, k, W, row, c0, sub, lpr, single, xo);
 }
 
+// ---------------------------------------------------------------------------
+// Structured 13/27-point operators (one pass of a row group covers all k
+// columns and V divides k)
+// ---------------------------------------------------------------------------
+
+// Column (c + D) mod k of each of this lane's V columns c = c0 .. c0+V-1:
+// from the lane's own values when it holds that column, else from the lane
+// of the row group that does.
+template <typename T, int V, int D>
+__device__ __forceinline__ vec_t<T, V> plane_shift(const vec_t<T, V> &xo, int c0, int lpr, int k) {
+    vec_t<T, V> out;
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+        const int u = t + D;
+        if (u >= 0 && u < V) {
+            out[t] = xo[u >= 0 && u < V ? u : 0];
+        } else {
+            const int g = ((c0 + u) % k + k) % k;
+            out[t] = __shfl(xo[((u % V) + V) % V], g / V, lpr);
+        }
+    }
+    return out;
+}
+
+// One row of the structured operator:
+//   diag x_i + sum_e v0_e x_j(e) + w1 (x_i[l+1] + x_i[l-1])
+//   [+ w2 (x_i[l+2] + x_i[l-2])]                 (13-point, S2)
+//   [+ sum_e v1_e (x_j(e)[l+1] + x_j(e)[l-1])]   (27-point, E1)
+// Each neighbour row is loaded once; its shifted planes come from lane
+// shuffles.
+template <typename T, int V, int WT, bool E1, bool S2>
+__device__ __forceinline__ vec_t<T, V> stencil_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b, int k,
+                                                   int ld, int64_t row, int c0, int lpr) {
+    using vt = vec_t<T, V>;
+    int32_t col[WT];
+    T v0[WT], v1[WT];
+#pragma unroll
+    for (int e = 0; e < WT; ++e) {
+        col[e] = A.ell_col[e * n_b + row];
+        v0[e] = A.ell_val[e * n_b + row];
+        v1[e] = E1 ? A.ell_v1[e * n_b + row] : T(0);
+    }
+    const vt xo = ldv<T, V>(X + row * ld + c0);
+    vt xj[WT];
+#pragma unroll
+    for (int e = 0; e < WT; ++e) xj[e] = ldv<T, V>(X + int64_t(col[e]) * ld + c0);
+    // Explicit fused multiply-adds fix the rounding of every term, so the
+    // result does not depend on the vector width the tile picks.
+    auto fma_into = [](T a, const vt &b, vt &acc) { acc = __builtin_elementwise_fma(vt(a), b, acc); };
+    vt acc = A.diag[row] * xo;
+#pragma unroll
+    for (int e = 0; e < WT; ++e) fma_into(v0[e], xj[e], acc);
+    fma_into(A.w[row], plane_shift<T, V, 1>(xo, c0, lpr, k) + plane_shift<T, V, -1>(xo, c0, lpr, k), acc);
+    if constexpr (S2)
+        fma_into(A.w2[row], plane_shift<T, V, 2>(xo, c0, lpr, k) + plane_shift<T, V, -2>(xo, c0, lpr, k), acc);
+    if constexpr (E1) {
+#pragma unroll
+        for (int e = 0; e < WT; ++e)
+            fma_into(v1[e], plane_shift<T, V, 1>(xj[e], c0, lpr, k) + plane_shift<T, V, -1>(xj[e], c0, lpr, k), acc);
+    }
+    return acc;
+}
+
 // Launch arguments of a row-tiled kernel (lanes_per_row lanes per row,
 // tiles of rows_per_tile rows, tiles_per_block consecutive tiles per block).
 template <typename T>

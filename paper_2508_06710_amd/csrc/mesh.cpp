@@ -99,6 +99,10 @@ int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y
         m->n_cells = nc;
         m->grid_nx = nx;
         m->grid_ny = ny;
+        m->xf = xf;
+        m->yf = yf;
+        m->periodic_x = periodic_x != 0;
+        m->periodic_y = periodic_y != 0;
         m->area.resize(nc);
         m->cx.resize(nc);
         m->cy.resize(nc);

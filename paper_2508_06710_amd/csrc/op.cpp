@@ -18,13 +18,171 @@ struct HostOp {
     int64_t n_b = 0, F_b = 0, nnz_b = 0;
     int W = 0, Wd = 0;
     std::vector<double> diag, w, ell_val, area, cf_coef, f_invd;
+    std::vector<double> ell_v1, w2;  // structured 13/27-point operators only
     std::vector<int32_t> ell_col, cf_face, f_c1, f_c2;
     // FP32 copies: diagonal rebuilt in FP32 so that rows sum to zero up to
     // FP32 rounding of that sum.
     std::vector<float> diag32;
 };
 
+// One axis of a Cartesian base: cell centres and, when periodic, the period.
+struct Axis {
+    int n;
+    bool periodic;
+    std::vector<double> c;
+    double period;
+    Axis(const std::vector<double> &faces, bool per) : n(int(faces.size()) - 1), periodic(per) {
+        for (int i = 0; i < n; ++i) c.push_back(0.5 * (faces[i] + faces[i + 1]));
+        period = faces[n] - faces[0];
+    }
+    // index i + d on the axis (wrapped when periodic), or -1 past a wall
+    int at(int i, int d) const {
+        const int v = i + d;
+        if (periodic) return ((v % n) + n) % n;
+        return v >= 0 && v < n ? v : -1;
+    }
+    // distance from centre i forward to centre i + d (d >= 1, across the period if needed)
+    double ahead(int i, int d) const {
+        double s = 0.0;
+        for (int q = 0; q < d; ++q) {
+            const int u = (i + q) % n;
+            s += u + 1 < n ? c[u + 1] - c[u] : c[0] + period - c[u];
+        }
+        return s;
+    }
+    // Row i of the 1D element stiffness K and consistent mass M on the centres
+    // (linear elements between consecutive centres; node -> (K, M)).
+    std::map<int, std::pair<double, double>> km(int i) const {
+        std::map<int, std::pair<double, double>> r;
+        std::vector<int> elems;
+        if (periodic) {
+            elems.push_back(((i - 1) % n + n) % n);
+            if (elems[0] != i) elems.push_back(i);
+        } else {
+            if (i >= 1) elems.push_back(i - 1);
+            if (i + 1 < n) elems.push_back(i);
+        }
+        for (int e : elems) {
+            const int u = e, v = (e + 1) % n;
+            const double s = ahead(e, 1);
+            for (int side = 0; side < 2; ++side) {
+                const int me = side == 0 ? u : v, other = side == 0 ? v : u;
+                if (me != i) continue;
+                r[i].first += 1.0 / s;
+                r[other].first -= 1.0 / s;
+                r[i].second += s / 3.0;
+                r[other].second += s / 6.0;
+            }
+        }
+        return r;
+    }
+};
+
+// The structured 13- and 27-point operators (Section 4.1) on a Cartesian
+// base repeated in periodic planes: in-plane entries (shift 0 and, for 27,
+// planes l +- 1 of each neighbour), the row's own planes l +- 1 and (13)
+// l +- 2.  Neighbours that meet at one cell (short periodic axes) are merged;
+// a neighbour that is the row itself joins the diagonal.
+HostOp build_host_stencil(const fvx_mesh &m, const fvx_op_desc &d) {
+    HostOp h;
+    const int nx = m.grid_nx, ny = m.grid_ny;
+    const int64_t nb = int64_t(nx) * ny;
+    const double dz = d.dz;
+    h.n_b = nb;
+    h.F_b = m.n_faces;
+    const Axis ax(m.xf, m.periodic_x), ay(m.yf, m.periodic_y);
+    std::vector<std::map<int32_t, std::pair<double, double>>> nbr(nb);  // col -> (shift 0, planes +-1)
+    h.diag.assign(nb, 0.0);
+    h.w.assign(nb, 0.0);
+    h.w2.assign(nb, 0.0);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int32_t r = j * nx + i;
+            const double hx = m.xf[i + 1] - m.xf[i], hy = m.yf[j + 1] - m.yf[j];
+            if (d.stencil == 27) {
+                // planes: M = 2dz/3 (same plane), dz/6 (l +- 1); K = 2/dz, -1/dz
+                const double mz0 = 2.0 * dz / 3.0, mz1 = dz / 6.0, kz0 = 2.0 / dz, kz1 = -1.0 / dz;
+                for (const auto &X : ax.km(i))
+                    for (const auto &Y : ay.km(j)) {
+                        const double kx = X.second.first, mx = X.second.second;
+                        const double ky = Y.second.first, my = Y.second.second;
+                        const double v0 = -(kx * my * mz0 + mx * ky * mz0 + mx * my * kz0);
+                        const double v1 = -(kx * my * mz1 + mx * ky * mz1 + mx * my * kz1);
+                        const int32_t c = Y.first * nx + X.first;
+                        if (c == r) {
+                            h.diag[r] += v0;
+                            h.w[r] += v1;
+                        } else {
+                            nbr[r][c].first += v0;
+                            nbr[r][c].second += v1;
+                        }
+                    }
+            } else {
+                double off = 0.0;
+                for (int dd = 1; dd <= 2; ++dd) {
+                    const double wt = dd == 1 ? 4.0 / 3.0 : -1.0 / 6.0;
+                    for (int sgn : {-1, 1}) {
+                        const int I = ax.at(i, sgn * dd), J = ay.at(j, sgn * dd);
+                        if (I >= 0) {
+                            const double dist = sgn > 0 ? ax.ahead(i, dd) : ax.ahead(I, dd);
+                            const double cf = wt * hy * dz / dist;
+                            const int32_t c = j * nx + I;
+                            off += cf;
+                            if (c == r)
+                                h.diag[r] += cf;
+                            else
+                                nbr[r][c].first += cf;
+                        }
+                        if (J >= 0) {
+                            const double dist = sgn > 0 ? ay.ahead(j, dd) : ay.ahead(J, dd);
+                            const double cf = wt * hx * dz / dist;
+                            const int32_t c = J * nx + i;
+                            off += cf;
+                            if (c == r)
+                                h.diag[r] += cf;
+                            else
+                                nbr[r][c].first += cf;
+                        }
+                    }
+                }
+                const double area = hx * hy;
+                h.w[r] = (4.0 / 3.0) * area / dz;
+                h.w2[r] = -(1.0 / 6.0) * area / (2.0 * dz);
+                h.diag[r] -= off + 2.0 * h.w[r] + 2.0 * h.w2[r];
+            }
+        }
+    h.W = 8;  // the 8 in-plane neighbours (fewer on short periodic axes, padded)
+    for (int64_t i = 0; i < nb; ++i) FVX_REQUIRE(nbr[i].size() <= 8, FVX_E_MESH, "structured stencil row too wide");
+    h.ell_col.assign(size_t(h.W) * nb, 0);
+    h.ell_val.assign(size_t(h.W) * nb, 0.0);
+    if (d.stencil == 27) h.ell_v1.assign(size_t(h.W) * nb, 0.0);
+    if (d.stencil != 13) h.w2.clear();
+    h.nnz_b = nb;
+    for (int64_t i = 0; i < nb; ++i) {
+        int e = 0;
+        for (const auto &kv : nbr[i]) {
+            h.ell_col[size_t(e) * nb + i] = kv.first;
+            h.ell_val[size_t(e) * nb + i] = kv.second.first;
+            if (!h.ell_v1.empty()) h.ell_v1[size_t(e) * nb + i] = kv.second.second;
+            ++e;
+        }
+        h.nnz_b += e;
+        for (; e < h.W; ++e) h.ell_col[size_t(e) * nb + i] = int32_t(i);  // padding: self, value 0
+    }
+    h.diag32.assign(nb, 0.0f);
+    for (int64_t i = 0; i < nb; ++i) h.diag32[i] = float(h.diag[i]);
+    return h;
+}
+
+// The divergence and gradient data of the face graph (all operators).
+void build_div_grad(const fvx_mesh &m, const fvx_op_desc &d, HostOp &h);
+
 HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
+    if (d.stencil == 13 || d.stencil == 27) {
+        HostOp h = build_host_stencil(m, d);
+        build_div_grad(m, d, h);
+        return h;
+    }
     HostOp h;
     const int64_t nb = m.n_cells;
     h.n_b = nb;
@@ -87,7 +245,13 @@ HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
         }
         h.diag32[i] = -s32 + float(wall[i]);
     }
+    build_div_grad(m, d, h);
+    return h;
+}
 
+void build_div_grad(const fvx_mesh &m, const fvx_op_desc &d, HostOp &h) {
+    const int64_t nb = m.n_cells;
+    const double dz = d.dz;
     // Divergence: cell -> face incidence.
     std::vector<std::vector<std::pair<int32_t, double>>> inc(nb);
     for (int f = 0; f < m.n_faces; ++f) {
@@ -112,7 +276,6 @@ HostOp build_host(const fvx_mesh &m, const fvx_op_desc &d) {
     h.f_c2 = m.c2;
     h.f_invd.resize(m.n_faces);
     for (int f = 0; f < m.n_faces; ++f) h.f_invd[f] = 1.0 / m.dist[f];
-    return h;
 }
 
 // Byte layout of the device image; every array starts on a 256-byte boundary.
@@ -127,7 +290,7 @@ struct Layout {
 
 struct Offsets {
     size_t ell_col, cf_face, f_c1, f_c2;
-    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2];
+    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2];
     size_t total;
 };
 
@@ -147,6 +310,8 @@ Offsets layout(const HostOp &h, bool f32) {
         o.cf_coef[p] = L.take(v * h.Wd * nb);
         o.area[p] = L.take(v * nb);
         o.f_invd[p] = L.take(v * fb);
+        o.ell_v1[p] = L.take(v * h.ell_v1.size());
+        o.w2[p] = L.take(v * h.w2.size());
     }
     o.total = L.off;
     return o;
@@ -161,6 +326,15 @@ void check_desc(const fvx_mesh *m, const fvx_op_desc *d) {
     FVX_REQUIRE(d->wall_bc == FVX_WALL_NEUMANN || d->wall_bc == FVX_WALL_DIRICHLET, FVX_E_ARG,
                 "unknown wall_bc");
     FVX_REQUIRE(m->n_cells < (1 << 30) && m->n_faces < (1 << 30), FVX_E_ARG, "mesh too large for int32 indices");
+    FVX_REQUIRE(d->stencil == 0 || d->stencil == 7 || d->stencil == 13 || d->stencil == 27, FVX_E_ARG,
+                "stencil must be 0, 7, 13 or 27");
+    if (d->stencil == 13 || d->stencil == 27) {
+        FVX_REQUIRE(m->grid_nx > 0 && m->grid_ny > 0, FVX_E_ARG, "13/27-point operators need a Cartesian base mesh");
+        FVX_REQUIRE(d->coupling == FVX_COUPLING_PERIODIC_Z, FVX_E_ARG, "13/27-point operators need PERIODIC_Z");
+        FVX_REQUIRE(d->wall_bc == FVX_WALL_NEUMANN, FVX_E_ARG, "13/27-point operators have zero-flux walls");
+        FVX_REQUIRE(d->k <= 64 || (d->k <= 128 && d->k % 2 == 0), FVX_E_UNSUPPORTED,
+                    "13/27-point operators support k <= 64, or even k <= 128 (one pass of a row group)");
+    }
 }
 
 template <typename T>
@@ -175,7 +349,7 @@ fvx_tile default_tile(const fvx_op *op, int dtype) {
     const int vmax = dtype == FVX_F32 ? 4 : 2;
     int v = 1;
     for (int c = vmax; c >= 1; c >>= 1)
-        if (op->ld % c == 0) {
+        if (op->ld % c == 0 && (op->stencil == 7 || op->k % c == 0)) {
             v = c;
             break;
         }
@@ -205,6 +379,11 @@ void check_tile(const fvx_op *op, int dtype, const fvx_tile &t) {
     FVX_REQUIRE(!t.stage_lds || t.block / t.lanes_per_row <= kMaxStageRows, FVX_E_ARG,
                 "tile.stage_lds needs at most 64 rows per tile");
     FVX_REQUIRE(t.nt_store == 0 || t.nt_store == 1, FVX_E_ARG, "tile.nt_store must be 0 or 1");
+    if (op->stencil != 7) {
+        FVX_REQUIRE(t.lanes_per_row * t.vec >= op->k && op->k % t.vec == 0, FVX_E_ARG,
+                    "13/27-point operators need one pass of a row group over k, vec dividing k");
+        FVX_REQUIRE(!t.stage_lds, FVX_E_ARG, "13/27-point operators do not stage rows in LDS");
+    }
 }
 
 RowGrid row_grid(int64_t n_rows, const fvx_tile &t, int max_blocks) {
@@ -224,7 +403,9 @@ void expand_csr(const fvx_mesh &m, const fvx_op_desc &d, std::vector<int32_t> &p
     const HostOp h = build_host(m, d);
     const int64_t nb = h.n_b, N = nb * int64_t(d.k);
     FVX_REQUIRE(N < (int64_t(1) << 31), FVX_E_ARG, "expanded matrix too large for int32 indices");
-    const bool zf = d.coupling == FVX_COUPLING_PERIODIC_Z && d.k >= 2;
+    const bool structured = d.stencil == 13 || d.stencil == 27;
+    const bool zf = (d.coupling == FVX_COUPLING_PERIODIC_Z && d.k >= 2) || structured;
+    auto plane = [&](int l, int s) { return int64_t(((l + s) % d.k + d.k) % d.k) * nb; };
     ptr.assign(size_t(N) + 1, 0);
     col.clear();
     val.clear();
@@ -238,11 +419,13 @@ void expand_csr(const fvx_mesh &m, const fvx_op_desc &d, std::vector<int32_t> &p
                 const int32_t j = h.ell_col[size_t(e) * nb + i];
                 if (j == i) continue;  // padding
                 row.push_back({int32_t(off + j), h.ell_val[size_t(e) * nb + i]});
+                if (!h.ell_v1.empty())
+                    for (int sgn : {1, -1}) row.push_back({int32_t(plane(l, sgn) + j), h.ell_v1[size_t(e) * nb + i]});
             }
-            if (zf) {
-                row.push_back({int32_t(((l + 1) % d.k) * nb + i), h.w[i]});
-                row.push_back({int32_t(((l - 1 + d.k) % d.k) * nb + i), h.w[i]});
-            }
+            if (zf)
+                for (int sgn : {1, -1}) row.push_back({int32_t(plane(l, sgn) + i), h.w[i]});
+            if (!h.w2.empty())
+                for (int sgn : {2, -2}) row.push_back({int32_t(plane(l, sgn) + i), h.w2[i]});
             std::sort(row.begin(), row.end(), [](auto &a, auto &b) { return a.first < b.first; });
             for (size_t e = 0; e < row.size(); ++e) {
                 if (!col.empty() && int64_t(col.size()) > ptr[off + i] && col.back() == row[e].first)
@@ -302,8 +485,14 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         put(o.cf_coef[0], h.cf_coef.data(), 8 * h.cf_coef.size());
         put(o.area[0], h.area.data(), 8 * nb);
         put(o.f_invd[0], h.f_invd.data(), 8 * fb);
-        std::vector<float> ev32, w32, cf32, ar32, fi32;
+        put(o.ell_v1[0], h.ell_v1.data(), 8 * h.ell_v1.size());
+        put(o.w2[0], h.w2.data(), 8 * h.w2.size());
+        std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232;
         if (f32) {
+            v132 = fvx::cast<float>(h.ell_v1);
+            w232 = fvx::cast<float>(h.w2);
+            put(o.ell_v1[1], v132.data(), 4 * v132.size());
+            put(o.w2[1], w232.data(), 4 * w232.size());
             ev32 = fvx::cast<float>(h.ell_val);
             w32 = fvx::cast<float>(h.w);
             cf32 = fvx::cast<float>(h.cf_coef);
@@ -334,6 +523,7 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         op->has_f32 = f32;
         op->grid_nx = m->grid_nx;
         op->grid_ny = m->grid_ny;
+        op->stencil = (d->stencil == 13 || d->stencil == 27) ? d->stencil : 7;
         FVX_HIP(hipGetDevice(&op->device));
         auto fill = [&](auto &D, int p, auto tag) {
             using T = decltype(tag);
@@ -348,6 +538,8 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             D.f_c2 = reinterpret_cast<const int32_t *>(base + o.f_c2);
             D.f_invd = reinterpret_cast<const T *>(base + o.f_invd[p]);
             D.inv_dz = T(1.0 / d->dz);
+            D.ell_v1 = h.ell_v1.empty() ? nullptr : reinterpret_cast<const T *>(base + o.ell_v1[p]);
+            D.w2 = h.w2.empty() ? nullptr : reinterpret_cast<const T *>(base + o.w2[p]);
         };
         fill(op->d64, 0, double{});
         if (f32) fill(op->d32, 1, float{});

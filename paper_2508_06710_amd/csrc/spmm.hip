@@ -108,6 +108,25 @@ __global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__res
     }
 }
 
+// Y = A X for the structured 13/27-point operators (ELL width 8, one pass of
+// a row group covers all k columns).
+template <typename T, int V, bool E1, bool S2, bool NT>
+__global__ __launch_bounds__(1024) void k_lap_stencil(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int c0 = sub * V;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        if (c0 < a.k) {
+            const vec_t<T, V> acc = stencil_row<T, V, 8, E1, S2>(a.A, X, a.n_b, a.k, a.ld, row, c0, lpr);
+            stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
+        }
+    }
+}
+
 // D = M U: integrated divergence of in-plane face fluxes plus the fluxes
 // through the faces between planes.
 template <typename T, int V, bool Z, int WT>
@@ -243,7 +262,37 @@ void check_dtype(const fvx_op *op, int dtype) {
 }  // namespace
 
 template <typename T>
+void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_t s) {
+    FVX_REQUIRE(cs == nullptr, FVX_E_ARG, "colscale applies to independent planes only");
+    RowGrid g;
+    const fvx_tile &t = op->tile[dtype_of<T>()];
+    FVX_REQUIRE(t.lanes_per_row * t.vec >= op->k && op->k % t.vec == 0, FVX_E_ARG,
+                "13/27-point operators need a tile whose row group covers k in one pass, vec dividing k");
+    auto a = row_args<T>(op, op->n_b, g, t);
+    by_vec<T>(t.vec, true, [&](auto V, auto) {
+        constexpr int v = decltype(V)::value;
+        auto go = [&](auto E1t, auto S2t) {
+            constexpr bool e1 = decltype(E1t)::value, s2 = decltype(S2t)::value;
+            if (t.nt_store)
+                hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, true>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y);
+            else
+                hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X,
+                                   Y);
+        };
+        if (op->stencil == 27)
+            go(std::true_type{}, std::false_type{});
+        else
+            go(std::false_type{}, std::true_type{});
+    });
+    FVX_HIP(hipGetLastError());
+}
+
+template <typename T>
 void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_t s) {
+    if (op->stencil != 7) {
+        launch_lap_stencil<T>(op, X, Y, cs, s);
+        return;
+    }
     RowGrid g;
     const fvx_tile &t = op->tile[dtype_of<T>()];
     auto a = row_args<T>(op, op->n_b, g, t);

@@ -18,8 +18,11 @@ std::vector<fvx_tile> shape_candidates(const fvx_op *op, int dtype) {
     const int vmax = dtype == FVX_F32 ? 4 : 2;
     for (int vec = vmax; vec >= 1; vec >>= 1) {
         if (op->ld % vec) continue;
+        if (op->stencil != 7 && op->k % vec) continue;
         const int base = std::min(64, next_pow2(int(ceil_div(op->k, vec))));
-        for (int lpr = base; lpr >= 1 && lpr >= base / 4; lpr >>= 1)
+        if (op->stencil != 7 && base * vec < op->k) continue;
+        const int lowest = op->stencil != 7 ? base : base / 4;  // structured: one pass only
+        for (int lpr = base; lpr >= 1 && lpr >= lowest; lpr >>= 1)
             for (int block : {64, 128, 256, 512}) {
                 if (block < lpr) continue;
                 out.push_back(fvx_tile{vec, lpr, block, 1, 0, 0, 0});
@@ -30,12 +33,12 @@ std::vector<fvx_tile> shape_candidates(const fvx_op *op, int dtype) {
 
 // Stage 2: the launch options (grid cap, XCD remap, LDS staging of the row
 // metadata, non-temporal stores) around the best row mapping.
-std::vector<fvx_tile> option_candidates(const fvx_tile &b) {
+std::vector<fvx_tile> option_candidates(const fvx_op *op, const fvx_tile &b) {
     std::vector<fvx_tile> out;
     for (int cap : {0, 2048})
         for (int remap : {1, 0})
             for (int stage : {0, 1}) {
-                if (stage && b.block / b.lanes_per_row > kMaxStageRows) continue;
+                if (stage && (b.block / b.lanes_per_row > kMaxStageRows || op->stencil != 7)) continue;
                 for (int nt : {0, 1}) {
                     if (cap == 0 && remap == 1 && stage == 0 && nt == 0) continue;  // timed in stage 1
                     out.push_back(fvx_tile{b.vec, b.lanes_per_row, b.block, remap, cap, stage, nt});
@@ -105,7 +108,7 @@ extern "C" int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_byt
         };
         try {
             try_all(fvx::shape_candidates(op, dtype));
-            try_all(fvx::option_candidates(best));
+            try_all(fvx::option_candidates(op, best));
         } catch (...) {
             op->tile[dtype] = keep;
             hipEventDestroy(e0);

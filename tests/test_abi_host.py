@@ -128,3 +128,36 @@ def test_one_hip_runtime_whatever_the_import_order():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+
+@pytest.mark.parametrize("stencil", [13, 27])
+@pytest.mark.parametrize("spec", [inputs.channel_base(7, 9), inputs.convection_base(6, 5),
+                                  inputs.CartSpec(3, 4, 2.0, 0.0, 1.5, 0.0, True, True),
+                                  inputs.CartSpec(1, 2, 1.0, 0.0, 1.0, 0.0, True, True)])
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_structured_stencil_expansion_matches_oracle(fvx, orc, stencil, spec, k):
+    """The builder's 13/27-point base blocks (in-plane entries, coefficients of
+    the neighbouring planes), expanded over k planes, equal the oracle's
+    assembly; short periodic axes merge neighbours like the oracle does."""
+    dz = 0.61
+    m = fvx.Mesh.from_spec(spec)
+    ptr, col, val = fvx.expand_csr(m, k, dz, fvx.PERIODIC_Z, fvx.NEUMANN, stencil=stencil)
+    import scipy.sparse as sp
+    n = spec.nx * spec.ny * k
+    A = sp.csr_matrix((val, col, ptr), shape=(n, n)).toarray()
+    B = orc.stencil_lap(spec, k, dz, stencil).toarray()
+    assert np.max(np.abs(A - B)) <= 4e-15 * np.max(np.abs(B))
+
+
+def test_structured_stencil_rejections(fvx):
+    tri = fvx.Mesh.from_spec(inputs.unit_square_triangles(3))
+    cart = fvx.Mesh.from_spec(inputs.channel_base(4, 4))
+    for mesh, kw in ((tri, {}), (cart, {"coupling": fvx.NONE}), (cart, {"wall_bc": fvx.DIRICHLET}),
+                     (cart, {"k": 200})):
+        args = dict(k=4, dz=0.5, coupling=fvx.PERIODIC_Z, wall_bc=fvx.NEUMANN)
+        args.update(kw)
+        with pytest.raises(fvx.FvxError):
+            fvx.expand_csr(mesh, args["k"], args["dz"], args["coupling"], args["wall_bc"], stencil=27)
+    with pytest.raises(fvx.FvxError):
+        fvx.expand_csr(cart, 4, 0.5, stencil=9)

@@ -1,0 +1,179 @@
+"""Parity of the structured 13- and 27-point SpMMs (the higher-order stencils
+of Section 4.1: 13-point fourth-order differences, 27-point trilinear
+elements) with the oracle's assembled 3D matrices, element by element, in
+FP64 and FP32, over ragged row counts, every supported k class and every
+single-pass tile; plus the argument checks of these operators."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from helpers import componentwise, fp32_bound_factor
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+STENCILS = (13, 27)
+
+
+def _box(nx, ny):
+    return inputs.CartSpec(nx, ny, 2 * math.pi, 0.0, 2 * math.pi, 0.0, True, True)
+
+
+SPECS = {
+    "channel7x9": inputs.channel_base(7, 9),
+    "convection6x5": inputs.convection_base(6, 5),
+    "box3x4": _box(3, 4),
+    "box2x2": _box(2, 2),
+    "box1x2": _box(1, 2),
+    "channel37x29": inputs.channel_base(37, 29),  # 1073 rows: several tiles and a ragged tail
+}
+
+
+def _op(spec, k, stencil, dz=None):
+    import paper_2508_06710_amd as fvx
+    dz = dz if dz is not None else 2 * math.pi / k
+    op = fvx.Operator(fvx.Mesh.from_spec(spec), k, dz, fvx.PERIODIC_Z, fvx.NEUMANN, with_f32=True,
+                      stencil=stencil)
+    return fvx, op, oracle.stencil_lap(spec, k, dz, stencil)
+
+
+def _lap64(op, x):
+    return op.to_planes(op.lap(op.to_rows(x)))
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("name", list(SPECS))
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6, 8])
+def test_stencil_f64_small_k(stencil, name, k):
+    spec = SPECS[name]
+    fvx, op, A = _op(spec, k, stencil)
+    x = inputs.uniform(40, k, op.n_b * k)
+    assert componentwise(_lap64(op, x), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("k", [5, 16, 33, 64, 66, 128])
+def test_stencil_f64_wide_k(stencil, k):
+    spec = SPECS["channel37x29"]
+    fvx, op, A = _op(spec, k, stencil, dz=0.05)
+    x = inputs.uniform(41, k, op.n_b * k)
+    assert componentwise(_lap64(op, x), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("k", [6, 8, 16, 64, 128])
+def test_stencil_f32_within_rounding_bound(stencil, k):
+    """FP32 coefficients and arithmetic: within (2n + 3) u of |A||x| per row.
+    Planes and axes are long enough (k >= 5, 37 x 29 cells) that no two
+    stencil entries fall on the same cell, so |A| is the entry-wise bound of
+    what the kernel sums."""
+    spec = SPECS["channel37x29"]
+    fvx, op, A = _op(spec, k, stencil, dz=0.05)
+    x = inputs.uniform(42, k, op.n_b * k).astype(np.float32).astype(np.float64)
+    y = op.to_planes(op.lap(op.to_rows(x, dtype=fvx.F32)), dtype=fvx.F32).astype(np.float64)
+    bound = abs(A) @ np.abs(x)
+    assert np.all(np.abs(y - oracle.spmv(A, x)) <= fp32_bound_factor(A) * bound + 1e-30)
+
+
+def _single_pass_tiles(fvx, op, dtype):
+    vmax = 4 if dtype == fvx.F32 else 2
+    for vec in (1, 2, 4):
+        if vec > vmax or op.k % vec or op.ld % vec:
+            continue
+        need = 1 << max(0, math.ceil(math.log2(op.k / vec)))
+        for lpr in sorted({need, min(64, 2 * need)}):
+            if lpr * vec < op.k or lpr > 64:
+                continue
+            for block in (64, 256, 1024):
+                for remap in (0, 1):
+                    for cap in (0, 7):
+                        for nt in (0, 1):
+                            yield vec, lpr, block, remap, cap, nt
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("k", [4, 12, 64])
+def test_every_single_pass_tile_gives_the_same_product(stencil, k):
+    """Each output element sums the same terms in the same order whatever
+    the tile, so every tile's product is bit-identical."""
+    spec = SPECS["channel37x29"]
+    fvx, op, A = _op(spec, k, stencil, dz=0.1)
+    x = inputs.uniform(43, k, op.n_b * k)
+    for dtype in (fvx.F64, fvx.F32):
+        X = op.to_rows(x, dtype=dtype)
+        ref = None
+        n = 0
+        for vec, lpr, block, remap, cap, nt in _single_pass_tiles(fvx, op, dtype):
+            op.set_tile(vec, lpr, block, remap, cap, 0, nt, dtype=dtype)
+            y = op.to_planes(op.lap(X), dtype=dtype)
+            if ref is None:
+                ref = y
+            assert np.array_equal(y, ref), (dtype, vec, lpr, block, remap, cap, nt)
+            n += 1
+        assert n >= 12
+        if dtype == fvx.F64:
+            assert componentwise(ref.astype(np.float64), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+def test_tuner_picks_a_single_pass_tile(stencil):
+    spec = SPECS["channel37x29"]
+    fvx, op, A = _op(spec, 64, stencil, dz=0.1)
+    for dtype in (fvx.F64, fvx.F32):
+        op.tune(dtype, scratch_bytes=32 << 20, reps=1)
+        vec, lpr, _, _, _, stage, _ = op.get_tile(dtype)
+        assert lpr * vec >= op.k and op.k % vec == 0 and stage == 0
+    x = inputs.uniform(44, 0, op.n_b * op.k)
+    assert componentwise(_lap64(op, x), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+def test_lap_many_matches_single_products(stencil):
+    fvx, op, A = _op(SPECS["channel7x9"], 8, stencil)
+    xs = [inputs.uniform(45, i, op.n_b * 8) for i in range(3)]
+    Xs = [op.to_rows(x) for x in xs]
+    Ys = [op.zeros() for _ in xs]
+    op.lap_many(Xs, Ys)
+    for x, Y in zip(xs, Ys):
+        assert componentwise(op.to_planes(Y), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+def test_div_and_grad_are_the_face_graph_operators(stencil):
+    """The structured operators change the Laplacian only; divergence and
+    gradient stay the face-graph M and G of the same base mesh."""
+    spec = SPECS["channel7x9"]
+    k = 6
+    fvx, op, _ = _op(spec, k, stencil)
+    m3 = oracle.Mesh3D(oracle.geometry(spec), k, 2 * math.pi / k, oracle.PERIODIC_Z)
+    M, G = m3.div(), m3.grad()
+    u = inputs.normal(46, 0, m3.F3)
+    kF = k * m3.g.n_faces
+    D = op.to_planes(op.div(op.to_rows(u[:kF], rows=op.F_b), op.to_rows(u[kF:])))
+    assert componentwise(D, oracle.spmv(M, u), M, u) <= TOL64
+    x = inputs.uniform(46, 1, op.n_b * k)
+    Gf, Gz = op.grad(op.to_rows(x))
+    g = np.concatenate([op.to_planes(Gf, rows=op.F_b), op.to_planes(Gz)])
+    assert componentwise(g, oracle.spmv(G, x), G, x) <= TOL64
+
+
+def test_structured_operator_argument_checks():
+    fvx, op, _ = _op(SPECS["channel7x9"], 12, 27)
+    with pytest.raises(fvx.FvxError):
+        op.set_tile(1, 4, 256, 1, dtype=fvx.F64)  # 4 lanes x 1 column < 12 planes: two passes
+    with pytest.raises(fvx.FvxError):
+        op.set_tile(2, 8, 256, 1, 0, 1, dtype=fvx.F64)  # no LDS staging
+    _, op6, _ = _op(SPECS["channel7x9"], 6, 13)
+    with pytest.raises(fvx.FvxError):
+        op6.set_tile(4, 2, 256, 1, dtype=fvx.F32)  # 4 does not divide 6 planes (or ld)
+    X = op.to_rows(inputs.uniform(47, 0, op.n_b * 12))
+    import torch
+    cs = torch.ones(12, dtype=torch.float64, device=X.device)
+    with pytest.raises(fvx.FvxError):
+        op.lap(X, colscale=cs)
+    with pytest.raises(fvx.FvxError) as e:
+        op.solve(X, rtol=1e-8)
+    assert e.value.code == fvx._lib.E_UNSUPPORTED
