@@ -76,6 +76,15 @@ def spmm_flops(nnz_b, n_b, k):
     return 2 * nnz_b * k + 3 * n_b * k
 
 
+def stencil_bytes(n_b, k, stencil, v=8):
+    """Algorithmic bytes of one structured 13/27-point SpMM: the 8 in-plane
+    entries per base row (values and int32 columns), the 27-point's second
+    value per entry (planes l+-1), the diagonal, the plane weight w, the
+    13-point's w2 (planes l+-2), X read once and Y written once."""
+    vals = 8 * (2 if stencil == 27 else 1) + 2 + (1 if stencil == 13 else 0)
+    return 32 * n_b + v * vals * n_b + 2 * v * n_b * k
+
+
 def csr3d_bytes(nnz3, n3, v=8):
     return (v + 4) * nnz3 + 4 * (n3 + 1) + 2 * v * n3
 
@@ -277,6 +286,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-airfoil", action="store_true")
     ap.add_argument("--no-guess", action="store_true")
+    ap.add_argument("--no-stencil", action="store_true")
+    ap.add_argument("--profile-stencil", action="store_true")
     ap.add_argument("--guess-epochs", type=int, default=20)
     ap.add_argument("--guess-lr", type=float, default=1e-4)
     args = ap.parse_args()
@@ -302,9 +313,12 @@ def main():
     if args.profile_mixed:
         mixed_profile_mode(fvx, inputs, torch)
         return
+    if args.profile_stencil:
+        stencil_profile_mode(fvx, inputs, torch)
+        return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
-        args.no_batch = args.no_airfoil = args.no_guess = True
+        args.no_batch = args.no_airfoil = args.no_guess = args.no_stencil = True
 
     rtol = 1e-8
     log("building the channel operator")
@@ -404,6 +418,9 @@ def main():
         if out.get("copy_ceiling_GBs"):
             out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GBs"]
 
+    if not args.no_stencil:
+        out["stencils"] = stencil_leg(fvx, inputs, torch, np)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
         torch.cuda.empty_cache()
@@ -453,31 +470,7 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
         del X, Y
         Bk, Fk = spmm_bytes(opk.nnz_b, opk.n_b, k), spmm_flops(opk.nnz_b, opk.n_b, k)
         ptr, col, val = fvx.expand_csr(mesh, k, math.pi / k, fvx.PERIODIC_Z)
-        A = fvx.CsrMatrix(ptr, col, val)
-        per = 2 * Nk * 8
-        R = max(2, math.ceil(COLD_BYTES / per))
-        xs = [torch.as_tensor(inputs.uniform(0, 0, Nk)).cuda() for _ in range(min(R, 4))]
-        xs = [xs[i % len(xs)].clone() for i in range(R)]
-        ys = [torch.empty_like(xs[0]) for _ in range(R)]
-        # The comparator's sweep is captured once in a HIP graph so that its
-        # launches are not paced by the Python loop.
-        A.spmv(xs[0], ys[0])
-        graph = torch.cuda.CUDAGraph()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            with torch.cuda.graph(graph):
-                for xx, yy in zip(xs, ys):
-                    A.spmv(xx, yy)
-        torch.cuda.current_stream().wait_stream(side)
-        graph.replay()
-        tm = Timer(torch)
-        with tm:
-            graph.replay()
-            graph.replay()
-        t3 = tm.ms() / (2 * R)
-        del graph
-        del xs, ys, A
+        t3 = time_csr_spmv(fvx, torch, inputs, ptr, col, val, Nk)
         if k == 1:
             t1 = tk
         rec = {"k": k, "tile": list(tile_k), "spmm_us": tk * 1e3, "spmm_GBs": Bk / (tk * 1e-3) / 1e9,
@@ -513,6 +506,105 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
                        "relres_true": stm["relres_true"]}
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
+
+
+def time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3):
+    """Mean time of the assembled 3D CSR SpMV over rotating vectors, its
+    sweep captured once in a HIP graph so that the launches are not paced by
+    the Python loop."""
+    A = fvx.CsrMatrix(ptr, col, val)
+    per = 2 * n3 * 8
+    R = max(2, math.ceil(COLD_BYTES / per))
+    xs = [torch.as_tensor(inputs.uniform(0, 0, n3)).cuda() for _ in range(min(R, 4))]
+    xs = [xs[i % len(xs)].clone() for i in range(R)]
+    ys = [torch.empty_like(xs[0]) for _ in range(R)]
+    A.spmv(xs[0], ys[0])
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph):
+            for xx, yy in zip(xs, ys):
+                A.spmv(xx, yy)
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    tm = Timer(torch)
+    with tm:
+        graph.replay()
+        graph.replay()
+    t = tm.ms() / (2 * R)
+    del graph, xs, ys, A
+    return t
+
+
+def stencil_leg(fvx, inputs, torch, np):
+    """The 7-, 13- and 27-point operators (first neighbours; first and second
+    neighbours; all 26 neighbours) on the channel base at several plane
+    counts: SpMM bandwidth against the HBM roofline with tuned tiles, beside
+    the assembled 3D CSR SpMV of the same matrix.  The bytes ratio is the
+    speed-up the repeated-block format allows over the assembled matrix when
+    both run at the same bandwidth."""
+    spec = inputs.channel_base(*BASE)
+    mesh = fvx.Mesh.from_spec(spec)
+    out = []
+    for k in (16, 64):
+        dz = math.pi / k
+        for stencil in (7, 13, 27):
+            op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=True, stencil=stencil)
+            ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z, stencil=stencil)
+            n3, nnz3 = op.n_b * k, len(col)
+            t3 = time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3)
+            del ptr, col, val
+            for dt, name, v in ((fvx.F64, "f64", 8), (fvx.F32, "f32", 4)):
+                tile = tune(op, fvx, dt)
+                x = op.to_rows(inputs.uniform(0, 0, n3), dtype=dt)
+                R = max(3, math.ceil(COLD_BYTES / (2 * op.n_b * op.ld * v)))
+                X = [x.clone() for _ in range(R)]
+                Y = [torch.empty_like(x) for _ in range(R)]
+                lap_sweep(op, X[:2], Y[:2], torch)
+                t = lap_sweep(op, X, Y, torch, reps=2)
+                del X, Y, x
+                Bk = spmm_bytes(op.nnz_b, op.n_b, k, v) if stencil == 7 else stencil_bytes(op.n_b, k, stencil, v)
+                rec = {"stencil": stencil, "k": k, "dtype": name, "tile": list(tile), "nnz_per_row_3d": nnz3 / n3,
+                       "bytes_per_launch": Bk, "spmm_us": t * 1e3, "spmm_GBs": Bk / (t * 1e-3) / 1e9,
+                       "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "tflops_2nnz": 2 * nnz3 / (t * 1e-3) / 1e12}
+                if dt == fvx.F64:
+                    rec.update({"csr3d_us": t3 * 1e3, "speedup_vs_csr3d": t3 / t,
+                                "bytes_ratio_csr3d": csr3d_bytes(nnz3, n3) / Bk})
+                out.append(rec)
+                log(f"stencil {stencil} k={k} {name}: {rec['spmm_GBs']:.0f} GB/s "
+                    f"({100 * rec['frac_hbm']:.0f}% of 8 TB/s)"
+                    + (f", {rec['speedup_vs_csr3d']:.2f}x the 3D CSR SpMV" if dt == fvx.F64 else ""))
+            del op
+            torch.cuda.empty_cache()
+    return out
+
+
+def stencil_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 of the 13- and 27-point SpMMs on the channel
+    base with 64 planes: 8 cold FP64 launches of each (tuned tiles), then 8
+    copies of a known size (the calibration of FETCH_SIZE / WRITE_SIZE)."""
+    spec = inputs.channel_base(*BASE)
+    mesh = fvx.Mesh.from_spec(spec)
+    for stencil in (13, 27):
+        op = fvx.Operator(mesh, K_MAIN, math.pi / K_MAIN, fvx.PERIODIC_Z, with_f32=False, stencil=stencil)
+        tune(op, fvx)
+        x = op.to_rows(inputs.uniform(0, 0, op.n_b * op.k))
+        X, Y = rotating_sets(op, fvx, torch, x)
+        for i in range(8):
+            op.lap(X[i], Y[i])
+        torch.cuda.synchronize()
+        log(f"stencil {stencil}: bytes/launch {stencil_bytes(op.n_b, op.k, stencil)}")
+        del X, Y, op
+        torch.cuda.empty_cache()
+    nbytes = 256 * 2 ** 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = [torch.empty_like(src) for _ in range(2)]
+    for i in range(8):
+        fvx.copy(dst[i % 2], src)
+    torch.cuda.synchronize()
+    log("stencil profile run done")
 
 
 def large_sweep(fvx, inputs, torch, np):

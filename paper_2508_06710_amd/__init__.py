@@ -296,12 +296,13 @@ class Operator:
 
     def tune_cached(self, dtype=F64, cache_path=None, scratch_bytes=int(1.1 * 2 ** 30), reps=2):
         """Autotuned tile, cached in a JSON file keyed by (device architecture,
-        precision, k, ld, base rows, ELL width class).  Returns (tile, source)."""
+        precision, k, ld, base rows, base nonzeros, stencil).  Returns (tile, source)."""
         import json
         import os
         torch = _torch()
         arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
-        key = f"{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}|nnz_b={self.nnz_b}"
+        key = (f"{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}|nnz_b={self.nnz_b}"
+               f"|stencil={self.stencil}")
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as fh:

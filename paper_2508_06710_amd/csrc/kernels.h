@@ -288,41 +288,149 @@ __device__ __forceinline__ vec_t<T, V> plane_shift(const vec_t<T, V> &xo, int c0
     return out;
 }
 
+// Row metadata load; UNI: the row is the same for the whole wavefront, so the
+// load goes through the constant address space (a scalar load into SGPRs).
+template <bool UNI, typename T>
+__device__ __forceinline__ T ld_meta(const T *p, int64_t i) {
+    if constexpr (UNI) {
+        typedef const __attribute__((address_space(4))) T *cptr;
+        return ((cptr)p)[i];
+    } else {
+        return p[i];
+    }
+}
+
+// Everything one row of a structured operator reads: its metadata and the
+// V columns of this lane in the row itself and its 8 in-plane neighbours.
+template <typename T, int V, bool E1, bool S2>
+struct StencilRow {
+    T v0[8], v1[E1 ? 8 : 1];
+    T dg, w1, w2;
+    vec_t<T, V> xo, xj[8];
+};
+
+template <typename T, int V, bool E1, bool S2, bool UNI>
+__device__ __forceinline__ void stencil_load(StencilRow<T, V, E1, S2> &r, const OpDev<T> &A,
+                                             const T *__restrict__ X, int64_t n_b, int ld, int64_t row, int c0,
+                                             bool active) {
+    int32_t col[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        col[e] = ld_meta<UNI>(A.ell_col, e * n_b + row);
+        r.v0[e] = ld_meta<UNI>(A.ell_val, e * n_b + row);
+        if constexpr (E1) r.v1[e] = ld_meta<UNI>(A.ell_v1, e * n_b + row);
+    }
+    r.dg = ld_meta<UNI>(A.diag, row);
+    r.w1 = ld_meta<UNI>(A.w, row);
+    r.w2 = S2 ? ld_meta<UNI>(A.w2, row) : T(0);
+    if (active) {
+        r.xo = ldv<T, V>(X + row * ld + c0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) r.xj[e] = ldv<T, V>(X + int64_t(col[e]) * ld + c0);
+    }
+}
+
 // One row of the structured operator:
 //   diag x_i + sum_e v0_e x_j(e) + w1 (x_i[l+1] + x_i[l-1])
 //   [+ w2 (x_i[l+2] + x_i[l-2])]                 (13-point, S2)
 //   [+ sum_e v1_e (x_j(e)[l+1] + x_j(e)[l-1])]   (27-point, E1)
 // Each neighbour row is loaded once; its shifted planes come from lane
-// shuffles.
-template <typename T, int V, int WT, bool E1, bool S2>
-__device__ __forceinline__ vec_t<T, V> stencil_row(const OpDev<T> &A, const T *__restrict__ X, int64_t n_b, int k,
-                                                   int ld, int64_t row, int c0, int lpr) {
+// shuffles.  Explicit fused multiply-adds fix the rounding of every term, so
+// the result does not depend on the tile.
+template <typename T, int V, bool E1, bool S2>
+__device__ __forceinline__ vec_t<T, V> stencil_apply(const StencilRow<T, V, E1, S2> &r, int c0, int lpr, int k) {
     using vt = vec_t<T, V>;
-    int32_t col[WT];
-    T v0[WT], v1[WT];
-#pragma unroll
-    for (int e = 0; e < WT; ++e) {
-        col[e] = A.ell_col[e * n_b + row];
-        v0[e] = A.ell_val[e * n_b + row];
-        v1[e] = E1 ? A.ell_v1[e * n_b + row] : T(0);
-    }
-    const vt xo = ldv<T, V>(X + row * ld + c0);
-    vt xj[WT];
-#pragma unroll
-    for (int e = 0; e < WT; ++e) xj[e] = ldv<T, V>(X + int64_t(col[e]) * ld + c0);
-    // Explicit fused multiply-adds fix the rounding of every term, so the
-    // result does not depend on the vector width the tile picks.
     auto fma_into = [](T a, const vt &b, vt &acc) { acc = __builtin_elementwise_fma(vt(a), b, acc); };
-    vt acc = A.diag[row] * xo;
+    vt acc = r.dg * r.xo;
 #pragma unroll
-    for (int e = 0; e < WT; ++e) fma_into(v0[e], xj[e], acc);
-    fma_into(A.w[row], plane_shift<T, V, 1>(xo, c0, lpr, k) + plane_shift<T, V, -1>(xo, c0, lpr, k), acc);
+    for (int e = 0; e < 8; ++e) fma_into(r.v0[e], r.xj[e], acc);
+    fma_into(r.w1, plane_shift<T, V, 1>(r.xo, c0, lpr, k) + plane_shift<T, V, -1>(r.xo, c0, lpr, k), acc);
     if constexpr (S2)
-        fma_into(A.w2[row], plane_shift<T, V, 2>(xo, c0, lpr, k) + plane_shift<T, V, -2>(xo, c0, lpr, k), acc);
+        fma_into(r.w2, plane_shift<T, V, 2>(r.xo, c0, lpr, k) + plane_shift<T, V, -2>(r.xo, c0, lpr, k), acc);
     if constexpr (E1) {
 #pragma unroll
-        for (int e = 0; e < WT; ++e)
-            fma_into(v1[e], plane_shift<T, V, 1>(xj[e], c0, lpr, k) + plane_shift<T, V, -1>(xj[e], c0, lpr, k), acc);
+        for (int e = 0; e < 8; ++e)
+            fma_into(r.v1[e], plane_shift<T, V, 1>(r.xj[e], c0, lpr, k) + plane_shift<T, V, -1>(r.xj[e], c0, lpr, k),
+                     acc);
+    }
+    return acc;
+}
+
+// Multi-pass rows: lane sub of a row group of lpr lanes holds columns
+// p * lpr * V + sub * V + t of every pass p.  The columns of one row form a
+// ring of k = P * lpr * V planes.
+template <typename T, int V, bool E1, bool S2, int P>
+struct StencilPasses {
+    T v0[8], v1[E1 ? 8 : 1];
+    T dg, w1, w2;
+    vec_t<T, V> xo[P], xj[8][P];
+};
+
+template <typename T, int V, bool E1, bool S2, int P>
+__device__ __forceinline__ void stencil_load_passes(StencilPasses<T, V, E1, S2, P> &r, const OpDev<T> &A,
+                                                    const T *__restrict__ X, int64_t n_b, int ld, int64_t row, int c0,
+                                                    int span) {
+    int32_t col[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        col[e] = A.ell_col[e * n_b + row];
+        r.v0[e] = A.ell_val[e * n_b + row];
+        if constexpr (E1) r.v1[e] = A.ell_v1[e * n_b + row];
+    }
+    r.dg = A.diag[row];
+    r.w1 = A.w[row];
+    r.w2 = S2 ? A.w2[row] : T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) r.xo[p] = ldv<T, V>(X + row * ld + p * span + c0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int p = 0; p < P; ++p) r.xj[e][p] = ldv<T, V>(X + int64_t(col[e]) * ld + p * span + c0);
+}
+
+// Columns (c + D) mod k of this lane's V columns of pass p, D in -2..2.  A
+// value that lives dl lanes away comes from that lane by a shuffle; the
+// source lanes whose reader sits across the group's edge hand over their
+// value of the neighbouring pass instead (each source lane has one reader).
+// Needs |dl| <= lpr, i.e. lpr * V >= 2.
+template <typename T, int V, int P, int D>
+__device__ __forceinline__ vec_t<T, V> ring_shift(const vec_t<T, V> (&x)[P], int p, int sub, int lpr) {
+    vec_t<T, V> out;
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+        const int u = t + D;
+        if (u >= 0 && u < V) {
+            out[t] = x[p][u >= 0 && u < V ? u : 0];
+        } else {
+            const int dl = u >= 0 ? u / V : -((-u + V - 1) / V);
+            const int e = u - dl * V;
+            const bool wrap = dl > 0 ? sub < dl : sub >= lpr + dl;
+            const int pw = dl > 0 ? (p + 1) % P : (p + P - 1) % P;
+            const T val = wrap ? x[pw][e] : x[p][e];
+            out[t] = __shfl(val, (sub + dl) & (lpr - 1), lpr);
+        }
+    }
+    return out;
+}
+
+// Pass p of a multi-pass row; the terms and their order are those of
+// stencil_apply, so the result is bit-identical to the single-pass kernel.
+template <typename T, int V, bool E1, bool S2, int P>
+__device__ __forceinline__ vec_t<T, V> stencil_apply_pass(const StencilPasses<T, V, E1, S2, P> &r, int p, int sub,
+                                                          int lpr) {
+    using vt = vec_t<T, V>;
+    auto fma_into = [](T a, const vt &b, vt &acc) { acc = __builtin_elementwise_fma(vt(a), b, acc); };
+    vt acc = r.dg * r.xo[p];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) fma_into(r.v0[e], r.xj[e][p], acc);
+    fma_into(r.w1, ring_shift<T, V, P, 1>(r.xo, p, sub, lpr) + ring_shift<T, V, P, -1>(r.xo, p, sub, lpr), acc);
+    if constexpr (S2)
+        fma_into(r.w2, ring_shift<T, V, P, 2>(r.xo, p, sub, lpr) + ring_shift<T, V, P, -2>(r.xo, p, sub, lpr), acc);
+    if constexpr (E1) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            fma_into(r.v1[e], ring_shift<T, V, P, 1>(r.xj[e], p, sub, lpr) + ring_shift<T, V, P, -1>(r.xj[e], p, sub, lpr),
+                     acc);
     }
     return acc;
 }

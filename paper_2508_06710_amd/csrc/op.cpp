@@ -380,8 +380,12 @@ void check_tile(const fvx_op *op, int dtype, const fvx_tile &t) {
                 "tile.stage_lds needs at most 64 rows per tile");
     FVX_REQUIRE(t.nt_store == 0 || t.nt_store == 1, FVX_E_ARG, "tile.nt_store must be 0 or 1");
     if (op->stencil != 7) {
-        FVX_REQUIRE(t.lanes_per_row * t.vec >= op->k && op->k % t.vec == 0, FVX_E_ARG,
-                    "13/27-point operators need one pass of a row group over k, vec dividing k");
+        const int span = t.lanes_per_row * t.vec;
+        const bool one = span >= op->k && op->k % t.vec == 0;
+        const bool multi = span >= 2 && t.block <= 512 && (op->k == 2 * span || op->k == 4 * span);
+        FVX_REQUIRE(one || multi, FVX_E_ARG,
+                    "13/27-point operators need one pass of a row group over k with vec dividing k, or exactly 2 or 4 "
+                    "passes (block <= 512)");
         FVX_REQUIRE(!t.stage_lds, FVX_E_ARG, "13/27-point operators do not stage rows in LDS");
     }
 }

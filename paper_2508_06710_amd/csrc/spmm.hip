@@ -108,22 +108,49 @@ __global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__res
     }
 }
 
-// Y = A X for the structured 13/27-point operators (ELL width 8, one pass of
-// a row group covers all k columns).
-template <typename T, int V, bool E1, bool S2, bool NT>
+// Y = A X for the structured 13/27-point operators, one pass of a row group
+// covering all k columns.  UNI: 64 lanes per row, so the metadata of a row is
+// wavefront-uniform and comes in through scalar loads.
+template <typename T, int V, bool E1, bool S2, bool NT, bool UNI>
 __global__ __launch_bounds__(1024) void k_lap_stencil(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y) {
+    const int lpr = UNI ? 64 : a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int c0 = sub * V;
+    const bool active = c0 < a.k;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        int64_t row = t * a.rows_per_tile + grp;
+        if constexpr (UNI) row = __builtin_amdgcn_readfirstlane(int32_t(row));
+        if (row >= a.n_rows) break;
+        StencilRow<T, V, E1, S2> r;
+        stencil_load<T, V, E1, S2, UNI>(r, a.A, X, a.n_b, a.ld, row, c0, active);
+        if (active)
+            stv_masked<T, V, NT>(Y + row * a.ld + c0, stencil_apply<T, V, E1, S2>(r, c0, lpr, a.k), a.k - c0);
+    }
+}
+
+// The same product with P passes of a row group (k = P * lanes_per_row * V):
+// every lane holds its V columns of all P passes of the row and of its 8
+// neighbours, so the plane shifts rotate across the lanes of the group and,
+// at the group's edge, into the next or previous pass.
+template <typename T, int V, bool E1, bool S2, bool NT, int P>
+__global__ __launch_bounds__(512) void k_lap_stencil_passes(RowArgs<T> a, const T *__restrict__ X,
+                                                            T *__restrict__ Y) {
     const int lpr = a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
+    const int span = lpr * V;
     const int c0 = sub * V;
     const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
     for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
         const int64_t row = t * a.rows_per_tile + grp;
         if (row >= a.n_rows) break;
-        if (c0 < a.k) {
-            const vec_t<T, V> acc = stencil_row<T, V, 8, E1, S2>(a.A, X, a.n_b, a.k, a.ld, row, c0, lpr);
-            stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
-        }
+        StencilPasses<T, V, E1, S2, P> r;
+        stencil_load_passes<T, V, E1, S2, P>(r, a.A, X, a.n_b, a.ld, row, c0, span);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            stv_masked<T, V, NT>(Y + row * a.ld + p * span + c0, stencil_apply_pass<T, V, E1, S2, P>(r, p, sub, lpr), V);
     }
 }
 
@@ -266,18 +293,32 @@ void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hi
     FVX_REQUIRE(cs == nullptr, FVX_E_ARG, "colscale applies to independent planes only");
     RowGrid g;
     const fvx_tile &t = op->tile[dtype_of<T>()];
-    FVX_REQUIRE(t.lanes_per_row * t.vec >= op->k && op->k % t.vec == 0, FVX_E_ARG,
-                "13/27-point operators need a tile whose row group covers k in one pass, vec dividing k");
+    const int span = t.lanes_per_row * t.vec;
+    const int passes = span >= op->k ? 1 : op->k / span;
+    FVX_REQUIRE(op->k % t.vec == 0 && (passes == 1 || (op->k == passes * span && (passes == 2 || passes == 4) &&
+                                                       span >= 2 && t.block <= 512)),
+                FVX_E_ARG, "13/27-point operators need a tile with 1, 2 or 4 passes over k, vec dividing k");
     auto a = row_args<T>(op, op->n_b, g, t);
     by_vec<T>(t.vec, true, [&](auto V, auto) {
         constexpr int v = decltype(V)::value;
         auto go = [&](auto E1t, auto S2t) {
             constexpr bool e1 = decltype(E1t)::value, s2 = decltype(S2t)::value;
-            if (t.nt_store)
-                hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, true>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y);
-            else
-                hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X,
-                                   Y);
+            auto launch = [&](auto NTt) {
+                constexpr bool nt = decltype(NTt)::value;
+                if (passes == 4)
+                    hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, 4>), dim3(g.n_blocks), dim3(t.block), 0,
+                                       s, a, X, Y);
+                else if (passes == 2)
+                    hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, 2>), dim3(g.n_blocks), dim3(t.block), 0,
+                                       s, a, X, Y);
+                else if (t.lanes_per_row == 64)
+                    hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, nt, true>), dim3(g.n_blocks), dim3(t.block), 0, s,
+                                       a, X, Y);
+                else
+                    hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, nt, false>), dim3(g.n_blocks), dim3(t.block), 0, s,
+                                       a, X, Y);
+            };
+            t.nt_store ? launch(std::true_type{}) : launch(std::false_type{});
         };
         if (op->stencil == 27)
             go(std::true_type{}, std::false_type{});

@@ -20,11 +20,13 @@ std::vector<fvx_tile> shape_candidates(const fvx_op *op, int dtype) {
         if (op->ld % vec) continue;
         if (op->stencil != 7 && op->k % vec) continue;
         const int base = std::min(64, next_pow2(int(ceil_div(op->k, vec))));
-        if (op->stencil != 7 && base * vec < op->k) continue;
-        const int lowest = op->stencil != 7 ? base : base / 4;  // structured: one pass only
-        for (int lpr = base; lpr >= 1 && lpr >= lowest; lpr >>= 1)
+        for (int lpr = base; lpr >= 1 && lpr >= base / 4; lpr >>= 1)
             for (int block : {64, 128, 256, 512}) {
                 if (block < lpr) continue;
+                if (op->stencil != 7) {  // structured: one pass, or exactly 2 or 4
+                    const int span = lpr * vec;
+                    if (!(span >= op->k || (span >= 2 && (op->k == 2 * span || op->k == 4 * span)))) continue;
+                }
                 out.push_back(fvx_tile{vec, lpr, block, 1, 0, 0, 0});
             }
     }

@@ -2,7 +2,8 @@
 of Section 4.1: 13-point fourth-order differences, 27-point trilinear
 elements) with the oracle's assembled 3D matrices, element by element, in
 FP64 and FP32, over ragged row counts, every supported k class and every
-single-pass tile; plus the argument checks of these operators."""
+tile shape (one, two or four passes of a row group); plus the argument
+checks of these operators."""
 import math
 
 import numpy as np
@@ -78,16 +79,22 @@ def test_stencil_f32_within_rounding_bound(stencil, k):
     assert np.all(np.abs(y - oracle.spmv(A, x)) <= fp32_bound_factor(A) * bound + 1e-30)
 
 
-def _single_pass_tiles(fvx, op, dtype):
+def _tiles(fvx, op, dtype):
+    """Every valid tile shape: one pass of a row group over k (idle lanes
+    allowed), or exactly 2 or 4 passes."""
     vmax = 4 if dtype == fvx.F32 else 2
     for vec in (1, 2, 4):
         if vec > vmax or op.k % vec or op.ld % vec:
             continue
-        need = 1 << max(0, math.ceil(math.log2(op.k / vec)))
-        for lpr in sorted({need, min(64, 2 * need)}):
-            if lpr * vec < op.k or lpr > 64:
+        for lpr in (1, 2, 4, 8, 16, 32, 64):
+            span = lpr * vec
+            single = span >= op.k and span < 2 * op.k
+            multi = span >= 2 and op.k in (2 * span, 4 * span)
+            if not (single or multi):
                 continue
-            for block in (64, 256, 1024):
+            for block in (64, 256, 512, 1024):
+                if block < lpr or (multi and block > 512):
+                    continue
                 for remap in (0, 1):
                     for cap in (0, 7):
                         for nt in (0, 1):
@@ -95,10 +102,11 @@ def _single_pass_tiles(fvx, op, dtype):
 
 
 @pytest.mark.parametrize("stencil", STENCILS)
-@pytest.mark.parametrize("k", [4, 12, 64])
-def test_every_single_pass_tile_gives_the_same_product(stencil, k):
+@pytest.mark.parametrize("k", [4, 12, 16, 64])
+def test_every_tile_gives_the_same_product(stencil, k):
     """Each output element sums the same terms in the same order whatever
-    the tile, so every tile's product is bit-identical."""
+    the tile (one pass, two or four passes, any vector width), so every
+    tile's product is bit-identical."""
     spec = SPECS["channel37x29"]
     fvx, op, A = _op(spec, k, stencil, dz=0.1)
     x = inputs.uniform(43, k, op.n_b * k)
@@ -106,7 +114,7 @@ def test_every_single_pass_tile_gives_the_same_product(stencil, k):
         X = op.to_rows(x, dtype=dtype)
         ref = None
         n = 0
-        for vec, lpr, block, remap, cap, nt in _single_pass_tiles(fvx, op, dtype):
+        for vec, lpr, block, remap, cap, nt in _tiles(fvx, op, dtype):
             op.set_tile(vec, lpr, block, remap, cap, 0, nt, dtype=dtype)
             y = op.to_planes(op.lap(X), dtype=dtype)
             if ref is None:
@@ -119,13 +127,27 @@ def test_every_single_pass_tile_gives_the_same_product(stencil, k):
 
 
 @pytest.mark.parametrize("stencil", STENCILS)
-def test_tuner_picks_a_single_pass_tile(stencil):
+@pytest.mark.parametrize("k,vec,lpr", [(64, 2, 8), (64, 1, 16), (128, 2, 16), (32, 1, 8), (8, 1, 2), (4, 2, 1)])
+def test_multi_pass_tiles_match_the_oracle(stencil, k, vec, lpr):
+    """Two or four passes (k = passes * lanes * vec), FP64 against the oracle,
+    the group's edge lanes taking their neighbours from the adjacent pass."""
+    spec = SPECS["channel37x29"]
+    fvx, op, A = _op(spec, k, stencil, dz=0.07)
+    op.set_tile(vec, lpr, 256, 1, 0, 0, 0, dtype=fvx.F64)
+    x = inputs.uniform(48, k, op.n_b * k)
+    assert componentwise(_lap64(op, x), oracle.spmv(A, x), A, x) <= TOL64
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+def test_tuner_picks_a_valid_tile(stencil):
     spec = SPECS["channel37x29"]
     fvx, op, A = _op(spec, 64, stencil, dz=0.1)
     for dtype in (fvx.F64, fvx.F32):
         op.tune(dtype, scratch_bytes=32 << 20, reps=1)
-        vec, lpr, _, _, _, stage, _ = op.get_tile(dtype)
-        assert lpr * vec >= op.k and op.k % vec == 0 and stage == 0
+        vec, lpr, block, _, _, stage, _ = op.get_tile(dtype)
+        span = lpr * vec
+        assert op.k % vec == 0 and stage == 0
+        assert span >= op.k or (op.k in (2 * span, 4 * span) and block <= 512)
     x = inputs.uniform(44, 0, op.n_b * op.k)
     assert componentwise(_lap64(op, x), oracle.spmv(A, x), A, x) <= TOL64
 
@@ -163,9 +185,17 @@ def test_div_and_grad_are_the_face_graph_operators(stencil):
 def test_structured_operator_argument_checks():
     fvx, op, _ = _op(SPECS["channel7x9"], 12, 27)
     with pytest.raises(fvx.FvxError):
-        op.set_tile(1, 4, 256, 1, dtype=fvx.F64)  # 4 lanes x 1 column < 12 planes: two passes
+        op.set_tile(1, 4, 256, 1, dtype=fvx.F64)  # 3 passes of 4 columns
+    with pytest.raises(fvx.FvxError):
+        op.set_tile(1, 2, 256, 1, dtype=fvx.F64)  # 6 passes
+    with pytest.raises(fvx.FvxError):
+        op.set_tile(2, 2, 1024, 1, dtype=fvx.F64)  # 3 passes
     with pytest.raises(fvx.FvxError):
         op.set_tile(2, 8, 256, 1, 0, 1, dtype=fvx.F64)  # no LDS staging
+    _, op16, _ = _op(SPECS["channel7x9"], 16, 13)
+    with pytest.raises(fvx.FvxError):
+        op16.set_tile(1, 4, 1024, 1, dtype=fvx.F64)  # 4 passes need block <= 512
+    op16.set_tile(1, 4, 512, 1, dtype=fvx.F64)
     _, op6, _ = _op(SPECS["channel7x9"], 6, 13)
     with pytest.raises(fvx.FvxError):
         op6.set_tile(4, 2, 256, 1, dtype=fvx.F32)  # 4 does not divide 6 planes (or ld)
