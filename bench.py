@@ -539,22 +539,27 @@ def time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3):
 
 def stencil_leg(fvx, inputs, torch, np):
     """The 7-, 13- and 27-point operators (first neighbours; first and second
-    neighbours; all 26 neighbours) on the channel base at several plane
-    counts: SpMM bandwidth against the HBM roofline with tuned tiles, beside
-    the assembled 3D CSR SpMV of the same matrix.  The bytes ratio is the
-    speed-up the repeated-block format allows over the assembled matrix when
-    both run at the same bandwidth."""
+    neighbours; all 26 neighbours) on the channel base: SpMM bandwidth against
+    the HBM roofline with tuned tiles, the speed-up over k single-column
+    products (P_k = k t_1 / t_k, the quantity of Fig. 8) beside its
+    bandwidth bound k B_1 / B_k, and the assembled 3D CSR SpMV of the same
+    matrix.  The CSR bytes ratio is the speed-up the repeated-block format
+    allows over the assembled matrix when both run at the same bandwidth."""
     spec = inputs.channel_base(*BASE)
     mesh = fvx.Mesh.from_spec(spec)
     out = []
-    for k in (16, 64):
-        dz = math.pi / k
-        for stencil in (7, 13, 27):
+    t1 = {}
+    for stencil in (7, 13, 27):
+        for k in (1, 16, 64):
+            dz = math.pi / k
             op = fvx.Operator(mesh, k, dz, fvx.PERIODIC_Z, with_f32=True, stencil=stencil)
-            ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z, stencil=stencil)
-            n3, nnz3 = op.n_b * k, len(col)
-            t3 = time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3)
-            del ptr, col, val
+            n3 = op.n_b * k
+            t3 = nnz3 = None
+            if k > 1:
+                ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z, stencil=stencil)
+                nnz3 = len(col)
+                t3 = time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3)
+                del ptr, col, val
             for dt, name, v in ((fvx.F64, "f64", 8), (fvx.F32, "f32", 4)):
                 tile = tune(op, fvx, dt)
                 x = op.to_rows(inputs.uniform(0, 0, n3), dtype=dt)
@@ -565,17 +570,22 @@ def stencil_leg(fvx, inputs, torch, np):
                 t = lap_sweep(op, X, Y, torch, reps=2)
                 del X, Y, x
                 Bk = spmm_bytes(op.nnz_b, op.n_b, k, v) if stencil == 7 else stencil_bytes(op.n_b, k, stencil, v)
-                rec = {"stencil": stencil, "k": k, "dtype": name, "tile": list(tile), "nnz_per_row_3d": nnz3 / n3,
-                       "bytes_per_launch": Bk, "spmm_us": t * 1e3, "spmm_GBs": Bk / (t * 1e-3) / 1e9,
-                       "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                       "tflops_2nnz": 2 * nnz3 / (t * 1e-3) / 1e12}
-                if dt == fvx.F64:
-                    rec.update({"csr3d_us": t3 * 1e3, "speedup_vs_csr3d": t3 / t,
+                if k == 1:
+                    t1[(stencil, name)] = (t, Bk)
+                rec = {"stencil": stencil, "k": k, "dtype": name, "tile": list(tile), "bytes_per_launch": Bk,
+                       "spmm_us": t * 1e3, "spmm_GBs": Bk / (t * 1e-3) / 1e9,
+                       "frac_hbm": Bk / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                if k > 1:
+                    ta, Ba = t1[(stencil, name)]
+                    rec.update({"P_k": k * ta / t, "P_bound_bytes": k * Ba / Bk})
+                if k > 1 and dt == fvx.F64:
+                    rec.update({"nnz_per_row_3d": nnz3 / n3, "csr3d_us": t3 * 1e3, "speedup_vs_csr3d": t3 / t,
                                 "bytes_ratio_csr3d": csr3d_bytes(nnz3, n3) / Bk})
                 out.append(rec)
                 log(f"stencil {stencil} k={k} {name}: {rec['spmm_GBs']:.0f} GB/s "
                     f"({100 * rec['frac_hbm']:.0f}% of 8 TB/s)"
-                    + (f", {rec['speedup_vs_csr3d']:.2f}x the 3D CSR SpMV" if dt == fvx.F64 else ""))
+                    + (f", P_k {rec['P_k']:.1f} (bound {rec['P_bound_bytes']:.1f})" if k > 1 else "")
+                    + (f", {rec['speedup_vs_csr3d']:.2f}x the 3D CSR SpMV" if "csr3d_us" in rec else ""))
             del op
             torch.cuda.empty_cache()
     return out

@@ -436,19 +436,22 @@ int fvx_poisson_solve_net(const fvx_op *op, fvx_net *net, const double *B, const
 int fvx_expand_csr(const fvx_mesh *m, const fvx_op_desc *d, int64_t *nnz, int32_t *ptr, int32_t *col,
                    double *val);
 
-/* y = A x for an assembled CSR matrix (one row per thread; device arrays,
- * int32 row pointers and column indices, FP64 values): the plain SpMV that
- * the repeated-block SpMM replaces. */
-int fvx_csr_spmv(int64_t n_rows, const int32_t *ptr, const int32_t *col, const double *val,
+/* y = A x for an assembled CSR matrix (device arrays, int32 row pointers and
+ * column indices, FP64 values): the plain SpMV that the repeated-block SpMM
+ * replaces.  nnz = ptr[n_rows], passed from the host, only sizes the lane
+ * groups: a group of lanes per row (the mean row length rounded up to a power
+ * of two, 1 when it is at most 2) strides over the row and reduces by
+ * shuffles. */
+int fvx_csr_spmv(int64_t n_rows, int64_t nnz, const int32_t *ptr, const int32_t *col, const double *val,
                  const double *x, double *y, void *stream);
 
 /* Textbook FP64 CG on an assembled CSR matrix (SPD -A form as fvx_poisson_solve)
- * with separate kernels for the SpMV, each dot product, each axpy and the
- * search-direction update.  B, X: device double [n].  singular != 0
+ * with separate kernels for the SpMV (as fvx_csr_spmv), each dot product,
+ * each axpy and the search-direction update.  B, X: device double [n].  singular != 0
  * projects b (and x on exit) to zero plain mean.  Options and statistics as
  * fvx_poisson_solve (precision must be FVX_F64). */
 int fvx_csr_solve_bytes(int64_t n_rows, size_t *bytes);
-int fvx_csr_poisson_solve(int64_t n_rows, const int32_t *ptr, const int32_t *col, const double *val,
+int fvx_csr_poisson_solve(int64_t n_rows, int64_t nnz, const int32_t *ptr, const int32_t *col, const double *val,
                           const double *B, double *X, int singular, const fvx_solve_opts *opts,
                           void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
 

@@ -419,7 +419,7 @@ class CsrMatrix:
     def spmv(self, x, y=None, stream=None):
         torch = _torch()
         y = torch.empty(self.n, dtype=torch.float64, device=self.device) if y is None else y
-        check(lib().fvx_csr_spmv(self.n, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(x), _ptr(y),
+        check(lib().fvx_csr_spmv(self.n, self.nnz, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(x), _ptr(y),
                                  _stream(stream)), "fvx_csr_spmv")
         return y
 
@@ -435,7 +435,8 @@ class CsrMatrix:
             self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         x = torch.zeros(self.n, dtype=torch.float64, device=self.device) if x is None else x
         st = SolveStats()
-        rc = lib().fvx_csr_poisson_solve(self.n, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(b), _ptr(x),
+        rc = lib().fvx_csr_poisson_solve(self.n, self.nnz, _ptr(self.ptr), _ptr(self.col), _ptr(self.val), _ptr(b),
+                                         _ptr(x),
                                          int(singular), C.byref(o), _ptr(self._ws), self._ws.numel(), C.byref(st),
                                          _stream(stream))
         check(rc, "fvx_csr_poisson_solve", (0, 1) if allow_not_converged else (0,))

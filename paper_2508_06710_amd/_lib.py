@@ -102,9 +102,9 @@ SIGNATURES = {
     "fvx_poisson_solve_batch": (C.c_int, [C.c_int, _P(_vp), _P(_vp), _P(_vp), _P(SolveOpts), _vp, C.c_size_t,
                                           _vp, _vp]),
     "fvx_expand_csr": (C.c_int, [_vp, _P(OpDesc), _P(_i64), _vp, _vp, _vp]),
-    "fvx_csr_spmv": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fvx_csr_spmv": (C.c_int, [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fvx_csr_solve_bytes": (C.c_int, [_i64, _P(C.c_size_t)]),
-    "fvx_csr_poisson_solve": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
+    "fvx_csr_poisson_solve": (C.c_int, [_i64, _i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
                                         C.c_size_t, _P(SolveStats), _vp]),
     "fvx_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "fvx_net_n_params": (C.c_int, []),

@@ -1,5 +1,5 @@
-// Comparators for measurement: the assembled 3D CSR SpMV (no block reuse,
-// one matrix row per thread) and the textbook FP64 SpMV-CG built from it
+// Comparators for measurement: the assembled 3D CSR SpMV (no block reuse;
+// a group of lanes per row sized to the mean row length) and the textbook FP64 SpMV-CG built from it
 // with separate SpMV, dot, axpy and xpay kernels; plus a streaming copy
 // kernel that measures the achievable HBM bandwidth.
 #include <chrono>
@@ -41,6 +41,28 @@ __global__ __launch_bounds__(kFlatBlock) void k_csr_spmv(int64_t n, const int32_
         double s = 0.0;
         for (int32_t j = ptr[i]; j < ptr[i + 1]; ++j) s += val[j] * x[col[j]];
         y[i] = s;
+    }
+}
+
+// CSR-vector SpMV: G lanes per row stride over its nonzeros and reduce by
+// shuffles (G about the mean row length), so that the loads of one row are
+// contiguous across lanes.
+template <int G>
+__global__ __launch_bounds__(kFlatBlock) void k_csr_spmv_vec(int64_t n, const int32_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val,
+                                                             const double *__restrict__ x, double *__restrict__ y,
+                                                             const int32_t *__restrict__ done) {
+    if (done && *done) return;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t per_block = kFlatBlock / G;
+    for (int64_t i = blockIdx.x * per_block + threadIdx.x / G; i < n; i += int64_t(gridDim.x) * per_block) {
+        double s = 0.0;
+        const int32_t j1 = ptr[i + 1];
+        for (int32_t j = ptr[i] + lane; j < j1; j += G) s += val[j] * x[col[j]];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (lane == 0) y[i] = s;
     }
 }
 
@@ -268,6 +290,33 @@ CsrWs carve_csr(void *ws, int64_t n) {
 
 int spmv_blocks(int64_t n) { return int(std::min<int64_t>(65536, std::max<int64_t>(1, ceil_div(n, kFlatBlock)))); }
 
+// Lanes per row of the CSR SpMV: the mean row length rounded up to a power of
+// two (1 = the row-per-thread kernel).
+int csr_lanes(int64_t n, int64_t nnz) {
+    const int64_t mean = n > 0 ? ceil_div(std::max<int64_t>(nnz, 1), n) : 1;
+    int g = 1;
+    while (g < mean && g < 64) g <<= 1;
+    return g <= 2 ? 1 : g;
+}
+
+void launch_csr_spmv(int g, int64_t n, const int32_t *ptr, const int32_t *col, const double *val, const double *x,
+                     double *y, const int32_t *done, hipStream_t s) {
+    const dim3 block(kFlatBlock);
+    auto go = [&](auto Gt) {
+        constexpr int G = decltype(Gt)::value;
+        const int64_t nb = std::min<int64_t>(1 << 20, std::max<int64_t>(1, ceil_div(n * G, kFlatBlock)));
+        hipLaunchKernelGGL(k_csr_spmv_vec<G>, dim3(int(nb)), block, 0, s, n, ptr, col, val, x, y, done);
+    };
+    switch (g) {
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    case 8: go(std::integral_constant<int, 8>{}); break;
+    case 16: go(std::integral_constant<int, 16>{}); break;
+    case 32: go(std::integral_constant<int, 32>{}); break;
+    case 64: go(std::integral_constant<int, 64>{}); break;
+    default: hipLaunchKernelGGL(k_csr_spmv, dim3(spmv_blocks(n)), block, 0, s, n, ptr, col, val, x, y, done);
+    }
+}
+
 }  // namespace
 }  // namespace fvx
 
@@ -275,13 +324,13 @@ using fvx::guard;
 
 extern "C" {
 
-int fvx_csr_spmv(int64_t n_rows, const int32_t *ptr, const int32_t *col, const double *val, const double *x,
-                 double *y, void *stream) {
+int fvx_csr_spmv(int64_t n_rows, int64_t nnz, const int32_t *ptr, const int32_t *col, const double *val,
+                 const double *x, double *y, void *stream) {
     return guard([&] {
-        FVX_REQUIRE(n_rows >= 0 && ptr && col && val && x && y, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(n_rows >= 0 && nnz >= 0 && ptr && col && val && x && y, FVX_E_ARG, "NULL argument");
         if (n_rows == 0) return FVX_OK;
-        hipLaunchKernelGGL(fvx::k_csr_spmv, dim3(fvx::spmv_blocks(n_rows)), dim3(fvx::kFlatBlock), 0,
-                           fvx::as_stream(stream), n_rows, ptr, col, val, x, y, (const int32_t *)nullptr);
+        fvx::launch_csr_spmv(fvx::csr_lanes(n_rows, nnz), n_rows, ptr, col, val, x, y, nullptr,
+                             fvx::as_stream(stream));
         FVX_HIP(hipGetLastError());
         return FVX_OK;
     });
@@ -295,13 +344,14 @@ int fvx_csr_solve_bytes(int64_t n_rows, size_t *bytes) {
     });
 }
 
-int fvx_csr_poisson_solve(int64_t n, const int32_t *ptr, const int32_t *col, const double *val, const double *B,
-                          double *X, int singular, const fvx_solve_opts *o, void *ws, size_t ws_bytes,
-                          fvx_solve_stats *stats, void *stream) {
+int fvx_csr_poisson_solve(int64_t n, int64_t nnz, const int32_t *ptr, const int32_t *col, const double *val,
+                          const double *B, double *X, int singular, const fvx_solve_opts *o, void *ws,
+                          size_t ws_bytes, fvx_solve_stats *stats, void *stream) {
     return guard([&] {
         using namespace fvx;
         const auto t_start = std::chrono::steady_clock::now();
-        FVX_REQUIRE(n >= 1 && ptr && col && val && B && X && ws && o, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(n >= 1 && nnz >= 0 && ptr && col && val && B && X && ws && o, FVX_E_ARG, "NULL argument");
+        const int g = csr_lanes(n, nnz);
         FVX_REQUIRE(o->rtol > 0 && o->rtol < 1 && o->max_iter >= 1 && o->poll_every >= 1, FVX_E_ARG, "bad options");
         FVX_REQUIRE(o->precision == FVX_F64, FVX_E_UNSUPPORTED, "the assembled-matrix comparator is FP64 only");
         FVX_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, FVX_E_ARG, "ws must be 256-byte aligned");
@@ -315,10 +365,10 @@ int fvx_csr_poisson_solve(int64_t n, const int32_t *ptr, const int32_t *col, con
         FVX_HIP(hipMemcpyAsync(d.st, &st0, sizeof(CgState), hipMemcpyHostToDevice, s));
         const Flat f = flat(n);
         const int nblk = flat_blocks(f);
-        const dim3 grid(nblk), block(kFlatBlock), sgrid(spmv_blocks(n));
+        const dim3 grid(nblk), block(kFlatBlock);
         const bool given = o->guess == FVX_GUESS_GIVEN;
         if (singular) hipLaunchKernelGGL(k_b_sum, grid, block, 0, s, f, d, B, d.part_a);
-        if (given) hipLaunchKernelGGL(k_csr_spmv, sgrid, block, 0, s, n, ptr, col, val, X, w.q, (const int32_t *)nullptr);
+        if (given) launch_csr_spmv(g, n, ptr, col, val, X, w.q, nullptr, s);
         hipLaunchKernelGGL(k_b_init, grid, block, 0, s, f, d, nblk, singular, B, w.bp, X, w.r, w.p, w.q, int(given));
         hipLaunchKernelGGL(k_b_check0, dim3(1), block, 0, s, d, nblk);
         FVX_HIP(hipGetLastError());
@@ -327,7 +377,7 @@ int fvx_csr_poisson_solve(int64_t n, const int32_t *ptr, const int32_t *col, con
         while (true) {
             const int batch = std::min(o->poll_every, std::max(1, o->max_iter - it));
             for (int i = 0; i < batch; ++i, ++it) {
-                hipLaunchKernelGGL(k_csr_spmv, sgrid, block, 0, s, n, ptr, col, val, w.p, w.q, &d.st->done);
+                launch_csr_spmv(g, n, ptr, col, val, w.p, w.q, &d.st->done, s);
                 hipLaunchKernelGGL(k_b_dot, grid, block, 0, s, f, d, w.p, w.q, d.part_a);
                 hipLaunchKernelGGL(k_b_axpy, grid, block, 0, s, f, d, it, nblk, X, w.p, 1);
                 hipLaunchKernelGGL(k_b_axpy, grid, block, 0, s, f, d, it, nblk, w.r, w.q, 0);
@@ -349,7 +399,7 @@ int fvx_csr_poisson_solve(int64_t n, const int32_t *ptr, const int32_t *col, con
         FVX_HIP(hipMemcpyAsync(&its, d.iters, 4, hipMemcpyDeviceToHost, s));
         if (singular) hipLaunchKernelGGL(k_b_sum, grid, block, 0, s, f, d, X, d.part_a);
         hipLaunchKernelGGL(k_b_fix_x, grid, block, 0, s, f, d, nblk, X, singular);
-        hipLaunchKernelGGL(k_csr_spmv, sgrid, block, 0, s, n, ptr, col, val, X, w.q, (const int32_t *)nullptr);
+        launch_csr_spmv(g, n, ptr, col, val, X, w.q, nullptr, s);
         hipLaunchKernelGGL(k_b_resid, grid, block, 0, s, f, d, w.bp, w.q);
         FVX_HIP(hipGetLastError());
         std::vector<double> part(nblk);

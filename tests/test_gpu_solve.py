@@ -162,6 +162,39 @@ def test_assembled_csr_comparator(spec, k):
     assert abs(xs.mean()) <= 1e-13 * np.abs(xs).max()
 
 
+@pytest.mark.parametrize("per_row", [1, 2, 3, 7, 13, 27, 50, 100])
+def test_csr_spmv_lane_groups(per_row):
+    """The comparator SpMV over every lane-group width (1 to 64 lanes per row,
+    chosen from the mean row length), on random rows of varied length with
+    repeated columns, against the oracle's CSR loop."""
+    import scipy.sparse as sp
+    fvx = __import__("paper_2508_06710_amd")
+    n = 3001
+    lens = (inputs.u64(23, 0, n) % np.uint64(2 * per_row)).astype(np.int64) + 1  # mean about per_row
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    nnz = int(ptr[-1])
+    col = (inputs.u64(23, 1, nnz) % np.uint64(n)).astype(np.int32)
+    val = inputs.uniform(23, 2, nnz)
+    A = sp.csr_matrix((val, col, ptr), shape=(n, n))
+    x = inputs.uniform(23, 3, n)
+    y = fvx.CsrMatrix(ptr, col, val).spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+    ref = oracle.spmv(A, x)
+    from helpers import componentwise
+    assert componentwise(y, ref, A, x) <= 1e-12
+
+
+@pytest.mark.parametrize("stencil", [13, 27])
+def test_csr_comparator_on_structured_operators(stencil):
+    fvx = __import__("paper_2508_06710_amd")
+    spec, k, dz = inputs.channel_base(12, 10), 6, 0.4
+    ptr, col, val = fvx.expand_csr(fvx.Mesh.from_spec(spec), k, dz, fvx.PERIODIC_Z, stencil=stencil)
+    L = oracle.stencil_lap(spec, k, dz, stencil)
+    x = inputs.uniform(24, 0, L.shape[0])
+    y = fvx.CsrMatrix(ptr, col, val).spmv(torch.as_tensor(x).cuda()).cpu().numpy()
+    from helpers import componentwise
+    assert componentwise(y, oracle.spmv(L, x), L, x) <= 1e-12
+
+
 def test_copy_kernel():
     fvx = __import__("paper_2508_06710_amd")
     src = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
