@@ -139,14 +139,15 @@ typedef struct fvx_op_desc {
                            graph (Section 3, Eq. 9); 13 or 27 = the higher-order
                            structured stencils of Section 4.1 on a Cartesian base
                            (fvx_mesh_cartesian), coupling PERIODIC_Z, zero-flux walls,
-                           k <= 128:
+                           k <= 64 or even k <= 128:
                              27: minus the trilinear-element (Q1) stiffness on the
                                  cell centres, -(Kx My Mz + Mx Ky Mz + Mx My Kz);
                              13: (4/3) L1 - (1/6) L2, L1 the 7-point finite-volume
                                  form and L2 the same form between second neighbours
                                  along each axis (area/(2 dz) between planes l, l+-2):
                                  the fourth-order central difference on uniform grids.
-                           div/grad stay the face-graph operators; solves need 7. */
+                           div/grad stay the face-graph operators; solves and
+                           fvx_lap's colscale need 7 (E_UNSUPPORTED / E_ARG). */
     int32_t reserved[3];
 } fvx_op_desc;
 
@@ -162,7 +163,10 @@ typedef struct fvx_op_desc {
  * Laplacian SpMM's output with non-temporal stores (not re-read by the same
  * kernel).  When one row group covers the k columns in exactly 2 or 4 passes
  * (k = passes * lanes_per_row * vec, no LDS staging, block <= 512), every
- * pass's loads are issued before the arithmetic.  All tiles give bitwise the
+ * pass's loads are issued before the arithmetic.  For the 13/27-point
+ * operators a tile must cover k in one pass with vec dividing k, or in exactly
+ * 2 or 4 passes (block <= 512), without LDS staging; with lanes_per_row = 64
+ * their row metadata is read with scalar loads.  All tiles give bitwise the
  * same product. */
 typedef struct fvx_tile {
     int32_t vec, lanes_per_row, block, xcd_remap, max_blocks, stage_lds, nt_store;
