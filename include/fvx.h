@@ -287,8 +287,30 @@ typedef struct fvx_solve_opts {
     int32_t max_outer;    /* MIXED: cap on outer corrections */
     int32_t guess;        /* FVX_GUESS_ZERO or FVX_GUESS_GIVEN (X holds x0) */
     int32_t poll_every;   /* iterations between host reads of the device flag (>= 1) */
-    int32_t reserved[5];
+    int32_t precond;      /* FVX_PRECOND_NONE (plain CG), FVX_PRECOND_JACOBI or
+                             FVX_PRECOND_CHEBYSHEV (see below) */
+    int32_t cheb_degree;  /* CHEBYSHEV: steps of the semi-iteration per application
+                             (1..16; 1 is Jacobi) */
+    double cheb_ratio;    /* CHEBYSHEV: the polynomial targets the interval
+                             [2 / cheb_ratio, 2] of the spectrum of D^-1 A (> 1) */
 } fvx_solve_opts;
+
+/* Preconditioners of the CG (A = -L, D = diag(A); every step an SpMM or a
+ * row-local update, no extra reductions):
+ *   JACOBI:    z = D^-1 r, formed on the fly where z is read (no extra
+ *              vector traffic per iteration).
+ *   CHEBYSHEV: z = p(D^-1 A) D^-1 r, cheb_degree steps of the Chebyshev
+ *              semi-iteration for D^-1 A z = D^-1 r from z = 0 (Saad,
+ *              Iterative Methods for Sparse Linear Systems, Algorithm 12.1)
+ *              on [2 / cheb_ratio, 2]; 2 bounds the spectrum of D^-1 A
+ *              (Gershgorin).  Each step after the first is one fused SpMM
+ *              kernel (5 vector passes); the workspace grows by 3 vectors
+ *              per precision.
+ * The paper's own solver preconditions CG with an adaptive AMG (Section 4);
+ * these polynomial preconditioners keep every operation an SpMM. */
+#define FVX_PRECOND_NONE 0
+#define FVX_PRECOND_JACOBI 1
+#define FVX_PRECOND_CHEBYSHEV 2
 
 typedef struct fvx_solve_stats {
     int32_t status;       /* same as the return value */
@@ -303,7 +325,8 @@ typedef struct fvx_solve_stats {
 } fvx_solve_stats;
 
 /* Fills opts with defaults: rtol 1e-8, max_iter 100000, FP64, inner_rtol 1e-4,
- * max_outer 50, zero guess, poll_every 64. */
+ * max_outer 50, zero guess, poll_every 64, no preconditioner (cheb_degree 4,
+ * cheb_ratio 30). */
 int fvx_solve_opts_default(fvx_solve_opts *opts);
 
 /* Device workspace bytes for fvx_poisson_solve. */

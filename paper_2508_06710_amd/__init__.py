@@ -12,10 +12,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
-                   PERIODIC_Z, FvxError, SolveOpts, SolveStats, Tile, check, lib)
+                   PERIODIC_Z, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, FvxError, SolveOpts, SolveStats,
+                   Tile, check, lib)
 
 __all__ = ["Mesh", "Operator", "GuessNet", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
-           "NEUMANN", "DIRICHLET", "lib"]
+           "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "lib"]
 
 
 def _torch():
@@ -343,18 +344,19 @@ class Operator:
 
     # ---- solves -----------------------------------------------------------
     def solve_opts(self, rtol=1e-8, max_iter=100000, precision=F64, inner_rtol=1e-4, max_outer=50,
-                   guess=GUESS_ZERO, poll_every=64):
+                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=4, cheb_ratio=30.0):
         o = SolveOpts()
         check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
         o.rtol, o.max_iter, o.precision = float(rtol), int(max_iter), int(precision)
         o.inner_rtol, o.max_outer, o.guess, o.poll_every = float(inner_rtol), int(max_outer), int(guess), int(poll_every)
+        o.precond, o.cheb_degree, o.cheb_ratio = int(precond), int(cheb_degree), float(cheb_ratio)
         return o
 
     def workspace(self, opts):
         torch = _torch()
         nbytes = C.c_size_t()
         check(lib().fvx_solve_bytes(self._h, C.byref(opts), C.byref(nbytes)), "fvx_solve_bytes")
-        key = int(opts.precision)
+        key = (int(opts.precision), int(opts.precond == PRECOND_CHEBYSHEV and opts.cheb_degree > 1))
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nbytes.value:
             ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)

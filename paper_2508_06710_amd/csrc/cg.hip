@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_sum(RowArgs<T> a, CgDev d, cons
 // Start: mean (if singular) from partials; bp = b - mean; r = L x0 - bp (x0
 // given, L x0 in q) or -bp; x = 0 for the zero guess; partials of r.r and
 // b.b into part_b.
-template <typename T, int V>
+template <typename T, int V, int PRE>
 __device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_src, int singular,
                           const T *__restrict__ b, T *__restrict__ bp, T *__restrict__ x, T *__restrict__ r,
                           const T *__restrict__ q, int given) {
@@ -108,11 +108,12 @@ __device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_s
         for (int g = threadIdx.x; g < G; g += blockDim.x) tot[g] = 0.0;
     }
     __syncthreads();
-    double c[2][V] = {};
+    double c[2][V] = {}, cz[1][V] = {};
     FOR_ROWS {
         const int64_t o = row * a.ld + c0;
         vec_t<T, V> bv = ldv<T, V>(b + o), rv;
         const vec_t<T, V> qv = given ? ldv<T, V>(q + o) : vec_t<T, V>(0);
+        const double di = PRE == 1 ? double(a.A.dinv[row]) : 0.0;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             if (c0 + u >= a.k) continue;
@@ -120,6 +121,7 @@ __device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_s
             rv[u] = given ? qv[u] - bv[u] : -bv[u];
             c[0][u] += double(rv[u]) * double(rv[u]);
             c[1][u] += double(bv[u]) * double(bv[u]);
+            if constexpr (PRE == 1) cz[0][u] += double(rv[u]) * (di * double(rv[u]));
         }
         stv_masked<T, V>(bp + o, bv, a.k - c0);
         stv_masked<T, V>(r + o, rv, a.k - c0);
@@ -127,41 +129,53 @@ __device__ void b_cg_init(const RowArgs<T> &a, const CgDev &d, VB vb, Src mean_s
     }
     END_ROWS
     write_partials<2, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
+    if constexpr (PRE == 1) {
+        __syncthreads();
+        write_partials<1, V>(cz, sub, lpr, G, d.percol, d.part_b + 2 * int64_t(vb.nblk) * G, blk, vb.nblk, lds);
+    }
 }
 
-template <typename T, int V>
+template <typename T, int V, int PRE>
 __global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, Src mean_src, int singular,
                                                          const T *__restrict__ b, T *__restrict__ bp,
                                                          T *__restrict__ x, T *__restrict__ r,
                                                          const T *__restrict__ q, int given) {
-    b_cg_init<T, V>(a, d, vb_single(a.remap), mean_src, singular, b, bp, x, r, q, given);
+    b_cg_init<T, V, PRE>(a, d, vb_single(a.remap), mean_src, singular, b, bp, x, r, q, given);
 }
 
 // A: direction update fused with the SpMM.  rr: partial sums of r.r after the
 // previous iteration (or after init, with bb the b.b sums, when it == 0).
-template <typename T, int V, bool Z, int WT>
-__device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, const T *__restrict__ r,
-                       const T *__restrict__ p_old, T *__restrict__ p_new, T *__restrict__ q) {
+// Preconditioned (PRE = 1 Jacobi, 2 Chebyshev): rz holds the partials of r.z,
+// which replaces r.r in rho = r.z and beta; the stopping test stays on r.r.
+// The direction is p' = z + beta p: z = D^-1 r on the fly for Jacobi, the
+// stored Chebyshev output (passed as r) otherwise.
+template <typename T, int V, bool Z, int WT, int PRE>
+__device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, Src rz,
+                       const T *__restrict__ r, const T *__restrict__ p_old, T *__restrict__ p_new,
+                       T *__restrict__ q) {
     if (d.st->done) return;
     __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
     __shared__ double tbb[kMaxGroups];
+    __shared__ double trz[kMaxGroups];
     __shared__ double s_beta[kMaxGroups];
     __shared__ int s_any, s_bad;
     ROW_PROLOGUE
     const int G = d.G;
     sum_partials(rr.p, rr.n, G, lds, tot);
     if (it == 0) sum_partials(bb.p, bb.n, G, lds, tbb);
+    if (PRE) sum_partials(rz.p, rz.n, G, lds, trz);
     if (threadIdx.x == 0) s_any = s_bad = 0;
     __syncthreads();
     const int prev = (it + 1) & 1, cur = it & 1;
     for (int g = threadIdx.x; g < G; g += blockDim.x) {
         const double rn = tot[g];
-        double beta = 0.0, rho = rn;
+        const double rzn = PRE ? trz[g] : rn;
+        double beta = 0.0, rho = rzn;
         int act;
         if (it == 0) {
             const double b2 = tbb[g];
-            const bool bad = !isfinite(rn) || !isfinite(b2);
+            const bool bad = !isfinite(rn) || !isfinite(b2) || !isfinite(rzn);
             if (bad) atomicOr(&s_bad, 1);
             act = !bad && b2 > 0.0 && rn > d.rtol2 * b2;
             if (blk == 0) {
@@ -171,11 +185,11 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
                 d.rho_last[g] = rn;
             }
         } else if (d.active[prev * G + g]) {
-            if (!isfinite(rn)) {
+            if (!isfinite(rn) || !isfinite(rzn)) {
                 atomicOr(&s_bad, 1);
                 act = 0;
             } else {
-                beta = rn / d.rho[prev * G + g];
+                beta = rzn / d.rho[prev * G + g];
                 act = rn > d.rtol2 * d.bnorm2[g];
             }
             if (blk == 0) {
@@ -209,7 +223,12 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
     const bool single = lpr * V >= a.k;
     double c[1][V] = {};
     FOR_ROWS {
-        DirLoad<T, V> in{r, p_old, a.ld, vec_t<T, V>(0)};
+        using Load = std::conditional_t<PRE == 1, DirLoadJ<T, V>, DirLoad<T, V>>;
+        Load in;
+        if constexpr (PRE == 1)
+            in = Load{r, p_old, a.A.dinv, a.ld, vec_t<T, V>(0)};
+        else
+            in = Load{r, p_old, a.ld, vec_t<T, V>(0)};
 #pragma unroll
         for (int u = 0; u < V; ++u) in.beta[u] = T(s_beta[d.percol ? (c0 + u < a.k ? c0 + u : 0) : 0]);
         vec_t<T, V> pn;
@@ -224,8 +243,9 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, vb.nblk, lds);
 }
 
-// B: alpha from the p.q partials; x += alpha p; r += alpha q; partial r.r.
-template <typename T, int V>
+// B: alpha from the p.q partials; x += alpha p; r += alpha q; partial r.r
+// (and, with the Jacobi preconditioner, r.z with z = D^-1 r).
+template <typename T, int V, int PRE>
 __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
                        T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q) {
     if (d.st->done) return;
@@ -258,11 +278,12 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
         }
         return;
     }
-    double c[1][V] = {};
+    double c[1][V] = {}, cz[1][V] = {};
     FOR_ROWS {
         const int64_t o = row * a.ld + c0;
         vec_t<T, V> xv = ldv<T, V>(x + o), rv = ldv<T, V>(r + o);
         const vec_t<T, V> pv = ldv<T, V>(p + o), qv = ldv<T, V>(q + o);
+        const double di = PRE == 1 ? double(a.A.dinv[row]) : 0.0;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             if (c0 + u >= a.k) continue;
@@ -270,12 +291,61 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
             xv[u] += al * pv[u];
             rv[u] += al * qv[u];
             c[0][u] += double(rv[u]) * double(rv[u]);
+            if constexpr (PRE == 1) cz[0][u] += double(rv[u]) * (di * double(rv[u]));
         }
         stv_masked<T, V>(x + o, xv, a.k - c0);
         stv_masked<T, V>(r + o, rv, a.k - c0);
     }
     END_ROWS
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
+    if constexpr (PRE == 1) {
+        __syncthreads();
+        write_partials<1, V>(cz, sub, lpr, G, d.percol, d.part_b + 2 * int64_t(vb.nblk) * G, blk, vb.nblk, lds);
+    }
+}
+
+// One step j >= 1 of the Chebyshev semi-iteration for D^-1 A z = D^-1 r
+// (A = -L; Saad, Algorithm 12.1):
+//   d_j = c1 d_{j-1} + c2 D^-1 (r - A z_j),   z_{j+1} = z_j + d_j,
+// with c1 = rho_j rho_{j-1}, c2 = 2 rho_j / delta from the host.  FIRST: z_1 =
+// d_0 = D^-1 r / theta is formed on the fly from r.  LAST: d is not stored and
+// the partials of r.z_{j+1} go to the r.z slot of part_b.  The gather reads
+// zin (or r) and writes zout, so the two z buffers alternate.
+template <typename T, int V, bool Z, int WT, bool FIRST, bool LAST>
+__device__ void b_cheb(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__restrict__ r,
+                       const T *__restrict__ zin, T *__restrict__ zout, T *__restrict__ dv, T c1, T c2,
+                       T inv_theta) {
+    if (d.st->done) return;
+    __shared__ double lds[kMaxPercolBlock * kMaxV];
+    ROW_PROLOGUE
+    const int G = d.G;
+    const bool single = lpr * V >= a.k;
+    double c[1][V] = {};
+    FOR_ROWS {
+        const int64_t o = row * a.ld + c0;
+        vec_t<T, V> zj, acc;
+        if constexpr (FIRST)
+            acc = lap_row_ld<T, V, Z, WT>(a.A, ChebFirstLoad<T, V>{r, a.A.dinv, a.ld, inv_theta}, a.n_b, a.k, a.W,
+                                          row, c0, sub, lpr, single, zj);
+        else
+            acc = lap_row_ld<T, V, Z, WT>(a.A, PlainLoad<T, V>{zin, a.ld}, a.n_b, a.k, a.W, row, c0, sub, lpr,
+                                          single, zj);
+        const vec_t<T, V> rv = ldv<T, V>(r + o);
+        const vec_t<T, V> dprev = FIRST ? zj : ldv<T, V>(dv + o);
+        const T di = a.A.dinv[row];
+        const vec_t<T, V> dn = c1 * dprev + (c2 * di) * (rv + acc);  // r - A z = r + L z
+        const vec_t<T, V> zn = zj + dn;
+        if constexpr (!LAST) stv_masked<T, V>(dv + o, dn, a.k - c0);
+        stv_masked<T, V>(zout + o, zn, a.k - c0);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+                if (c0 + u < a.k) c[0][u] += double(rv[u]) * double(zn[u]);
+        }
+    }
+    END_ROWS
+    if constexpr (LAST)
+        write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b + 2 * int64_t(vb.nblk) * G, blk, vb.nblk, lds);
 }
 
 
@@ -385,7 +455,8 @@ struct BItem {
     CgDev d;
     const T *b;
     T *x, *bp, *r, *p0, *p1, *q;
-    Src rr, bb, pq;
+    T *z[2], *dv, *zf;  // Chebyshev: z buffers, d, and the buffer holding the final z
+    Src rr, bb, pq, rz;
     int nblk, first;
 };
 
@@ -406,7 +477,7 @@ __device__ __forceinline__ int find_item(const BItem<T> *items, int n) {
 
 // p' of iteration it: p0 on even iterations, p1 on odd ones; the previous
 // direction is r at it = 0 (p' = r + 0 r) and the other buffer afterwards.
-template <typename T, int V, bool Z, int WT>
+template <typename T, int V, bool Z, int WT, int PRE>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restrict__ items, int n, int it) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
@@ -414,12 +485,13 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restric
     const RowArgs<T> a = I.a;
     const CgDev d = I.d;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
-    T *pold = it == 0 ? I.r : ((it & 1) ? I.p0 : I.p1);
+    T *src = PRE == 2 ? I.zf : I.r;
+    T *pold = it == 0 ? src : ((it & 1) ? I.p0 : I.p1);
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_a<T, V, Z, WT>(a, d, vb, it, I.rr, I.bb, I.r, pold, pnew, I.q);
+    b_cg_a<T, V, Z, WT, PRE>(a, d, vb, it, I.rr, I.bb, I.rz, src, pold, pnew, I.q);
 }
 
-template <typename T, int V>
+template <typename T, int V, int PRE>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n, int it) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
@@ -428,7 +500,21 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     const CgDev d = I.d;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_b<T, V>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
+    b_cg_b<T, V, PRE>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
+}
+
+// Chebyshev step j >= 1 for every item: reads z buffer (j - 2) & 1 (r when
+// j == 1), writes buffer (j - 1) & 1.
+template <typename T, int V, bool Z, int WT, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kMaxCgBlock) void kb_cheb(const BItem<T> *__restrict__ items, int n, int j, T c1, T c2,
+                                                       T inv_theta) {
+    const BItem<T> &I = items[find_item(items, n)];
+    const int local = int(blockIdx.x) - I.first;
+    if (local >= I.nblk) return;
+    const RowArgs<T> a = I.a;
+    const CgDev d = I.d;
+    const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
+    b_cheb<T, V, Z, WT, FIRST, LAST>(a, d, vb, I.r, I.z[j & 1], I.z[(j - 1) & 1], I.dv, c1, c2, inv_theta);
 }
 
 // A fixed, nonzero right-hand side for timing CG tiles: a hash of the index
@@ -505,8 +591,8 @@ CgDev carve_cg(Carve &c, const fvx_op *op) {
     d.rho_last = c.take<double>(G);
     d.iters = c.take<int32_t>(G);
     d.part_a = c.take<double>(2 * mb * G);
-    d.part_b = c.take<double>(2 * mb * G);
-    d.tot = c.take<double>(4 * G);
+    d.part_b = c.take<double>(3 * mb * G);
+    d.tot = c.take<double>(6 * G);
     d.mean = c.take<double>(G);
     d.G = G;
     d.percol = op->percol ? 1 : 0;
@@ -517,12 +603,14 @@ CgDev carve_cg(Carve &c, const fvx_op *op) {
 struct Workspace {
     CgDev outer, inner;
     double *bp, *r, *p0, *p1, *q;
+    double *z[2], *dv;     // Chebyshev preconditioner buffers (FP64 CG)
     double *gmean, *gact;  // [G] host-filled per-group arrays (mixed outer loop)
     float *b32, *x32, *bp32, *r32, *p32a, *p32b, *q32;
+    float *z32[2], *dv32;  // Chebyshev preconditioner buffers (FP32 inner CG)
     size_t bytes;
 };
 
-Workspace carve(void *ws, const fvx_op *op, bool mixed) {
+Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb) {
     Carve c{static_cast<char *>(ws), 0};
     Workspace w{};
     const size_t nv = size_t(op->n_b) * op->ld;
@@ -532,6 +620,11 @@ Workspace carve(void *ws, const fvx_op *op, bool mixed) {
     w.p0 = c.take<double>(nv);
     w.p1 = c.take<double>(nv);
     w.q = c.take<double>(nv);
+    if (cheb && !mixed) {
+        w.z[0] = c.take<double>(nv);
+        w.z[1] = c.take<double>(nv);
+        w.dv = c.take<double>(nv);
+    }
     if (mixed) {
         w.inner = carve_cg(c, op);
         w.gmean = c.take<double>(groups_of(op));
@@ -543,6 +636,11 @@ Workspace carve(void *ws, const fvx_op *op, bool mixed) {
         w.p32a = c.take<float>(nv);
         w.p32b = c.take<float>(nv);
         w.q32 = c.take<float>(nv);
+        if (cheb) {
+            w.z32[0] = c.take<float>(nv);
+            w.z32[1] = c.take<float>(nv);
+            w.dv32 = c.take<float>(nv);
+        }
     }
     w.bytes = c.off;
     return w;
@@ -642,7 +740,51 @@ struct CgJob {
     bool given;
     double rtol;
     int max_iter;
+    T *z0 = nullptr, *z1 = nullptr, *dv = nullptr;  // Chebyshev buffers
 };
+
+// Preconditioner of a batch (the same for all its problems): kind 0 none,
+// 1 Jacobi, 2 Chebyshev with `degree` >= 2 steps (degree 1 is Jacobi up to a
+// constant factor, which CG does not see, so it runs as kind 1).  The step
+// coefficients follow Saad's Algorithm 12.1 on [2 / ratio, 2].
+struct Precond {
+    int kind = 0, degree = 1;
+    double inv_theta = 1.0;
+    std::vector<double> c1, c2;  // [degree]: step j uses c1[j], c2[j] (j >= 1)
+};
+
+Precond make_precond(const fvx_solve_opts *o) {
+    Precond pc;
+    if (o->precond == FVX_PRECOND_JACOBI || (o->precond == FVX_PRECOND_CHEBYSHEV && o->cheb_degree == 1)) {
+        pc.kind = 1;
+    } else if (o->precond == FVX_PRECOND_CHEBYSHEV) {
+        pc.kind = 2;
+        pc.degree = o->cheb_degree;
+        const double b = 2.0, a = b / o->cheb_ratio;
+        const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+        pc.inv_theta = 1.0 / theta;
+        pc.c1.assign(pc.degree, 0.0);
+        pc.c2.assign(pc.degree, 0.0);
+        double rho = 1.0 / sigma;
+        for (int j = 1; j < pc.degree; ++j) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            pc.c1[j] = rn * rho;
+            pc.c2[j] = 2.0 * rn / delta;
+            rho = rn;
+        }
+    }
+    return pc;
+}
+
+template <typename F>
+void by_pre(int kind, F &&f) {
+    if (kind == 1)
+        f(std::integral_constant<int, 1>{});
+    else if (kind == 2)
+        f(std::integral_constant<int, 2>{});
+    else
+        f(std::integral_constant<int, 0>{});
+}
 
 // Batched launches group jobs whose kernels share one instance: block size,
 // vector width, plane coupling and ELL width.
@@ -655,7 +797,8 @@ struct GroupKey {
 // (its own launches), then every iteration is one batched launch per phase and
 // group.  items_dev: device array for the launch descriptors (>= jobs.size()).
 template <typename T>
-void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *flags_dev, int poll, hipStream_t s) {
+void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *flags_dev, int poll, const Precond &pc,
+                  hipStream_t s) {
     if (jobs.empty()) return;
     std::vector<BItem<T>> items(jobs.size());
     std::vector<GroupKey> keys(jobs.size());
@@ -677,9 +820,16 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
                 mean = fold_or_direct(d, d.part_a, 1, nb, 0, d.tot + 3 * d.G, s);
             }
             if (J.given) launch_lap<T>(J.op, J.x, J.q, nullptr, s);
-            hipLaunchKernelGGL((k_cg_init<T, V>), c.grid, c.block, 0, s, c.a, d, mean, int(J.op->singular), J.b, J.bp,
-                               J.x, J.r, J.q, int(J.given));
+            if (pc.kind == 1)
+                hipLaunchKernelGGL((k_cg_init<T, V, 1>), c.grid, c.block, 0, s, c.a, d, mean, int(J.op->singular),
+                                   J.b, J.bp, J.x, J.r, J.q, int(J.given));
+            else
+                hipLaunchKernelGGL((k_cg_init<T, V, 0>), c.grid, c.block, 0, s, c.a, d, mean, int(J.op->singular),
+                                   J.b, J.bp, J.x, J.r, J.q, int(J.given));
             I.rr = fold_or_direct(d, d.part_b, 2, nb, 0, d.tot, s);
+            if (pc.kind == 1 && d.percol)
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_b + size_t(2) * nb * d.G, nb, d.G,
+                                   d.tot + 4 * d.G);
             FVX_HIP(hipGetLastError());
         });
         I.a = c.a;
@@ -691,8 +841,13 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         I.p0 = J.p0;
         I.p1 = J.p1;
         I.q = J.q;
+        I.z[0] = J.z0;
+        I.z[1] = J.z1;
+        I.dv = J.dv;
+        I.zf = pc.kind == 2 ? (pc.degree % 2 == 0 ? J.z0 : J.z1) : nullptr;  // written by step degree - 1
         I.bb = d.percol ? Src{d.tot + d.G, 1} : Src{d.part_b + size_t(nb) * d.G, nb};
         I.pq = d.percol ? Src{d.tot + 2 * d.G, 1} : Src{d.part_a, nb};
+        I.rz = d.percol ? Src{d.tot + 4 * d.G, 1} : Src{d.part_b + size_t(2) * nb * d.G, nb};
         I.nblk = nb;
         keys[j] = GroupKey{c.t.block, c.t.vec, int(J.op->zfaces), J.op->W};
     }
@@ -732,37 +887,86 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
     }
     FVX_HIP(hipMemcpyAsync(items_dev, packed.data(), sizeof(BItem<T>) * packed.size(), hipMemcpyHostToDevice, s));
     FVX_HIP(hipStreamSynchronize(s));
-    auto fold_percol = [&](const Launch &L, bool after_a) {
+    // Per-column groups fold their partials for the next kernel: 0 p.q (after
+    // A), 1 r.r (after B), 2 r.z (after B with Jacobi, after the last
+    // Chebyshev step).
+    auto fold_percol = [&](const Launch &L, int what) {
         for (int j : L.jobs) {
             const CgDev &d = jobs[j].d;
             if (!d.percol) continue;
-            if (after_a)
-                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_a, items[j].nblk, d.G, d.tot + 2 * d.G);
+            const int nb = items[j].nblk;
+            if (what == 0)
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_a, nb, d.G, d.tot + 2 * d.G);
+            else if (what == 1)
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_b, nb, d.G, d.tot);
             else
-                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_b, items[j].nblk, d.G, d.tot);
+                hipLaunchKernelGGL(k_fold, dim3(d.G), dim3(256), 0, s, d.part_b + size_t(2) * nb * d.G, nb, d.G,
+                                   d.tot + 4 * d.G);
         }
     };
+    // The Chebyshev preconditioner on the current r of every item.
+    auto cheb_pass = [&](const Launch &L) {
+        const BItem<T> *dev = items_dev + L.offset;
+        by_v<T>(L.key.vec, [&](auto Vt) {
+            constexpr int V = decltype(Vt)::value;
+            by_width(L.key.w, [&](auto Wt) {
+                constexpr int WT = decltype(Wt)::value;
+                for (int j = 1; j < pc.degree; ++j) {
+                    const T c1 = T(pc.c1[j]), c2 = T(pc.c2[j]), ith = T(pc.inv_theta);
+                    const bool first = j == 1, last = j == pc.degree - 1;
+                    auto go = [&](auto Zt, auto Ft, auto Lt) {
+                        hipLaunchKernelGGL((kb_cheb<T, V, decltype(Zt)::value, WT, decltype(Ft)::value,
+                                                    decltype(Lt)::value>),
+                                           dim3(L.blocks), dim3(L.key.block), 0, s, dev, L.n, j, c1, c2, ith);
+                    };
+                    auto by_fl = [&](auto Zt) {
+                        if (first && last)
+                            go(Zt, std::true_type{}, std::true_type{});
+                        else if (first)
+                            go(Zt, std::true_type{}, std::false_type{});
+                        else if (last)
+                            go(Zt, std::false_type{}, std::true_type{});
+                        else
+                            go(Zt, std::false_type{}, std::false_type{});
+                    };
+                    if (L.key.z)
+                        by_fl(std::true_type{});
+                    else
+                        by_fl(std::false_type{});
+                }
+            });
+        });
+        fold_percol(L, 2);
+    };
+    if (pc.kind == 2)
+        for (const Launch &L : launches) cheb_pass(L);
     int it = 0;
     while (true) {
         const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
         for (int i = 0; i < batch; ++i, ++it) {
             for (const Launch &L : launches) {
                 const BItem<T> *dev = items_dev + L.offset;
-                by_v<T>(L.key.vec, [&](auto Vt) {
-                    constexpr int V = decltype(Vt)::value;
-                    by_width(L.key.w, [&](auto Wt) {
-                        constexpr int WT = decltype(Wt)::value;
-                        if (L.key.z)
-                            hipLaunchKernelGGL((kb_cg_a<T, V, true, WT>), dim3(L.blocks), dim3(L.key.block), 0, s, dev,
-                                               L.n, it);
-                        else
-                            hipLaunchKernelGGL((kb_cg_a<T, V, false, WT>), dim3(L.blocks), dim3(L.key.block), 0, s,
-                                               dev, L.n, it);
+                by_pre(pc.kind, [&](auto Pt) {
+                    constexpr int PRE = decltype(Pt)::value;
+                    by_v<T>(L.key.vec, [&](auto Vt) {
+                        constexpr int V = decltype(Vt)::value;
+                        by_width(L.key.w, [&](auto Wt) {
+                            constexpr int WT = decltype(Wt)::value;
+                            if (L.key.z)
+                                hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE>), dim3(L.blocks), dim3(L.key.block),
+                                                   0, s, dev, L.n, it);
+                            else
+                                hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE>), dim3(L.blocks), dim3(L.key.block),
+                                                   0, s, dev, L.n, it);
+                        });
+                        fold_percol(L, 0);
+                        hipLaunchKernelGGL((kb_cg_b<T, V, PRE == 1 ? 1 : 0>), dim3(L.blocks), dim3(L.key.block), 0, s,
+                                           dev, L.n, it);
+                        fold_percol(L, 1);
+                        if (PRE == 1) fold_percol(L, 2);
                     });
-                    fold_percol(L, true);
-                    hipLaunchKernelGGL((kb_cg_b<T, V>), dim3(L.blocks), dim3(L.key.block), 0, s, dev, L.n, it);
-                    fold_percol(L, false);
                 });
+                if (pc.kind == 2) cheb_pass(L);
             }
         }
         FVX_HIP(hipGetLastError());
@@ -828,6 +1032,12 @@ void check_opts(const fvx_op *op, const fvx_solve_opts *o) {
                 "precision must be FVX_F64 or FVX_MIXED");
     FVX_REQUIRE(o->guess == FVX_GUESS_ZERO || o->guess == FVX_GUESS_GIVEN, FVX_E_ARG, "bad guess mode");
     FVX_REQUIRE(o->poll_every >= 1, FVX_E_ARG, "poll_every must be >= 1");
+    FVX_REQUIRE(o->precond == FVX_PRECOND_NONE || o->precond == FVX_PRECOND_JACOBI ||
+                    o->precond == FVX_PRECOND_CHEBYSHEV,
+                FVX_E_ARG, "unknown preconditioner");
+    if (o->precond == FVX_PRECOND_CHEBYSHEV)
+        FVX_REQUIRE(o->cheb_degree >= 1 && o->cheb_degree <= 16 && o->cheb_ratio > 1.0 && std::isfinite(o->cheb_ratio),
+                    FVX_E_ARG, "Chebyshev preconditioner: degree 1..16, ratio > 1");
     if (o->precision == FVX_MIXED) {
         FVX_REQUIRE(op->has_f32, FVX_E_ARG, "mixed precision needs an operator built with FP32 copies");
         FVX_REQUIRE(o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 1, FVX_E_ARG,
@@ -854,8 +1064,8 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
     std::vector<CgJob<double>> jobs;
     for (auto &p : P)
         jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
-                                     o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter});
-    run_cg_batch<double>(jobs, items, flags, o->poll_every, s);
+                                     o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter, p.w.z[0], p.w.z[1], p.w.dv});
+    run_cg_batch<double>(jobs, items, flags, o->poll_every, make_precond(o), s);
     for (auto &p : P) {
         p.h = read_state(p.w.outer, s);
         p.res2 = finish_f64(p.op, p.w.outer, p.X, p.w.bp, p.w.q, s);
@@ -888,8 +1098,8 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             }
             const bool given = o->guess == FVX_GUESS_GIVEN;
             if (given) launch_lap<double>(op, p.X, p.w.q, nullptr, s);
-            hipLaunchKernelGGL((k_cg_init<double, V>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), p.B,
-                               p.w.bp, p.X, p.w.r, p.w.q, int(given));
+            hipLaunchKernelGGL((k_cg_init<double, V, 0>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular),
+                               p.B, p.w.bp, p.X, p.w.r, p.w.q, int(given));
             FVX_HIP(hipGetLastError());
         });
         const auto t0 = host_totals(D, D.part_b, 2, nb, s);
@@ -955,11 +1165,11 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             // to half of what separates the outer residual from its target.
             const double inner_rtol = std::max(o->inner_rtol, need);
             jobs.push_back(CgJob<float>{op, p.w.inner, p.w.b32, p.w.x32, p.w.bp32, p.w.r32, p.w.p32a, p.w.p32b,
-                                        p.w.q32, false, inner_rtol, budget});
+                                        p.w.q32, false, inner_rtol, budget, p.w.z32[0], p.w.z32[1], p.w.dv32});
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;
-        run_cg_batch<float>(jobs, items, flags, o->poll_every, s);
+        run_cg_batch<float>(jobs, items, flags, o->poll_every, make_precond(o), s);
         for (Problem *pp : in_jobs) {
             Problem &p = *pp;
             const auto hi = read_state(p.w.inner, s);
@@ -992,7 +1202,7 @@ struct BatchLayout {
     std::vector<size_t> offs;
 };
 
-BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed) {
+BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed, bool cheb) {
     BatchLayout L;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -1003,7 +1213,7 @@ BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed) {
     L.items64 = take(sizeof(BItem<double>) * size_t(n));
     L.items32 = take(sizeof(BItem<float>) * size_t(n));
     L.flags = take(sizeof(int32_t) * size_t(n));
-    for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed).bytes));
+    for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed, cheb).bytes));
     L.total = off;
     return L;
 }
@@ -1019,7 +1229,8 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
                     FVX_E_ARG, "B[i] and X[i] must be 16-byte aligned");
     }
     const bool mixed = o->precision == FVX_MIXED;
-    const BatchLayout L = batch_layout(n, ops, mixed);
+    const bool cheb = make_precond(o).kind == 2;
+    const BatchLayout L = batch_layout(n, ops, mixed, cheb);
     FVX_REQUIRE(ws_bytes >= L.total, FVX_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
     char *base = static_cast<char *>(ws);
     std::vector<Problem> P(n);
@@ -1027,7 +1238,7 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
         P[i].op = ops[i];
         P[i].B = B[i];
         P[i].X = X[i];
-        P[i].w = carve(base + L.offs[i], ops[i], mixed);
+        P[i].w = carve(base + L.offs[i], ops[i], mixed, cheb);
     }
     if (mixed)
         solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32),
@@ -1051,7 +1262,7 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
 }  // namespace
 
 double guess_residual_ratio(const fvx_op *op, const double *B, const double *X, void *ws, hipStream_t s) {
-    const Workspace w = carve(ws, op, false);
+    const Workspace w = carve(ws, op, false, false);
     const CgDev D = w.outer;
     const Ctx<double> c(op);
     const int nb = c.g.n_blocks;
@@ -1065,8 +1276,8 @@ double guess_residual_ratio(const fvx_op *op, const double *B, const double *X, 
         }
         launch_lap<double>(op, X, w.q, nullptr, s);
         // given = 1: x is only read.
-        hipLaunchKernelGGL((k_cg_init<double, V>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), B, w.bp,
-                           const_cast<double *>(X), w.r, w.q, 1);
+        hipLaunchKernelGGL((k_cg_init<double, V, 0>), c.grid, c.block, 0, s, c.a, D, mean, int(op->singular), B,
+                           w.bp, const_cast<double *>(X), w.r, w.q, 1);
         FVX_HIP(hipGetLastError());
     });
     const auto t = host_totals(D, D.part_b, 2, nb, s);
@@ -1098,6 +1309,9 @@ int fvx_solve_opts_default(fvx_solve_opts *o) {
     o->max_outer = 50;
     o->guess = FVX_GUESS_ZERO;
     o->poll_every = 64;
+    o->precond = FVX_PRECOND_NONE;
+    o->cheb_degree = 4;
+    o->cheb_ratio = 30.0;
     return FVX_OK;
 }
 
@@ -1106,7 +1320,7 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *o, size_t *bytes) {
         fvx::check_opts(op, o);
         FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
         const fvx_op *ops[1] = {op};
-        *bytes = fvx::batch_layout(1, ops, o->precision == FVX_MIXED).total;
+        *bytes = fvx::batch_layout(1, ops, o->precision == FVX_MIXED, fvx::make_precond(o).kind == 2).total;
         return FVX_OK;
     });
 }
@@ -1129,7 +1343,7 @@ int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts 
     return guard([&] {
         FVX_REQUIRE(n >= 1 && ops && bytes, FVX_E_ARG, "bad argument");
         for (int i = 0; i < n; ++i) fvx::check_opts(ops[i], o);
-        *bytes = fvx::batch_layout(n, ops, o->precision == FVX_MIXED).total;
+        *bytes = fvx::batch_layout(n, ops, o->precision == FVX_MIXED, fvx::make_precond(o).kind == 2).total;
         return FVX_OK;
     });
 }

@@ -56,6 +56,9 @@ struct OpDev {
     // coefficient (13-point); NULL otherwise.
     const T *ell_v1 = nullptr;
     const T *w2 = nullptr;
+    // Jacobi scaling of the SPD form -L: 1 / (-diag) per base row (1 where
+    // the diagonal vanishes), shared by the k planes.
+    const T *dinv = nullptr;
 };
 
 }  // namespace fvx

@@ -121,6 +121,36 @@ struct DirLoad {
     __device__ __forceinline__ T scalar(int64_t row, int l) const { return R[row * ld + l] + beta[0] * P[row * ld + l]; }
 };
 
+// Direction of preconditioned CG with the Jacobi preconditioner formed on the
+// fly: p' = D^-1 r + beta p, D^-1 per base row (shared by the planes).
+template <typename T, int V>
+struct DirLoadJ {
+    const T *__restrict__ R;
+    const T *__restrict__ P;
+    const T *__restrict__ Dinv;
+    int ld;
+    vec_t<T, V> beta;
+    __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const {
+        return Dinv[row] * ldv<T, V>(R + row * ld + c0) + beta * ldv<T, V>(P + row * ld + c0);
+    }
+    __device__ __forceinline__ T scalar(int64_t row, int l) const {
+        return Dinv[row] * R[row * ld + l] + beta[0] * P[row * ld + l];
+    }
+};
+
+// First Chebyshev iterate z_1 = D^-1 r / theta, formed on the fly.
+template <typename T, int V>
+struct ChebFirstLoad {
+    const T *__restrict__ R;
+    const T *__restrict__ Dinv;
+    int ld;
+    T inv_theta;
+    __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const {
+        return (Dinv[row] * inv_theta) * ldv<T, V>(R + row * ld + c0);
+    }
+    __device__ __forceinline__ T scalar(int64_t row, int l) const { return (Dinv[row] * inv_theta) * R[row * ld + l]; }
+};
+
 // One base-block row: its WT off-diagonal column indices and values (padding
 // entries point at the row itself with value 0), diagonal, and coupling weight.
 template <typename T, int WT>

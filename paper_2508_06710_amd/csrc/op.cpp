@@ -290,7 +290,7 @@ struct Layout {
 
 struct Offsets {
     size_t ell_col, cf_face, f_c1, f_c2;
-    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2];
+    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2], dinv[2];
     size_t total;
 };
 
@@ -312,6 +312,7 @@ Offsets layout(const HostOp &h, bool f32) {
         o.f_invd[p] = L.take(v * fb);
         o.ell_v1[p] = L.take(v * h.ell_v1.size());
         o.w2[p] = L.take(v * h.w2.size());
+        o.dinv[p] = L.take(v * nb);
     }
     o.total = L.off;
     return o;
@@ -491,6 +492,13 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         put(o.f_invd[0], h.f_invd.data(), 8 * fb);
         put(o.ell_v1[0], h.ell_v1.data(), 8 * h.ell_v1.size());
         put(o.w2[0], h.w2.data(), 8 * h.w2.size());
+        std::vector<double> dinv(nb);
+        std::vector<float> dinv32(nb);
+        for (size_t i = 0; i < nb; ++i) {
+            dinv[i] = h.diag[i] != 0.0 ? 1.0 / -h.diag[i] : 1.0;
+            dinv32[i] = h.diag32[i] != 0.0f ? float(1.0 / -double(h.diag32[i])) : 1.0f;
+        }
+        put(o.dinv[0], dinv.data(), 8 * nb);
         std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232;
         if (f32) {
             v132 = fvx::cast<float>(h.ell_v1);
@@ -508,6 +516,7 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             put(o.cf_coef[1], cf32.data(), 4 * cf32.size());
             put(o.area[1], ar32.data(), 4 * nb);
             put(o.f_invd[1], fi32.data(), 4 * fb);
+            put(o.dinv[1], dinv32.data(), 4 * nb);
         }
         FVX_HIP(hipStreamSynchronize(s));
 
@@ -544,6 +553,7 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             D.inv_dz = T(1.0 / d->dz);
             D.ell_v1 = h.ell_v1.empty() ? nullptr : reinterpret_cast<const T *>(base + o.ell_v1[p]);
             D.w2 = h.w2.empty() ? nullptr : reinterpret_cast<const T *>(base + o.w2[p]);
+            D.dinv = reinterpret_cast<const T *>(base + o.dinv[p]);
         };
         fill(op->d64, 0, double{});
         if (f32) fill(op->d32, 1, float{});
