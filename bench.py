@@ -288,6 +288,7 @@ def main():
     ap.add_argument("--no-guess", action="store_true")
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--profile-stencil", action="store_true")
+    ap.add_argument("--profile-pcg", action="store_true")
     ap.add_argument("--guess-epochs", type=int, default=20)
     ap.add_argument("--guess-lr", type=float, default=1e-4)
     args = ap.parse_args()
@@ -315,6 +316,9 @@ def main():
         return
     if args.profile_stencil:
         stencil_profile_mode(fvx, inputs, torch)
+        return
+    if args.profile_pcg:
+        pcg_profile_mode(fvx, inputs, torch)
         return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
@@ -504,6 +508,7 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
         _, stm = op.solve(D, rtol=rtol, precision=fvx.MIXED, inner_rtol=1e-4)
     res["mixed_cg"] = {"s_to_1e-8": tm.ms() / 1e3, "inner_iters": stm["iters"], "outer": stm["outer"],
                        "relres_true": stm["relres_true"]}
+    res["poisson_pcg"] = pcg_leg(fvx, torch, op, D, rtol)
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
 
@@ -615,6 +620,45 @@ def stencil_profile_mode(fvx, inputs, torch):
         fvx.copy(dst[i % 2], src)
     torch.cuda.synchronize()
     log("stencil profile run done")
+
+
+def pcg_leg(fvx, torch, op, D, rtol):
+    """Preconditioned CG on the benchmark's projection right-hand side: Jacobi
+    and the Chebyshev polynomial (degree 8 on [2/300, 2], the library's
+    defaults), FP64 and mixed precision; the best of 3 timed solves each."""
+    out = {}
+    cases = {"jacobi": dict(precond=fvx.PRECOND_JACOBI),
+             "chebyshev": dict(precond=fvx.PRECOND_CHEBYSHEV),
+             "mixed_chebyshev": dict(precond=fvx.PRECOND_CHEBYSHEV, precision=fvx.MIXED)}
+    for name, kw in cases.items():
+        op.solve(D, rtol=rtol, **kw)
+        best, st = None, None
+        for _ in range(3):
+            tm = Timer(torch)
+            with tm:
+                _, st = op.solve(D, rtol=rtol, **kw)
+            best = tm.ms() if best is None else min(best, tm.ms())
+        o = op.solve_opts(**kw)
+        out[name] = {"s_to_1e-8": best / 1e3, "iters": st["iters"], "outer": st["outer"],
+                     "relres_true": st["relres_true"], "cheb_degree": int(o.cheb_degree),
+                     "cheb_ratio": float(o.cheb_ratio)}
+        log(f"pcg {name}: {best:.2f} ms, {st['iters']} iterations, true residual {st['relres_true']:.2e}")
+    return out
+
+
+def pcg_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 kernel traces of the Chebyshev-preconditioned
+    CG on the channel workload: one warm-up and one timed FP64 solve to 1e-8."""
+    spec, mesh, op = build_case(fvx, inputs, K_MAIN)
+    tune(op, fvx)
+    tune_cg(op, fvx)
+    u = inputs.normal(2, 0, op.F_b * op.k + op.n_b * op.k)
+    D = op.div(op.to_rows(u[:op.F_b * op.k], rows=op.F_b), op.to_rows(u[op.F_b * op.k:]))
+    for _ in range(2):
+        _, st = op.solve(D, rtol=1e-8, precond=fvx.PRECOND_CHEBYSHEV)
+    torch.cuda.synchronize()
+    log(f"pcg profile run done: {st['iters']} iterations, {st['seconds']:.4f} s, "
+        f"Chebyshev step bytes {5 * 8 * op.n_b * op.k + 16 * op.n_b} + matrix")
 
 
 def large_sweep(fvx, inputs, torch, np):

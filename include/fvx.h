@@ -325,8 +325,9 @@ typedef struct fvx_solve_stats {
 } fvx_solve_stats;
 
 /* Fills opts with defaults: rtol 1e-8, max_iter 100000, FP64, inner_rtol 1e-4,
- * max_outer 50, zero guess, poll_every 64, no preconditioner (cheb_degree 4,
- * cheb_ratio 30). */
+ * max_outer 50, zero guess, poll_every 64, no preconditioner (cheb_degree 8,
+ * cheb_ratio 300: the fastest FP64 setting measured on the 192 x 128 x 64
+ * channel). */
 int fvx_solve_opts_default(fvx_solve_opts *opts);
 
 /* Device workspace bytes for fvx_poisson_solve. */

@@ -344,7 +344,7 @@ class Operator:
 
     # ---- solves -----------------------------------------------------------
     def solve_opts(self, rtol=1e-8, max_iter=100000, precision=F64, inner_rtol=1e-4, max_outer=50,
-                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=4, cheb_ratio=30.0):
+                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=8, cheb_ratio=300.0):
         o = SolveOpts()
         check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
         o.rtol, o.max_iter, o.precision = float(rtol), int(max_iter), int(precision)

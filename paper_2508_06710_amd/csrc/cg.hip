@@ -1310,8 +1310,8 @@ int fvx_solve_opts_default(fvx_solve_opts *o) {
     o->guess = FVX_GUESS_ZERO;
     o->poll_every = 64;
     o->precond = FVX_PRECOND_NONE;
-    o->cheb_degree = 4;
-    o->cheb_ratio = 30.0;
+    o->cheb_degree = 8;
+    o->cheb_ratio = 300.0;
     return FVX_OK;
 }
 
