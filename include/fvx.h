@@ -66,6 +66,7 @@ enum { FVX_GUESS_NET = 2 };
 
 typedef struct fvx_mesh fvx_mesh;   /* host-side base mesh (face graph) */
 typedef struct fvx_op fvx_op;       /* operator: base block on the device + launch tiles */
+typedef struct fvx_sparse fvx_sparse; /* a general CSR matrix on the device (fvx_sparse_*) */
 typedef struct fvx_net fvx_net;     /* learned initial-guess network (device parameters) */
 
 /* Returns a static string naming a status code. */
@@ -482,6 +483,50 @@ int fvx_csr_solve_bytes(int64_t n_rows, size_t *bytes);
 int fvx_csr_poisson_solve(int64_t n_rows, int64_t nnz, const int32_t *ptr, const int32_t *col, const double *val,
                           const double *B, double *X, int singular, const fvx_solve_opts *opts,
                           void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* General sparse matrix times multivector (Section 2, Algorithm 1)     */
+/* ------------------------------------------------------------------ */
+/* Any n_rows x n_cols matrix A (rectangular allowed) given in CSR on the host
+ * (int32 ptr [n_rows+1] with ptr[0] = 0, int32 col [nnz] in 0..n_cols-1,
+ * finite double val [nnz]; duplicates allowed and summed), copied once into
+ * caller-owned device memory of fvx_sparse_bytes bytes (256-byte aligned;
+ * FP32 values too when with_f32).  The handle owns no device memory; the
+ * buffer must outlive it.  Errors: FVX_E_ARG for a malformed CSR, FVX_E_NOMEM
+ * for a short buffer. */
+int fvx_sparse_bytes(int64_t n_rows, int64_t nnz, int with_f32, size_t *bytes);
+int fvx_sparse_create(int64_t n_rows, int64_t n_cols, const int32_t *ptr, const int32_t *col, const double *val,
+                      int with_f32, void *dev_mem, size_t bytes, void *stream, fvx_sparse **out);
+int fvx_sparse_destroy(fvx_sparse *A);
+int fvx_sparse_shape(const fvx_sparse *A, int64_t *n_rows, int64_t *n_cols, int64_t *nnz);
+/* Launch tile (fvx_tile; stage_lds must be 0).  block 0 or NULL restores the
+ * default: the widest vector dividing ldx and ldy, lanes per row covering k,
+ * 256 threads, XCD remap.  All tiles give bitwise the same product. */
+int fvx_sparse_set_tile(fvx_sparse *A, int dtype, const fvx_tile *tile);
+/* Y = diag(colscale) (A X): X device [n_cols][ldx], Y device [n_rows][ldy],
+ * row-major multivectors of k columns (16-byte aligned; ldx a multiple of the
+ * tile's vector width holding k rounded up to it, ldy >= k; only the first k
+ * columns of Y are written).  colscale: device double [k] (one factor per
+ * column, e.g. one viscosity per parameter) or NULL.  Each stored entry of A
+ * is read once per row group and applied to all k columns in entry order with
+ * fused multiply-adds.  X and Y must not overlap. */
+int fvx_sparse_spmm(const fvx_sparse *A, int dtype, int k, const void *X, int ldx, void *Y, int ldy,
+                    const double *colscale, void *stream);
+
+/* Inline mesh refinement (Section 3.3) on a Cartesian base: fvx_mesh_refine
+ * splits every cell into rf x rf equal children (rf 1..16; the same periodic
+ * axes and walls); fvx_refine_prolongation gives the coarse-to-fine state
+ * mapping as a CSR matrix of (nx rf)(ny rf) rows and nx ny columns (rows and
+ * columns in the meshes' j*nx+i order): each fine value is the bilinear
+ * interpolation of the coarse cell-centre values at the fine centre, periodic
+ * axes wrapping across the period and wall-bounded axes taking the end
+ * centre's value beyond it (zero gradient at walls); rows sum to 1.  Call with
+ * ptr, col and val NULL for nnz, then with arrays of n_fine+1, nnz, nnz.
+ * Applied with fvx_sparse_spmm to all k states at once.  FVX_E_UNSUPPORTED
+ * for non-Cartesian meshes. */
+int fvx_mesh_refine(const fvx_mesh *coarse, int rf, fvx_mesh **fine);
+int fvx_refine_prolongation(const fvx_mesh *coarse, int rf, int64_t *nnz, int32_t *ptr, int32_t *col,
+                            double *val);
 
 /* Streaming device copy of `bytes` (multiple of 16, 16-byte aligned buffers):
  * the achievable-bandwidth reference of the roofline. */

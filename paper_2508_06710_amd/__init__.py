@@ -15,7 +15,7 @@ from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXE
                    PERIODIC_Z, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, FvxError, SolveOpts, SolveStats,
                    Tile, check, lib)
 
-__all__ = ["Mesh", "Operator", "GuessNet", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
+__all__ = ["Mesh", "Operator", "GuessNet", "SparseMatrix", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
            "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "lib"]
 
 
@@ -107,6 +107,25 @@ class Mesh:
         cx, cy = np.zeros(n), np.zeros(n)
         check(lib().fvx_mesh_centroids(self._h, _np_ptr(cx), _np_ptr(cy)), "fvx_mesh_centroids")
         return cx, cy
+
+    def refine(self, rf=2):
+        """The Cartesian mesh with every cell split into rf x rf children."""
+        h = C.c_void_p()
+        check(lib().fvx_mesh_refine(self._h, int(rf), C.byref(h)), "fvx_mesh_refine")
+        return Mesh(h)
+
+    def prolongation(self, rf=2):
+        """Host CSR (ptr, col, val) of the coarse-to-fine state mapping onto refine(rf)."""
+        nnz = C.c_int64()
+        check(lib().fvx_refine_prolongation(self._h, int(rf), C.byref(nnz), None, None, None),
+              "fvx_refine_prolongation")
+        n_fine = self.n_cells * rf * rf
+        ptr = np.zeros(n_fine + 1, np.int32)
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1))
+        check(lib().fvx_refine_prolongation(self._h, int(rf), C.byref(nnz), _np_ptr(ptr), _np_ptr(col),
+                                            _np_ptr(val)), "fvx_refine_prolongation")
+        return ptr, col[:nnz.value], val[:nnz.value]
 
     def faces(self):
         nc, nf, _ = self.info()
@@ -402,6 +421,52 @@ def solve_batch(ops, Bs, Xs=None, stream=None, allow_not_converged=False, **kw):
     rc = lib().fvx_poisson_solve_batch(n, oa, ba, xa, C.byref(opts), _ptr(ws), ws.numel(), st, _stream(stream))
     check(rc, "fvx_poisson_solve_batch", (0, 1) if allow_not_converged else (0,))
     return Xs, [st[i].as_dict() for i in range(n)]
+
+
+class SparseMatrix:
+    """A general CSR matrix on the device applied to row-major multivectors
+    (fvx_sparse_*): Y = diag(colscale) (A X) for k columns at once."""
+
+    def __init__(self, ptr, col, val, n_cols, with_f32=True, device=None, stream=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.ptr = np.ascontiguousarray(ptr, np.int32)
+        self.col = np.ascontiguousarray(col, np.int32)
+        self.val = np.ascontiguousarray(val, np.float64)
+        self.n_rows, self.n_cols = len(self.ptr) - 1, int(n_cols)
+        nbytes = C.c_size_t()
+        check(lib().fvx_sparse_bytes(self.n_rows, int(self.ptr[-1]), int(with_f32), C.byref(nbytes)),
+              "fvx_sparse_bytes")
+        self._mem = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(lib().fvx_sparse_create(self.n_rows, self.n_cols, _np_ptr(self.ptr), _np_ptr(self.col),
+                                      _np_ptr(self.val), int(with_f32), _ptr(self._mem), nbytes.value,
+                                      _stream(stream), C.byref(h)), "fvx_sparse_create")
+        self._h = h
+        self.nnz = int(self.ptr[-1])
+
+    def set_tile(self, vec=0, lanes_per_row=1, block=0, xcd_remap=1, max_blocks=0, nt_store=0, dtype=F64):
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), 0, int(nt_store))
+        check(lib().fvx_sparse_set_tile(self._h, dtype, C.byref(t)), "fvx_sparse_set_tile")
+
+    def spmm(self, X, Y=None, k=None, colscale=None, dtype=None, stream=None):
+        """X: device [n_cols][ldx] tensor; Y: device [n_rows][ldy] (allocated with ldy = ldx if None)."""
+        torch = _torch()
+        dt = dtype if dtype is not None else (F32 if str(X.dtype).endswith("float32") else F64)
+        ldx = X.shape[1]
+        k = ldx if k is None else int(k)
+        if Y is None:
+            Y = torch.zeros((self.n_rows, ldx), dtype=X.dtype, device=X.device)
+        check(lib().fvx_sparse_spmm(self._h, dt, k, _ptr(X), ldx, _ptr(Y), Y.shape[1], _ptr(colscale),
+                                    _stream(stream)), "fvx_sparse_spmm")
+        return Y
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            try:
+                lib().fvx_sparse_destroy(self._h)
+            except Exception:
+                pass
 
 
 class CsrMatrix:

@@ -109,6 +109,14 @@ SIGNATURES = {
     "fvx_csr_poisson_solve": (C.c_int, [_i64, _i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
                                         C.c_size_t, _P(SolveStats), _vp]),
     "fvx_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "fvx_sparse_bytes": (C.c_int, [_i64, _i64, C.c_int, _P(C.c_size_t)]),
+    "fvx_sparse_create": (C.c_int, [_i64, _i64, _vp, _vp, _vp, C.c_int, _vp, C.c_size_t, _vp, _P(C.c_void_p)]),
+    "fvx_sparse_destroy": (C.c_int, [_vp]),
+    "fvx_sparse_shape": (C.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
+    "fvx_sparse_set_tile": (C.c_int, [_vp, C.c_int, _vp]),
+    "fvx_sparse_spmm": (C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp, _vp]),
+    "fvx_mesh_refine": (C.c_int, [_vp, C.c_int, _P(C.c_void_p)]),
+    "fvx_refine_prolongation": (C.c_int, [_vp, C.c_int, _P(_i64), _vp, _vp, _vp]),
     "fvx_net_n_params": (C.c_int, []),
     "fvx_net_bytes": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _P(C.c_size_t)]),
     "fvx_net_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_size_t, _vp, _P(_vp)]),

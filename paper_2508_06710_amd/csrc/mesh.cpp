@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <tuple>
 
 #include "common.h"
@@ -79,22 +80,18 @@ const char *fvx_last_error(void) { return fvx::g_last_error.c_str(); }
 
 int fvx_version(void) { return 10000; }
 
-int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y1, double stretch,
-                       int periodic_x, int periodic_y, fvx_mesh **out) {
-    return guard([&] {
-        FVX_REQUIRE(out, FVX_E_ARG, "out is NULL");
-        FVX_REQUIRE(nx >= 1 && ny >= 1, FVX_E_ARG, "nx and ny must be >= 1");
-        FVX_REQUIRE(Lx > 0 && y1 > y0 && std::isfinite(stretch) && stretch >= 0, FVX_E_ARG,
-                    "empty extent or bad stretch");
-        auto m = new fvx_mesh();
-        std::vector<double> xf(nx + 1), yf(ny + 1);
-        for (int i = 0; i <= nx; ++i) xf[i] = x0 + Lx * double(i) / double(nx);
-        for (int j = 0; j <= ny; ++j) {
-            double t = double(j) / double(ny);
-            yf[j] = stretch == 0.0
-                        ? y0 + (y1 - y0) * t
-                        : y0 + (y1 - y0) * 0.5 * (1.0 + std::tanh(stretch * (2.0 * t - 1.0)) / std::tanh(stretch));
-        }
+}  // extern "C"
+
+namespace {
+
+// Cartesian face graph from the face coordinates of both axes: cell (i, j) is
+// j * nx + i; x-faces first, then y-faces; walls where an axis is not
+// periodic.
+fvx_mesh *cartesian_from_faces(const std::vector<double> &xf, const std::vector<double> &yf, int periodic_x,
+                               int periodic_y) {
+    const int nx = int(xf.size()) - 1, ny = int(yf.size()) - 1;
+    auto m = new fvx_mesh();
+    {
         const int nc = nx * ny;
         m->n_cells = nc;
         m->grid_nx = nx;
@@ -149,7 +146,125 @@ int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y
                 add_wall((ny - 1) * nx + i, xf[i + 1] - xf[i], half(yf, ny - 1));
             }
         m->n_walls = int(m->wcell.size());
-        *out = m;
+    }
+    return m;
+}
+
+// Centres of an axis and the coarse-centre interpolation of a point x:
+// (index, weight) pairs.  Between two centres: linear weights; past the first
+// or last centre of a wall-bounded axis: the end centre with weight 1; a
+// periodic axis wraps across the period.
+void axis_weights(const std::vector<double> &f, bool periodic, double x, std::vector<std::pair<int, double>> &out) {
+    const int n = int(f.size()) - 1;
+    out.clear();
+    std::vector<double> c(n);
+    for (int i = 0; i < n; ++i) c[i] = 0.5 * (f[i] + f[i + 1]);
+    if (n == 1) {
+        out.push_back({0, 1.0});
+        return;
+    }
+    const int hi = int(std::upper_bound(c.begin(), c.end(), x) - c.begin());  // first centre > x
+    if (hi > 0 && hi < n) {
+        const double t = (x - c[hi - 1]) / (c[hi] - c[hi - 1]);
+        out.push_back({hi - 1, 1.0 - t});
+        out.push_back({hi, t});
+        return;
+    }
+    if (!periodic) {
+        out.push_back({hi == 0 ? 0 : n - 1, 1.0});
+        return;
+    }
+    const double period = f[n] - f[0];
+    const double left = c[n - 1] - period, right = c[0] + period;  // images across the period
+    if (hi == 0) {
+        const double t = (x - left) / (c[0] - left);
+        out.push_back({n - 1, 1.0 - t});
+        out.push_back({0, t});
+    } else {
+        const double t = (x - c[n - 1]) / (right - c[n - 1]);
+        out.push_back({n - 1, 1.0 - t});
+        out.push_back({0, t});
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fvx_mesh_cartesian(int nx, int ny, double x0, double Lx, double y0, double y1, double stretch,
+                       int periodic_x, int periodic_y, fvx_mesh **out) {
+    return guard([&] {
+        FVX_REQUIRE(out, FVX_E_ARG, "out is NULL");
+        FVX_REQUIRE(nx >= 1 && ny >= 1, FVX_E_ARG, "nx and ny must be >= 1");
+        FVX_REQUIRE(Lx > 0 && y1 > y0 && std::isfinite(stretch) && stretch >= 0, FVX_E_ARG,
+                    "empty extent or bad stretch");
+        std::vector<double> xf(nx + 1), yf(ny + 1);
+        for (int i = 0; i <= nx; ++i) xf[i] = x0 + Lx * double(i) / double(nx);
+        for (int j = 0; j <= ny; ++j) {
+            double t = double(j) / double(ny);
+            yf[j] = stretch == 0.0
+                        ? y0 + (y1 - y0) * t
+                        : y0 + (y1 - y0) * 0.5 * (1.0 + std::tanh(stretch * (2.0 * t - 1.0)) / std::tanh(stretch));
+        }
+        *out = cartesian_from_faces(xf, yf, periodic_x, periodic_y);
+        return FVX_OK;
+    });
+}
+
+int fvx_mesh_refine(const fvx_mesh *coarse, int rf, fvx_mesh **fine) {
+    return guard([&] {
+        FVX_REQUIRE(coarse && fine, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(coarse->grid_nx > 0, FVX_E_UNSUPPORTED, "refinement needs a Cartesian base mesh");
+        FVX_REQUIRE(rf >= 1 && rf <= 16, FVX_E_ARG, "rf must be in 1..16");
+        auto split = [&](const std::vector<double> &f) {
+            std::vector<double> g;
+            for (size_t i = 0; i + 1 < f.size(); ++i)
+                for (int a = 0; a < rf; ++a) g.push_back(f[i] + (f[i + 1] - f[i]) * double(a) / double(rf));
+            g.push_back(f.back());
+            return g;
+        };
+        *fine = cartesian_from_faces(split(coarse->xf), split(coarse->yf), coarse->periodic_x, coarse->periodic_y);
+        return FVX_OK;
+    });
+}
+
+int fvx_refine_prolongation(const fvx_mesh *coarse, int rf, int64_t *nnz, int32_t *ptr, int32_t *col,
+                            double *val) {
+    return guard([&] {
+        FVX_REQUIRE(coarse && nnz, FVX_E_ARG, "NULL argument");
+        FVX_REQUIRE(coarse->grid_nx > 0, FVX_E_UNSUPPORTED, "refinement needs a Cartesian base mesh");
+        FVX_REQUIRE(rf >= 1 && rf <= 16, FVX_E_ARG, "rf must be in 1..16");
+        const int nx = coarse->grid_nx, ny = coarse->grid_ny, NX = nx * rf, NY = ny * rf;
+        std::vector<std::pair<int, double>> wx, wy;
+        std::vector<std::map<int32_t, double>> rows(size_t(NX) * NY);
+        for (int J = 0; J < NY; ++J) {
+            const int j = J / rf, b = J % rf;
+            const double hy = coarse->yf[j + 1] - coarse->yf[j];
+            axis_weights(coarse->yf, coarse->periodic_y, coarse->yf[j] + hy * (b + 0.5) / rf, wy);
+            for (int I = 0; I < NX; ++I) {
+                const int i = I / rf, a = I % rf;
+                const double hx = coarse->xf[i + 1] - coarse->xf[i];
+                axis_weights(coarse->xf, coarse->periodic_x, coarse->xf[i] + hx * (a + 0.5) / rf, wx);
+                auto &row = rows[size_t(J) * NX + I];
+                for (const auto &py : wy)
+                    for (const auto &px : wx) row[py.first * nx + px.first] += py.second * px.second;
+            }
+        }
+        int64_t total = 0;
+        for (const auto &r : rows) total += int64_t(r.size());
+        *nnz = total;
+        if (!ptr && !col && !val) return FVX_OK;
+        FVX_REQUIRE(ptr && col && val, FVX_E_ARG, "ptr, col and val must all be given");
+        int64_t e = 0;
+        ptr[0] = 0;
+        for (size_t r = 0; r < rows.size(); ++r) {
+            for (const auto &kv : rows[r]) {
+                col[e] = kv.first;
+                val[e] = kv.second;
+                ++e;
+            }
+            ptr[r + 1] = int32_t(e);
+        }
         return FVX_OK;
     });
 }
