@@ -425,6 +425,8 @@ def main():
     if not args.no_stencil:
         out["stencils"] = stencil_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
+        out["refine_mapping"] = refine_leg(fvx, inputs, torch, np)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
         torch.cuda.empty_cache()
@@ -620,6 +622,48 @@ def stencil_profile_mode(fvx, inputs, torch):
         fvx.copy(dst[i % 2], src)
     torch.cuda.synchronize()
     log("stencil profile run done")
+
+
+def refine_leg(fvx, inputs, torch, np):
+    """The inline-refinement coarse-to-fine mapping as a rectangular SpMM
+    (fvx_sparse_spmm): the 96 x 64 channel base refined twice in x and y
+    (24,576 fine rows, 6,144 coarse columns, bilinear weights) applied to
+    k flow states at once, k = 1, 16, 64, FP64 and FP32; bandwidth against
+    the HBM roofline and P_k = k t_1 / t_k beside Eq. 3a's bound for these
+    n_r, n_c and nnz."""
+    import oracle  # closed-form bound of Eq. 3a only
+    spec = inputs.channel_base(96, 64)
+    m = fvx.Mesh.from_spec(spec)
+    ptr, col, val = m.prolongation(2)
+    P = fvx.SparseMatrix(ptr, col, val, m.n_cells)
+    n_r, n_c, nnz = P.n_rows, P.n_cols, P.nnz
+    out, t1 = [], {}
+    for k in (1, 16, 64):
+        for name, tdt, v in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            ld = max(k, 4) if k > 1 else 1
+            R = max(3, math.ceil(COLD_BYTES / ((n_r + n_c) * ld * v)))
+            X = [torch.as_tensor(inputs.uniform(0, 0, n_c * ld).reshape(n_c, ld)).to(tdt).cuda() for _ in range(R)]
+            Y = [torch.empty((n_r, ld), dtype=tdt, device="cuda") for _ in range(R)]
+            for i in range(2):
+                P.spmm(X[i], Y[i], k=k)
+            tm = Timer(torch)
+            with tm:
+                for _ in range(2):
+                    for xx, yy in zip(X, Y):
+                        P.spmm(xx, yy, k=k)
+            t = tm.ms() / (2 * R)
+            del X, Y
+            B = (v + 4) * nnz + 4 * (n_r + 1) + v * (n_c + n_r) * k
+            if k == 1:
+                t1[name] = t
+            rec = {"k": k, "dtype": name, "n_rows": n_r, "n_cols": n_c, "nnz": nnz, "bytes_per_launch": B,
+                   "spmm_us": t * 1e3, "spmm_GBs": B / (t * 1e-3) / 1e9, "frac_hbm": B / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if k > 1:
+                rec.update({"P_k": k * t1[name] / t, "P_ub_eq3a": oracle.p_spmm_ub(nnz, n_r, n_c, k)})
+            out.append(rec)
+            log(f"refine mapping k={k} {name}: {rec['spmm_us']:.2f} us, {rec['spmm_GBs']:.0f} GB/s"
+                + (f", P_k {rec['P_k']:.1f} (Eq. 3a bound {rec['P_ub_eq3a']:.1f})" if k > 1 else ""))
+    return out
 
 
 def pcg_leg(fvx, torch, op, D, rtol):
