@@ -259,6 +259,18 @@ int fvx_lap_many(const fvx_op *op, int dtype, int n, const void *const *X, void 
  * D: device [n_b][ld]. */
 int fvx_div(const fvx_op *op, int dtype, const void *Uf, const void *Wz, void *D, void *stream);
 
+/* Convective operator C(u_s) = M U_s Pi (Section 3.1: the divergence of the
+ * face velocities times the face-interpolated cell values, Pi the midpoint
+ * interpolation):
+ *   Out[i][l] = sum_{faces f of i} (+-) len_f dz Uf[f][l] (Phi[i][l] + Phi[j][l]) / 2
+ *             + A_i (Wz[i][l] (Phi[i][l] + Phi[i][l+1]) - Wz[i][l-1] (Phi[i][l-1] + Phi[i][l])) / 2
+ * (j the cell across f; plane indices mod k).  Uf, Wz: face velocities as in
+ * fvx_div; Phi, Out: device [n_b][ld] (Out must not overlap the inputs).  For
+ * a divergence-free u_s (M u_s = 0) the operator is skew-symmetric, so it
+ * neither creates nor destroys the discrete kinetic energy. */
+int fvx_convect(const fvx_op *op, int dtype, const void *Uf, const void *Wz, const void *Phi, void *Out,
+                void *stream);
+
 /* Gradient SpMM, G = -Omega_s^{-1} M^T (Eq. 9b):
  *   Gf[f][l] = (P[c2][l] - P[c1][l]) / dist_f,   Gz[i][l] = (P[i][l+1 mod k] - P[i][l]) / dz
  * P: device [n_b][ld]; Gf: device [F_b][ld]; Gz: device [n_b][ld] (may be

@@ -346,6 +346,14 @@ class Operator:
         check(lib().fvx_div(self._h, dt, _ptr(Uf), _ptr(Wz), _ptr(D), _stream(stream)), "fvx_div")
         return D
 
+    def convect(self, Uf, Wz, Phi, Out=None, dtype=None, stream=None):
+        """Out = C(u_s) Phi = M U_s Pi Phi (fvx_convect)."""
+        dt = dtype if dtype is not None else (F32 if str(Phi.dtype).endswith("float32") else F64)
+        Out = self.empty(dtype=dt) if Out is None else Out
+        check(lib().fvx_convect(self._h, dt, _ptr(Uf), _ptr(Wz), _ptr(Phi), _ptr(Out), _stream(stream)),
+              "fvx_convect")
+        return Out
+
     def grad_axpy(self, alpha, P, Gf, Gz=None, dtype=None, stream=None):
         """Gf += alpha * G P (and Gz on the faces between planes)."""
         dt = dtype if dtype is not None else (F32 if str(P.dtype).endswith("float32") else F64)

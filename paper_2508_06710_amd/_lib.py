@@ -92,6 +92,7 @@ SIGNATURES = {
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_lap_many": (C.c_int, [_vp, C.c_int, C.c_int, _P(_vp), _P(_vp), _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "fvx_convect": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp]),
     "fvx_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_grad_axpy": (C.c_int, [_vp, C.c_int, C.c_double, _vp, _vp, _vp, _vp]),
     "fvx_pack": (C.c_int, [_vp, C.c_int, _i64, _vp, _vp, _vp]),

@@ -201,6 +201,56 @@ __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict_
     }
 }
 
+// Out = C(u_s) Phi = M U_s Pi Phi: the convective operator of Section 3.1 --
+// the divergence of the face fluxes u_f * (phi_c1 + phi_c2) / 2 (midpoint
+// interpolation of the cell values to the face).  Each cell gathers, for each
+// of its faces, the face velocity and the value of the cell across the face;
+// the faces between planes take the neighbouring planes from the row itself.
+template <typename T, int V, bool Z, int WT>
+__global__ __launch_bounds__(1024) void k_convect(RowArgs<T> a, const T *__restrict__ U, const T *__restrict__ Wz,
+                                                  const T *__restrict__ Phi, T *__restrict__ Out) {
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const bool single = lpr * V >= a.k;
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    const T half = T(0.5);
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;
+        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V) {
+            const vec_t<T, V> po = ldv<T, V>(Phi + row * a.ld + c0);
+            vec_t<T, V> acc = 0;
+            auto face = [&](int64_t f, T cf) {
+                const int64_t other = cf > T(0) ? a.A.f_c2[f] : a.A.f_c1[f];
+                const vec_t<T, V> uf = ldv<T, V>(U + f * a.ld + c0);
+                const vec_t<T, V> pn = ldv<T, V>(Phi + other * a.ld + c0);
+                acc += (cf * half) * (uf * (po + pn));
+            };
+            if constexpr (WT > 0) {
+#pragma unroll
+                for (int e = 0; e < WT; ++e) face(a.A.cf_face[e * a.n_b + row], a.A.cf_coef[e * a.n_b + row]);
+            } else {
+                for (int e = 0; e < a.Wd; ++e) face(a.A.cf_face[e * a.n_b + row], a.A.cf_coef[e * a.n_b + row]);
+            }
+            if constexpr (Z) {
+                const T ar = a.A.area[row];
+                const vec_t<T, V> wo = ldv<T, V>(Wz + row * a.ld + c0);
+                const auto nw = neighbours_of<T, V>(wo, PlainLoad<T, V>{Wz, a.ld}, row, c0, sub, lpr, a.k, single);
+                const auto np = neighbours_of<T, V>(po, PlainLoad<T, V>{Phi, a.ld}, row, c0, sub, lpr, a.k, single);
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const int l = c0 + q;
+                    const T up = wo[q] * (po[q] + right_of<T, V>(po, np, q, l, a.k));
+                    const T dn = left_of<T, V>(wo, nw, q) * (left_of<T, V>(po, np, q) + po[q]);
+                    acc[q] += (ar * half) * (up - dn);
+                }
+            }
+            stv_masked<T, V>(Out + row * a.ld + c0, acc, a.k - c0);
+        }
+    }
+}
+
 // Gf = G_b P on in-plane faces (rows [0, F_b)), Gz on the faces between
 // planes (rows [F_b, F_b + n_b)).
 template <typename T, int V, bool Z>
@@ -396,6 +446,20 @@ void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s) 
 }
 
 template <typename T>
+void launch_convect(const fvx_op *op, const T *U, const T *Wz, const T *Phi, T *Out, hipStream_t s) {
+    RowGrid g;
+    const fvx_tile &t = op->tile[dtype_of<T>()];
+    auto a = row_args<T>(op, op->n_b, g, t);
+    by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
+        by_width(op->Wd, [&](auto Wt) {
+            hipLaunchKernelGGL((k_convect<T, decltype(V)::value, decltype(Z)::value, decltype(Wt)::value>),
+                               dim3(g.n_blocks), dim3(t.block), 0, s, a, U, Wz, Phi, Out);
+        });
+    });
+    FVX_HIP(hipGetLastError());
+}
+
+template <typename T>
 void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s, double alpha, bool acc) {
     RowGrid g;
     const int64_t rows = op->F_b + (op->zfaces ? op->n_b : 0);
@@ -497,6 +561,27 @@ static int grad_impl(const fvx_op *op, int dtype, const void *P, void *Gf, void 
         else
             fvx::launch_grad<float>(op, static_cast<const float *>(P), static_cast<float *>(Gf),
                                     static_cast<float *>(Gz), fvx::as_stream(stream), alpha, acc);
+        return FVX_OK;
+    });
+}
+
+int fvx_convect(const fvx_op *op, int dtype, const void *Uf, const void *Wz, const void *Phi, void *Out,
+                void *stream) {
+    return guard([&] {
+        fvx::check_dtype(op, dtype);
+        fvx::check_ptr(Uf, "Uf");
+        fvx::check_ptr(Phi, "Phi");
+        fvx::check_ptr(Out, "Out");
+        FVX_REQUIRE(!op->zfaces || Wz, FVX_E_ARG, "Wz is required when the planes are coupled");
+        FVX_REQUIRE(Out != Phi && Out != Uf && (!Wz || Out != Wz), FVX_E_ARG, "Out must not overlap the inputs");
+        if (dtype == FVX_F64)
+            fvx::launch_convect<double>(op, static_cast<const double *>(Uf), static_cast<const double *>(Wz),
+                                        static_cast<const double *>(Phi), static_cast<double *>(Out),
+                                        fvx::as_stream(stream));
+        else
+            fvx::launch_convect<float>(op, static_cast<const float *>(Uf), static_cast<const float *>(Wz),
+                                       static_cast<const float *>(Phi), static_cast<float *>(Out),
+                                       fvx::as_stream(stream));
         return FVX_OK;
     });
 }
