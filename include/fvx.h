@@ -540,6 +540,33 @@ int fvx_mesh_refine(const fvx_mesh *coarse, int rf, fvx_mesh **fine);
 int fvx_refine_prolongation(const fvx_mesh *coarse, int rf, int64_t *nnz, int32_t *ptr, int32_t *col,
                             double *val);
 
+/* ------------------------------------------------------------------ */
+/* Incompressible time step (Sections 3 and 4)                          */
+/* ------------------------------------------------------------------ */
+/* One step of Heun's third-order Runge-Kutta scheme for the incompressible
+ * Navier-Stokes equations on the extruded mesh, with a projection at every
+ * stage (collocated velocities, symmetry-preserving operators):
+ *   Omega du/dt = -C(u_s) u + nu L_v u - Omega Gamma_sc G p,   M u_s = 0,
+ * C(u_s) = M U_s Pi (fvx_convect), L_v the viscous Laplacian of `visc` (NULL:
+ * op's own L; e.g. an operator with FVX_WALL_DIRICHLET for no-slip walls),
+ * Gamma_cs the cell-to-face interpolation u_s = n_f . (u_c1 + u_c2)/2 (and
+ * (w_l + w_{l+1})/2 between planes), Gamma_sc = Omega^-1 Gamma_cs^T Omega_s its
+ * volume-weighted adjoint.  A stage u* is projected by solving
+ * L phi = M Gamma_cs u* / (c dt) with fvx_poisson_solve(opts) and setting
+ * u_s = Gamma_cs u* - c dt G phi, u = u* - c dt Gamma_sc G phi; Heun's nodes
+ * are 0, 1/3, 2/3 and weights 1/4, 0, 3/4.
+ * U[3]: device double [n_b][ld] cell velocity components (in/out); Uf, Wz:
+ * face velocities as in fvx_div (in: those of U; out: divergence-free); P:
+ * device double [n_b][ld], out: phi of the last projection (its initial
+ * guess when opts->guess is FVX_GUESS_GIVEN).  dt > 0, nu >= 0.  ws: device
+ * workspace of fvx_ns_step_bytes bytes (256-byte aligned).  stats: the last
+ * solve's, with iters summed over the three projections.  FP64 only; needs
+ * face normals (Cartesian or triangle bases), else FVX_E_UNSUPPORTED. */
+int fvx_ns_step_bytes(const fvx_op *op, const fvx_solve_opts *opts, size_t *bytes);
+int fvx_ns_step(const fvx_op *op, const fvx_op *visc, double *const U[3], double *Uf, double *Wz, double *P,
+                double dt, double nu, const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
+                void *stream);
+
 /* Streaming device copy of `bytes` (multiple of 16, 16-byte aligned buffers):
  * the achievable-bandwidth reference of the roofline. */
 int fvx_copy(void *dst, const void *src, size_t bytes, void *stream);

@@ -403,6 +403,27 @@ class Operator:
         check(rc, "fvx_poisson_solve", allow)
         return X, st.as_dict()
 
+    def ns_step(self, U, Uf, Wz, P, dt, nu, visc=None, stream=None, allow_not_converged=False, **kw):
+        """One Heun-RK3 projection step (fvx_ns_step): U = [u, v, w] device
+        [n_b][ld] tensors, Uf/Wz face velocities, P pressure; all updated in
+        place.  Returns the stats dict (iters summed over the 3 projections)."""
+        torch = _torch()
+        opts = self.solve_opts(**kw)
+        nbytes = C.c_size_t()
+        check(lib().fvx_ns_step_bytes(self._h, C.byref(opts), C.byref(nbytes)), "fvx_ns_step_bytes")
+        key = ("ns", int(nbytes.value))
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        ua = (C.c_void_p * 3)(*[u.data_ptr() for u in U])
+        st = SolveStats()
+        rc = lib().fvx_ns_step(self._h, None if visc is None else visc._h, ua, _ptr(Uf), _ptr(Wz), _ptr(P),
+                               float(dt), float(nu), C.byref(opts), _ptr(ws), ws.numel(), C.byref(st),
+                               _stream(stream))
+        check(rc, "fvx_ns_step", (0, 1) if allow_not_converged else (0,))
+        return st.as_dict()
+
     def __del__(self):
         if getattr(self, "_h", None):
             try:

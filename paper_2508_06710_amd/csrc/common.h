@@ -25,6 +25,7 @@ struct fvx_mesh {
     std::vector<double> area, cx, cy;
     std::vector<int32_t> c1, c2;
     std::vector<double> len, dist;
+    std::vector<double> fnx, fny;  // unit face normal from c1 to c2 (empty when the builder has no geometry)
     std::vector<int32_t> wcell;
     std::vector<double> wlen, wdist;
 };
@@ -59,6 +60,13 @@ struct OpDev {
     // Jacobi scaling of the SPD form -L: 1 / (-diag) per base row (1 where
     // the diagonal vanishes), shared by the k planes.
     const T *dinv = nullptr;
+    // Velocity interpolation of the time step (NULL when the mesh has no face
+    // normals): cell -> face, u_f = n_f . (u_c1 + u_c2) / 2; face -> cell,
+    // the adjoint weighted by face and cell volumes,
+    //   (Gamma_sc g)_c = sum_f (len_f dist_f / (2 area_c)) n_f g_f.
+    const T *fnx = nullptr, *fny = nullptr;   // [F_b]
+    const T *gsx = nullptr, *gsy = nullptr;   // [F_b] len_f dist_f n_f / 2
+    const T *inv_area = nullptr;              // [n_b]
 };
 
 }  // namespace fvx
@@ -152,6 +160,8 @@ template <typename T>
 void launch_lap(const fvx_op *op, const T *X, T *Y, const double *colscale, hipStream_t s);
 template <typename T>
 void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s);
+template <typename T>
+void launch_convect(const fvx_op *op, const T *U, const T *Wz, const T *Phi, T *Out, hipStream_t s);
 template <typename T>
 void launch_grad(const fvx_op *op, const T *P, T *Gf, T *Gz, hipStream_t s, double alpha = 1.0,
                  bool acc = false);

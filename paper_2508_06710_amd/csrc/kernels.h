@@ -465,6 +465,28 @@ __device__ __forceinline__ vec_t<T, V> stencil_apply_pass(const StencilPasses<T,
     return acc;
 }
 
+// Picks the kernel instance for (vec, planes coupled); vec * sizeof(T) <= 16.
+template <typename T, typename F>
+void by_vec(int vec, bool z, F &&f) {
+    auto go = [&](auto vtag) {
+        constexpr int V = decltype(vtag)::value;
+        if constexpr (V * sizeof(T) <= 16) {
+            if (z)
+                f(std::integral_constant<int, V>{}, std::true_type{});
+            else
+                f(std::integral_constant<int, V>{}, std::false_type{});
+        } else {
+            throw Error(FVX_E_ARG, "vector width too large for this precision");
+        }
+    };
+    switch (vec) {
+        case 1: go(std::integral_constant<int, 1>{}); break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 4: go(std::integral_constant<int, 4>{}); break;
+        default: throw Error(FVX_E_ARG, "bad vector width");
+    }
+}
+
 // Launch arguments of a row-tiled kernel (lanes_per_row lanes per row,
 // tiles of rows_per_tile rows, tiles_per_block consecutive tiles per block).
 template <typename T>

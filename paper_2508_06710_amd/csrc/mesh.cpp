@@ -110,24 +110,26 @@ fvx_mesh *cartesian_from_faces(const std::vector<double> &xf, const std::vector<
                 m->cx[c] = 0.5 * (xf[i] + xf[i + 1]);
                 m->cy[c] = 0.5 * (yf[j] + yf[j + 1]);
             }
-        auto add_face = [&](int a, int b, double l, double d) {
+        auto add_face = [&](int a, int b, double l, double d, double nxv, double nyv) {
             m->c1.push_back(a);
             m->c2.push_back(b);
             m->len.push_back(l);
             m->dist.push_back(d);
+            m->fnx.push_back(nxv);
+            m->fny.push_back(nyv);
         };
         auto half = [](const std::vector<double> &f, int i) { return 0.5 * (f[i + 1] - f[i]); };
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 if (i == nx - 1 && !periodic_x) continue;
                 const int ip = (i + 1) % nx;
-                add_face(j * nx + i, j * nx + ip, yf[j + 1] - yf[j], half(xf, i) + half(xf, ip));
+                add_face(j * nx + i, j * nx + ip, yf[j + 1] - yf[j], half(xf, i) + half(xf, ip), 1.0, 0.0);
             }
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 if (j == ny - 1 && !periodic_y) continue;
                 const int jp = (j + 1) % ny;
-                add_face(j * nx + i, jp * nx + i, xf[i + 1] - xf[i], half(yf, j) + half(yf, jp));
+                add_face(j * nx + i, jp * nx + i, xf[i + 1] - xf[i], half(yf, j) + half(yf, jp), 0.0, 1.0);
             }
         m->n_faces = int(m->c1.size());
         auto add_wall = [&](int c, double l, double d) {
@@ -312,12 +314,15 @@ int fvx_mesh_triangles(int n_pts, const double *xy, int n_tri, const int32_t *tr
             const int ta = std::get<2>(e[i]);
             if (j - i == 2) {
                 const int tb = std::get<2>(e[i + 1]);
-                const double d = std::fabs(nxv * (m->cx[tb] - m->cx[ta]) + nyv * (m->cy[tb] - m->cy[ta]));
+                const double dn = nxv * (m->cx[tb] - m->cx[ta]) + nyv * (m->cy[tb] - m->cy[ta]);
+                const double d = std::fabs(dn);
                 FVX_REQUIRE(d > 0.0, FVX_E_MESH, "zero centroid distance across a face");
                 m->c1.push_back(ta);
                 m->c2.push_back(tb);
                 m->len.push_back(l);
                 m->dist.push_back(d);
+                m->fnx.push_back(dn > 0 ? nxv : -nxv);  // oriented from ta to tb
+                m->fny.push_back(dn > 0 ? nyv : -nyv);
             } else {
                 m->wcell.push_back(ta);
                 m->wlen.push_back(l);

@@ -19,6 +19,7 @@ struct HostOp {
     int W = 0, Wd = 0;
     std::vector<double> diag, w, ell_val, area, cf_coef, f_invd;
     std::vector<double> ell_v1, w2;  // structured 13/27-point operators only
+    std::vector<double> fnx, fny, gsx, gsy, inv_area;  // velocity interpolation (meshes with face normals)
     std::vector<int32_t> ell_col, cf_face, f_c1, f_c2;
     // FP32 copies: diagonal rebuilt in FP32 so that rows sum to zero up to
     // FP32 rounding of that sum.
@@ -276,6 +277,18 @@ void build_div_grad(const fvx_mesh &m, const fvx_op_desc &d, HostOp &h) {
     h.f_c2 = m.c2;
     h.f_invd.resize(m.n_faces);
     for (int f = 0; f < m.n_faces; ++f) h.f_invd[f] = 1.0 / m.dist[f];
+    if (m.n_faces > 0 && m.fnx.size() == size_t(m.n_faces)) {
+        h.fnx = m.fnx;
+        h.fny = m.fny;
+        h.gsx.resize(m.n_faces);
+        h.gsy.resize(m.n_faces);
+        for (int f = 0; f < m.n_faces; ++f) {
+            h.gsx[f] = 0.5 * m.len[f] * m.dist[f] * m.fnx[f];
+            h.gsy[f] = 0.5 * m.len[f] * m.dist[f] * m.fny[f];
+        }
+        h.inv_area.resize(m.n_cells);
+        for (int c = 0; c < m.n_cells; ++c) h.inv_area[c] = 1.0 / m.area[c];
+    }
 }
 
 // Byte layout of the device image; every array starts on a 256-byte boundary.
@@ -291,6 +304,7 @@ struct Layout {
 struct Offsets {
     size_t ell_col, cf_face, f_c1, f_c2;
     size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2], dinv[2];
+    size_t fnx[2], fny[2], gsx[2], gsy[2], inv_area[2];
     size_t total;
 };
 
@@ -313,6 +327,11 @@ Offsets layout(const HostOp &h, bool f32) {
         o.ell_v1[p] = L.take(v * h.ell_v1.size());
         o.w2[p] = L.take(v * h.w2.size());
         o.dinv[p] = L.take(v * nb);
+        o.fnx[p] = L.take(v * h.fnx.size());
+        o.fny[p] = L.take(v * h.fny.size());
+        o.gsx[p] = L.take(v * h.gsx.size());
+        o.gsy[p] = L.take(v * h.gsy.size());
+        o.inv_area[p] = L.take(v * h.inv_area.size());
     }
     o.total = L.off;
     return o;
@@ -499,6 +518,11 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             dinv32[i] = h.diag32[i] != 0.0f ? float(1.0 / -double(h.diag32[i])) : 1.0f;
         }
         put(o.dinv[0], dinv.data(), 8 * nb);
+        for (auto pr : {std::make_pair(o.fnx[0], &h.fnx), std::make_pair(o.fny[0], &h.fny),
+                        std::make_pair(o.gsx[0], &h.gsx), std::make_pair(o.gsy[0], &h.gsy),
+                        std::make_pair(o.inv_area[0], &h.inv_area)})
+            put(pr.first, pr.second->data(), 8 * pr.second->size());
+        std::vector<float> nv32[5];
         std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232;
         if (f32) {
             v132 = fvx::cast<float>(h.ell_v1);
@@ -517,6 +541,12 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             put(o.area[1], ar32.data(), 4 * nb);
             put(o.f_invd[1], fi32.data(), 4 * fb);
             put(o.dinv[1], dinv32.data(), 4 * nb);
+            const std::vector<double> *src[5] = {&h.fnx, &h.fny, &h.gsx, &h.gsy, &h.inv_area};
+            const size_t dst[5] = {o.fnx[1], o.fny[1], o.gsx[1], o.gsy[1], o.inv_area[1]};
+            for (int q = 0; q < 5; ++q) {
+                nv32[q] = fvx::cast<float>(*src[q]);
+                put(dst[q], nv32[q].data(), 4 * nv32[q].size());
+            }
         }
         FVX_HIP(hipStreamSynchronize(s));
 
@@ -554,6 +584,13 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             D.ell_v1 = h.ell_v1.empty() ? nullptr : reinterpret_cast<const T *>(base + o.ell_v1[p]);
             D.w2 = h.w2.empty() ? nullptr : reinterpret_cast<const T *>(base + o.w2[p]);
             D.dinv = reinterpret_cast<const T *>(base + o.dinv[p]);
+            if (!h.fnx.empty()) {
+                D.fnx = reinterpret_cast<const T *>(base + o.fnx[p]);
+                D.fny = reinterpret_cast<const T *>(base + o.fny[p]);
+                D.gsx = reinterpret_cast<const T *>(base + o.gsx[p]);
+                D.gsy = reinterpret_cast<const T *>(base + o.gsy[p]);
+                D.inv_area = reinterpret_cast<const T *>(base + o.inv_area[p]);
+            }
         };
         fill(op->d64, 0, double{});
         if (f32) fill(op->d32, 1, float{});

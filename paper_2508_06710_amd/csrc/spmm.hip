@@ -303,27 +303,6 @@ __global__ void k_pack(int64_t n_rows, int k, int ld, const T *__restrict__ src,
     }
 }
 
-// Picks the kernel instance for (vec, planes coupled); vec * sizeof(T) <= 16.
-template <typename T, typename F>
-void by_vec(int vec, bool z, F &&f) {
-    auto go = [&](auto vtag) {
-        constexpr int V = decltype(vtag)::value;
-        if constexpr (V * sizeof(T) <= 16) {
-            if (z)
-                f(std::integral_constant<int, V>{}, std::true_type{});
-            else
-                f(std::integral_constant<int, V>{}, std::false_type{});
-        } else {
-            throw Error(FVX_E_ARG, "vector width too large for this precision");
-        }
-    };
-    switch (vec) {
-        case 1: go(std::integral_constant<int, 1>{}); break;
-        case 2: go(std::integral_constant<int, 2>{}); break;
-        case 4: go(std::integral_constant<int, 4>{}); break;
-        default: throw Error(FVX_E_ARG, "bad vector width");
-    }
-}
 
 void check_ptr(const void *p, const char *what) {
     FVX_REQUIRE(p, FVX_E_ARG, std::string(what) + " is NULL");
@@ -484,6 +463,9 @@ template void launch_lap<double>(const fvx_op *, const double *, double *, const
 template void launch_lap<float>(const fvx_op *, const float *, float *, const double *, hipStream_t);
 template void launch_div<double>(const fvx_op *, const double *, const double *, double *, hipStream_t);
 template void launch_div<float>(const fvx_op *, const float *, const float *, float *, hipStream_t);
+template void launch_convect<double>(const fvx_op *, const double *, const double *, const double *, double *,
+                                     hipStream_t);
+template void launch_convect<float>(const fvx_op *, const float *, const float *, const float *, float *, hipStream_t);
 template void launch_grad<double>(const fvx_op *, const double *, double *, double *, hipStream_t, double, bool);
 template void launch_grad<float>(const fvx_op *, const float *, float *, float *, hipStream_t, double, bool);
 template void launch_pack<double>(const fvx_op *, int64_t, const double *, double *, bool, hipStream_t);

@@ -64,3 +64,44 @@ def test_skew_symmetric_for_divergence_free_velocity(spec, k, coupling):
     assert np.max(np.abs(C + C.T)) <= 1e-10 * np.abs(C).max()
     phi = inputs.uniform(82, 0, m3.N)
     assert abs(phi @ C @ phi) <= 1e-10 * np.abs(C).max() * (phi @ phi)
+
+
+def test_uniform_velocity_survives_interpolation_both_ways():
+    """Gamma_sc Gamma_cs reproduces a uniform velocity on a uniform periodic
+    box (the normal and volume-weight conventions of both operators)."""
+    spec = inputs.CartSpec(6, 5, 1.2, 0.0, 1.0, 0.0, True, True)
+    m3 = oracle.Mesh3D(oracle.geometry(spec), 4, 0.3, oracle.PERIODIC_Z)
+    o = ns.NSOracle(spec, m3)
+    U = np.concatenate([np.full(m3.N, 0.7), np.full(m3.N, -1.3), np.full(m3.N, 0.4)])
+    assert np.max(np.abs(o.Gsc @ (o.Gcs @ U) - U)) <= 1e-13
+
+
+def test_triangle_normals_are_unit_and_oriented():
+    spec = inputs.unit_square_triangles(4)
+    g = oracle.geometry(spec)
+    nx, ny = ns.face_normals(spec, g)
+    assert np.allclose(np.hypot(nx, ny), 1.0, atol=1e-14)
+    assert np.all(nx * (g.cx[g.c2] - g.cx[g.c1]) + ny * (g.cy[g.c2] - g.cy[g.c1]) > 0)
+
+
+def _tgv_error(n, nu=0.1, T=0.25, steps=25):
+    spec = inputs.CartSpec(n, n, 2 * math.pi, 0.0, 2 * math.pi, 0.0, True, True)
+    m3 = oracle.Mesh3D(oracle.geometry(spec), 1, 1.0, oracle.PERIODIC_Z)
+    o = ns.NSOracle(spec, m3)
+    g = m3.g
+    U = [np.sin(g.cx) * np.cos(g.cy), -np.cos(g.cx) * np.sin(g.cy), np.zeros(m3.N)]
+    U, us, _ = o.project(U, 1.0, 1e-13)
+    dt = T / steps
+    for _ in range(steps):
+        U, us, _ = o.step(U, us, dt, nu)
+    decay = math.exp(-2 * nu * T)
+    ex = np.sin(g.cx) * np.cos(g.cy) * decay
+    return np.max(np.abs(U[0] - ex)), np.max(np.abs(o.M @ us))
+
+
+def test_taylor_green_vortex_second_order_and_divergence_free():
+    e16, d16 = _tgv_error(16)
+    e32, d32 = _tgv_error(32)
+    rate = math.log2(e16 / e32)
+    assert 1.8 <= rate <= 2.3, (e16, e32, rate)
+    assert d16 <= 1e-11 and d32 <= 1e-11
