@@ -289,6 +289,8 @@ def main():
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--profile-stencil", action="store_true")
     ap.add_argument("--profile-pcg", action="store_true")
+    ap.add_argument("--profile-ns", action="store_true")
+    ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--guess-epochs", type=int, default=20)
     ap.add_argument("--guess-lr", type=float, default=1e-4)
     args = ap.parse_args()
@@ -320,9 +322,12 @@ def main():
     if args.profile_pcg:
         pcg_profile_mode(fvx, inputs, torch)
         return
+    if args.profile_ns:
+        ns_profile_mode(fvx, inputs, torch)
+        return
     if args.profile:
         args.steps, args.warmup, args.no_cpu, args.no_sweep = 2, 1, True, True
-        args.no_batch = args.no_airfoil = args.no_guess = args.no_stencil = True
+        args.no_batch = args.no_airfoil = args.no_guess = args.no_stencil = args.no_ns = True
 
     rtol = 1e-8
     log("building the channel operator")
@@ -426,6 +431,9 @@ def main():
         out["stencils"] = stencil_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
         out["refine_mapping"] = refine_leg(fvx, inputs, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_ns:
+        out["ns_step"] = ns_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
@@ -664,6 +672,71 @@ def refine_leg(fvx, inputs, torch, np):
             log(f"refine mapping k={k} {name}: {rec['spmm_us']:.2f} us, {rec['spmm_GBs']:.0f} GB/s"
                 + (f", P_k {rec['P_k']:.1f} (Eq. 3a bound {rec['P_ub_eq3a']:.1f})" if k > 1 else ""))
     return out
+
+
+def ns_leg(fvx, inputs, torch, np, rtol=1e-8):
+    """The whole incompressible time step (Heun RK3, a projection per stage,
+    Chebyshev-preconditioned Poisson solves warm-started from the previous
+    pressure) on the channel base: the coupled 192 x 128 x 64 channel, and
+    independent flow states (the base plane repeated k = 1, 16, 64 times
+    without coupling) for the whole-iteration speed-up P_k,ite = k t_1 / t_k
+    (the paper's P_m,ite).  Random initial velocities, projected by the
+    warm-up steps; the mean of 3 timed steps."""
+    spec = inputs.channel_base(*BASE)
+    mesh = fvx.Mesh.from_spec(spec)
+    out = {}
+    kw = dict(rtol=rtol, precond=fvx.PRECOND_CHEBYSHEV, guess=fvx.GUESS_GIVEN)
+
+    def run(op, label):
+        U = [op.to_rows(inputs.uniform(0, d, op.n_b * op.k)) for d in range(3)]
+        Uf = op.zeros(op.F_b)
+        Wz = op.zeros() if op.zfaces else None
+        P = op.zeros()
+        dt, nu = 1e-3, 1.0 / 180.0
+        for _ in range(2):
+            op.ns_step(U, Uf, Wz, P, dt, nu, **kw)
+        tm = Timer(torch)
+        its = 0
+        with tm:
+            for _ in range(3):
+                st = op.ns_step(U, Uf, Wz, P, dt, nu, **kw)
+                its += st["iters"]
+        t = tm.ms() / 3
+        log(f"ns step {label}: {t:.2f} ms per step, {its / 3:.0f} CG iterations per step")
+        return {"ms_per_step": t, "cg_iters_per_step": its / 3, "cells": op.n_b * op.k}
+
+    op = fvx.Operator(mesh, K_MAIN, math.pi / K_MAIN, fvx.PERIODIC_Z, with_f32=False)
+    tune(op, fvx)
+    tune_cg(op, fvx)
+    out["channel_coupled_k64"] = run(op, "coupled channel k=64")
+    del op
+    states = {}
+    for k in (1, 16, 64):
+        opk = fvx.Operator(mesh, k, math.pi / K_MAIN, fvx.NONE, with_f32=False)
+        tune(opk, fvx)
+        states[k] = run(opk, f"independent states k={k}")
+        del opk
+        torch.cuda.empty_cache()
+    for k in (16, 64):
+        states[k]["P_k_ite"] = k * states[1]["ms_per_step"] / states[k]["ms_per_step"]
+    out["independent_states"] = {str(k): v for k, v in states.items()}
+    return out
+
+
+def ns_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 kernel traces of the time step on the coupled
+    channel (192 x 128 x 64): two steps."""
+    spec = inputs.channel_base(*BASE)
+    op = fvx.Operator(fvx.Mesh.from_spec(spec), K_MAIN, math.pi / K_MAIN, fvx.PERIODIC_Z, with_f32=False)
+    tune(op, fvx)
+    tune_cg(op, fvx)
+    U = [op.to_rows(inputs.uniform(0, d, op.n_b * op.k)) for d in range(3)]
+    Uf, Wz, P = op.zeros(op.F_b), op.zeros(), op.zeros()
+    for _ in range(2):
+        st = op.ns_step(U, Uf, Wz, P, 1e-3, 1.0 / 180.0, rtol=1e-8, precond=fvx.PRECOND_CHEBYSHEV,
+                        guess=fvx.GUESS_GIVEN)
+    torch.cuda.synchronize()
+    log(f"ns profile run done: {st['iters']} CG iterations in the last step")
 
 
 def pcg_leg(fvx, torch, op, D, rtol):
