@@ -523,6 +523,29 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
     return res
 
 
+def graph_time(torch, calls):
+    """Mean time per call of a list of launches captured once in a HIP graph
+    (so that the launches are not paced by the Python loop); the graph is
+    replayed once untimed and twice timed."""
+    calls[0]()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph):
+            for f in calls:
+                f()
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()
+    tm = Timer(torch)
+    with tm:
+        graph.replay()
+        graph.replay()
+    t = tm.ms() / (2 * len(calls))
+    del graph
+    return t
+
+
 def time_csr_spmv(fvx, torch, inputs, ptr, col, val, n3):
     """Mean time of the assembled 3D CSR SpMV over rotating vectors, its
     sweep captured once in a HIP graph so that the launches are not paced by
@@ -638,7 +661,8 @@ def refine_leg(fvx, inputs, torch, np):
     (24,576 fine rows, 6,144 coarse columns, bilinear weights) applied to
     k flow states at once, k = 1, 16, 64, FP64 and FP32; bandwidth against
     the HBM roofline and P_k = k t_1 / t_k beside Eq. 3a's bound for these
-    n_r, n_c and nnz."""
+    n_r, n_c and nnz.  The sweep over rotating buffers is captured in a HIP
+    graph, so the launches are not paced by the Python loop."""
     import oracle  # closed-form bound of Eq. 3a only
     spec = inputs.channel_base(96, 64)
     m = fvx.Mesh.from_spec(spec)
@@ -652,14 +676,7 @@ def refine_leg(fvx, inputs, torch, np):
             R = max(3, math.ceil(COLD_BYTES / ((n_r + n_c) * ld * v)))
             X = [torch.as_tensor(inputs.uniform(0, 0, n_c * ld).reshape(n_c, ld)).to(tdt).cuda() for _ in range(R)]
             Y = [torch.empty((n_r, ld), dtype=tdt, device="cuda") for _ in range(R)]
-            for i in range(2):
-                P.spmm(X[i], Y[i], k=k)
-            tm = Timer(torch)
-            with tm:
-                for _ in range(2):
-                    for xx, yy in zip(X, Y):
-                        P.spmm(xx, yy, k=k)
-            t = tm.ms() / (2 * R)
+            t = graph_time(torch, [lambda xx=xx, yy=yy: P.spmm(xx, yy, k=k) for xx, yy in zip(X, Y)])
             del X, Y
             B = (v + 4) * nnz + 4 * (n_r + 1) + v * (n_c + n_r) * k
             if k == 1:
