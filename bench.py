@@ -731,6 +731,7 @@ def ns_leg(fvx, inputs, torch, np, rtol=1e-8):
     for k in (1, 16, 64):
         opk = fvx.Operator(mesh, k, math.pi / K_MAIN, fvx.NONE, with_f32=False)
         tune(opk, fvx)
+        tune_cg(opk, fvx)
         states[k] = run(opk, f"independent states k={k}")
         del opk
         torch.cuda.empty_cache()

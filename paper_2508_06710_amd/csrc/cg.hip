@@ -547,7 +547,7 @@ struct Carve {
 };
 
 int groups_of(const fvx_op *op) { return op->percol ? op->k : 1; }
-int max_blocks_for(const fvx_op *op) { return op->percol ? 256 : 2048; }
+int max_blocks_for(const fvx_op *) { return 2048; }
 
 // CG launch tile for precision T: the tile set by the CG autotuner, else a
 // default (the SpMM tile's vector width, 256 threads, XCD remap, a grid of at
@@ -1442,7 +1442,6 @@ int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, voi
             if (block < base.lanes_per_row) continue;
             for (int remap : {1, 0})
                 for (int cap : {1024, 512, 2048}) {
-                    if (op->percol && cap != 1024) continue;  // independent planes: grids of at most 256 blocks
                     fvx_tile t = base;
                     t.block = block;
                     t.xcd_remap = remap;
