@@ -873,7 +873,16 @@ def batch_leg(fvx, inputs, torch, np, rtol):
         _, st = A.solve(b, rtol=rtol)
         csr.append(time.perf_counter() - t0)
         del A, b
+    # The same batch with the Chebyshev preconditioner (degree 8 on [2/300, 2]).
+    kwc = dict(rtol=rtol, precision=fvx.MIXED, precond=fvx.PRECOND_CHEBYSHEV)
+    fvx.solve_batch(opl, Bs, **kwc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stc = fvx.solve_batch(opl, Bs, **kwc)
+    batch_cheb_s = time.perf_counter() - t0
     out = {
+        "batch_chebyshev_s": batch_cheb_s,
+        "max_relres_true_chebyshev": max(s["relres_true"] for s in stc),
         "problems": [{"base": f"{p['base'].nx}x{p['base'].ny}", "k": p["k"], "cells": o.n_b * o.k,
                       "tile_f64": list(t[0]), "tile_f32": list(t[1]), "cg_tile_f64": list(t[2]),
                       "cg_tile_f32": list(t[3]), "inner_iters": s["iters"],
@@ -886,7 +895,8 @@ def batch_leg(fvx, inputs, torch, np, rtol):
         "max_relres_true": max(s["relres_true"] for s in sts),
         "rtol": rtol,
     }
-    log(f"batch {batch_s:.3f} s, singles {out['sum_single_s']:.3f} s, csr3d {out['sum_csr3d_fp64_s']:.3f} s")
+    log(f"batch {batch_s:.3f} s (Chebyshev {batch_cheb_s:.3f} s), singles {out['sum_single_s']:.3f} s, "
+        f"csr3d {out['sum_csr3d_fp64_s']:.3f} s")
     return out
 
 
@@ -915,10 +925,12 @@ def airfoil_leg(fvx, inputs, torch, np):
         del X, Y
     res["cg_tile_f64"], res["cg_tile_f32"] = list(tune_cg(op, fvx)), list(tune_cg(op, fvx, fvx.F32))
     B = op.to_rows(inputs.rhs_uniform(3, op.n_b * k))
-    for prec, name in ((fvx.MIXED, "mixed"), (fvx.F64, "f64")):
-        op.solve(B, rtol=rtol, precision=prec)
+    cheb = fvx.PRECOND_CHEBYSHEV
+    for prec, pre, name in ((fvx.MIXED, 0, "mixed"), (fvx.F64, 0, "f64"), (fvx.MIXED, cheb, "mixed_chebyshev"),
+                            (fvx.F64, cheb, "f64_chebyshev")):
+        op.solve(B, rtol=rtol, precision=prec, precond=pre)
         t0 = time.perf_counter()
-        _, st = op.solve(B, rtol=rtol, precision=prec)
+        _, st = op.solve(B, rtol=rtol, precision=prec, precond=pre)
         res[f"solve_{name}"] = {"s": time.perf_counter() - t0, "iters": st["iters"], "outer": st["outer"],
                                 "relres_true": st["relres_true"]}
     ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z)
@@ -931,6 +943,7 @@ def airfoil_leg(fvx, inputs, torch, np):
     res["solve_csr3d_fp64"] = {"s": time.perf_counter() - t0, "iters": st["iters"],
                                "relres_true": st["relres_true"]}
     log(f"airfoil {op.n_b}x{k}: mixed {res['solve_mixed']['s']:.3f} s, f64 {res['solve_f64']['s']:.3f} s, "
+        f"Chebyshev mixed {res['solve_mixed_chebyshev']['s']:.3f} s, f64 {res['solve_f64_chebyshev']['s']:.3f} s, "
         f"csr3d {res['solve_csr3d_fp64']['s']:.3f} s")
     return res
 
