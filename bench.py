@@ -432,6 +432,8 @@ def main():
         torch.cuda.empty_cache()
         out["refine_mapping"] = refine_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
+        out["generic_spmm"] = generic_leg(fvx, inputs, torch, np)
+        torch.cuda.empty_cache()
     if not args.no_ns:
         out["ns_step"] = ns_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
@@ -755,6 +757,52 @@ def ns_profile_mode(fvx, inputs, torch):
                         guess=fvx.GUESS_GIVEN)
     torch.cuda.synchronize()
     log(f"ns profile run done: {st['iters']} CG iterations in the last step")
+
+
+def generic_leg(fvx, inputs, torch, np):
+    """Section 2's setting: a square sparse matrix with n = 10^6 rows and 7 or
+    13 nonzeros per row (periodic 100^3 structured matrices) times m
+    right-hand sides with the general CSR SpMM (fvx_sparse_spmm, tuned per
+    m): P_m = m t_1 / t_m against its own single-column product, beside the
+    upper and lower bounds of Eqs. 3a and 3b for the same nnz, n_r, n_c, and
+    against m products with the CSR-vector SpMV (fvx_csr_spmv).  Sweeps
+    captured in HIP graphs."""
+    import oracle  # closed-form bounds of Section 2 only (Eqs. 3a, 3b)
+    out = []
+    for points in (7, 13):
+        ptr, col, val = inputs.structured_csr(100, points)
+        n, nnz = len(ptr) - 1, len(col)
+        M = fvx.SparseMatrix(ptr, col, val, n, with_f32=False)
+        A = fvx.CsrMatrix(ptr, col, val)
+        x = torch.as_tensor(inputs.uniform(0, 0, n)).cuda()
+        R1 = max(2, math.ceil(COLD_BYTES / (16 * n)))
+        xs = [x.clone() for _ in range(R1)]
+        ys = [torch.empty_like(x) for _ in range(R1)]
+        t_spmv = graph_time(torch, [lambda a=a, b=b: A.spmv(a, b) for a, b in zip(xs, ys)])
+        del xs, ys
+        for m in (1, 2, 4, 8, 16, 32, 64, 128):
+            ld = m if m < 4 else m + (-m) % 4
+            R = max(2, math.ceil(COLD_BYTES / (16 * n * ld)))
+            x0 = torch.as_tensor(inputs.uniform(1, m, n * ld).reshape(n, ld)).cuda()
+            X = [x0] + [x0.clone() for _ in range(R - 1)]
+            Y = [torch.empty((n, ld), dtype=torch.float64, device="cuda") for _ in range(R)]
+            M.tune(X[0], Y[0], k=m, reps=3)
+            t = graph_time(torch, [lambda a=a, b=b: M.spmm(a, b, k=m) for a, b in zip(X, Y)])
+            del X, Y
+            B = 12 * nnz + 4 * (n + 1) + 16 * n * m
+            if m == 1:
+                t_own = t
+            rec = {"nnz_per_row": points, "m": m, "spmm_us": t * 1e3, "spmm_GBs": B / (t * 1e-3) / 1e9,
+                   "frac_hbm": B / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "spmv_us": t_spmv * 1e3,
+                   "P_m_vs_csr_spmv": m * t_spmv / t, "P_m": m * t_own / t,
+                   "P_ub_eq3a": oracle.p_spmm_ub(nnz, n, n, m), "P_lb_eq3b": oracle.p_spmm_lb(nnz, n, m)}
+            out.append(rec)
+            log(f"generic SpMM {points} nnz/row m={m}: {rec['spmm_us']:.1f} us ({rec['spmm_GBs']:.0f} GB/s), "
+                f"P_m {rec['P_m']:.2f} (bounds {rec['P_lb_eq3b']:.2f}..{rec['P_ub_eq3a']:.2f}; "
+                f"vs the CSR-vector SpMV {rec['P_m_vs_csr_spmv']:.2f})")
+            torch.cuda.empty_cache()
+        del M, A
+    return out
 
 
 def pcg_leg(fvx, torch, op, D, rtol):

@@ -513,7 +513,10 @@ int fvx_sparse_destroy(fvx_sparse *A);
 int fvx_sparse_shape(const fvx_sparse *A, int64_t *n_rows, int64_t *n_cols, int64_t *nnz);
 /* Launch tile (fvx_tile; stage_lds must be 0).  block 0 or NULL restores the
  * default: the widest vector dividing ldx and ldy, lanes per row covering k,
- * 256 threads, XCD remap.  All tiles give bitwise the same product. */
+ * 256 threads, XCD remap.  lanes_per_row beyond what k needs (c = the power of
+ * two covering ceil(k / vec)) splits each row's nonzeros among
+ * lanes_per_row / c sub-groups whose sums are added by shuffles.  Tiles with
+ * the same split factor give bitwise the same product. */
 int fvx_sparse_set_tile(fvx_sparse *A, int dtype, const fvx_tile *tile);
 /* Y = diag(colscale) (A X): X device [n_cols][ldx], Y device [n_rows][ldy],
  * row-major multivectors of k columns (16-byte aligned; ldx a multiple of the
@@ -524,6 +527,13 @@ int fvx_sparse_set_tile(fvx_sparse *A, int dtype, const fvx_tile *tile);
  * fused multiply-adds.  X and Y must not overlap. */
 int fvx_sparse_spmm(const fvx_sparse *A, int dtype, int k, const void *X, int ldx, void *Y, int ldy,
                     const double *colscale, void *stream);
+/* Autotuner of the tile for products with k columns and these strides: times
+ * every row mapping (vector width, lanes per row, workgroup), then the launch
+ * options (XCD remap, grid cap, non-temporal stores) around the best, `reps`
+ * launches each on the caller's X (finite values) and Y, and keeps the
+ * fastest as A's tile for dtype.  results: optional [max_results] timings. */
+int fvx_sparse_tune(fvx_sparse *A, int dtype, int k, const void *X, int ldx, void *Y, int ldy, int reps,
+                    void *stream, fvx_tune_result *results, int max_results, int *n_results);
 
 /* Inline mesh refinement (Section 3.3) on a Cartesian base: fvx_mesh_refine
  * splits every cell into rf x rf equal children (rf 1..16; the same periodic

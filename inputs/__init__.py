@@ -331,3 +331,30 @@ def integrated_rhs(modes: FourierModes, cx: np.ndarray, cy: np.ndarray, area: np
     z = (np.arange(k) + 0.5) * dz
     f = modes.evaluate(np.asarray(cx)[None, :], np.asarray(cy)[None, :], z[:, None])
     return (f * np.asarray(area)[None, :] * dz).ravel()
+
+
+def structured_csr(n: int, points: int = 7):
+    """CSR arrays (ptr, col, val) of a periodic n x n x n structured matrix
+    with 7 (first neighbours along each axis) or 13 (first and second
+    neighbours) nonzeros per row and the values of the unit-spacing second
+    and fourth-order differences: the square test matrices of the paper's
+    Section 2 bounds (n^3 rows)."""
+    N = n ** 3
+    idx = np.arange(N, dtype=np.int64)
+    i, j, l = idx % n, (idx // n) % n, idx // (n * n)
+    offs = [(0, 0, 0)]
+    if points == 7:
+        w = [-6.0] + [1.0] * 6
+        offs += [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    elif points == 13:
+        w = [-7.5] + [4.0 / 3.0] * 6 + [-1.0 / 12.0] * 6
+        offs += [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+        offs += [(2, 0, 0), (-2, 0, 0), (0, 2, 0), (0, -2, 0), (0, 0, 2), (0, 0, -2)]
+    else:
+        raise ValueError("points must be 7 or 13")
+    cols = np.stack([((i + a) % n) + ((j + b) % n) * n + ((l + c) % n) * n * n for a, b, c in offs], axis=1)
+    order = np.argsort(cols, axis=1)
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(np.broadcast_to(np.array(w), cols.shape), order, axis=1)
+    ptr = np.arange(N + 1, dtype=np.int64) * len(offs)
+    return ptr.astype(np.int32), cols.ravel().astype(np.int32), np.ascontiguousarray(vals.ravel())

@@ -478,6 +478,16 @@ class SparseMatrix:
         t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), 0, int(nt_store))
         check(lib().fvx_sparse_set_tile(self._h, dtype, C.byref(t)), "fvx_sparse_set_tile")
 
+    def tune(self, X, Y, k=None, reps=5, dtype=None, stream=None):
+        """Autotunes the tile for products with X's and Y's strides
+        (fvx_sparse_tune); returns the number of candidates timed."""
+        dt = dtype if dtype is not None else (F32 if str(X.dtype).endswith("float32") else F64)
+        k = X.shape[1] if k is None else int(k)
+        n = C.c_int()
+        check(lib().fvx_sparse_tune(self._h, dt, k, _ptr(X), X.shape[1], _ptr(Y), Y.shape[1], int(reps),
+                                    _stream(stream), None, 0, C.byref(n)), "fvx_sparse_tune")
+        return n.value
+
     def spmm(self, X, Y=None, k=None, colscale=None, dtype=None, stream=None):
         """X: device [n_cols][ldx] tensor; Y: device [n_rows][ldy] (allocated with ldy = ldx if None)."""
         torch = _torch()

@@ -116,6 +116,8 @@ SIGNATURES = {
     "fvx_sparse_shape": (C.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "fvx_sparse_set_tile": (C.c_int, [_vp, C.c_int, _vp]),
     "fvx_sparse_spmm": (C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp, _vp]),
+    "fvx_sparse_tune": (C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int,
+                                  _P(C.c_int)]),
     "fvx_mesh_refine": (C.c_int, [_vp, C.c_int, _P(C.c_void_p)]),
     "fvx_ns_step_bytes": (C.c_int, [_vp, _P(SolveOpts), _P(C.c_size_t)]),
     "fvx_ns_step": (C.c_int, [_vp, _vp, _P(C.c_void_p), _vp, _vp, _vp, C.c_double, C.c_double, _P(SolveOpts), _vp,

@@ -25,28 +25,41 @@ struct SpArgs {
     const T *val;
     const double *colscale;
     int64_t n_rows;
-    int k, ldx, ldy, lpr, rows_per_tile, remap;
+    int k, ldx, ldy, lpr, cpr, rows_per_tile, remap;  // cpr: lanes per row that own columns
     int64_t tiles_per_block;
 };
 
-// Row group of lpr lanes per row; each lane owns V consecutive columns per
-// pass.  Every entry (column index, value) of the row is loaded once per pass
-// by the lanes of the group and multiplied into their X columns with fused
-// multiply-adds in entry order, so the result does not depend on the tile.
+// Lanes of a row group that own columns: enough to cover k with V columns
+// each (a power of two, at most lanes_per_row).  The remaining factor
+// lanes_per_row / cpr splits the row's nonzeros.
+inline int column_lanes(int k, int vec, int lpr) { return std::min(lpr, next_pow2(int(ceil_div(k, vec)))); }
+
+// Row group of lpr lanes per row: cpr lanes own V consecutive columns each
+// per pass, and S = lpr / cpr such sub-groups split the row's nonzeros
+// (sub-group s takes entries s, s + S, ...) and add their sums by shuffles.
+// Each sub-group applies its entries in order with fused multiply-adds, so
+// tiles with the same split factor S give bitwise the same product.
 template <typename T, int V, bool NT>
 __global__ __launch_bounds__(1024) void k_spmm_csr(SpArgs<T> a, const T *__restrict__ X, T *__restrict__ Y) {
     using vt = vec_t<T, V>;
     const int sub = threadIdx.x & (a.lpr - 1);
     const int grp = threadIdx.x / a.lpr;
+    const int cl = sub & (a.cpr - 1), sg = sub / a.cpr, S = a.lpr / a.cpr;
     const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
     for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
         const int64_t row = t * a.rows_per_tile + grp;
         if (row >= a.n_rows) break;
         const int32_t j0 = a.ptr[row], j1 = a.ptr[row + 1];
-        for (int c0 = sub * V; c0 < a.k; c0 += a.lpr * V) {
+        for (int c0 = cl * V; c0 < a.k; c0 += a.cpr * V) {
             vt acc = vt(0);
-            for (int32_t j = j0; j < j1; ++j)
+            for (int32_t j = j0 + sg; j < j1; j += S)
                 acc = __builtin_elementwise_fma(vt(a.val[j]), ldv<T, V>(X + int64_t(a.col[j]) * a.ldx + c0), acc);
+            // partners differ only in the split bits, so they share cl and the pass count
+            for (int o = a.cpr; o < a.lpr; o <<= 1) {
+#pragma unroll
+                for (int u = 0; u < V; ++u) acc[u] += __shfl_xor(acc[u], o, a.lpr);
+            }
+            if (sg != 0) continue;
             if (a.colscale) {
 #pragma unroll
                 for (int u = 0; u < V; ++u)
@@ -101,6 +114,7 @@ void launch_spmm(const fvx_sparse *A, int dtype, int k, const T *X, int ldx, T *
     a.ldx = ldx;
     a.ldy = ldy;
     a.lpr = t.lanes_per_row;
+    a.cpr = column_lanes(k, t.vec, t.lanes_per_row);
     a.rows_per_tile = t.block / t.lanes_per_row;
     a.remap = t.xcd_remap;
     const int64_t tiles = std::max<int64_t>(1, ceil_div(A->n_rows, a.rows_per_tile));
@@ -251,6 +265,82 @@ int fvx_sparse_spmm(const fvx_sparse *A, int dtype, int k, const void *X, int ld
         else
             fvx::launch_spmm<float>(A, dtype, k, static_cast<const float *>(X), ldx, static_cast<float *>(Y), ldy,
                                     colscale, fvx::as_stream(stream));
+        return FVX_OK;
+    });
+}
+
+int fvx_sparse_tune(fvx_sparse *A, int dtype, int k, const void *X, int ldx, void *Y, int ldy, int reps,
+                    void *stream, fvx_tune_result *results, int max_results, int *n_results) {
+    return guard([&] {
+        FVX_REQUIRE(A && X && Y && X != Y, FVX_E_ARG, "NULL or aliasing argument");
+        FVX_REQUIRE(dtype == FVX_F64 || (dtype == FVX_F32 && A->has_f32), FVX_E_ARG, "bad dtype for this matrix");
+        FVX_REQUIRE(k >= 1 && ldx >= k && ldy >= k, FVX_E_ARG, "k >= 1, ldx >= k, ldy >= k");
+        hipStream_t s = fvx::as_stream(stream);
+        reps = std::max(1, reps);
+        // Row mappings first (vector width, lanes per row, workgroup), then the
+        // launch options around the best one.
+        std::vector<fvx_tile> shapes;
+        const int vmax = dtype == FVX_F32 ? 4 : 2;
+        for (int vec = vmax; vec >= 1; vec >>= 1) {
+            if (ldx % vec || ldy % vec || ldx < fvx::ceil_div(k, vec) * vec) continue;
+            const int base = std::min(64, fvx::next_pow2(int(fvx::ceil_div(k, vec))));
+            // fewer lanes than columns (several passes), or more (split rows)
+            for (int lpr = std::max(1, base / 4); lpr <= std::min(64, base * 8); lpr <<= 1)
+                for (int block : {64, 128, 256, 512})
+                    if (block >= lpr) shapes.push_back(fvx_tile{vec, lpr, block, 1, 0, 0, 0});
+        }
+        FVX_REQUIRE(!shapes.empty(), FVX_E_ARG, "no tile fits these strides");
+        hipEvent_t e0, e1;
+        FVX_HIP(hipEventCreate(&e0));
+        FVX_HIP(hipEventCreate(&e1));
+        const fvx_tile keep = A->tile[dtype];
+        fvx_tile best = shapes[0];
+        double best_us = 1e30;
+        int n = 0;
+        auto time_one = [&](const fvx_tile &t) {
+            A->tile[dtype] = t;
+            auto run = [&] {
+                if (dtype == FVX_F64)
+                    fvx::launch_spmm<double>(A, dtype, k, static_cast<const double *>(X), ldx, static_cast<double *>(Y),
+                                             ldy, nullptr, s);
+                else
+                    fvx::launch_spmm<float>(A, dtype, k, static_cast<const float *>(X), ldx, static_cast<float *>(Y),
+                                            ldy, nullptr, s);
+            };
+            run();
+            FVX_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) run();
+            FVX_HIP(hipEventRecord(e1, s));
+            FVX_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            FVX_HIP(hipEventElapsedTime(&ms, e0, e1));
+            const double us = 1e3 * double(ms) / reps;
+            if (results && n < max_results) results[n] = fvx_tune_result{t, us};
+            ++n;
+            if (us < best_us) {
+                best_us = us;
+                best = t;
+            }
+        };
+        try {
+            for (const auto &t : shapes) time_one(t);
+            const fvx_tile b = best;
+            for (int cap : {0, 2048})
+                for (int remap : {1, 0})
+                    for (int nt : {0, 1}) {
+                        if (cap == 0 && remap == 1 && nt == 0) continue;  // timed above
+                        time_one(fvx_tile{b.vec, b.lanes_per_row, b.block, remap, cap, 0, nt});
+                    }
+        } catch (...) {
+            A->tile[dtype] = keep;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            throw;
+        }
+        A->tile[dtype] = best;
+        if (n_results) *n_results = n;
+        FVX_HIP(hipEventDestroy(e0));
+        FVX_HIP(hipEventDestroy(e1));
         return FVX_OK;
     });
 }

@@ -68,18 +68,30 @@ def test_rectangular_random_f32_within_rounding_bound(k):
         assert np.all(np.abs(Y[:, c] - ref) <= (n + 1) * U32 * bound + 1e-30)
 
 
-def test_every_tile_gives_the_same_product():
+@pytest.mark.parametrize("k", [1, 3, 24])
+def test_tiles_with_the_same_split_give_the_same_product(k):
+    """Tiles that differ in vector width, lanes per column pass, workgroup,
+    remap, grid cap or store kind give bitwise the same product when they
+    split the rows' nonzeros the same way; every split matches the oracle."""
     import paper_2508_06710_amd as fvx
     ptr, col, val = _random_csr(74, 513, 300, 9)
     A = sp.csr_matrix((val, col, ptr), shape=(513, 300))
     M = fvx.SparseMatrix(ptr, col, val, 300)
-    k = 24
+    ld = k if k < 4 else k + (-k) % 4
     for dtype, tdt, vecs in ((fvx.F64, torch.float64, (1, 2)), (fvx.F32, torch.float32, (1, 2, 4))):
-        X = torch.as_tensor(inputs.uniform(75, 0, 300 * k).reshape(300, k)).to(tdt).cuda()
-        ref = None
+        Xh = np.zeros((300, ld))
+        Xh[:, :k] = inputs.uniform(75, k, 300 * k).reshape(300, k)
+        X = torch.as_tensor(Xh).to(tdt).cuda()
+        refs = {}
         n = 0
         for vec in vecs:
+            if ld % vec:
+                continue
+            c = 1
+            while c < -(-k // vec):
+                c *= 2
             for lpr in (1, 2, 4, 8, 16, 32, 64):
+                split = max(1, lpr // c)
                 for block in (64, 256, 1024):
                     for remap in (0, 1):
                         for cap in (0, 5):
@@ -87,16 +99,16 @@ def test_every_tile_gives_the_same_product():
                                 if block < lpr:
                                     continue
                                 M.set_tile(vec, lpr, block, remap, cap, nt, dtype=dtype)
-                                Y = M.spmm(X).cpu().numpy()
-                                if ref is None:
-                                    ref = Y
+                                Y = M.spmm(X, k=k).cpu().numpy()
+                                ref = refs.setdefault(split, Y)
                                 assert np.array_equal(Y, ref), (dtype, vec, lpr, block, remap, cap, nt)
                                 n += 1
-        M.set_tile(0, dtype=dtype)  # back to the default
-        assert np.array_equal(M.spmm(X).cpu().numpy(), ref)
+        M.set_tile(0, dtype=dtype)  # back to the default (no split)
+        assert np.array_equal(M.spmm(X, k=k).cpu().numpy(), refs[1])
         if dtype == fvx.F64:
-            _check64(A, X.cpu().numpy(), ref)
-        assert n > 100
+            for Y in refs.values():
+                _check64(A, Xh[:, :k], Y[:, :k])
+        assert n > 50 and len(refs) >= 2
 
 
 def test_column_scaling():
@@ -154,3 +166,22 @@ def test_bad_arguments_are_rejected():
         M.spmm(X, k=5)  # ldx 4 < k
     with pytest.raises(fvx.FvxError):
         M.set_tile(4, 8, 256, dtype=fvx.F64)  # 32-byte vectors
+
+
+@pytest.mark.parametrize("k", [1, 8, 64])
+def test_tuned_tile_matches_the_oracle(k):
+    import paper_2508_06710_amd as fvx
+    ptr, col, val = _random_csr(80, 3000, 2000, 13)
+    A = sp.csr_matrix((val, col, ptr), shape=(3000, 2000))
+    M = fvx.SparseMatrix(ptr, col, val, 2000)
+    ld = max(k, 4) if k > 1 else 1
+    Xh = np.zeros((2000, ld))
+    Xh[:, :k] = inputs.uniform(81, k, 2000 * k).reshape(2000, k)
+    X = torch.as_tensor(Xh).cuda()
+    Y0 = M.spmm(X, k=k).cpu().numpy()
+    Y = torch.zeros((3000, ld), dtype=torch.float64, device="cuda")
+    n = M.tune(X, Y, k=k, reps=2)
+    assert n >= 4
+    Y1 = M.spmm(X, k=k).cpu().numpy()
+    _check64(A, Xh[:, :k], Y0[:, :k])
+    _check64(A, Xh[:, :k], Y1[:, :k])  # the tuned tile may split rows: same bound, other rounding
