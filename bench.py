@@ -661,7 +661,8 @@ def refine_leg(fvx, inputs, torch, np):
     """The inline-refinement coarse-to-fine mapping as a rectangular SpMM
     (fvx_sparse_spmm): the 96 x 64 channel base refined twice in x and y
     (24,576 fine rows, 6,144 coarse columns, bilinear weights) applied to
-    k flow states at once, k = 1, 16, 64, FP64 and FP32; bandwidth against
+    k flow states at once, k = 1, 16, 64, FP64 and FP32, tiles tuned per k
+    and precision; bandwidth against
     the HBM roofline and P_k = k t_1 / t_k beside Eq. 3a's bound for these
     n_r, n_c and nnz.  The sweep over rotating buffers is captured in a HIP
     graph, so the launches are not paced by the Python loop."""
@@ -678,6 +679,7 @@ def refine_leg(fvx, inputs, torch, np):
             R = max(3, math.ceil(COLD_BYTES / ((n_r + n_c) * ld * v)))
             X = [torch.as_tensor(inputs.uniform(0, 0, n_c * ld).reshape(n_c, ld)).to(tdt).cuda() for _ in range(R)]
             Y = [torch.empty((n_r, ld), dtype=tdt, device="cuda") for _ in range(R)]
+            P.tune(X[0], Y[0], k=k, reps=3)
             t = graph_time(torch, [lambda xx=xx, yy=yy: P.spmm(xx, yy, k=k) for xx, yy in zip(X, Y)])
             del X, Y
             B = (v + 4) * nnz + 4 * (n_r + 1) + v * (n_c + n_r) * k
