@@ -305,16 +305,18 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
 }
 
 // One step j >= 1 of the Chebyshev semi-iteration for D^-1 A z = D^-1 r
-// (A = -L; Saad, Algorithm 12.1):
-//   d_j = c1 d_{j-1} + c2 D^-1 (r - A z_j),   z_{j+1} = z_j + d_j,
-// with c1 = rho_j rho_{j-1}, c2 = 2 rho_j / delta from the host.  FIRST: z_1 =
-// d_0 = D^-1 r / theta is formed on the fly from r.  LAST: d is not stored and
-// the partials of r.z_{j+1} go to the r.z slot of part_b.  The gather reads
-// zin (or r) and writes zout, so the two z buffers alternate.
-template <typename T, int V, bool Z, int WT, bool FIRST, bool LAST>
+// (A = -L; Saad, Algorithm 12.1), in its three-term form: with d_{j-1} =
+// z_j - z_{j-1},
+//   z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 D^-1 (r - A z_j),
+// c1 = rho_j rho_{j-1}, c2 = 2 rho_j / delta from the host.  MODE 0 (j = 1):
+// z_1 = D^-1 r / theta is formed on the fly from r and z_0 = 0; MODE 1
+// (j = 2): z_1 is formed again from the row's own r; MODE 2 (j >= 3): z_{j-1}
+// is read from zio, which then receives z_{j+1} (each row reads its own
+// entry before writing it; the gather reads only zin).  LAST: the partials
+// of r.z_{j+1} go to the r.z slot of part_b.
+template <typename T, int V, bool Z, int WT, int MODE, bool LAST>
 __device__ void b_cheb(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__restrict__ r,
-                       const T *__restrict__ zin, T *__restrict__ zout, T *__restrict__ dv, T c1, T c2,
-                       T inv_theta) {
+                       const T *__restrict__ zin, T *__restrict__ zio, T c1, T c2, T inv_theta) {
     if (d.st->done) return;
     __shared__ double lds[kMaxPercolBlock * kMaxV];
     ROW_PROLOGUE
@@ -324,19 +326,23 @@ __device__ void b_cheb(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__re
     FOR_ROWS {
         const int64_t o = row * a.ld + c0;
         vec_t<T, V> zj, acc;
-        if constexpr (FIRST)
+        if constexpr (MODE == 0)
             acc = lap_row_ld<T, V, Z, WT>(a.A, ChebFirstLoad<T, V>{r, a.A.dinv, a.ld, inv_theta}, a.n_b, a.k, a.W,
                                           row, c0, sub, lpr, single, zj);
         else
             acc = lap_row_ld<T, V, Z, WT>(a.A, PlainLoad<T, V>{zin, a.ld}, a.n_b, a.k, a.W, row, c0, sub, lpr,
                                           single, zj);
         const vec_t<T, V> rv = ldv<T, V>(r + o);
-        const vec_t<T, V> dprev = FIRST ? zj : ldv<T, V>(dv + o);
         const T di = a.A.dinv[row];
-        const vec_t<T, V> dn = c1 * dprev + (c2 * di) * (rv + acc);  // r - A z = r + L z
-        const vec_t<T, V> zn = zj + dn;
-        if constexpr (!LAST) stv_masked<T, V>(dv + o, dn, a.k - c0);
-        stv_masked<T, V>(zout + o, zn, a.k - c0);
+        vec_t<T, V> zprev;
+        if constexpr (MODE == 0)
+            zprev = vec_t<T, V>(0);
+        else if constexpr (MODE == 1)
+            zprev = (di * inv_theta) * rv;
+        else
+            zprev = ldv<T, V>(zio + o);
+        const vec_t<T, V> zn = zj + c1 * (zj - zprev) + (c2 * di) * (rv + acc);  // r - A z = r + L z
+        stv_masked<T, V>(zio + o, zn, a.k - c0);
         if constexpr (LAST) {
 #pragma unroll
             for (int u = 0; u < V; ++u)
@@ -455,7 +461,7 @@ struct BItem {
     CgDev d;
     const T *b;
     T *x, *bp, *r, *p0, *p1, *q;
-    T *z[2], *dv, *zf;  // Chebyshev: z buffers, d, and the buffer holding the final z
+    T *z[2], *zf;  // Chebyshev: the two z buffers and the one holding the final z
     Src rr, bb, pq, rz;
     int nblk, first;
 };
@@ -503,9 +509,9 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     b_cg_b<T, V, PRE>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
 }
 
-// Chebyshev step j >= 1 for every item: reads z buffer (j - 2) & 1 (r when
-// j == 1), writes buffer (j - 1) & 1.
-template <typename T, int V, bool Z, int WT, bool FIRST, bool LAST>
+// Chebyshev step j >= 1 for every item: gathers z_j from buffer (j - 2) & 1
+// (r when j == 1) and writes z_{j+1} over z_{j-1} in buffer (j - 1) & 1.
+template <typename T, int V, bool Z, int WT, int MODE, bool LAST>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cheb(const BItem<T> *__restrict__ items, int n, int j, T c1, T c2,
                                                        T inv_theta) {
     const BItem<T> &I = items[find_item(items, n)];
@@ -514,7 +520,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cheb(const BItem<T> *__restric
     const RowArgs<T> a = I.a;
     const CgDev d = I.d;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
-    b_cheb<T, V, Z, WT, FIRST, LAST>(a, d, vb, I.r, I.z[j & 1], I.z[(j - 1) & 1], I.dv, c1, c2, inv_theta);
+    b_cheb<T, V, Z, WT, MODE, LAST>(a, d, vb, I.r, I.z[j & 1], I.z[(j - 1) & 1], c1, c2, inv_theta);
 }
 
 // A fixed, nonzero right-hand side for timing CG tiles: a hash of the index
@@ -603,10 +609,10 @@ CgDev carve_cg(Carve &c, const fvx_op *op) {
 struct Workspace {
     CgDev outer, inner;
     double *bp, *r, *p0, *p1, *q;
-    double *z[2], *dv;     // Chebyshev preconditioner buffers (FP64 CG)
+    double *z[2];          // Chebyshev preconditioner buffers (FP64 CG)
     double *gmean, *gact;  // [G] host-filled per-group arrays (mixed outer loop)
     float *b32, *x32, *bp32, *r32, *p32a, *p32b, *q32;
-    float *z32[2], *dv32;  // Chebyshev preconditioner buffers (FP32 inner CG)
+    float *z32[2];         // Chebyshev preconditioner buffers (FP32 inner CG)
     size_t bytes;
 };
 
@@ -623,7 +629,6 @@ Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb) {
     if (cheb && !mixed) {
         w.z[0] = c.take<double>(nv);
         w.z[1] = c.take<double>(nv);
-        w.dv = c.take<double>(nv);
     }
     if (mixed) {
         w.inner = carve_cg(c, op);
@@ -639,7 +644,6 @@ Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb) {
         if (cheb) {
             w.z32[0] = c.take<float>(nv);
             w.z32[1] = c.take<float>(nv);
-            w.dv32 = c.take<float>(nv);
         }
     }
     w.bytes = c.off;
@@ -740,7 +744,7 @@ struct CgJob {
     bool given;
     double rtol;
     int max_iter;
-    T *z0 = nullptr, *z1 = nullptr, *dv = nullptr;  // Chebyshev buffers
+    T *z0 = nullptr, *z1 = nullptr;  // Chebyshev buffers
 };
 
 // Preconditioner of a batch (the same for all its problems): kind 0 none,
@@ -843,7 +847,6 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         I.q = J.q;
         I.z[0] = J.z0;
         I.z[1] = J.z1;
-        I.dv = J.dv;
         I.zf = pc.kind == 2 ? (pc.degree % 2 == 0 ? J.z0 : J.z1) : nullptr;  // written by step degree - 1
         I.bb = d.percol ? Src{d.tot + d.G, 1} : Src{d.part_b + size_t(nb) * d.G, nb};
         I.pq = d.percol ? Src{d.tot + 2 * d.G, 1} : Src{d.part_a, nb};
@@ -913,21 +916,25 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
                 constexpr int WT = decltype(Wt)::value;
                 for (int j = 1; j < pc.degree; ++j) {
                     const T c1 = T(pc.c1[j]), c2 = T(pc.c2[j]), ith = T(pc.inv_theta);
-                    const bool first = j == 1, last = j == pc.degree - 1;
-                    auto go = [&](auto Zt, auto Ft, auto Lt) {
-                        hipLaunchKernelGGL((kb_cheb<T, V, decltype(Zt)::value, WT, decltype(Ft)::value,
+                    const bool last = j == pc.degree - 1;
+                    auto go = [&](auto Zt, auto Mt, auto Lt) {
+                        hipLaunchKernelGGL((kb_cheb<T, V, decltype(Zt)::value, WT, decltype(Mt)::value,
                                                     decltype(Lt)::value>),
                                            dim3(L.blocks), dim3(L.key.block), 0, s, dev, L.n, j, c1, c2, ith);
                     };
                     auto by_fl = [&](auto Zt) {
-                        if (first && last)
-                            go(Zt, std::true_type{}, std::true_type{});
-                        else if (first)
-                            go(Zt, std::true_type{}, std::false_type{});
-                        else if (last)
-                            go(Zt, std::false_type{}, std::true_type{});
+                        auto with_mode = [&](auto Mt) {
+                            if (last)
+                                go(Zt, Mt, std::true_type{});
+                            else
+                                go(Zt, Mt, std::false_type{});
+                        };
+                        if (j == 1)
+                            with_mode(std::integral_constant<int, 0>{});
+                        else if (j == 2)
+                            with_mode(std::integral_constant<int, 1>{});
                         else
-                            go(Zt, std::false_type{}, std::false_type{});
+                            with_mode(std::integral_constant<int, 2>{});
                     };
                     if (L.key.z)
                         by_fl(std::true_type{});
@@ -1064,7 +1071,7 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
     std::vector<CgJob<double>> jobs;
     for (auto &p : P)
         jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
-                                     o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter, p.w.z[0], p.w.z[1], p.w.dv});
+                                     o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter, p.w.z[0], p.w.z[1]});
     run_cg_batch<double>(jobs, items, flags, o->poll_every, make_precond(o), s);
     for (auto &p : P) {
         p.h = read_state(p.w.outer, s);
@@ -1165,7 +1172,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             // to half of what separates the outer residual from its target.
             const double inner_rtol = std::max(o->inner_rtol, need);
             jobs.push_back(CgJob<float>{op, p.w.inner, p.w.b32, p.w.x32, p.w.bp32, p.w.r32, p.w.p32a, p.w.p32b,
-                                        p.w.q32, false, inner_rtol, budget, p.w.z32[0], p.w.z32[1], p.w.dv32});
+                                        p.w.q32, false, inner_rtol, budget, p.w.z32[0], p.w.z32[1]});
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;
