@@ -69,10 +69,11 @@ def chebyshev_polynomial(lam: np.ndarray, degree: int, ratio: float) -> np.ndarr
 
 
 def pcg(mesh, L: sp.csr_matrix, b: np.ndarray, tol: float, precond: str = "jacobi", degree: int = 1,
-        ratio: float = 30.0, max_iter: int = 100000, x0: np.ndarray | None = None) -> PCGResult:
+        ratio: float = 30.0, max_iter: int = 100000, x0: np.ndarray | None = None, amg_opts=None) -> PCGResult:
     """Textbook preconditioned CG for L x = b; stops when ||r|| <= tol ||b||
     (b after projection), r the recursive residual.  Independent planes
-    (coupling NONE, or k == 1) are solved plane by plane."""
+    (coupling NONE, or k == 1) are solved plane by plane.  precond "amg": one
+    V-cycle of the aggregation multigrid (oracle/amg.py) of each system."""
     from . import NONE
     ind = mesh.coupling == NONE or mesh.k == 1
     groups = [(l * mesh.n_b, mesh.n_b) for l in range(mesh.k)] if ind else [(0, mesh.N)]
@@ -92,7 +93,13 @@ def pcg(mesh, L: sp.csr_matrix, b: np.ndarray, tol: float, precond: str = "jacob
             out.iters.append(0), out.status.append(0), out.relres_rec.append(0.0), out.relres_true.append(0.0)
             continue
 
+        if precond == "amg":
+            from . import amg as _amg
+            hier = _amg.build(A, mesh.n_b, 1 if ind else mesh.k, not ind, amg_opts)
+
         def prec(v):
+            if precond == "amg":
+                return _amg.vcycle(hier, v)
             if precond == "none":
                 return v.copy()
             if precond == "jacobi":

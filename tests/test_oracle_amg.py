@@ -1,0 +1,237 @@
+"""Pins of the oracle's aggregation multigrid (oracle/amg.py) against facts
+that do not come from it: aggregates worked out by hand on small chains, the
+structure a Galerkin product of piecewise-constant aggregates must keep (zero
+row sums, symmetry, identical plane blocks coupled only to neighbouring
+planes), the two-level error propagation written as the product of its three
+stages, symmetry and definiteness of the cycle, exactness with one level,
+and dense solves."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import inputs
+import oracle
+from oracle import amg
+from oracle import pcg as opcg
+
+
+def _chain(c):
+    """Symmetric coupling matrix of a chain with couplings c[i] between i, i+1."""
+    n = len(c) + 1
+    r = np.arange(n - 1)
+    return sp.csr_matrix((np.r_[c, c], (np.r_[r, r + 1], np.r_[r + 1, r])), shape=(n, n))
+
+
+@pytest.mark.parametrize("c,expect", [
+    ([1, 3, 1, 1, 2], [0, 0, 1, 1, 2, 2]),           # pairs in order
+    ([1, 10, 1, 1], [0, 0, 1, 2, 2]),                # cell 2: its only free neighbour is weak (1 < 0.25 * 10)
+    ([1, 1, 1], [0, 0, 1, 1]),                       # ties go to the smallest index
+    ([5, 1, 5, 1, 5], [0, 0, 1, 1, 2, 2]),
+    ([1, 4, 4, 1], [0, 0, 1, 1, 2]),                 # cell 2 pairs with 3 (tie 4 = 4, 1 is taken); 4 alone
+])
+def test_pairwise_by_hand(c, expect):
+    agg, nc = amg.pairwise(_chain(np.array(c, float)), 0.25)
+    assert agg.tolist() == expect and nc == max(expect) + 1
+
+
+def test_pairwise_prefers_the_strongest_free_neighbour():
+    # star: 0 linked to 1 (1.0), 2 (3.0), 3 (2.0): 0 pairs with 2; 1 and 3 alone (their only neighbour is taken)
+    T = sp.csr_matrix((np.r_[[1.0, 3.0, 2.0] * 2], (np.r_[0, 0, 0, 1, 2, 3], np.r_[1, 2, 3, 0, 0, 0])), shape=(4, 4))
+    agg, nc = amg.pairwise(T, 0.25)
+    assert agg.tolist() == [0, 1, 0, 2] and nc == 3
+
+
+def test_pairwise_breaks_ties_towards_the_smallest_index():
+    # star with equal couplings: 0 pairs with 1; 2 and 3 touch only 0 (taken) and stay alone
+    T = sp.csr_matrix((np.ones(6), (np.r_[0, 0, 0, 3, 2, 1], np.r_[3, 2, 1, 0, 0, 0])), shape=(4, 4))
+    agg, nc = amg.pairwise(T, 0.25)
+    assert agg.tolist() == [0, 0, 1, 2] and nc == 3
+    # equal within the relative tie tolerance counts as a tie
+    T = sp.csr_matrix((np.r_[1.0, 1.0 + 1e-12, 1.0, 1.0 + 1e-12], (np.r_[0, 0, 1, 2], np.r_[1, 2, 0, 0])), shape=(3, 3))
+    assert amg.pairwise(T, 0.25)[0].tolist() == [0, 0, 1]
+
+
+def test_double_pairwise_on_a_uniform_grid_makes_2x2_boxes():
+    nx, ny = 8, 6
+    idx = np.arange(nx * ny).reshape(ny, nx)
+    rows, cols = [], []
+    for a, b in ((idx[:, :-1], idx[:, 1:]), (idx[:-1, :], idx[1:, :])):
+        rows += [a.ravel(), b.ravel()]
+        cols += [b.ravel(), a.ravel()]
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    T = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(nx * ny, nx * ny))
+    agg, nc = amg.aggregate(T, 0.25)
+    assert nc == nx * ny // 4
+    for a in range(nc):
+        m = np.flatnonzero(agg == a)
+        j, i = m // nx, m % nx
+        assert len(m) == 4 and np.ptp(i) == 1 and np.ptp(j) == 1
+
+
+def _case(spec, k, dz=None, dirichlet=False, coupling=oracle.PERIODIC_Z):
+    m3 = oracle.Mesh3D(oracle.geometry(spec), k, dz or math.pi / k, coupling, dirichlet)
+    return m3, (-m3.lap()).tocsr()
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_galerkin_levels_keep_the_extruded_form(dirichlet):
+    m3, A = _case(inputs.channel_base(24, 20), 16, dz=0.02, dirichlet=dirichlet)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40))
+    kinds = [lv.kind for lv in h.levels]
+    assert "z" in kinds and "xy" in kinds and len(h.levels) >= 4
+    for lv in h.levels:
+        B = lv.A.toarray()
+        n, k = lv.n_b, lv.k
+        assert np.allclose(B, B.T, rtol=0, atol=1e-13 * np.abs(B).max())
+        if not dirichlet:
+            assert np.abs(B.sum(axis=1)).max() <= 1e-12 * np.abs(B).max()
+        blk = lambda a, b: B[a * n:(a + 1) * n, b * n:(b + 1) * n]
+        for l in range(k):
+            assert np.array_equal(blk(l, l), blk(0, 0))
+            for m in range(k):
+                d = min((l - m) % k, (m - l) % k)
+                if d > 1:
+                    assert not blk(l, m).any()
+                elif d == 1:
+                    c = blk(l, m)
+                    assert np.count_nonzero(c - np.diag(np.diag(c))) == 0  # planes couple cell to same cell
+    for lv in h.levels[:-1]:
+        P = lv.P.toarray()
+        assert np.array_equal(P.sum(axis=1), np.ones(P.shape[0]))      # one aggregate per unknown
+        if lv.kind == "xy":
+            sizes = np.bincount(lv.agg)
+            assert sizes.min() >= 1 and sizes.max() <= 4
+            T, _ = amg.couplings(lv.A, lv.n_b, lv.k)
+            for a in range(sizes.size):                                  # aggregates are connected
+                m = np.flatnonzero(lv.agg == a)
+                if len(m) > 1:
+                    sub = T[m][:, m]
+                    ncomp, _ = sp.csgraph.connected_components(sub, directed=False)
+                    assert ncomp == 1
+
+
+def test_z_coarsening_follows_the_dominant_coupling():
+    spec = inputs.CartSpec(16, 16, 1.0, 0.0, 1.0, 0.0, True, True)
+    _, A = _case(spec, 8, dz=0.01)           # planes 0.01 apart, cells 1/16: plane coupling dominates
+    _, B = _case(spec, 8, dz=1.0)            # planes far apart: in-plane coupling dominates
+    ha = amg.build(A, 256, 8, True, amg.AmgOpts(coarse_max=16))
+    hb = amg.build(B, 256, 8, True, amg.AmgOpts(coarse_max=16))
+    assert ha.levels[0].kind == "z" and hb.levels[0].kind == "xy"
+    assert ha.levels[1].k == 4 and hb.levels[1].k == 8
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_two_level_cycle_equals_the_product_of_its_stages(degree):
+    m3, A = _case(inputs.channel_base(8, 6), 4)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(degree=degree, coarse_max=60))
+    assert len(h.levels) == 2
+    n = A.shape[0]
+    Minv = np.column_stack([amg.vcycle(h, e) for e in np.eye(n)])
+    E = np.eye(n) - Minv @ A.toarray()
+    Eref = amg.two_level_error(h)
+    # on the complement of the constants (the cycle's range there is what CG uses)
+    Q = np.eye(n) - np.ones((n, n)) / n
+    assert np.abs(Q @ (E - Eref) @ Q).max() <= 1e-10
+    ev = np.linalg.eigvals(Q @ Eref @ Q)
+    assert ev.real.min() >= -1e-10 and ev.real.max() < 1.0
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_cycle_is_symmetric_and_positive_definite(dirichlet):
+    m3, A = _case(inputs.channel_base(10, 8), 6, dirichlet=dirichlet)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=20))
+    assert len(h.levels) >= 3
+    n = A.shape[0]
+    M = np.column_stack([amg.vcycle(h, e) for e in np.eye(n)])
+    assert np.abs(M - M.T).max() <= 1e-10 * np.abs(M).max()
+    if not dirichlet:
+        Q = np.eye(n) - np.ones((n, n)) / n
+        M = Q @ M @ Q
+        ev = np.linalg.eigvalsh((M + M.T) / 2)
+        assert np.sum(ev > 1e-12 * ev.max()) == n - 1 and ev.min() > -1e-10 * ev.max()
+    else:
+        assert np.linalg.eigvalsh((M + M.T) / 2).min() > 0
+
+
+def test_one_level_is_the_pseudo_inverse():
+    m3, A = _case(inputs.channel_base(6, 5), 3)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=1000))
+    assert len(h.levels) == 1
+    r = oracle.project_mean(inputs.rhs_uniform(90, m3.N), 1)
+    x = amg.vcycle(h, r)
+    assert np.linalg.norm(A @ x - r) <= 1e-12 * np.linalg.norm(r)
+    assert abs(x.mean()) <= 1e-14 * np.abs(x).max()
+    got = opcg.pcg(m3, -A, -r, 1e-12, precond="amg", amg_opts=amg.AmgOpts(coarse_max=1000))
+    assert got.iters == [1]
+
+
+def test_smoother_from_a_guess_is_the_smoother_of_the_residual():
+    m3, A = _case(inputs.channel_base(9, 7), 4)
+    dinv = 1.0 / A.diagonal()
+    r = inputs.rhs_uniform(91, m3.N)
+    z0 = inputs.uniform(92, 0, m3.N)
+    for degree in (1, 2, 4):
+        a = amg.chebyshev_smooth(A, dinv, r, degree, 8.0, z0=z0)
+        b = z0 + opcg.chebyshev_apply(A, dinv, r - A @ z0, degree, 8.0)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+        assert np.array_equal(amg.chebyshev_smooth(A, dinv, r, degree, 8.0),
+                              amg.chebyshev_smooth(A, dinv, r, degree, 8.0, z0=None))
+
+
+@pytest.mark.parametrize("spec,k,coupling,dirichlet", [
+    (inputs.channel_base(16, 12), 8, oracle.PERIODIC_Z, False),
+    (inputs.channel_base(16, 12), 6, oracle.PERIODIC_Z, True),
+    (inputs.channel_base(12, 10), 4, oracle.NONE, False),
+    (inputs.unit_square_triangles(7), 4, oracle.PERIODIC_Z, False),
+])
+def test_amg_pcg_matches_dense_solve(spec, k, coupling, dirichlet):
+    m3 = oracle.Mesh3D(oracle.geometry(spec), k, math.pi / k, coupling, dirichlet)
+    L = m3.lap().tocsr()
+    b = inputs.rhs_uniform(93, m3.N)
+    got = opcg.pcg(m3, L, b, 1e-12, precond="amg", amg_opts=amg.AmgOpts(coarse_max=30))
+    ng = m3.n_groups()
+    xd = oracle.dense_solve(L.toarray(), oracle.project_mean(b, ng) if m3.singular else b, ng)
+    assert np.max(np.abs(got.x - xd)) <= 1e-9 * np.max(np.abs(xd))
+    plain = opcg.pcg(m3, L, b, 1e-12, precond="none")
+    assert max(got.iters) < max(plain.iters)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8])
+def test_level_couplings_are_the_geometric_coefficients(k):
+    """t_ij = dz len_f / dist_f and w_i = area_i / dz, read from the assembled
+    operator (for two planes the two plane faces of a cell meet the same
+    neighbour)."""
+    spec = inputs.channel_base(6, 5)
+    g = oracle.geometry(spec)
+    dz = 0.3
+    m3 = oracle.Mesh3D(g, k, dz, oracle.PERIODIC_Z)
+    T, w = amg.couplings((-m3.lap()).tocsr(), m3.n_b, k)
+    ref = np.zeros((m3.n_b, m3.n_b))
+    for f in range(g.n_faces):
+        a, b = g.c1[f], g.c2[f]
+        if a != b:
+            ref[a, b] += dz * g.len[f] / g.dist[f]
+            ref[b, a] += dz * g.len[f] / g.dist[f]
+    assert np.allclose(T.toarray(), ref, rtol=1e-14, atol=0)
+    assert np.allclose(w, g.area / dz if k >= 2 else 0.0, rtol=1e-14, atol=0)
+
+
+def test_prolongation_maps_each_plane_to_the_same_plane():
+    """Base aggregation acts within every plane: unknown (l, c) feeds coarse
+    unknown (l, agg[c]); plane merging sends plane l to plane l // 2."""
+    m3, A = _case(inputs.channel_base(12, 10), 4, dz=0.05)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40, z_rule=1e9))
+    lv = h.levels[0]
+    assert lv.kind == "xy"
+    nc = h.levels[1].n_b
+    P = lv.P.tocoo()
+    l, c = P.row // m3.n_b, P.row % m3.n_b
+    assert np.array_equal(P.col, l * nc + lv.agg[c])
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40, z_rule=-1.0))
+    lv = h.levels[0]
+    assert lv.kind == "z"
+    P = lv.P.tocoo()
+    l, c = P.row // m3.n_b, P.row % m3.n_b
+    assert np.array_equal(P.col, (l // 2) * m3.n_b + c)
