@@ -289,6 +289,7 @@ def main():
     ap.add_argument("--no-stencil", action="store_true")
     ap.add_argument("--profile-stencil", action="store_true")
     ap.add_argument("--profile-pcg", action="store_true")
+    ap.add_argument("--profile-amg", action="store_true")
     ap.add_argument("--profile-ns", action="store_true")
     ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--guess-epochs", type=int, default=20)
@@ -321,6 +322,9 @@ def main():
         return
     if args.profile_pcg:
         pcg_profile_mode(fvx, inputs, torch)
+        return
+    if args.profile_amg:
+        amg_profile_mode(fvx, inputs, torch)
         return
     if args.profile_ns:
         ns_profile_mode(fvx, inputs, torch)
@@ -521,6 +525,7 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
     res["mixed_cg"] = {"s_to_1e-8": tm.ms() / 1e3, "inner_iters": stm["iters"], "outer": stm["outer"],
                        "relres_true": stm["relres_true"]}
     res["poisson_pcg"] = pcg_leg(fvx, torch, op, D, rtol)
+    res["poisson_amg"] = amg_leg(fvx, torch, inputs, op, D, rtol)
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
 
@@ -829,6 +834,60 @@ def pcg_leg(fvx, torch, op, D, rtol):
                      "cheb_ratio": float(o.cheb_ratio)}
         log(f"pcg {name}: {best:.2f} ms, {st['iters']} iterations, true residual {st['relres_true']:.2e}")
     return out
+
+
+def amg_leg(fvx, torch, inputs, op, D, rtol):
+    """CG preconditioned by one V-cycle of the aggregation multigrid (default
+    options: Chebyshev degree 2 on [2/8, 2], pairwise aggregation with beta
+    0.25, plane merging when the plane coupling dominates, coarsest level at
+    most 512 unknowns) on the benchmark's projection right-hand side, FP64 and
+    mixed precision, the best of 3 timed solves each; the time of one V-cycle
+    and, per level, the level's SpMM (its operator on the level's k planes;
+    graph-timed, inputs warm in the caches) -- the per-level SpMM table of the
+    paper's multigrid appendix."""
+    t0 = time.perf_counter()
+    amg = fvx.Amg(op)
+    out = {"setup_s": time.perf_counter() - t0, "levels": []}
+    for name, kw in (("f64", {}), ("mixed", dict(precision=fvx.MIXED))):
+        op.solve(D, rtol=rtol, amg=amg, **kw)
+        best, st = None, None
+        for _ in range(3):
+            tm = Timer(torch)
+            with tm:
+                _, st = op.solve(D, rtol=rtol, amg=amg, **kw)
+            best = tm.ms() if best is None else min(best, tm.ms())
+        out[name] = {"s_to_1e-8": best / 1e3, "iters": st["iters"], "outer": st["outer"],
+                     "relres_true": st["relres_true"]}
+        log(f"amg {name}: {best:.2f} ms, {st['iters']} iterations, true residual {st['relres_true']:.2e}")
+    Z = torch.empty_like(D)
+    out["vcycle_us"] = graph_time(torch, [lambda: amg.apply(D, Z)] * 10) * 1e3
+    for lvl, (n_b, k, nnz_b, kind) in enumerate(amg.levels()):
+        lop = amg.level_op(lvl)
+        X = lop.to_rows(inputs.uniform(0, 0, n_b * k))
+        Y = torch.empty_like(X)
+        t = graph_time(torch, [lambda: lop.lap(X, Y)] * 20)
+        B = spmm_bytes(lop.nnz_b, n_b, k)
+        out["levels"].append({"n_b": n_b, "k": k, "nnz_b": nnz_b, "next": ["coarsest", "base", "planes"][kind],
+                              "spmm_us": t * 1e3, "spmm_GBs": B / (t * 1e-3) / 1e9})
+        log(f"amg level {lvl}: n_b {n_b} k {k} nnz_b {nnz_b} -> {out['levels'][-1]['next']}, "
+            f"SpMM {t * 1e3:.2f} us")
+    log(f"amg V-cycle {out['vcycle_us']:.1f} us")
+    return out
+
+
+def amg_profile_mode(fvx, inputs, torch):
+    """A short run for rocprofv3 kernel traces of the multigrid-preconditioned
+    CG on the channel workload: one warm-up and one timed FP64 solve to 1e-8."""
+    spec, mesh, op = build_case(fvx, inputs, K_MAIN)
+    tune(op, fvx)
+    tune_cg(op, fvx)
+    amg = fvx.Amg(op)
+    u = inputs.normal(2, 0, op.F_b * op.k + op.n_b * op.k)
+    D = op.div(op.to_rows(u[:op.F_b * op.k], rows=op.F_b), op.to_rows(u[op.F_b * op.k:]))
+    for _ in range(2):
+        _, st = op.solve(D, rtol=1e-8, amg=amg)
+    torch.cuda.synchronize()
+    log(f"amg profile run done: {st['iters']} iterations, {st['seconds']:.4f} s, levels {amg.levels()}")
 
 
 def pcg_profile_mode(fvx, inputs, torch):

@@ -68,6 +68,7 @@ typedef struct fvx_mesh fvx_mesh;   /* host-side base mesh (face graph) */
 typedef struct fvx_op fvx_op;       /* operator: base block on the device + launch tiles */
 typedef struct fvx_sparse fvx_sparse; /* a general CSR matrix on the device (fvx_sparse_*) */
 typedef struct fvx_net fvx_net;     /* learned initial-guess network (device parameters) */
+typedef struct fvx_amg fvx_amg;     /* aggregation multigrid hierarchy of an operator (fvx_amg_*) */
 
 /* Returns a static string naming a status code. */
 const char *fvx_status_str(int status);
@@ -306,6 +307,8 @@ typedef struct fvx_solve_opts {
                              (1..16; 1 is Jacobi) */
     double cheb_ratio;    /* CHEBYSHEV: the polynomial targets the interval
                              [2 / cheb_ratio, 2] of the spectrum of D^-1 A (> 1) */
+    const fvx_amg *amg;   /* AMG: the hierarchy built for this operator (fvx_amg_create);
+                             NULL otherwise */
 } fvx_solve_opts;
 
 /* Preconditioners of the CG (A = -L, D = diag(A); every step an SpMM or a
@@ -317,13 +320,17 @@ typedef struct fvx_solve_opts {
  *              Iterative Methods for Sparse Linear Systems, Algorithm 12.1)
  *              on [2 / cheb_ratio, 2]; 2 bounds the spectrum of D^-1 A
  *              (Gershgorin).  Each step after the first is one fused SpMM
- *              kernel (5 vector passes); the workspace grows by 3 vectors
+ *              kernel (4 vector passes); the workspace grows by 2 vectors
  *              per precision.
+ *   AMG:       z = one V-cycle of the aggregation multigrid opts.amg (see
+ *              fvx_amg_create), in the solve's precision (FP32 inside the
+ *              MIXED inner CG); single solves only (FVX_E_ARG in a batch).
  * The paper's own solver preconditions CG with an adaptive AMG (Section 4);
- * these polynomial preconditioners keep every operation an SpMM. */
+ * every level of these preconditioners is applied as an SpMM. */
 #define FVX_PRECOND_NONE 0
 #define FVX_PRECOND_JACOBI 1
 #define FVX_PRECOND_CHEBYSHEV 2
+#define FVX_PRECOND_AMG 3
 
 typedef struct fvx_solve_stats {
     int32_t status;       /* same as the return value */
@@ -370,6 +377,80 @@ int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts 
 int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const *B, double *const *X,
                             const fvx_solve_opts *opts, void *ws, size_t ws_bytes, fvx_solve_stats *stats,
                             void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Aggregation multigrid preconditioner (Section 4, Appendix A)          */
+/* ------------------------------------------------------------------ */
+/* The paper preconditions its CG with an algebraic multigrid whose every
+ * level, and every restriction and prolongation between levels, is applied
+ * to all stacked fields as one SpMM (Appendix A lists those products).  This
+ * hierarchy keeps the repeated-block form on every level: a Galerkin product
+ * P^T A P with piecewise-constant aggregates P of an operator
+ * I_k (x) A_b + C is again such an operator, so each level is an fvx_op and
+ * runs the same SpMM kernels as the fine one.
+ *   Coarsening (host, once): each level is coarsened EITHER in the base
+ *   plane, by two passes of pairwise aggregation of the base cells (cells in
+ *   index order; a free cell i joins its free neighbour j of largest coupling
+ *   t_ij among those with t_ij >= beta * max_j' t_ij', ties within a relative
+ *   1e-9 to the smallest j; else it stays alone), OR along the repeated
+ *   direction, merging planes 2l and 2l + 1 (coupled planes, k even), which
+ *   it does when the lower median over base cells of w_i / max_j t_ij
+ *   exceeds z_rule (w_i: coupling to a neighbouring plane).  A level with at
+ *   most coarse_max unknowns per independent system (n_b k coupled, n_b for
+ *   independent planes) is the coarsest; it is solved with its dense
+ *   pseudo-inverse (inverse with Dirichlet walls), formed on the host in
+ *   FP64.
+ *   Cycle: V-cycle; on each level `degree` Chebyshev steps for A z = r on
+ *   [2 / ratio, 2] of the spectrum of D^-1 A from z = 0, restriction of the
+ *   residual (fused with its SpMM), the coarse cycle, prolongation of the
+ *   correction (fused with the first post-smoothing SpMM) and `degree`
+ *   post-smoothing steps from the corrected iterate.  Pre- and post-smoother
+ *   are the same symmetric polynomial, so the cycle is a symmetric
+ *   preconditioner for CG.  Kernels per level: 2 degree + 1 (one fewer for
+ *   degree 2 on the way down); every one returns at once once the solve
+ *   using the cycle has converged.
+ * Ownership: dev_mem (fvx_amg_bytes) holds every coarse operator, the
+ * aggregate maps and the coarsest pseudo-inverse; the caller keeps it and the
+ * fine op alive until fvx_amg_destroy.  The hierarchy is immutable. */
+typedef struct fvx_amg_opts {
+    int32_t degree;      /* Chebyshev smoothing steps before and after the coarse correction (2..8) */
+    double ratio;        /* smoother interval [2 / ratio, 2] (> 1) */
+    double beta;         /* aggregation strength threshold (0 < beta <= 1) */
+    double z_rule;       /* plane-merging threshold (>= 0) */
+    int32_t coarse_max;  /* coarsest level size per independent system (1..2048) */
+    int32_t max_levels;  /* 1..16 */
+} fvx_amg_opts;
+
+/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 512, max_levels 16. */
+int fvx_amg_opts_default(fvx_amg_opts *opts);
+
+/* Builds the hierarchy of op (which must have been built from mesh m with
+ * the finite-volume stencil, 7) on the host and returns the device bytes it
+ * needs.  FVX_E_UNSUPPORTED for the 13/27-point operators. */
+int fvx_amg_bytes(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *opts, size_t *bytes);
+/* Builds the hierarchy into dev_mem (256-byte aligned, >= fvx_amg_bytes);
+ * the coarse operators carry FP32 copies when op does.  Copies on `stream`
+ * and returns after the copies. */
+int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *opts, void *dev_mem, size_t bytes,
+                   void *stream, fvx_amg **out);
+int fvx_amg_destroy(fvx_amg *amg);
+
+/* Number of levels (the fine operator is level 0). */
+int fvx_amg_n_levels(const fvx_amg *amg, int32_t *n_levels);
+/* Level `level`: base cells, planes, nonzeros of its base block, how the
+ * next level is made (0: this is the coarsest, 1: base-plane aggregation,
+ * 2: plane merging) and its operator (owned by the hierarchy; usable with
+ * fvx_lap and the other operator calls).  Any pointer may be NULL. */
+int fvx_amg_level(const fvx_amg *amg, int32_t level, int64_t *n_b, int32_t *k, int64_t *nnz_b, int32_t *kind,
+                  const fvx_op **op);
+/* Base cell -> aggregate of a level of kind 1 (host int32 [n_b]). */
+int fvx_amg_aggregates(const fvx_amg *amg, int32_t level, int32_t *agg);
+
+/* One V-cycle Z = M^-1 R (device [n_b][ld] of the fine op, precision dtype
+ * FVX_F64 or FVX_F32; R and Z must not overlap).  ws: device workspace of at
+ * least fvx_amg_apply_bytes bytes (per-level vectors).  Asynchronous. */
+int fvx_amg_apply_bytes(const fvx_amg *amg, int dtype, size_t *bytes);
+int fvx_amg_apply(const fvx_amg *amg, int dtype, const void *R, void *Z, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Learned initial guess                                                */

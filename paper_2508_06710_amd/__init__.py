@@ -12,11 +12,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
-                   PERIODIC_Z, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, FvxError, SolveOpts, SolveStats,
+                   PERIODIC_Z, PRECOND_AMG, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, FvxError, SolveOpts, SolveStats,
                    Tile, check, lib)
 
 __all__ = ["Mesh", "Operator", "GuessNet", "SparseMatrix", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
-           "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "lib"]
+           "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "PRECOND_AMG", "Amg", "lib"]
 
 
 def _torch():
@@ -371,19 +371,26 @@ class Operator:
 
     # ---- solves -----------------------------------------------------------
     def solve_opts(self, rtol=1e-8, max_iter=100000, precision=F64, inner_rtol=1e-4, max_outer=50,
-                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=8, cheb_ratio=300.0):
+                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=8, cheb_ratio=300.0, amg=None):
+        """Solve options; amg: an Amg hierarchy of this operator (sets the
+        AMG preconditioner unless precond is given otherwise)."""
         o = SolveOpts()
         check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
         o.rtol, o.max_iter, o.precision = float(rtol), int(max_iter), int(precision)
         o.inner_rtol, o.max_outer, o.guess, o.poll_every = float(inner_rtol), int(max_outer), int(guess), int(poll_every)
         o.precond, o.cheb_degree, o.cheb_ratio = int(precond), int(cheb_degree), float(cheb_ratio)
+        if amg is not None:
+            o.amg = amg._h.value
+            if precond == PRECOND_NONE:
+                o.precond = PRECOND_AMG
         return o
 
     def workspace(self, opts):
         torch = _torch()
         nbytes = C.c_size_t()
         check(lib().fvx_solve_bytes(self._h, C.byref(opts), C.byref(nbytes)), "fvx_solve_bytes")
-        key = (int(opts.precision), int(opts.precond == PRECOND_CHEBYSHEV and opts.cheb_degree > 1))
+        key = (int(opts.precision), int(opts.precond == PRECOND_CHEBYSHEV and opts.cheb_degree > 1),
+               int(opts.amg or 0) if opts.precond == PRECOND_AMG else 0)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nbytes.value:
             ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
@@ -424,10 +431,103 @@ class Operator:
         check(rc, "fvx_ns_step", (0, 1) if allow_not_converged else (0,))
         return st.as_dict()
 
+    @classmethod
+    def _borrow(cls, handle, owner, mesh=None):
+        """An Operator view of a handle owned by `owner` (a multigrid level)."""
+        self = cls.__new__(cls)
+        self.mesh, self._owner, self._borrowed = mesh, owner, True
+        self.device = owner.device
+        self._h = C.c_void_p(handle)
+        nb, fb, kk, ld, nnz = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64()
+        check(lib().fvx_op_shape(self._h, C.byref(nb), C.byref(fb), C.byref(kk), C.byref(ld), C.byref(nnz)),
+              "fvx_op_shape")
+        self.n_b, self.F_b, self.k, self.ld, self.nnz_b = nb.value, fb.value, kk.value, ld.value, nnz.value
+        self.stencil, self.coupling, self.dz, self.wall_bc = 7, owner.op.coupling, 1.0, owner.op.wall_bc
+        self.zfaces = self.coupling == PERIODIC_Z and self.k >= 2
+        self.singular = bool(lib().fvx_op_singular(self._h))
+        self.op_bytes = 0
+        self._ws = {}
+        return self
+
+    def __del__(self):
+        if getattr(self, "_h", None) and not getattr(self, "_borrowed", False):
+            try:
+                lib().fvx_op_destroy(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class Amg:
+    """Aggregation multigrid hierarchy of an operator (fvx_amg_*): every
+    level an operator of the same repeated-block form.  Pass it to
+    Operator.solve(amg=...) to precondition CG with one V-cycle."""
+
+    def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=512, max_levels=16,
+                 stream=None):
+        torch = _torch()
+        if op.mesh is None:
+            raise ValueError("the operator's mesh is needed to build its multigrid")
+        o = _lib.AmgOpts()
+        check(lib().fvx_amg_opts_default(C.byref(o)), "fvx_amg_opts_default")
+        o.degree, o.ratio, o.beta, o.z_rule = int(degree), float(ratio), float(beta), float(z_rule)
+        o.coarse_max, o.max_levels = int(coarse_max), int(max_levels)
+        nbytes = C.c_size_t()
+        check(lib().fvx_amg_bytes(op.mesh._h, op._h, C.byref(o), C.byref(nbytes)), "fvx_amg_bytes")
+        self.op, self.device = op, op.device
+        self._mem = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(lib().fvx_amg_create(op.mesh._h, op._h, C.byref(o), _ptr(self._mem), nbytes.value, _stream(stream),
+                                   C.byref(h)), "fvx_amg_create")
+        self._h = h
+        n = C.c_int32()
+        check(lib().fvx_amg_n_levels(h, C.byref(n)), "fvx_amg_n_levels")
+        self.n_levels = n.value
+        self._ws = {}
+
+    def level(self, i):
+        """(n_b, k, nnz_b, kind) of level i (kind 0 coarsest, 1 base aggregation, 2 plane merging)."""
+        nb, kk, nnz, kind = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32()
+        check(lib().fvx_amg_level(self._h, int(i), C.byref(nb), C.byref(kk), C.byref(nnz), C.byref(kind), None),
+              "fvx_amg_level")
+        return nb.value, kk.value, nnz.value, kind.value
+
+    def levels(self):
+        return [self.level(i) for i in range(self.n_levels)]
+
+    def level_op(self, i):
+        """Level i's operator (level 0 is the fine operator itself)."""
+        if i == 0:
+            return self.op
+        h = C.c_void_p()
+        check(lib().fvx_amg_level(self._h, int(i), None, None, None, None, C.byref(h)), "fvx_amg_level")
+        return Operator._borrow(h.value, self)
+
+    def aggregates(self, i):
+        nb = self.level(i)[0]
+        out = np.zeros(nb, np.int32)
+        check(lib().fvx_amg_aggregates(self._h, int(i), _np_ptr(out)), "fvx_amg_aggregates")
+        return out
+
+    def apply(self, R, Z=None, dtype=None, stream=None):
+        """One V-cycle Z = M^-1 R (device [n_b][ld] tensors of the fine operator)."""
+        torch = _torch()
+        dt = dtype if dtype is not None else (F32 if str(R.dtype).endswith("float32") else F64)
+        Z = torch.zeros_like(R) if Z is None else Z
+        nbytes = C.c_size_t()
+        check(lib().fvx_amg_apply_bytes(self._h, dt, C.byref(nbytes)), "fvx_amg_apply_bytes")
+        ws = self._ws.get(dt)
+        if ws is None or ws.numel() < nbytes.value:
+            ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+            self._ws[dt] = ws
+        check(lib().fvx_amg_apply(self._h, dt, _ptr(R), _ptr(Z), _ptr(ws), ws.numel(), _stream(stream)),
+              "fvx_amg_apply")
+        return Z
+
     def __del__(self):
         if getattr(self, "_h", None):
             try:
-                lib().fvx_op_destroy(self._h)
+                lib().fvx_amg_destroy(self._h)
             except Exception:
                 pass
             self._h = None

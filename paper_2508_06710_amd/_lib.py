@@ -18,7 +18,7 @@ GUESS_ZERO, GUESS_GIVEN, GUESS_NET = 0, 1, 2
 
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_AMG = 0, 1, 2, 3
 
 
 class OpDesc(C.Structure):
@@ -45,7 +45,12 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int32), ("guess", C.c_int32),
                 ("poll_every", C.c_int32), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
-                ("cheb_ratio", C.c_double)]
+                ("cheb_ratio", C.c_double), ("amg", C.c_void_p)]
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("ratio", C.c_double), ("beta", C.c_double), ("z_rule", C.c_double),
+                ("coarse_max", C.c_int32), ("max_levels", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -116,6 +121,15 @@ SIGNATURES = {
     "fvx_sparse_shape": (C.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "fvx_sparse_set_tile": (C.c_int, [_vp, C.c_int, _vp]),
     "fvx_sparse_spmm": (C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp, _vp]),
+    "fvx_amg_opts_default": (C.c_int, [_P(AmgOpts)]),
+    "fvx_amg_bytes": (C.c_int, [_vp, _vp, _P(AmgOpts), _P(C.c_size_t)]),
+    "fvx_amg_create": (C.c_int, [_vp, _vp, _P(AmgOpts), _vp, C.c_size_t, _vp, _P(C.c_void_p)]),
+    "fvx_amg_destroy": (C.c_int, [_vp]),
+    "fvx_amg_n_levels": (C.c_int, [_vp, _P(_i32)]),
+    "fvx_amg_level": (C.c_int, [_vp, _i32, _P(_i64), _P(_i32), _P(_i64), _P(_i32), _P(C.c_void_p)]),
+    "fvx_amg_aggregates": (C.c_int, [_vp, _i32, _vp]),
+    "fvx_amg_apply_bytes": (C.c_int, [_vp, C.c_int, _P(C.c_size_t)]),
+    "fvx_amg_apply": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_size_t, _vp]),
     "fvx_sparse_tune": (C.c_int, [_vp, C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int,
                                   _P(C.c_int)]),
     "fvx_mesh_refine": (C.c_int, [_vp, C.c_int, _P(C.c_void_p)]),

@@ -20,36 +20,11 @@
 #include <chrono>
 #include <cmath>
 
-#include "cg_common.h"
+#include "amg.h"
 
 namespace fvx {
 namespace {
 
-// A kernel body runs one virtual block vb.blk of a grid of vb.nblk blocks.
-// A single-problem launch maps hardware blocks onto virtual blocks (XCD-aware
-// order); a batched launch maps them onto (problem, virtual block) items.  The
-// arithmetic of a virtual block does not depend on which launch runs it.
-struct VB {
-    int64_t blk;
-    int nblk;
-};
-
-__device__ __forceinline__ VB vb_single(int remap) { return VB{logical_block(remap), int(gridDim.x)}; }
-
-#define ROW_PROLOGUE                                 \
-    const int lpr = a.lpr;                           \
-    const int sub = threadIdx.x & (lpr - 1);         \
-    const int grp = threadIdx.x / lpr;               \
-    const int64_t blk = vb.blk;                      \
-    const int64_t t0 = blk * a.tiles_per_block;
-
-#define FOR_ROWS                                                         \
-    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {              \
-        const int64_t row = t * a.rows_per_tile + grp;                   \
-        if (row >= a.n_rows) break;                                      \
-        for (int c0 = sub * V; c0 < a.k; c0 += lpr * V)
-
-#define END_ROWS }
 
 // Where a kernel finds the partials it has to sum: n rows of G values.
 struct Src {
@@ -303,57 +278,6 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
         write_partials<1, V>(cz, sub, lpr, G, d.percol, d.part_b + 2 * int64_t(vb.nblk) * G, blk, vb.nblk, lds);
     }
 }
-
-// One step j >= 1 of the Chebyshev semi-iteration for D^-1 A z = D^-1 r
-// (A = -L; Saad, Algorithm 12.1), in its three-term form: with d_{j-1} =
-// z_j - z_{j-1},
-//   z_{j+1} = z_j + c1 (z_j - z_{j-1}) + c2 D^-1 (r - A z_j),
-// c1 = rho_j rho_{j-1}, c2 = 2 rho_j / delta from the host.  MODE 0 (j = 1):
-// z_1 = D^-1 r / theta is formed on the fly from r and z_0 = 0; MODE 1
-// (j = 2): z_1 is formed again from the row's own r; MODE 2 (j >= 3): z_{j-1}
-// is read from zio, which then receives z_{j+1} (each row reads its own
-// entry before writing it; the gather reads only zin).  LAST: the partials
-// of r.z_{j+1} go to the r.z slot of part_b.
-template <typename T, int V, bool Z, int WT, int MODE, bool LAST>
-__device__ void b_cheb(const RowArgs<T> &a, const CgDev &d, VB vb, const T *__restrict__ r,
-                       const T *__restrict__ zin, T *__restrict__ zio, T c1, T c2, T inv_theta) {
-    if (d.st->done) return;
-    __shared__ double lds[kMaxPercolBlock * kMaxV];
-    ROW_PROLOGUE
-    const int G = d.G;
-    const bool single = lpr * V >= a.k;
-    double c[1][V] = {};
-    FOR_ROWS {
-        const int64_t o = row * a.ld + c0;
-        vec_t<T, V> zj, acc;
-        if constexpr (MODE == 0)
-            acc = lap_row_ld<T, V, Z, WT>(a.A, ChebFirstLoad<T, V>{r, a.A.dinv, a.ld, inv_theta}, a.n_b, a.k, a.W,
-                                          row, c0, sub, lpr, single, zj);
-        else
-            acc = lap_row_ld<T, V, Z, WT>(a.A, PlainLoad<T, V>{zin, a.ld}, a.n_b, a.k, a.W, row, c0, sub, lpr,
-                                          single, zj);
-        const vec_t<T, V> rv = ldv<T, V>(r + o);
-        const T di = a.A.dinv[row];
-        vec_t<T, V> zprev;
-        if constexpr (MODE == 0)
-            zprev = vec_t<T, V>(0);
-        else if constexpr (MODE == 1)
-            zprev = (di * inv_theta) * rv;
-        else
-            zprev = ldv<T, V>(zio + o);
-        const vec_t<T, V> zn = zj + c1 * (zj - zprev) + (c2 * di) * (rv + acc);  // r - A z = r + L z
-        stv_masked<T, V>(zio + o, zn, a.k - c0);
-        if constexpr (LAST) {
-#pragma unroll
-            for (int u = 0; u < V; ++u)
-                if (c0 + u < a.k) c[0][u] += double(rv[u]) * double(zn[u]);
-        }
-    }
-    END_ROWS
-    if constexpr (LAST)
-        write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b + 2 * int64_t(vb.nblk) * G, blk, vb.nblk, lds);
-}
-
 
 // End: x -= mean(x) (singular L; mean from partials), x = 0 where b vanished.
 template <typename T, int V>
@@ -613,10 +537,12 @@ struct Workspace {
     double *gmean, *gact;  // [G] host-filled per-group arrays (mixed outer loop)
     float *b32, *x32, *bp32, *r32, *p32a, *p32b, *q32;
     float *z32[2];         // Chebyshev preconditioner buffers (FP32 inner CG)
+    AmgWork<double> amg64;  // multigrid vectors (FP64 CG)
+    AmgWork<float> amg32;   // multigrid vectors (FP32 inner CG)
     size_t bytes;
 };
 
-Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb) {
+Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb, const fvx_amg *amg = nullptr) {
     Carve c{static_cast<char *>(ws), 0};
     Workspace w{};
     const size_t nv = size_t(op->n_b) * op->ld;
@@ -645,6 +571,12 @@ Workspace carve(void *ws, const fvx_op *op, bool mixed, bool cheb) {
             w.z32[0] = c.take<float>(nv);
             w.z32[1] = c.take<float>(nv);
         }
+    }
+    if (amg) {
+        if (mixed)
+            w.amg32 = amg_carve<float>(amg, c.take<char>(amg_work_bytes(amg, FVX_F32)));
+        else
+            w.amg64 = amg_carve<double>(amg, c.take<char>(amg_work_bytes(amg, FVX_F64)));
     }
     w.bytes = c.off;
     return w;
@@ -745,6 +677,7 @@ struct CgJob {
     double rtol;
     int max_iter;
     T *z0 = nullptr, *z1 = nullptr;  // Chebyshev buffers
+    const AmgWork<T> *amgw = nullptr;  // multigrid vectors
 };
 
 // Preconditioner of a batch (the same for all its problems): kind 0 none,
@@ -752,7 +685,8 @@ struct CgJob {
 // constant factor, which CG does not see, so it runs as kind 1).  The step
 // coefficients follow Saad's Algorithm 12.1 on [2 / ratio, 2].
 struct Precond {
-    int kind = 0, degree = 1;
+    int kind = 0, degree = 1;  // kind 3: one V-cycle of the multigrid amg
+    const fvx_amg *amg = nullptr;
     double inv_theta = 1.0;
     std::vector<double> c1, c2;  // [degree]: step j uses c1[j], c2[j] (j >= 1)
 };
@@ -761,6 +695,9 @@ Precond make_precond(const fvx_solve_opts *o) {
     Precond pc;
     if (o->precond == FVX_PRECOND_JACOBI || (o->precond == FVX_PRECOND_CHEBYSHEV && o->cheb_degree == 1)) {
         pc.kind = 1;
+    } else if (o->precond == FVX_PRECOND_AMG) {
+        pc.kind = 3;
+        pc.amg = o->amg;
     } else if (o->precond == FVX_PRECOND_CHEBYSHEV) {
         pc.kind = 2;
         pc.degree = o->cheb_degree;
@@ -780,11 +717,13 @@ Precond make_precond(const fvx_solve_opts *o) {
     return pc;
 }
 
+// The CG kernels' view of the preconditioner: 1 Jacobi (formed on the fly),
+// 2 a stored z (Chebyshev or multigrid output), 0 none.
 template <typename F>
 void by_pre(int kind, F &&f) {
     if (kind == 1)
         f(std::integral_constant<int, 1>{});
-    else if (kind == 2)
+    else if (kind == 2 || kind == 3)
         f(std::integral_constant<int, 2>{});
     else
         f(std::integral_constant<int, 0>{});
@@ -847,7 +786,9 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         I.q = J.q;
         I.z[0] = J.z0;
         I.z[1] = J.z1;
-        I.zf = pc.kind == 2 ? (pc.degree % 2 == 0 ? J.z0 : J.z1) : nullptr;  // written by step degree - 1
+        I.zf = pc.kind == 2   ? (pc.degree % 2 == 0 ? J.z0 : J.z1)  // written by step degree - 1
+               : pc.kind == 3 ? amg_output<T>(pc.amg, *J.amgw)
+                              : nullptr;
         I.bb = d.percol ? Src{d.tot + d.G, 1} : Src{d.part_b + size_t(nb) * d.G, nb};
         I.pq = d.percol ? Src{d.tot + 2 * d.G, 1} : Src{d.part_a, nb};
         I.rz = d.percol ? Src{d.tot + 4 * d.G, 1} : Src{d.part_b + size_t(2) * nb * d.G, nb};
@@ -945,8 +886,23 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         });
         fold_percol(L, 2);
     };
-    if (pc.kind == 2)
-        for (const Launch &L : launches) cheb_pass(L);
+    // The multigrid V-cycle on the current r of every item (one item per
+    // launch: a hierarchy belongs to one operator); its last step runs with
+    // the CG's tile and writes the r.z partials.
+    auto amg_pass = [&](const Launch &L) {
+        for (int j : L.jobs) {
+            const CgJob<T> &J = jobs[j];
+            const Ctx<T> c(J.op);
+            const AmgFinal<T> fin{c.a, c.grid, c.block, c.t.vec};
+            amg_vcycle<T>(pc.amg, J.r, *J.amgw, J.d, &fin, s);
+        }
+        fold_percol(L, 2);
+    };
+    auto pre_pass = [&](const Launch &L) {
+        if (pc.kind == 2) cheb_pass(L);
+        if (pc.kind == 3) amg_pass(L);
+    };
+    for (const Launch &L : launches) pre_pass(L);
     int it = 0;
     while (true) {
         const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
@@ -973,7 +929,7 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
                         if (PRE == 1) fold_percol(L, 2);
                     });
                 });
-                if (pc.kind == 2) cheb_pass(L);
+                pre_pass(L);
             }
         }
         FVX_HIP(hipGetLastError());
@@ -1040,8 +996,9 @@ void check_opts(const fvx_op *op, const fvx_solve_opts *o) {
     FVX_REQUIRE(o->guess == FVX_GUESS_ZERO || o->guess == FVX_GUESS_GIVEN, FVX_E_ARG, "bad guess mode");
     FVX_REQUIRE(o->poll_every >= 1, FVX_E_ARG, "poll_every must be >= 1");
     FVX_REQUIRE(o->precond == FVX_PRECOND_NONE || o->precond == FVX_PRECOND_JACOBI ||
-                    o->precond == FVX_PRECOND_CHEBYSHEV,
+                    o->precond == FVX_PRECOND_CHEBYSHEV || o->precond == FVX_PRECOND_AMG,
                 FVX_E_ARG, "unknown preconditioner");
+    if (o->precond == FVX_PRECOND_AMG) amg_check_solve(o->amg, op, o->precision == FVX_MIXED);
     if (o->precond == FVX_PRECOND_CHEBYSHEV)
         FVX_REQUIRE(o->cheb_degree >= 1 && o->cheb_degree <= 16 && o->cheb_ratio > 1.0 && std::isfinite(o->cheb_ratio),
                     FVX_E_ARG, "Chebyshev preconditioner: degree 1..16, ratio > 1");
@@ -1072,6 +1029,7 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
     for (auto &p : P)
         jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
                                      o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter, p.w.z[0], p.w.z[1]});
+    for (size_t i = 0; i < P.size(); ++i) jobs[i].amgw = &P[i].w.amg64;
     run_cg_batch<double>(jobs, items, flags, o->poll_every, make_precond(o), s);
     for (auto &p : P) {
         p.h = read_state(p.w.outer, s);
@@ -1172,7 +1130,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             // to half of what separates the outer residual from its target.
             const double inner_rtol = std::max(o->inner_rtol, need);
             jobs.push_back(CgJob<float>{op, p.w.inner, p.w.b32, p.w.x32, p.w.bp32, p.w.r32, p.w.p32a, p.w.p32b,
-                                        p.w.q32, false, inner_rtol, budget, p.w.z32[0], p.w.z32[1]});
+                                        p.w.q32, false, inner_rtol, budget, p.w.z32[0], p.w.z32[1], &p.w.amg32});
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;
@@ -1209,7 +1167,7 @@ struct BatchLayout {
     std::vector<size_t> offs;
 };
 
-BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed, bool cheb) {
+BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed, bool cheb, const fvx_amg *amg) {
     BatchLayout L;
     size_t off = 0;
     auto take = [&](size_t b) {
@@ -1220,7 +1178,7 @@ BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed, bool cheb)
     L.items64 = take(sizeof(BItem<double>) * size_t(n));
     L.items32 = take(sizeof(BItem<float>) * size_t(n));
     L.flags = take(sizeof(int32_t) * size_t(n));
-    for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed, cheb).bytes));
+    for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed, cheb, amg).bytes));
     L.total = off;
     return L;
 }
@@ -1237,7 +1195,9 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
     }
     const bool mixed = o->precision == FVX_MIXED;
     const bool cheb = make_precond(o).kind == 2;
-    const BatchLayout L = batch_layout(n, ops, mixed, cheb);
+    const fvx_amg *amg = make_precond(o).kind == 3 ? o->amg : nullptr;
+    FVX_REQUIRE(!amg || n == 1, FVX_E_ARG, "the multigrid preconditioner serves single solves");
+    const BatchLayout L = batch_layout(n, ops, mixed, cheb, amg);
     FVX_REQUIRE(ws_bytes >= L.total, FVX_E_NOMEM, "workspace too small: need " + std::to_string(L.total));
     char *base = static_cast<char *>(ws);
     std::vector<Problem> P(n);
@@ -1245,7 +1205,7 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
         P[i].op = ops[i];
         P[i].B = B[i];
         P[i].X = X[i];
-        P[i].w = carve(base + L.offs[i], ops[i], mixed, cheb);
+        P[i].w = carve(base + L.offs[i], ops[i], mixed, cheb, amg);
     }
     if (mixed)
         solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32),
@@ -1319,6 +1279,7 @@ int fvx_solve_opts_default(fvx_solve_opts *o) {
     o->precond = FVX_PRECOND_NONE;
     o->cheb_degree = 8;
     o->cheb_ratio = 300.0;
+    o->amg = nullptr;
     return FVX_OK;
 }
 
@@ -1327,7 +1288,9 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *o, size_t *bytes) {
         fvx::check_opts(op, o);
         FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
         const fvx_op *ops[1] = {op};
-        *bytes = fvx::batch_layout(1, ops, o->precision == FVX_MIXED, fvx::make_precond(o).kind == 2).total;
+        const fvx::Precond pc = fvx::make_precond(o);
+        *bytes = fvx::batch_layout(1, ops, o->precision == FVX_MIXED, pc.kind == 2, pc.kind == 3 ? o->amg : nullptr)
+                     .total;
         return FVX_OK;
     });
 }
@@ -1350,7 +1313,10 @@ int fvx_solve_batch_bytes(int n, const fvx_op *const *ops, const fvx_solve_opts 
     return guard([&] {
         FVX_REQUIRE(n >= 1 && ops && bytes, FVX_E_ARG, "bad argument");
         for (int i = 0; i < n; ++i) fvx::check_opts(ops[i], o);
-        *bytes = fvx::batch_layout(n, ops, o->precision == FVX_MIXED, fvx::make_precond(o).kind == 2).total;
+        const fvx::Precond pc = fvx::make_precond(o);
+        FVX_REQUIRE(pc.kind != 3 || n == 1, FVX_E_ARG, "the multigrid preconditioner serves single solves");
+        *bytes = fvx::batch_layout(n, ops, o->precision == FVX_MIXED, pc.kind == 2, pc.kind == 3 ? o->amg : nullptr)
+                     .total;
         return FVX_OK;
     });
 }

@@ -1,0 +1,200 @@
+"""The aggregation multigrid on the GPU (fvx_amg_*) against the oracle's
+multigrid on assembled matrices (oracle/amg.py): the same levels and
+aggregates (integer work: bit-exact), every coarse level's SpMM against the
+oracle's Galerkin product P^T A P, one V-cycle element by element, and CG
+preconditioned by the cycle against the oracle's PCG (true residual,
+iteration count, dense solves), in FP64 and mixed precision."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import inputs
+import oracle
+from helpers import Case
+from oracle import amg as oamg
+from oracle import pcg as opcg
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # spec, k, dz, coupling, dirichlet, coarse_max
+    (inputs.channel_base(32, 24), 8, None, 1, False, 40),
+    (inputs.channel_base(24, 20), 16, 0.02, 1, False, 40),      # planes strongly coupled: plane merging
+    (inputs.convection_base(12, 20), 16, None, 1, False, 60),
+    (inputs.channel_base(16, 12), 6, None, 1, True, 30),        # Dirichlet walls
+    (inputs.channel_base(20, 16), 5, None, 0, False, 20),       # independent planes
+    (inputs.channel_base(17, 13), 5, 0.05, 1, False, 25),       # odd k: no plane merging possible
+    (inputs.unit_square_triangles(8), 4, None, 1, False, 30),
+]
+IDS = ["channel", "channel-z", "convection", "dirichlet", "independent", "odd-k", "triangles"]
+
+
+def _setup(spec, k, dz, coupling, dirichlet, coarse_max, degree=2):
+    import paper_2508_06710_amd as fvx
+    c = Case(spec, k, dz=dz, coupling=coupling, dirichlet=dirichlet)
+    amg = fvx.Amg(c.op, degree=degree, coarse_max=coarse_max)
+    coupled = coupling == 1 and k >= 2
+    A = (-c.L).tocsr()
+    n_b = c.m3.n_b
+    opts = oamg.AmgOpts(degree=degree, coarse_max=coarse_max)
+    h = oamg.build(A if coupled else A[:n_b, :n_b].tocsr(), n_b, k if coupled else 1, coupled, opts)
+    return c, amg, h, coupled
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_levels_and_aggregates_equal_the_oracle(case):
+    c, amg, h, coupled = _setup(*case)
+    got = amg.levels()
+    assert len(got) == len(h.levels)
+    kinds = {"": 0, "xy": 1, "z": 2}
+    for l, (lv, g) in enumerate(zip(h.levels, got)):
+        n_b, k, _, kind = g
+        assert (n_b, kind) == (lv.n_b, kinds[lv.kind]), l
+        assert k == (lv.k if coupled else c.k), l
+        if lv.kind == "xy":
+            assert np.array_equal(amg.aggregates(l), lv.agg), l
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_every_level_operator_is_the_galerkin_product(case):
+    c, amg, h, coupled = _setup(*case)
+    for l in range(1, len(h.levels)):
+        op = amg.level_op(l)
+        lv = h.levels[l]
+        A = lv.A if coupled else sp.kron(sp.identity(c.k), lv.A).tocsr()
+        x = inputs.uniform(100 + l, 0, A.shape[0])
+        y = op.to_planes(op.lap(op.to_rows(x)))
+        ref = -(A @ x)
+        bound = abs(A) @ np.abs(x)
+        assert np.max(np.abs(y - ref) / bound) <= 1e-12, l
+
+
+def _oracle_cycle(h, c, coupled, r):
+    if coupled:
+        return oamg.vcycle(h, r)
+    n_b = c.m3.n_b
+    return np.concatenate([oamg.vcycle(h, r[l * n_b:(l + 1) * n_b]) for l in range(c.k)])
+
+
+@pytest.mark.parametrize("degree", [2, 3])
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_one_v_cycle_matches_the_oracle(case, degree):
+    c, amg, h, coupled = _setup(*case, degree=degree)
+    ng = c.m3.n_groups()
+    r = inputs.rhs_uniform(110, c.m3.N)
+    if c.m3.singular:
+        r = oracle.project_mean(r, ng)
+    z = c.op.to_planes(amg.apply(c.op.to_rows(r)))
+    ref = _oracle_cycle(h, c, coupled, r)
+    # the cycle is one linear map computed in two rounding orders; its error
+    # grows with the coarse levels' condition numbers (< 1e5 here): 1e-16 x 1e5 x margin
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_fp32_cycle_is_close_to_the_fp64_cycle():
+    c, amg, h, coupled = _setup(*CASES[0])
+    r = oracle.project_mean(inputs.rhs_uniform(111, c.m3.N), 1)
+    z32 = c.op.to_planes(amg.apply(c.op.to_rows(r, dtype=c.fvx.F32)), dtype=c.fvx.F32).astype(np.float64)
+    ref = oamg.vcycle(h, r)
+    assert np.linalg.norm(z32 - ref) <= 1e-3 * np.linalg.norm(ref)
+
+
+def test_one_level_is_the_exact_pseudo_inverse():
+    import paper_2508_06710_amd as fvx
+    c = Case(inputs.channel_base(10, 8), 4)
+    amg = fvx.Amg(c.op, coarse_max=2048)
+    assert amg.n_levels == 1
+    r = oracle.project_mean(inputs.rhs_uniform(112, c.m3.N), 1)
+    z = c.op.to_planes(amg.apply(c.op.to_rows(r)))
+    A = (-c.L).tocsr()
+    assert np.linalg.norm(A @ z - r) <= 1e-12 * np.linalg.norm(r)
+    b = inputs.rhs_uniform(113, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, amg=amg)
+    assert st["status"] == 0 and st["iters"] == 1
+
+
+def _true_relres(c, x, b):
+    ng = c.m3.n_groups()
+    bp = oracle.project_mean(b, ng) if c.m3.singular else b
+    r = bp - oracle.spmv(c.L, x)
+    if c.coupling == 0 and c.k > 1:
+        return max(np.linalg.norm(rr) / np.linalg.norm(bb) for rr, bb in zip(r.reshape(c.k, -1), bp.reshape(c.k, -1)))
+    return np.linalg.norm(r) / np.linalg.norm(bp)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_amg_pcg_residual_and_iterations_match_the_oracle(case):
+    c, amg, h, coupled = _setup(*case)
+    b = inputs.rhs_uniform(114, c.m3.N)
+    rtol = 1e-9
+    X, st = c.op.solve(c.op.to_rows(b), rtol=rtol, amg=amg)
+    assert st["status"] == 0
+    assert _true_relres(c, c.op.to_planes(X), b) <= rtol * 1.05
+    ref = opcg.pcg(c.m3, c.L, b, rtol, precond="amg", amg_opts=h.opts)
+    it_ref = max(ref.iters)
+    assert abs(st["iters"] - it_ref) <= max(2, math.ceil(0.02 * it_ref)), (st["iters"], it_ref)
+    _, s0 = c.op.solve(c.op.to_rows(b), rtol=rtol)
+    assert st["iters"] < s0["iters"]
+
+
+def test_amg_pcg_matches_dense_solve_and_repeats_bitwise():
+    c, amg, h, coupled = _setup(inputs.channel_base(8, 6), 4, None, 1, False, 12)
+    assert amg.n_levels >= 3
+    b = inputs.rhs_uniform(115, c.m3.N)
+    B = c.op.to_rows(b)
+    X1, s1 = c.op.solve(B, rtol=1e-13, amg=amg)
+    X2, s2 = c.op.solve(B, rtol=1e-13, amg=amg)
+    x = c.op.to_planes(X1)
+    assert s1["iters"] == s2["iters"] and np.array_equal(x, c.op.to_planes(X2))
+    xd = oracle.dense_solve(c.L.toarray(), oracle.project_mean(b, 1), 1)
+    assert np.max(np.abs(x - xd)) <= 1e-9 * np.max(np.abs(xd))
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[4]], ids=["coupled", "independent"])
+def test_mixed_precision_with_amg(case):
+    c, amg, h, coupled = _setup(*case)
+    b = inputs.rhs_uniform(116, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, precision=c.fvx.MIXED, amg=amg)
+    assert st["status"] == 0
+    assert _true_relres(c, c.op.to_planes(X), b) <= 1e-10 * 1.05
+
+
+def test_given_guess_with_amg():
+    c, amg, h, coupled = _setup(*CASES[0])
+    b = inputs.rhs_uniform(117, c.m3.N)
+    x0 = inputs.uniform(117, 1, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), X=c.op.to_rows(x0), rtol=1e-10, guess=c.fvx.GUESS_GIVEN, amg=amg)
+    assert st["status"] == 0
+    assert _true_relres(c, c.op.to_planes(X), b) <= 1e-10 * 1.05
+    ref = opcg.pcg(c.m3, c.L, b, 1e-10, precond="amg", amg_opts=h.opts, x0=x0)
+    assert abs(st["iters"] - ref.iters[0]) <= max(2, math.ceil(0.02 * ref.iters[0]))
+
+
+def test_arguments_are_checked():
+    import paper_2508_06710_amd as fvx
+    c = Case(inputs.channel_base(12, 10), 4)
+    amg = fvx.Amg(c.op, coarse_max=20)
+    other = Case(inputs.channel_base(12, 10), 4)
+    B = c.op.to_rows(inputs.rhs_uniform(118, c.m3.N))
+    with pytest.raises(fvx.FvxError):
+        other.op.solve(B, amg=amg)                      # hierarchy of another operator
+    with pytest.raises(fvx.FvxError):
+        c.op.solve(B, precond=fvx.PRECOND_AMG)          # no hierarchy
+    with pytest.raises(fvx.FvxError):
+        fvx.solve_batch([c.op, c.op], [B, B], amg=amg)  # batches: single solves only
+    for kw in (dict(degree=1), dict(degree=9), dict(ratio=1.0), dict(beta=0.0), dict(coarse_max=0),
+               dict(coarse_max=4096), dict(max_levels=0), dict(max_levels=17)):
+        with pytest.raises(fvx.FvxError):
+            fvx.Amg(c.op, **kw)
+    big = Case(inputs.channel_base(40, 30), 4)          # 4800 unknowns
+    with pytest.raises(fvx.FvxError):
+        fvx.Amg(big.op, max_levels=1)                   # coarsest level above 2048 unknowns
+    m = fvx.Mesh.from_spec(inputs.channel_base(12, 10))
+    s13 = fvx.Operator(m, 4, 0.5, fvx.PERIODIC_Z, stencil=13)
+    with pytest.raises(fvx.FvxError):
+        fvx.Amg(s13)
+    R = c.op.to_rows(inputs.rhs_uniform(119, c.m3.N))
+    with pytest.raises(fvx.FvxError):
+        amg.apply(R, Z=R)                                # aliasing
