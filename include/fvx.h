@@ -300,7 +300,11 @@ typedef struct fvx_solve_opts {
                              1/(2 inner_rtol) of rtol ||b||) stops at half its need */
     int32_t max_outer;    /* MIXED: cap on outer corrections */
     int32_t guess;        /* FVX_GUESS_ZERO or FVX_GUESS_GIVEN (X holds x0) */
-    int32_t poll_every;   /* iterations between host reads of the device flag (>= 1) */
+    int32_t poll_every;   /* most iterations between host reads of the device flag (>= 1):
+                             the first read comes after min(poll_every, 8), later
+                             ones when the residual's decay since the previous
+                             read predicts convergence (the iterates do not
+                             depend on when the host reads) */
     int32_t precond;      /* FVX_PRECOND_NONE (plain CG), FVX_PRECOND_JACOBI or
                              FVX_PRECOND_CHEBYSHEV (see below) */
     int32_t cheb_degree;  /* CHEBYSHEV: steps of the semi-iteration per application

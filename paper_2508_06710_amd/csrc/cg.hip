@@ -454,11 +454,24 @@ __global__ __launch_bounds__(256) void k_fill_pattern(double *__restrict__ b, in
         b[i] = double((uint64_t(i) * 2654435761ull) % 1000ull) / 1000.0 - 0.5;
 }
 
-// flags[i] = done flag of item i's CG (one read back per poll for the batch).
+// What the host reads at a poll, per item: its CG's done flag and the
+// largest ||r||^2 / ||b||^2 over its groups still iterating (one read back
+// per poll for the batch).
+struct PollRec {
+    int32_t done, pad;
+    double r2;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void kb_done(const BItem<T> *__restrict__ items, int n, int32_t *__restrict__ flags) {
-    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        flags[i] = items[i].d.st->done;
+__global__ __launch_bounds__(256) void kb_done(const BItem<T> *__restrict__ items, int n, PollRec *__restrict__ out) {
+    for (int i = int(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const CgDev &d = items[i].d;
+        double r2 = 0.0;
+        for (int g = 0; g < d.G; ++g)
+            if (d.bnorm2[g] > 0.0) r2 = fmax(r2, d.rho_last[g] / d.bnorm2[g]);
+        out[i].done = d.st->done;
+        out[i].r2 = r2;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -740,7 +753,7 @@ struct GroupKey {
 // (its own launches), then every iteration is one batched launch per phase and
 // group.  items_dev: device array for the launch descriptors (>= jobs.size()).
 template <typename T>
-void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *flags_dev, int poll, const Precond &pc,
+void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *flags_dev, int poll, const Precond &pc,
                   hipStream_t s) {
     if (jobs.empty()) return;
     std::vector<BItem<T>> items(jobs.size());
@@ -903,9 +916,16 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         if (pc.kind == 3) amg_pass(L);
     };
     for (const Launch &L : launches) pre_pass(L);
-    int it = 0;
+    // Iterations launched between polls: min(poll, 8) first, then the number
+    // the residual's decay since the previous poll predicts to reach every
+    // job's tolerance (plus one), at most `poll`.  Kernels launched after
+    // convergence return at once but still cost a launch each, so the batch
+    // follows the prediction; the arithmetic does not depend on it.
+    int it = 0, next = std::min(poll, 8);
+    std::vector<int> it_prev(jobs.size(), 0);
+    std::vector<double> r2_prev(jobs.size(), 1.0);
     while (true) {
-        const int batch = std::min(poll, std::max(1, max_iter + 1 - it));
+        const int batch = std::min(next, std::max(1, max_iter + 1 - it));
         for (int i = 0; i < batch; ++i, ++it) {
             for (const Launch &L : launches) {
                 const BItem<T> *dev = items_dev + L.offset;
@@ -934,14 +954,33 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, int32_t *fla
         }
         FVX_HIP(hipGetLastError());
         bool all_done = true;
-        std::vector<int32_t> done(jobs.size(), 0);
         const int nj = int(jobs.size());
+        std::vector<PollRec> rec(nj);
         hipLaunchKernelGGL(kb_done<T>, dim3(unsigned(ceil_div(nj, 256))), dim3(256), 0, s, items_dev, nj, flags_dev);
         FVX_HIP(hipGetLastError());
-        FVX_HIP(hipMemcpyAsync(done.data(), flags_dev, 4 * size_t(nj), hipMemcpyDeviceToHost, s));
+        FVX_HIP(hipMemcpyAsync(rec.data(), flags_dev, sizeof(PollRec) * size_t(nj), hipMemcpyDeviceToHost, s));
         FVX_HIP(hipStreamSynchronize(s));
-        for (auto v : done) all_done &= v != 0;
+        for (const auto &r : rec) all_done &= r.done != 0;
         if (all_done || it > max_iter) break;
+        // items_dev is ordered by launch group; map back to jobs.
+        next = 1;
+        int slot = 0;
+        for (const Launch &L : launches)
+            for (int j : L.jobs) {
+                const PollRec &r = rec[slot++];
+                if (r.done) continue;
+                const double target = jobs[j].rtol * jobs[j].rtol;
+                const int span = it - it_prev[j];
+                int need = poll;
+                if (span > 0 && r.r2 > 0.0 && r2_prev[j] > 0.0 && r.r2 < r2_prev[j]) {
+                    const double per = std::log(r.r2 / r2_prev[j]) / span;  // log decay per iteration (< 0)
+                    const double rem = std::log(target / r.r2) / per;
+                    if (std::isfinite(rem)) need = int(std::min<double>(poll, std::max(0.0, std::ceil(rem)) + 1.0));
+                }
+                next = std::max(next, need);
+                it_prev[j] = it;
+                r2_prev[j] = r.r2;
+            }
     }
 }
 
@@ -1023,7 +1062,7 @@ struct Problem {
     bool outer_active = true;
 };
 
-void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<double> *items, int32_t *flags,
+void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<double> *items, PollRec *flags,
                      hipStream_t s) {
     std::vector<CgJob<double>> jobs;
     for (auto &p : P)
@@ -1042,7 +1081,7 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
 // FP32-SpMM inner CG (FP64 dot products and scalars).  Each problem takes the
 // same steps and decisions as when solved alone; the inner CGs of all problems
 // still iterating run as one batch.
-void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<float> *items, int32_t *flags,
+void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<float> *items, PollRec *flags,
                        hipStream_t s) {
     for (auto &p : P) {
         CgDev D = p.w.outer;
@@ -1177,7 +1216,7 @@ BatchLayout batch_layout(int n, const fvx_op *const *ops, bool mixed, bool cheb,
     };
     L.items64 = take(sizeof(BItem<double>) * size_t(n));
     L.items32 = take(sizeof(BItem<float>) * size_t(n));
-    L.flags = take(sizeof(int32_t) * size_t(n));
+    L.flags = take(sizeof(PollRec) * size_t(n));
     for (int i = 0; i < n; ++i) L.offs.push_back(take(carve(nullptr, ops[i], mixed, cheb, amg).bytes));
     L.total = off;
     return L;
@@ -1209,10 +1248,10 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
     }
     if (mixed)
         solve_mixed_batch(P, o, reinterpret_cast<BItem<float> *>(base + L.items32),
-                          reinterpret_cast<int32_t *>(base + L.flags), s);
+                          reinterpret_cast<PollRec *>(base + L.flags), s);
     else
         solve_f64_batch(P, o, reinterpret_cast<BItem<double> *>(base + L.items64),
-                        reinterpret_cast<int32_t *>(base + L.flags), s);
+                        reinterpret_cast<PollRec *>(base + L.flags), s);
     int worst = FVX_OK;
     for (int i = 0; i < n; ++i) {
         fill_stats(stats ? &stats[i] : nullptr, P[i].h, P[i].res2, P[i].status);
