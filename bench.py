@@ -702,8 +702,8 @@ def refine_leg(fvx, inputs, torch, np):
 
 def ns_leg(fvx, inputs, torch, np, rtol=1e-8):
     """The whole incompressible time step (Heun RK3, a projection per stage,
-    Chebyshev-preconditioned Poisson solves warm-started from the previous
-    pressure) on the channel base: the coupled 192 x 128 x 64 channel, and
+    Poisson solves warm-started from the previous pressure, preconditioned by
+    the Chebyshev polynomial or by the multigrid) on the channel base: the coupled 192 x 128 x 64 channel, and
     independent flow states (the base plane repeated k = 1, 16, 64 times
     without coupling) for the whole-iteration speed-up P_k,ite = k t_1 / t_k
     (the paper's P_m,ite).  Random initial velocities, projected by the
@@ -711,9 +711,9 @@ def ns_leg(fvx, inputs, torch, np, rtol=1e-8):
     spec = inputs.channel_base(*BASE)
     mesh = fvx.Mesh.from_spec(spec)
     out = {}
-    kw = dict(rtol=rtol, precond=fvx.PRECOND_CHEBYSHEV, guess=fvx.GUESS_GIVEN)
+    cheb = dict(rtol=rtol, precond=fvx.PRECOND_CHEBYSHEV, guess=fvx.GUESS_GIVEN)
 
-    def run(op, label):
+    def run(op, label, kw):
         U = [op.to_rows(inputs.uniform(0, d, op.n_b * op.k)) for d in range(3)]
         Uf = op.zeros(op.F_b)
         Wz = op.zeros() if op.zfaces else None
@@ -734,19 +734,25 @@ def ns_leg(fvx, inputs, torch, np, rtol=1e-8):
     op = fvx.Operator(mesh, K_MAIN, math.pi / K_MAIN, fvx.PERIODIC_Z, with_f32=False)
     tune(op, fvx)
     tune_cg(op, fvx)
-    out["channel_coupled_k64"] = run(op, "coupled channel k=64")
-    del op
-    states = {}
+    out["channel_coupled_k64"] = run(op, "coupled channel k=64", cheb)
+    amg = fvx.Amg(op)
+    out["channel_coupled_k64_amg"] = run(op, "coupled channel k=64, multigrid", dict(cheb, precond=0, amg=amg))
+    del op, amg
+    states, states_amg = {}, {}
     for k in (1, 16, 64):
         opk = fvx.Operator(mesh, k, math.pi / K_MAIN, fvx.NONE, with_f32=False)
         tune(opk, fvx)
         tune_cg(opk, fvx)
-        states[k] = run(opk, f"independent states k={k}")
-        del opk
+        states[k] = run(opk, f"independent states k={k}", cheb)
+        amg = fvx.Amg(opk)
+        states_amg[k] = run(opk, f"independent states k={k}, multigrid", dict(cheb, precond=0, amg=amg))
+        del opk, amg
         torch.cuda.empty_cache()
-    for k in (16, 64):
-        states[k]["P_k_ite"] = k * states[1]["ms_per_step"] / states[k]["ms_per_step"]
+    for st in (states, states_amg):
+        for k in (16, 64):
+            st[k]["P_k_ite"] = k * st[1]["ms_per_step"] / st[k]["ms_per_step"]
     out["independent_states"] = {str(k): v for k, v in states.items()}
+    out["independent_states_amg"] = {str(k): v for k, v in states_amg.items()}
     return out
 
 
