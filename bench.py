@@ -1041,13 +1041,19 @@ def airfoil_leg(fvx, inputs, torch, np):
     res["cg_tile_f64"], res["cg_tile_f32"] = list(tune_cg(op, fvx)), list(tune_cg(op, fvx, fvx.F32))
     B = op.to_rows(inputs.rhs_uniform(3, op.n_b * k))
     cheb = fvx.PRECOND_CHEBYSHEV
+    t0 = time.perf_counter()
+    amg = fvx.Amg(op)
+    res["amg_setup_s"] = time.perf_counter() - t0
+    res["amg_levels"] = amg.levels()
     for prec, pre, name in ((fvx.MIXED, 0, "mixed"), (fvx.F64, 0, "f64"), (fvx.MIXED, cheb, "mixed_chebyshev"),
-                            (fvx.F64, cheb, "f64_chebyshev")):
-        op.solve(B, rtol=rtol, precision=prec, precond=pre)
+                            (fvx.F64, cheb, "f64_chebyshev"), (fvx.MIXED, amg, "mixed_amg"), (fvx.F64, amg, "f64_amg")):
+        kw = dict(amg=pre) if isinstance(pre, fvx.Amg) else dict(precond=pre)
+        op.solve(B, rtol=rtol, precision=prec, **kw)
         t0 = time.perf_counter()
-        _, st = op.solve(B, rtol=rtol, precision=prec, precond=pre)
+        _, st = op.solve(B, rtol=rtol, precision=prec, **kw)
         res[f"solve_{name}"] = {"s": time.perf_counter() - t0, "iters": st["iters"], "outer": st["outer"],
                                 "relres_true": st["relres_true"]}
+    del amg
     ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z)
     A = fvx.CsrMatrix(ptr, col, val)
     b = torch.as_tensor(op.to_planes(B)).cuda()
@@ -1059,7 +1065,8 @@ def airfoil_leg(fvx, inputs, torch, np):
                                "relres_true": st["relres_true"]}
     log(f"airfoil {op.n_b}x{k}: mixed {res['solve_mixed']['s']:.3f} s, f64 {res['solve_f64']['s']:.3f} s, "
         f"Chebyshev mixed {res['solve_mixed_chebyshev']['s']:.3f} s, f64 {res['solve_f64_chebyshev']['s']:.3f} s, "
-        f"csr3d {res['solve_csr3d_fp64']['s']:.3f} s")
+        f"multigrid mixed {res['solve_mixed_amg']['s']:.3f} s, f64 {res['solve_f64_amg']['s']:.3f} s "
+        f"(setup {res['amg_setup_s']:.2f} s), csr3d {res['solve_csr3d_fp64']['s']:.3f} s")
     return res
 
 

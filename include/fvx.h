@@ -396,7 +396,8 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   plane, by two passes of pairwise aggregation of the base cells (cells in
  *   index order; a free cell i joins its free neighbour j of largest coupling
  *   t_ij among those with t_ij >= beta * max_j' t_ij', ties within a relative
- *   1e-9 to the smallest j; else it stays alone), OR along the repeated
+ *   1e-9 to the smallest j; else it stays alone, and after the pass joins the
+ *   aggregate of its neighbour of largest coupling), OR along the repeated
  *   direction, merging planes 2l and 2l + 1 (coupled planes, k even), which
  *   it does when the lower median over base cells of w_i / max_j t_ij
  *   exceeds z_rule (w_i: coupling to a neighbouring plane).  A level with at

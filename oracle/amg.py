@@ -14,8 +14,10 @@ with no block reuse:
       (Notay, ETNA 37, 2010): cells are visited in index order; an
       unaggregated cell i joins the unaggregated neighbour j with the largest
       coupling t_ij among those with t_ij >= beta * max_j' t_ij' (ties within
-      a relative 1e-9 go to the smallest j), else it stays alone.  The second
-      pass pairs the aggregates of the first on the coarse couplings;
+      a relative 1e-9 go to the smallest j), else it stays alone; then each
+      cell left alone joins the aggregate of its neighbour of largest
+      coupling (the second phase of plain aggregation).  The second pass
+      pairs the aggregates of the first on the coarse couplings;
     - repeated direction: planes 2l and 2l+1 are merged (k even, planes
       coupled periodically);
   the direction is the repeated one when the plane coupling dominates: the
@@ -89,18 +91,30 @@ def couplings(A: sp.csr_matrix, n_b: int, k: int):
     return T, w
 
 
+def _row(T: sp.csr_matrix, i: int):
+    cols = T.indices[T.indptr[i]:T.indptr[i + 1]]
+    vals = T.data[T.indptr[i]:T.indptr[i + 1]]
+    keep = cols != i
+    return cols[keep], vals[keep]
+
+
 def pairwise(T: sp.csr_matrix, beta: float):
-    """One pass of pairwise aggregation; returns (aggregate of each node, count)."""
+    """One pass of pairwise aggregation; returns (aggregate of each node, count).
+
+    Pairing: nodes in index order; a free node pairs with its free neighbour
+    of largest coupling among those at least beta times its largest coupling.
+    Then every node left alone (with a neighbour) joins, in index order, the
+    aggregate of its neighbour of largest coupling: without this, a node whose
+    strong neighbours are always taken first stays alone on every level and
+    coarsening stalls.  Aggregates are numbered in order of their smallest
+    node."""
     n = T.shape[0]
     agg = -np.ones(n, np.int64)
     nc = 0
     for i in range(n):
         if agg[i] >= 0:
             continue
-        cols = T.indices[T.indptr[i]:T.indptr[i + 1]]
-        vals = T.data[T.indptr[i]:T.indptr[i + 1]]
-        keep = cols != i
-        cols, vals = cols[keep], vals[keep]
+        cols, vals = _row(T, i)
         pick = -1
         if len(vals):
             mx = vals.max()
@@ -113,7 +127,21 @@ def pairwise(T: sp.csr_matrix, beta: float):
         if pick >= 0:
             agg[pick] = nc
         nc += 1
-    return agg, nc
+    size = np.bincount(agg, minlength=nc)
+    for i in range(n):
+        if size[agg[i]] != 1:
+            continue
+        cols, vals = _row(T, i)
+        if not len(vals):
+            continue
+        j = int(cols[vals >= vals.max() * (1.0 - TIE)].min())
+        size[agg[i]] -= 1
+        agg[i] = agg[j]
+        size[agg[j]] += 1
+    used = np.flatnonzero(size > 0)
+    renum = -np.ones(nc, np.int64)
+    renum[used] = np.arange(len(used))
+    return renum[agg], len(used)
 
 
 def aggregate(T: sp.csr_matrix, beta: float, passes: int = 2):

@@ -85,7 +85,12 @@ HostLevel fine_level(const fvx_mesh &m, const fvx_op *op, bool dirichlet) {
 
 // One pass of pairwise aggregation: cells in index order; a free cell joins
 // its free neighbour of largest coupling among those at least beta times its
-// largest coupling (ties to the smallest index), else stays alone.
+// largest coupling (ties to the smallest index), else stays alone.  Then each
+// cell left alone (with a neighbour) joins, in index order, the aggregate of
+// its neighbour of largest coupling -- otherwise a cell whose strong
+// neighbours are always taken first stays alone on every level and the
+// coarsening stalls (unstructured meshes) -- and the aggregates are numbered
+// again in their order.
 std::vector<int32_t> pairwise(int64_t n, const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
                               const std::vector<double> &val, double beta, int64_t &nc) {
     std::vector<int32_t> agg(n, -1);
@@ -108,6 +113,27 @@ std::vector<int32_t> pairwise(int64_t n, const std::vector<int64_t> &ptr, const 
         if (pick >= 0) agg[pick] = int32_t(nc);
         ++nc;
     }
+    std::vector<int64_t> size(nc, 0);
+    for (int64_t i = 0; i < n; ++i) ++size[agg[i]];
+    for (int64_t i = 0; i < n; ++i) {
+        if (size[agg[i]] != 1) continue;
+        double mx = -1.0;
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (col[p] != i) mx = std::max(mx, val[p]);
+        if (mx < 0.0) continue;
+        int32_t j = -1;
+        for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p)
+            if (col[p] != i && val[p] >= mx * (1.0 - kTie) && (j < 0 || col[p] < j)) j = col[p];
+        --size[agg[i]];
+        agg[i] = agg[j];
+        ++size[agg[j]];
+    }
+    std::vector<int32_t> renum(nc, -1);
+    int64_t m = 0;
+    for (int64_t c = 0; c < nc; ++c)
+        if (size[c] > 0) renum[c] = int32_t(m++);
+    for (int64_t i = 0; i < n; ++i) agg[i] = renum[agg[i]];
+    nc = m;
     return agg;
 }
 

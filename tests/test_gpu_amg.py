@@ -27,8 +27,9 @@ CASES = [
     (inputs.channel_base(20, 16), 5, None, 0, False, 20),       # independent planes
     (inputs.channel_base(17, 13), 5, 0.05, 1, False, 25),       # odd k: no plane merging possible
     (inputs.unit_square_triangles(8), 4, None, 1, False, 30),
+    (inputs.naca_delaunay(seed=3, n_interior=1500, n_surface=60, n_box_side=16), 4, 0.2, 1, False, 40),
 ]
-IDS = ["channel", "channel-z", "convection", "dirichlet", "independent", "odd-k", "triangles"]
+IDS = ["channel", "channel-z", "convection", "dirichlet", "independent", "odd-k", "triangles", "airfoil"]
 
 
 def _setup(spec, k, dz, coupling, dirichlet, coarse_max, degree=2):

@@ -26,31 +26,57 @@ def _chain(c):
 
 @pytest.mark.parametrize("c,expect", [
     ([1, 3, 1, 1, 2], [0, 0, 1, 1, 2, 2]),           # pairs in order
-    ([1, 10, 1, 1], [0, 0, 1, 2, 2]),                # cell 2: its only free neighbour is weak (1 < 0.25 * 10)
+    ([1, 10, 1, 1], [0, 0, 0, 1, 1]),                # cell 2: its only free neighbour is weak (1 < 0.25 * 10),
+                                                     # so it stays alone, then joins its strongest neighbour's pair
     ([1, 1, 1], [0, 0, 1, 1]),                       # ties go to the smallest index
     ([5, 1, 5, 1, 5], [0, 0, 1, 1, 2, 2]),
-    ([1, 4, 4, 1], [0, 0, 1, 1, 2]),                 # cell 2 pairs with 3 (tie 4 = 4, 1 is taken); 4 alone
+    ([1, 4, 4, 1], [0, 0, 1, 1, 1]),                 # cell 2 pairs with 3 (tie 4 = 4, 1 is taken); 4 alone, joins 3
+    ([4, 1, 1, 4, 1, 1], [0, 0, 1, 1, 2, 2, 2]),     # 2 pairs with 3 (1 = 1, 1 is taken); 4 pairs with 5 (its
+                                                     # threshold 0.25 * 4 admits 1); 6 alone, joins 5's pair
 ])
 def test_pairwise_by_hand(c, expect):
     agg, nc = amg.pairwise(_chain(np.array(c, float)), 0.25)
     assert agg.tolist() == expect and nc == max(expect) + 1
 
 
+def _sym(edges, n):
+    r, c, v = zip(*edges)
+    return sp.csr_matrix((np.r_[v, v], (np.r_[r, c], np.r_[c, r])), shape=(n, n))
+
+
 def test_pairwise_prefers_the_strongest_free_neighbour():
-    # star: 0 linked to 1 (1.0), 2 (3.0), 3 (2.0): 0 pairs with 2; 1 and 3 alone (their only neighbour is taken)
-    T = sp.csr_matrix((np.r_[[1.0, 3.0, 2.0] * 2], (np.r_[0, 0, 0, 1, 2, 3], np.r_[1, 2, 3, 0, 0, 0])), shape=(4, 4))
-    agg, nc = amg.pairwise(T, 0.25)
-    assert agg.tolist() == [0, 1, 0, 2] and nc == 3
+    # star: 0 linked to 1 (1.0), 2 (3.0), 3 (2.0): 0 pairs with 2; 1 and 3 (their only neighbour taken) join it
+    agg, nc = amg.pairwise(_sym([(0, 1, 1.0), (0, 2, 3.0), (0, 3, 2.0)], 4), 0.25)
+    assert agg.tolist() == [0, 0, 0, 0] and nc == 1
+    # a chain 4 - 0 - 1 - 2 - 3 with 0-1 strongest: 0 pairs with 1, 2 with 3; 4 joins 0's pair
+    agg, nc = amg.pairwise(_sym([(0, 1, 5.0), (1, 2, 1.0), (2, 3, 2.0), (0, 4, 1.0)], 5), 0.25)
+    assert agg.tolist() == [0, 0, 1, 1, 0] and nc == 2
 
 
 def test_pairwise_breaks_ties_towards_the_smallest_index():
-    # star with equal couplings: 0 pairs with 1; 2 and 3 touch only 0 (taken) and stay alone
-    T = sp.csr_matrix((np.ones(6), (np.r_[0, 0, 0, 3, 2, 1], np.r_[3, 2, 1, 0, 0, 0])), shape=(4, 4))
-    agg, nc = amg.pairwise(T, 0.25)
-    assert agg.tolist() == [0, 0, 1, 2] and nc == 3
-    # equal within the relative tie tolerance counts as a tie
-    T = sp.csr_matrix((np.r_[1.0, 1.0 + 1e-12, 1.0, 1.0 + 1e-12], (np.r_[0, 0, 1, 2], np.r_[1, 2, 0, 0])), shape=(3, 3))
-    assert amg.pairwise(T, 0.25)[0].tolist() == [0, 0, 1]
+    # equal couplings 0-1, 0-2 and 1-3: 0 pairs with 1 (smallest), 2 joins them, 3 joins 1's aggregate
+    agg, nc = amg.pairwise(_sym([(0, 1, 1.0), (0, 2, 1.0), (1, 3, 1.0)], 4), 0.25)
+    assert agg.tolist() == [0, 0, 0, 0]
+    # 0 - 1 - 2 and 2 - 3 equal, 3 - 4 stronger: 0 pairs with 1; 2 pairs with 3 (tie of 1 and 3: 1 is taken);
+    # 4 alone joins 3's pair
+    agg, nc = amg.pairwise(_sym([(0, 1, 1.0), (1, 2, 1.0), (2, 3, 1.0), (3, 4, 3.0)], 5), 0.25)
+    assert agg.tolist() == [0, 0, 1, 1, 1] and nc == 2
+    # equal within the relative tie tolerance counts as a tie: with 0-2 stronger by 1e-12, 0 still pairs with 1
+    # (2 then pairs with 4, 3 joins 1's pair); stronger by 1e-6, 0 pairs with 2 (1 with 3, 4 joins 2's pair)
+    e = lambda d: _sym([(0, 1, 1.0), (0, 2, 1.0 + d), (1, 3, 1.0), (2, 4, 1.0)], 5)
+    assert amg.pairwise(e(1e-12), 0.25)[0].tolist() == [0, 0, 1, 0, 1]
+    assert amg.pairwise(e(1e-6), 0.25)[0].tolist() == [0, 1, 0, 1, 0]
+
+
+def test_lonely_cells_do_not_stall_coarsening():
+    """A graph where index order strands many cells (each cell 2m links
+    strongly to 2m - 1, taken first by 2m - 2): without the second phase
+    every other cell would stay alone on every level."""
+    n = 40
+    e = [(i, i + 1, 1.0 if i % 2 == 0 else 3.0) for i in range(n - 1)]
+    agg, nc = amg.aggregate(_sym(e, n), 0.25)
+    assert nc <= n // 3
+    assert np.bincount(agg).min() >= 2
 
 
 def test_double_pairwise_on_a_uniform_grid_makes_2x2_boxes():
@@ -102,7 +128,7 @@ def test_galerkin_levels_keep_the_extruded_form(dirichlet):
         assert np.array_equal(P.sum(axis=1), np.ones(P.shape[0]))      # one aggregate per unknown
         if lv.kind == "xy":
             sizes = np.bincount(lv.agg)
-            assert sizes.min() >= 1 and sizes.max() <= 4
+            assert sizes.min() >= 1 and sizes.sum() == lv.n_b
             T, _ = amg.couplings(lv.A, lv.n_b, lv.k)
             for a in range(sizes.size):                                  # aggregates are connected
                 m = np.flatnonzero(lv.agg == a)
@@ -235,3 +261,15 @@ def test_prolongation_maps_each_plane_to_the_same_plane():
     P = lv.P.tocoo()
     l, c = P.row // m3.n_b, P.row % m3.n_b
     assert np.array_equal(P.col, (l // 2) * m3.n_b + c)
+
+
+def test_unstructured_mesh_coarsens_steadily():
+    """On a Delaunay mesh around an airfoil (cells of very different sizes)
+    every base-plane level at least halves the cells, down to the coarsest."""
+    spec = inputs.naca_delaunay(seed=3, n_interior=1500, n_surface=60, n_box_side=16)
+    m3 = oracle.Mesh3D(oracle.geometry(spec), 4, 0.2, oracle.PERIODIC_Z)
+    h = amg.build((-m3.lap()).tocsr(), m3.n_b, 4, True, amg.AmgOpts(coarse_max=40))
+    assert h.levels[-1].n_b * h.levels[-1].k <= 40
+    for a, b in zip(h.levels, h.levels[1:]):
+        if a.kind == "xy":
+            assert b.n_b <= a.n_b // 2
