@@ -846,7 +846,7 @@ def amg_leg(fvx, torch, inputs, op, D, rtol):
     """CG preconditioned by one V-cycle of the aggregation multigrid (default
     options: Chebyshev degree 2 on [2/8, 2], pairwise aggregation with beta
     0.25, plane merging when the plane coupling dominates, coarsest level at
-    most 512 unknowns) on the benchmark's projection right-hand side, FP64 and
+    most 2048 unknowns) on the benchmark's projection right-hand side, FP64 and
     mixed precision, the best of 3 timed solves each; the time of one V-cycle
     and, per level, the level's SpMM (its operator on the level's k planes;
     graph-timed, inputs warm in the caches) -- the per-level SpMM table of the

@@ -426,7 +426,7 @@ typedef struct fvx_amg_opts {
     int32_t max_levels;  /* 1..16 */
 } fvx_amg_opts;
 
-/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 512, max_levels 16. */
+/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 2048, max_levels 16. */
 int fvx_amg_opts_default(fvx_amg_opts *opts);
 
 /* Builds the hierarchy of op (which must have been built from mesh m with

@@ -53,7 +53,7 @@ class AmgOpts:
     ratio: float = 8.0
     beta: float = 0.25
     z_rule: float = 1.0
-    coarse_max: int = 512
+    coarse_max: int = 2048
     max_levels: int = 16
 
 

@@ -463,7 +463,7 @@ class Amg:
     level an operator of the same repeated-block form.  Pass it to
     Operator.solve(amg=...) to precondition CG with one V-cycle."""
 
-    def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=512, max_levels=16,
+    def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=2048, max_levels=16,
                  stream=None):
         torch = _torch()
         if op.mesh is None:

@@ -247,7 +247,9 @@ std::vector<double> dense_level(const HostLevel &L, bool coupled) {
     return A;
 }
 
-// Inverse of an SPD matrix by Cholesky factorisation (n <= kMaxAmgCoarse).
+// Inverse of an SPD matrix (n <= kMaxAmgCoarse) by Cholesky factorisation
+// A = L L^T, M = L^-1 row by row, A^-1 = M^T M (every inner loop runs along
+// a row).
 std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
     for (int64_t j = 0; j < n; ++j) {
         double d = A[j * n + j];
@@ -261,18 +263,25 @@ std::vector<double> spd_inverse(std::vector<double> A, int64_t n) {
             A[i * n + j] = s / d;
         }
     }
-    // inv = L^-T L^-1, column by column.
-    std::vector<double> inv(size_t(n * n), 0.0), y(n);
-    for (int64_t c = 0; c < n; ++c) {
-        for (int64_t i = 0; i < n; ++i) {
-            double s = i == c ? 1.0 : 0.0;
-            for (int64_t p = c; p < i; ++p) s -= A[i * n + p] * y[p];
-            y[i] = i < c ? 0.0 : s / A[i * n + i];
+    std::vector<double> M(size_t(n * n), 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        double *mi = &M[i * n];
+        mi[i] = 1.0;
+        for (int64_t p = 0; p < i; ++p) {
+            const double l = A[i * n + p];
+            const double *mp = &M[p * n];
+            for (int64_t c = 0; c <= p; ++c) mi[c] -= l * mp[c];
         }
-        for (int64_t i = n - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int64_t p = i + 1; p < n; ++p) s -= A[p * n + i] * inv[p * n + c];
-            inv[i * n + c] = s / A[i * n + i];
+        const double inv_d = 1.0 / A[i * n + i];
+        for (int64_t c = 0; c <= i; ++c) mi[c] *= inv_d;
+    }
+    std::vector<double> inv(size_t(n * n), 0.0);
+    for (int64_t k = 0; k < n; ++k) {
+        const double *mk = &M[k * n];
+        for (int64_t i = 0; i <= k; ++i) {
+            const double a = mk[i];
+            double *row = &inv[i * n];
+            for (int64_t c = 0; c <= k; ++c) row[c] += a * mk[c];
         }
     }
     return inv;
@@ -415,13 +424,24 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_amg_restrict(RowArgs<T> a, cons
     const VB vb = vb_single(a.remap);
     ROW_PROLOGUE
     const bool single = lpr * V >= a.k;
+    const PlainLoad<T, V> in{z, a.ld};
     FOR_ROWS {
         vec_t<T, V> sum(0);
-        for (int32_t p = mptr[row]; p < mptr[row + 1]; ++p) {
+        int32_t p = mptr[row];
+        const int32_t pe = mptr[row + 1];
+        // Two members per step, so that their loads overlap; summed in member order.
+        for (; p + 2 <= pe; p += 2) {
+            const int64_t i0 = midx[p], i1 = midx[p + 1];
+            vec_t<T, V> z0, z1;
+            const vec_t<T, V> a0 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i0, c0, sub, lpr, single, z0);
+            const vec_t<T, V> a1 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i1, c0, sub, lpr, single, z1);
+            sum += ldv<T, V>(r + i0 * a.ld + c0) + a0;
+            sum += ldv<T, V>(r + i1 * a.ld + c0) + a1;
+        }
+        if (p < pe) {
             const int64_t i = midx[p];
             vec_t<T, V> zi;
-            const vec_t<T, V> acc =
-                lap_row_ld<T, V, Z, WT>(a.A, PlainLoad<T, V>{z, a.ld}, a.n_b, a.k, a.W, i, c0, sub, lpr, single, zi);
+            const vec_t<T, V> acc = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i, c0, sub, lpr, single, zi);
             sum += ldv<T, V>(r + i * a.ld + c0) + acc;
         }
         stv_masked<T, V>(rc + row * a.ld + c0, sum, a.k - c0);
@@ -813,7 +833,7 @@ int fvx_amg_opts_default(fvx_amg_opts *o) {
     o->ratio = 8.0;
     o->beta = 0.25;
     o->z_rule = 1.0;
-    o->coarse_max = 512;
+    o->coarse_max = 2048;
     o->max_levels = 16;
     return FVX_OK;
 }

@@ -259,7 +259,24 @@ __device__ __forceinline__ vec_t<T, V> lap_row_dyn(const OpDev<T> &A, const Ld &
     using vt = vec_t<T, V>;
     xo = in.vec(row, c0);
     vt acc = A.diag[row] * xo;
-    for (int e = 0; e < W; ++e) {
+    // Entries in groups of 4: the group's column indices, values and gathers
+    // are all issued before its multiply-adds (same order of the sum).
+    int e = 0;
+    for (; e + 4 <= W; e += 4) {
+        int64_t j[4];
+        T v[4];
+        vt xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            j[u] = A.ell_col[(e + u) * n_b + row];
+            v[u] = A.ell_val[(e + u) * n_b + row];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xj[u] = in.vec(j[u], c0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * xj[u];
+    }
+    for (; e < W; ++e) {
         const int64_t j = A.ell_col[e * n_b + row];
         const T v = A.ell_val[e * n_b + row];
         acc += v * in.vec(j, c0);
