@@ -401,10 +401,9 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   direction, merging planes 2l and 2l + 1 (coupled planes, k even), which
  *   it does when the lower median over base cells of w_i / max_j t_ij
  *   exceeds z_rule (w_i: coupling to a neighbouring plane).  A level with at
- *   most coarse_max unknowns per independent system (n_b k coupled, n_b for
- *   independent planes) is the coarsest; it is solved with its dense
- *   pseudo-inverse (inverse with Dirichlet walls), formed on the host in
- *   FP64.
+ *   most coarse_max unknowns (n_b k, all planes) is the coarsest; it is
+ *   solved with its dense pseudo-inverse (inverse with Dirichlet walls) per
+ *   independent system, formed on the host in FP64.
  *   Cycle: V-cycle; on each level `degree` Chebyshev steps for A z = r on
  *   [2 / ratio, 2] of the spectrum of D^-1 A from z = 0, restriction of the
  *   residual (fused with its SpMM), the coarse cycle, prolongation of the
@@ -422,7 +421,7 @@ typedef struct fvx_amg_opts {
     double ratio;        /* smoother interval [2 / ratio, 2] (> 1) */
     double beta;         /* aggregation strength threshold (0 < beta <= 1) */
     double z_rule;       /* plane-merging threshold (>= 0) */
-    int32_t coarse_max;  /* coarsest level size per independent system (1..2048) */
+    int32_t coarse_max;  /* coarsest level size n_b k (1..2048) */
     int32_t max_levels;  /* 1..16 */
 } fvx_amg_opts;
 

@@ -27,9 +27,11 @@ with no block reuse:
   products on the assembled matrices.  t and w of a level are read back from
   its assembled operator: t_ij = -a_ij within plane 0, w_i = -a_i,(plane 1, i)
   (halved for two planes, whose two plane neighbours coincide).
-* Coarsest level (at most coarse_max unknowns per independent system): the
-  pseudo-inverse, from the eigen-decomposition with eigenvalues below 1e-10
-  of the largest dropped.
+* Coarsest level (at most coarse_max unknowns, counted over all planes;
+  independent planes share one hierarchy): the pseudo-inverse, from the
+  eigen-decomposition with the eigenvalues below 1e-10 of the Galerkin scale
+  dropped (the largest row sum of |P|^T |A| |P| carried down the levels: a
+  one-cell Neumann level is zero up to the rounding of its sums).
 * Cycle: a V-cycle with the Chebyshev-polynomial smoother of the
   preconditioned CG on [2 / ratio, 2] (Saad, Iterative Methods for Sparse
   Linear Systems, 2nd ed., Algorithm 12.1, with the Jacobi scaling D^-1):
@@ -163,15 +165,19 @@ def lower_median(v: np.ndarray) -> float:
     return float(s[(len(s) - 1) // 2])
 
 
-def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | None = None) -> Hierarchy:
+def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | None = None,
+          columns: int = 1) -> Hierarchy:
     """The hierarchy of A0 (SPD form -L of one independent system: k planes
-    coupled periodically when `coupled`, else k = 1)."""
+    coupled periodically when `coupled`, else k = 1), shared by `columns`
+    independent systems (the planes of uncoupled operators): a level with at
+    most coarse_max unknowns over all of them is the coarsest."""
     opts = opts or AmgOpts()
     h = Hierarchy(opts=opts)
     lev = Level(A0.tocsr(), n_b, k)
+    absA = abs(lev.A)  # |P|^T |A| |P| down the levels: the scale of the Galerkin sums' rounding
     while True:
         h.levels.append(lev)
-        if lev.n_b * lev.k <= opts.coarse_max or len(h.levels) >= opts.max_levels:
+        if lev.n_b * lev.k * columns <= opts.coarse_max or len(h.levels) >= opts.max_levels:
             break
         T, w = couplings(lev.A, lev.n_b, lev.k)
         tmax = np.zeros(lev.n_b)
@@ -191,11 +197,12 @@ def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | No
             P = sp.kron(sp.identity(lev.k), Pb).tocsr()
             lev.kind, lev.agg, lev.P = "xy", agg, P
             nxt = Level((P.T @ lev.A @ P).tocsr(), nc, lev.k)
+        absA = (lev.P.T @ absA @ lev.P).tocsr()
         lev = nxt
     last = h.levels[-1]
     last.kind, last.agg, last.P = "", None, None
     lam, Q = np.linalg.eigh(last.A.toarray())
-    keep = lam > 1e-10 * lam.max()
+    keep = lam > 1e-10 * abs(absA).sum(axis=1).max()
     h.pinv = (Q[:, keep] / lam[keep]) @ Q[:, keep].T
     return h
 

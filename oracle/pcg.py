@@ -95,7 +95,7 @@ def pcg(mesh, L: sp.csr_matrix, b: np.ndarray, tol: float, precond: str = "jacob
 
         if precond == "amg":
             from . import amg as _amg
-            hier = _amg.build(A, mesh.n_b, 1 if ind else mesh.k, not ind, amg_opts)
+            hier = _amg.build(A, mesh.n_b, 1 if ind else mesh.k, not ind, amg_opts, columns=mesh.k if ind else 1)
 
         def prec(v):
             if precond == "amg":

@@ -202,8 +202,7 @@ std::vector<HostLevel> build_levels(HostLevel L0, bool coupled, const fvx_amg_op
     L.push_back(std::move(L0));
     while (true) {
         HostLevel &lev = L.back();
-        const int64_t size = lev.n * (coupled ? lev.k : 1);
-        if (size <= o.coarse_max || int(L.size()) >= o.max_levels) break;
+        if (lev.n * lev.k <= o.coarse_max || int(L.size()) >= o.max_levels) break;
         if (coupled && lev.k >= 2 && lev.k % 2 == 0 && plane_dominance(lev) > o.z_rule) {
             lev.kind = 2;
             HostLevel nxt = merge_planes(lev);
@@ -297,6 +296,7 @@ std::vector<double> coarsest_pinv(const HostLevel &L, bool coupled, bool singula
     if (singular) {
         double tr = 0.0;
         for (int64_t i = 0; i < n; ++i) tr += A[i * n + i];
+        if (!(tr > 0.0)) return std::vector<double>(size_t(n * n), 0.0);  // one cell: A = 0, A^+ = 0
         alpha = tr / double(n) / double(n);
         for (auto &v : A) v += alpha;
     }
