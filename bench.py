@@ -60,6 +60,8 @@ def lap_kernel_name(tile, k):
     vec, lpr, block, _, _, stage, nt = tile
     span = vec * lpr
     passes = k // span if k % span == 0 else 0
+    if span == k and lpr >= 8 and not stage:  # the channel base is a Cartesian 5-point grid
+        return f"k_lap_cart<double,{vec},true,{bool(nt)}>"
     if passes in (2, 4) and not stage and block <= 512:
         return f"k_lap_passes<double,{vec},true,4,{bool(nt)},{passes}>"
     return f"k_lap<double,{vec},true,4,{bool(stage)},{bool(nt)}>"

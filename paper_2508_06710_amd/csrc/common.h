@@ -67,6 +67,12 @@ struct OpDev {
     const T *fnx = nullptr, *fny = nullptr;   // [F_b]
     const T *gsx = nullptr, *gsy = nullptr;   // [F_b] len_f dist_f n_f / 2
     const T *inv_area = nullptr;              // [n_b]
+    // Cartesian base (cell (i, j) at j*nx + i) whose face graph is the
+    // 5-point stencil: per row [diag, w, c_S, c_W, c_E, c_N, 0, 0] with the
+    // neighbours' indices computed from (i, j) (an absent neighbour has
+    // coefficient 0); NULL when the base is not such a grid.
+    const T *cart = nullptr;
+    int cart_nx = 0, cart_ny = 0, cart_px = 0, cart_py = 0;
 };
 
 }  // namespace fvx

@@ -239,13 +239,13 @@ __device__ __forceinline__ vec_t<T, V> lap_row_meta(const RowMeta<T, WT> &m, con
     for (int e = 0; e < WT; ++e) xj[e] = in.vec(m.col[e], c0);
     vt acc = m.diag * xo;
 #pragma unroll
-    for (int e = 0; e < WT; ++e) acc += m.val[e] * xj[e];
+    for (int e = 0; e < WT; ++e) acc = __builtin_elementwise_fma(vt(m.val[e]), xj[e], acc);
     if constexpr (Z) {
         const auto nb = neighbours_of<T, V>(xo, in, row, c0, sub, lpr, k, single);
 #pragma unroll
         for (int t = 0; t < V; ++t) {
             const int l = c0 + t;
-            acc[t] += m.w * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
+            acc[t] = __builtin_elementwise_fma(m.w, left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k), acc[t]);
         }
     }
     return acc;
@@ -274,12 +274,12 @@ __device__ __forceinline__ vec_t<T, V> lap_row_dyn(const OpDev<T> &A, const Ld &
 #pragma unroll
         for (int u = 0; u < 4; ++u) xj[u] = in.vec(j[u], c0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u] * xj[u];
+        for (int u = 0; u < 4; ++u) acc = __builtin_elementwise_fma(vt(v[u]), xj[u], acc);
     }
     for (; e < W; ++e) {
         const int64_t j = A.ell_col[e * n_b + row];
         const T v = A.ell_val[e * n_b + row];
-        acc += v * in.vec(j, c0);
+        acc = __builtin_elementwise_fma(vt(v), in.vec(j, c0), acc);
     }
     if constexpr (Z) {
         const T wr = A.w[row];
@@ -287,7 +287,7 @@ __device__ __forceinline__ vec_t<T, V> lap_row_dyn(const OpDev<T> &A, const Ld &
 #pragma unroll
         for (int t = 0; t < V; ++t) {
             const int l = c0 + t;
-            acc[t] += wr * (left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k));
+            acc[t] = __builtin_elementwise_fma(wr, left_of<T, V>(xo, nb, t) + right_of<T, V>(xo, nb, t, l, k), acc[t]);
         }
     }
     return acc;

@@ -24,6 +24,10 @@ struct HostOp {
     // FP32 copies: diagonal rebuilt in FP32 so that rows sum to zero up to
     // FP32 rounding of that sum.
     std::vector<float> diag32;
+    // Cartesian 5-point record [n_b][8] (diag, w, S, W, E, N, 0, 0); empty
+    // when the base is not such a grid.
+    std::vector<double> cart;
+    int nx = 0, ny = 0, px = 0, py = 0;
 };
 
 // One axis of a Cartesian base: cell centres and, when periodic, the period.
@@ -302,7 +306,7 @@ struct Layout {
 };
 
 struct Offsets {
-    size_t ell_col, cf_face, f_c1, f_c2;
+    size_t ell_col, cf_face, f_c1, f_c2, cart[2];
     size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2], dinv[2];
     size_t fnx[2], fny[2], gsx[2], gsy[2], inv_area[2];
     size_t total;
@@ -332,6 +336,7 @@ Offsets layout(const HostOp &h, bool f32) {
         o.gsx[p] = L.take(v * h.gsx.size());
         o.gsy[p] = L.take(v * h.gsy.size());
         o.inv_area[p] = L.take(v * h.inv_area.size());
+        o.cart[p] = L.take(v * h.cart.size());
     }
     o.total = L.off;
     return o;
@@ -355,6 +360,59 @@ void check_desc(const fvx_mesh *m, const fvx_op_desc *d) {
         FVX_REQUIRE(d->k <= 64 || (d->k <= 128 && d->k % 2 == 0), FVX_E_UNSUPPORTED,
                     "13/27-point operators support k <= 64, or even k <= 128 (one pass of a row group)");
     }
+}
+
+// The Cartesian record of a 7-point operator on an nx x ny grid: every ELL
+// entry of row (i, j) must be exactly one of its S, W, E, N neighbours
+// (periodic axes need at least 3 cells, so that no two directions meet the
+// same cell, and the ELL width is 4); otherwise no record is built.  With a
+// record, the ELL rows are stored in that direction order too (an absent
+// neighbour as padding in its place), so that every kernel sums a row's
+// entries in the same order.
+void build_cart(const fvx_mesh &m, HostOp &h) {
+    const int nx = m.grid_nx, ny = m.grid_ny;
+    if (nx <= 0 || ny <= 0 || int64_t(nx) * ny != h.n_b || h.W != 4) return;
+    const bool px = m.periodic_x, py = m.periodic_y;
+    if ((px && nx < 3) || (py && ny < 3)) return;
+    const int64_t nb = h.n_b;
+    std::vector<double> rec(size_t(nb) * 8, 0.0);
+    for (int64_t row = 0; row < nb; ++row) {
+        const int64_t i = row % nx, j = row / nx;
+        const int64_t dir[4] = {j > 0 ? row - nx : (py ? row + int64_t(nx) * (ny - 1) : -1),
+                                i > 0 ? row - 1 : (px ? row + nx - 1 : -1),
+                                i < nx - 1 ? row + 1 : (px ? row - (nx - 1) : -1),
+                                j < ny - 1 ? row + nx : (py ? row - int64_t(nx) * (ny - 1) : -1)};
+        double *r = &rec[size_t(row) * 8];
+        r[0] = h.diag[row];
+        r[1] = h.w[row];
+        bool seen[4] = {false, false, false, false};
+        for (int e = 0; e < h.W; ++e) {
+            const int64_t c = h.ell_col[size_t(e) * nb + row];
+            const double v = h.ell_val[size_t(e) * nb + row];
+            if (c == row && v == 0.0) continue;  // padding
+            int d = 0;
+            while (d < 4 && dir[d] != c) ++d;
+            if (d == 4 || seen[d]) return;
+            seen[d] = true;
+            r[2 + d] = v;
+        }
+    }
+    for (int64_t row = 0; row < nb; ++row) {
+        const int64_t i = row % nx, j = row / nx;
+        const int64_t dir[4] = {j > 0 ? row - nx : (py ? row + int64_t(nx) * (ny - 1) : row),
+                                i > 0 ? row - 1 : (px ? row + nx - 1 : row),
+                                i < nx - 1 ? row + 1 : (px ? row - (nx - 1) : row),
+                                j < ny - 1 ? row + nx : (py ? row - int64_t(nx) * (ny - 1) : row)};
+        for (int d = 0; d < 4; ++d) {
+            h.ell_col[size_t(d) * nb + row] = int32_t(dir[d]);
+            h.ell_val[size_t(d) * nb + row] = rec[size_t(row) * 8 + 2 + d];
+        }
+    }
+    h.cart = std::move(rec);
+    h.nx = nx;
+    h.ny = ny;
+    h.px = px;
+    h.py = py;
 }
 
 template <typename T>
@@ -476,6 +534,7 @@ int fvx_op_bytes(const fvx_mesh *m, const fvx_op_desc *d, size_t *bytes) {
         fvx::check_desc(m, d);
         FVX_REQUIRE(bytes, FVX_E_ARG, "bytes is NULL");
         auto h = fvx::build_host(*m, *d);
+        if (d->stencil != 13 && d->stencil != 27) fvx::build_cart(*m, h);
         *bytes = fvx::layout(h, d->with_f32 != 0).total;
         return FVX_OK;
     });
@@ -490,6 +549,7 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
                     "device buffer must be 256-byte aligned");
         const bool f32 = d->with_f32 != 0;
         auto h = fvx::build_host(*m, *d);
+        if (d->stencil != 13 && d->stencil != 27) fvx::build_cart(*m, h);
         auto o = fvx::layout(h, f32);
         FVX_REQUIRE(bytes >= o.total, FVX_E_NOMEM,
                     "operator buffer too small: need " + std::to_string(o.total));
@@ -518,13 +578,17 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             dinv32[i] = h.diag32[i] != 0.0f ? float(1.0 / -double(h.diag32[i])) : 1.0f;
         }
         put(o.dinv[0], dinv.data(), 8 * nb);
+        put(o.cart[0], h.cart.data(), 8 * h.cart.size());
         for (auto pr : {std::make_pair(o.fnx[0], &h.fnx), std::make_pair(o.fny[0], &h.fny),
                         std::make_pair(o.gsx[0], &h.gsx), std::make_pair(o.gsy[0], &h.gsy),
                         std::make_pair(o.inv_area[0], &h.inv_area)})
             put(pr.first, pr.second->data(), 8 * pr.second->size());
         std::vector<float> nv32[5];
-        std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232;
+        std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232, cart32;
         if (f32) {
+            cart32 = fvx::cast<float>(h.cart);
+            for (size_t r = 0; r < cart32.size() / 8; ++r) cart32[r * 8] = h.diag32[r];  // the FP32 diagonal
+            put(o.cart[1], cart32.data(), 4 * cart32.size());
             v132 = fvx::cast<float>(h.ell_v1);
             w232 = fvx::cast<float>(h.w2);
             put(o.ell_v1[1], v132.data(), 4 * v132.size());
@@ -584,6 +648,13 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             D.ell_v1 = h.ell_v1.empty() ? nullptr : reinterpret_cast<const T *>(base + o.ell_v1[p]);
             D.w2 = h.w2.empty() ? nullptr : reinterpret_cast<const T *>(base + o.w2[p]);
             D.dinv = reinterpret_cast<const T *>(base + o.dinv[p]);
+            if (!h.cart.empty()) {
+                D.cart = reinterpret_cast<const T *>(base + o.cart[p]);
+                D.cart_nx = h.nx;
+                D.cart_ny = h.ny;
+                D.cart_px = h.px;
+                D.cart_py = h.py;
+            }
             if (!h.fnx.empty()) {
                 D.fnx = reinterpret_cast<const T *>(base + o.fnx[p]);
                 D.fny = reinterpret_cast<const T *>(base + o.fny[p]);

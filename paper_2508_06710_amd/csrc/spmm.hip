@@ -53,6 +53,60 @@ __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict_
     }
 }
 
+// The same product on a Cartesian base with the 5-point face graph, when one
+// pass of a row group covers the k columns exactly (lanes_per_row * V == k,
+// lanes_per_row >= 8): the neighbours' indices come from (i, j) instead of
+// the ELL columns, and the row's 8 coefficients [diag, w, S, W, E, N, 0, 0]
+// arrive with one coalesced load per row group (lane q takes coefficient q)
+// and shuffles -- so the gathers depend on no load.  The four entries are
+// applied in the order S, W, E, N, which is the order of the ELL row of such
+// an operator (an absent neighbour has coefficient 0 and points at the row
+// itself), with the multiply-adds of lap_row_meta: the result is bitwise that
+// of k_lap.
+template <typename T, int V, bool Z, bool NT>
+__global__ __launch_bounds__(1024) void k_lap_cart(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+                                                   const double *__restrict__ cs) {
+    using vt = vec_t<T, V>;
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const int grp = threadIdx.x / lpr;
+    const int c0 = sub * V;
+    const uint32_t nx = uint32_t(a.A.cart_nx), ny = uint32_t(a.A.cart_ny);  // n_b < 2^30
+    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
+    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
+        const int64_t row = t * a.rows_per_tile + grp;
+        if (row >= a.n_rows) break;  // uniform over the row group
+        const T mine = a.A.cart[row * 8 + (sub & 7)];
+        const uint32_t r = uint32_t(row), j = r / nx, i = r - j * nx;  // 32-bit: no 64-bit division
+        const uint32_t cS = j > 0 ? r - nx : (a.A.cart_py ? r + nx * (ny - 1) : r);
+        const uint32_t cW = i > 0 ? r - 1 : (a.A.cart_px ? r + nx - 1 : r);
+        const uint32_t cE = i < nx - 1 ? r + 1 : (a.A.cart_px ? r - (nx - 1) : r);
+        const uint32_t cN = j < ny - 1 ? r + nx : (a.A.cart_py ? r - nx * (ny - 1) : r);
+        const vt xo = ldv<T, V>(X + row * a.ld + c0);
+        const vt xS = ldv<T, V>(X + int64_t(cS) * a.ld + c0), xW = ldv<T, V>(X + int64_t(cW) * a.ld + c0);
+        const vt xE = ldv<T, V>(X + int64_t(cE) * a.ld + c0), xN = ldv<T, V>(X + int64_t(cN) * a.ld + c0);
+        const T d = __shfl(mine, 0, lpr), w = __shfl(mine, 1, lpr);
+        const T vS = __shfl(mine, 2, lpr), vW = __shfl(mine, 3, lpr), vE = __shfl(mine, 4, lpr), vN = __shfl(mine, 5, lpr);
+        vt acc = d * xo;
+        acc = __builtin_elementwise_fma(vt(vS), xS, acc);
+        acc = __builtin_elementwise_fma(vt(vW), xW, acc);
+        acc = __builtin_elementwise_fma(vt(vE), xE, acc);
+        acc = __builtin_elementwise_fma(vt(vN), xN, acc);
+        if constexpr (Z) {
+            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, a.k);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                acc[q] = __builtin_elementwise_fma(w, left_of<T, V>(xo, nb, q) + right_of<T, V>(xo, nb, q, c0 + q, a.k),
+                                                   acc[q]);
+        }
+        if (cs) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) acc[q] *= T(cs[c0 + q]);
+        }
+        stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
+    }
+}
+
 // The same product when a row group covers the k columns in exactly P
 // passes (k = P * lanes_per_row * V): the row's entries are read once, and
 // every pass's own-row and neighbour-row loads are issued before the first
@@ -83,7 +137,7 @@ __global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__res
             const int c0 = (p * lpr + sub) * V;
             vec_t<T, V> acc = m.diag * xo[p];
 #pragma unroll
-            for (int e = 0; e < WT; ++e) acc += m.val[e] * xj[p][e];
+            for (int e = 0; e < WT; ++e) acc = __builtin_elementwise_fma(vec_t<T, V>(m.val[e]), xj[p][e], acc);
             if constexpr (Z) {
                 // column c0 - 1: lane sub - 1 of this pass, or the last lane of the
                 // previous pass (of the last pass for column k - 1); column c0 + V:
@@ -97,7 +151,8 @@ __global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__res
                 nb.rightV = sub < lpr - 1 ? r_same : r_next;
 #pragma unroll
                 for (int q = 0; q < V; ++q)
-                    acc[q] += m.w * (left_of<T, V>(xo[p], nb, q) + right_of<T, V>(xo[p], nb, q, c0 + q, a.k));
+                    acc[q] = __builtin_elementwise_fma(m.w, left_of<T, V>(xo[p], nb, q) + right_of<T, V>(xo[p], nb, q, c0 + q, a.k),
+                                           acc[q]);
             }
             if (cs) {
 #pragma unroll
@@ -375,6 +430,14 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
             const bool st = can_stage && t.stage_lds;
             const int span = t.lanes_per_row * v;
             const int passes = op->k % span == 0 ? op->k / span : 0;
+            if (a.A.cart && !st && span == op->k && t.lanes_per_row >= 8) {
+                if (t.nt_store)
+                    hipLaunchKernelGGL((k_lap_cart<T, v, z, true>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+                else
+                    hipLaunchKernelGGL((k_lap_cart<T, v, z, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y,
+                                       cs);
+                return;
+            }
             if constexpr (wt > 0) {
                 if (!st && (passes == 2 || passes == 4) && t.block <= 512) {  // its launch bound
                     auto go = [&](auto Pt) {
