@@ -61,7 +61,7 @@ def lap_kernel_name(tile, k):
     span = vec * lpr
     passes = k // span if k % span == 0 else 0
     if span == k and lpr >= 8 and not stage:  # the channel base is a Cartesian 5-point grid
-        return f"k_lap_cart<double,{vec},true,{bool(nt)}>"
+        return f"k_lap_cart<double,{vec},true,{bool(nt)},True>"  # 32-bit offsets below 4 GiB
     if passes in (2, 4) and not stage and block <= 512:
         return f"k_lap_passes<double,{vec},true,4,{bool(nt)},{passes}>"
     return f"k_lap<double,{vec},true,4,{bool(stage)},{bool(nt)}>"

@@ -63,28 +63,48 @@ __global__ __launch_bounds__(1024) void k_lap(RowArgs<T> a, const T *__restrict_
 // an operator (an absent neighbour has coefficient 0 and points at the row
 // itself), with the multiply-adds of lap_row_meta: the result is bitwise that
 // of k_lap.
-template <typename T, int V, bool Z, bool NT>
-__global__ __launch_bounds__(1024) void k_lap_cart(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+// Arguments of k_lap_cart: the grid and the operator's record, nothing else.
+template <typename T>
+struct CartArgs {
+    const T *rec;            // [n_b][8]: diag, w, S, W, E, N, 0, 0
+    uint32_t nx, ny, n_b, ld;
+    uint32_t rows_per_tile, n_tiles;
+    int px, py, lpr, remap;
+};
+
+// O32: the multivectors are below 4 GiB, so every address is a uniform base
+// plus a 32-bit byte offset.  Tiles of rows_per_tile rows, a grid-stride loop
+// over them (one tile per workgroup without a grid cap).
+template <typename T, int V, bool Z, bool NT, bool O32>
+__global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                    const double *__restrict__ cs) {
     using vt = vec_t<T, V>;
     const int lpr = a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
-    const int grp = threadIdx.x / lpr;
-    const int c0 = sub * V;
-    const uint32_t nx = uint32_t(a.A.cart_nx), ny = uint32_t(a.A.cart_ny);  // n_b < 2^30
-    const int64_t t0 = logical_block(a.remap) * a.tiles_per_block;
-    for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
-        const int64_t row = t * a.rows_per_tile + grp;
-        if (row >= a.n_rows) break;  // uniform over the row group
-        const T mine = a.A.cart[row * 8 + (sub & 7)];
-        const uint32_t r = uint32_t(row), j = r / nx, i = r - j * nx;  // 32-bit: no 64-bit division
-        const uint32_t cS = j > 0 ? r - nx : (a.A.cart_py ? r + nx * (ny - 1) : r);
-        const uint32_t cW = i > 0 ? r - 1 : (a.A.cart_px ? r + nx - 1 : r);
-        const uint32_t cE = i < nx - 1 ? r + 1 : (a.A.cart_px ? r - (nx - 1) : r);
-        const uint32_t cN = j < ny - 1 ? r + nx : (a.A.cart_py ? r - nx * (ny - 1) : r);
-        const vt xo = ldv<T, V>(X + row * a.ld + c0);
-        const vt xS = ldv<T, V>(X + int64_t(cS) * a.ld + c0), xW = ldv<T, V>(X + int64_t(cW) * a.ld + c0);
-        const vt xE = ldv<T, V>(X + int64_t(cE) * a.ld + c0), xN = ldv<T, V>(X + int64_t(cN) * a.ld + c0);
+    const uint32_t grp = threadIdx.x / lpr;
+    const uint32_t c0 = uint32_t(sub) * V;
+    const uint32_t nx = a.nx, ny = a.ny;
+    auto at = [&](const T *base, uint32_t rr) -> const T * {
+        if constexpr (O32)
+            return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                               (rr * a.ld + c0) * uint32_t(sizeof(T)));
+        else
+            return base + int64_t(rr) * a.ld + c0;
+    };
+    for (uint32_t t = uint32_t(logical_block(a.remap)); t < a.n_tiles; t += gridDim.x) {
+        const uint32_t r = t * a.rows_per_tile + grp;
+        if (r >= a.n_b) break;  // uniform over the row group
+        const uint32_t j = r / nx, i = r - j * nx;
+        const uint32_t cS = j > 0 ? r - nx : (a.py ? r + nx * (ny - 1) : r);
+        const uint32_t cW = i > 0 ? r - 1 : (a.px ? r + nx - 1 : r);
+        const uint32_t cE = i < nx - 1 ? r + 1 : (a.px ? r - (nx - 1) : r);
+        const uint32_t cN = j < ny - 1 ? r + nx : (a.py ? r - nx * (ny - 1) : r);
+        const vt xo = ldv<T, V>(at(X, r));
+        const vt xS = ldv<T, V>(at(X, cS)), xW = ldv<T, V>(at(X, cW));
+        const vt xE = ldv<T, V>(at(X, cE)), xN = ldv<T, V>(at(X, cN));
+        const T mine = a.rec[r * 8u + uint32_t(sub & 7)];
+        // all six loads are in flight before the first shuffle waits on one
+        __builtin_amdgcn_sched_barrier(0);
         const T d = __shfl(mine, 0, lpr), w = __shfl(mine, 1, lpr);
         const T vS = __shfl(mine, 2, lpr), vW = __shfl(mine, 3, lpr), vE = __shfl(mine, 4, lpr), vN = __shfl(mine, 5, lpr);
         vt acc = d * xo;
@@ -93,17 +113,27 @@ __global__ __launch_bounds__(1024) void k_lap_cart(RowArgs<T> a, const T *__rest
         acc = __builtin_elementwise_fma(vt(vE), xE, acc);
         acc = __builtin_elementwise_fma(vt(vN), xN, acc);
         if constexpr (Z) {
-            const auto nb = plane_neighbours<T, V>(xo, sub, lpr, a.k);
+            // the group covers the k columns exactly: column c0 - 1 is the
+            // previous lane's last value (lane lpr - 1 holds column k - 1), and
+            // column c0 + V the next lane's first (lane 0 holds column 0)
+            const T left0 = __shfl(xo[V - 1], (sub + lpr - 1) & (lpr - 1), lpr);
+            const T rightV = __shfl(xo[0], (sub + 1) & (lpr - 1), lpr);
 #pragma unroll
-            for (int q = 0; q < V; ++q)
-                acc[q] = __builtin_elementwise_fma(w, left_of<T, V>(xo, nb, q) + right_of<T, V>(xo, nb, q, c0 + q, a.k),
-                                                   acc[q]);
+            for (int q = 0; q < V; ++q) {
+                const T lq = q > 0 ? xo[q > 0 ? q - 1 : 0] : left0;
+                const T rq = q + 1 < V ? xo[q + 1 < V ? q + 1 : 0] : rightV;
+                acc[q] = __builtin_elementwise_fma(w, lq + rq, acc[q]);
+            }
         }
         if (cs) {
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] *= T(cs[c0 + q]);
         }
-        stv_masked<T, V, NT>(Y + row * a.ld + c0, acc, a.k - c0);
+        vt *out = const_cast<vt *>(reinterpret_cast<const vt *>(at(Y, r)));
+        if constexpr (NT)
+            __builtin_nontemporal_store(acc, out);
+        else
+            *out = acc;
     }
 }
 
@@ -431,11 +461,31 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
             const int span = t.lanes_per_row * v;
             const int passes = op->k % span == 0 ? op->k / span : 0;
             if (a.A.cart && !st && span == op->k && t.lanes_per_row >= 8) {
-                if (t.nt_store)
-                    hipLaunchKernelGGL((k_lap_cart<T, v, z, true>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y, cs);
+                const bool o32 = uint64_t(op->n_b) * uint64_t(op->ld) * sizeof(T) < (uint64_t(1) << 32);
+                CartArgs<T> ca;
+                ca.rec = a.A.cart;
+                ca.nx = uint32_t(a.A.cart_nx);
+                ca.ny = uint32_t(a.A.cart_ny);
+                ca.n_b = uint32_t(op->n_b);
+                ca.ld = uint32_t(op->ld);
+                ca.rows_per_tile = uint32_t(g.rows_per_tile);
+                ca.n_tiles = uint32_t(ceil_div(op->n_b, g.rows_per_tile));
+                ca.px = a.A.cart_px;
+                ca.py = a.A.cart_py;
+                ca.lpr = t.lanes_per_row;
+                ca.remap = t.xcd_remap;
+                auto go = [&](auto NTt, auto Ot) {
+                    hipLaunchKernelGGL((k_lap_cart<T, v, z, decltype(NTt)::value, decltype(Ot)::value>),
+                                       dim3(g.n_blocks), dim3(t.block), 0, s, ca, X, Y, cs);
+                };
+                if (t.nt_store && o32)
+                    go(std::true_type{}, std::true_type{});
+                else if (t.nt_store)
+                    go(std::true_type{}, std::false_type{});
+                else if (o32)
+                    go(std::false_type{}, std::true_type{});
                 else
-                    hipLaunchKernelGGL((k_lap_cart<T, v, z, false>), dim3(g.n_blocks), dim3(t.block), 0, s, a, X, Y,
-                                       cs);
+                    go(std::false_type{}, std::false_type{});
                 return;
             }
             if constexpr (wt > 0) {
