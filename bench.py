@@ -139,6 +139,37 @@ def tune(op, fvx, dtype=None):
     return tile
 
 
+def refine_tile(op, fvx, torch, X, Y):
+    """The autotuner times its candidates on scratch buffers of its own; for
+    the headline operator its pick is refined under the headline's cold
+    sweep: the tuner's tile and its neighbours (XCD remap on and off,
+    workgroups of 64 to 512 threads, the same row mapping) are timed with
+    lap_sweep on the rotating buffers and the fastest is kept and written to
+    the tile cache, so the profiling and counter runs use the same tile
+    (outside every timed region)."""
+    path = os.environ.get("FVX_TUNE_CACHE")
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            entry = json.load(fh).get(op._tile_key(fvx.F64), {})
+        if entry.get("source") == "refined":  # refined by an earlier run: keep it (profiling runs)
+            op.set_tile(*entry["tile"])
+            return tuple(entry["tile"])
+    base = tuple(op.get_tile())
+    vec, lpr, _, _, _, stage, nt = base
+    cands = {base} | {(vec, lpr, b, rm, 0, stage, nt) for b in (64, 128, 256, 512) for rm in (0, 1) if b >= lpr}
+    best, bt = base, None
+    for t in sorted(cands):
+        op.set_tile(*t)
+        lap_sweep(op, X[:2], Y[:2], torch)
+        tt = min(lap_sweep(op, X, Y, torch) for _ in range(2))
+        if bt is None or tt < bt:
+            best, bt = t, tt
+    op.set_tile(*best)
+    op.remember_tile(best, os.environ.get("FVX_TUNE_CACHE"))
+    log(f"tile k={op.k} f64 refined on the cold sweep: {best} ({bt * 1e3:.2f} us; tuner's {base})")
+    return best
+
+
 def tune_cg(op, fvx, dtype=None):
     """Autotuned CG tile for this operator (outside every timed region)."""
     dt = fvx.F64 if dtype is None else dtype
@@ -352,6 +383,7 @@ def main():
     W0 = op.to_rows(u[op.F_b * k:])
     U, W = torch.empty_like(U0), torch.empty_like(W0)
     X, Y = rotating_sets(op, fvx, torch, op.to_rows(inputs.uniform(0, 0, N)))
+    tile = refine_tile(op, fvx, torch, X, Y)
     D = op.empty()
     PHI = op.zeros()
     op.workspace(op.solve_opts(rtol=rtol))

@@ -314,15 +314,36 @@ class Operator:
         check(lib().fvx_lap_many(self._h, dt, n, xa, ya, _stream(stream)), "fvx_lap_many")
         return Ys
 
+    def _tile_key(self, dtype):
+        torch = _torch()
+        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
+        return (f"{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}|nnz_b={self.nnz_b}"
+                f"|stencil={self.stencil}")
+
+    def remember_tile(self, tile, cache_path, dtype=F64, note="refined"):
+        """Stores a tile chosen outside the autotuner in the tile cache."""
+        import json
+        import os
+        if not cache_path:
+            return
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        entry = cache.get(self._tile_key(dtype), {})
+        entry.update({"tile": list(tile), "source": note})
+        cache[self._tile_key(dtype)] = entry
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+
     def tune_cached(self, dtype=F64, cache_path=None, scratch_bytes=int(1.1 * 2 ** 30), reps=2):
         """Autotuned tile, cached in a JSON file keyed by (device architecture,
         precision, k, ld, base rows, base nonzeros, stencil).  Returns (tile, source)."""
         import json
         import os
-        torch = _torch()
-        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
-        key = (f"{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}|nnz_b={self.nnz_b}"
-               f"|stencil={self.stencil}")
+        key = self._tile_key(dtype)
         cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as fh:
