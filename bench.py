@@ -55,12 +55,26 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def lap_kernel_name(tile, k):
+def cart_lines(nx, ny, rows_per_tile, cap):
+    """Grid lines per row group of the Cartesian lap kernel under a
+    workgroup cap (the library's rule)."""
+    if cap <= 0 or -(-(nx * ny) // rows_per_tile) <= cap:
+        return 1
+    r = 2 if -(-nx // rows_per_tile) * -(-ny // 2) <= cap else 4
+    while r > ny:
+        r //= 2
+    return r
+
+
+def lap_kernel_name(tile, k, base=BASE):
     """The lap SpMM kernel a tile selects (vec, lanes, block, remap, cap, stage, nt)."""
-    vec, lpr, block, _, _, stage, nt = tile
+    vec, lpr, block, _, cap, stage, nt = tile
     span = vec * lpr
     passes = k // span if k % span == 0 else 0
     if span == k and lpr >= 8 and not stage:  # the channel base is a Cartesian 5-point grid
+        lines = cart_lines(base[0], base[1], block // lpr, cap)
+        if lines > 1:
+            return f"k_lap_cart_lines<double,{vec},true,{bool(nt)},True,{lines}>"
         return f"k_lap_cart<double,{vec},true,{bool(nt)},True>"  # 32-bit offsets below 4 GiB
     if passes in (2, 4) and not stage and block <= 512:
         return f"k_lap_passes<double,{vec},true,4,{bool(nt)},{passes}>"
@@ -143,7 +157,8 @@ def refine_tile(op, fvx, torch, X, Y):
     """The autotuner times its candidates on scratch buffers of its own; for
     the headline operator its pick is refined under the headline's cold
     sweep: the tuner's tile and its neighbours (XCD remap on and off,
-    workgroups of 64 to 512 threads, the same row mapping) are timed with
+    workgroups of 64 to 512 threads, no cap or a cap of 1024 or 2048
+    workgroups, the same row mapping) are timed with
     lap_sweep on the rotating buffers and the fastest is kept and written to
     the tile cache, so the profiling and counter runs use the same tile
     (outside every timed region)."""
@@ -156,7 +171,8 @@ def refine_tile(op, fvx, torch, X, Y):
             return tuple(entry["tile"])
     base = tuple(op.get_tile())
     vec, lpr, _, _, _, stage, nt = base
-    cands = {base} | {(vec, lpr, b, rm, 0, stage, nt) for b in (64, 128, 256, 512) for rm in (0, 1) if b >= lpr}
+    cands = {base} | {(vec, lpr, b, rm, cap, stage, nt) for b in (64, 128, 256, 512) for rm in (0, 1)
+                      for cap in (0, 1024, 2048) if b >= lpr}
     best, bt = base, None
     for t in sorted(cands):
         op.set_tile(*t)

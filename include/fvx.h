@@ -158,7 +158,11 @@ typedef struct fvx_op_desc {
  * (power of two, 1..64); block = threads per workgroup (64..1024, multiple of
  * 64); xcd_remap = nonzero maps consecutive row tiles to the same XCD;
  * max_blocks = cap on workgroups (each then walks several consecutive row
- * tiles), 0 = one tile per workgroup; stage_lds = nonzero stages each tile's
+ * tiles), 0 = one tile per workgroup; on a Cartesian 5-point base whose
+ * k columns one row group covers (lanes_per_row * vec == k, lanes_per_row
+ * >= 8, no LDS staging) a cap below the tile count instead gives each row
+ * group 2 or 4 grid lines along y, the fewest that fit under the cap (at
+ * most ny), loaded together; stage_lds = nonzero stages each tile's
  * base-block rows (column indices, values, diagonal, coupling weight) in LDS
  * with coalesced loads, shared by all lanes of a row (needs at most 64 rows
  * per tile, i.e. block / lanes_per_row <= 64); nt_store = nonzero writes the

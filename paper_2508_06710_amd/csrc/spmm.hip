@@ -69,6 +69,7 @@ struct CartArgs {
     const T *rec;            // [n_b][8]: diag, w, S, W, E, N, 0, 0
     uint32_t nx, ny, n_b, ld;
     uint32_t rows_per_tile, n_tiles;
+    uint32_t n_xtiles;       // k_lap_cart_lines: tiles along x
     int px, py, lpr, remap;
 };
 
@@ -134,6 +135,102 @@ __global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__res
             __builtin_nontemporal_store(acc, out);
         else
             *out = acc;
+    }
+}
+
+// The same product with R grid lines along y per row group (R = 2 or 4, at
+// most ny): a tile is rows_per_tile cells along x times R lines, and the row
+// group of cell column i loads the R + 2 values x(i, j0 - 1 .. j0 + R) once,
+// so that each line's own value is also the north neighbour of the line below
+// and the south neighbour of the line above (R + 2 loads in place of 3R), and
+// a lane keeps about R times the bytes of k_lap_cart in flight.  Lines past
+// ny (a ragged last tile) load in-range values and store nothing.  Each
+// line's neighbour values and coefficients are those of k_lap_cart (a wall
+// neighbour is the cell itself, a periodic one wraps), combined in the same
+// order: the result is bitwise that of k_lap_cart.
+template <typename T, int V, bool Z, bool NT, bool O32, int R>
+__global__ __launch_bounds__(1024) void k_lap_cart_lines(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+                                                         const double *__restrict__ cs) {
+    using vt = vec_t<T, V>;
+    const int lpr = a.lpr;
+    const int sub = threadIdx.x & (lpr - 1);
+    const uint32_t grp = threadIdx.x / lpr;
+    const uint32_t c0 = uint32_t(sub) * V;
+    const uint32_t nx = a.nx;
+    const int ny = int(a.ny);
+    auto at = [&](const T *base, uint32_t rr) -> const T * {
+        if constexpr (O32)
+            return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                               (rr * a.ld + c0) * uint32_t(sizeof(T)));
+        else
+            return base + int64_t(rr) * a.ld + c0;
+    };
+    // line index -> stored line: wrap when periodic in y, else clamp (the
+    // wall neighbour of lines 0 and ny - 1 is the line itself); selects, no
+    // branches, so the loads below stay in one basic block
+    auto line = [&](int jj) -> uint32_t {
+        const int jw = jj + (jj < 0 ? ny : 0) - (jj >= ny ? ny : 0);
+        const int jc = min(max(jj, 0), ny - 1);
+        return uint32_t(a.py ? jw : jc);
+    };
+    for (uint32_t t = uint32_t(logical_block(a.remap)); t < a.n_tiles; t += gridDim.x) {
+        const uint32_t tj = t / a.n_xtiles, ti = t - tj * a.n_xtiles;
+        const uint32_t i = ti * a.rows_per_tile + grp;
+        if (i >= nx) continue;  // uniform over the row group
+        const int j0 = int(tj) * R;
+        const uint32_t iW = i > 0 ? i - 1 : (a.px ? nx - 1 : i);
+        const uint32_t iE = i < nx - 1 ? i + 1 : (a.px ? 0 : i);
+        vt col[R + 2], xW[R], xE[R];
+        T mine[R];
+#pragma unroll
+        for (int q = 0; q < R + 2; ++q) col[q] = ldv<T, V>(at(X, line(j0 - 1 + q) * nx + i));
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const uint32_t jr = (j0 + q < ny ? uint32_t(j0 + q) : uint32_t(ny - 1)) * nx;
+            xW[q] = ldv<T, V>(at(X, jr + iW));
+            xE[q] = ldv<T, V>(at(X, jr + iE));
+            mine[q] = a.rec[(jr + i) * 8u + uint32_t(sub & 7)];
+        }
+        // every load is in flight before the first shuffle waits on one; all
+        // R lines are computed (no branch between the loads and their uses)
+        // and only the lines inside the grid are stored
+        __builtin_amdgcn_sched_barrier(0);
+        vt acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T d = __shfl(mine[q], 0, lpr), w = __shfl(mine[q], 1, lpr);
+            const T vS = __shfl(mine[q], 2, lpr), vW = __shfl(mine[q], 3, lpr), vE = __shfl(mine[q], 4, lpr),
+                    vN = __shfl(mine[q], 5, lpr);
+            const vt xo = col[q + 1];
+            acc[q] = d * xo;
+            acc[q] = __builtin_elementwise_fma(vt(vS), col[q], acc[q]);
+            acc[q] = __builtin_elementwise_fma(vt(vW), xW[q], acc[q]);
+            acc[q] = __builtin_elementwise_fma(vt(vE), xE[q], acc[q]);
+            acc[q] = __builtin_elementwise_fma(vt(vN), col[q + 2], acc[q]);
+            if constexpr (Z) {
+                const T left0 = __shfl(xo[V - 1], (sub + lpr - 1) & (lpr - 1), lpr);
+                const T rightV = __shfl(xo[0], (sub + 1) & (lpr - 1), lpr);
+#pragma unroll
+                for (int p = 0; p < V; ++p) {
+                    const T lp = p > 0 ? xo[p > 0 ? p - 1 : 0] : left0;
+                    const T rp = p + 1 < V ? xo[p + 1 < V ? p + 1 : 0] : rightV;
+                    acc[q][p] = __builtin_elementwise_fma(w, lp + rp, acc[q][p]);
+                }
+            }
+            if (cs) {
+#pragma unroll
+                for (int p = 0; p < V; ++p) acc[q][p] *= T(cs[c0 + p]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (j0 + q >= ny) break;  // uniform over the workgroup
+            vt *out = const_cast<vt *>(reinterpret_cast<const vt *>(at(Y, uint32_t(j0 + q) * nx + i)));
+            if constexpr (NT)
+                __builtin_nontemporal_store(acc[q], out);
+            else
+                *out = acc[q];
+        }
     }
 }
 
@@ -442,6 +539,17 @@ void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hi
     FVX_HIP(hipGetLastError());
 }
 
+// Grid lines along y per row group of the Cartesian kernel: 1 without a
+// workgroup cap or when one line per tile fits under it, else the fewest of
+// 2 or 4 that does (4 if neither), at most ny.
+int cart_lines(int64_t n_b, int nx, int ny, int rows_per_tile, int max_blocks) {
+    if (max_blocks <= 0 || ceil_div(n_b, rows_per_tile) <= max_blocks) return 1;
+    const int64_t xt = ceil_div(nx, rows_per_tile);
+    int r = xt * ceil_div(ny, 2) <= max_blocks ? 2 : 4;
+    while (r > ny) r >>= 1;
+    return r;
+}
+
 template <typename T>
 void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_t s) {
     if (op->stencil != 7) {
@@ -470,13 +578,29 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
                 ca.ld = uint32_t(op->ld);
                 ca.rows_per_tile = uint32_t(g.rows_per_tile);
                 ca.n_tiles = uint32_t(ceil_div(op->n_b, g.rows_per_tile));
+                ca.n_xtiles = 0;
                 ca.px = a.A.cart_px;
                 ca.py = a.A.cart_py;
                 ca.lpr = t.lanes_per_row;
                 ca.remap = t.xcd_remap;
+                const int lines = cart_lines(op->n_b, a.A.cart_nx, a.A.cart_ny, g.rows_per_tile, t.max_blocks);
+                int n_blocks = g.n_blocks;
+                if (lines > 1) {
+                    ca.n_xtiles = uint32_t(ceil_div(a.A.cart_nx, g.rows_per_tile));
+                    ca.n_tiles = ca.n_xtiles * uint32_t(ceil_div(a.A.cart_ny, lines));
+                    n_blocks = int(std::min<int64_t>(ca.n_tiles, t.max_blocks));
+                }
                 auto go = [&](auto NTt, auto Ot) {
-                    hipLaunchKernelGGL((k_lap_cart<T, v, z, decltype(NTt)::value, decltype(Ot)::value>),
-                                       dim3(g.n_blocks), dim3(t.block), 0, s, ca, X, Y, cs);
+                    constexpr bool nt = decltype(NTt)::value, o = decltype(Ot)::value;
+                    if (lines == 4)
+                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 4>), dim3(n_blocks), dim3(t.block), 0, s,
+                                           ca, X, Y, cs);
+                    else if (lines == 2)
+                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 2>), dim3(n_blocks), dim3(t.block), 0, s,
+                                           ca, X, Y, cs);
+                    else
+                        hipLaunchKernelGGL((k_lap_cart<T, v, z, nt, o>), dim3(n_blocks), dim3(t.block), 0, s, ca, X, Y,
+                                           cs);
                 };
                 if (t.nt_store && o32)
                     go(std::true_type{}, std::true_type{});

@@ -37,7 +37,7 @@ std::vector<fvx_tile> shape_candidates(const fvx_op *op, int dtype) {
 // metadata, non-temporal stores) around the best row mapping.
 std::vector<fvx_tile> option_candidates(const fvx_op *op, const fvx_tile &b) {
     std::vector<fvx_tile> out;
-    for (int cap : {0, 2048})
+    for (int cap : {0, 1024, 2048})
         for (int remap : {1, 0})
             for (int stage : {0, 1}) {
                 if (stage && (b.block / b.lanes_per_row > kMaxStageRows || op->stencil != 7)) continue;

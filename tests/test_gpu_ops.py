@@ -111,6 +111,59 @@ def test_every_tile_gives_the_same_product(k):
         c.op.set_tile(2, 1, 256, 1, 0, 1, dtype=fvx.F64)  # 256 rows per tile do not fit the stage
 
 
+def _cart_lines(n_b, nx, ny, rows_per_tile, cap):
+    """Grid lines per row group the Cartesian kernel takes under a workgroup
+    cap (1 without one, else the fewest of 2 or 4 that fits, at most ny)."""
+    if cap <= 0 or -(-n_b // rows_per_tile) <= cap:
+        return 1
+    xt = -(-nx // rows_per_tile)
+    r = 2 if xt * -(-ny // 2) <= cap else 4
+    while r > ny:
+        r //= 2
+    return r
+
+
+CART_SPECS = {
+    "chan13x9": inputs.channel_base(13, 9),                                    # periodic x, walls y
+    "box7x11": inputs.convection_base(7, 11),                                  # walls on all sides
+    "torus11x7": inputs.CartSpec(11, 7, 1.0, 0.0, 1.0, 0.0, True, True),       # periodic x and y
+    "torus5x3": inputs.CartSpec(5, 3, 1.0, 0.0, 1.0, 0.0, True, True),         # ny = 3: wraps past the last line
+    "pery6x10": inputs.CartSpec(6, 10, 1.0, 0.0, 1.0, 1.2, False, True),       # walls x, periodic y
+}
+
+
+@pytest.mark.parametrize("spec", list(CART_SPECS))
+@pytest.mark.parametrize("k,coupling", [(16, 1), (64, 1), (16, 0)])
+def test_cartesian_line_tiles_give_the_same_product(spec, k, coupling):
+    """Workgroup caps on a Cartesian 5-point base give each row group 2 or 4
+    grid lines along y (ragged last tiles in x and y, walls and periodic
+    wraps): the product is the oracle's and bitwise that of the one-line
+    kernel and of the ELL kernel (LDS-staged tile)."""
+    c = Case(CART_SPECS[spec], k, coupling=coupling)
+    fvx = c.fvx
+    sp_ = CART_SPECS[spec]
+    cs = torch.tensor(inputs.uniform(11, 0, k, 0.5, 2.0), dtype=torch.float64, device="cuda")
+    for scale in ((None, cs) if coupling == 0 else (None,)):
+        c.op.set_tile(2, 8, 64, 1, 0, 1, 0, dtype=fvx.F64)   # ELL kernel, rows staged in LDS
+        y_ell, ref, A, x = _lap_check(c, seed=12, colscale=scale)
+        assert componentwise(y_ell, ref, A, x) <= TOL64
+        seen = set()
+        for vec, lpr in ((2, k // 2), (1, min(64, k))):
+            if lpr * vec != k:
+                continue
+            for block in (64, 128, 256):
+                if block < lpr:
+                    continue
+                for cap in (0, 1, 3, 12, 24, 40):
+                    for remap, nt in ((0, 1), (1, 0)):
+                        c.op.set_tile(vec, lpr, block, remap, cap, 0, nt, dtype=fvx.F64)
+                        y, _, _, _ = _lap_check(c, seed=12, colscale=scale)
+                        key = (vec, lpr, block, cap, remap, nt)
+                        assert np.array_equal(y, y_ell), key
+                        seen.add(_cart_lines(sp_.nx * sp_.ny, sp_.nx, sp_.ny, block // lpr, cap))
+        assert seen == ({1, 2} if sp_.ny < 4 else {1, 2, 4}), seen
+
+
 @pytest.mark.parametrize("k,dtype", [(16, 0), (5, 1), (64, 1)])
 def test_tuner_keeps_the_fastest_candidate(k, dtype):
     """The autotuner's two stages: every row mapping with default options,
