@@ -445,7 +445,8 @@ def main():
     sha = kernel_source_sha()
     cnt = load_counters(sha)
     traffic = None
-    if cnt:
+    norm = lambda n: n.replace(" ", "").lower()
+    if cnt and norm(cnt.get("kernel", "")) == norm(lap_kernel_name(tile, k)):  # counters of this very kernel
         traffic = cnt["fetch_bytes_per_launch"] + cnt["write_bytes_per_launch"]
     out = {
         "metric": "SpMM GB/s & % HBM roofline vs k×SpMV; Poisson time to rel. residual 1e-8",
