@@ -164,6 +164,28 @@ def test_cartesian_line_tiles_give_the_same_product(spec, k, coupling):
         assert seen == ({1, 2} if sp_.ny < 4 else {1, 2, 4}), seen
 
 
+@pytest.mark.parametrize("spec", ["chan13x9", "torus5x3", "pery6x10"])
+@pytest.mark.parametrize("k", [16, 64])
+def test_cartesian_line_tiles_fp32(spec, k):
+    """The FP32 product (the mixed solve's inner SpMM) on the same line
+    tiles: within the FP32 rounding bound of the oracle and bitwise that of
+    the FP32 ELL kernel."""
+    c = Case(CART_SPECS[spec], k)
+    fvx = c.fvx
+    c.op.set_tile(2, 8, 64, 1, 0, 1, 0, dtype=fvx.F32)   # ELL kernel, rows staged in LDS
+    y_ell, ref, A, x = _lap_check(c, seed=13, dtype=fvx.F32)
+    assert componentwise(y_ell, ref, A, x) <= float(np.max(fp32_bound_factor(A)))
+    for vec in (4, 2):
+        lpr = k // vec
+        if lpr < 8 or lpr > 64:
+            continue
+        for block in (64, 256):
+            for cap in (0, 1, 12, 40):
+                c.op.set_tile(vec, lpr, block, cap % 2, cap, 0, 1, dtype=fvx.F32)
+                y, _, _, _ = _lap_check(c, seed=13, dtype=fvx.F32)
+                assert np.array_equal(y, y_ell), (vec, lpr, block, cap)
+
+
 @pytest.mark.parametrize("k,dtype", [(16, 0), (5, 1), (64, 1)])
 def test_tuner_keeps_the_fastest_candidate(k, dtype):
     """The autotuner's two stages: every row mapping with default options,
