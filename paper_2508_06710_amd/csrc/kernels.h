@@ -173,6 +173,57 @@ __device__ __forceinline__ RowMeta<T, WT> meta_global(const OpDev<T> &A, int64_t
     return m;
 }
 
+// The same entries on a Cartesian 5-point base: the neighbours' indices from
+// (i, j) = (row mod nx, row div nx) (periodic axes wrap, an absent neighbour
+// is the row itself) and the coefficients from the row's record
+// [diag, w, S, W, E, N, 0, 0] (one 64-byte line in FP64, 32 bytes in FP32).
+// The builder writes such an operator's ELL rows in the same S, W, E, N order
+// with the same values, so both give the same RowMeta; this one issues 3 (FP64)
+// or 2 (FP32) vector loads from one line in place of 10 scattered ones, and the
+// gathers wait on no load.
+template <typename T, bool Z>
+__device__ __forceinline__ RowMeta<T, 4> meta_cart(const OpDev<T> &A, int64_t row) {
+    const uint32_t r = uint32_t(row), nx = uint32_t(A.cart_nx), ny = uint32_t(A.cart_ny);
+    const uint32_t j = r / nx, i = r - j * nx;
+    RowMeta<T, 4> m;
+    m.col[0] = int32_t(j > 0 ? r - nx : (A.cart_py ? r + nx * (ny - 1) : r));
+    m.col[1] = int32_t(i > 0 ? r - 1 : (A.cart_px ? r + nx - 1 : r));
+    m.col[2] = int32_t(i < nx - 1 ? r + 1 : (A.cart_px ? r - (nx - 1) : r));
+    m.col[3] = int32_t(j < ny - 1 ? r + nx : (A.cart_py ? r - nx * (ny - 1) : r));
+    const T *rec = A.cart + size_t(r) * 8;
+    if constexpr (sizeof(T) == 8) {
+        const vec_t<T, 2> a = *reinterpret_cast<const vec_t<T, 2> *>(rec);
+        const vec_t<T, 2> b = *reinterpret_cast<const vec_t<T, 2> *>(rec + 2);
+        const vec_t<T, 2> c = *reinterpret_cast<const vec_t<T, 2> *>(rec + 4);
+        m.diag = a[0];
+        m.w = Z ? a[1] : T(0);
+        m.val[0] = b[0];
+        m.val[1] = b[1];
+        m.val[2] = c[0];
+        m.val[3] = c[1];
+    } else {
+        const vec_t<T, 4> a = *reinterpret_cast<const vec_t<T, 4> *>(rec);
+        const vec_t<T, 4> b = *reinterpret_cast<const vec_t<T, 4> *>(rec + 4);
+        m.diag = a[0];
+        m.w = Z ? a[1] : T(0);
+        m.val[0] = a[2];
+        m.val[1] = a[3];
+        m.val[2] = b[0];
+        m.val[3] = b[1];
+    }
+    return m;
+}
+
+// A row's entries from the Cartesian record when the operator has one (a
+// uniform branch), else from the ELL arrays.
+template <typename T, int WT, bool Z>
+__device__ __forceinline__ RowMeta<T, WT> meta_of(const OpDev<T> &A, int64_t n_b, int64_t row) {
+    if constexpr (WT == 4) {
+        if (A.cart) return meta_cart<T, Z>(A, row);
+    }
+    return meta_global<T, WT, Z>(A, n_b, row);
+}
+
 // LDS stage of one tile's base-block rows: [rows][WT] columns, [rows][WT]
 // values, [rows] diagonal, [rows] coupling weight.
 __host__ __device__ constexpr size_t stage_col_bytes(int rows, int wt) {
@@ -299,7 +350,7 @@ __device__ __forceinline__ vec_t<T, V> lap_row_ld(const OpDev<T> &A, const Ld &i
                                                   int64_t row, int c0, int sub, int lpr, bool single,
                                                   vec_t<T, V> &xo) {
     if constexpr (WT > 0)
-        return lap_row_meta<T, V, Z, WT>(meta_global<T, WT, Z>(A, n_b, row), in, k, row, c0, sub, lpr, single, xo);
+        return lap_row_meta<T, V, Z, WT>(meta_of<T, WT, Z>(A, n_b, row), in, k, row, c0, sub, lpr, single, xo);
     else
         return lap_row_dyn<T, V, Z>(A, in, n_b, k, W, row, c0, sub, lpr, single, xo);
 }

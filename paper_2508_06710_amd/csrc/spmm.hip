@@ -250,7 +250,7 @@ __global__ __launch_bounds__(512) void k_lap_passes(RowArgs<T> a, const T *__res
     for (int64_t t = t0; t < t0 + a.tiles_per_block; ++t) {
         const int64_t row = t * a.rows_per_tile + grp;
         if (row >= a.n_rows) break;
-        const RowMeta<T, WT> m = meta_global<T, WT, Z>(a.A, a.n_b, row);
+        const RowMeta<T, WT> m = meta_of<T, WT, Z>(a.A, a.n_b, row);
         vec_t<T, V> xo[P], xj[P][WT];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
