@@ -212,14 +212,28 @@ def load_counters(sha):
 
 
 def counters_mode(fvx, inputs, torch):
-    """A short run for rocprofv3 --pmc: 8 cold lap launches, then 8 copies of
-    a known size (the calibration of FETCH_SIZE / WRITE_SIZE)."""
+    """A short run for rocprofv3 --pmc: 8 cold lap launches of the headline
+    tile, then 8 of each other kernel instance its row mapping can select
+    (the Cartesian kernel with 1, 2 or 4 grid lines per row group, chosen by
+    the workgroup cap), then 8 copies of a known size (the calibration of
+    FETCH_SIZE / WRITE_SIZE)."""
     spec, mesh, op = build_case(fvx, inputs, K_MAIN)
-    tune(op, fvx)
+    tile = tune(op, fvx)
     x = op.to_rows(inputs.uniform(0, 0, op.n_b * op.k))
     X, Y = rotating_sets(op, fvx, torch, x)
-    for i in range(8):
-        op.lap(X[i], Y[i])
+    seen = {lap_kernel_name(tile, op.k)}
+    tiles = [tile]
+    for cap in (0, 2048, 1024):
+        alt = tuple(tile[:4]) + (cap,) + tuple(tile[5:])
+        if lap_kernel_name(alt, op.k) not in seen:
+            seen.add(lap_kernel_name(alt, op.k))
+            tiles.append(alt)
+    for n, t in enumerate(tiles):
+        op.set_tile(*t)
+        for i in range(8):
+            op.lap(X[8 * n + i], Y[8 * n + i])
+        log(f"counters: 8 launches of {lap_kernel_name(t, op.k)} (tile {t})")
+    op.set_tile(*tile)
     nbytes = 256 * 2 ** 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = [torch.empty_like(src) for _ in range(2)]
@@ -446,8 +460,11 @@ def main():
     cnt = load_counters(sha)
     traffic = None
     norm = lambda n: n.replace(" ", "").lower()
-    if cnt and norm(cnt.get("kernel", "")) == norm(lap_kernel_name(tile, k)):  # counters of this very kernel
-        traffic = cnt["fetch_bytes_per_launch"] + cnt["write_bytes_per_launch"]
+    if cnt:  # counters of this very kernel instance
+        entries = [cnt] + list(cnt.get("by_kernel", {}).values())
+        hit = [e for e in entries if norm(e.get("kernel", "")) == norm(lap_kernel_name(tile, k))]
+        if hit:
+            traffic = hit[0]["fetch_bytes_per_launch"] + hit[0]["write_bytes_per_launch"]
     out = {
         "metric": "SpMM GB/s & % HBM roofline vs k×SpMV; Poisson time to rel. residual 1e-8",
         "value": achieved,
