@@ -76,11 +76,11 @@ struct CartArgs {
 // O32: the multivectors are below 4 GiB, so every address is a uniform base
 // plus a 32-bit byte offset.  Tiles of rows_per_tile rows, a grid-stride loop
 // over them (one tile per workgroup without a grid cap).
-template <typename T, int V, bool Z, bool NT, bool O32>
+template <typename T, int V, bool Z, bool NT, bool O32, int LPR, bool CS>
 __global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                    const double *__restrict__ cs) {
     using vt = vec_t<T, V>;
-    const int lpr = a.lpr;
+    const int lpr = LPR ? LPR : a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
     const uint32_t grp = threadIdx.x / lpr;
     const uint32_t c0 = uint32_t(sub) * V;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__res
                 acc[q] = __builtin_elementwise_fma(w, lq + rq, acc[q]);
             }
         }
-        if (cs) {
+        if constexpr (CS) {
 #pragma unroll
             for (int q = 0; q < V; ++q) acc[q] *= T(cs[c0 + q]);
         }
@@ -148,11 +148,11 @@ __global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__res
 // line's neighbour values and coefficients are those of k_lap_cart (a wall
 // neighbour is the cell itself, a periodic one wraps), combined in the same
 // order: the result is bitwise that of k_lap_cart.
-template <typename T, int V, bool Z, bool NT, bool O32, int R>
+template <typename T, int V, bool Z, bool NT, bool O32, int R, int LPR, bool CS>
 __global__ __launch_bounds__(1024) void k_lap_cart_lines(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                          const double *__restrict__ cs) {
     using vt = vec_t<T, V>;
-    const int lpr = a.lpr;
+    const int lpr = LPR ? LPR : a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
     const uint32_t grp = threadIdx.x / lpr;
     const uint32_t c0 = uint32_t(sub) * V;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_lap_cart_lines(CartArgs<T> a, const T 
                     acc[q][p] = __builtin_elementwise_fma(w, lp + rp, acc[q][p]);
                 }
             }
-            if (cs) {
+            if constexpr (CS) {
 #pragma unroll
                 for (int p = 0; p < V; ++p) acc[q][p] *= T(cs[c0 + p]);
             }
@@ -590,17 +590,28 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
                     ca.n_tiles = ca.n_xtiles * uint32_t(ceil_div(a.A.cart_ny, lines));
                     n_blocks = int(std::min<int64_t>(ca.n_tiles, t.max_blocks));
                 }
-                auto go = [&](auto NTt, auto Ot) {
-                    constexpr bool nt = decltype(NTt)::value, o = decltype(Ot)::value;
+                // the row-group width as a constant for 32 lanes (k = 64 in FP64, the
+                // common case), and the column scale as a flag
+                auto launch = [&](auto NTt, auto Ot, auto Lt, auto Ct) {
+                    constexpr bool nt = decltype(NTt)::value, o = decltype(Ot)::value, c = decltype(Ct)::value;
+                    constexpr int L = decltype(Lt)::value;
                     if (lines == 4)
-                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 4>), dim3(n_blocks), dim3(t.block), 0, s,
-                                           ca, X, Y, cs);
+                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 4, L, c>), dim3(n_blocks), dim3(t.block),
+                                           0, s, ca, X, Y, cs);
                     else if (lines == 2)
-                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 2>), dim3(n_blocks), dim3(t.block), 0, s,
-                                           ca, X, Y, cs);
+                        hipLaunchKernelGGL((k_lap_cart_lines<T, v, z, nt, o, 2, L, c>), dim3(n_blocks), dim3(t.block),
+                                           0, s, ca, X, Y, cs);
                     else
-                        hipLaunchKernelGGL((k_lap_cart<T, v, z, nt, o>), dim3(n_blocks), dim3(t.block), 0, s, ca, X, Y,
-                                           cs);
+                        hipLaunchKernelGGL((k_lap_cart<T, v, z, nt, o, L, c>), dim3(n_blocks), dim3(t.block), 0, s, ca,
+                                           X, Y, cs);
+                };
+                auto go = [&](auto NTt, auto Ot) {
+                    if (cs)
+                        launch(NTt, Ot, std::integral_constant<int, 0>{}, std::true_type{});
+                    else if (t.lanes_per_row == 32)
+                        launch(NTt, Ot, std::integral_constant<int, 32>{}, std::false_type{});
+                    else
+                        launch(NTt, Ot, std::integral_constant<int, 0>{}, std::false_type{});
                 };
                 if (t.nt_store && o32)
                     go(std::true_type{}, std::true_type{});

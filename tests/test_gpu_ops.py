@@ -143,7 +143,7 @@ def test_cartesian_line_tiles_give_the_same_product(spec, k, coupling):
     fvx = c.fvx
     sp_ = CART_SPECS[spec]
     cs = torch.tensor(inputs.uniform(11, 0, k, 0.5, 2.0), dtype=torch.float64, device="cuda")
-    for scale in ((None, cs) if coupling == 0 else (None,)):
+    for scale in (None, cs):  # the column scale applies to coupled planes as well
         c.op.set_tile(2, 8, 64, 1, 0, 1, 0, dtype=fvx.F64)   # ELL kernel, rows staged in LDS
         y_ell, ref, A, x = _lap_check(c, seed=12, colscale=scale)
         assert componentwise(y_ell, ref, A, x) <= TOL64
