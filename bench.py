@@ -73,7 +73,7 @@ def lap_kernel_name(tile, k, base=BASE):
     passes = k // span if k % span == 0 else 0
     if span == k and lpr >= 8 and not stage:  # the channel base is a Cartesian 5-point grid
         lines = cart_lines(base[0], base[1], block // lpr, cap)
-        width = 32 if lpr == 32 else 0  # the row-group width is a constant for 32 lanes; no column scale
+        width = lpr  # the row-group width is a template constant; no column scale
         if lines > 1:
             return f"k_lap_cart_lines<double,{vec},true,{bool(nt)},True,{lines},{width},False>"
         return f"k_lap_cart<double,{vec},true,{bool(nt)},True,{width},False>"  # 32-bit offsets below 4 GiB

@@ -80,7 +80,7 @@ template <typename T, int V, bool Z, bool NT, bool O32, int LPR, bool CS>
 __global__ __launch_bounds__(1024) void k_lap_cart(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                    const double *__restrict__ cs) {
     using vt = vec_t<T, V>;
-    const int lpr = LPR ? LPR : a.lpr;
+    constexpr int lpr = LPR;  // the row-group width, a compile-time constant
     const int sub = threadIdx.x & (lpr - 1);
     const uint32_t grp = threadIdx.x / lpr;
     const uint32_t c0 = uint32_t(sub) * V;
@@ -152,7 +152,7 @@ template <typename T, int V, bool Z, bool NT, bool O32, int R, int LPR, bool CS>
 __global__ __launch_bounds__(1024) void k_lap_cart_lines(CartArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                          const double *__restrict__ cs) {
     using vt = vec_t<T, V>;
-    const int lpr = LPR ? LPR : a.lpr;
+    constexpr int lpr = LPR;  // the row-group width, a compile-time constant
     const int sub = threadIdx.x & (lpr - 1);
     const uint32_t grp = threadIdx.x / lpr;
     const uint32_t c0 = uint32_t(sub) * V;
@@ -590,8 +590,8 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
                     ca.n_tiles = ca.n_xtiles * uint32_t(ceil_div(a.A.cart_ny, lines));
                     n_blocks = int(std::min<int64_t>(ca.n_tiles, t.max_blocks));
                 }
-                // the row-group width as a constant for 32 lanes (k = 64 in FP64, the
-                // common case), and the column scale as a flag
+                // the row-group width (8, 16, 32 or 64 lanes here) as a constant, so
+                // that the shuffles' source lanes fold, and the column scale as a flag
                 auto launch = [&](auto NTt, auto Ot, auto Lt, auto Ct) {
                     constexpr bool nt = decltype(NTt)::value, o = decltype(Ot)::value, c = decltype(Ct)::value;
                     constexpr int L = decltype(Lt)::value;
@@ -605,13 +605,19 @@ void launch_lap(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_
                         hipLaunchKernelGGL((k_lap_cart<T, v, z, nt, o, L, c>), dim3(n_blocks), dim3(t.block), 0, s, ca,
                                            X, Y, cs);
                 };
-                auto go = [&](auto NTt, auto Ot) {
+                auto with_scale = [&](auto NTt, auto Ot, auto Lt) {
                     if (cs)
-                        launch(NTt, Ot, std::integral_constant<int, 0>{}, std::true_type{});
-                    else if (t.lanes_per_row == 32)
-                        launch(NTt, Ot, std::integral_constant<int, 32>{}, std::false_type{});
+                        launch(NTt, Ot, Lt, std::true_type{});
                     else
-                        launch(NTt, Ot, std::integral_constant<int, 0>{}, std::false_type{});
+                        launch(NTt, Ot, Lt, std::false_type{});
+                };
+                auto go = [&](auto NTt, auto Ot) {
+                    switch (t.lanes_per_row) {
+                        case 8: with_scale(NTt, Ot, std::integral_constant<int, 8>{}); break;
+                        case 16: with_scale(NTt, Ot, std::integral_constant<int, 16>{}); break;
+                        case 32: with_scale(NTt, Ot, std::integral_constant<int, 32>{}); break;
+                        default: with_scale(NTt, Ot, std::integral_constant<int, 64>{}); break;
+                    }
                 };
                 if (t.nt_store && o32)
                     go(std::true_type{}, std::true_type{});
