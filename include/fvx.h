@@ -206,7 +206,9 @@ int fvx_op_set_tile(fvx_op *op, int dtype, const fvx_tile *tile);
  * candidate tiles and sets the fastest on the op, in two stages: every row
  * mapping (vector width, lanes per row, workgroup size) with default launch
  * options, then every launch option (XCD remap, workgroup cap, LDS staging,
- * non-temporal stores) around the best mapping.  Each candidate is timed with
+ * non-temporal stores) around the best mapping; on a Cartesian base whose k
+ * columns one row group covers, also the caps of 1024 and 2048 (grid lines per
+ * row group) at the other workgroup sizes.  Each candidate is timed with
  * HIP events over `reps` sweeps of up to 512 launches on rotating pairs.
  * scratch: device buffer for input/output pairs, at least
  * 2 * n_b * ld * sizeof(element) bytes; the more pairs fit, the colder the

@@ -46,6 +46,17 @@ std::vector<fvx_tile> option_candidates(const fvx_op *op, const fvx_tile &b) {
                     out.push_back(fvx_tile{b.vec, b.lanes_per_row, b.block, remap, cap, stage, nt});
                 }
             }
+    // A Cartesian base whose k columns one row group covers: the cap sets the
+    // grid lines per row group, whose best workgroup differs from the
+    // one-line kernel's (few workgroups of 64 threads leave a capped grid
+    // unbalanced), so the caps are also timed at the other workgroup sizes.
+    if (op->d64.cart && b.lanes_per_row * b.vec == op->k && b.lanes_per_row >= 8)
+        for (int block : {128, 256, 512}) {
+            if (block == b.block || block < b.lanes_per_row) continue;
+            for (int cap : {1024, 2048})
+                for (int remap : {1, 0})
+                    for (int nt : {0, 1}) out.push_back(fvx_tile{b.vec, b.lanes_per_row, block, remap, cap, 0, nt});
+        }
     return out;
 }
 

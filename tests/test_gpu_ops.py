@@ -198,7 +198,9 @@ def test_tuner_keeps_the_fastest_candidate(k, dtype):
     assert len(set(tiles)) == len(tiles)
     stage1 = [t for t in tiles if t[3:] == (1, 0, 0, 0)]
     first = min(((us, t) for t, us in res if t in stage1))[1]
-    assert all(t[:3] == first[:3] for t in tiles[len(stage1):])
+    for t in tiles[len(stage1):]:  # options around the stage-1 row mapping; on a Cartesian base also
+        assert t[:2] == first[:2]    # the line caps at the other workgroup sizes
+        assert t[2] == first[2] or (t[4] in (1024, 2048) and t[5] == 0), t
     assert c.op.get_tile(dtype) == min(res, key=lambda r: r[1])[0]
     y, ref, A, x = _lap_check(c, seed=7, dtype=dtype)
     tol = TOL64 if dtype == fvx.F64 else float(np.max(fp32_bound_factor(A)))
