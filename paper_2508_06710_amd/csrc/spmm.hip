@@ -316,10 +316,10 @@ __global__ __launch_bounds__(1024) void k_lap_stencil(RowArgs<T> a, const T *__r
 // every lane holds its V columns of all P passes of the row and of its 8
 // neighbours, so the plane shifts rotate across the lanes of the group and,
 // at the group's edge, into the next or previous pass.
-template <typename T, int V, bool E1, bool S2, bool NT, int P>
+template <typename T, int V, bool E1, bool S2, bool NT, int P, int LPR>
 __global__ __launch_bounds__(512) void k_lap_stencil_passes(RowArgs<T> a, const T *__restrict__ X,
                                                             T *__restrict__ Y) {
-    const int lpr = a.lpr;
+    const int lpr = LPR ? LPR : a.lpr;  // LPR: the row-group width as a constant (0: from the arguments)
     const int sub = threadIdx.x & (lpr - 1);
     const int grp = threadIdx.x / lpr;
     const int span = lpr * V;
@@ -516,12 +516,33 @@ void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hi
             constexpr bool e1 = decltype(E1t)::value, s2 = decltype(S2t)::value;
             auto launch = [&](auto NTt) {
                 constexpr bool nt = decltype(NTt)::value;
+                // the row-group width as a constant for the common widths, so that the
+                // ring shifts' source lanes fold
+                auto passes_kernel = [&](auto Pt) {
+                    constexpr int P = decltype(Pt)::value;
+                    switch (t.lanes_per_row) {
+                        case 4:
+                            hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, P, 4>), dim3(g.n_blocks),
+                                               dim3(t.block), 0, s, a, X, Y);
+                            break;
+                        case 8:
+                            hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, P, 8>), dim3(g.n_blocks),
+                                               dim3(t.block), 0, s, a, X, Y);
+                            break;
+                        case 16:
+                            hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, P, 16>), dim3(g.n_blocks),
+                                               dim3(t.block), 0, s, a, X, Y);
+                            break;
+                        default:
+                            hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, P, 0>), dim3(g.n_blocks),
+                                               dim3(t.block), 0, s, a, X, Y);
+                            break;
+                    }
+                };
                 if (passes == 4)
-                    hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, 4>), dim3(g.n_blocks), dim3(t.block), 0,
-                                       s, a, X, Y);
+                    passes_kernel(std::integral_constant<int, 4>{});
                 else if (passes == 2)
-                    hipLaunchKernelGGL((k_lap_stencil_passes<T, v, e1, s2, nt, 2>), dim3(g.n_blocks), dim3(t.block), 0,
-                                       s, a, X, Y);
+                    passes_kernel(std::integral_constant<int, 2>{});
                 else if (t.lanes_per_row == 64)
                     hipLaunchKernelGGL((k_lap_stencil<T, v, e1, s2, nt, true>), dim3(g.n_blocks), dim3(t.block), 0, s,
                                        a, X, Y);
