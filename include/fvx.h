@@ -672,6 +672,11 @@ int fvx_ns_step(const fvx_op *op, const fvx_op *visc, double *const U[3], double
  * the achievable-bandwidth reference of the roofline. */
 int fvx_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* n copies dst[i] <- src[i] of `bytes` each (same rules as fvx_copy),
+ * launched back to back from the library: a bandwidth sweep whose launch
+ * rate is not limited by the caller's language. */
+int fvx_copy_many(int n, void *const *dst, const void *const *src, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

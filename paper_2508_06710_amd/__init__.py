@@ -789,3 +789,12 @@ def copy(dst, src, nbytes=None, stream=None):
     """Device streaming copy (the bandwidth reference kernel)."""
     n = dst.numel() * dst.element_size() if nbytes is None else nbytes
     check(lib().fvx_copy(_ptr(dst), _ptr(src), n, _stream(stream)), "fvx_copy")
+
+
+def copy_many(dsts, srcs, nbytes=None, stream=None):
+    """dsts[i] <- srcs[i] for every pair, launched back to back from C."""
+    n = len(dsts)
+    nb = dsts[0].numel() * dsts[0].element_size() if nbytes is None else nbytes
+    da = (C.c_void_p * n)(*[d.data_ptr() for d in dsts])
+    sa = (C.c_void_p * n)(*[t.data_ptr() for t in srcs])
+    check(lib().fvx_copy_many(n, da, sa, nb, _stream(stream)), "fvx_copy_many")

@@ -115,6 +115,7 @@ SIGNATURES = {
     "fvx_csr_poisson_solve": (C.c_int, [_i64, _i64, _vp, _vp, _vp, _vp, _vp, C.c_int, _P(SolveOpts), _vp,
                                         C.c_size_t, _P(SolveStats), _vp]),
     "fvx_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "fvx_copy_many": (C.c_int, [C.c_int, _P(_vp), _P(_vp), C.c_size_t, _vp]),
     "fvx_sparse_bytes": (C.c_int, [_i64, _i64, C.c_int, _P(C.c_size_t)]),
     "fvx_sparse_create": (C.c_int, [_i64, _i64, _vp, _vp, _vp, C.c_int, _vp, C.c_size_t, _vp, _P(C.c_void_p)]),
     "fvx_sparse_destroy": (C.c_int, [_vp]),

@@ -240,12 +240,31 @@ __global__ __launch_bounds__(kFlatBlock) void k_b_resid(Flat f, CgDev d, const d
     flat_partial(c, f, d.part_b, lds);
 }
 
-// 16-byte streaming copy, each block a contiguous range.
-__global__ __launch_bounds__(kFlatBlock) void k_copy(int64_t n16, int64_t per_block, const uint4 *__restrict__ src,
-                                                     uint4 *__restrict__ dst) {
-    const int64_t i0 = int64_t(blockIdx.x) * per_block;
-    const int64_t i1 = min(n16, i0 + per_block);
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+// Streaming copy: per trip a block moves one contiguous chunk of
+// kCopyUnroll * kFlatBlock 16-byte words (16 KiB), each lane holding
+// kCopyUnroll independent non-temporal loads in flight before its stores;
+// chunks are dealt to blocks in a grid-stride loop.  Contiguous chunks per
+// block keep the DRAM pages each block opens local, which measured faster on
+// gfx950 than spreading a block's loads over the whole buffer (grid-stride
+// per lane) at every size from 17 MB to 1 GiB.
+constexpr int kCopyUnroll = 4;
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kFlatBlock) void k_copy(int64_t n16, const u32x4 *__restrict__ src,
+                                                     u32x4 *__restrict__ dst) {
+    constexpr int64_t chunk = int64_t(kCopyUnroll) * kFlatBlock;
+    for (int64_t c = int64_t(blockIdx.x) * chunk; c < n16; c += int64_t(gridDim.x) * chunk) {
+        if (c + chunk <= n16) {
+            u32x4 v[kCopyUnroll];
+#pragma unroll
+            for (int u = 0; u < kCopyUnroll; ++u)
+                v[u] = __builtin_nontemporal_load(src + c + u * kFlatBlock + threadIdx.x);
+#pragma unroll
+            for (int u = 0; u < kCopyUnroll; ++u)
+                __builtin_nontemporal_store(v[u], dst + c + u * kFlatBlock + threadIdx.x);
+        } else {
+            for (int64_t i = c + threadIdx.x; i < n16; i += kFlatBlock) dst[i] = src[i];
+        }
+    }
 }
 
 struct CsrWs {
@@ -432,11 +451,22 @@ int fvx_copy(void *dst, const void *src, size_t bytes, void *stream) {
                     FVX_E_ARG, "copy needs 16-byte aligned buffers and sizes");
         const int64_t n16 = int64_t(bytes / 16);
         if (n16 == 0) return FVX_OK;
-        const int64_t nb = std::min<int64_t>(8192, fvx::ceil_div(n16, fvx::kFlatBlock * 8));
-        const int64_t per = fvx::ceil_div(n16, nb);
-        hipLaunchKernelGGL(fvx::k_copy, dim3(int(fvx::ceil_div(n16, per))), dim3(fvx::kFlatBlock), 0,
-                           fvx::as_stream(stream), n16, per, static_cast<const uint4 *>(src), static_cast<uint4 *>(dst));
+        // one chunk per block up to 8192 blocks (32 per CU), then grid-stride
+        const int64_t nb = std::min<int64_t>(8192, fvx::ceil_div(n16, int64_t(fvx::kCopyUnroll) * fvx::kFlatBlock));
+        hipLaunchKernelGGL(fvx::k_copy, dim3(int(nb)), dim3(fvx::kFlatBlock), 0, fvx::as_stream(stream), n16,
+                           static_cast<const fvx::u32x4 *>(src), static_cast<fvx::u32x4 *>(dst));
         FVX_HIP(hipGetLastError());
+        return FVX_OK;
+    });
+}
+
+int fvx_copy_many(int n, void *const *dst, const void *const *src, size_t bytes, void *stream) {
+    return guard([&]() -> int {
+        FVX_REQUIRE(n >= 0 && (n == 0 || (dst && src)), FVX_E_ARG, "bad pointer arrays");
+        for (int i = 0; i < n; ++i) {
+            const int rc = fvx_copy(dst[i], src[i], bytes, stream);
+            if (rc != FVX_OK) return rc;
+        }
         return FVX_OK;
     });
 }
