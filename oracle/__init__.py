@@ -70,6 +70,8 @@ def lib():
         L.orc_spmv.restype = None
         L.orc_cg.argtypes = [l64, l64, _lp, _ip, _dp, _dp, _dp, i, d, i, i, P(_CGStats)]
         L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [i]
+        L.orc_set_threads.restype = None
         L.orc_stencil_max_nnz.argtypes = [i, i, i, i]
         L.orc_stencil_max_nnz.restype = l64
         L.orc_assemble_stencil.argtypes = [i, i, d, d, d, d, d, i, i, i, d, i, _lp, _ip, _dp, P(l64)]
@@ -261,6 +263,11 @@ def stencil_lap(spec, k: int, dz: float, stencil: int) -> sp.csr_matrix:
 def threads() -> int:
     """Number of host threads the oracle's OpenMP loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the number of host threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(int(n))
 
 
 def spmv(A: sp.csr_matrix, x: np.ndarray, out: np.ndarray | None = None) -> np.ndarray:

@@ -672,6 +672,17 @@ int orc_threads(void)
 #endif
 }
 
+/* Sets the number of threads of the OpenMP loops above (n >= 1; ignored
+ * without OpenMP). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 
 /* ---- higher-order structured operators (13- and 27-point) --------------
  *

@@ -101,6 +101,7 @@ int orc_cg(int64_t row0, int64_t n, const int64_t *ptr, const int32_t *col, cons
            orc_cg_stats *st);
 
 int orc_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

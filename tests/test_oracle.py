@@ -255,3 +255,53 @@ def test_speedup_bounds_are_intensity_ratios(orc, nnz_row):
     # Eq. 7: all time in SpMM (chi = 1) gives the SpMM speed-up; none gives 1.
     assert orc.p_poisson(3.0, 1.0) == pytest.approx(3.0)
     assert orc.p_poisson(3.0, 0.0) == pytest.approx(1.0)
+
+
+def test_speedup_bounds_match_fig2_values(orc):
+    """Eqs. 3a/3b at the Fig. 2 setting (n = 10^6, 7 and 13 nonzeros per row)
+    against the values in tests/golden/spmm_bounds_fig2.txt."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "spmm_bounds_fig2.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 8
+    n = 1e6
+    for r, m, ub, lb in rows:
+        nnz = int(r) * n
+        assert orc.p_spmm_ub(nnz, n, n, int(m)) == pytest.approx(float(ub), abs=6e-4)
+        assert orc.p_spmm_lb(nnz, n, int(m)) == pytest.approx(float(lb), abs=6e-4)
+
+
+def _alg1_bytes(A, m, fresh_gathers):
+    """Bytes Algorithm 1 moves for an actual CSR matrix A (FP64 values, int32
+    indices and row pointers) and m right-hand sides, counted from the arrays
+    it touches: the matrix once, the output y and the column scale c once,
+    and the input x either once per distinct element (perfect reuse) or once
+    per gathered entry (every gather a fresh load)."""
+    val = A.data.astype(np.float64)
+    idx = A.indices.astype(np.int32)
+    ptr = A.indptr.astype(np.int32)
+    n_r, n_c = A.shape
+    x_elems = (A.nnz if fresh_gathers else n_c) * m
+    return val.nbytes + idx.nbytes + ptr.nbytes + 8 * x_elems + 8 * n_r * m + 8 * m
+
+
+@pytest.mark.parametrize("shape,per_row", [((400, 400), 7), ((300, 500), 13), ((600, 200), 5)])
+def test_speedup_bounds_match_counted_bytes(orc, shape, per_row):
+    """Eqs. 3a/3b against a byte count of Algorithm 1 on real random CSR
+    matrices: with the flops of m right-hand sides m times those of one, the
+    upper bound is m B(1) / B(m) with the input read once, and the lower
+    bound the same ratio with every gather a fresh load; Eq. 2's denominator
+    is B(m) with the input read once."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(per_row)
+    n_r, n_c = shape
+    cols = np.stack([rng.choice(n_c, per_row, replace=False) for _ in range(n_r)])
+    A = sp.csr_matrix((rng.standard_normal(n_r * per_row), cols.ravel(), np.arange(0, n_r * per_row + 1, per_row)),
+                      shape=shape)
+    for m in (1, 2, 5, 16, 128):
+        ub = m * _alg1_bytes(A, 1, False) / _alg1_bytes(A, m, False)
+        lb = m * _alg1_bytes(A, 1, True) / _alg1_bytes(A, m, True)
+        assert orc.p_spmm_lb(A.nnz, n_r, m) == pytest.approx(lb, rel=1e-13)  # n_c drops out of Eq. 3b
+        assert orc.p_spmm_ub(A.nnz, n_r, n_c, m) == pytest.approx(ub, rel=1e-13)
+        flops = orc.ai_spmm(A.nnz, n_r, n_c, m) * _alg1_bytes(A, m, False)
+        assert flops == pytest.approx((2 * A.nnz + 1) * m, rel=1e-13)

@@ -273,3 +273,51 @@ def test_unstructured_mesh_coarsens_steadily():
     for a, b in zip(h.levels, h.levels[1:]):
         if a.kind == "xy":
             assert b.n_b <= a.n_b // 2
+
+
+def test_galerkin_level_of_a_uniform_periodic_box_is_the_closed_form_stencil():
+    """On a uniform box periodic in x, y and z, two pairwise passes give
+    aligned 2 x 2 aggregates, and the Galerkin product P^T A P of the
+    piecewise-constant prolongation is again the 7-point operator on the
+    half-size box, worked out by hand: across an x-face pair of aggregates
+    two cell faces of coupling t_x = dz h_y / h_x each (-2 t_x), likewise
+    -2 t_y in y, four cells of plane coupling w = h_x h_y / dz each between
+    planes (-4 w), and the diagonal the negated sum of those (the internal
+    faces of an aggregate cancel).  Checked entry by entry on the oracle's
+    level-1 operator, with the aggregates mapped to their (I, J) by their
+    member cells."""
+    nx, ny, k, dz = 8, 6, 4, 1.0
+    spec = inputs.CartSpec(nx, ny, 1.0, 0.0, 1.0, 0.0, True, True)   # h_x = 1/8, h_y = 1/6, uniform
+    hx, hy = 1.0 / nx, 1.0 / ny
+    tx, ty, w = dz * hy / hx, dz * hx / hy, hx * hy / dz
+    assert 2 * ty > tx > ty >= 0.25 * tx   # x pairs first, then the pairs pair along y: 2 x 2 boxes
+    m3 = oracle.Mesh3D(oracle.geometry(spec), k, dz, oracle.PERIODIC_Z)
+    A0 = (-m3.lap()).tocsr()
+    h = amg.build(A0, nx * ny, k, True, amg.AmgOpts(coarse_max=16))
+    lev = h.levels[0]
+    assert lev.kind == "xy" and len(h.levels) >= 2
+    cx, cy = nx // 2, ny // 2
+    nc = cx * cy
+    pos = np.empty(nc, dtype=int)   # aggregate -> coarse cell J * cx + I
+    for a in range(nc):
+        m = np.flatnonzero(lev.agg == a)
+        j, i = m // nx, m % nx
+        assert len(m) == 4 and np.ptp(i) == 1 and np.ptp(j) == 1 and i.min() % 2 == 0 and j.min() % 2 == 0
+        pos[a] = (j.min() // 2) * cx + i.min() // 2
+    assert sorted(pos) == list(range(nc))
+    E = np.zeros((k * nc, k * nc))
+    for l in range(k):
+        for J in range(cy):
+            for I in range(cx):
+                r = l * nc + J * cx + I
+                E[r, r] = 2 * (2 * tx) + 2 * (2 * ty) + 2 * (4 * w)
+                E[r, l * nc + J * cx + (I + 1) % cx] -= 2 * tx
+                E[r, l * nc + J * cx + (I - 1) % cx] -= 2 * tx
+                E[r, l * nc + ((J + 1) % cy) * cx + I] -= 2 * ty
+                E[r, l * nc + ((J - 1) % cy) * cx + I] -= 2 * ty
+                E[r, ((l + 1) % k) * nc + J * cx + I] -= 4 * w
+                E[r, ((l - 1) % k) * nc + J * cx + I] -= 4 * w
+    perm = np.concatenate([l * nc + pos for l in range(k)])   # oracle row l*nc + a is expected row l*nc + pos[a]
+    A1 = np.zeros_like(E)
+    A1[np.ix_(perm, perm)] = h.levels[1].A.toarray()
+    np.testing.assert_allclose(A1, E, rtol=0, atol=1e-13 * np.abs(E).max())
