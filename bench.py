@@ -41,6 +41,12 @@ BASE = (192, 128)
 K_MAIN = 64
 K_SWEEP = (1, 4, 16, 64)
 COUNTER_FILE = os.path.join(ROOT, "profiles", "lap_f64_channel192x128_k64_counters.json")
+# Tuned-tile database of the library on MI355X (gfx950): every tile the
+# autotuner and the headline refinement chose for the operators this
+# benchmark builds, keyed by (architecture, precision, k, ld, base rows, base
+# nonzeros, stencil).  Runs start from it, so the timed and the profiled
+# kernels are the same instances; --retune rebuilds it from scratch.
+TILE_DB = os.path.join(ROOT, "paper_2508_06710_amd", "tiles_gfx950.json")
 
 
 def log(msg):
@@ -136,8 +142,30 @@ def rotating_sets(op, fvx, torch, x_rows):
     return X, Y
 
 
-def lap_sweep(op, X, Y, torch, reps=1):
-    """Mean time per lap SpMM over the rotating pairs (launched from C)."""
+class Plug:
+    """About 1 ms of streaming copies (3 x 1 GiB) put on the stream ahead of a
+    timed sweep: the sweep's launches queue up behind it, so they run back to
+    back on the GPU whatever the host's launch rate -- also under a kernel
+    tracer, whose per-launch host overhead (about 13 us here) would
+    otherwise leave each short kernel isolated with its own ramp and drain.
+    The copies also flush the caches ahead of the sweep."""
+
+    def __init__(self, fvx, torch):
+        self.fvx = fvx
+        self.a = torch.empty(2 ** 30 // 8, dtype=torch.float64, device="cuda")
+        self.b = torch.empty_like(self.a)
+
+    def __call__(self):
+        for _ in range(3):
+            self.fvx.copy(self.b, self.a)
+
+
+def lap_sweep(op, X, Y, torch, reps=1, plug=None):
+    """Mean time per lap SpMM over the rotating pairs (launched from C),
+    HIP events around the sweep on the launch stream; with a plug, its
+    copies run ahead of the first event."""
+    if plug is not None:
+        plug()
     t = Timer(torch)
     with t:
         for _ in range(reps):
@@ -195,6 +223,92 @@ def tune_cg(op, fvx, dtype=None):
     return tile
 
 
+def setup_tile_cache(retune):
+    """The run's tile cache: FVX_TUNE_CACHE if set, else
+    gpurun_out/tiles_gfx950.json, seeded from the committed database unless
+    retune (operators missing from it are tuned and added)."""
+    import shutil
+    path = os.environ.get("FVX_TUNE_CACHE") or os.path.join(ROOT, "gpurun_out", "tiles_gfx950.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    if retune:
+        if os.path.exists(path):
+            os.remove(path)
+    elif not os.path.exists(path) and os.path.exists(TILE_DB):
+        shutil.copyfile(TILE_DB, path)
+    os.environ["FVX_TUNE_CACHE"] = path
+    log(f"tile cache {path} ({'retune' if retune else 'from the database' if os.path.exists(path) else 'empty'})")
+
+
+def lanczos_kappa(op, inputs, torch, m, seed=11):
+    """kappa_est of the SPD operator A = -L on the complement of its null
+    space: the ratio of the extreme Ritz values of m Lanczos steps (the
+    tridiagonal that CG builds implicitly), started from a random vector;
+    the Lanczos vectors are kept at zero mean (per column for independent
+    planes) so that rounding does not bring the null space back.  Ritz
+    values lie inside the spectrum, so this estimate is at most kappa."""
+    import numpy as np
+    from scipy.linalg import eigvalsh_tridiagonal
+    k = op.k
+    percol = op.coupling == 0 or k == 1
+
+    def proj(v):
+        if op.singular:
+            vv = v[:, :k]
+            vv -= vv.mean(dim=0, keepdim=True) if percol else vv.mean()
+
+    def dot(a, b):
+        return (a[:, :k] * b[:, :k]).sum()
+
+    v = op.to_rows(inputs.uniform(seed, 0, op.n_b * k))
+    proj(v)
+    v /= torch.sqrt(dot(v, v))
+    vp, w = torch.zeros_like(v), torch.empty_like(v)
+    beta = torch.zeros((), dtype=torch.float64, device=v.device)
+    al, be = [], []
+    for _ in range(m):
+        op.lap(v, w)
+        w.neg_()
+        a = dot(w, v)
+        w -= a * v
+        w -= beta * vp
+        proj(w)
+        beta = torch.sqrt(dot(w, w))
+        al.append(a)
+        be.append(beta)
+        w /= beta
+        vp, v, w = v, w, vp
+    d = torch.stack(al).cpu().numpy()
+    e = torch.stack(be).cpu().numpy()[:-1]
+    lo = eigvalsh_tridiagonal(d, e, select="i", select_range=(0, 0))[0]
+    hi = eigvalsh_tridiagonal(d, e, select="i", select_range=(m - 1, m - 1))[0]
+    return float(hi / lo), float(lo), float(hi)
+
+
+def rel_err(torch, op, X, Xs):
+    k = op.k
+    return float(torch.linalg.vector_norm(X[:, :k] - Xs[:, :k]) / torch.linalg.vector_norm(Xs[:, :k]))
+
+
+def mixed_errors(fvx, inputs, torch, op, B, sols, rtol_star=1e-13, steps=None, star_kw=None):
+    """Error of mixed-precision solutions against the FP64 solution x* to
+    rtol_star (the library's FP64 CG, plain or with star_kw's
+    preconditioner), per result, beside the a-posteriori bound
+    kappa_est (relres + relres*): ||x - x_true|| <= ||r|| / lambda_min and
+    ||x_true|| >= ||b|| / lambda_max.  kappa_est comes from `steps` Lanczos
+    steps (default: the plain x* solve's iteration count, at most 3000).
+    sols: {name: (X, stats)}.  Returns (record, x*)."""
+    Xs, sts = op.solve(B, rtol=rtol_star, **(star_kw or {}))
+    m = steps if steps else min(max(sts["iters"], 50), 3000)
+    kap, lo, hi = lanczos_kappa(op, inputs, torch, m)
+    out = {"x_star": {"rtol": rtol_star, "iters": sts["iters"], "relres_true": sts["relres_true"]},
+           "kappa_est": kap, "lanczos_steps": m}
+    for name, (X, st) in sols.items():
+        err = rel_err(torch, op, X, Xs)
+        bound = kap * (st["relres_true"] + sts["relres_true"])
+        out[name] = {"rel_err_vs_fp64": err, "bound_kappa": bound, "relres_true": st["relres_true"]}
+    return out, Xs
+
+
 def build_case(fvx, inputs, k):
     spec = inputs.channel_base(*BASE)
     mesh = fvx.Mesh.from_spec(spec)
@@ -244,6 +358,79 @@ def counters_mode(fvx, inputs, torch):
     log(f"counters run done: lap bytes/launch {spmm_bytes(op.nnz_b, op.n_b, op.k)}, copy bytes {nbytes}")
 
 
+def summarize_counters(fetch_dir, write_dir, flops_dir, out=COUNTER_FILE):
+    """Writes the counters file from three rocprofv3 --pmc runs of
+    `bench.py --counters` (FETCH_SIZE; WRITE_SIZE; the FP64 VALU counters):
+    per lap kernel instance the median FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by what the same counters read for the 256 MiB copy of
+    the run, and the FP64 floating-point operations counted per dispatch.
+    Runs on any host (CSV files only)."""
+    import csv
+    import glob
+    import re
+    import statistics
+
+    def rows(d):
+        out = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                out += list(csv.DictReader(fh))
+        return out
+
+    def short(n):
+        n = n.replace("void ", "").replace("fvx::(anonymous namespace)::", "").replace("fvx::", "")
+        return re.sub(r"\(.*", "", n).strip()
+
+    def per_kernel(rs):
+        acc = {}
+        for r in rs:
+            key = (short(r["Kernel_Name"]), int(r["Dispatch_Id"]))
+            acc.setdefault(key, {})
+            acc[key][r["Counter_Name"]] = acc[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        byk = {}
+        for (name, _), cs in acc.items():
+            byk.setdefault(name, []).append(cs)
+        return byk
+
+    fk, wk, pk = per_kernel(rows(fetch_dir)), per_kernel(rows(write_dir)), per_kernel(rows(flops_dir))
+    med = lambda lst, c: statistics.median(x.get(c, 0.0) for x in lst)
+    copy_bytes = 256 * 2 ** 20
+    cf, cw = med(fk["k_copy"], "FETCH_SIZE"), med(wk["k_copy"], "WRITE_SIZE")
+    fs, ws = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    nb, k = BASE[0] * BASE[1], K_MAIN
+    nnz_b = nb + 2 * (BASE[0] * BASE[1] * 2 - BASE[0])  # periodic x faces + interior y faces, 5-point base
+    alg = spmm_bytes(nnz_b, nb, k)
+    by_kernel = {}
+    for name in fk:
+        if not name.startswith("k_lap"):
+            continue
+        f = med(fk[name], "FETCH_SIZE") * 1024 * fs
+        w = med(wk.get(name, [{}]), "WRITE_SIZE") * 1024 * ws
+        e = {"kernel": name, "dispatches": len(fk[name]), "fetch_kib_per_dispatch": med(fk[name], "FETCH_SIZE"),
+             "write_kib_per_dispatch": med(wk.get(name, [{}]), "WRITE_SIZE"), "fetch_bytes_per_launch": f,
+             "write_bytes_per_launch": w, "traffic_over_algorithmic": (f + w) / alg}
+        if name in pk:
+            lst = pk[name]
+            e["fp64_flops_counted"] = med(lst, "SQ_INSTS_VALU_FLOPS_FP64")
+            e["fp64_flops_from_insts"] = 64 * (med(lst, "SQ_INSTS_VALU_ADD_F64") + med(lst, "SQ_INSTS_VALU_MUL_F64")
+                                               + 2 * med(lst, "SQ_INSTS_VALU_FMA_F64"))
+            e["fp64_flops_algorithmic"] = spmm_flops(nnz_b, nb, k)
+        by_kernel[name] = e
+    rec = {"workload": f"channel {BASE[0]}x{BASE[1]} base x {K_MAIN} periodic planes, FP64, cold (rotating buffers > 1 GiB)",
+           "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --counters",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --counters",
+                        "rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+                        "SQ_INSTS_VALU_FMA_F64 --output-format csv -d gpurun_out/pmc_flops -o flops -- python3 bench.py --counters",
+                        "python bench.py --summarize-counters gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/pmc_flops"],
+           "algorithmic_bytes_per_launch": alg,
+           "copy_calibration": {"copy_bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw, "fetch_scale": fs,
+                                "write_scale": ws},
+           "source_sha": kernel_source_sha(), "by_kernel": by_kernel}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"wrote {out}: " + ", ".join(f"{n}: {e['traffic_over_algorithmic']:.3f}x" for n, e in by_kernel.items()))
+
+
 def mixed_profile_mode(fvx, inputs, torch):
     """A short run for rocprofv3 kernel traces of the mixed-precision solve on
     the channel workload: one warm-up and one timed solve to 1e-8 of the
@@ -286,7 +473,10 @@ def net_profile_mode(fvx, inputs, torch):
 
 def cpu_baseline(inputs, oracle, b_plane, k, rtol):
     """The oracle as it stands, on the host cores: its assembled-3D CSR SpMV
-    (timed repeatedly) and its textbook CG to rtol on the same right-hand side."""
+    (timed repeatedly) and its textbook CG to rtol on the same right-hand
+    side, with all host threads; then on one thread the SpMV and a CG capped
+    at 60 iterations, whose time per iteration is scaled to the all-thread
+    run's iteration count (a bounded sample: about 10 s of one core)."""
     spec = inputs.channel_base(*BASE)
     g = oracle.geometry(spec)
     m3 = oracle.Mesh3D(g, k, math.pi / k, oracle.PERIODIC_Z)
@@ -295,30 +485,50 @@ def cpu_baseline(inputs, oracle, b_plane, k, rtol):
     t_asm = time.perf_counter() - t0
     x = inputs.uniform(0, 0, m3.N)
     y = oracle.spmv(L, x)
-    reps, t_spmv = 0, 0.0
-    while reps < 20 and t_spmv < 5.0:
-        t0 = time.perf_counter()
-        oracle.spmv(L, x, out=y)
-        t_spmv += time.perf_counter() - t0
-        reps += 1
-    t_spmv /= reps
-    log(f"oracle spmv {t_spmv * 1e3:.2f} ms ({reps} reps), assembly {t_asm:.1f} s")
+
+    def time_spmv(max_reps, budget_s):
+        ts = []
+        while len(ts) < max_reps and sum(ts) < budget_s:
+            t0 = time.perf_counter()
+            oracle.spmv(L, x, out=y)
+            ts.append(time.perf_counter() - t0)
+        return float(sorted(ts)[len(ts) // 2]), len(ts)
+
+    threads = oracle.threads()
+    t_spmv, reps = time_spmv(20, 5.0)
+    log(f"oracle spmv {t_spmv * 1e3:.2f} ms (median of {reps}, {threads} threads), assembly {t_asm:.1f} s")
     t0 = time.perf_counter()
     r = oracle.cg(m3, L, b_plane, rtol, max_iter=20000)
     t_cg = time.perf_counter() - t0
-    log(f"oracle CG {r.iters[0]} iters {t_cg:.1f} s")
+    log(f"oracle CG {r.iters[0]} iters {t_cg:.2f} s ({threads} threads)")
+    oracle.set_threads(1)
+    try:
+        t_spmv1, reps1 = time_spmv(5, 3.0)
+        cap = 60
+        t0 = time.perf_counter()
+        oracle.cg(m3, L, b_plane, rtol, max_iter=cap)
+        t_it1 = (time.perf_counter() - t0) / cap
+    finally:
+        oracle.set_threads(threads)
+    log(f"oracle 1 thread: spmv {t_spmv1 * 1e3:.2f} ms, CG {t_it1 * 1e3:.2f} ms per iteration")
     nb = g.n_cells
     nnz_b = nb + 2 * g.n_faces
+    Bk = spmm_bytes(nnz_b, nb, k)
     return {
-        "value": spmm_bytes(nnz_b, nb, k) / t_spmv / 1e9,
+        "value": Bk / t_spmv / 1e9,
         "unit": "GB/s",
-        "cores": oracle.threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle assembled-3D CSR SpMV on the {BASE[0]}x{BASE[1]}x{k} channel, "
-                   f"{reps} repetitions, GB/s counted with the SpMM's algorithmic bytes; "
-                   f"plus one oracle CG to {rtol:g} on the projection right-hand side"),
+        "sample": (f"oracle assembled-3D CSR SpMV on the {BASE[0]}x{BASE[1]}x{k} channel (median of {reps}), "
+                   f"GB/s counted with the SpMM's algorithmic bytes (the same product); one oracle CG to {rtol:g} "
+                   f"on the projection right-hand side; 1 thread: SpMV median of {reps1} and a 60-iteration CG "
+                   f"scaled to the full iteration count"),
+        "value_1thread": Bk / t_spmv1 / 1e9,
+        "csr_own_GBs": csr3d_bytes(L.nnz, m3.N) / t_spmv / 1e9,
         "spmv_ms": t_spmv * 1e3,
+        "spmv_ms_1thread": t_spmv1 * 1e3,
         "poisson_s_to_1e-8": t_cg,
+        "poisson_s_to_1e-8_1thread": t_it1 * r.iters[0],
         "poisson_iters": r.iters[0],
         "cpu_model": _cpu_model(),
         "nproc": os.cpu_count(),
@@ -358,7 +568,14 @@ def main():
     ap.add_argument("--no-ns", action="store_true")
     ap.add_argument("--guess-epochs", type=int, default=20)
     ap.add_argument("--guess-lr", type=float, default=1e-4)
+    ap.add_argument("--retune", action="store_true",
+                    help="ignore the tile database and tune every operator again")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "FLOPS_DIR"),
+                    help="write the counters file from rocprofv3 --pmc output of --counters runs (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path runs on a single device)", file=sys.stderr)
@@ -372,6 +589,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    setup_tile_cache(args.retune)
     if args.counters:
         counters_mode(fvx, inputs, torch)
         return
@@ -418,6 +636,7 @@ def main():
     D = op.empty()
     PHI = op.zeros()
     op.workspace(op.solve_opts(rtol=rtol))
+    plug = Plug(fvx, torch)
     log(f"{N} cells, {len(X)} rotating lap buffer pairs ({len(X) * 2 * n_b * op.ld * 8 / 2**30:.2f} GiB)")
 
     def step():
@@ -432,7 +651,7 @@ def main():
         t_grad = Timer(torch)
         with t_grad:
             op.grad_axpy(-1.0, PHI, U, W)
-        t_lap = lap_sweep(op, X, Y, torch)
+        t_lap = lap_sweep(op, X, Y, torch, plug=plug)
         return dict(div_ms=t_div.ms(), solve_ms=t_sol.ms(), grad_ms=t_grad.ms(), lap_ms=t_lap, stats=st)
 
     for i in range(args.warmup):
@@ -449,7 +668,11 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
 
-    lap_ms = float(np.mean([r["lap_ms"] for r in recs]))
+    # Headline: per step, the mean launch time of the lap SpMM over one sweep
+    # of the rotating buffers (HIP events around the sweep on the launch
+    # stream); the median over the timed steps.
+    laps = sorted(r["lap_ms"] for r in recs)
+    lap_ms = float(np.median(laps))
     achieved = Bk / (lap_ms * 1e-3) / 1e9
     st = recs[-1]["stats"]
     solve_s = float(np.median([r["solve_ms"] for r in recs])) / 1e3
@@ -461,12 +684,13 @@ def main():
     cnt = load_counters(sha)
     traffic = None
     norm = lambda n: n.replace(" ", "").lower()
+    flops_counted = None
     if cnt:  # counters of this very kernel instance
-        entries = [cnt] + list(cnt.get("by_kernel", {}).values())
-        hit = [e for e in entries if norm(e.get("kernel", "")) == norm(lap_kernel_name(tile, k))]
+        hit = [e for e in cnt.get("by_kernel", {}).values() if norm(e.get("kernel", "")) == norm(lap_kernel_name(tile, k))]
         if hit:
             traffic = hit[0]["fetch_bytes_per_launch"] + hit[0]["write_bytes_per_launch"]
-    out = {
+            flops_counted = hit[0].get("fp64_flops_counted")
+    full = {
         "metric": "SpMM GB/s & % HBM roofline vs k×SpMV; Poisson time to rel. residual 1e-8",
         "value": achieved,
         "unit": "GB/s",
@@ -486,7 +710,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": lap_kernel_name(tile, k), "tile": list(tile), "bytes_per_launch": Bk,
-                     "launch_us": lap_ms * 1e3, "fp64_tflops": Fk / (lap_ms * 1e-3) / 1e12,
+                     "launch_us": lap_ms * 1e3, "launch_us_min": laps[0] * 1e3, "launch_us_max": laps[-1] * 1e3,
+                     "sweep_launches": len(X), "fp64_tflops": Fk / (lap_ms * 1e-3) / 1e12,
+                     "fp64_tflops_counted": None if flops_counted is None else flops_counted / (lap_ms * 1e-3) / 1e12,
                      "fp64_peak_tflops": FP64_PEAK_TFLOPS, "intensity_flop_per_byte": Fk / Bk,
                      "source_sha": sha},
         "poisson": {"s_to_1e-8": solve_s, "iters": st["iters"], "relres_true": st["relres_true"], "cg_tiles": cg_tiles,
@@ -495,55 +721,135 @@ def main():
         "phases_ms": {p: float(np.mean([r[p] for r in recs])) for p in ("div_ms", "solve_ms", "grad_ms", "lap_ms")},
     }
 
+    legs = {}
     if not args.no_sweep:
-        out.update(extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D))
-        if out.get("copy_ceiling_GBs"):
-            out["roofline"]["frac_of_copy"] = achieved / out["copy_ceiling_GBs"]
+        legs.update(extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D))
+        same = [c for c in legs["copy_ceiling"] if c["size"] == "headline_traffic"]
+        if same:
+            full["roofline"]["copy_same_bytes_GBs"] = same[0]["GBs"]
+            full["roofline"]["frac_of_copy"] = achieved / same[0]["GBs"]
 
     if not args.no_stencil:
-        out["stencils"] = stencil_leg(fvx, inputs, torch, np)
+        legs["stencils"] = stencil_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
-        out["refine_mapping"] = refine_leg(fvx, inputs, torch, np)
+        legs["refine_mapping"] = refine_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
-        out["generic_spmm"] = generic_leg(fvx, inputs, torch, np)
+        legs["generic_spmm"] = generic_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
     if not args.no_ns:
-        out["ns_step"] = ns_leg(fvx, inputs, torch, np)
+        legs["ns_step"] = ns_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
     if not args.no_batch:
-        out["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
+        legs["batched"] = batch_leg(fvx, inputs, torch, np, rtol)
         torch.cuda.empty_cache()
     if not args.no_airfoil:
-        out["airfoil"] = airfoil_leg(fvx, inputs, torch, np)
+        legs["airfoil"] = airfoil_leg(fvx, inputs, torch, np)
         torch.cuda.empty_cache()
     if not args.no_guess:
-        out["learned_guess"] = guess_leg(fvx, inputs, torch, np, args.guess_epochs, args.guess_lr, rtol)
+        legs["learned_guess"] = guess_leg(fvx, inputs, torch, np, args.guess_epochs, args.guess_lr, rtol)
         torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("timing the CPU oracle")
         b_plane = op.to_planes(D)
-        out["cpu_baseline"] = cpu_baseline(inputs, __import__("oracle"), b_plane, k, rtol)
-    print(json.dumps(out), flush=True)
+        full["cpu_baseline"] = cpu_baseline(inputs, __import__("oracle"), b_plane, k, rtol)
+    full.update(legs)
+    path = os.path.join(ROOT, "gpurun_out", "bench_full.json")
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(full, fh, indent=1)
+        log(f"every leg written to {path}")
+    except OSError as e:
+        log(f"could not write {path}: {e}")
+    line = json.dumps(compact_line(full, legs))
+    print(line, flush=True)
+
+
+def compact_line(full, legs):
+    """The one JSON line of the contract: the headline, its roofline, the
+    Poisson times and the CPU baseline, each leg reduced to its key figures
+    (the full record goes to gpurun_out/bench_full.json), under 4 KB."""
+    r = lambda v, n=4: None if v is None else float(f"{v:.{n}g}")
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data")
+    out = {k: full[k] for k in keys}
+    out["value"] = r(out["value"], 5)
+    out["ms_per_step"] = r(out["ms_per_step"], 5)
+    c = full["config"]
+    out["config"] = {"workload": c["workload"], "base": c["base"], "k": c["k"], "cells": c["cells"]}
+    rf = full["roofline"]
+    out["roofline"] = {q: (r(rf[q]) if isinstance(rf.get(q), float) else rf.get(q))
+                       for q in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "launch_us",
+                                 "launch_us_min", "launch_us_max", "bytes_per_launch", "fp64_tflops",
+                                 "fp64_tflops_counted",
+                                 "copy_same_bytes_GBs", "frac_of_copy") if q in rf}
+    p = full["poisson"]
+    out["poisson"] = {"s_to_1e-8": r(p["s_to_1e-8"]), "iters": p["iters"], "relres_true": r(p["relres_true"], 3),
+                      "ms_per_iter": r(p["ms_per_iter"])}
+    if "csr3d_cg" in legs:
+        out["poisson"]["csr3d_spmv_cg_s"] = r(legs["csr3d_cg"]["s_to_1e-8"])
+    if "mixed_cg" in legs:
+        m = legs["mixed_cg"]
+        out["poisson"]["mixed"] = {"s": r(m["s_to_1e-8"]), "rel_err_vs_fp64": r(m["rel_err_vs_fp64"], 3),
+                                   "bound": r(m["bound_kappa"], 3), "kappa_est": r(m["kappa_est"], 3)}
+    if "poisson_pcg" in legs:
+        out["poisson"]["chebyshev_s"] = r(legs["poisson_pcg"]["chebyshev"]["s_to_1e-8"])
+    if "poisson_amg" in legs:
+        out["poisson"]["multigrid_s"] = r(legs["poisson_amg"]["f64"]["s_to_1e-8"])
+        out["poisson"]["multigrid_iters"] = legs["poisson_amg"]["f64"]["iters"]
+    if "k_sweep" in legs:
+        out["k_sweep"] = [{"k": e["k"], "GBs": r(e["spmm_GBs"]), "P_k": r(e["P_k"], 3),
+                           "vs_csr3d": r(e["speedup_vs_csr3d"], 3)} for e in legs["k_sweep"]]
+    if "copy_ceiling" in legs:
+        out["copy_GBs"] = {e["size"]: r(e["GBs"]) for e in legs["copy_ceiling"]}
+    if "stencils" in legs:
+        out["stencil_k64_f64_GBs"] = {str(e["stencil"]): r(e["spmm_GBs"]) for e in legs["stencils"]
+                                      if e["k"] == 64 and e["dtype"] == "f64"}
+    if "batched" in legs:
+        b = legs["batched"]
+        out["batched"] = {"s": r(b["batch_s"]), "singles_s": r(b["sum_single_s"]), "csr3d_s": r(b["sum_csr3d_fp64_s"]),
+                          "max_rel_err_vs_fp64": r(b["max_rel_err_vs_fp64"], 3),
+                          "max_err_over_bound": r(b["max_err_over_bound"], 3)}
+    if "airfoil" in legs:
+        a = legs["airfoil"]
+        out["airfoil"] = {"mixed_s": r(a["solve_mixed"]["s"]), "f64_s": r(a["solve_f64"]["s"]),
+                          "mixed_multigrid_s": r(a["solve_mixed_amg"]["s"]),
+                          "csr3d_s": r(a["solve_csr3d_fp64"]["s"]),
+                          "mixed_rel_err_vs_fp64": r(a["solve_mixed"]["rel_err_vs_fp64"], 3),
+                          "mixed_bound": r(a["solve_mixed"]["bound_kappa"], 3)}
+    if "learned_guess" in legs:
+        g = legs["learned_guess"]
+        out["learned_guess"] = {"iters_zero": r(g["zero_guess"]["mean_iters"]),
+                                "iters_prev": r(g["prev_pressure_guess"]["mean_iters"]),
+                                "iters_net": r(g["net_guess"]["mean_iters"]),
+                                "ms_zero": r(g["zero_guess"]["mean_ms_to_1e-8"]),
+                                "ms_net": r(g["net_guess"]["mean_ms_to_1e-8"]),
+                                "net_chosen": g["guess_chosen"]["net"], "eval_pairs": g["eval_pairs"]}
+    if "cpu_baseline" in full:
+        cb = full["cpu_baseline"]
+        out["cpu_baseline"] = {"value": r(cb["value"]), "unit": cb["unit"], "cores": cb["cores"], "kind": cb["kind"],
+                               "sample": cb["sample"], "value_1thread": r(cb["value_1thread"]),
+                               "poisson_s_to_1e-8": r(cb["poisson_s_to_1e-8"]),
+                               "poisson_s_to_1e-8_1thread": r(cb["poisson_s_to_1e-8_1thread"]),
+                               "nproc": cb["nproc"], "cpu_model": cb["cpu_model"]}
+    out["legs_file"] = "gpurun_out/bench_full.json"
+    while len(json.dumps(out)) > 4000:  # keep the line short enough for any capture
+        for q in ("stencil_k64_f64_GBs", "copy_GBs", "k_sweep", "learned_guess", "airfoil", "batched"):
+            if q in out:
+                del out[q]
+                break
+        else:
+            break
+    return out
 
 
 def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
     """k sweep (SpMM vs k single-column products and vs the assembled 3D CSR
     SpMV), the copy ceiling, the assembled-CSR CG comparator and the mixed
     precision solve.  Measured outside the timed steps."""
-    res = {}
-    # copy ceiling: 1 GiB each way, rotating
-    nbytes = 2 ** 30
-    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    fvx.copy(dst, src)
-    t = Timer(torch)
-    with t:
-        for i in range(5):
-            fvx.copy(dst if i % 2 == 0 else src, src if i % 2 == 0 else dst)
-    res["copy_ceiling_GBs"] = 5 * 2 * nbytes / (t.ms() * 1e-3) / 1e9
-    del src, dst
-    log(f"copy ceiling {res['copy_ceiling_GBs']:.0f} GB/s")
+    res = {"copy_ceiling": copy_leg(fvx, torch, spmm_bytes(op.nnz_b, op.n_b, op.k))}
+    res["copy_ceiling_GBs"] = max(c["GBs"] for c in res["copy_ceiling"])
 
     import oracle  # closed-form bounds of Section 2 only (Eq. 2, 3a)
     sweep = []
@@ -586,17 +892,64 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
         _, st3 = A.solve(b, rtol=rtol)
     res["csr3d_cg"] = {"s_to_1e-8": tm.ms() / 1e3, "iters": st3["iters"], "relres_true": st3["relres_true"]}
     del A
-    # Mixed precision solve to 1e-8 on the SpMM operator.
+    # Mixed precision solve to 1e-8 on the SpMM operator, and its error
+    # against the FP64 solution to 1e-13 beside the kappa bound.
     op.solve(D, rtol=rtol, precision=fvx.MIXED)
     tm = Timer(torch)
     with tm:
-        _, stm = op.solve(D, rtol=rtol, precision=fvx.MIXED, inner_rtol=1e-4)
+        Xm, stm = op.solve(D, rtol=rtol, precision=fvx.MIXED, inner_rtol=1e-4)
+    Xf, stf = op.solve(D, rtol=rtol)
+    errs, Xstar = mixed_errors(fvx, inputs, torch, op, D, {"mixed": (Xm, stm), "fp64": (Xf, stf)})
     res["mixed_cg"] = {"s_to_1e-8": tm.ms() / 1e3, "inner_iters": stm["iters"], "outer": stm["outer"],
-                       "relres_true": stm["relres_true"]}
-    res["poisson_pcg"] = pcg_leg(fvx, torch, op, D, rtol)
-    res["poisson_amg"] = amg_leg(fvx, torch, inputs, op, D, rtol)
+                       "relres_true": stm["relres_true"], "rel_err_vs_fp64": errs["mixed"]["rel_err_vs_fp64"],
+                       "bound_kappa": errs["mixed"]["bound_kappa"], "kappa_est": errs["kappa_est"],
+                       "fp64_rtol_rel_err": errs["fp64"]["rel_err_vs_fp64"], "x_star": errs["x_star"]}
+    log(f"mixed vs FP64 x*: rel err {errs['mixed']['rel_err_vs_fp64']:.2e} (bound {errs['mixed']['bound_kappa']:.2e},"
+        f" kappa_est {errs['kappa_est']:.3e}); FP64 at rtol: {errs['fp64']['rel_err_vs_fp64']:.2e}")
+    kap = errs["kappa_est"]
+    star_res = errs["x_star"]["relres_true"]
+
+    def err_of(X, st):
+        return {"rel_err_vs_fp64": rel_err(torch, op, X, Xstar), "bound_kappa": kap * (st["relres_true"] + star_res)}
+
+    res["poisson_pcg"] = pcg_leg(fvx, torch, op, D, rtol, err_of)
+    res["poisson_amg"] = amg_leg(fvx, torch, inputs, op, D, rtol, err_of)
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
+
+
+def copy_leg(fvx, torch, headline_bytes):
+    """Achievable-bandwidth reference: the library's streaming copy (fvx_copy)
+    over rotating buffer pairs totalling more than 1 GiB (cold Infinity
+    Cache), at the headline launch's traffic (a copy of half its algorithmic
+    bytes), at buffers of 16.8, 26.9, 56.1 and 213 MB, and at 1 GiB.  Time
+    per launch: the median over 3 back-to-back sweeps of the mean per launch
+    (HIP events on the launch stream); GB/s counts the bytes read and
+    written."""
+    out = []
+    sizes = [("headline_traffic", headline_bytes / 2)] + [(f"{mb:g}MB", mb * 1e6) for mb in (16.8, 26.9, 56.1, 213.0)] \
+        + [("1GiB", float(2 ** 30))]
+    for label, size in sizes:
+        nbytes = int(size) // 4096 * 4096
+        R = max(2, math.ceil(COLD_BYTES / (2 * nbytes)))
+        src = [torch.ones(nbytes // 8, dtype=torch.float64, device="cuda") for _ in range(R)]
+        dst = [torch.empty_like(src[0]) for _ in range(R)]
+        fvx.copy_many(dst, src)
+        ts = []
+        for _ in range(3):
+            tm = Timer(torch)
+            with tm:
+                fvx.copy_many(dst, src)
+            ts.append(tm.ms() / R)
+        t = sorted(ts)[1]
+        rec = {"size": label, "bytes_per_launch": 2 * nbytes, "us": t * 1e3, "GBs": 2 * nbytes / (t * 1e-3) / 1e9}
+        rec["frac_hbm"] = rec["GBs"] / HBM_PEAK_GBS
+        out.append(rec)
+        log(f"copy {label} ({2 * nbytes / 1e6:.1f} MB moved): {rec['us']:.2f} us, {rec['GBs']:.0f} GB/s "
+            f"({100 * rec['frac_hbm']:.1f}% of 8 TB/s)")
+        del src, dst
+        torch.cuda.empty_cache()
+    return out
 
 
 def graph_time(torch, calls):
@@ -887,7 +1240,7 @@ def generic_leg(fvx, inputs, torch, np):
     return out
 
 
-def pcg_leg(fvx, torch, op, D, rtol):
+def pcg_leg(fvx, torch, op, D, rtol, err_of=None):
     """Preconditioned CG on the benchmark's projection right-hand side: Jacobi
     and the Chebyshev polynomial (degree 8 on [2/300, 2], the library's
     defaults), FP64 and mixed precision; the best of 3 timed solves each."""
@@ -901,17 +1254,19 @@ def pcg_leg(fvx, torch, op, D, rtol):
         for _ in range(3):
             tm = Timer(torch)
             with tm:
-                _, st = op.solve(D, rtol=rtol, **kw)
+                X, st = op.solve(D, rtol=rtol, **kw)
             best = tm.ms() if best is None else min(best, tm.ms())
         o = op.solve_opts(**kw)
         out[name] = {"s_to_1e-8": best / 1e3, "iters": st["iters"], "outer": st["outer"],
                      "relres_true": st["relres_true"], "cheb_degree": int(o.cheb_degree),
                      "cheb_ratio": float(o.cheb_ratio)}
+        if err_of is not None and kw.get("precision") == fvx.MIXED:
+            out[name].update(err_of(X, st))
         log(f"pcg {name}: {best:.2f} ms, {st['iters']} iterations, true residual {st['relres_true']:.2e}")
     return out
 
 
-def amg_leg(fvx, torch, inputs, op, D, rtol):
+def amg_leg(fvx, torch, inputs, op, D, rtol, err_of=None):
     """CG preconditioned by one V-cycle of the aggregation multigrid (default
     options: Chebyshev degree 2 on [2/8, 2], pairwise aggregation with beta
     0.25, plane merging when the plane coupling dominates, coarsest level at
@@ -929,10 +1284,12 @@ def amg_leg(fvx, torch, inputs, op, D, rtol):
         for _ in range(3):
             tm = Timer(torch)
             with tm:
-                _, st = op.solve(D, rtol=rtol, amg=amg, **kw)
+                X, st = op.solve(D, rtol=rtol, amg=amg, **kw)
             best = tm.ms() if best is None else min(best, tm.ms())
         out[name] = {"s_to_1e-8": best / 1e3, "iters": st["iters"], "outer": st["outer"],
                      "relres_true": st["relres_true"]}
+        if err_of is not None and name == "mixed":
+            out[name].update(err_of(X, st))
         log(f"amg {name}: {best:.2f} ms, {st['iters']} iterations, true residual {st['relres_true']:.2e}")
     Z = torch.empty_like(D)
     out["vcycle_us"] = graph_time(torch, [lambda: amg.apply(D, Z)] * 10) * 1e3
@@ -1001,12 +1358,11 @@ def large_sweep(fvx, inputs, torch, np):
             t = lap_sweep(op, X, Y, torch, reps=2)
             Bk = spmm_bytes(op.nnz_b, op.n_b, k, v)
             nbytes = op.n_b * op.ld * v
-            fvx.copy(Y[0], X[0], nbytes)
+            fvx.copy_many(Y, X, nbytes)
             tc = Timer(torch)
             with tc:
                 for _ in range(2):
-                    for xx, yy in zip(X, Y):
-                        fvx.copy(yy, xx, nbytes)
+                    fvx.copy_many(Y, X, nbytes)
             t_copy = tc.ms() / (2 * R)
             rec = {"k": k, "dtype": name, "tile": list(tile), "cells": op.n_b * k, "bytes_per_launch": Bk,
                    "spmm_us": t * 1e3, "spmm_GBs": Bk / (t * 1e-3) / 1e9,
@@ -1057,6 +1413,17 @@ def batch_leg(fvx, inputs, torch, np, rtol):
         _, st = A.solve(b, rtol=rtol)
         csr.append(time.perf_counter() - t0)
         del A, b
+    # Error of every mixed result against its FP64 solution to 1e-13 (the
+    # batched FP64 CG), beside kappa_est (relres + relres*).
+    Xstar, sstar = fvx.solve_batch(opl, Bs, rtol=1e-13)
+    perr = []
+    for op, X, st, Xs, ss in zip(opl, Xs, sts, Xstar, sstar):
+        m = min(max(ss["iters"], 50), 2000)
+        kap = lanczos_kappa(op, inputs, torch, m)[0]
+        perr.append({"rel_err_vs_fp64": rel_err(torch, op, X, Xs), "kappa_est": kap, "lanczos_steps": m,
+                     "bound_kappa": kap * (st["relres_true"] + ss["relres_true"])})
+    log("batch mixed vs FP64 x*: max rel err {:.2e}, max err/bound {:.3f}".format(
+        max(e["rel_err_vs_fp64"] for e in perr), max(e["rel_err_vs_fp64"] / e["bound_kappa"] for e in perr)))
     # The same batch with the Chebyshev preconditioner (degree 8 on [2/300, 2]).
     kwc = dict(rtol=rtol, precision=fvx.MIXED, precond=fvx.PRECOND_CHEBYSHEV)
     fvx.solve_batch(opl, Bs, **kwc)
@@ -1070,8 +1437,11 @@ def batch_leg(fvx, inputs, torch, np, rtol):
         "problems": [{"base": f"{p['base'].nx}x{p['base'].ny}", "k": p["k"], "cells": o.n_b * o.k,
                       "tile_f64": list(t[0]), "tile_f32": list(t[1]), "cg_tile_f64": list(t[2]),
                       "cg_tile_f32": list(t[3]), "inner_iters": s["iters"],
-                      "outer": s["outer"], "relres_true": s["relres_true"], "single_s": ts, "csr3d_fp64_s": tc}
-                     for p, o, t, s, ts, tc in zip(probs, opl, tiles, sts, singles, csr)],
+                      "outer": s["outer"], "relres_true": s["relres_true"], "single_s": ts, "csr3d_fp64_s": tc,
+                      **e}
+                     for p, o, t, s, ts, tc, e in zip(probs, opl, tiles, sts, singles, csr, perr)],
+        "max_rel_err_vs_fp64": max(e["rel_err_vs_fp64"] for e in perr),
+        "max_err_over_bound": max(e["rel_err_vs_fp64"] / e["bound_kappa"] for e in perr),
         "cells": cells,
         "batch_s": batch_s,
         "sum_single_s": float(sum(singles)),
@@ -1114,14 +1484,24 @@ def airfoil_leg(fvx, inputs, torch, np):
     amg = fvx.Amg(op)
     res["amg_setup_s"] = time.perf_counter() - t0
     res["amg_levels"] = amg.levels()
+    mixed = {}
     for prec, pre, name in ((fvx.MIXED, 0, "mixed"), (fvx.F64, 0, "f64"), (fvx.MIXED, cheb, "mixed_chebyshev"),
                             (fvx.F64, cheb, "f64_chebyshev"), (fvx.MIXED, amg, "mixed_amg"), (fvx.F64, amg, "f64_amg")):
         kw = dict(amg=pre) if isinstance(pre, fvx.Amg) else dict(precond=pre)
         op.solve(B, rtol=rtol, precision=prec, **kw)
         t0 = time.perf_counter()
-        _, st = op.solve(B, rtol=rtol, precision=prec, **kw)
+        X, st = op.solve(B, rtol=rtol, precision=prec, **kw)
         res[f"solve_{name}"] = {"s": time.perf_counter() - t0, "iters": st["iters"], "outer": st["outer"],
                                 "relres_true": st["relres_true"]}
+        if prec == fvx.MIXED:
+            mixed[name] = (X, st)
+    # error of each mixed solve against the FP64 solution to 1e-13 (multigrid PCG)
+    errs, _ = mixed_errors(fvx, inputs, torch, op, B, mixed, steps=3000, star_kw=dict(amg=amg))
+    for name in mixed:
+        res[f"solve_{name}"].update(errs[name])
+    res["kappa_est"], res["lanczos_steps"], res["x_star"] = errs["kappa_est"], errs["lanczos_steps"], errs["x_star"]
+    log(f"airfoil mixed vs FP64 x*: " + ", ".join(f"{n} {errs[n]['rel_err_vs_fp64']:.2e} (bound "
+                                                  f"{errs[n]['bound_kappa']:.2e})" for n in mixed))
     del amg
     ptr, col, val = fvx.expand_csr(mesh, k, dz, fvx.PERIODIC_Z)
     A = fvx.CsrMatrix(ptr, col, val)
