@@ -374,6 +374,25 @@ int fvx_solve_bytes(const fvx_op *op, const fvx_solve_opts *opts, size_t *bytes)
 int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *opts,
                       void *ws, size_t ws_bytes, fvx_solve_stats *stats, void *stream);
 
+/* The same solve with no device allocation and no workspace argument, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is
+ * the library's built-in scratch, a device array of
+ * FVX_NOALLOC_SCRATCH_BYTES (128 MiB) that each device the library runs on
+ * holds until the process ends; enough for an FP64 or MIXED plain-CG solve of
+ * about 2.4 M unknowns (FP64) or 1.5 M (MIXED), e.g. 192 x 128 cells x 64
+ * planes in either precision.  A solve whose workspace (fvx_solve_bytes)
+ * exceeds the scratch fails with FVX_E_NOMEM before any device work.  B, X,
+ * opts, stats and the other results are those of fvx_poisson_solve with the
+ * same tiles (bitwise the same X).  The solve initialises every scratch byte
+ * it reads, so nothing carries over from the previous call; but all calls on
+ * one device share that device's scratch, so calls that overlap in time on
+ * one device (several host threads or streams) race and must be serialised
+ * by the caller.  Calls no hipMalloc/hipFree.  Synchronises `stream`. */
+#define FVX_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int fvx_poisson_solve_noalloc(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *opts,
+                              fvx_solve_stats *stats, void *stream);
+
 /* Many independent solves (uneven meshes and k) advanced together: every
  * CG phase of all problems still iterating is one launch (per group of
  * problems sharing a kernel instance: block size, vector width, coupling and

@@ -431,6 +431,17 @@ class Operator:
         check(rc, "fvx_poisson_solve", allow)
         return X, st.as_dict()
 
+    def solve_noalloc(self, B, X=None, stream=None, allow_not_converged=False, **kw):
+        """The same solve on the library's built-in device scratch
+        (fvx_poisson_solve_noalloc): no workspace is allocated."""
+        opts = self.solve_opts(**kw)
+        if X is None:
+            X = self.zeros()
+        st = SolveStats()
+        rc = lib().fvx_poisson_solve_noalloc(self._h, _ptr(B), _ptr(X), C.byref(opts), C.byref(st), _stream(stream))
+        check(rc, "fvx_poisson_solve_noalloc", (0, 1) if allow_not_converged else (0,))
+        return X, st.as_dict()
+
     def ns_step(self, U, Uf, Wz, P, dt, nu, visc=None, stream=None, allow_not_converged=False, **kw):
         """One Heun-RK3 projection step (fvx_ns_step): U = [u, v, w] device
         [n_b][ld] tensors, Uf/Wz face velocities, P pressure; all updated in

@@ -19,6 +19,7 @@ GUESS_ZERO, GUESS_GIVEN, GUESS_NET = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_AMG = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
 class OpDesc(C.Structure):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "fvx_solve_bytes": (C.c_int, [_vp, _P(SolveOpts), _P(C.c_size_t)]),
     "fvx_poisson_solve": (C.c_int, [_vp, _vp, _vp, _P(SolveOpts), _vp, C.c_size_t,
                                     _P(SolveStats), _vp]),
+    "fvx_poisson_solve_noalloc": (C.c_int, [_vp, _vp, _vp, _P(SolveOpts), _P(SolveStats), _vp]),
     "fvx_solve_batch_bytes": (C.c_int, [C.c_int, _P(_vp), _P(SolveOpts), _P(C.c_size_t)]),
     "fvx_poisson_solve_batch": (C.c_int, [C.c_int, _P(_vp), _P(_vp), _P(_vp), _P(SolveOpts), _vp, C.c_size_t,
                                           _vp, _vp]),

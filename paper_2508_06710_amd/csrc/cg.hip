@@ -19,6 +19,7 @@
 // convergence return at once.
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "amg.h"
 
@@ -1265,6 +1266,31 @@ int solve_batch(int n, const fvx_op *const *ops, const double *const *B, double 
     return worst;
 }
 
+// The scratch of fvx_poisson_solve_noalloc: a file-scope device array of a
+// fixed size (each device holds its own copy for the life of the process).
+// Host code never passes the array's name to a kernel or a copy: the name is
+// a host-side stand-in, not a device address.  The device address is looked
+// up once per device, with that device current, and kept.
+__device__ __align__(256) char scratch[FVX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+void *noalloc_scratch() {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    FVX_HIP(hipGetDevice(&dev));
+    FVX_REQUIRE(dev >= 0 && dev < kMaxDevices, FVX_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        FVX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        FVX_REQUIRE(p && reinterpret_cast<uintptr_t>(p) % 256 == 0, FVX_E_HIP, "scratch address lookup failed");
+        addr[dev] = p;
+    }
+    return addr[dev];
+}
+
 }  // namespace
 
 double guess_residual_ratio(const fvx_op *op, const double *B, const double *X, void *ws, hipStream_t s) {
@@ -1342,6 +1368,31 @@ int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_so
         const double *Bs[1] = {B};
         double *Xs[1] = {X};
         const int rc = fvx::solve_batch(1, ops, Bs, Xs, o, ws, ws_bytes, stats, fvx::as_stream(stream));
+        if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (rc < 0) throw fvx::Error(rc, fvx_status_str(rc));
+        return rc;
+    });
+}
+
+int fvx_poisson_solve_noalloc(const fvx_op *op, const double *B, double *X, const fvx_solve_opts *o,
+                              fvx_solve_stats *stats, void *stream) {
+    return guard([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        FVX_REQUIRE(op && o, FVX_E_ARG, "NULL argument");
+        const fvx_op *ops[1] = {op};
+        const fvx::Precond pc = fvx::make_precond(o);
+        fvx::check_opts(op, o);
+        const size_t need =
+            fvx::batch_layout(1, ops, o->precision == FVX_MIXED, pc.kind == 2, pc.kind == 3 ? o->amg : nullptr).total;
+        FVX_REQUIRE(need <= FVX_NOALLOC_SCRATCH_BYTES, FVX_E_NOMEM,
+                    "fvx_poisson_solve_noalloc: this solve needs " + std::to_string(need) +
+                        " bytes of scratch; the library's built-in scratch holds " +
+                        std::to_string(size_t(FVX_NOALLOC_SCRATCH_BYTES)));
+        void *ws = fvx::noalloc_scratch();
+        const double *Bs[1] = {B};
+        double *Xs[1] = {X};
+        const int rc = fvx::solve_batch(1, ops, Bs, Xs, o, ws, FVX_NOALLOC_SCRATCH_BYTES, stats,
+                                        fvx::as_stream(stream));
         if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc < 0) throw fvx::Error(rc, fvx_status_str(rc));
         return rc;
