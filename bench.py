@@ -143,7 +143,7 @@ def rotating_sets(op, fvx, torch, x_rows):
 
 
 class Plug:
-    """About 1 ms of streaming copies (3 x 1 GiB) put on the stream ahead of a
+    """About 2 ms of streaming copies (6 x 1 GiB) put on the stream ahead of a
     timed sweep: the sweep's launches queue up behind it, so they run back to
     back on the GPU whatever the host's launch rate -- also under a kernel
     tracer, whose per-launch host overhead (about 13 us here) would
@@ -156,14 +156,14 @@ class Plug:
         self.b = torch.empty_like(self.a)
 
     def __call__(self):
-        for _ in range(3):
+        for _ in range(6):
             self.fvx.copy(self.b, self.a)
 
 
 def lap_sweep(op, X, Y, torch, reps=1, plug=None):
     """Mean time per lap SpMM over the rotating pairs (launched from C),
     HIP events around the sweep on the launch stream; with a plug, its
-    copies run ahead of the first event."""
+    copies run ahead of the first event.""" 
     if plug is not None:
         plug()
     t = Timer(torch)
@@ -411,7 +411,9 @@ def summarize_counters(fetch_dir, write_dir, flops_dir, out=COUNTER_FILE):
              "write_bytes_per_launch": w, "traffic_over_algorithmic": (f + w) / alg}
         if name in pk:
             lst = pk[name]
-            e["fp64_flops_counted"] = med(lst, "SQ_INSTS_VALU_FLOPS_FP64")
+            # the counter adds each FP64 VALU instruction's flops per lane (FMA 2,
+            # ADD/MUL 1) once per wave instruction: times 64 lanes
+            e["fp64_flops_counted"] = 64 * med(lst, "SQ_INSTS_VALU_FLOPS_FP64")
             e["fp64_flops_from_insts"] = 64 * (med(lst, "SQ_INSTS_VALU_ADD_F64") + med(lst, "SQ_INSTS_VALU_MUL_F64")
                                                + 2 * med(lst, "SQ_INSTS_VALU_FMA_F64"))
             e["fp64_flops_algorithmic"] = spmm_flops(nnz_b, nb, k)

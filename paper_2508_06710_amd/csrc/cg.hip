@@ -6,9 +6,15 @@
 //      iteration (every block, fixed order) into rho, beta and the
 //      convergence test; the body forms p' = r + beta p on the fly for every
 //      row it gathers, stores p' for its own rows (p is double-buffered), and
-//      computes q = L p' with the partial dot products p'.q;
-//   B (update):  prologue sums the p'.q partials into alpha; the body updates
+//      computes q = L p' for the partial dot products p'.q -- q itself is not
+//      stored;
+//   B (update):  prologue sums the p'.q partials into alpha; the body forms
+//      q = L p' again from the stored p' (gathering p' as A gathered r and
+//      p, with the same operations, so it is A's q bit for bit) and updates
 //      x += alpha p', r -= alpha A p' (= r + alpha q) with partial r.r.
+// Recomputing q instead of storing and re-reading it moves 8 vectors per
+// iteration instead of 10 (A: r, p read, p' written; B: p', x, r read, x, r
+// written); the SpMM's arithmetic is far below the bandwidth roofline.
 // All scalars stay on the device; every block derives them from the same
 // partials in the same order, so results are deterministic and no kernel
 // waits on another block of its own grid.  Groups are the k columns when the
@@ -127,8 +133,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, 
 // stored Chebyshev output (passed as r) otherwise.
 template <typename T, int V, bool Z, int WT, int PRE>
 __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, Src rz,
-                       const T *__restrict__ r, const T *__restrict__ p_old, T *__restrict__ p_new,
-                       T *__restrict__ q) {
+                       const T *__restrict__ r, const T *__restrict__ p_old, T *__restrict__ p_new) {
     if (d.st->done) return;
     __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
@@ -210,7 +215,6 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
         vec_t<T, V> pn;
         const vec_t<T, V> acc = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, row, c0, sub, lpr, single, pn);
         stv_masked<T, V>(p_new + row * a.ld + c0, pn, a.k - c0);
-        stv_masked<T, V>(q + row * a.ld + c0, acc, a.k - c0);
 #pragma unroll
         for (int u = 0; u < V; ++u)
             if (c0 + u < a.k) c[0][u] += double(pn[u]) * double(acc[u]);
@@ -219,11 +223,12 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, vb.nblk, lds);
 }
 
-// B: alpha from the p.q partials; x += alpha p; r += alpha q; partial r.r
-// (and, with the Jacobi preconditioner, r.z with z = D^-1 r).
-template <typename T, int V, int PRE>
+// B: alpha from the p.q partials; q = L p from the stored p (gathered);
+// x += alpha p; r += alpha q; partial r.r (and, with the Jacobi
+// preconditioner, r.z with z = D^-1 r).
+template <typename T, int V, bool Z, int WT, int PRE>
 __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
-                       T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q) {
+                       T *__restrict__ r, const T *__restrict__ p) {
     if (d.st->done) return;
     __shared__ double lds[kMaxPercolBlock * kMaxV];
     __shared__ double tot[kMaxGroups];
@@ -254,11 +259,13 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
         }
         return;
     }
+    const bool single = lpr * V >= a.k;
     double c[1][V] = {}, cz[1][V] = {};
     FOR_ROWS {
         const int64_t o = row * a.ld + c0;
+        vec_t<T, V> pv;
+        const vec_t<T, V> qv = lap_row<T, V, Z, WT>(a.A, p, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, pv);
         vec_t<T, V> xv = ldv<T, V>(x + o), rv = ldv<T, V>(r + o);
-        const vec_t<T, V> pv = ldv<T, V>(p + o), qv = ldv<T, V>(q + o);
         const double di = PRE == 1 ? double(a.A.dinv[row]) : 0.0;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
@@ -419,10 +426,10 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restric
     T *src = PRE == 2 ? I.zf : I.r;
     T *pold = it == 0 ? src : ((it & 1) ? I.p0 : I.p1);
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_a<T, V, Z, WT, PRE>(a, d, vb, it, I.rr, I.bb, I.rz, src, pold, pnew, I.q);
+    b_cg_a<T, V, Z, WT, PRE>(a, d, vb, it, I.rr, I.bb, I.rz, src, pold, pnew);
 }
 
-template <typename T, int V, int PRE>
+template <typename T, int V, bool Z, int WT, int PRE>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n, int it) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     const CgDev d = I.d;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_b<T, V, PRE>(a, d, vb, it, I.pq, I.x, I.r, pnew, I.q);
+    b_cg_b<T, V, Z, WT, PRE>(a, d, vb, it, I.pq, I.x, I.r, pnew);
 }
 
 // Chebyshev step j >= 1 for every item: gathers z_j from buffer (j - 2) & 1
@@ -934,6 +941,7 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
                     constexpr int PRE = decltype(Pt)::value;
                     by_v<T>(L.key.vec, [&](auto Vt) {
                         constexpr int V = decltype(Vt)::value;
+                        constexpr int PB = PRE == 1 ? 1 : 0;
                         by_width(L.key.w, [&](auto Wt) {
                             constexpr int WT = decltype(Wt)::value;
                             if (L.key.z)
@@ -944,8 +952,15 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
                                                    0, s, dev, L.n, it);
                         });
                         fold_percol(L, 0);
-                        hipLaunchKernelGGL((kb_cg_b<T, V, PRE == 1 ? 1 : 0>), dim3(L.blocks), dim3(L.key.block), 0, s,
-                                           dev, L.n, it);
+                        by_width(L.key.w, [&](auto Wt) {
+                            constexpr int WT = decltype(Wt)::value;
+                            if (L.key.z)
+                                hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB>), dim3(L.blocks), dim3(L.key.block),
+                                                   0, s, dev, L.n, it);
+                            else
+                                hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB>), dim3(L.blocks), dim3(L.key.block),
+                                                   0, s, dev, L.n, it);
+                        });
                         fold_percol(L, 1);
                         if (PRE == 1) fold_percol(L, 2);
                     });

@@ -115,10 +115,14 @@ struct DirLoad {
     const T *__restrict__ P;
     int ld;
     vec_t<T, V> beta;  // beta of this lane's V columns (equal entries when global)
+    // one fused multiply-add per element, in the vector and the scalar form
+    // alike: a neighbour's p' formed here equals the p' its owner stores
     __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const {
-        return ldv<T, V>(R + row * ld + c0) + beta * ldv<T, V>(P + row * ld + c0);
+        return __builtin_elementwise_fma(beta, ldv<T, V>(P + row * ld + c0), ldv<T, V>(R + row * ld + c0));
     }
-    __device__ __forceinline__ T scalar(int64_t row, int l) const { return R[row * ld + l] + beta[0] * P[row * ld + l]; }
+    __device__ __forceinline__ T scalar(int64_t row, int l) const {
+        return __builtin_elementwise_fma(beta[0], P[row * ld + l], R[row * ld + l]);
+    }
 };
 
 // Direction of preconditioned CG with the Jacobi preconditioner formed on the
@@ -131,10 +135,10 @@ struct DirLoadJ {
     int ld;
     vec_t<T, V> beta;
     __device__ __forceinline__ vec_t<T, V> vec(int64_t row, int c0) const {
-        return Dinv[row] * ldv<T, V>(R + row * ld + c0) + beta * ldv<T, V>(P + row * ld + c0);
+        return __builtin_elementwise_fma(beta, ldv<T, V>(P + row * ld + c0), Dinv[row] * ldv<T, V>(R + row * ld + c0));
     }
     __device__ __forceinline__ T scalar(int64_t row, int l) const {
-        return Dinv[row] * R[row * ld + l] + beta[0] * P[row * ld + l];
+        return __builtin_elementwise_fma(beta[0], P[row * ld + l], Dinv[row] * R[row * ld + l]);
     }
 };
 
