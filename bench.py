@@ -756,7 +756,7 @@ def main():
         b_plane = op.to_planes(D)
         full["cpu_baseline"] = cpu_baseline(inputs, __import__("oracle"), b_plane, k, rtol)
     full.update(legs)
-    path = os.path.join(ROOT, "gpurun_out", "bench_full.json")
+    path = os.path.join(ROOT, "gpurun_out", "bench_profile.json" if args.profile else "bench_full.json")
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as fh:

@@ -253,9 +253,10 @@ class Operator:
         check(lib().fvx_op_get_cg_tile(self._h, dtype, C.byref(t)), "fvx_op_get_cg_tile")
         return t.as_tuple()
 
-    def set_cg_tile(self, vec=0, lanes_per_row=1, block=0, xcd_remap=1, max_blocks=0, dtype=F64):
-        """CG launch tile (block 0 restores the default)."""
-        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), 0, 0)
+    def set_cg_tile(self, vec=0, lanes_per_row=1, block=0, xcd_remap=1, max_blocks=0, lines=0, dtype=F64):
+        """CG launch tile (block 0 restores the default); lines = 1 selects the
+        line tiles of the iteration kernels on Cartesian bases."""
+        t = Tile(int(vec), int(lanes_per_row), int(block), int(xcd_remap), int(max_blocks), int(lines), 0)
         check(lib().fvx_op_set_cg_tile(self._h, dtype, C.byref(t)), "fvx_op_set_cg_tile")
 
     def tune_cg(self, dtype=F64, iters=40, max_results=64, stream=None):
@@ -286,7 +287,7 @@ class Operator:
                 cache = json.load(fh)
         if key in cache:
             t = cache[key]["tile"]
-            self.set_cg_tile(t[0], t[1], t[2], t[3], t[4], dtype=dtype)
+            self.set_cg_tile(t[0], t[1], t[2], t[3], t[4], t[5] if len(t) > 5 else 0, dtype=dtype)
             return tuple(t), "cache"
         res = self.tune_cg(dtype=dtype, iters=iters)
         best = self.get_cg_tile(dtype)

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_cg_init(RowArgs<T> a, CgDev d, 
 // which replaces r.r in rho = r.z and beta; the stopping test stays on r.r.
 // The direction is p' = z + beta p: z = D^-1 r on the fly for Jacobi, the
 // stored Chebyshev output (passed as r) otherwise.
-template <typename T, int V, bool Z, int WT, int PRE>
+template <typename T, int V, bool Z, int WT, int PRE, bool LN>
 __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src rr, Src bb, Src rz,
                        const T *__restrict__ r, const T *__restrict__ p_old, T *__restrict__ p_new) {
     if (d.st->done) return;
@@ -203,8 +203,8 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
     if (blk == 0 && threadIdx.x == 0) d.st->iter = it;
     const bool single = lpr * V >= a.k;
     double c[1][V] = {};
-    FOR_ROWS {
-        using Load = std::conditional_t<PRE == 1, DirLoadJ<T, V>, DirLoad<T, V>>;
+    using Load = std::conditional_t<PRE == 1, DirLoadJ<T, V>, DirLoad<T, V>>;
+    auto loader = [&](int c0) {
         Load in;
         if constexpr (PRE == 1)
             in = Load{r, p_old, a.A.dinv, a.ld, vec_t<T, V>(0)};
@@ -212,21 +212,40 @@ __device__ void b_cg_a(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src r
             in = Load{r, p_old, a.ld, vec_t<T, V>(0)};
 #pragma unroll
         for (int u = 0; u < V; ++u) in.beta[u] = T(s_beta[d.percol ? (c0 + u < a.k ? c0 + u : 0) : 0]);
-        vec_t<T, V> pn;
-        const vec_t<T, V> acc = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, row, c0, sub, lpr, single, pn);
+        return in;
+    };
+    auto emit = [&](int64_t row, int c0, const vec_t<T, V> &pn, const vec_t<T, V> &acc) {
         stv_masked<T, V>(p_new + row * a.ld + c0, pn, a.k - c0);
 #pragma unroll
         for (int u = 0; u < V; ++u)
             if (c0 + u < a.k) c[0][u] += double(pn[u]) * double(acc[u]);
+    };
+    if constexpr (LN) {
+        FOR_LINE_TILES {
+            vec_t<T, V> acc[kCgLines], pn[kCgLines];
+            int64_t rows[kCgLines];
+            bool ok[kCgLines];
+            cart_lines<T, V, Z>(a, loader(sub * V), uint32_t(t), uint32_t(grp), sub, lpr, acc, pn, rows, ok);
+#pragma unroll
+            for (int q = 0; q < kCgLines; ++q)
+                if (ok[q]) emit(rows[q], sub * V, pn[q], acc[q]);
+        }
+    } else {
+        FOR_ROWS {
+            vec_t<T, V> pn;
+            const vec_t<T, V> acc =
+                lap_row_ld<T, V, Z, WT>(a.A, loader(c0), a.n_b, a.k, a.W, row, c0, sub, lpr, single, pn);
+            emit(row, c0, pn, acc);
+        }
+        END_ROWS
     }
-    END_ROWS
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_a, blk, vb.nblk, lds);
 }
 
 // B: alpha from the p.q partials; q = L p from the stored p (gathered);
 // x += alpha p; r += alpha q; partial r.r (and, with the Jacobi
 // preconditioner, r.z with z = D^-1 r).
-template <typename T, int V, bool Z, int WT, int PRE>
+template <typename T, int V, bool Z, int WT, int PRE, bool LN>
 __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src pq, T *__restrict__ x,
                        T *__restrict__ r, const T *__restrict__ p) {
     if (d.st->done) return;
@@ -261,11 +280,9 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
     }
     const bool single = lpr * V >= a.k;
     double c[1][V] = {}, cz[1][V] = {};
-    FOR_ROWS {
+    auto update = [&](int64_t row, int c0, const vec_t<T, V> &pv, const vec_t<T, V> &qv, vec_t<T, V> xv,
+                      vec_t<T, V> rv) {
         const int64_t o = row * a.ld + c0;
-        vec_t<T, V> pv;
-        const vec_t<T, V> qv = lap_row<T, V, Z, WT>(a.A, p, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, pv);
-        vec_t<T, V> xv = ldv<T, V>(x + o), rv = ldv<T, V>(r + o);
         const double di = PRE == 1 ? double(a.A.dinv[row]) : 0.0;
 #pragma unroll
         for (int u = 0; u < V; ++u) {
@@ -278,8 +295,31 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
         }
         stv_masked<T, V>(x + o, xv, a.k - c0);
         stv_masked<T, V>(r + o, rv, a.k - c0);
+    };
+    if constexpr (LN) {
+        FOR_LINE_TILES {
+            vec_t<T, V> qv[kCgLines], pv[kCgLines], xv[kCgLines], rv[kCgLines];
+            int64_t rows[kCgLines];
+            bool ok[kCgLines];
+            cart_lines<T, V, Z>(a, PlainLoad<T, V>{p, a.ld}, uint32_t(t), uint32_t(grp), sub, lpr, qv, pv, rows, ok);
+#pragma unroll
+            for (int q = 0; q < kCgLines; ++q) {
+                xv[q] = ldv<T, V>(x + rows[q] * a.ld + sub * V);
+                rv[q] = ldv<T, V>(r + rows[q] * a.ld + sub * V);
+            }
+#pragma unroll
+            for (int q = 0; q < kCgLines; ++q)
+                if (ok[q]) update(rows[q], sub * V, pv[q], qv[q], xv[q], rv[q]);
+        }
+    } else {
+        FOR_ROWS {
+            const int64_t o = row * a.ld + c0;
+            vec_t<T, V> pv;
+            const vec_t<T, V> qv = lap_row<T, V, Z, WT>(a.A, p, a.n_b, a.k, a.ld, a.W, row, c0, sub, lpr, single, pv);
+            update(row, c0, pv, qv, ldv<T, V>(x + o), ldv<T, V>(r + o));
+        }
+        END_ROWS
     }
-    END_ROWS
     write_partials<1, V>(c, sub, lpr, G, d.percol, d.part_b, blk, vb.nblk, lds);
     if constexpr (PRE == 1) {
         __syncthreads();
@@ -415,7 +455,7 @@ __device__ __forceinline__ int find_item(const BItem<T> *items, int n) {
 
 // p' of iteration it: p0 on even iterations, p1 on odd ones; the previous
 // direction is r at it = 0 (p' = r + 0 r) and the other buffer afterwards.
-template <typename T, int V, bool Z, int WT, int PRE>
+template <typename T, int V, bool Z, int WT, int PRE, bool LN>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restrict__ items, int n, int it) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
@@ -426,10 +466,10 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restric
     T *src = PRE == 2 ? I.zf : I.r;
     T *pold = it == 0 ? src : ((it & 1) ? I.p0 : I.p1);
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_a<T, V, Z, WT, PRE>(a, d, vb, it, I.rr, I.bb, I.rz, src, pold, pnew);
+    b_cg_a<T, V, Z, WT, PRE, LN>(a, d, vb, it, I.rr, I.bb, I.rz, src, pold, pnew);
 }
 
-template <typename T, int V, bool Z, int WT, int PRE>
+template <typename T, int V, bool Z, int WT, int PRE, bool LN>
 __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n, int it) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
@@ -438,7 +478,7 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restric
     const CgDev d = I.d;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *pnew = (it & 1) ? I.p1 : I.p0;
-    b_cg_b<T, V, Z, WT, PRE>(a, d, vb, it, I.pq, I.x, I.r, pnew);
+    b_cg_b<T, V, Z, WT, PRE, LN>(a, d, vb, it, I.pq, I.x, I.r, pnew);
 }
 
 // Chebyshev step j >= 1 for every item: gathers z_j from buffer (j - 2) & 1
@@ -527,6 +567,16 @@ fvx_tile cg_tile(const fvx_op *op) {
                 "independent-plane solve: k exceeds one pass of a row group");
     t.block = std::max(std::min(t.block, op->percol ? kMaxPercolBlock : kMaxCgBlock), t.lanes_per_row);
     return t;
+}
+
+// Line tiles (stage_lds of a CG tile) apply on a Cartesian 5-point base
+// with its coefficient record, when one pass of a row group covers the k
+// columns and the grid has at least kCgLines lines; elsewhere the tile's
+// row mapping is used.
+template <typename T>
+bool cg_lines_ok(const fvx_op *op, const fvx_tile &t) {
+    return op->stencil == 7 && dev<T>(op).cart != nullptr && op->W == 4 && op->grid_nx > 0 &&
+           op->grid_ny >= kCgLines && t.lanes_per_row * t.vec >= op->k;
 }
 
 CgDev carve_cg(Carve &c, const fvx_op *op) {
@@ -662,6 +712,14 @@ struct Ctx {
     explicit Ctx(const fvx_op *op) {
         t = cg_tile<T>(op);
         a = row_args<T>(op, op->n_b, g, t, max_blocks_for(op));
+        if (t.stage_lds && cg_lines_ok<T>(op, t)) {
+            // the iteration kernels take line tiles; the other kernels of the
+            // solve keep the row tiles (same blocks, same partials layout)
+            a.lines = kCgLines;
+            a.n_xtiles = uint32_t(ceil_div(op->grid_nx, a.rows_per_tile));
+            a.n_ltiles = a.n_xtiles * uint32_t(ceil_div(op->grid_ny, kCgLines));
+            a.ltiles_per_block = ceil_div(int64_t(a.n_ltiles), int64_t(g.n_blocks));
+        }
         grid = dim3(g.n_blocks);
         block = dim3(t.block);
     }
@@ -753,8 +811,10 @@ void by_pre(int kind, F &&f) {
 // Batched launches group jobs whose kernels share one instance: block size,
 // vector width, plane coupling and ELL width.
 struct GroupKey {
-    int block, vec, z, w;
-    bool operator==(const GroupKey &o) const { return block == o.block && vec == o.vec && z == o.z && w == o.w; }
+    int block, vec, z, w, lines;
+    bool operator==(const GroupKey &o) const {
+        return block == o.block && vec == o.vec && z == o.z && w == o.w && lines == o.lines;
+    }
 };
 
 // Runs the CGs of all jobs.  Each job starts exactly as a single solve would
@@ -814,7 +874,7 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
         I.pq = d.percol ? Src{d.tot + 2 * d.G, 1} : Src{d.part_a, nb};
         I.rz = d.percol ? Src{d.tot + 4 * d.G, 1} : Src{d.part_b + size_t(2) * nb * d.G, nb};
         I.nblk = nb;
-        keys[j] = GroupKey{c.t.block, c.t.vec, int(J.op->zfaces), J.op->W};
+        keys[j] = GroupKey{c.t.block, c.t.vec, int(J.op->zfaces), J.op->W, c.a.lines};
     }
     // Order jobs by group, give each a block range aligned to 8, upload.
     std::vector<int> order(jobs.size());
@@ -942,24 +1002,39 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
                     by_v<T>(L.key.vec, [&](auto Vt) {
                         constexpr int V = decltype(Vt)::value;
                         constexpr int PB = PRE == 1 ? 1 : 0;
+                        const dim3 gb(L.blocks), bb(L.key.block);
+                        // line tiles exist for the compiled width 4 (the Cartesian
+                        // 5-point base) only
                         by_width(L.key.w, [&](auto Wt) {
                             constexpr int WT = decltype(Wt)::value;
-                            if (L.key.z)
-                                hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE>), dim3(L.blocks), dim3(L.key.block),
-                                                   0, s, dev, L.n, it);
-                            else
-                                hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE>), dim3(L.blocks), dim3(L.key.block),
-                                                   0, s, dev, L.n, it);
+                            const bool ln = WT == 4 && L.key.lines;
+                            if (L.key.z) {
+                                if (ln)
+                                    hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n, it);
+                                else
+                                    hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, false>), gb, bb, 0, s, dev, L.n, it);
+                            } else {
+                                if (ln)
+                                    hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n, it);
+                                else
+                                    hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, false>), gb, bb, 0, s, dev, L.n, it);
+                            }
                         });
                         fold_percol(L, 0);
                         by_width(L.key.w, [&](auto Wt) {
                             constexpr int WT = decltype(Wt)::value;
-                            if (L.key.z)
-                                hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB>), dim3(L.blocks), dim3(L.key.block),
-                                                   0, s, dev, L.n, it);
-                            else
-                                hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB>), dim3(L.blocks), dim3(L.key.block),
-                                                   0, s, dev, L.n, it);
+                            const bool ln = WT == 4 && L.key.lines;
+                            if (L.key.z) {
+                                if (ln)
+                                    hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n, it);
+                                else
+                                    hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, false>), gb, bb, 0, s, dev, L.n, it);
+                            } else {
+                                if (ln)
+                                    hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n, it);
+                                else
+                                    hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, false>), gb, bb, 0, s, dev, L.n, it);
+                            }
                         });
                         fold_percol(L, 1);
                         if (PRE == 1) fold_percol(L, 2);
@@ -1459,7 +1534,12 @@ int fvx_op_set_cg_tile(fvx_op *op, int dtype, const fvx_tile *tile) {
             op->cg_tile[dtype] = fvx_tile{};
             return FVX_OK;
         }
-        fvx::check_tile(op, dtype, *tile);
+        // stage_lds of a CG tile selects line tiles (no LDS stage): validate
+        // the rest like an SpMM tile
+        fvx_tile chk = *tile;
+        FVX_REQUIRE(chk.stage_lds == 0 || chk.stage_lds == 1, FVX_E_ARG, "CG tile stage_lds (line tiles) must be 0 or 1");
+        chk.stage_lds = 0;
+        fvx::check_tile(op, dtype, chk);
         FVX_REQUIRE(tile->block <= (op->percol ? fvx::kMaxPercolBlock : fvx::kMaxCgBlock), FVX_E_ARG,
                     "CG tile block too large (512, or 256 for independent planes)");
         op->cg_tile[dtype] = *tile;
@@ -1519,13 +1599,18 @@ int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, voi
             if (op->percol && block > fvx::kMaxPercolBlock) continue;
             if (block < base.lanes_per_row) continue;
             for (int remap : {1, 0})
-                for (int cap : {1024, 512, 2048}) {
-                    fvx_tile t = base;
-                    t.block = block;
-                    t.xcd_remap = remap;
-                    t.max_blocks = cap;
-                    cands.push_back(t);
-                }
+                for (int cap : {1024, 512, 2048})
+                    for (int lines : {0, 1}) {
+                        fvx_tile t = base;
+                        t.block = block;
+                        t.xcd_remap = remap;
+                        t.max_blocks = cap;
+                        t.stage_lds = lines;
+                        t.nt_store = 0;
+                        const bool ok = dtype == FVX_F64 ? fvx::cg_lines_ok<double>(op, t) : fvx::cg_lines_ok<float>(op, t);
+                        if (lines && !ok) continue;
+                        cands.push_back(t);
+                    }
         }
         if (cands.empty()) cands.push_back(base);
         const fvx_tile keep = op->cg_tile[dtype];
@@ -1544,7 +1629,9 @@ int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, voi
                 }
                 if (results && count < max_results) results[count] = fvx_tune_result{t, us};
                 ++count;
-                if (us < best_us) {
+                // line tiles split launch groups in a batch and use twice the
+                // registers: taken only on a clear win over the best so far
+                if (us < (t.stage_lds ? 0.95 : 1.0) * best_us) {
                     best_us = us;
                     best = t;
                 }

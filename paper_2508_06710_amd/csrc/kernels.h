@@ -568,6 +568,12 @@ struct RowArgs {
     int k, ld, W, Wd, lpr, rows_per_tile, remap;
     int64_t tiles_per_block;
     int64_t F_b;
+    // Line-blocked tiles of the CG kernels on a Cartesian base (0: row
+    // tiles): a tile is rows_per_tile cells along x times `lines` grid lines,
+    // n_xtiles tiles along x, n_ltiles in all, ltiles_per_block per block.
+    int lines;
+    uint32_t n_xtiles, n_ltiles;
+    int64_t ltiles_per_block;
 };
 
 template <typename T>
@@ -588,6 +594,9 @@ inline RowArgs<T> row_args(const fvx_op *op, int64_t n_rows, RowGrid &g, const f
     a.remap = t.xcd_remap;
     a.tiles_per_block = g.tiles_per_block;
     a.F_b = op->F_b;
+    a.lines = 0;
+    a.n_xtiles = a.n_ltiles = 0;
+    a.ltiles_per_block = 0;
     return a;
 }
 

@@ -267,3 +267,38 @@ def test_cg_tiles_and_tuner(precision):
     assert c.op.get_cg_tile(dt)[2] == 256
     with pytest.raises(fvx.FvxError):
         c.op.set_cg_tile(vec, 8, 1024, 1, 0, dtype=dt)
+
+
+@pytest.mark.parametrize("spec,k,coupling", [
+    (inputs.channel_base(40, 24), 16, 1),                                   # ragged tiles along x
+    (inputs.convection_base(12, 22), 8, 1),                                 # walls on all sides, ny % 4 = 2
+    (inputs.CartSpec(10, 9, 1.0, 0.0, 1.0, 0.3, True, True), 4, 1),        # periodic in x and y
+    (inputs.channel_base(13, 9), 5, 0),                                     # independent planes, k = 5
+    (inputs.channel_base(24, 16), 1, 1),                                    # one plane: no coupling term
+])
+@pytest.mark.parametrize("kw", [{}, {"precond": 1}, {"precond": 2, "cheb_degree": 3, "cheb_ratio": 30.0},
+                                {"precision": 2}])
+def test_cg_line_tiles(spec, k, coupling, kw):
+    """The CG iteration kernels on line tiles (stage_lds = 1 of a CG tile: a
+    row group takes 4 grid lines of one cell column) against the row tiles:
+    the same products in another order of the FP64 partial sums, so the true
+    residual by the oracle's matrix meets the tolerance, the iteration count
+    is the row tiles' within one, and the solve is bitwise repeatable."""
+    c = Case(spec, k, coupling=coupling, with_f32=True)
+    fvx = c.fvx
+    prec = kw.get("precision", fvx.F64)
+    dt = fvx.F32 if prec == fvx.MIXED else fvx.F64
+    b = inputs.rhs_uniform(41, c.m3.N)
+    B = c.op.to_rows(b)
+    vec = c.op.get_cg_tile(dt)[0]
+    out = {}
+    for lines in (0, 1):
+        c.op.set_cg_tile(vec, 1, 128, 1, 0, lines, dtype=dt)
+        assert c.op.get_cg_tile(dt)[5] == lines
+        X, st = c.op.solve(B, rtol=1e-10, **kw)
+        X2, st2 = c.op.solve(B, rtol=1e-10, **kw)
+        assert torch.equal(X, X2) and st["iters"] == st2["iters"]
+        assert max(_true_relres(c, c.op.to_planes(X), b)) <= 1e-10 * 1.05
+        out[lines] = st["iters"]
+    assert abs(out[1] - out[0]) <= 1, out
+    c.op.set_cg_tile(block=0, dtype=dt)
