@@ -108,6 +108,24 @@ def stencil_bytes(n_b, k, stencil, v=8):
     return 32 * n_b + v * vals * n_b + 2 * v * n_b * k
 
 
+# Section 2's closed forms, as measurement bookkeeping (the tests pin the
+# oracle's copy of them against independent values; the benchmark keeps its
+# own so that no leg but the CPU baseline runs the oracle).
+def ai_eq2(nnz, n_r, n_c, m):
+    """Eq. 2: flops (2 nnz + 1) m over bytes 12 nnz + 4 (n_r + 1) + m (8 n_r + 8 n_c + 8)."""
+    return (2 * nnz + 1) * m / (12 * nnz + 4 * (n_r + 1) + m * (8 * n_r + 8 * n_c + 8))
+
+
+def p_ub_eq3a(nnz, n_r, n_c, m):
+    """Eq. 3a (= I(m) / I(1) of Eq. 2)."""
+    return m * (3 * (nnz + n_r + 1) + 2 * n_c) / (3 * nnz + (1 + 2 * m) * (n_r + 1) + 2 * m * n_c)
+
+
+def p_lb_eq3b(nnz, n_r, m):
+    """Eq. 3b (no reuse of the gathered input)."""
+    return m * (5 * nnz + 3 * (n_r + 1)) / ((3 + 2 * m) * nnz + (1 + 2 * m) * (n_r + 1))
+
+
 def csr3d_bytes(nnz3, n3, v=8):
     return (v + 4) * nnz3 + 4 * (n3 + 1) + 2 * v * n3
 
@@ -853,7 +871,6 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
     res = {"copy_ceiling": copy_leg(fvx, torch, spmm_bytes(op.nnz_b, op.n_b, op.k))}
     res["copy_ceiling_GBs"] = max(c["GBs"] for c in res["copy_ceiling"])
 
-    import oracle  # closed-form bounds of Section 2 only (Eq. 2, 3a)
     sweep = []
     t1 = None
     for k in K_SWEEP:
@@ -876,7 +893,7 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
                "csr3d_us": t3 * 1e3, "csr3d_GBs": csr3d_bytes(len(col), Nk) / (t3 * 1e-3) / 1e9,
                "speedup_vs_csr3d": t3 / tk,
                "P_k": (k * t1 / tk) if t1 else None,
-               "P_ub_eq3a": oracle.p_spmm_ub(opk.nnz_b, opk.n_b, opk.n_b, k)}
+               "P_ub_eq3a": p_ub_eq3a(opk.nnz_b, opk.n_b, opk.n_b, k)}
         sweep.append(rec)
         log(f"k={k}: spmm {rec['spmm_us']:.2f} us ({rec['spmm_GBs']:.0f} GB/s), csr3d {rec['csr3d_us']:.2f} us, "
             f"P_k {rec['P_k']}")
@@ -1095,7 +1112,6 @@ def refine_leg(fvx, inputs, torch, np):
     the HBM roofline and P_k = k t_1 / t_k beside Eq. 3a's bound for these
     n_r, n_c and nnz.  The sweep over rotating buffers is captured in a HIP
     graph, so the launches are not paced by the Python loop."""
-    import oracle  # closed-form bound of Eq. 3a only
     spec = inputs.channel_base(96, 64)
     m = fvx.Mesh.from_spec(spec)
     ptr, col, val = m.prolongation(2)
@@ -1117,7 +1133,7 @@ def refine_leg(fvx, inputs, torch, np):
             rec = {"k": k, "dtype": name, "n_rows": n_r, "n_cols": n_c, "nnz": nnz, "bytes_per_launch": B,
                    "spmm_us": t * 1e3, "spmm_GBs": B / (t * 1e-3) / 1e9, "frac_hbm": B / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
             if k > 1:
-                rec.update({"P_k": k * t1[name] / t, "P_ub_eq3a": oracle.p_spmm_ub(nnz, n_r, n_c, k)})
+                rec.update({"P_k": k * t1[name] / t, "P_ub_eq3a": p_ub_eq3a(nnz, n_r, n_c, k)})
             out.append(rec)
             log(f"refine mapping k={k} {name}: {rec['spmm_us']:.2f} us, {rec['spmm_GBs']:.0f} GB/s"
                 + (f", P_k {rec['P_k']:.1f} (Eq. 3a bound {rec['P_ub_eq3a']:.1f})" if k > 1 else ""))
@@ -1204,7 +1220,6 @@ def generic_leg(fvx, inputs, torch, np):
     upper and lower bounds of Eqs. 3a and 3b for the same nnz, n_r, n_c, and
     against m products with the CSR-vector SpMV (fvx_csr_spmv).  Sweeps
     captured in HIP graphs."""
-    import oracle  # closed-form bounds of Section 2 only (Eqs. 3a, 3b)
     out = []
     for points in (7, 13):
         ptr, col, val = inputs.structured_csr(100, points)
@@ -1232,7 +1247,7 @@ def generic_leg(fvx, inputs, torch, np):
             rec = {"nnz_per_row": points, "m": m, "spmm_us": t * 1e3, "spmm_GBs": B / (t * 1e-3) / 1e9,
                    "frac_hbm": B / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "spmv_us": t_spmv * 1e3,
                    "P_m_vs_csr_spmv": m * t_spmv / t, "P_m": m * t_own / t,
-                   "P_ub_eq3a": oracle.p_spmm_ub(nnz, n, n, m), "P_lb_eq3b": oracle.p_spmm_lb(nnz, n, m)}
+                   "P_ub_eq3a": p_ub_eq3a(nnz, n, n, m), "P_lb_eq3b": p_lb_eq3b(nnz, n, m)}
             out.append(rec)
             log(f"generic SpMM {points} nnz/row m={m}: {rec['spmm_us']:.1f} us ({rec['spmm_GBs']:.0f} GB/s), "
                 f"P_m {rec['P_m']:.2f} (bounds {rec['P_lb_eq3b']:.2f}..{rec['P_ub_eq3a']:.2f}; "
@@ -1306,7 +1321,64 @@ def amg_leg(fvx, torch, inputs, op, D, rtol, err_of=None):
         log(f"amg level {lvl}: n_b {n_b} k {k} nnz_b {nnz_b} -> {out['levels'][-1]['next']}, "
             f"SpMM {t * 1e3:.2f} us")
     log(f"amg V-cycle {out['vcycle_us']:.1f} us")
+    out["app_a"] = app_a_accounting(out["levels"], out["f64"]["iters"], amg.degree if hasattr(amg, "degree") else 2)
+    a = out["app_a"]
+    log(f"App. A: weighted Eq. 3a bound {a['P_ub_weighted']:.2f} over {len(a['products'])} product kinds, "
+        f"pi_SpMM {a['pi_spmm_gflops']:.0f} GFLOP/s over the timed square products")
     return out
+
+
+def app_a_accounting(levels, cg_iters, degree=2):
+    """The accounting of the paper's Appendix A for this multigrid: every
+    sparse product of one preconditioned-CG solve with its shape (rows,
+    columns, nonzeros of the base block, right-hand sides m = planes) and
+    call count, the weight w_i = calls_i / all calls, the weighted upper bound
+    sum_i w_i P_ub(nnz_i, n_r,i, n_c,i, m_i) (Eq. 3a per product), the weighted
+    Eq. 2 intensity, and pi_SpMM = sum_i w_i OC_i / t_i with OC_i = (2 nnz_i +
+    1) m_i over the products timed one by one (the square level products; the
+    restrictions and prolongations are fused into level kernels and carry no
+    time of their own, so pi's weights are renormalised over the timed ones).
+    Per CG iteration: two level-0 products (direction and update kernels)
+    and one V-cycle, which on every level but the coarsest applies the level
+    operator 2 * degree times (degree - 1 pre-smoothing products, the
+    residual before the restriction, degree post-smoothing products), one
+    restriction and one prolongation; the coarsest level is a dense product
+    with its pseudo-inverse."""
+    prods = []
+
+    def add(kind, lvl, n_r, n_c, nnz, m, calls, t_us=None):
+        prods.append({"kind": kind, "level": lvl, "n_r": n_r, "n_c": n_c, "nnz": nnz, "m": m, "calls": calls,
+                      "t_us": t_us})
+
+    L = levels
+    add("cg level 0", 0, L[0]["n_b"], L[0]["n_b"], L[0]["nnz_b"], L[0]["k"], 2 * cg_iters, L[0]["spmm_us"])
+    for l, lv in enumerate(L):
+        n, k, nnz = lv["n_b"], lv["k"], lv["nnz_b"]
+        if lv["next"] == "coarsest":
+            nd = n * k
+            add("coarsest dense", l, nd, nd, nd * nd, 1, cg_iters)
+            break
+        add("level operator", l, n, n, nnz, k, 2 * degree * cg_iters, lv["spmm_us"])
+        nxt = L[l + 1]
+        if lv["next"] == "base":   # aggregates of base cells: one entry per fine row
+            add("restriction", l, nxt["n_b"], n, n, k, cg_iters)
+            add("prolongation", l, n, nxt["n_b"], n, k, cg_iters)
+        else:                      # plane pairs merged: one entry per fine row and plane pair
+            add("restriction (planes)", l, n, n, n, nxt["k"], cg_iters)
+            add("prolongation (planes)", l, n, n, n, nxt["k"], cg_iters)
+    total = sum(p["calls"] for p in prods)
+    for p in prods:
+        p["weight"] = p["calls"] / total
+        p["P_ub_eq3a"] = p_ub_eq3a(p["nnz"], p["n_r"], p["n_c"], p["m"])
+        p["intensity_eq2"] = ai_eq2(p["nnz"], p["n_r"], p["n_c"], p["m"])
+        p["oc"] = (2 * p["nnz"] + 1) * p["m"]
+    timed = [p for p in prods if p["t_us"]]
+    wt = sum(p["weight"] for p in timed)
+    return {"products": prods,
+            "P_ub_weighted": sum(p["weight"] * p["P_ub_eq3a"] for p in prods),
+            "intensity_weighted": sum(p["weight"] * p["intensity_eq2"] for p in prods),
+            "pi_spmm_gflops": sum(p["weight"] / wt * p["oc"] / (p["t_us"] * 1e-6) for p in timed) / 1e9,
+            "timed_weight": wt}
 
 
 def amg_profile_mode(fvx, inputs, torch):
