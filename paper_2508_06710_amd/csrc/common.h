@@ -88,6 +88,8 @@ struct fvx_op {
     bool has_f32 = false;
     int grid_nx = 0, grid_ny = 0;  // structured base (Cartesian builder), else 0
     int stencil = 7;                // 7: finite-volume face graph; 13, 27: structured operators
+    int grid_px = 0, grid_py = 0;   // structured base: periodic x / y
+    bool stencil_dir = false;       // 13/27: ELL entries in the fixed direction order (see op.cpp)
     int device = 0;
     fvx::OpDev<double> d64;
     fvx::OpDev<float> d32;

@@ -28,6 +28,10 @@ struct HostOp {
     // when the base is not such a grid.
     std::vector<double> cart;
     int nx = 0, ny = 0, px = 0, py = 0;
+    // structured 13/27-point operators: 1 when every row's 8 ELL entries are
+    // stored in the fixed direction order of stencil_dirs (an absent
+    // neighbour, past a wall, being the row itself with value 0)
+    int sdir = 0;
 };
 
 // One axis of a Cartesian base: cell centres and, when periodic, the period.
@@ -82,6 +86,15 @@ struct Axis {
         return r;
     }
 };
+
+// The fixed order of the 8 in-plane entries of a structured operator row,
+// as (dj, di) offsets: 27-point SW, S, SE, W, E, NW, N, NE; 13-point SS, S,
+// WW, W, E, EE, N, NN -- the column order of an interior row.
+const int (*stencil_dirs(int stencil))[2] {
+    static const int d27[8][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
+    static const int d13[8][2] = {{-2, 0}, {-1, 0}, {0, -2}, {0, -1}, {0, 1}, {0, 2}, {1, 0}, {2, 0}};
+    return stencil == 27 ? d27 : d13;
+}
 
 // The structured 13- and 27-point operators (Section 4.1) on a Cartesian
 // base repeated in periodic planes: in-plane entries (shift 0 and, for 27,
@@ -162,18 +175,52 @@ HostOp build_host_stencil(const fvx_mesh &m, const fvx_op_desc &d) {
     h.ell_val.assign(size_t(h.W) * nb, 0.0);
     if (d.stencil == 27) h.ell_v1.assign(size_t(h.W) * nb, 0.0);
     if (d.stencil != 13) h.w2.clear();
+    // Entry order: the fixed direction order when every direction of every
+    // row is a distinct cell or past a wall (axes of at least 3 cells for the
+    // 27-point operator, 5 for the 13-point one), else by column index.
+    const int (*dirs)[2] = stencil_dirs(d.stencil);
+    const int reach = d.stencil == 27 ? 1 : 2;
+    h.sdir = nx >= 2 * reach + 1 && ny >= 2 * reach + 1;
     h.nnz_b = nb;
-    for (int64_t i = 0; i < nb; ++i) {
-        int e = 0;
-        for (const auto &kv : nbr[i]) {
-            h.ell_col[size_t(e) * nb + i] = kv.first;
-            h.ell_val[size_t(e) * nb + i] = kv.second.first;
-            if (!h.ell_v1.empty()) h.ell_v1[size_t(e) * nb + i] = kv.second.second;
-            ++e;
+    for (int j = 0; j < ny && h.sdir; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t r = int64_t(j) * nx + i;
+            size_t found = 0;
+            for (int e = 0; e < 8; ++e) {
+                const int J = ay.at(j, dirs[e][0]), I = ax.at(i, dirs[e][1]);
+                if (I >= 0 && J >= 0 && nbr[r].count(J * nx + I)) ++found;
+            }
+            if (found != nbr[r].size()) h.sdir = 0;
         }
-        h.nnz_b += e;
-        for (; e < h.W; ++e) h.ell_col[size_t(e) * nb + i] = int32_t(i);  // padding: self, value 0
-    }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t r = int64_t(j) * nx + i;
+            int e = 0;
+            if (h.sdir) {
+                for (; e < 8; ++e) {
+                    const int J = ay.at(j, dirs[e][0]), I = ax.at(i, dirs[e][1]);
+                    const auto it = (I >= 0 && J >= 0) ? nbr[r].find(J * nx + I) : nbr[r].end();
+                    h.ell_col[size_t(e) * nb + r] = it == nbr[r].end() ? int32_t(r) : it->first;
+                    if (it == nbr[r].end()) continue;  // past a wall: the row itself, value 0
+                    h.ell_val[size_t(e) * nb + r] = it->second.first;
+                    if (!h.ell_v1.empty()) h.ell_v1[size_t(e) * nb + r] = it->second.second;
+                }
+                h.nnz_b += int64_t(nbr[r].size());
+                continue;
+            }
+            for (const auto &kv : nbr[r]) {
+                h.ell_col[size_t(e) * nb + r] = kv.first;
+                h.ell_val[size_t(e) * nb + r] = kv.second.first;
+                if (!h.ell_v1.empty()) h.ell_v1[size_t(e) * nb + r] = kv.second.second;
+                ++e;
+            }
+            h.nnz_b += e;
+            for (; e < h.W; ++e) h.ell_col[size_t(e) * nb + r] = int32_t(r);  // padding: self, value 0
+        }
+    h.nx = nx;
+    h.ny = ny;
+    h.px = m.periodic_x;
+    h.py = m.periodic_y;
     h.diag32.assign(nb, 0.0f);
     for (int64_t i = 0; i < nb; ++i) h.diag32[i] = float(h.diag[i]);
     return h;
@@ -631,6 +678,9 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         op->grid_nx = m->grid_nx;
         op->grid_ny = m->grid_ny;
         op->stencil = (d->stencil == 13 || d->stencil == 27) ? d->stencil : 7;
+        op->grid_px = m->periodic_x;
+        op->grid_py = m->periodic_y;
+        op->stencil_dir = op->stencil != 7 && h.sdir;
         FVX_HIP(hipGetDevice(&op->device));
         auto fill = [&](auto &D, int p, auto tag) {
             using T = decltype(tag);

@@ -336,6 +336,119 @@ __global__ __launch_bounds__(512) void k_lap_stencil_passes(RowArgs<T> a, const 
     }
 }
 
+// The structured 13/27-point products on line tiles, for a Cartesian base
+// whose rows store their 8 in-plane entries in the fixed direction order
+// (27-point SW, S, SE, W, E, NW, N, NE; 13-point SS, S, WW, W, E, EE, N, NN)
+// and a tile whose 64 lanes cover the k = 64 V columns in one pass.  A
+// wavefront takes one cell column i and R (2, 4 or 8) grid lines
+// j0 .. j0 + R - 1; the
+// row's coefficients are wavefront-uniform (scalar loads).  It loads each
+// value of the column strip once: 27-point the columns i - 1, i, i + 1 of
+// the lines j0 - 1 .. j0 + R (3 (R + 2) loads for R rows, against 9 R);
+// 13-point the column i of the lines j0 - 2 .. j0 + R + 1 and the columns
+// i +- 1, i +- 2 of each line (5 R + 4 against 9 R).  The plane shifts of a
+// loaded value are formed once and serve every line that reads it.  A
+// neighbour past a wall is read at the clamped cell, with coefficient 0 (the
+// ELL row holds the row itself there), so each term and the order of the
+// terms are those of stencil_apply: bitwise k_lap_stencil.
+template <typename T, int V, bool E1, bool S2, bool NT, int R>
+__global__ __launch_bounds__(512) void k_stencil_lines(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
+                                                        int nx, int ny, int px, int py, uint32_t n_xtiles,
+                                                        uint32_t n_tiles) {
+    using vt = vec_t<T, V>;
+    constexpr int LPR = 64;
+    const int lane = threadIdx.x & 63;
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wavefront's cell column
+    const int c0 = lane * V;
+    const int k = a.k;
+    const OpDev<T> &A = a.A;
+    auto wrapc = [](int v, int n, int per) {  // periodic wrap or wall clamp, always inside [0, n)
+        return per ? ((v % n) + n) % n : min(max(v, 0), n - 1);
+    };
+    auto ld = [&](int j, int i) { return ldv<T, V>(X + (int64_t(j) * nx + i) * a.ld + c0); };
+    auto fma_into = [](T cf, const vt &b, vt &acc) { acc = __builtin_elementwise_fma(vt(cf), b, acc); };
+    auto shifts = [&](const vt &x, auto Dt) {  // x[l + D] + x[l - D]
+        constexpr int D = decltype(Dt)::value;
+        return plane_shift<T, V, D>(x, c0, LPR, k) + plane_shift<T, V, -D>(x, c0, LPR, k);
+    };
+    for (uint32_t t = uint32_t(logical_block(a.remap)); t < n_tiles; t += gridDim.x) {
+        const uint32_t tj = t / n_xtiles, ti = t - tj * n_xtiles;
+        const uint32_t i_raw = ti * uint32_t(a.rows_per_tile) + w;
+        const bool in_x = i_raw < uint32_t(nx);  // uniform over the wavefront
+        const int i = in_x ? int(i_raw) : nx - 1;
+        const int j0 = int(tj) * R;
+        vt acc[R];
+        if constexpr (E1) {
+            // 27-point: columns iW, i, iE of the lines j0 - 1 .. j0 + R
+            const int iW = wrapc(i - 1, nx, px), iE = wrapc(i + 1, nx, px);
+            vt xw[R + 2], xc[R + 2], xe[R + 2];
+#pragma unroll
+            for (int q = 0; q < R + 2; ++q) {
+                const int j = wrapc(j0 - 1 + q, ny, py);
+                xw[q] = ld(j, iW);
+                xc[q] = ld(j, i);
+                xe[q] = ld(j, iE);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            vt sw[R + 2], sc[R + 2], se[R + 2];
+#pragma unroll
+            for (int q = 0; q < R + 2; ++q) {
+                sw[q] = shifts(xw[q], std::integral_constant<int, 1>{});
+                sc[q] = shifts(xc[q], std::integral_constant<int, 1>{});
+                se[q] = shifts(xe[q], std::integral_constant<int, 1>{});
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int64_t row = int64_t(min(j0 + q, ny - 1)) * nx + i;
+                const vt *xs[8] = {&xw[q], &xc[q], &xe[q], &xw[q + 1], &xe[q + 1], &xw[q + 2], &xc[q + 2], &xe[q + 2]};
+                const vt *ss[8] = {&sw[q], &sc[q], &se[q], &sw[q + 1], &se[q + 1], &sw[q + 2], &sc[q + 2], &se[q + 2]};
+                vt s_ = ld_meta<true>(A.diag, row) * xc[q + 1];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_val, e * a.n_b + row), *xs[e], s_);
+                fma_into(ld_meta<true>(A.w, row), sc[q + 1], s_);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_v1, e * a.n_b + row), *ss[e], s_);
+                acc[q] = s_;
+            }
+        } else {
+            // 13-point: column i of the lines j0 - 2 .. j0 + R + 1; columns i +- 1,
+            // i +- 2 of each line
+            const int iWW = wrapc(i - 2, nx, px), iW = wrapc(i - 1, nx, px);
+            const int iE = wrapc(i + 1, nx, px), iEE = wrapc(i + 2, nx, px);
+            vt xc[R + 4], xww[R], xw[R], xe[R], xee[R];
+#pragma unroll
+            for (int q = 0; q < R + 4; ++q) xc[q] = ld(wrapc(j0 - 2 + q, ny, py), i);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int j = min(j0 + q, ny - 1);
+                xww[q] = ld(j, iWW);
+                xw[q] = ld(j, iW);
+                xe[q] = ld(j, iE);
+                xee[q] = ld(j, iEE);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int64_t row = int64_t(min(j0 + q, ny - 1)) * nx + i;
+                const vt &xo = xc[q + 2];
+                const vt *xs[8] = {&xc[q], &xc[q + 1], &xww[q], &xw[q], &xe[q], &xee[q], &xc[q + 3], &xc[q + 4]};
+                vt s_ = ld_meta<true>(A.diag, row) * xo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_val, e * a.n_b + row), *xs[e], s_);
+                fma_into(ld_meta<true>(A.w, row), shifts(xo, std::integral_constant<int, 1>{}), s_);
+                fma_into(ld_meta<true>(A.w2, row), shifts(xo, std::integral_constant<int, 2>{}), s_);
+                acc[q] = s_;
+            }
+        }
+        if (!in_x) continue;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (j0 + q >= ny) break;
+            stv_masked<T, V, NT>(Y + (int64_t(j0 + q) * nx + i) * a.ld + c0, acc[q], V);
+        }
+    }
+}
+
 // D = M U: integrated divergence of in-plane face fluxes plus the fluxes
 // through the faces between planes.
 template <typename T, int V, bool Z, int WT>
@@ -499,6 +612,17 @@ void check_dtype(const fvx_op *op, int dtype) {
 
 }  // namespace
 
+// Grid lines along y per row group of the Cartesian kernel: 1 without a
+// workgroup cap or when one line per tile fits under it, else the fewest of
+// 2 or 4 that does (4 if neither), at most ny.
+int cart_lines(int64_t n_b, int nx, int ny, int rows_per_tile, int max_blocks) {
+    if (max_blocks <= 0 || ceil_div(n_b, rows_per_tile) <= max_blocks) return 1;
+    const int64_t xt = ceil_div(nx, rows_per_tile);
+    int r = xt * ceil_div(ny, 2) <= max_blocks ? 2 : 4;
+    while (r > ny) r >>= 1;
+    return r;
+}
+
 template <typename T>
 void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hipStream_t s) {
     FVX_REQUIRE(cs == nullptr, FVX_E_ARG, "colscale applies to independent planes only");
@@ -510,12 +634,40 @@ void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hi
                                                        span >= 2 && t.block <= 512)),
                 FVX_E_ARG, "13/27-point operators need a tile with 1, 2 or 4 passes over k, vec dividing k");
     auto a = row_args<T>(op, op->n_b, g, t);
+    // line tiles: a direction-ordered operator, one pass of 64 lanes over k,
+    // workgroups of at most 512 threads, and a workgroup cap that the
+    // one-line tiles exceed
+    int lines = 1;
+    if (op->stencil_dir && t.lanes_per_row == 64 && op->k == 64 * t.vec && !t.stage_lds && t.max_blocks > 0 &&
+        t.block <= 512 && ceil_div(op->n_b, g.rows_per_tile) > t.max_blocks) {
+        // the fewest of 2, 4 or 8 lines per wavefront that fit under the cap
+        // (8 if none does), at most ny
+        const int64_t xt = ceil_div(op->grid_nx, g.rows_per_tile);
+        lines = 2;
+        while (lines < 8 && xt * ceil_div(op->grid_ny, lines) > t.max_blocks) lines *= 2;
+        while (lines > op->grid_ny) lines >>= 1;
+    }
     by_vec<T>(t.vec, true, [&](auto V, auto) {
         constexpr int v = decltype(V)::value;
         auto go = [&](auto E1t, auto S2t) {
             constexpr bool e1 = decltype(E1t)::value, s2 = decltype(S2t)::value;
             auto launch = [&](auto NTt) {
                 constexpr bool nt = decltype(NTt)::value;
+                if (lines > 1) {
+                    const uint32_t n_xtiles = uint32_t(ceil_div(op->grid_nx, g.rows_per_tile));
+                    const uint32_t n_tiles = n_xtiles * uint32_t(ceil_div(op->grid_ny, lines));
+                    const int nblk = int(std::min<int64_t>(n_tiles, t.max_blocks));
+                    if (lines == 8)
+                        hipLaunchKernelGGL((k_stencil_lines<T, v, e1, s2, nt, 8>), dim3(nblk), dim3(t.block), 0, s, a,
+                                           X, Y, op->grid_nx, op->grid_ny, op->grid_px, op->grid_py, n_xtiles, n_tiles);
+                    else if (lines == 4)
+                        hipLaunchKernelGGL((k_stencil_lines<T, v, e1, s2, nt, 4>), dim3(nblk), dim3(t.block), 0, s, a,
+                                           X, Y, op->grid_nx, op->grid_ny, op->grid_px, op->grid_py, n_xtiles, n_tiles);
+                    else
+                        hipLaunchKernelGGL((k_stencil_lines<T, v, e1, s2, nt, 2>), dim3(nblk), dim3(t.block), 0, s, a,
+                                           X, Y, op->grid_nx, op->grid_ny, op->grid_px, op->grid_py, n_xtiles, n_tiles);
+                    return;
+                }
                 // the row-group width as a constant for the common widths, so that the
                 // ring shifts' source lanes fold
                 auto passes_kernel = [&](auto Pt) {
@@ -558,17 +710,6 @@ void launch_lap_stencil(const fvx_op *op, const T *X, T *Y, const double *cs, hi
             go(std::false_type{}, std::true_type{});
     });
     FVX_HIP(hipGetLastError());
-}
-
-// Grid lines along y per row group of the Cartesian kernel: 1 without a
-// workgroup cap or when one line per tile fits under it, else the fewest of
-// 2 or 4 that does (4 if neither), at most ny.
-int cart_lines(int64_t n_b, int nx, int ny, int rows_per_tile, int max_blocks) {
-    if (max_blocks <= 0 || ceil_div(n_b, rows_per_tile) <= max_blocks) return 1;
-    const int64_t xt = ceil_div(nx, rows_per_tile);
-    int r = xt * ceil_div(ny, 2) <= max_blocks ? 2 : 4;
-    while (r > ny) r >>= 1;
-    return r;
 }
 
 template <typename T>

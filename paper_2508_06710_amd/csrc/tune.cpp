@@ -60,6 +60,22 @@ std::vector<fvx_tile> option_candidates(const fvx_op *op, const fvx_tile &b) {
     return out;
 }
 
+// Structured operators stored in direction order: the line tiles (64 lanes
+// over k = 64 vec in one pass, a workgroup cap selecting 2, 4 or 8 grid lines
+// per wavefront) at every workgroup size, whatever the best row mapping of
+// stage 1.
+std::vector<fvx_tile> stencil_line_candidates(const fvx_op *op, int dtype) {
+    std::vector<fvx_tile> out;
+    const int vec = op->k / 64;
+    const int vmax = dtype == FVX_F32 ? 4 : 2;
+    if (!op->stencil_dir || op->k % 64 || vec < 1 || vec > vmax || (vec & (vec - 1)) || op->ld % vec) return out;
+    for (int block : {64, 128, 256, 512})
+        for (int cap : {256, 512, 1024, 2048})
+            for (int remap : {1, 0})
+                for (int nt : {0, 1}) out.push_back(fvx_tile{vec, 64, block, remap, cap, 0, nt});
+    return out;
+}
+
 template <typename T>
 double time_tile(fvx_op *op, int dtype, const fvx_tile &t, T *buf, int pairs, size_t nv, int reps, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
@@ -122,6 +138,7 @@ extern "C" int fvx_tune(fvx_op *op, int dtype, void *scratch, size_t scratch_byt
         try {
             try_all(fvx::shape_candidates(op, dtype));
             try_all(fvx::option_candidates(op, best));
+            try_all(fvx::stencil_line_candidates(op, dtype));
         } catch (...) {
             op->tile[dtype] = keep;
             hipEventDestroy(e0);

@@ -207,3 +207,45 @@ def test_structured_operator_argument_checks():
     with pytest.raises(fvx.FvxError) as e:
         op.solve(X, rtol=1e-8)
     assert e.value.code == fvx._lib.E_UNSUPPORTED
+
+
+LINE_SPECS = {
+    "channel40x24": inputs.channel_base(40, 24),         # walls in y, ragged x tiles
+    "convection12x22": inputs.convection_base(12, 22),   # walls on all sides, ny % 4 = 2
+    "box10x9": _box(10, 9),                              # periodic in x and y
+    "box5x5": _box(5, 5),                                # the smallest direction-ordered 13-point grid
+    "channel3x7": inputs.channel_base(3, 7),             # the smallest direction-ordered 27-point x axis
+}
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("name", list(LINE_SPECS))
+@pytest.mark.parametrize("k,dt", [(64, "f64"), (128, "f64"), (64, "f32"), (128, "f32")])
+def test_stencil_line_tiles(stencil, name, k, dt):
+    """The line tiles of a direction-ordered structured operator (64 lanes
+    over k, 2 or 4 grid lines per wavefront by the workgroup cap, a grid
+    stride when the cap is below the tile count) against the one-line
+    64-lane kernel, bit for bit, and against the oracle's matrix."""
+    spec = LINE_SPECS[name]
+    if stencil == 13 and min(spec.nx, spec.ny) < 5:
+        pytest.skip("13-point direction order needs axes of at least 5 cells")
+    fvx, op, A = _op(spec, k, stencil)
+    dtype = fvx.F64 if dt == "f64" else fvx.F32
+    vec = k // 64
+    x = inputs.uniform(44, k, op.n_b * k)
+    X = op.to_rows(x, dtype=dtype)
+    op.set_tile(vec, 64, 64, 1, 0, 0, 0, dtype=dtype)   # one line per wavefront, no cap
+    ref = op.lap(X, dtype=dtype).clone()
+    n_rows = op.n_b
+    seen = set()
+    for block, cap, remap, nt in ((64, 8, 1, 0), (128, 5, 0, 1), (64, n_rows // 3, 1, 1), (256, 3, 1, 0),
+                                  (64, n_rows // 2, 0, 0), (512, 1, 1, 0)):
+        if block // 64 * cap >= n_rows or cap < 1:
+            continue
+        op.set_tile(vec, 64, block, remap, cap, 0, nt, dtype=dtype)
+        Y = op.lap(X, dtype=dtype)
+        assert bool((Y == ref).all()), (block, cap, remap, nt)
+        seen.add((block, cap))
+    assert seen
+    if dt == "f64":
+        assert componentwise(op.to_planes(ref), oracle.spmv(A, x), A, x) <= TOL64
