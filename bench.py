@@ -586,6 +586,8 @@ def main():
     ap.add_argument("--profile-amg", action="store_true")
     ap.add_argument("--profile-ns", action="store_true")
     ap.add_argument("--no-ns", action="store_true")
+    ap.add_argument("--launch-only", action="store_true",
+                    help="only the launch-mode comparison (phase by phase vs graph replay) of the solves")
     ap.add_argument("--guess-epochs", type=int, default=20)
     ap.add_argument("--guess-lr", type=float, default=1e-4)
     ap.add_argument("--retune", action="store_true",
@@ -658,6 +660,15 @@ def main():
     op.workspace(op.solve_opts(rtol=rtol))
     plug = Plug(fvx, torch)
     log(f"{N} cells, {len(X)} rotating lap buffer pairs ({len(X) * 2 * n_b * op.ld * 8 / 2**30:.2f} GiB)")
+    if args.launch_only:
+        op.div(U0, W0, D)
+        rec = {"launch_modes": launch_leg(fvx, torch, op, D, rtol)}
+        rec["launch_modes"]["batch_mixed"] = batch_leg(fvx, inputs, torch, np, rtol, launch_only=True)
+        path = os.path.join(ROOT, "gpurun_out", "bench_launch.json")
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+        log(f"wrote {path}")
+        return
 
     def step():
         fvx.copy(U, U0)
@@ -933,8 +944,44 @@ def extra_measurements(fvx, inputs, torch, np, op, mesh, rtol, D):
 
     res["poisson_pcg"] = pcg_leg(fvx, torch, op, D, rtol, err_of)
     res["poisson_amg"] = amg_leg(fvx, torch, inputs, op, D, rtol, err_of)
+    res["launch_modes"] = launch_leg(fvx, torch, op, D, rtol)
     log(f"csr3d CG {res['csr3d_cg']['s_to_1e-8']:.3f} s, mixed {res['mixed_cg']['s_to_1e-8']:.3f} s")
     return res
+
+
+def launch_modes(fvx, torch, solve, reps=3):
+    """One solve configuration launched phase by phase and replayed from HIP
+    graphs: per mode the first solve (in graph mode it captures the graphs)
+    and the best of `reps` later ones.  solve(launch) returns (X, stats) or
+    (Xs, [stats])."""
+    rec = {}
+    for mode, lm in (("phases", fvx.LAUNCH_PHASES), ("graph", fvx.LAUNCH_GRAPH)):
+        times = []
+        for _ in range(reps + 1):
+            tm = Timer(torch)
+            with tm:
+                _, st = solve(lm)
+            times.append(tm.ms() / 1e3)
+        sts = st if isinstance(st, list) else [st]
+        rec[mode] = {"first_s": times[0], "s": min(times[1:]), "iters": max(x["iters"] for x in sts)}
+    rec["graph_speedup"] = rec["phases"]["s"] / rec["graph"]["s"]
+    return rec
+
+
+def launch_leg(fvx, torch, op, D, rtol):
+    """The CG iterations of the benchmark's solves launched kernel by kernel
+    and replayed from HIP graphs: plain, Chebyshev and multigrid CG in FP64,
+    multigrid and plain CG in mixed precision (default options otherwise)."""
+    amg = fvx.Amg(op)
+    cases = {"plain": {}, "chebyshev": dict(precond=fvx.PRECOND_CHEBYSHEV), "mixed": dict(precision=fvx.MIXED),
+             "multigrid": dict(amg=amg), "multigrid_mixed": dict(amg=amg, precision=fvx.MIXED)}
+    out = {}
+    for name, kw in cases.items():
+        out[name] = launch_modes(fvx, torch, lambda lm: op.solve(D, rtol=rtol, launch=lm, **kw))
+        r = out[name]
+        log(f"launch {name}: phases {r['phases']['s'] * 1e3:.2f} ms, graph {r['graph']['s'] * 1e3:.2f} ms "
+            f"(first {r['graph']['first_s'] * 1e3:.2f} ms), {r['phases']['iters']} iterations")
+    return out
 
 
 def copy_leg(fvx, torch, headline_bytes):
@@ -1452,10 +1499,12 @@ def large_sweep(fvx, inputs, torch, np):
     return out
 
 
-def batch_leg(fvx, inputs, torch, np, rtol):
+def batch_leg(fvx, inputs, torch, np, rtol, launch_only=False):
     """24 uneven problems (4 channel bases x k in {4..128}) solved together in
     mixed precision to rtol, against the same problems solved one by one and
-    against plain FP64 SpMV-CG on their assembled matrices."""
+    against plain FP64 SpMV-CG on their assembled matrices; the batch launched
+    phase by phase and replayed from graphs (launch_only: that comparison
+    alone)."""
     probs = inputs.batch_problems()
     ops, Bs, tiles = [], [], []
     for p in probs:
@@ -1467,6 +1516,11 @@ def batch_leg(fvx, inputs, torch, np, rtol):
     opl = [o for o, _ in ops]
     cells = sum(o.n_b * o.k for o in opl)
     log(f"batch: {len(opl)} problems, {cells} cells")
+    modes = launch_modes(fvx, torch, lambda lm: fvx.solve_batch(opl, Bs, rtol=rtol, precision=fvx.MIXED, launch=lm))
+    log(f"batch launch modes: phases {modes['phases']['s']:.3f} s, graph {modes['graph']['s']:.3f} s "
+        f"(first {modes['graph']['first_s']:.3f} s)")
+    if launch_only:
+        return modes
     fvx.solve_batch(opl, Bs, rtol=rtol, precision=fvx.MIXED)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -1507,6 +1561,7 @@ def batch_leg(fvx, inputs, torch, np, rtol):
     batch_cheb_s = time.perf_counter() - t0
     out = {
         "batch_chebyshev_s": batch_cheb_s,
+        "launch_modes": modes,
         "max_relres_true_chebyshev": max(s["relres_true"] for s in stc),
         "problems": [{"base": f"{p['base'].nx}x{p['base'].ny}", "k": p["k"], "cells": o.n_b * o.k,
                       "tile_f64": list(t[0]), "tile_f32": list(t[1]), "cg_tile_f64": list(t[2]),

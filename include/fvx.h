@@ -319,7 +319,31 @@ typedef struct fvx_solve_opts {
                              [2 / cheb_ratio, 2] of the spectrum of D^-1 A (> 1) */
     const fvx_amg *amg;   /* AMG: the hierarchy built for this operator (fvx_amg_create);
                              NULL otherwise */
+    int32_t launch;       /* FVX_LAUNCH_PHASES or FVX_LAUNCH_GRAPH (see below) */
 } fvx_solve_opts;
+
+/* How the CG iterations between two host polls are launched:
+ *   PHASES: kernel by kernel (the direction kernel, the update kernel and
+ *           the preconditioner's kernels of every iteration).
+ *   GRAPH (the default of fvx_solve_opts_default):
+ *           after the first poll, replayed from HIP graphs of 1, 2, 4, ...,
+ *           64 iterations.  The graphs are captured on first use (on a
+ *           library-owned stream of the device, default priority) and kept
+ *           in a process-wide cache of the 16 most recently used solve
+ *           configurations, keyed by the device, precision, workspace
+ *           address, operators (with their tiles), preconditioner and
+ *           hierarchy: a repeated solve with the same operator, options and
+ *           workspace (e.g. every time step) replays them with no capture.
+ *           Same kernels, arguments and order as PHASES: the same X bitwise.
+ *           Capturing allocates host and driver resources, so
+ *           fvx_poisson_solve_noalloc always launches phase by phase.
+ *           Dropping a cached configuration synchronises the device.
+ *           On MI355X the replay saves 1-4 % per solve (the GPU's own time
+ *           per dependent kernel, not the host's launch cost, bounds these
+ *           iterations); the first solve of a configuration pays the capture
+ *           (about 15 % of a plain-CG solve of 1.57 M unknowns). */
+#define FVX_LAUNCH_PHASES 0
+#define FVX_LAUNCH_GRAPH 1
 
 /* Preconditioners of the CG (A = -L, D = diag(A); every step an SpMM or a
  * row-local update, no extra reductions):
@@ -384,7 +408,7 @@ int fvx_poisson_solve(const fvx_op *op, const double *B, double *X, const fvx_so
  * planes in either precision.  A solve whose workspace (fvx_solve_bytes)
  * exceeds the scratch fails with FVX_E_NOMEM before any device work.  B, X,
  * opts, stats and the other results are those of fvx_poisson_solve with the
- * same tiles (bitwise the same X).  The solve initialises every scratch byte
+ * same tiles (bitwise the same X); opts.launch is ignored (phase by phase).  The solve initialises every scratch byte
  * it reads, so nothing carries over from the previous call; but all calls on
  * one device share that device's scratch, so calls that overlap in time on
  * one device (several host threads or streams) race and must be serialised

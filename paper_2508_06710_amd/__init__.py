@@ -12,11 +12,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXED, NEUMANN, NONE,  # noqa: F401
-                   PERIODIC_Z, PRECOND_AMG, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, FvxError, SolveOpts, SolveStats,
+                   PERIODIC_Z, PRECOND_AMG, PRECOND_CHEBYSHEV, PRECOND_JACOBI, PRECOND_NONE, LAUNCH_PHASES,
+                   LAUNCH_GRAPH, FvxError, SolveOpts, SolveStats,
                    Tile, check, lib)
 
 __all__ = ["Mesh", "Operator", "GuessNet", "SparseMatrix", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
-           "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "PRECOND_AMG", "Amg", "lib"]
+           "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "PRECOND_AMG", "LAUNCH_PHASES",
+           "LAUNCH_GRAPH", "Amg", "lib"]
 
 
 def _torch():
@@ -393,14 +395,18 @@ class Operator:
 
     # ---- solves -----------------------------------------------------------
     def solve_opts(self, rtol=1e-8, max_iter=100000, precision=F64, inner_rtol=1e-4, max_outer=50,
-                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=8, cheb_ratio=300.0, amg=None):
+                   guess=GUESS_ZERO, poll_every=64, precond=PRECOND_NONE, cheb_degree=8, cheb_ratio=300.0, amg=None,
+                   launch=None):
         """Solve options; amg: an Amg hierarchy of this operator (sets the
-        AMG preconditioner unless precond is given otherwise)."""
+        AMG preconditioner unless precond is given otherwise); launch:
+        LAUNCH_PHASES or LAUNCH_GRAPH (None: the library's default)."""
         o = SolveOpts()
         check(lib().fvx_solve_opts_default(C.byref(o)), "fvx_solve_opts_default")
         o.rtol, o.max_iter, o.precision = float(rtol), int(max_iter), int(precision)
         o.inner_rtol, o.max_outer, o.guess, o.poll_every = float(inner_rtol), int(max_outer), int(guess), int(poll_every)
         o.precond, o.cheb_degree, o.cheb_ratio = int(precond), int(cheb_degree), float(cheb_ratio)
+        if launch is not None:
+            o.launch = int(launch)
         if amg is not None:
             o.amg = amg._h.value
             if precond == PRECOND_NONE:

@@ -19,6 +19,7 @@ GUESS_ZERO, GUESS_GIVEN, GUESS_NET = 0, 1, 2
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_AMG = 0, 1, 2, 3
+LAUNCH_PHASES, LAUNCH_GRAPH = 0, 1
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
 
 
@@ -46,7 +47,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("inner_rtol", C.c_double), ("max_outer", C.c_int32), ("guess", C.c_int32),
                 ("poll_every", C.c_int32), ("precond", C.c_int32), ("cheb_degree", C.c_int32),
-                ("cheb_ratio", C.c_double), ("amg", C.c_void_p)]
+                ("cheb_ratio", C.c_double), ("amg", C.c_void_p), ("launch", C.c_int32)]
 
 
 class AmgOpts(C.Structure):

@@ -31,6 +31,7 @@ struct fvx_amg {
     const float *pinv32 = nullptr;
     double inv_theta = 1.0;
     double c1[fvx::kMaxAmgDegree] = {}, c2[fvx::kMaxAmgDegree] = {};  // smoother step j uses c1[j], c2[j]
+    uint64_t serial = fvx::next_serial();
 };
 
 namespace fvx {

@@ -25,6 +25,7 @@
 // convergence return at once.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 
 #include "amg.h"
@@ -254,6 +255,7 @@ __device__ void b_cg_b(const RowArgs<T> &a, const CgDev &d, VB vb, int it, Src p
     __shared__ int s_bad;
     ROW_PROLOGUE
     const int G = d.G;
+    if (blk == 0 && threadIdx.x == 0) d.st->next_it = it + 1;
     sum_partials(pq.p, pq.n, G, lds, tot);
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
@@ -455,13 +457,17 @@ __device__ __forceinline__ int find_item(const BItem<T> *items, int n) {
 
 // p' of iteration it: p0 on even iterations, p1 on odd ones; the previous
 // direction is r at it = 0 (p' = r + 0 r) and the other buffer afterwards.
+// The iteration number comes from the item's state (next_it here, iter in
+// the update kernel), so the kernels take the same arguments on every
+// iteration.
 template <typename T, int V, bool Z, int WT, int PRE, bool LN>
-__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restrict__ items, int n, int it) {
+__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restrict__ items, int n) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
     if (local >= I.nblk) return;
     const RowArgs<T> a = I.a;
     const CgDev d = I.d;
+    const int it = d.st->next_it;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *src = PRE == 2 ? I.zf : I.r;
     T *pold = it == 0 ? src : ((it & 1) ? I.p0 : I.p1);
@@ -470,12 +476,13 @@ __global__ __launch_bounds__(kMaxCgBlock) void kb_cg_a(const BItem<T> *__restric
 }
 
 template <typename T, int V, bool Z, int WT, int PRE, bool LN>
-__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n, int it) {
+__global__ __launch_bounds__(kMaxCgBlock) void kb_cg_b(const BItem<T> *__restrict__ items, int n) {
     const BItem<T> &I = items[find_item(items, n)];
     const int local = int(blockIdx.x) - I.first;
     if (local >= I.nblk) return;
     const RowArgs<T> a = I.a;
     const CgDev d = I.d;
+    const int it = d.st->iter;
     const VB vb{logical_block_of(local, I.nblk, a.remap), I.nblk};
     T *pnew = (it & 1) ? I.p1 : I.p0;
     b_cg_b<T, V, Z, WT, PRE, LN>(a, d, vb, it, I.pq, I.x, I.r, pnew);
@@ -817,12 +824,124 @@ struct GroupKey {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Launch graphs of the CG iteration (FVX_LAUNCH_GRAPH)
+// ---------------------------------------------------------------------------
+// The iterations between two polls can be replayed from HIP graphs instead of
+// being launched kernel by kernel: graphs of 1, 2, 4, ..., 64 iterations,
+// captured on first use and kept in a process-wide cache under a key that
+// holds everything a captured launch depends on (device, precision,
+// workspace and descriptor addresses, each operator's serial and tiles, the
+// preconditioner with its hierarchy's serial, the launch groups).  A later
+// solve with the same key replays the cached graphs.  The captured kernels,
+// arguments and order are those of the launches they replace, so the
+// iterates are bitwise the same either way.
+constexpr int kGraphSizes = 7;     // graphs of 2^0 .. 2^6 iterations
+constexpr size_t kGraphSets = 16;  // cached keys; the least recently used is dropped first
+constexpr int kGraphDevices = 64;
+
+struct GraphSet {
+    std::vector<uint64_t> key;
+    hipGraphExec_t ex[kGraphSizes] = {};
+    uint64_t used = 0;
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::vector<std::unique_ptr<GraphSet>> sets;
+    hipStream_t cap[kGraphDevices] = {};  // per device: the stream graphs are captured on
+    uint64_t clock = 0;
+};
+
+// Never destroyed: graph objects are not released during the runtime's own
+// teardown at process exit.
+GraphCache &graph_cache() {
+    static GraphCache *c = new GraphCache;
+    return *c;
+}
+
+struct KeyBuf {
+    std::vector<uint64_t> v;
+    void u(int64_t x) { v.push_back(uint64_t(x)); }
+    void p(const void *x) { v.push_back(uint64_t(reinterpret_cast<uintptr_t>(x))); }
+    void d(double x) {
+        uint64_t b;
+        std::memcpy(&b, &x, sizeof b);
+        v.push_back(b);
+    }
+    void tile(const fvx_tile &t) {
+        for (int x : {t.vec, t.lanes_per_row, t.block, t.xcd_remap, t.max_blocks, t.stage_lds, t.nt_store}) u(x);
+    }
+};
+
+// The cached set for `key` (created empty when absent).  Dropping a set waits
+// for the device first: one of its graphs may still be running on another
+// stream.  Caller holds the cache's mutex.
+GraphSet &graph_set(GraphCache &c, const std::vector<uint64_t> &key) {
+    for (auto &g : c.sets)
+        if (g->key == key) {
+            g->used = ++c.clock;
+            return *g;
+        }
+    if (c.sets.size() >= kGraphSets) {
+        size_t old = 0;
+        for (size_t i = 1; i < c.sets.size(); ++i)
+            if (c.sets[i]->used < c.sets[old]->used) old = i;
+        FVX_HIP(hipDeviceSynchronize());
+        for (hipGraphExec_t e : c.sets[old]->ex)
+            if (e) FVX_HIP(hipGraphExecDestroy(e));
+        c.sets.erase(c.sets.begin() + long(old));
+    }
+    c.sets.push_back(std::make_unique<GraphSet>());
+    c.sets.back()->key = key;
+    c.sets.back()->used = ++c.clock;
+    return *c.sets.back();
+}
+
+// Captures `launch` (which launches on the stream variable `s`) into a graph
+// on the device's capture stream and instantiates it.  `s` is pointed at the
+// capture stream meanwhile and restored afterwards, also when a launch throws
+// (the capture is then ended and its graph dropped).
+hipGraphExec_t capture_graph(GraphCache &c, hipStream_t &s, const std::function<void()> &launch) {
+    int dev = 0;
+    FVX_HIP(hipGetDevice(&dev));
+    FVX_REQUIRE(dev >= 0 && dev < kGraphDevices, FVX_E_UNSUPPORTED, "device index beyond the graph cache");
+    if (!c.cap[dev]) FVX_HIP(hipStreamCreateWithFlags(&c.cap[dev], hipStreamNonBlocking));
+    const hipStream_t user = s, cap = c.cap[dev];
+    struct Restore {
+        hipStream_t &s, user, cap;
+        bool open = true;
+        ~Restore() {
+            s = user;
+            if (open) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+            }
+        }
+    } restore{s, user, cap};
+    FVX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    s = cap;
+    launch();
+    hipGraph_t g = nullptr;
+    restore.open = false;
+    FVX_HIP(hipStreamEndCapture(cap, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    FVX_HIP(rc);
+    return e;
+}
+
 // Runs the CGs of all jobs.  Each job starts exactly as a single solve would
 // (its own launches), then every iteration is one batched launch per phase and
 // group.  items_dev: device array for the launch descriptors (>= jobs.size()).
+// launch_mode FVX_LAUNCH_GRAPH: the iterations after the first poll are
+// replayed from cached graphs (above); the launches, hence the iterates, are
+// those of FVX_LAUNCH_PHASES.
 template <typename T>
 void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *flags_dev, int poll, const Precond &pc,
-                  hipStream_t s) {
+                  int launch_mode, hipStream_t s) {
     if (jobs.empty()) return;
     std::vector<BItem<T>> items(jobs.size());
     std::vector<GroupKey> keys(jobs.size());
@@ -989,60 +1108,127 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
     // job's tolerance (plus one), at most `poll`.  Kernels launched after
     // convergence return at once but still cost a launch each, so the batch
     // follows the prediction; the arithmetic does not depend on it.
+    // One iteration of every item: per launch group the direction kernel, the
+    // update kernel, the folds of per-column partials and the preconditioner.
+    // Every iteration launches the same kernels with the same arguments.
+    auto iteration = [&]() {
+        for (const Launch &L : launches) {
+            const BItem<T> *dev = items_dev + L.offset;
+            by_pre(pc.kind, [&](auto Pt) {
+                constexpr int PRE = decltype(Pt)::value;
+                by_v<T>(L.key.vec, [&](auto Vt) {
+                    constexpr int V = decltype(Vt)::value;
+                    constexpr int PB = PRE == 1 ? 1 : 0;
+                    const dim3 gb(L.blocks), bb(L.key.block);
+                    // line tiles exist for the compiled width 4 (the Cartesian
+                    // 5-point base) only
+                    by_width(L.key.w, [&](auto Wt) {
+                        constexpr int WT = decltype(Wt)::value;
+                        const bool ln = WT == 4 && L.key.lines;
+                        if (L.key.z) {
+                            if (ln)
+                                hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n);
+                            else
+                                hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, false>), gb, bb, 0, s, dev, L.n);
+                        } else {
+                            if (ln)
+                                hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n);
+                            else
+                                hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, false>), gb, bb, 0, s, dev, L.n);
+                        }
+                    });
+                    fold_percol(L, 0);
+                    by_width(L.key.w, [&](auto Wt) {
+                        constexpr int WT = decltype(Wt)::value;
+                        const bool ln = WT == 4 && L.key.lines;
+                        if (L.key.z) {
+                            if (ln)
+                                hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n);
+                            else
+                                hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, false>), gb, bb, 0, s, dev, L.n);
+                        } else {
+                            if (ln)
+                                hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n);
+                            else
+                                hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, false>), gb, bb, 0, s, dev, L.n);
+                        }
+                    });
+                    fold_percol(L, 1);
+                    if (PRE == 1) fold_percol(L, 2);
+                });
+            });
+            pre_pass(L);
+        }
+    };
+    // Graph replay: the key of every captured argument (see graph_cache).
+    KeyBuf key;
+    if (launch_mode == FVX_LAUNCH_GRAPH) {
+        int dev = 0;
+        FVX_HIP(hipGetDevice(&dev));
+        key.u(dev);
+        key.u(sizeof(T));
+        key.p(items_dev);
+        key.u(pc.kind);
+        key.u(pc.degree);
+        key.u(pc.amg ? int64_t(pc.amg->serial) : 0);
+        key.d(pc.inv_theta);
+        for (double c : pc.c1) key.d(c);
+        for (double c : pc.c2) key.d(c);
+        for (const CgJob<T> &J : jobs) {
+            key.u(int64_t(J.op->serial));
+            for (int t = 0; t < 2; ++t) {
+                key.tile(J.op->tile[t]);
+                key.tile(J.op->cg_tile[t]);
+            }
+            // The state by value (the V-cycle's last step takes it); its
+            // rtol2 is read from the descriptors only, so it is left out.
+            const CgDev &d = J.d;
+            for (const void *q : {(const void *)d.st, (const void *)d.rho, (const void *)d.active,
+                                  (const void *)d.alpha, (const void *)d.bnorm2, (const void *)d.r0,
+                                  (const void *)d.rho_last, (const void *)d.iters, (const void *)d.part_a,
+                                  (const void *)d.part_b, (const void *)d.tot, (const void *)d.mean,
+                                  (const void *)J.r, (const void *)J.z0, (const void *)J.z1})
+                key.p(q);
+            key.u(d.G);
+            key.u(d.percol);
+            key.u(d.count);
+            key.p(pc.kind == 3 ? (const void *)amg_output<T>(pc.amg, *J.amgw) : nullptr);
+        }
+        for (const Launch &L : launches) {
+            for (int x : {L.key.block, L.key.vec, L.key.z, L.key.w, L.key.lines, L.offset, L.n, L.blocks}) key.u(x);
+            for (int j : L.jobs) key.u(j);
+        }
+    }
+    // Replays `count` iterations from the cached graphs (binary decomposition
+    // of count), capturing each size on first use.
+    auto replay = [&](int count) {
+        GraphCache &gc = graph_cache();
+        std::lock_guard<std::mutex> lk(gc.mu);
+        GraphSet &g = graph_set(gc, key.v);
+        for (int j = kGraphSizes - 1; j >= 0; --j) {
+            const int m = 1 << j;
+            while (count >= m) {
+                if (!g.ex[j])
+                    g.ex[j] = capture_graph(gc, s, [&] {
+                        for (int i = 0; i < m; ++i) iteration();
+                    });
+                FVX_HIP(hipGraphLaunch(g.ex[j], s));
+                count -= m;
+            }
+        }
+    };
     int it = 0, next = std::min(poll, 8);
     std::vector<int> it_prev(jobs.size(), 0);
     std::vector<double> r2_prev(jobs.size(), 1.0);
     while (true) {
         const int batch = std::min(next, std::max(1, max_iter + 1 - it));
-        for (int i = 0; i < batch; ++i, ++it) {
-            for (const Launch &L : launches) {
-                const BItem<T> *dev = items_dev + L.offset;
-                by_pre(pc.kind, [&](auto Pt) {
-                    constexpr int PRE = decltype(Pt)::value;
-                    by_v<T>(L.key.vec, [&](auto Vt) {
-                        constexpr int V = decltype(Vt)::value;
-                        constexpr int PB = PRE == 1 ? 1 : 0;
-                        const dim3 gb(L.blocks), bb(L.key.block);
-                        // line tiles exist for the compiled width 4 (the Cartesian
-                        // 5-point base) only
-                        by_width(L.key.w, [&](auto Wt) {
-                            constexpr int WT = decltype(Wt)::value;
-                            const bool ln = WT == 4 && L.key.lines;
-                            if (L.key.z) {
-                                if (ln)
-                                    hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n, it);
-                                else
-                                    hipLaunchKernelGGL((kb_cg_a<T, V, true, WT, PRE, false>), gb, bb, 0, s, dev, L.n, it);
-                            } else {
-                                if (ln)
-                                    hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, WT == 4>), gb, bb, 0, s, dev, L.n, it);
-                                else
-                                    hipLaunchKernelGGL((kb_cg_a<T, V, false, WT, PRE, false>), gb, bb, 0, s, dev, L.n, it);
-                            }
-                        });
-                        fold_percol(L, 0);
-                        by_width(L.key.w, [&](auto Wt) {
-                            constexpr int WT = decltype(Wt)::value;
-                            const bool ln = WT == 4 && L.key.lines;
-                            if (L.key.z) {
-                                if (ln)
-                                    hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n, it);
-                                else
-                                    hipLaunchKernelGGL((kb_cg_b<T, V, true, WT, PB, false>), gb, bb, 0, s, dev, L.n, it);
-                            } else {
-                                if (ln)
-                                    hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, WT == 4>), gb, bb, 0, s, dev, L.n, it);
-                                else
-                                    hipLaunchKernelGGL((kb_cg_b<T, V, false, WT, PB, false>), gb, bb, 0, s, dev, L.n, it);
-                            }
-                        });
-                        fold_percol(L, 1);
-                        if (PRE == 1) fold_percol(L, 2);
-                    });
-                });
-                pre_pass(L);
-            }
-        }
+        // The first interval runs launch by launch in either mode (it also
+        // settles every lazily chosen tile before anything is captured).
+        if (launch_mode == FVX_LAUNCH_GRAPH && it > 0)
+            replay(batch);
+        else
+            for (int i = 0; i < batch; ++i) iteration();
+        it += batch;
         FVX_HIP(hipGetLastError());
         bool all_done = true;
         const int nj = int(jobs.size());
@@ -1125,6 +1311,7 @@ void check_opts(const fvx_op *op, const fvx_solve_opts *o) {
                 "precision must be FVX_F64 or FVX_MIXED");
     FVX_REQUIRE(o->guess == FVX_GUESS_ZERO || o->guess == FVX_GUESS_GIVEN, FVX_E_ARG, "bad guess mode");
     FVX_REQUIRE(o->poll_every >= 1, FVX_E_ARG, "poll_every must be >= 1");
+    FVX_REQUIRE(o->launch == FVX_LAUNCH_PHASES || o->launch == FVX_LAUNCH_GRAPH, FVX_E_ARG, "unknown launch mode");
     FVX_REQUIRE(o->precond == FVX_PRECOND_NONE || o->precond == FVX_PRECOND_JACOBI ||
                     o->precond == FVX_PRECOND_CHEBYSHEV || o->precond == FVX_PRECOND_AMG,
                 FVX_E_ARG, "unknown preconditioner");
@@ -1160,7 +1347,7 @@ void solve_f64_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<dou
         jobs.push_back(CgJob<double>{p.op, p.w.outer, p.B, p.X, p.w.bp, p.w.r, p.w.p0, p.w.p1, p.w.q,
                                      o->guess == FVX_GUESS_GIVEN, o->rtol, o->max_iter, p.w.z[0], p.w.z[1]});
     for (size_t i = 0; i < P.size(); ++i) jobs[i].amgw = &P[i].w.amg64;
-    run_cg_batch<double>(jobs, items, flags, o->poll_every, make_precond(o), s);
+    run_cg_batch<double>(jobs, items, flags, o->poll_every, make_precond(o), o->launch, s);
     for (auto &p : P) {
         p.h = read_state(p.w.outer, s);
         p.res2 = finish_f64(p.op, p.w.outer, p.X, p.w.bp, p.w.q, s);
@@ -1264,7 +1451,7 @@ void solve_mixed_batch(std::vector<Problem> &P, const fvx_solve_opts *o, BItem<f
             in_jobs.push_back(&p);
         }
         if (jobs.empty()) break;
-        run_cg_batch<float>(jobs, items, flags, o->poll_every, make_precond(o), s);
+        run_cg_batch<float>(jobs, items, flags, o->poll_every, make_precond(o), o->launch, s);
         for (Problem *pp : in_jobs) {
             Problem &p = *pp;
             const auto hi = read_state(p.w.inner, s);
@@ -1435,6 +1622,7 @@ int fvx_solve_opts_default(fvx_solve_opts *o) {
     o->cheb_degree = 8;
     o->cheb_ratio = 300.0;
     o->amg = nullptr;
+    o->launch = FVX_LAUNCH_GRAPH;
     return FVX_OK;
 }
 
@@ -1481,7 +1669,9 @@ int fvx_poisson_solve_noalloc(const fvx_op *op, const double *B, double *X, cons
         void *ws = fvx::noalloc_scratch();
         const double *Bs[1] = {B};
         double *Xs[1] = {X};
-        const int rc = fvx::solve_batch(1, ops, Bs, Xs, o, ws, FVX_NOALLOC_SCRATCH_BYTES, stats,
+        fvx_solve_opts phases = *o;  // graph capture allocates: launch phase by phase
+        phases.launch = FVX_LAUNCH_PHASES;
+        const int rc = fvx::solve_batch(1, ops, Bs, Xs, &phases, ws, FVX_NOALLOC_SCRATCH_BYTES, stats,
                                         fvx::as_stream(stream));
         if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (rc < 0) throw fvx::Error(rc, fvx_status_str(rc));
@@ -1581,6 +1771,7 @@ int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, voi
         o.max_outer = 1;
         o.max_iter = iters;
         o.poll_every = iters;
+        o.launch = FVX_LAUNCH_PHASES;  // the kernels' own time
         size_t sws = 0;
         fvx_solve_bytes(op, &o, &sws);
         sws = (sws + 255) / 256 * 256;

@@ -18,10 +18,16 @@ constexpr int kMaxPercolBlock = 256;  // independent planes: per-column partials
 constexpr int kMaxV = 4;
 constexpr int kMaxGroups = 256;
 
+// iter: the iteration the direction kernel last started (written by its block
+// 0, read by the update kernel that follows); next_it: the iteration the next
+// direction kernel runs (written by block 0 of the update kernel, 0 after
+// reset).  Each is read by a kernel in which no block writes it, so the
+// iteration kernels take no iteration argument and every iteration launches
+// the same kernels with the same arguments.
 struct CgState {
     int32_t done, status, rhs_projected, iter;
-    int32_t max_iter;
-    int32_t pad[3];
+    int32_t max_iter, next_it;
+    int32_t pad[2];
 };
 
 // Per-group scalars.  rho/active are double-buffered by iteration parity: the

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <functional>
 #include <memory>
@@ -16,6 +17,15 @@
 // ---------------------------------------------------------------------------
 // Host-side objects behind the opaque handles
 // ---------------------------------------------------------------------------
+
+namespace fvx {
+// A process-wide number that no later object takes again (an address can be
+// reused after a free; a serial cannot).  Cached launch graphs are keyed by it.
+inline uint64_t next_serial() {
+    static std::atomic<uint64_t> n{1};
+    return n.fetch_add(1);
+}
+}  // namespace fvx
 
 struct fvx_mesh {
     int n_cells = 0, n_faces = 0, n_walls = 0;
@@ -95,6 +105,7 @@ struct fvx_op {
     fvx::OpDev<float> d32;
     fvx_tile tile[2];
     fvx_tile cg_tile[2] = {};  // CG launch tile per precision (block 0: not set)
+    uint64_t serial = fvx::next_serial();
 };
 
 namespace fvx {
