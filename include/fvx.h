@@ -116,6 +116,19 @@ int fvx_mesh_from_faces(int n_cells, const double *area, const double *cx, const
                         int n_walls, const int32_t *wcell, const double *wlen,
                         const double *wdist, fvx_mesh **out);
 
+/* Cell order for locality (host only, no device work): perm[i] = index of
+ * the point visited i-th along a Hilbert curve over the points' bounding box
+ * (each axis scaled to a 2^16 grid; points in one grid cell keep index
+ * order).  x, y, perm: host arrays of n.  Numbering a base mesh's cells in
+ * this order (e.g. the triangles of fvx_mesh_triangles by their centroids)
+ * keeps the in-plane neighbours of a row close in memory, so the SpMM's
+ * gathers of the input multivector hit the caches: the reads of X move from
+ * the no-reuse case of Section 2, Eq. 3b, toward the read-once case of
+ * Eq. 3a.  The operator's rows follow the mesh's cell order, so the caller
+ * numbers its fields the same way.  FVX_E_ARG for NULL arrays (n > 0),
+ * n < 0 or n > INT32_MAX, or a non-finite coordinate. */
+int fvx_hilbert_order(int64_t n, const double *x, const double *y, int32_t *perm);
+
 /* Sizes of a mesh (any pointer may be NULL). */
 int fvx_mesh_info(const fvx_mesh *m, int64_t *n_cells, int64_t *n_faces, int64_t *n_walls);
 /* Copies the cell centres (host arrays of n_cells). */

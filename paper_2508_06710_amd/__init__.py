@@ -16,7 +16,7 @@ from ._lib import (DIRICHLET, F32, F64, GUESS_GIVEN, GUESS_NET, GUESS_ZERO, MIXE
                    LAUNCH_GRAPH, FvxError, SolveOpts, SolveStats,
                    Tile, check, lib)
 
-__all__ = ["Mesh", "Operator", "GuessNet", "SparseMatrix", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
+__all__ = ["Mesh", "hilbert_order", "Operator", "GuessNet", "SparseMatrix", "FvxError", "F64", "F32", "MIXED", "NONE", "PERIODIC_Z",
            "NEUMANN", "DIRICHLET", "PRECOND_NONE", "PRECOND_JACOBI", "PRECOND_CHEBYSHEV", "PRECOND_AMG", "LAUNCH_PHASES",
            "LAUNCH_GRAPH", "Amg", "lib"]
 
@@ -40,12 +40,27 @@ def _np_ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-class Mesh:
-    """A 2D finite-volume base mesh (host object)."""
+def hilbert_order(x, y):
+    """Host permutation that visits the points (x[i], y[i]) along a Hilbert
+    curve over their bounding box (fvx_hilbert_order)."""
+    xs = np.ascontiguousarray(x, dtype=np.float64)
+    ys = np.ascontiguousarray(y, dtype=np.float64)
+    if xs.shape != ys.shape or xs.ndim != 1:
+        raise ValueError("x and y must be 1-D arrays of one length")
+    perm = np.empty(len(xs), dtype=np.int32)
+    check(lib().fvx_hilbert_order(len(xs), _np_ptr(xs), _np_ptr(ys), _np_ptr(perm)), "fvx_hilbert_order")
+    return perm
 
-    def __init__(self, handle: C.c_void_p, keep=()):
+
+class Mesh:
+    """A 2D finite-volume base mesh (host object).  cell_perm: for a mesh
+    whose cells were renumbered at build time (order="hilbert"), new cell i is
+    cell cell_perm[i] of the input; None otherwise."""
+
+    def __init__(self, handle: C.c_void_p, keep=(), cell_perm=None):
         self._h = handle
         self._keep = keep
+        self.cell_perm = cell_perm
 
     @classmethod
     def cartesian(cls, nx, ny, x0=0.0, Lx=1.0, y0=0.0, y1=1.0, stretch=0.0, periodic_x=True,
@@ -56,21 +71,32 @@ class Mesh:
         return cls(h)
 
     @classmethod
-    def from_spec(cls, spec):
-        """From an ``inputs.CartSpec`` or ``inputs.TriSpec``."""
+    def from_spec(cls, spec, order=None):
+        """From an ``inputs.CartSpec`` or ``inputs.TriSpec`` (order: see
+        ``triangles``; a Cartesian base is already in line order)."""
         if hasattr(spec, "triangles"):
-            return cls.triangles(spec.points, spec.triangles)
+            return cls.triangles(spec.points, spec.triangles, order=order)
         return cls.cartesian(spec.nx, spec.ny, spec.x0, spec.Lx, spec.y0, spec.y1, spec.stretch,
                              spec.periodic_x, spec.periodic_y)
 
     @classmethod
-    def triangles(cls, points, tris):
+    def triangles(cls, points, tris, order=None):
+        """Triangle base; order="hilbert" numbers the cells along a Hilbert
+        curve of their vertex centroids (fvx_hilbert_order) and keeps the
+        permutation in cell_perm."""
         xy = np.ascontiguousarray(points, dtype=np.float64)
         tri = np.ascontiguousarray(tris, dtype=np.int32)
+        perm = None
+        if order == "hilbert":
+            cen = xy[tri].mean(axis=1)
+            perm = hilbert_order(cen[:, 0], cen[:, 1])
+            tri = np.ascontiguousarray(tri[perm])
+        elif order is not None:
+            raise ValueError(f"unknown cell order {order!r}")
         h = C.c_void_p()
         check(lib().fvx_mesh_triangles(len(xy), _np_ptr(xy), len(tri), _np_ptr(tri), C.byref(h)),
               "fvx_mesh_triangles")
-        return cls(h)
+        return cls(h, cell_perm=perm)
 
     @classmethod
     def from_faces(cls, area, c1, c2, length, dist, wcell=None, wlen=None, wdist=None,

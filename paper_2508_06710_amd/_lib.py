@@ -82,6 +82,7 @@ SIGNATURES = {
                                       C.c_int, _vp, _vp, _vp, _P(_vp)]),
     "fvx_mesh_info": (C.c_int, [_vp, _P(_i64), _P(_i64), _P(_i64)]),
     "fvx_mesh_centroids": (C.c_int, [_vp, _vp, _vp]),
+    "fvx_hilbert_order": (C.c_int, [_i64, _vp, _vp, _vp]),
     "fvx_mesh_faces": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fvx_mesh_destroy": (C.c_int, [_vp]),
     "fvx_op_bytes": (C.c_int, [_vp, _P(OpDesc), _P(C.c_size_t)]),

@@ -29,9 +29,9 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    # .cpp sources hold host code only; they get the same target so that no
+    # device pass is made for another architecture
     cmd = [HIPCC] + COMMON + DEVICE + ["-c", src, "-o", obj]
-    if src.endswith(".cpp"):
-        cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,10 +1,13 @@
 // Base meshes: 2D finite-volume face graphs (host side), plus the library's
 // error handling.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <tuple>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -366,6 +369,60 @@ int fvx_mesh_from_faces(int n_cells, const double *area, const double *cx, const
         }
         fvx::validate(*m);
         *out = m.release();
+        return FVX_OK;
+    });
+}
+
+namespace {
+
+// Distance along the Hilbert curve that fills the 2^bits x 2^bits grid, of
+// grid point (x, y): per level from the coarsest, the quadrant contributes
+// s^2 times its digit (3 rx) xor ry along the curve, then the point is
+// reflected and transposed into the sub-square's standard orientation.
+uint64_t hilbert_distance(uint32_t x, uint32_t y, int bits) {
+    const uint32_t n = 1u << bits;
+    uint64_t d = 0;
+    for (uint32_t s = n >> 1; s > 0; s >>= 1) {
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += uint64_t(s) * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n - 1 - x;
+                y = n - 1 - y;
+            }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+}  // namespace
+
+int fvx_hilbert_order(int64_t n, const double *x, const double *y, int32_t *perm) {
+    return guard([&] {
+        FVX_REQUIRE(n >= 0 && n <= INT32_MAX, FVX_E_ARG, "n out of range");
+        if (n == 0) return FVX_OK;
+        FVX_REQUIRE(x && y && perm, FVX_E_ARG, "NULL argument");
+        double lo[2] = {x[0], y[0]}, hi[2] = {x[0], y[0]};
+        for (int64_t i = 0; i < n; ++i) {
+            FVX_REQUIRE(std::isfinite(x[i]) && std::isfinite(y[i]), FVX_E_ARG, "non-finite coordinate");
+            lo[0] = std::min(lo[0], x[i]);
+            hi[0] = std::max(hi[0], x[i]);
+            lo[1] = std::min(lo[1], y[i]);
+            hi[1] = std::max(hi[1], y[i]);
+        }
+        constexpr int kBits = 16;
+        constexpr double kTop = double((1u << kBits) - 1);
+        auto grid = [&](double v, int a) -> uint32_t {
+            const double w = hi[a] - lo[a];
+            if (!(w > 0.0)) return 0;
+            const double g = std::floor((v - lo[a]) / w * kTop);
+            return uint32_t(std::min(std::max(g, 0.0), kTop));
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key(static_cast<size_t>(n));
+        for (int64_t i = 0; i < n; ++i) key[size_t(i)] = {hilbert_distance(grid(x[i], 0), grid(y[i], 1), kBits), int32_t(i)};
+        std::sort(key.begin(), key.end());  // ties: ascending index
+        for (int64_t i = 0; i < n; ++i) perm[i] = key[size_t(i)].second;
         return FVX_OK;
     });
 }

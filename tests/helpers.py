@@ -14,14 +14,19 @@ U32 = 2.0 ** -24
 class Case:
     """One (base mesh, k, dz, coupling, wall) case, on the GPU and in the oracle."""
 
-    def __init__(self, spec, k, dz=None, coupling=1, dirichlet=False, with_f32=True):
+    def __init__(self, spec, k, dz=None, coupling=1, dirichlet=False, with_f32=True, order=None):
         import paper_2508_06710_amd as fvx
         self.fvx = fvx
-        self.spec, self.k = spec, k
+        self.k = k
         self.dz = dz if dz is not None else math.pi / k
         self.coupling, self.dirichlet = coupling, dirichlet
-        self.op = fvx.Operator(fvx.Mesh.from_spec(spec), k, self.dz, coupling,
-                               fvx.DIRICHLET if dirichlet else fvx.NEUMANN, with_f32=with_f32)
+        mesh = fvx.Mesh.from_spec(spec, order=order)
+        if mesh.cell_perm is not None:
+            # the oracle assembles the same numbering from the renumbered triangles
+            spec = type(spec)(spec.points, np.ascontiguousarray(spec.triangles[mesh.cell_perm]), spec.name)
+        self.spec = spec
+        self.op = fvx.Operator(mesh, k, self.dz, coupling, fvx.DIRICHLET if dirichlet else fvx.NEUMANN,
+                               with_f32=with_f32)
         self.m3 = oracle.Mesh3D(oracle.geometry(spec), k, self.dz, coupling, dirichlet)
         self._L = self._M = self._G = None
 

@@ -161,3 +161,64 @@ def test_structured_stencil_rejections(fvx):
             fvx.expand_csr(mesh, args["k"], args["dz"], args["coupling"], args["wall_bc"], stencil=27)
     with pytest.raises(fvx.FvxError):
         fvx.expand_csr(cart, 4, 0.5, stencil=9)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 5])
+def test_hilbert_order_on_a_grid_is_the_hilbert_curve(fvx, b):
+    """On the 2^b x 2^b grid of integer points (shuffled), the order visits
+    every point once, each step goes to a unit neighbour, and the walk runs
+    from (0, 0) to (2^b - 1, 0): the defining properties of the Hilbert
+    curve in its standard orientation."""
+    n = 1 << b
+    gx, gy = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    x, y = gx.ravel().astype(float), gy.ravel().astype(float)
+    shuffle = np.random.default_rng(b).permutation(n * n)
+    x, y = x[shuffle], y[shuffle]
+    perm = fvx.hilbert_order(x, y)
+    assert sorted(perm.tolist()) == list(range(n * n))
+    px, py = x[perm], y[perm]
+    steps = np.abs(np.diff(px)) + np.abs(np.diff(py))
+    assert np.all(steps == 1)
+    assert (px[0], py[0]) == (0, 0) and (px[-1], py[-1]) == (n - 1, 0)
+
+
+def test_hilbert_order_edge_cases(fvx):
+    assert len(fvx.hilbert_order(np.zeros(0), np.zeros(0))) == 0
+    # equal points (and a zero-width box): index order
+    assert fvx.hilbert_order(np.ones(5), np.ones(5)).tolist() == [0, 1, 2, 3, 4]
+    # points on a horizontal line: sorted by x along the curve's bottom edge
+    x = np.array([3.0, 0.0, 2.0, 1.0])
+    assert fvx.hilbert_order(x, np.zeros(4)).tolist() == [1, 3, 2, 0]
+    with pytest.raises(fvx.FvxError):
+        fvx.hilbert_order(np.array([0.0, np.nan]), np.zeros(2))
+
+
+def test_hilbert_order_keeps_neighbours_close(fvx):
+    """Random points: consecutive points in the order are on average far
+    closer than in index order (about n^-1/2 of the box against a third)."""
+    rng = np.random.default_rng(3)
+    x, y = rng.random(20000), rng.random(20000)
+    perm = fvx.hilbert_order(x, y)
+    assert sorted(perm.tolist()) == list(range(len(x)))
+    step = np.hypot(np.diff(x[perm]), np.diff(y[perm])).mean()
+    assert step < 0.03 < np.hypot(np.diff(x), np.diff(y)).mean()
+
+
+def test_mesh_in_hilbert_order_renumbers_cells(fvx):
+    """A triangle mesh built with order="hilbert": cell i is input triangle
+    cell_perm[i] (centroids, areas and the face graph follow the permutation)."""
+    spec = inputs.unit_square_triangles(6)
+    m0 = fvx.Mesh.from_spec(spec)
+    m1 = fvx.Mesh.from_spec(spec, order="hilbert")
+    perm = m1.cell_perm
+    assert sorted(perm.tolist()) == list(range(len(spec.triangles)))
+    c0, c1 = m0.centroids(), m1.centroids()
+    assert np.array_equal(c1[0], c0[0][perm]) and np.array_equal(c1[1], c0[1][perm])
+    a0, f10, f20 = m0.faces()[:3]
+    a1, f11, f21 = m1.faces()[:3]
+    assert np.array_equal(a1, a0[perm])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    e0 = sorted(tuple(sorted(e)) for e in zip(inv[f10], inv[f20]))
+    e1 = sorted(tuple(sorted(e)) for e in zip(f11, f21))
+    assert e0 == e1
