@@ -414,7 +414,7 @@ size_t plan_bytes(const Plan &P, bool f32) {
 // Restriction of the residual to the aggregates: rc[c] = sum over the
 // members i of aggregate c of (r - A z)_i = r_i + (L z)_i; a.n_rows is the
 // number of aggregates, the row computation is the fine level's.
-template <typename T, int V, bool Z, int WT>
+template <typename T, int V, bool Z, int WT, int MW>
 __global__ __launch_bounds__(kMaxCgBlock) void k_amg_restrict(RowArgs<T> a, const CgState *__restrict__ st,
                                                               const int32_t *__restrict__ mptr,
                                                               const int32_t *__restrict__ midx,
@@ -429,7 +429,23 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_amg_restrict(RowArgs<T> a, cons
         vec_t<T, V> sum(0);
         int32_t p = mptr[row];
         const int32_t pe = mptr[row + 1];
-        // Two members per step, so that their loads overlap; summed in member order.
+        // MW = 4: four (then two) members per step, one round of loads for the
+        // usual aggregate of up to four cells, for the small grids of the
+        // coarse levels (one block per CU or fewer: latency, not occupancy,
+        // sets their time); MW = 2 elsewhere (fewer registers).  Summed in
+        // member order either way.
+        for (; MW == 4 && p + 4 <= pe; p += 4) {
+            const int64_t i0 = midx[p], i1 = midx[p + 1], i2 = midx[p + 2], i3 = midx[p + 3];
+            vec_t<T, V> z0, z1, z2, z3;
+            const vec_t<T, V> a0 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i0, c0, sub, lpr, single, z0);
+            const vec_t<T, V> a1 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i1, c0, sub, lpr, single, z1);
+            const vec_t<T, V> a2 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i2, c0, sub, lpr, single, z2);
+            const vec_t<T, V> a3 = lap_row_ld<T, V, Z, WT>(a.A, in, a.n_b, a.k, a.W, i3, c0, sub, lpr, single, z3);
+            sum += ldv<T, V>(r + i0 * a.ld + c0) + a0;
+            sum += ldv<T, V>(r + i1 * a.ld + c0) + a1;
+            sum += ldv<T, V>(r + i2 * a.ld + c0) + a2;
+            sum += ldv<T, V>(r + i3 * a.ld + c0) + a3;
+        }
         for (; p + 2 <= pe; p += 2) {
             const int64_t i0 = midx[p], i1 = midx[p + 1];
             vec_t<T, V> z0, z1;
@@ -526,28 +542,53 @@ __global__ __launch_bounds__(kMaxCgBlock) void k_amg_cheb(RowArgs<T> a, CgDev d,
     b_cheb<T, V, Z, WT, MODE, LAST>(a, d, vb_single(a.remap), r, zin, zio, c1, c2, inv_theta);
 }
 
-// Coarsest level: z = A^+ r with the dense pseudo-inverse, one wavefront per
-// output (cell i, plane l).  Coupled planes: the system index is i * k + l;
-// independent planes: every plane uses the same [n_b][n_b] matrix.
+// Coarsest level: z = A^+ r with the dense pseudo-inverse.  Coupled planes
+// (one system of n_b * k unknowns, system index i * k + l): one block per
+// output, each thread taking every 256th term of the row, all its loads in
+// flight at once (the row has at most kMaxAmgCoarse terms), then a block
+// reduction.  Independent planes (every plane uses the same [n_b][n_b]
+// matrix): one wavefront per output (cell i, plane l).
+constexpr int kDenseBlock = 256;
+constexpr int kCoarseGridBlocks = 256;  // MI355X compute units
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_amg_dense(const CgState *__restrict__ st, const T *__restrict__ pinv,
-                                                   int n_b, int k, int ld, int coupled, const T *__restrict__ r,
-                                                   T *__restrict__ z) {
+__global__ __launch_bounds__(kDenseBlock) void k_amg_dense(const CgState *__restrict__ st, const T *__restrict__ pinv,
+                                                           int n_b, int k, int ld, int coupled,
+                                                           const T *__restrict__ r, T *__restrict__ z) {
     if (st->done) return;
+    if (coupled) {
+        __shared__ double part[kDenseBlock / 64];
+        const int nd = n_b * k;
+        const int out = int(blockIdx.x);
+        const T *row = pinv + int64_t(out) * nd;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kMaxAmgCoarse / kDenseBlock; ++u) {
+            const int p = int(threadIdx.x) + u * kDenseBlock;
+            if (p < nd) {
+                const int j = p / k;
+                s += double(row[p]) * double(r[int64_t(j) * ld + (p - j * k)]);
+            }
+        }
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kDenseBlock / 64; ++w) t += part[w];
+            const int i = out / k;
+            z[int64_t(i) * ld + (out - i * k)] = T(t);
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t out = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     if (out >= int64_t(n_b) * k) return;  // uniform over the wavefront
     const int64_t i = out / k;
     const int l = int(out % k);
+    const T *row = pinv + i * n_b;
     double s = 0.0;
-    if (coupled) {
-        const int64_t nd = int64_t(n_b) * k;
-        const T *row = pinv + out * nd;
-        for (int64_t p = lane; p < nd; p += 64) s += double(row[p]) * double(r[(p / k) * ld + p % k]);
-    } else {
-        const T *row = pinv + i * n_b;
-        for (int64_t j = lane; j < n_b; j += 64) s += double(row[j]) * double(r[j * ld + l]);
-    }
+    for (int64_t j = lane; j < n_b; j += 64) s += double(row[j]) * double(r[j * ld + l]);
     s = wave_sum(s);
     if (lane == 0) z[i * ld + l] = T(s);
 }
@@ -743,8 +784,14 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
                 constexpr bool Z = decltype(Zt)::value;
                 by_width(op->W, [&](auto Wt) {
                     constexpr int WT = decltype(Wt)::value;
-                    hipLaunchKernelGGL((k_amg_restrict<T, V, Z, WT>), R.grid, R.block, 0, s, R.a, d.st,
-                                       h->lv[l].mem_ptr, h->lv[l].mem_idx, r, zs, w.lv[l + 1].r);
+                    // a grid of at most one block per CU is latency-bound: take
+                    // four members per step (not at width 8, where it spills)
+                    if (WT != 8 && int(R.grid.x) <= kCoarseGridBlocks)
+                        hipLaunchKernelGGL((k_amg_restrict<T, V, Z, WT, WT == 8 ? 2 : 4>), R.grid, R.block, 0, s,
+                                           R.a, d.st, h->lv[l].mem_ptr, h->lv[l].mem_idx, r, zs, w.lv[l + 1].r);
+                    else
+                        hipLaunchKernelGGL((k_amg_restrict<T, V, Z, WT, 2>), R.grid, R.block, 0, s, R.a, d.st,
+                                           h->lv[l].mem_ptr, h->lv[l].mem_idx, r, zs, w.lv[l + 1].r);
                 });
             });
         } else {
@@ -761,7 +808,8 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
     {
         const fvx_op *op = h->lv[nl - 1].op;
         const int64_t outs = op->n_b * int64_t(op->k);
-        hipLaunchKernelGGL(k_amg_dense<T>, dim3(unsigned(ceil_div(outs, 4))), dim3(256), 0, s, d.st, pinv_of<T>(h),
+        const unsigned dense_grid = unsigned(h->coupled ? outs : ceil_div(outs, kDenseBlock / 64));
+        hipLaunchKernelGGL(k_amg_dense<T>, dim3(dense_grid), dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
                            int(op->n_b), op->k, op->ld, int(h->coupled), rhs(nl - 1), w.lv[nl - 1].q[0]);
         FVX_HIP(hipGetLastError());
         if (nl == 1 && fin) {
