@@ -38,7 +38,8 @@ constexpr int kCin[kLayers] = {2, kC, kC, kC};
 constexpr int kCout[kLayers] = {kC, kC, kC, 1};
 constexpr int kBlock = 256;
 constexpr int kChunk = 8;        // channels of weights staged in LDS at a time
-constexpr int kPosBlocks = 256;  // position ranges of the weight-gradient reduction
+constexpr int kPosBlocks = 256;  // position ranges of the weight-gradient reduction (32 -> 32 layers)
+constexpr int kMaxPosBlocks = 2048;  // ... and at most, for the smaller layers
 constexpr int kTile = 64;        // positions staged per pass of the weight gradient
 constexpr int kLossBlocks = 256;
 
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd_mfma(Grid g, int ns, const 
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[b][r] = bv;
     }
+#pragma unroll  // constant dz: the tap offsets t[b].z[dz] stay in registers
     for (int dz = 0; dz < 3; ++dz) {
         __syncthreads();
         for (int i = threadIdx.x; i < 9 * CI * CO; i += blockDim.x) {
@@ -357,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_bwd_data_mfma(Grid g, int ns, c
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
+#pragma unroll  // constant dz: the tap offsets t[b].z[dz] stay in registers
     for (int dz = 0; dz < 3; ++dz) {
         __syncthreads();
         for (int i = threadIdx.x; i < 9 * CO * CI; i += blockDim.x) {
@@ -444,6 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_bwd_w(Grid g, int ns, int CI, c
         __syncthreads();
         if (mine) {
             const float *src = in + ci * g.cells;
+#pragma unroll 8  // eight gathers in flight; each accumulator still sums in position order
             for (int j = 0; j < nt; ++j) {
                 const int xs = wrap(p_s[4 * j + 1] + dx - 1, g.X);
                 const int ys = min(max(p_s[4 * j + 2] + dy - 1, 0), g.Y - 1);
@@ -464,6 +468,198 @@ __global__ __launch_bounds__(kBlock) void k_conv_bwd_w(Grid g, int ns, int CI, c
     if (do_bias) out[npair * CO + threadIdx.x] = bacc;
 }
 
+// Weight gradient of a layer with 32 output channels on the matrix cores:
+//   dW[co][ci][tap] = sum_pos dout[co][pos] in[ci][src(pos, tap)]
+// as a GEMM with M = 32 output channels, N = the (ci, tap) pairs in column
+// blocks of 32 and K = the block's positions, two at a time
+// (v_mfma_f32_32x32x2_f32; operand and accumulator layouts as in
+// k_conv_fwd_mfma).  CI = 32: column block cb is tap cb with ci = column;
+// CI < 32: column n of block cb is pair 32 cb + n = ci * 27 + tap.  Per chunk
+// of 64 positions the block stages dout as [position][co]; in round q, wave
+// w gathers column block 4 q + w of the input as [position][column] (one
+// position per lane: coalesced along the positions) and runs 32 MFMAs on it.
+// The bias gradient and the partials' layout are those of k_conv_bwd_w, so
+// k_fold_w sums them in the same fixed order.
+constexpr int kWChunk = 64;
+constexpr int kWPad = kC + 1;  // LDS row stride: conflict-free column writes
+
+template <int CI>
+__global__ __launch_bounds__(kBlock) void k_conv_bwd_w_mfma(Grid g, int ns, const float *__restrict__ dout,
+                                                            const float *__restrict__ in, int per,
+                                                            float *__restrict__ part) {
+    constexpr int CO = kC, NPAIR = CI * kTaps, NCB = (NPAIR + 31) / 32, ROUNDS = (NCB + 3) / 4;
+    __shared__ float d_s[kWChunk * kWPad];     // [k][co]
+    __shared__ float a_s[4][kWChunk * kWPad];  // per wave: [k][column]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 31, hi = lane >> 5;
+    const int total = g.cells * ns;
+    const int p0 = int(blockIdx.x) * per, p1 = min(total, p0 + per);
+    float *a_w = a_s[wave];
+    mfma_acc16 acc[ROUNDS];
+#pragma unroll
+    for (int q = 0; q < ROUNDS; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    float bacc = 0.0f;
+    for (int c0 = p0; c0 < p1; c0 += kWChunk) {
+        const int nt = min(kWChunk, p1 - c0);
+        __syncthreads();  // the previous chunk's reads of d_s are done
+        for (int i = threadIdx.x; i < kWChunk * CO; i += kBlock) {
+            const int k = i % kWChunk, co = i / kWChunk;
+            float v = 0.0f;
+            if (k < nt) {
+                const Pos p = pos_of(g, c0 + k);
+                v = dout[(p.n * CO + co) * g.cells + p.cell];
+            }
+            d_s[k * kWPad + co] = v;
+        }
+        // this lane's position of the chunk (lane < nt)
+        const bool mine = lane < nt;
+        const Pos pk = pos_of(g, mine ? c0 + lane : p0);
+        const float *in_n = in + int64_t(pk.n) * CI * g.cells;
+        auto src_cell = [&](int tap) {
+            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+            const int xs = wrap(pk.x + dx - 1, g.X);
+            const int ys = min(max(pk.y + dy - 1, 0), g.Y - 1);
+            const int zs = wrap(pk.z + dz - 1, g.Z);
+            return (zs * g.Y + ys) * g.X + xs;
+        };
+        __syncthreads();
+        if (threadIdx.x < CO)
+            for (int k = 0; k < nt; ++k) bacc += d_s[k * kWPad + threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < ROUNDS; ++q) {
+            const int cb = 4 * q + wave;  // uniform over the wave
+            if (cb < NCB) {
+                float v[32];
+                if constexpr (CI == 32) {
+                    // all 32 loads in flight (staging them in two halves of 16 gave two
+                    // waves per SIMD but measured slower: 560 -> 600 us)
+                    const float *src = in_n + src_cell(cb);
+#pragma unroll
+                    for (int n = 0; n < 32; ++n) v[n] = mine ? src[int64_t(n) * g.cells] : 0.0f;
+#pragma unroll
+                    for (int n = 0; n < 32; ++n) a_w[lane * kWPad + n] = v[n];
+                } else {
+#pragma unroll
+                    for (int n = 0; n < 32; ++n) {
+                        const int pr = 32 * cb + n;
+                        v[n] = (mine && pr < NPAIR) ? in_n[int64_t(pr / kTaps) * g.cells + src_cell(pr % kTaps)] : 0.0f;
+                    }
+#pragma unroll
+                    for (int n = 0; n < 32; ++n) a_w[lane * kWPad + n] = v[n];
+                }
+            }
+            __syncthreads();  // a_w written (each wave reads only its own)
+            if (cb < NCB) {
+#pragma unroll
+                for (int k0 = 0; k0 < kWChunk; k0 += 2) {
+                    const float a = d_s[(k0 + hi) * kWPad + lo];
+                    const float b = a_w[(k0 + hi) * kWPad + lo];
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[q], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // a_w read before the next round overwrites it
+        }
+    }
+    float *out = part + size_t(blockIdx.x) * (size_t(NPAIR) * CO + CO);
+#pragma unroll
+    for (int q = 0; q < ROUNDS; ++q) {
+        const int cb = 4 * q + wave;
+        const int pr = CI == 32 ? lo * kTaps + cb : 32 * cb + lo;
+        if (cb >= NCB || pr >= NPAIR) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[pr * CO + 8 * (r / 4) + 4 * hi + (r % 4)] = acc[q][r];
+    }
+    if (threadIdx.x < CO) out[NPAIR * CO + threadIdx.x] = bacc;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Weight gradient of the output layer (32 -> 1 channel) on the matrix cores,
+// with the tap moved from the input onto the output gradient (the adjoint of
+// the padding, as in the data gradient):
+//   dW[0][ci][tap] = sum_p in[ci][p] adj(dout)(p, tap),
+// adj(dout)(p, tap) = the sum of dout over the outputs that read p through
+// tap.  M = 32 input channels, N = the 27 taps (padded to 32), K = positions,
+// two at a time.  Wave w takes chunks w, w + 4, ... of 64 positions of the
+// block's range: each lane stages its position's 32 inputs and 27 adjoint
+// taps in LDS as [position][column] and the wave runs 32 MFMAs; the four
+// waves' sums are added in wave order.  Partials: part[bx][ci * 27 + tap] and
+// the bias gradient (sum of dout) at part[bx][32 * 27].
+__global__ __launch_bounds__(kBlock) void k_conv_bwd_w1_mfma(Grid g, int ns, const float *__restrict__ dout,
+                                                             const float *__restrict__ in, int per,
+                                                             float *__restrict__ part) {
+    constexpr int CI = kC;
+    __shared__ float i_s[4][kWChunk * kWPad];  // per wave: [k][ci]
+    __shared__ float d_s[4][kWChunk * kWPad];  // per wave: [k][tap]
+    __shared__ float b_s[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lo = lane & 31, hi = lane >> 5;
+    const int total = g.cells * ns;
+    const int p0 = int(blockIdx.x) * per, p1 = min(total, p0 + per);
+    const int nchunk = (p1 - p0 + kWChunk - 1) / kWChunk;
+    float *iw = i_s[wave], *dw = d_s[wave];
+    mfma_acc16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    float bsum = 0.0f;
+    for (int j0 = 0; j0 < nchunk; j0 += 4) {  // the same trip count in every wave
+        const int j = j0 + wave;
+        const int c0 = p0 + j * kWChunk;
+        const bool live = j < nchunk && c0 + lane < p1;
+        const Pos pk = pos_of(g, live ? c0 + lane : p0);
+        const float *src = in + int64_t(pk.n) * CI * g.cells + pk.cell;
+        const float *dn = dout + int64_t(pk.n) * g.cells;
+        const AdjTaps t = adj_taps(g, pk.x, pk.y, pk.z);
+        float v[CI], a[kTaps];
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) v[ci] = live ? src[int64_t(ci) * g.cells] : 0.0f;
+#pragma unroll
+        for (int tap = 0; tap < kTaps; ++tap) {
+            const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+            const int ya = t.ya[dy], yb = t.yb[dy];
+            // both reads in bounds (offset 0 stands in for a missing row), selected without a branch
+            const float *d = dn + t.z[dz] + t.x[dx];
+            const float va = d[max(ya, 0)], vb = d[max(yb, 0)];
+            a[tap] = live ? (ya >= 0 ? va : 0.0f) + (yb >= 0 ? vb : 0.0f) : 0.0f;
+        }
+        bsum += wave_sum_f(live ? dn[pk.cell] : 0.0f);
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) iw[lane * kWPad + ci] = v[ci];
+#pragma unroll
+        for (int n = 0; n < 32; ++n) dw[lane * kWPad + n] = n < kTaps ? a[n] : 0.0f;
+        __syncthreads();
+#pragma unroll
+        for (int k0 = 0; k0 < kWChunk; k0 += 2) {
+            const float x = iw[(k0 + hi) * kWPad + lo];
+            const float y = dw[(k0 + hi) * kWPad + lo];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[ci][tap]: register r of lane l holds ci = 8 (r / 4) + 4 (l / 32) + r % 4, tap = l % 32
+    float *red = &i_s[0][0];  // [wave][r][lane] (4096 floats of the 4 x 2112), reused after the last barrier
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[r];
+    if (lane == 0) b_s[wave] = bsum;
+    __syncthreads();
+    float *out = part + size_t(blockIdx.x) * (size_t(CI) * kTaps + 1);
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            float s = 0.0f;
+            for (int w = 0; w < 4; ++w) s += red[(w * 16 + r) * 64 + lane];
+            if (lo < kTaps) out[(8 * (r / 4) + 4 * hi + (r % 4)) * kTaps + lo] = s;
+        }
+        if (lane == 0) out[CI * kTaps] = ((b_s[0] + b_s[1]) + b_s[2]) + b_s[3];
+    }
+}
+
 // Gradients of one layer (weights [co][ci][tap], biases) = sum over the
 // position blocks of the partials, in block order.
 __global__ __launch_bounds__(kBlock) void k_fold_w(const float *__restrict__ part, int nblk, int CI, int CO,
@@ -472,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_fold_w(const float *__restrict__ par
     const int stride = npair * CO + CO;
     for (int v = int(blockIdx.x) * blockDim.x + threadIdx.x; v < stride; v += gridDim.x * blockDim.x) {
         float s = 0.0f;
+#pragma unroll 8  // loads in flight; the sum keeps block order
         for (int b = 0; b < nblk; ++b) s += part[size_t(b) * stride + v];
         if (v < npair * CO) {
             const int pr = v / CO, co = v % CO;
@@ -644,17 +841,31 @@ double backward(fvx_net *n, int ns, const float *in, const float *target, hipStr
     hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kBlock), 0, s, n->act[4], target, nout, n->g0, n->lossp);
     FVX_HIP(hipGetLastError());
     float *dcur = n->g0, *dnext = n->g1;
-    const int per = int(ceil_div(nout, kPosBlocks));
-    const int nblk = int(ceil_div(nout, per));
     const int64_t threads2 = ceil_div(nout, 2);
     for (int l = kLayers - 1; l >= 0; --l) {
         const int CI = kCin[l], CO = kCout[l];
         const float *W = n->params + layer_offset(l);
         float *gw = n->grads + layer_offset(l), *gb = gw + w_size(l);
         const float *lin = l == 0 ? in : n->act[l];
+        // Position blocks of the weight-gradient partials: as many as the
+        // partial buffer holds for this layer, at most kMaxPosBlocks and at
+        // least 64 positions each (short per-thread chains for the small
+        // layers; 256 blocks for the 32 -> 32 layers).
+        const int64_t stride = int64_t(CI) * kTaps * CO + CO;
+        const int64_t want = std::min<int64_t>(std::min<int64_t>(kMaxPosBlocks, part_floats() / stride),
+                                               ceil_div(nout, 64));
+        const int per = int(ceil_div(nout, std::max<int64_t>(1, want)));
+        const int nblk = int(ceil_div(nout, per));
         const dim3 wgrid(unsigned(nblk), unsigned(ceil_div(CI * kTaps, kBlock)));
-        if (CO == kC)
-            hipLaunchKernelGGL((k_conv_bwd_w<kC>), wgrid, dim3(kBlock), 0, s, g, ns, CI, dcur, lin, per, n->part);
+        if (CO == kC && CI == kC)
+            hipLaunchKernelGGL((k_conv_bwd_w_mfma<kC>), dim3(unsigned(nblk)), dim3(kBlock), 0, s, g, ns, dcur, lin,
+                               per, n->part);
+        else if (CO == kC && CI == 2)
+            hipLaunchKernelGGL((k_conv_bwd_w_mfma<2>), dim3(unsigned(nblk)), dim3(kBlock), 0, s, g, ns, dcur, lin,
+                               per, n->part);
+        else if (CO == 1 && CI == kC)
+            hipLaunchKernelGGL(k_conv_bwd_w1_mfma, dim3(unsigned(nblk)), dim3(kBlock), 0, s, g, ns, dcur, lin, per,
+                               n->part);
         else
             hipLaunchKernelGGL((k_conv_bwd_w<1>), wgrid, dim3(kBlock), 0, s, g, ns, CI, dcur, lin, per, n->part);
         hipLaunchKernelGGL(k_fold_w, dim3(64), dim3(kBlock), 0, s, n->part, nblk, CI, CO, gw, gb);

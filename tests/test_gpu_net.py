@@ -105,7 +105,10 @@ def test_forward_full_size_batch_sampled():
     assert np.max(np.abs(got - ref)) <= FWD_TOL * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("nx,ny,nz,ns", GRIDS[:4])
+# (32, 16, 8, 5): 20,480 positions, more than the 256 position blocks of the
+# 32 -> 32 layers' weight gradient hold in one 64-position chunk each, so each
+# block takes a full chunk and a ragged one.
+@pytest.mark.parametrize("nx,ny,nz,ns", GRIDS[:4] + [(32, 16, 8, 5)])
 def test_gradients_match_oracle(nx, ny, nz, ns):
     p = _params()
     x = _samples(ns, nz, ny, nx, 2)
