@@ -367,6 +367,12 @@ def counters_mode(fvx, inputs, torch):
             op.lap(X[8 * n + i], Y[8 * n + i])
         log(f"counters: 8 launches of {lap_kernel_name(t, op.k)} (tile {t})")
     op.set_tile(*tile)
+    # 24 iterations of the plain FP64 CG with the tuned CG tile, launched
+    # phase by phase (the direction kernel kb_cg_a and the update kernel kb_cg_b)
+    tune_cg(op, fvx)
+    B = op.to_rows(inputs.rhs_uniform(3, op.n_b * op.k))
+    op.solve(B, rtol=1e-300, max_iter=24, poll_every=24, launch=fvx.LAUNCH_PHASES, allow_not_converged=True)
+    log("counters: 24 CG iterations")
     nbytes = 256 * 2 ** 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = [torch.empty_like(src) for _ in range(2)]
@@ -418,15 +424,25 @@ def summarize_counters(fetch_dir, write_dir, flops_dir, out=COUNTER_FILE):
     nb, k = BASE[0] * BASE[1], K_MAIN
     nnz_b = nb + 2 * (BASE[0] * BASE[1] * 2 - BASE[0])  # periodic x faces + interior y faces, 5-point base
     alg = spmm_bytes(nnz_b, nb, k)
+    # The CG kernels on the Cartesian base: per base row one 64-byte record
+    # (meta_cart) and, per vector pass, k FP64 values; the direction kernel
+    # reads r and p and writes p' (3 passes), the update kernel reads p', x and
+    # r and writes x and r (5 passes).  Their five vectors (63 MB) fit in the
+    # 256 MB Infinity Cache, so FETCH_SIZE counts reads from the fabric
+    # (Infinity Cache hits included), not HBM reads alone.
+    vec, rec_b = nb * k * 8, nb * 64
+    cg_alg = {"kb_cg_a": 3 * vec + rec_b, "kb_cg_b": 5 * vec + rec_b}
     by_kernel = {}
     for name in fk:
-        if not name.startswith("k_lap"):
+        base = name.split("<")[0]
+        if not (name.startswith("k_lap") or base in cg_alg):
             continue
+        alg_n = cg_alg.get(base, alg)
         f = med(fk[name], "FETCH_SIZE") * 1024 * fs
         w = med(wk.get(name, [{}]), "WRITE_SIZE") * 1024 * ws
         e = {"kernel": name, "dispatches": len(fk[name]), "fetch_kib_per_dispatch": med(fk[name], "FETCH_SIZE"),
              "write_kib_per_dispatch": med(wk.get(name, [{}]), "WRITE_SIZE"), "fetch_bytes_per_launch": f,
-             "write_bytes_per_launch": w, "traffic_over_algorithmic": (f + w) / alg}
+             "write_bytes_per_launch": w, "algorithmic_bytes": alg_n, "traffic_over_algorithmic": (f + w) / alg_n}
         if name in pk:
             lst = pk[name]
             # the counter adds each FP64 VALU instruction's flops per lane (FMA 2,
@@ -434,7 +450,8 @@ def summarize_counters(fetch_dir, write_dir, flops_dir, out=COUNTER_FILE):
             e["fp64_flops_counted"] = 64 * med(lst, "SQ_INSTS_VALU_FLOPS_FP64")
             e["fp64_flops_from_insts"] = 64 * (med(lst, "SQ_INSTS_VALU_ADD_F64") + med(lst, "SQ_INSTS_VALU_MUL_F64")
                                                + 2 * med(lst, "SQ_INSTS_VALU_FMA_F64"))
-            e["fp64_flops_algorithmic"] = spmm_flops(nnz_b, nb, k)
+            if base not in cg_alg:
+                e["fp64_flops_algorithmic"] = spmm_flops(nnz_b, nb, k)
         by_kernel[name] = e
     rec = {"workload": f"channel {BASE[0]}x{BASE[1]} base x {K_MAIN} periodic planes, FP64, cold (rotating buffers > 1 GiB)",
            "commands": ["rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --counters",

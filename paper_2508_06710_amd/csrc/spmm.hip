@@ -501,8 +501,13 @@ __global__ __launch_bounds__(1024) void k_div(RowArgs<T> a, const T *__restrict_
 // interpolation of the cell values to the face).  Each cell gathers, for each
 // of its faces, the face velocity and the value of the cell across the face;
 // the faces between planes take the neighbouring planes from the row itself.
+// At most 512 threads per block: under a 1024-thread bound the compiler caps
+// the kernel at 128 registers, and the wider face rows (6 and 8 faces per cell)
+// spilled to scratch.
+constexpr int kConvectBlock = 512;
+
 template <typename T, int V, bool Z, int WT>
-__global__ __launch_bounds__(1024) void k_convect(RowArgs<T> a, const T *__restrict__ U, const T *__restrict__ Wz,
+__global__ __launch_bounds__(kConvectBlock) void k_convect(RowArgs<T> a, const T *__restrict__ U, const T *__restrict__ Wz,
                                                   const T *__restrict__ Phi, T *__restrict__ Out) {
     const int lpr = a.lpr;
     const int sub = threadIdx.x & (lpr - 1);
@@ -843,7 +848,8 @@ void launch_div(const fvx_op *op, const T *U, const T *Wz, T *D, hipStream_t s) 
 template <typename T>
 void launch_convect(const fvx_op *op, const T *U, const T *Wz, const T *Phi, T *Out, hipStream_t s) {
     RowGrid g;
-    const fvx_tile &t = op->tile[dtype_of<T>()];
+    fvx_tile t = op->tile[dtype_of<T>()];
+    t.block = std::min(t.block, kConvectBlock);  // rows are independent: any block size gives the same result
     auto a = row_args<T>(op, op->n_b, g, t);
     by_vec<T>(t.vec, op->zfaces, [&](auto V, auto Z) {
         by_width(op->Wd, [&](auto Wt) {
