@@ -351,7 +351,7 @@ typedef struct fvx_solve_opts {
  *           Capturing allocates host and driver resources, so
  *           fvx_poisson_solve_noalloc always launches phase by phase.
  *           Dropping a cached configuration synchronises the device.
- *           On MI355X the replay saves 1-4 % per solve (the GPU's own time
+ *           On MI355X the replay saves 0-3 % per solve (the GPU's own time
  *           per dependent kernel, not the host's launch cost, bounds these
  *           iterations); the first solve of a configuration pays the capture
  *           (about 15 % of a plain-CG solve of 1.57 M unknowns). */
