@@ -54,7 +54,8 @@ typedef enum fvx_status {
     FVX_E_HIP = -4,          /* a HIP runtime call failed (text in fvx_last_error) */
     FVX_E_BREAKDOWN = -5,    /* CG breakdown: p.Ap <= 0 with nonzero residual, or non-finite */
     FVX_E_NONFINITE = -6,    /* NaN/Inf in the right-hand side or initial guess */
-    FVX_E_UNSUPPORTED = -7   /* valid request this build does not provide */
+    FVX_E_UNSUPPORTED = -7,  /* valid request this build does not provide */
+    FVX_E_IO = -8            /* a file could not be opened, read or written, or is not the expected format */
 } fvx_status;
 
 enum { FVX_F64 = 0, FVX_F32 = 1, FVX_MIXED = 2 };
@@ -258,6 +259,27 @@ int fvx_op_set_cg_tile(fvx_op *op, int dtype, const fvx_tile *tile);
 int fvx_tune_cg_bytes(const fvx_op *op, int dtype, size_t *bytes);
 int fvx_tune_cg(fvx_op *op, int dtype, void *ws, size_t ws_bytes, int iters, void *stream,
                 fvx_tune_result *results, int max_results, int *n_results);
+
+/* The autotuners behind a tile cache file: the tile stored for this
+ * operator's key is set without timing anything (*from_cache = 1); when the
+ * key is absent (or its tile is not valid for this build) the tuner runs
+ * (fvx_tune, fvx_tune_cg: same scratch/workspace and reps/iters arguments),
+ * its choice is set and stored (*from_cache = 0).  *tile (may be NULL)
+ * receives the tile in use.  Keys:
+ *   "<arch>|<f64|f32>|k=<k>|ld=<ld>|n_b=<n_b>|nnz_b=<nnz_b>|stencil=<7|13|27>"
+ *   "cg|<arch>|<f64|f32>|k=<k>|ld=<ld>|n_b=<n_b>|nnz_b=<nnz_b>|coupling=<0|1>"
+ * with <arch> the device's architecture name ("gfx950").  The file is a JSON
+ * object of entries {"tile": [vec, lanes_per_row, block, xcd_remap,
+ * max_blocks, stage_lds, nt_store], "us" or "us_per_iter", "candidates",
+ * ...}; other entries and members are kept when the file is rewritten (sorted
+ * keys, one-space indentation, written to "<path>.tmp" and renamed over the
+ * file).  cache_path NULL: tune without a cache.  Writers within one process
+ * are serialised; processes sharing a file may each tune a key once.
+ * FVX_E_IO for an unreadable or malformed file or a failed write. */
+int fvx_tune_cached(fvx_op *op, int dtype, const char *cache_path, void *scratch, size_t scratch_bytes, int reps,
+                    void *stream, fvx_tile *tile, int *from_cache);
+int fvx_tune_cg_cached(fvx_op *op, int dtype, const char *cache_path, void *ws, size_t ws_bytes, int iters,
+                       void *stream, fvx_tile *tile, int *from_cache);
 
 /* Laplacian SpMM (Algorithm 1 with the plane coupling):
  *   Y[i][l] = s_l ( sum_j A_b[i][j] X[j][l] + w_i (X[i][l+1 mod k] + X[i][l-1 mod k]) )
@@ -565,6 +587,19 @@ int fvx_net_get_params(const fvx_net *net, float *params, float *grads);
 
 /* Replaces the parameters and clears the Adam state.  Synchronises `stream`. */
 int fvx_net_set_params(fvx_net *net, const float *params, void *stream);
+
+/* Checkpoint of a network in a file: the parameters, the Adam moments and
+ * the number of Adam steps taken, so that training resumes exactly where it
+ * stopped.  Format (the host's byte order, little-endian on x86-64 hosts):
+ * the 8 bytes "FVXNET01", int32 n_params (= fvx_net_n_params()), int32
+ * steps, then float32 params[n_params], m[n_params], v[n_params].  The
+ * parameters do not depend on the grid: a checkpoint loads into a network of
+ * any grid and batch.  Both calls synchronise `stream`.  Errors: FVX_E_ARG
+ * for a NULL net or path; FVX_E_IO when the file cannot be opened, read or
+ * written, or its magic or parameter count differ (the network is then left
+ * unchanged). */
+int fvx_net_save(const fvx_net *net, const char *path, void *stream);
+int fvx_net_load(fvx_net *net, const char *path, void *stream);
 
 /* out = net(in) for ns samples (device arrays as above). */
 int fvx_net_forward(fvx_net *net, int ns, const float *in, float *out, void *stream);

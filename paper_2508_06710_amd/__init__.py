@@ -7,6 +7,7 @@ stream.  See include/fvx.h for the operations, layouts and error behaviour.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -300,32 +301,20 @@ class Operator:
                                 max_results, C.byref(n)), "fvx_tune_cg")
         return [(res[i].tile.as_tuple(), res[i].us) for i in range(min(n.value, max_results))]
 
-    def tune_cg_cached(self, dtype=F64, cache_path=None, iters=40):
-        """CG tile from a JSON cache (same keys as tune_cached, prefixed 'cg|'),
-        tuned and stored when absent.  Returns (tile, source)."""
-        import json
-        import os
+    def tune_cg_cached(self, dtype=F64, cache_path=None, iters=40, stream=None):
+        """CG tile through a tile cache file (fvx_tune_cg_cached: the keys of
+        tune_cached prefixed 'cg|', with the coupling in place of the stencil).
+        Returns (tile, "cache" or "tuned")."""
         torch = _torch()
-        arch = getattr(torch.cuda.get_device_properties(self.device), "gcnArchName", "unknown").split(":")[0]
-        key = (f"cg|{arch}|{'f64' if dtype == F64 else 'f32'}|k={self.k}|ld={self.ld}|n_b={self.n_b}"
-               f"|nnz_b={self.nnz_b}|coupling={self.coupling}")
-        cache = {}
-        if cache_path and os.path.exists(cache_path):
-            with open(cache_path) as fh:
-                cache = json.load(fh)
-        if key in cache:
-            t = cache[key]["tile"]
-            self.set_cg_tile(t[0], t[1], t[2], t[3], t[4], t[5] if len(t) > 5 else 0, dtype=dtype)
-            return tuple(t), "cache"
-        res = self.tune_cg(dtype=dtype, iters=iters)
-        best = self.get_cg_tile(dtype)
-        if cache_path:
-            cache[key] = {"tile": list(best), "us_per_iter": min(r[1] for r in res), "candidates": len(res)}
-            tmp = cache_path + ".tmp"
-            with open(tmp, "w") as fh:
-                json.dump(cache, fh, indent=1, sort_keys=True)
-            os.replace(tmp, cache_path)
-        return best, "tuned"
+        nbytes = C.c_size_t()
+        check(lib().fvx_tune_cg_bytes(self._h, dtype, C.byref(nbytes)), "fvx_tune_cg_bytes")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        t = Tile()
+        hit = C.c_int()
+        check(lib().fvx_tune_cg_cached(self._h, dtype, os.fsencode(cache_path) if cache_path else None, _ptr(ws),
+                                       nbytes.value, int(iters), _stream(stream), C.byref(t), C.byref(hit)),
+              "fvx_tune_cg_cached")
+        return t.as_tuple(), "cache" if hit.value else "tuned"
 
     # ---- operators --------------------------------------------------------
     def lap(self, X, Y=None, colscale=None, dtype=None, stream=None):
@@ -367,28 +356,20 @@ class Operator:
             json.dump(cache, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache_path)
 
-    def tune_cached(self, dtype=F64, cache_path=None, scratch_bytes=int(1.1 * 2 ** 30), reps=2):
-        """Autotuned tile, cached in a JSON file keyed by (device architecture,
-        precision, k, ld, base rows, base nonzeros, stencil).  Returns (tile, source)."""
-        import json
-        import os
-        key = self._tile_key(dtype)
-        cache = {}
-        if cache_path and os.path.exists(cache_path):
-            with open(cache_path) as fh:
-                cache = json.load(fh)
-        if key in cache:
-            self.set_tile(*cache[key]["tile"], dtype=dtype)
-            return tuple(cache[key]["tile"]), "cache"
-        res = self.tune(dtype=dtype, scratch_bytes=scratch_bytes, reps=reps)
-        best = self.get_tile(dtype)
-        if cache_path:
-            cache[key] = {"tile": list(best), "us": min(r[1] for r in res), "candidates": len(res)}
-            tmp = cache_path + ".tmp"
-            with open(tmp, "w") as fh:
-                json.dump(cache, fh, indent=1, sort_keys=True)
-            os.replace(tmp, cache_path)
-        return best, "tuned"
+    def tune_cached(self, dtype=F64, cache_path=None, scratch_bytes=int(1.1 * 2 ** 30), reps=2, stream=None):
+        """Autotuned SpMM tile through a tile cache file (fvx_tune_cached: keyed
+        by device architecture, precision, k, ld, base rows, base nonzeros,
+        stencil).  Returns (tile, "cache" or "tuned")."""
+        torch = _torch()
+        es = 8 if dtype == F64 else 4
+        pair = 2 * self.n_b * self.ld * es
+        nbytes = max(pair, min(int(scratch_bytes), 512 * pair))
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        t = Tile()
+        hit = C.c_int()
+        check(lib().fvx_tune_cached(self._h, dtype, os.fsencode(cache_path) if cache_path else None, _ptr(scratch),
+                                    nbytes, int(reps), _stream(stream), C.byref(t), C.byref(hit)), "fvx_tune_cached")
+        return t.as_tuple(), "cache" if hit.value else "tuned"
 
     def div(self, Uf, Wz=None, D=None, dtype=None, stream=None):
         dt = dtype if dtype is not None else (F32 if str(Uf.dtype).endswith("float32") else F64)
@@ -753,6 +734,15 @@ class GuessNet:
         g = np.zeros(self.n_params(), np.float32)
         check(lib().fvx_net_get_params(self._h, None, _np_ptr(g)), "fvx_net_get_params")
         return g
+
+    def save(self, path, stream=None):
+        """Checkpoint (parameters, Adam moments and step count) to a file (fvx_net_save)."""
+        check(lib().fvx_net_save(self._h, os.fsencode(path), _stream(stream)), "fvx_net_save")
+
+    def load(self, path, stream=None):
+        """Restores a checkpoint written by save (fvx_net_load); the network is
+        unchanged if the file is not a checkpoint of this parameter count."""
+        check(lib().fvx_net_load(self._h, os.fsencode(path), _stream(stream)), "fvx_net_load")
 
     def set_params(self, params, stream=None):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -17,7 +17,7 @@ NEUMANN, DIRICHLET = 0, 1
 GUESS_ZERO, GUESS_GIVEN, GUESS_NET = 0, 1, 2
 
 OK, NOT_CONVERGED = 0, 1
-E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+E_ARG, E_MESH, E_NOMEM, E_HIP, E_BREAKDOWN, E_NONFINITE, E_UNSUPPORTED, E_IO = -1, -2, -3, -4, -5, -6, -7, -8
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_CHEBYSHEV, PRECOND_AMG = 0, 1, 2, 3
 LAUNCH_PHASES, LAUNCH_GRAPH = 0, 1
 NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024
@@ -97,6 +97,8 @@ SIGNATURES = {
     "fvx_op_set_cg_tile": (C.c_int, [_vp, C.c_int, _P(Tile)]),
     "fvx_tune_cg_bytes": (C.c_int, [_vp, C.c_int, _P(C.c_size_t)]),
     "fvx_tune_cg": (C.c_int, [_vp, C.c_int, _vp, C.c_size_t, C.c_int, _vp, _vp, C.c_int, _P(C.c_int)]),
+    "fvx_tune_cached": (C.c_int, [_vp, C.c_int, C.c_char_p, _vp, C.c_size_t, C.c_int, _vp, _vp, _vp]),
+    "fvx_tune_cg_cached": (C.c_int, [_vp, C.c_int, C.c_char_p, _vp, C.c_size_t, C.c_int, _vp, _vp, _vp]),
     "fvx_lap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "fvx_lap_many": (C.c_int, [_vp, C.c_int, C.c_int, _P(_vp), _P(_vp), _vp]),
     "fvx_div": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
@@ -148,6 +150,8 @@ SIGNATURES = {
     "fvx_net_destroy": (C.c_int, [_vp]),
     "fvx_net_get_params": (C.c_int, [_vp, _vp, _vp]),
     "fvx_net_set_params": (C.c_int, [_vp, _vp, _vp]),
+    "fvx_net_save": (C.c_int, [_vp, C.c_char_p, _vp]),
+    "fvx_net_load": (C.c_int, [_vp, C.c_char_p, _vp]),
     "fvx_net_forward": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "fvx_net_gradients": (C.c_int, [_vp, C.c_int, _vp, _vp, _P(C.c_double), _vp]),
     "fvx_net_train_step": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_float, _P(C.c_double), _vp]),

@@ -75,6 +75,7 @@ const char *fvx_status_str(int s) {
         case FVX_E_BREAKDOWN: return "CG breakdown";
         case FVX_E_NONFINITE: return "non-finite input";
         case FVX_E_UNSUPPORTED: return "unsupported";
+        case FVX_E_IO: return "file input/output error";
         default: return "unknown status";
     }
 }

@@ -13,6 +13,10 @@
 // per-block partials summed in a fixed order, so training is deterministic.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -1040,6 +1044,64 @@ int fvx_net_set_params(fvx_net *n, const float *params, void *stream) {
         N::zero(n->v, np, s);
         FVX_HIP(hipStreamSynchronize(s));
         n->step = 0;
+        return FVX_OK;
+    });
+}
+
+namespace {
+constexpr char kNetMagic[8] = {'F', 'V', 'X', 'N', 'E', 'T', '0', '1'};
+
+struct FileCloser {
+    void operator()(FILE *f) const {
+        if (f) std::fclose(f);
+    }
+};
+}  // namespace
+
+int fvx_net_save(const fvx_net *n, const char *path, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        FVX_REQUIRE(path, FVX_E_ARG, "path is NULL");
+        const size_t np = size_t(N::n_params());
+        FVX_HIP(hipStreamSynchronize(fvx::as_stream(stream)));
+        std::vector<float> host(3 * np);
+        FVX_HIP(hipMemcpy(host.data(), n->params, 4 * np, hipMemcpyDeviceToHost));
+        FVX_HIP(hipMemcpy(host.data() + np, n->m, 4 * np, hipMemcpyDeviceToHost));
+        FVX_HIP(hipMemcpy(host.data() + 2 * np, n->v, 4 * np, hipMemcpyDeviceToHost));
+        std::unique_ptr<FILE, FileCloser> f(std::fopen(path, "wb"));
+        FVX_REQUIRE(f, FVX_E_IO, std::string("cannot open ") + path + " for writing");
+        const int32_t head[2] = {int32_t(np), int32_t(n->step)};
+        bool ok = std::fwrite(kNetMagic, 1, 8, f.get()) == 8 && std::fwrite(head, 4, 2, f.get()) == 2 &&
+                  std::fwrite(host.data(), 4, host.size(), f.get()) == host.size();
+        ok = std::fclose(f.release()) == 0 && ok;
+        FVX_REQUIRE(ok, FVX_E_IO, std::string("writing ") + path + " failed");
+        return FVX_OK;
+    });
+}
+
+int fvx_net_load(fvx_net *n, const char *path, void *stream) {
+    return guard([&] {
+        N::check_net(n);
+        FVX_REQUIRE(path, FVX_E_ARG, "path is NULL");
+        const size_t np = size_t(N::n_params());
+        std::unique_ptr<FILE, FileCloser> f(std::fopen(path, "rb"));
+        FVX_REQUIRE(f, FVX_E_IO, std::string("cannot open ") + path);
+        char magic[8];
+        int32_t head[2];
+        FVX_REQUIRE(std::fread(magic, 1, 8, f.get()) == 8 && std::memcmp(magic, kNetMagic, 8) == 0, FVX_E_IO,
+                    std::string(path) + " is not a network checkpoint");
+        FVX_REQUIRE(std::fread(head, 4, 2, f.get()) == 2 && head[0] == int32_t(np) && head[1] >= 0, FVX_E_IO,
+                    std::string(path) + ": parameter count " + std::to_string(head[0]) + ", this network has " +
+                        std::to_string(np));
+        std::vector<float> host(3 * np);
+        FVX_REQUIRE(std::fread(host.data(), 4, host.size(), f.get()) == host.size(), FVX_E_IO,
+                    std::string(path) + " is truncated");
+        hipStream_t s = fvx::as_stream(stream);
+        FVX_HIP(hipMemcpyAsync(n->params, host.data(), 4 * np, hipMemcpyHostToDevice, s));
+        FVX_HIP(hipMemcpyAsync(n->m, host.data() + np, 4 * np, hipMemcpyHostToDevice, s));
+        FVX_HIP(hipMemcpyAsync(n->v, host.data() + 2 * np, 4 * np, hipMemcpyHostToDevice, s));
+        FVX_HIP(hipStreamSynchronize(s));
+        n->step = head[1];
         return FVX_OK;
     });
 }

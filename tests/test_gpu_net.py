@@ -299,3 +299,43 @@ def test_net_argument_errors():
         net.forward(x)
     with pytest.raises(ValueError):
         net.set_params(np.zeros(10, np.float32))
+
+
+def test_checkpoint_resumes_training_exactly(tmp_path):
+    """fvx_net_save / fvx_net_load: a network restored from a checkpoint
+    (parameters, Adam moments, step count) takes the same next training step
+    as the one that kept training, bitwise; a checkpoint loads into a network
+    of another grid; a file that is not a checkpoint, or is truncated, is
+    refused and leaves the network unchanged."""
+    nx, ny, nz, ns = 12, 10, 4, 3
+    p = _params()
+    x, t = _samples(ns, nz, ny, nx, 21), _samples(ns, nz, ny, nx, 22, ch=1)
+    a = _net(nx, ny, nz, ns, p)
+    for _ in range(2):
+        a.train_step(_dev(x), _dev(t), 1e-3)
+    path = str(tmp_path / "net.ckpt")
+    a.save(path)
+    b = _net(nx, ny, nz, ns, np.zeros_like(p))
+    b.load(path)
+    saved = a.params()
+    assert np.array_equal(saved, b.params())
+    a.train_step(_dev(x), _dev(t), 1e-3)
+    b.train_step(_dev(x), _dev(t), 1e-3)
+    assert np.array_equal(a.params(), b.params())
+    other = _net(7, 5, 3, 1, np.zeros_like(p))
+    other.load(path)
+    assert np.array_equal(other.params(), saved)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"FVXNET01" and len(raw) == 16 + 3 * 4 * p.size
+    before = b.params()
+    bad = str(tmp_path / "bad.ckpt")
+    open(bad, "wb").write(b"NOTANET!" + raw[8:])
+    from paper_2508_06710_amd import FvxError
+    with pytest.raises(FvxError):
+        b.load(bad)
+    open(bad, "wb").write(raw[:len(raw) // 2])
+    with pytest.raises(FvxError):
+        b.load(bad)
+    with pytest.raises(FvxError):
+        b.load(str(tmp_path / "missing.ckpt"))
+    assert np.array_equal(b.params(), before)

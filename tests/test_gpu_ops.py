@@ -328,3 +328,42 @@ def test_operators_on_a_mesh_in_hilbert_order(k):
     bp = project_mean(b, c.m3.n_groups())
     r = bp - spmv(c.L, c.op.to_planes(X))
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(bp)
+
+
+def test_tile_cache_file(tmp_path):
+    """fvx_tune_cached / fvx_tune_cg_cached: tune and store on a miss, set
+    without timing on a hit; a file written by Python (other entries, other
+    members) is read, kept and rewritten in the same layout as Python's
+    json.dump(indent=1, sort_keys=True); a malformed file is an error."""
+    import json
+    c = Case(inputs.channel_base(13, 9), 8)
+    fvx = c.fvx
+    path = str(tmp_path / "tiles.json")
+    other = {"gfx950|f64|k=1|ld=1|n_b=1|nnz_b=1|stencil=7": {"tile": [1, 1, 64, 1, 0, 0, 0], "us": 3.3057108521461487,
+                                                             "candidates": 15, "source": "refined"}}
+    with open(path, "w") as fh:
+        json.dump(other, fh, indent=1, sort_keys=True)
+    t1, src1 = c.op.tune_cached(fvx.F64, path, scratch_bytes=64 << 20)
+    assert src1 == "tuned" and t1 == c.op.get_tile(fvx.F64)
+    doc = json.load(open(path))
+    key = [k for k in doc if k.endswith(f"|f64|k=8|ld={c.op.ld}|n_b={c.op.n_b}|nnz_b={c.op.nnz_b}|stencil=7")]
+    assert len(key) == 1 and tuple(doc[key[0]]["tile"]) == t1 and doc[key[0]]["candidates"] >= 1
+    assert doc[key[0]]["us"] > 0 and key[0].split("|")[0].startswith("gfx")
+    for k, v in other.items():
+        assert doc[k] == v  # kept, numbers included
+    text = open(path).read()
+    assert text == json.dumps(doc, indent=1, sort_keys=True)
+    c.op.set_tile(1, 8, 64, 0, 0, 0, 0)
+    t2, src2 = c.op.tune_cached(fvx.F64, path)
+    assert src2 == "cache" and t2 == t1 and c.op.get_tile(fvx.F64) == t1
+    assert open(path).read() == text  # a hit does not rewrite the file
+    tc, srcc = c.op.tune_cg_cached(fvx.F64, path, iters=8)
+    assert srcc == "tuned" and tc == c.op.get_cg_tile(fvx.F64)
+    doc2 = json.load(open(path))
+    ck = [k for k in doc2 if k.startswith("cg|") and k.endswith(f"|n_b={c.op.n_b}|nnz_b={c.op.nnz_b}|coupling=1")]
+    assert len(ck) == 1 and doc2[ck[0]]["us_per_iter"] > 0
+    assert c.op.tune_cg_cached(fvx.F64, path, iters=8) == (tc, "cache")
+    bad = str(tmp_path / "bad.json")
+    open(bad, "w").write('{"a": [1, 2,')
+    with pytest.raises(fvx.FvxError):
+        c.op.tune_cached(fvx.F64, bad)
