@@ -127,3 +127,16 @@ def test_graph_launch_mode_checked():
     B = c.op.to_rows(inputs.rhs_uniform(3, c.m3.N))
     with pytest.raises(fvx.FvxError):
         c.op.solve(B, launch=2)
+
+
+def test_graph_cache_eviction():
+    """More solve configurations than the cache keeps (16): the least
+    recently used are dropped (after a device synchronisation) and captured
+    again when they come back; every solve equals its phase-by-phase twin."""
+    import paper_2508_06710_amd as fvx
+    cases = [Case(inputs.channel_base(6 + i % 6, 5 + i // 6), 2 + i % 3, with_f32=False) for i in range(18)]
+    Bs = [c.op.to_rows(inputs.rhs_uniform(500 + i, c.m3.N)) for i, c in enumerate(cases)]
+    ref = [c.op.solve(B, rtol=1e-10, poll_every=4, launch=fvx.LAUNCH_PHASES) for c, B in zip(cases, Bs)]
+    for _ in range(2):
+        for c, B, r in zip(cases, Bs, ref):
+            _same(r, c.op.solve(B, rtol=1e-10, poll_every=4, launch=fvx.LAUNCH_GRAPH))
