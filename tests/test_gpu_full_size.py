@@ -70,11 +70,13 @@ def test_channel_full_size_poisson(channel):
     assert _relres(c, c.op.to_planes(Xm), b) <= 1e-8 * 1.0001
 
 
-def test_airfoil_full_size():
+@pytest.mark.parametrize("order", ["hilbert", None])
+def test_airfoil_full_size(order):
     """The extruded NACA-0012 Delaunay base (about 196,000 triangles) with 32
-    planes: lap SpMM in both precisions element by element, and the mixed
-    solve to 1e-10 by the oracle's residual."""
-    c = Case(inputs.naca_delaunay(seed=1), inputs.AIRFOIL_K, inputs.AIRFOIL_DZ)
+    planes, with the cells in Hilbert order (the benchmark's layout) and in
+    the generator's order: lap SpMM in both precisions element by element,
+    and the mixed solve to 1e-10 by the oracle's residual."""
+    c = Case(inputs.naca_delaunay(seed=1), inputs.AIRFOIL_K, inputs.AIRFOIL_DZ, order=order)
     fvx = c.fvx
     _tuned(c, (fvx.F64, fvx.F32))
     x = inputs.uniform(0, 0, c.m3.N)
