@@ -842,6 +842,7 @@ constexpr int kGraphDevices = 64;
 
 struct GraphSet {
     std::vector<uint64_t> key;
+    int device = 0;  // the device the graphs were instantiated on
     hipGraphExec_t ex[kGraphSizes] = {};
     uint64_t used = 0;
 };
@@ -874,10 +875,10 @@ struct KeyBuf {
     }
 };
 
-// The cached set for `key` (created empty when absent).  Dropping a set waits
-// for the device first: one of its graphs may still be running on another
-// stream.  Caller holds the cache's mutex.
-GraphSet &graph_set(GraphCache &c, const std::vector<uint64_t> &key) {
+// The cached set for `key` on `device` (created empty when absent).
+// Dropping a set first waits for its device: one of its graphs may still be
+// running on another stream.  Caller holds the cache's mutex.
+GraphSet &graph_set(GraphCache &c, const std::vector<uint64_t> &key, int device) {
     for (auto &g : c.sets)
         if (g->key == key) {
             g->used = ++c.clock;
@@ -887,13 +888,18 @@ GraphSet &graph_set(GraphCache &c, const std::vector<uint64_t> &key) {
         size_t old = 0;
         for (size_t i = 1; i < c.sets.size(); ++i)
             if (c.sets[i]->used < c.sets[old]->used) old = i;
-        FVX_HIP(hipDeviceSynchronize());
+        const int gone = c.sets[old]->device;
+        FVX_HIP(hipSetDevice(gone));
+        const hipError_t rc = hipDeviceSynchronize();
         for (hipGraphExec_t e : c.sets[old]->ex)
-            if (e) FVX_HIP(hipGraphExecDestroy(e));
+            if (e) (void)hipGraphExecDestroy(e);
         c.sets.erase(c.sets.begin() + long(old));
+        FVX_HIP(hipSetDevice(device));
+        FVX_HIP(rc);
     }
     c.sets.push_back(std::make_unique<GraphSet>());
     c.sets.back()->key = key;
+    c.sets.back()->device = device;
     c.sets.back()->used = ++c.clock;
     return *c.sets.back();
 }
@@ -1162,8 +1168,8 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
     };
     // Graph replay: the key of every captured argument (see graph_cache).
     KeyBuf key;
+    int dev = 0;
     if (launch_mode == FVX_LAUNCH_GRAPH) {
-        int dev = 0;
         FVX_HIP(hipGetDevice(&dev));
         key.u(dev);
         key.u(sizeof(T));
@@ -1204,7 +1210,7 @@ void run_cg_batch(std::vector<CgJob<T>> &jobs, BItem<T> *items_dev, PollRec *fla
     auto replay = [&](int count) {
         GraphCache &gc = graph_cache();
         std::lock_guard<std::mutex> lk(gc.mu);
-        GraphSet &g = graph_set(gc, key.v);
+        GraphSet &g = graph_set(gc, key.v, dev);
         for (int j = kGraphSizes - 1; j >= 0; --j) {
             const int m = 1 << j;
             while (count >= m) {

@@ -96,7 +96,9 @@ struct Parser {
                     case 't': out += '\t'; break;
                     case 'u': {
                         if (i + 4 > s.size()) fail("bad \\u escape");
-                        const unsigned cp = unsigned(std::stoul(s.substr(i, 4), nullptr, 16));
+                        unsigned cp = 0;
+                        const auto r = std::from_chars(s.data() + i, s.data() + i + 4, cp, 16);
+                        if (r.ec != std::errc() || r.ptr != s.data() + i + 4) fail("bad \\u escape");
                         i += 4;
                         if (cp >= 0x80) fail("non-ASCII \\u escape");
                         out += char(cp);
@@ -268,7 +270,9 @@ bool cached_tile(JVal &doc, const std::string &key, fvx_tile &t) {
     int v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < a->arr.size(); ++i) {
         if (a->arr[i].kind != JVal::Num) return false;
-        v[i] = std::stoi(a->arr[i].text);
+        const std::string &x = a->arr[i].text;
+        const auto r = std::from_chars(x.data(), x.data() + x.size(), v[i]);
+        if (r.ec != std::errc() || r.ptr != x.data() + x.size()) return false;  // not an integer: tuned again
     }
     t = fvx_tile{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
     return true;
