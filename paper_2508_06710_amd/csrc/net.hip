@@ -182,6 +182,49 @@ __global__ __launch_bounds__(kBlock) void k_conv_fwd(Grid g, int ns, int CI, con
     }
 }
 
+// The output layer (32 -> 1 channel): out[n][cell] = bias + sum_{ci,tap}
+// W[ci][tap] in[n][ci][src(cell, tap)] + skip.  A dot product per cell (no
+// matrix-core shape fits M = 1), so on the vector ALU with the input channels
+// split over kSplit1 lanes per cell (each lane 32 / kSplit1 channels, all 27
+// taps), the lanes' sums added by two xor shuffles: four times the threads of
+// one lane per cell, which a single-sample inference needs to fill the GPU.
+constexpr int kSplit1 = 4;
+// From this many cells (four single-sample 64 x 64 x 8 grids) on, the output
+// layer takes four cells per thread instead (k_conv_fwd<1, 4>): on the 16-sample
+// training batch 163 us against 230 us split; one sample 107 us against 29 us.
+constexpr int64_t kFwd1Split = int64_t(1) << 17;
+
+__global__ __launch_bounds__(kBlock) void k_conv_fwd1(Grid g, int ns, const float *__restrict__ in,
+                                                      const float *__restrict__ W, const float *__restrict__ bias,
+                                                      float *__restrict__ out, const float *__restrict__ skip,
+                                                      int skip_stride) {
+    constexpr int CI = kC, CG = CI / kSplit1;
+    __shared__ float w_s[CI * kTaps];  // [ci][tap]
+    for (int i = threadIdx.x; i < CI * kTaps; i += blockDim.x) w_s[i] = W[i];
+    __syncthreads();
+    const int total = g.cells * ns;
+    const int gid = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int pos = gid / kSplit1, part = gid % kSplit1;  // kSplit1 consecutive lanes share a cell
+    const bool live = pos < total;
+    const Pos p = pos_of(g, live ? pos : 0);
+    const Taps t = fwd_taps(g, p.x, p.y, p.z);
+    const float *src = in + (int64_t(p.n) * CI + part * CG) * g.cells;
+    const float *w = w_s + part * CG * kTaps;
+    float acc = 0.0f;
+    for (int ci = 0; ci < CG; ++ci) {
+#pragma unroll
+        for (int tap = 0; tap < kTaps; ++tap)
+            acc += w[ci * kTaps + tap] * src[int64_t(ci) * g.cells + t.z[tap / 9] + t.y[(tap / 3) % 3] + t.x[tap % 3]];
+    }
+    acc += __shfl_xor(acc, 1, kSplit1);
+    acc += __shfl_xor(acc, 2, kSplit1);
+    if (live && part == 0) {
+        float v = bias[0] + acc;
+        if (skip) v += skip[p.n * skip_stride + p.cell];
+        out[int64_t(p.n) * g.cells + p.cell] = v;
+    }
+}
+
 typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
 
 // The 32-output-channel layers as an implicit GEMM on the matrix cores
@@ -736,22 +779,68 @@ __device__ double block_sum(double v, double *red) {
 // Scales of one sample (one block): s[0] = plain mean of b (0 unless the
 // operator is singular), s[1] = rms over the cells of the source density
 // f = (b - s[0]) / (area * dz), or 1 when it is zero.  B: AoS [n_b][ld].
+// Loads in flight per thread in the single-block reductions below: each
+// thread issues kBatch loads before it adds any of them (one memory round
+// trip per kBatch elements instead of one per element); the sums keep the
+// element order of a plain strided loop.
+constexpr int kBatch = 8;
+
+// Element i of AoS [n_b][ld] for plane-fastest flat index i = c * k + l,
+// stepped by `stride` without a division per element.
+struct FlatIdx {
+    int c, l, dc, dl, k;
+    __device__ FlatIdx(int i, int stride, int kk) : c(i / kk), l(i % kk), dc(stride / kk), dl(stride % kk), k(kk) {}
+    __device__ void step() {
+        c += dc;
+        l += dl;
+        if (l >= k) {
+            l -= k;
+            ++c;
+        }
+    }
+};
+
 __global__ __launch_bounds__(1024) void k_scale(Grid g, const double *__restrict__ B, int ld,
                                                 const double *__restrict__ area, double inv_dz, int singular,
                                                 double *__restrict__ s) {
     __shared__ double red[1024];
-    const int k = g.Z;
+    const int k = g.Z, n = g.cells, T = blockDim.x;
     double a = 0.0;
-    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) a += B[(i / k) * ld + i % k];
-    const double sum = block_sum(a, red);
-    const double mean = singular ? sum / double(g.cells) : 0.0;
-    a = 0.0;
-    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) {
-        const int c = i / k;
-        const double f = (B[c * ld + i % k] - mean) / area[c] * inv_dz;
-        a += f * f;
+    {
+        FlatIdx ix(threadIdx.x, T, k);
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * T) {
+            double v[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                v[u] = i0 + u * T < n ? B[int64_t(ix.c) * ld + ix.l] : 0.0;
+                ix.step();
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) a += v[u];
+        }
     }
-    const double rms = sqrt(block_sum(a, red) / double(g.cells));
+    const double sum = block_sum(a, red);
+    const double mean = singular ? sum / double(n) : 0.0;
+    a = 0.0;
+    {
+        FlatIdx ix(threadIdx.x, T, k);
+        for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * T) {
+            double v[kBatch], ar[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const bool in = i0 + u * T < n;
+                v[u] = in ? B[int64_t(ix.c) * ld + ix.l] : mean;
+                ar[u] = in ? area[ix.c] : 1.0;
+                ix.step();
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const double f = (v[u] - mean) / ar[u] * inv_dz;
+                a += f * f;
+            }
+        }
+    }
+    const double rms = sqrt(block_sum(a, red) / double(n));
     if (threadIdx.x == 0) {
         s[0] = mean;
         s[1] = rms > 0.0 ? rms : 1.0;
@@ -777,18 +866,31 @@ __global__ __launch_bounds__(kBlock) void k_prepare(Grid g, const double *__rest
 }
 
 // x0 = s * (out - mean(out)) (mean removed only for a singular operator),
-// written into the AoS [n_b][ld] vector X (one block).
+// written into the AoS [n_b][ld] vector X.
+// Every block sums all of out in the same order (the same mean, bitwise), then
+// writes its range of cells, all planes of a cell by one thread (a contiguous
+// AoS row): the writes spread over the blocks instead of one CU's scattered stores.
+constexpr int kGuessOutBlocks = 32;
+
 __global__ __launch_bounds__(1024) void k_guess_out(Grid g, const float *__restrict__ out,
                                                     const double *__restrict__ s, int singular,
                                                     double *__restrict__ X, int ld) {
     __shared__ double red[1024];
-    const int nb = g.X * g.Y;
+    const int nb = g.X * g.Y, k = g.Z, n = g.cells, T = blockDim.x;
     double a = 0.0;
-    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) a += double(out[i]);
+    for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * T) {
+        float v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v[u] = i0 + u * T < n ? out[i0 + u * T] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) a += double(v[u]);
+    }
     const double sum = block_sum(a, red);
-    const double mean = singular ? sum / double(g.cells) : 0.0;
+    const double mean = singular ? sum / double(n) : 0.0;
     const double sc = s[1];
-    for (int i = threadIdx.x; i < g.cells; i += blockDim.x) X[(i % nb) * ld + i / nb] = sc * (double(out[i]) - mean);
+    // out is [plane][cell]; X is AoS [cell][ld]
+    for (int c = int(blockIdx.x) * T + threadIdx.x; c < nb; c += int(gridDim.x) * T)
+        for (int l = 0; l < k; ++l) X[int64_t(c) * ld + l] = sc * (double(out[int64_t(l) * nb + c]) - mean);
 }
 
 Grid grid_of(const fvx_net *n) { return Grid{n->nx, n->ny, n->nz, n->cells}; }
@@ -828,8 +930,13 @@ void forward(fvx_net *net, int ns, const float *in, hipStream_t s) {
                 conv_fwd_mfma<2>(g, ns, src, W, b, net->act[l + 1], s);
             else
                 conv_fwd_mfma<kC>(g, ns, src, W, b, net->act[l + 1], s);
-        } else {
+        } else if (int64_t(g.cells) * ns >= kFwd1Split) {
+            // enough cells to fill the GPU with four cells per thread (coalesced along the cells)
             conv_fwd<1, 4>(g, ns, kCin[l], src, W, b, net->act[l + 1], 0, in + g.cells, s);
+        } else {
+            const int64_t threads = int64_t(g.cells) * ns * kSplit1;
+            hipLaunchKernelGGL(k_conv_fwd1, dim3(unsigned(ceil_div(threads, kBlock))), dim3(kBlock), 0, s, g, ns, src,
+                               W, b, net->act[l + 1], in + g.cells, 2 * g.cells);
         }
         src = net->act[l + 1];
     }
@@ -954,7 +1061,9 @@ void guess(fvx_net *n, const fvx_op *op, const double *B, const double *Pprev, d
                        s, g, B, Pprev, (const double *)nullptr, op->ld, op->d64.area, 1.0 / op->dz, n->scal,
                        n->act[0], (float *)nullptr);
     forward(n, 1, n->act[0], s);
-    hipLaunchKernelGGL(k_guess_out, dim3(1), dim3(1024), 0, s, g, n->act[4], n->scal, int(op->singular), X0, op->ld);
+    const unsigned out_blocks = unsigned(std::min<int64_t>(kGuessOutBlocks, ceil_div(int64_t(g.X) * g.Y, 1024)));
+    hipLaunchKernelGGL(k_guess_out, dim3(out_blocks), dim3(1024), 0, s, g, n->act[4], n->scal, int(op->singular), X0,
+                       op->ld);
     FVX_HIP(hipGetLastError());
 }
 
