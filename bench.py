@@ -1354,14 +1354,15 @@ def amg_leg(fvx, torch, inputs, op, D, rtol, err_of=None):
     """CG preconditioned by one V-cycle of the aggregation multigrid (default
     options: Chebyshev degree 2 on [2/8, 2], pairwise aggregation with beta
     0.25, plane merging when the plane coupling dominates, coarsest level at
-    most 2048 unknowns) on the benchmark's projection right-hand side, FP64 and
+    most 2048 unknowns, or solved per plane mode at the first level whose
+    modes hold at most 2^23 terms) on the benchmark's projection right-hand side, FP64 and
     mixed precision, the best of 3 timed solves each; the time of one V-cycle
     and, per level, the level's SpMM (its operator on the level's k planes;
     graph-timed, inputs warm in the caches) -- the per-level SpMM table of the
     paper's multigrid appendix."""
     t0 = time.perf_counter()
     amg = fvx.Amg(op)
-    out = {"setup_s": time.perf_counter() - t0, "levels": []}
+    out = {"setup_s": time.perf_counter() - t0, "levels": [], "coarsest_modes": amg.coarsest_modes}
     for name, kw in (("f64", {}), ("mixed", dict(precision=fvx.MIXED))):
         op.solve(D, rtol=rtol, amg=amg, **kw)
         best, st = None, None
@@ -1648,6 +1649,7 @@ def airfoil_leg(fvx, inputs, torch, np):
     amg = fvx.Amg(op)
     res["amg_setup_s"] = time.perf_counter() - t0
     res["amg_levels"] = amg.levels()
+    res["amg_coarsest_modes"] = amg.coarsest_modes
     mixed = {}
     for prec, pre, name in ((fvx.MIXED, 0, "mixed"), (fvx.F64, 0, "f64"), (fvx.MIXED, cheb, "mixed_chebyshev"),
                             (fvx.F64, cheb, "f64_chebyshev"), (fvx.MIXED, amg, "mixed_amg"), (fvx.F64, amg, "f64_amg")):

@@ -488,6 +488,19 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   most coarse_max unknowns (n_b k, all planes) is the coarsest; it is
  *   solved with its dense pseudo-inverse (inverse with Dirichlet walls) per
  *   independent system, formed on the host in FP64.
+ *   Plane modes (coupled planes, mode_cells > 0): a level with at most
+ *   mode_cells base cells whose mode systems (below) hold at most 2^23
+ *   terms in all, (floor(k/2) + 1) n_b^2 <= 2^23 (64 MiB in FP64, read once
+ *   per cycle), is also the coarsest, and a coarsest level within both
+ *   limits is solved per plane mode.  Its planes are coupled
+ *   periodically, so the real discrete Fourier basis along the planes splits
+ *   it exactly into floor(k/2) + 1 systems A_b + (2 - 2 cos(2 pi m / k)) W of
+ *   n_b unknowns (mode m; one right-hand side for m = 0 and m = k/2, a cosine
+ *   and a sine one otherwise).  It is solved by the transform to the modes,
+ *   the dense pseudo-inverse of every mode system (formed on the host in
+ *   FP64) and the transform back: the same pseudo-inverse of the whole level,
+ *   in three launches and (floor(k/2) + 1) n_b^2 stored terms instead of
+ *   (n_b k)^2.
  *   Cycle: V-cycle; on each level `degree` Chebyshev steps for A z = r on
  *   [2 / ratio, 2] of the spectrum of D^-1 A from z = 0, restriction of the
  *   residual (fused with its SpMM), the coarse cycle, prolongation of the
@@ -507,9 +520,11 @@ typedef struct fvx_amg_opts {
     double z_rule;       /* plane-merging threshold (>= 0) */
     int32_t coarse_max;  /* coarsest level size n_b k (1..2048) */
     int32_t max_levels;  /* 1..16 */
+    int32_t mode_cells;  /* coupled planes: coarsest at <= mode_cells base cells (and <= 2^23 mode
+                            terms), solved per plane mode (0: off; 0..2048) */
 } fvx_amg_opts;
 
-/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 2048, max_levels 16. */
+/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 2048, max_levels 16, mode_cells 2048. */
 int fvx_amg_opts_default(fvx_amg_opts *opts);
 
 /* Builds the hierarchy of op (which must have been built from mesh m with
@@ -533,6 +548,9 @@ int fvx_amg_level(const fvx_amg *amg, int32_t level, int64_t *n_b, int32_t *k, i
                   const fvx_op **op);
 /* Base cell -> aggregate of a level of kind 1 (host int32 [n_b]). */
 int fvx_amg_aggregates(const fvx_amg *amg, int32_t level, int32_t *agg);
+/* Plane modes of the coarsest level's solve: floor(k/2) + 1 when it is
+ * solved per plane mode, 0 when by one dense pseudo-inverse (host int32). */
+int fvx_amg_coarsest_modes(const fvx_amg *amg, int32_t *modes);
 
 /* One V-cycle Z = M^-1 R (device [n_b][ld] of the fine op, precision dtype
  * FVX_F64 or FVX_F32; R and Z must not overlap).  ws: device workspace of at

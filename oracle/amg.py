@@ -28,7 +28,11 @@ with no block reuse:
   its assembled operator: t_ij = -a_ij within plane 0, w_i = -a_i,(plane 1, i)
   (halved for two planes, whose two plane neighbours coincide).
 * Coarsest level (at most coarse_max unknowns, counted over all planes;
-  independent planes share one hierarchy): the pseudo-inverse, from the
+  independent planes share one hierarchy; with coupled planes and
+  mode_cells > 0 also a level of at most mode_cells base cells whose plane
+  modes hold at most MODE_TERMS terms, (k // 2 + 1) n_b^2, which the
+  library solves per plane mode -- here it is solved like any other
+  coarsest level, as one matrix): the pseudo-inverse, from the
   eigen-decomposition with the eigenvalues below 1e-10 of the Galerkin scale
   dropped (the largest row sum of |P|^T |A| |P| carried down the levels: a
   one-cell Neumann level is zero up to the rounding of its sums).
@@ -47,6 +51,7 @@ import numpy as np
 import scipy.sparse as sp
 
 TIE = 1e-9
+MODE_TERMS = 2 ** 23   # plane-mode pseudo-inverse terms a coarsest level may hold
 
 
 @dataclass
@@ -57,6 +62,7 @@ class AmgOpts:
     z_rule: float = 1.0
     coarse_max: int = 2048
     max_levels: int = 16
+    mode_cells: int = 0     # off here; comparisons with the library pass the value they use
 
 
 @dataclass
@@ -166,11 +172,12 @@ def lower_median(v: np.ndarray) -> float:
 
 
 def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | None = None,
-          columns: int = 1) -> Hierarchy:
+          columns: int = 1, solve_coarsest: bool = True) -> Hierarchy:
     """The hierarchy of A0 (SPD form -L of one independent system: k planes
     coupled periodically when `coupled`, else k = 1), shared by `columns`
     independent systems (the planes of uncoupled operators): a level with at
-    most coarse_max unknowns over all of them is the coarsest."""
+    most coarse_max unknowns over all of them is the coarsest.  Without
+    solve_coarsest the levels only (no pseudo-inverse)."""
     opts = opts or AmgOpts()
     h = Hierarchy(opts=opts)
     lev = Level(A0.tocsr(), n_b, k)
@@ -178,6 +185,9 @@ def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | No
     while True:
         h.levels.append(lev)
         if lev.n_b * lev.k * columns <= opts.coarse_max or len(h.levels) >= opts.max_levels:
+            break
+        if (coupled and opts.mode_cells > 0 and lev.n_b <= opts.mode_cells
+                and (lev.k // 2 + 1) * lev.n_b ** 2 <= MODE_TERMS):
             break
         T, w = couplings(lev.A, lev.n_b, lev.k)
         tmax = np.zeros(lev.n_b)
@@ -201,6 +211,8 @@ def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | No
         lev = nxt
     last = h.levels[-1]
     last.kind, last.agg, last.P = "", None, None
+    if not solve_coarsest:
+        return h
     lam, Q = np.linalg.eigh(last.A.toarray())
     keep = lam > 1e-10 * abs(absA).sum(axis=1).max()
     h.pinv = (Q[:, keep] / lam[keep]) @ Q[:, keep].T

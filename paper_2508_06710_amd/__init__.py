@@ -510,7 +510,7 @@ class Amg:
     Operator.solve(amg=...) to precondition CG with one V-cycle."""
 
     def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=2048, max_levels=16,
-                 stream=None):
+                 mode_cells=None, stream=None):
         torch = _torch()
         if op.mesh is None:
             raise ValueError("the operator's mesh is needed to build its multigrid")
@@ -518,6 +518,8 @@ class Amg:
         check(lib().fvx_amg_opts_default(C.byref(o)), "fvx_amg_opts_default")
         o.degree, o.ratio, o.beta, o.z_rule = int(degree), float(ratio), float(beta), float(z_rule)
         o.coarse_max, o.max_levels = int(coarse_max), int(max_levels)
+        if mode_cells is not None:        # None: the library's default
+            o.mode_cells = int(mode_cells)
         nbytes = C.c_size_t()
         check(lib().fvx_amg_bytes(op.mesh._h, op._h, C.byref(o), C.byref(nbytes)), "fvx_amg_bytes")
         self.op, self.device = op, op.device
@@ -529,6 +531,8 @@ class Amg:
         n = C.c_int32()
         check(lib().fvx_amg_n_levels(h, C.byref(n)), "fvx_amg_n_levels")
         self.n_levels = n.value
+        check(lib().fvx_amg_coarsest_modes(h, C.byref(n)), "fvx_amg_coarsest_modes")
+        self.coarsest_modes = n.value      # plane modes of the coarsest solve (0: one dense pseudo-inverse)
         self._ws = {}
 
     def level(self, i):

@@ -52,7 +52,7 @@ class SolveOpts(C.Structure):
 
 class AmgOpts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("ratio", C.c_double), ("beta", C.c_double), ("z_rule", C.c_double),
-                ("coarse_max", C.c_int32), ("max_levels", C.c_int32)]
+                ("coarse_max", C.c_int32), ("max_levels", C.c_int32), ("mode_cells", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -133,6 +133,7 @@ SIGNATURES = {
     "fvx_amg_create": (C.c_int, [_vp, _vp, _P(AmgOpts), _vp, C.c_size_t, _vp, _P(C.c_void_p)]),
     "fvx_amg_destroy": (C.c_int, [_vp]),
     "fvx_amg_n_levels": (C.c_int, [_vp, _P(_i32)]),
+    "fvx_amg_coarsest_modes": (C.c_int, [_vp, _P(_i32)]),
     "fvx_amg_level": (C.c_int, [_vp, _i32, _P(_i64), _P(_i32), _P(_i64), _P(_i32), _P(C.c_void_p)]),
     "fvx_amg_aggregates": (C.c_int, [_vp, _i32, _vp]),
     "fvx_amg_apply_bytes": (C.c_int, [_vp, C.c_int, _P(C.c_size_t)]),

@@ -27,8 +27,11 @@ struct fvx_amg {
     fvx_amg_opts o{};
     bool coupled = false;                    // planes coupled (one system); else k independent systems
     int n_d = 0;                             // unknowns of the coarsest dense solve per system
-    const double *pinv64 = nullptr;          // [n_d][n_d] coarsest pseudo-inverse (AoS order: cell, plane)
-    const float *pinv32 = nullptr;
+    int modes = 0;                           // > 0: coarsest solved per plane mode (modes systems of n_d = n_b)
+    const double *pinv64 = nullptr;          // [n_d][n_d] coarsest pseudo-inverse (AoS order: cell, plane),
+    const float *pinv32 = nullptr;           //   or [modes][n_d][n_d], one per plane mode
+    const double *phi = nullptr;             // modes: [k][k] real Fourier basis, row j = basis function j
+    const double *phi_t = nullptr;           //   and its transpose
     double inv_theta = 1.0;
     double c1[fvx::kMaxAmgDegree] = {}, c2[fvx::kMaxAmgDegree] = {};  // smoother step j uses c1[j], c2[j]
     uint64_t serial = fvx::next_serial();
@@ -45,7 +48,8 @@ struct AmgWork {
         T *r = nullptr, *s[2] = {nullptr, nullptr}, *q[2] = {nullptr, nullptr};
     };
     Lv lv[kMaxAmgLevels];
-    CgState *st = nullptr;  // a never-set "done" flag for calls outside a solve
+    double *mr = nullptr, *mz = nullptr;  // plane modes: [k][n_b] right-hand sides and solutions
+    CgState *st = nullptr;                // a never-set "done" flag for calls outside a solve
 };
 
 // Bytes of the V-cycle vectors of precision dtype (plus the flag).

@@ -14,13 +14,18 @@
 //   pre-smoothing   Chebyshev steps from z = 0 (the CG's fused step kernel),
 //   restriction     r_c = P^T (r - A z), the residual's SpMM fused in,
 //   coarse cycle    recursively; the coarsest level by its dense
-//                   pseudo-inverse (one wavefront per output),
+//                   pseudo-inverse, or per plane mode (coupled planes: the
+//                   real Fourier transform along the planes, the dense
+//                   pseudo-inverse of each mode's base-plane system, the
+//                   transform back),
 //   prolongation    z += P e_c, fused with the first post-smoothing SpMM,
 //   post-smoothing  Chebyshev steps from the corrected iterate.
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <map>
 #include <numeric>
+#include <thread>
 
 #include "amg.h"
 
@@ -197,12 +202,22 @@ double plane_dominance(const HostLevel &L) {
     return ratio[m];
 }
 
+// Terms of the plane-mode pseudo-inverses of a coupled level: floor(k/2) + 1
+// modes of n x n.  A level is solved per mode only within kModeTerms (64 MiB
+// in FP64, read once per cycle).
+constexpr int64_t kModeTerms = int64_t(1) << 23;
+int64_t mode_terms(const HostLevel &L) { return int64_t(L.k / 2 + 1) * L.n * L.n; }
+bool by_modes(const HostLevel &L, bool coupled, const fvx_amg_opts &o) {
+    return coupled && o.mode_cells > 0 && L.n <= o.mode_cells && mode_terms(L) <= kModeTerms;
+}
+
 std::vector<HostLevel> build_levels(HostLevel L0, bool coupled, const fvx_amg_opts &o) {
     std::vector<HostLevel> L;
     L.push_back(std::move(L0));
     while (true) {
         HostLevel &lev = L.back();
         if (lev.n * lev.k <= o.coarse_max || int(L.size()) >= o.max_levels) break;
+        if (by_modes(lev, coupled, o)) break;
         if (coupled && lev.k >= 2 && lev.k % 2 == 0 && plane_dominance(lev) > o.z_rule) {
             lev.kind = 2;
             HostLevel nxt = merge_planes(lev);
@@ -308,6 +323,67 @@ std::vector<double> coarsest_pinv(const HostLevel &L, bool coupled, bool singula
     return inv;
 }
 
+// Real Fourier basis along k periodic planes, orthonormal, row j over the
+// planes l: j = 0 the constant 1/sqrt(k); for mode m = (j + 1) / 2 with
+// 2m < k, sqrt(2/k) cos(2 pi m l / k) for odd j and sqrt(2/k) sin(...) for
+// even j; for even k, j = k - 1 the alternating (-1)^l / sqrt(k).  Every row
+// of mode m is an eigenvector of the periodic second difference
+// (2 x_l - x_{l-1} - x_{l+1}) with eigenvalue 2 - 2 cos(2 pi m / k), also
+// for k = 2, whose two plane neighbours coincide (eigenvalues 0 and 4).
+std::vector<double> fourier_basis(int k) {
+    constexpr double kPi = 3.14159265358979323846;
+    std::vector<double> phi(size_t(k) * k);
+    const double a0 = 1.0 / std::sqrt(double(k)), a1 = std::sqrt(2.0 / double(k));
+    for (int j = 0; j < k; ++j) {
+        const int m = (j + 1) / 2;
+        for (int l = 0; l < k; ++l) {
+            const double ang = 2.0 * kPi * double((int64_t(m) * l) % k) / double(k);  // reduced: exact phase
+            double v;
+            if (j == 0)
+                v = a0;
+            else if (2 * m == k)
+                v = l % 2 ? -a0 : a0;
+            else
+                v = a1 * (j % 2 ? std::cos(ang) : std::sin(ang));
+            phi[size_t(j) * k + l] = v;
+        }
+    }
+    return phi;
+}
+
+// Pseudo-inverses of the plane modes of the coarsest level (coupled planes,
+// periodic): mode m's system is A_b + (2 - 2 cos(2 pi m / k)) diag(w) on the
+// base cells, singular only for m = 0 of a singular operator.  The modes are
+// formed on the host threads, each into its own [n][n] slice.
+std::vector<double> mode_pinvs(const HostLevel &L, bool singular, int modes) {
+    constexpr double kPi = 3.14159265358979323846;
+    const size_t nn = size_t(L.n) * size_t(L.n);
+    std::vector<double> out(size_t(modes) * nn);
+    std::vector<std::exception_ptr> err(static_cast<size_t>(modes));
+    auto one = [&](int m) {
+        try {
+            HostLevel M = L;
+            M.k = 1;
+            const double lam = 2.0 - 2.0 * std::cos(2.0 * kPi * double(m) / double(L.k));
+            for (int64_t i = 0; i < L.n; ++i) M.g[i] = L.g[i] + lam * L.w[i];
+            const std::vector<double> p = coarsest_pinv(M, false, singular && m == 0);
+            std::copy(p.begin(), p.end(), out.begin() + ptrdiff_t(size_t(m) * nn));
+        } catch (...) {
+            err[size_t(m)] = std::current_exception();
+        }
+    };
+    const int nt = std::max(1, std::min(modes, int(std::thread::hardware_concurrency())));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            for (int m = t; m < modes; m += nt) one(m);
+        });
+    for (auto &th : pool) th.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+    return out;
+}
+
 // Face graph whose finite-volume operator with plane spacing 1 is the level:
 // one face per coupled pair (len = coupling, dist = 1), a wall face per cell
 // with a wall term, areas = plane couplings (coupled) or cell areas.
@@ -353,8 +429,10 @@ struct Plan {
     std::vector<fvx_op_desc> descs;
     std::vector<size_t> op_bytes;
     std::vector<double> pinv;
+    std::vector<double> phi;  // plane modes: the Fourier basis of the coarsest level's planes
     bool coupled = false;
     int n_d = 0;
+    int modes = 0;
 };
 
 void check_amg_opts(const fvx_amg_opts *o) {
@@ -365,6 +443,7 @@ void check_amg_opts(const fvx_amg_opts *o) {
     FVX_REQUIRE(o->z_rule >= 0.0 && std::isfinite(o->z_rule), FVX_E_ARG, "z_rule must be >= 0");
     FVX_REQUIRE(o->coarse_max >= 1 && o->coarse_max <= kMaxAmgCoarse, FVX_E_ARG, "coarse_max must be 1..2048");
     FVX_REQUIRE(o->max_levels >= 1 && o->max_levels <= kMaxAmgLevels, FVX_E_ARG, "max_levels must be 1..16");
+    FVX_REQUIRE(o->mode_cells >= 0 && o->mode_cells <= kMaxAmgCoarse, FVX_E_ARG, "mode_cells must be 0..2048");
 }
 
 Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
@@ -378,11 +457,18 @@ Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
     P.coupled = op->zfaces;
     P.L = build_levels(fine_level(*m, op, dirichlet), P.coupled, *o);
     const HostLevel &last = P.L.back();
-    const int64_t nd = last.n * (P.coupled ? last.k : 1);
-    FVX_REQUIRE(nd <= kMaxAmgCoarse, FVX_E_UNSUPPORTED,
-                "coarsening stopped above 2048 unknowns (raise max_levels or coarse_max)");
-    P.n_d = int(nd);
-    P.pinv = coarsest_pinv(last, P.coupled, op->singular);
+    if (by_modes(last, P.coupled, *o)) {
+        P.n_d = int(last.n);
+        P.modes = last.k / 2 + 1;
+        P.pinv = mode_pinvs(last, op->singular, P.modes);
+        P.phi = fourier_basis(last.k);
+    } else {
+        const int64_t nd = last.n * (P.coupled ? last.k : 1);
+        FVX_REQUIRE(nd <= kMaxAmgCoarse, FVX_E_UNSUPPORTED,
+                    "coarsening stopped above 2048 unknowns (raise max_levels or coarse_max)");
+        P.n_d = int(nd);
+        P.pinv = coarsest_pinv(last, P.coupled, op->singular);
+    }
     for (size_t l = 1; l < P.L.size(); ++l) {
         P.meshes.push_back(level_mesh(P.L[l], P.coupled));
         P.descs.push_back(level_desc(op, P.L[l], dirichlet));
@@ -402,8 +488,9 @@ size_t plan_bytes(const Plan &P, bool f32) {
     for (size_t b : P.op_bytes) off += align256(b);
     for (const auto &L : P.L)
         if (L.kind == 1) off += align256(4 * size_t(L.n)) * 2 + align256(4 * size_t(L.nc + 1));
-    off += align256(8 * size_t(P.n_d) * P.n_d);
-    if (f32) off += align256(4 * size_t(P.n_d) * P.n_d);
+    off += align256(8 * P.pinv.size());
+    if (f32) off += align256(4 * P.pinv.size());
+    off += 2 * align256(8 * P.phi.size());
     return off;
 }
 
@@ -593,6 +680,87 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_dense(const CgState *__rest
     if (lane == 0) z[i * ld + l] = T(s);
 }
 
+// Coarsest level per plane mode (coupled planes).  The level's vectors are
+// [n_b][ld] (cell, plane); the mode vectors are [k][n_b] (basis function,
+// cell), one contiguous right-hand side per basis function.
+// Forward transform mr[j][i] = sum_l phi[j][l] r[i][l]: one thread per
+// (cell, basis function), the lanes of a cell reading the transposed table
+// along its rows and the cell's planes by broadcast.
+template <typename T>
+__global__ __launch_bounds__(kDenseBlock) void k_amg_modes_fwd(const CgState *__restrict__ st,
+                                                               const double *__restrict__ phi_t, int n_b, int k,
+                                                               int ld, const T *__restrict__ r,
+                                                               double *__restrict__ mr) {
+    if (st->done) return;
+    const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= int64_t(n_b) * k) return;
+    const int64_t i = o / k;
+    const int j = int(o - i * k);
+    const T *ri = r + i * ld;
+    double s = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < k; ++l) s += phi_t[int64_t(l) * k + j] * double(ri[l]);
+    mr[int64_t(j) * n_b + i] = s;
+}
+
+// Mode solves: row i of mode m's pseudo-inverse times the mode's right-hand
+// sides, basis functions 2m - 1 (cosine) and 2m (sine; mode 0 has basis
+// function 0 alone, mode k/2 of even k basis function k - 1 alone).  One
+// wavefront per (mode, row), 8 terms per lane in flight, the row read once
+// for both right-hand sides.
+template <typename T>
+__global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *__restrict__ st,
+                                                                 const T *__restrict__ pinv, int n_b, int k,
+                                                                 int modes, const double *__restrict__ mr,
+                                                                 double *__restrict__ mz) {
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (row >= int64_t(modes) * n_b) return;  // uniform over the wavefront
+    const int m = int(row / n_b);
+    const int64_t i = row - int64_t(m) * n_b;
+    const int jc = m == 0 ? 0 : 2 * m - 1;
+    const bool has_s = m > 0 && 2 * m < k;
+    const int js = has_s ? 2 * m : jc;
+    const T *prow = pinv + row * n_b;
+    const double *rc = mr + int64_t(jc) * n_b, *rs = mr + int64_t(js) * n_b;
+    double sc = 0.0, ss = 0.0;
+    for (int t0 = lane; t0 < n_b; t0 += 64 * 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 64 * u;
+            if (t < n_b) {
+                const double p = double(prow[t]);
+                sc += p * rc[t];
+                ss += p * rs[t];
+            }
+        }
+    }
+    sc = wave_sum(sc);
+    ss = wave_sum(ss);
+    if (lane == 0) {
+        mz[int64_t(jc) * n_b + i] = sc;
+        if (has_s) mz[int64_t(js) * n_b + i] = ss;
+    }
+}
+
+// Back transform z[i][l] = sum_j phi[j][l] mz[j][i]: one thread per (cell,
+// plane), the lanes reading the table along its rows.
+template <typename T>
+__global__ __launch_bounds__(kDenseBlock) void k_amg_modes_inv(const CgState *__restrict__ st,
+                                                               const double *__restrict__ phi, int n_b, int k, int ld,
+                                                               const double *__restrict__ mz, T *__restrict__ z) {
+    if (st->done) return;
+    const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= int64_t(n_b) * k) return;
+    const int64_t i = o / k;
+    const int l = int(o - i * k);
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < k; ++j) s += phi[int64_t(j) * k + l] * mz[int64_t(j) * n_b + i];
+    z[i * ld + l] = T(s);
+}
+
 // r.z partials into the r.z slot of part_b (a one-level hierarchy inside a
 // solve: the dense solve has no smoothing step to write them).
 template <typename T, int V>
@@ -728,6 +896,12 @@ AmgWork<T> carve_work(const fvx_amg *h, char *base, size_t *bytes) {
             v.q[0] = reinterpret_cast<T *>(take(nv));
         }
     }
+    if (h->modes) {
+        const fvx_op *op = h->lv[nl - 1].op;
+        const size_t nm = 8 * size_t(op->n_b) * op->k;
+        w.mr = reinterpret_cast<double *>(take(nm));
+        w.mz = reinterpret_cast<double *>(take(nm));
+    }
     if (bytes) *bytes = off;
     return w;
 }
@@ -804,13 +978,24 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
         }
         FVX_HIP(hipGetLastError());
     }
-    // Coarsest: dense pseudo-inverse.
+    // Coarsest: dense pseudo-inverse, or per plane mode.
     {
         const fvx_op *op = h->lv[nl - 1].op;
         const int64_t outs = op->n_b * int64_t(op->k);
-        const unsigned dense_grid = unsigned(h->coupled ? outs : ceil_div(outs, kDenseBlock / 64));
-        hipLaunchKernelGGL(k_amg_dense<T>, dim3(dense_grid), dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
-                           int(op->n_b), op->k, op->ld, int(h->coupled), rhs(nl - 1), w.lv[nl - 1].q[0]);
+        if (h->modes) {
+            const dim3 tgrid(unsigned(ceil_div(outs, kDenseBlock)));
+            const dim3 sgrid(unsigned(ceil_div(int64_t(h->modes) * op->n_b, kDenseBlock / 64)));
+            hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t, int(op->n_b),
+                               op->k, op->ld, rhs(nl - 1), w.mr);
+            hipLaunchKernelGGL(k_amg_modes_solve<T>, sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
+                               int(op->n_b), op->k, h->modes, static_cast<const double *>(w.mr), w.mz);
+            hipLaunchKernelGGL(k_amg_modes_inv<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi, int(op->n_b),
+                               op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
+        } else {
+            const unsigned dense_grid = unsigned(h->coupled ? outs : ceil_div(outs, kDenseBlock / 64));
+            hipLaunchKernelGGL(k_amg_dense<T>, dim3(dense_grid), dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
+                               int(op->n_b), op->k, op->ld, int(h->coupled), rhs(nl - 1), w.lv[nl - 1].q[0]);
+        }
         FVX_HIP(hipGetLastError());
         if (nl == 1 && fin) {
             by_v_only<T>(fin->vec, [&](auto Vt) {
@@ -883,6 +1068,7 @@ int fvx_amg_opts_default(fvx_amg_opts *o) {
     o->z_rule = 1.0;
     o->coarse_max = 2048;
     o->max_levels = 16;
+    o->mode_cells = 2048;
     return FVX_OK;
 }
 
@@ -917,6 +1103,7 @@ int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, v
         h->o = *o;
         h->coupled = P.coupled;
         h->n_d = P.n_d;
+        h->modes = P.modes;
         const size_t nl = P.L.size();
         h->lv.resize(nl);
         h->lv[0].op = op;
@@ -952,7 +1139,7 @@ int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, v
             keep.push_back(std::move(mptr));
             keep.push_back(std::move(midx));
         }
-        const size_t nd2 = size_t(P.n_d) * P.n_d;
+        const size_t nd2 = P.pinv.size();
         char *p64 = take(8 * nd2);
         FVX_HIP(hipMemcpyAsync(p64, P.pinv.data(), 8 * nd2, hipMemcpyHostToDevice, s));
         h->pinv64 = reinterpret_cast<const double *>(p64);
@@ -962,6 +1149,19 @@ int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, v
             char *q = take(4 * nd2);
             FVX_HIP(hipMemcpyAsync(q, p32.data(), 4 * nd2, hipMemcpyHostToDevice, s));
             h->pinv32 = reinterpret_cast<const float *>(q);
+        }
+        std::vector<double> phi_t;
+        if (P.modes) {
+            const int kc = P.L.back().k;
+            phi_t.resize(P.phi.size());
+            for (int j = 0; j < kc; ++j)
+                for (int l = 0; l < kc; ++l) phi_t[size_t(l) * kc + j] = P.phi[size_t(j) * kc + l];
+            char *a = take(8 * P.phi.size());
+            char *b = take(8 * phi_t.size());
+            FVX_HIP(hipMemcpyAsync(a, P.phi.data(), 8 * P.phi.size(), hipMemcpyHostToDevice, s));
+            FVX_HIP(hipMemcpyAsync(b, phi_t.data(), 8 * phi_t.size(), hipMemcpyHostToDevice, s));
+            h->phi = reinterpret_cast<const double *>(a);
+            h->phi_t = reinterpret_cast<const double *>(b);
         }
         // Smoother coefficients on [2 / ratio, 2] (Saad, Algorithm 12.1).
         const double b = 2.0, a = b / o->ratio;
@@ -1012,6 +1212,14 @@ int fvx_amg_aggregates(const fvx_amg *h, int32_t level, int32_t *agg) {
         FVX_REQUIRE(h && agg && level >= 0 && level < int32_t(h->lv.size()), FVX_E_ARG, "bad argument");
         FVX_REQUIRE(h->lv[level].kind == 1, FVX_E_ARG, "level is not coarsened by aggregation");
         std::copy(h->lv[level].agg.begin(), h->lv[level].agg.end(), agg);
+        return FVX_OK;
+    });
+}
+
+int fvx_amg_coarsest_modes(const fvx_amg *h, int32_t *modes) {
+    return guard([&] {
+        FVX_REQUIRE(h && modes, FVX_E_ARG, "NULL argument");
+        *modes = int32_t(h->modes);
         return FVX_OK;
     });
 }

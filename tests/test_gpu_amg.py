@@ -30,22 +30,36 @@ CASES = [
     (inputs.naca_delaunay(seed=3, n_interior=1500, n_surface=60, n_box_side=16), 4, 0.2, 1, False, 40),
 ]
 IDS = ["channel", "channel-z", "convection", "dirichlet", "independent", "odd-k", "triangles", "airfoil"]
+# coarsest level solved per plane mode (last entry: mode_cells); the oracle
+# solves the same coarsest level with one pseudo-inverse of all its planes
+MODE_CASES = [
+    (inputs.channel_base(32, 24), 8, None, 1, False, 40, 50),
+    (inputs.channel_base(24, 20), 16, 0.02, 1, False, 40, 30),   # planes merged down to one: a single mode
+    (inputs.channel_base(24, 20), 2, None, 1, False, 40, 150),   # two planes: modes 0 and 1, no sine
+    (inputs.channel_base(16, 12), 6, None, 1, True, 30, 60),
+    (inputs.channel_base(17, 13), 5, 0.05, 1, False, 25, 60),    # odd k: every mode > 0 has a sine
+    (inputs.unit_square_triangles(8), 4, None, 1, False, 30, 40),
+    (inputs.channel_base(20, 16), 5, None, 0, False, 20, 100),   # independent planes: no modes
+]
+MODE_IDS = ["channel-modes", "channel-z-modes", "k2-modes", "dirichlet-modes", "odd-k-modes", "triangles-modes",
+            "independent-modes"]
+ALL, ALL_IDS = CASES + MODE_CASES, IDS + MODE_IDS
 
 
-def _setup(spec, k, dz, coupling, dirichlet, coarse_max, degree=2):
+def _setup(spec, k, dz, coupling, dirichlet, coarse_max, mode_cells=0, degree=2):
     import paper_2508_06710_amd as fvx
     c = Case(spec, k, dz=dz, coupling=coupling, dirichlet=dirichlet)
-    amg = fvx.Amg(c.op, degree=degree, coarse_max=coarse_max)
+    amg = fvx.Amg(c.op, degree=degree, coarse_max=coarse_max, mode_cells=mode_cells)
     coupled = coupling == 1 and k >= 2
     A = (-c.L).tocsr()
     n_b = c.m3.n_b
-    opts = oamg.AmgOpts(degree=degree, coarse_max=coarse_max)
+    opts = oamg.AmgOpts(degree=degree, coarse_max=coarse_max, mode_cells=mode_cells)
     h = oamg.build(A if coupled else A[:n_b, :n_b].tocsr(), n_b, k if coupled else 1, coupled, opts,
                    columns=1 if coupled else k)
     return c, amg, h, coupled
 
 
-@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("case", ALL, ids=ALL_IDS)
 def test_levels_and_aggregates_equal_the_oracle(case):
     c, amg, h, coupled = _setup(*case)
     got = amg.levels()
@@ -57,9 +71,12 @@ def test_levels_and_aggregates_equal_the_oracle(case):
         assert k == (lv.k if coupled else c.k), l
         if lv.kind == "xy":
             assert np.array_equal(amg.aggregates(l), lv.agg), l
+    last, cells = h.levels[-1], (case[6] if len(case) > 6 else 0)
+    by_modes = coupled and 0 < last.n_b <= cells and (last.k // 2 + 1) * last.n_b ** 2 <= oamg.MODE_TERMS
+    assert amg.coarsest_modes == (last.k // 2 + 1 if by_modes else 0)
 
 
-@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("case", ALL, ids=ALL_IDS)
 def test_every_level_operator_is_the_galerkin_product(case):
     """Element by element within 1e-12 of (P^T |A| P)|x| carried down the
     levels -- the scale of the rounding of the Galerkin sums (a coarse entry
@@ -88,7 +105,7 @@ def _oracle_cycle(h, c, coupled, r):
 
 
 @pytest.mark.parametrize("degree", [2, 3])
-@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("case", ALL, ids=ALL_IDS)
 def test_one_v_cycle_matches_the_oracle(case, degree):
     c, amg, h, coupled = _setup(*case, degree=degree)
     ng = c.m3.n_groups()
@@ -102,8 +119,9 @@ def test_one_v_cycle_matches_the_oracle(case, degree):
     assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
-def test_fp32_cycle_is_close_to_the_fp64_cycle():
-    c, amg, h, coupled = _setup(*CASES[0])
+@pytest.mark.parametrize("case", [CASES[0], MODE_CASES[0]], ids=["dense", "modes"])
+def test_fp32_cycle_is_close_to_the_fp64_cycle(case):
+    c, amg, h, coupled = _setup(*case)
     r = oracle.project_mean(inputs.rhs_uniform(111, c.m3.N), 1)
     z32 = c.op.to_planes(amg.apply(c.op.to_rows(r, dtype=c.fvx.F32)), dtype=c.fvx.F32).astype(np.float64)
     ref = oamg.vcycle(h, r)
@@ -113,8 +131,8 @@ def test_fp32_cycle_is_close_to_the_fp64_cycle():
 def test_one_level_is_the_exact_pseudo_inverse():
     import paper_2508_06710_amd as fvx
     c = Case(inputs.channel_base(10, 8), 4)
-    amg = fvx.Amg(c.op, coarse_max=2048)
-    assert amg.n_levels == 1
+    amg = fvx.Amg(c.op, coarse_max=2048, mode_cells=0)
+    assert amg.n_levels == 1 and amg.coarsest_modes == 0
     r = oracle.project_mean(inputs.rhs_uniform(112, c.m3.N), 1)
     z = c.op.to_planes(amg.apply(c.op.to_rows(r)))
     A = (-c.L).tocsr()
@@ -122,6 +140,42 @@ def test_one_level_is_the_exact_pseudo_inverse():
     b = inputs.rhs_uniform(113, c.m3.N)
     X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, amg=amg)
     assert st["status"] == 0 and st["iters"] == 1
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_one_level_by_plane_modes_is_the_exact_pseudo_inverse(k):
+    import paper_2508_06710_amd as fvx
+    c = Case(inputs.channel_base(10, 8), k)
+    amg = fvx.Amg(c.op, coarse_max=20, mode_cells=80)
+    assert amg.n_levels == 1 and amg.coarsest_modes == k // 2 + 1
+    r = oracle.project_mean(inputs.rhs_uniform(120, c.m3.N), 1)
+    z = c.op.to_planes(amg.apply(c.op.to_rows(r)))
+    A = (-c.L).tocsr()
+    assert np.linalg.norm(A @ z - r) <= 1e-12 * np.linalg.norm(r)
+    assert abs(z.sum()) <= 1e-12 * np.abs(z).sum()         # the pseudo-inverse: no constant component
+    b = inputs.rhs_uniform(121, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, amg=amg)
+    assert st["status"] == 0 and st["iters"] == 1
+
+
+def test_default_options_use_plane_modes_within_the_term_budget():
+    """Default options (mode_cells 2048): 17 plane modes of the 768-cell base
+    exceed the 2^23-term budget, so the base is aggregated once more and the
+    next level is solved per mode; the levels equal the oracle's and the
+    preconditioned solve reaches its tolerance by the oracle's matrix."""
+    import paper_2508_06710_amd as fvx
+    c = Case(inputs.channel_base(32, 24), 32)
+    amg = fvx.Amg(c.op)
+    h = oamg.build((-c.L).tocsr(), c.m3.n_b, 32, True, oamg.AmgOpts(mode_cells=2048), solve_coarsest=False)
+    got = amg.levels()
+    assert [(g[0], g[1]) for g in got] == [(lv.n_b, lv.k) for lv in h.levels] and len(got) >= 2
+    assert amg.coarsest_modes == h.levels[-1].k // 2 + 1
+    b = inputs.rhs_uniform(122, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, amg=amg)
+    assert st["status"] == 0
+    assert _true_relres(c, c.op.to_planes(X), b) <= 1e-10 * 1.05
+    _, s0 = c.op.solve(c.op.to_rows(b), rtol=1e-10)
+    assert st["iters"] < s0["iters"] // 5
 
 
 def _true_relres(c, x, b):
@@ -133,7 +187,7 @@ def _true_relres(c, x, b):
     return np.linalg.norm(r) / np.linalg.norm(bp)
 
 
-@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("case", ALL, ids=ALL_IDS)
 def test_amg_pcg_residual_and_iterations_match_the_oracle(case):
     c, amg, h, coupled = _setup(*case)
     b = inputs.rhs_uniform(114, c.m3.N)
@@ -161,7 +215,7 @@ def test_amg_pcg_matches_dense_solve_and_repeats_bitwise():
     assert np.max(np.abs(x - xd)) <= 1e-9 * np.max(np.abs(xd))
 
 
-@pytest.mark.parametrize("case", [CASES[0], CASES[4]], ids=["coupled", "independent"])
+@pytest.mark.parametrize("case", [CASES[0], CASES[4], MODE_CASES[0]], ids=["coupled", "independent", "modes"])
 def test_mixed_precision_with_amg(case):
     c, amg, h, coupled = _setup(*case)
     b = inputs.rhs_uniform(116, c.m3.N)
@@ -194,12 +248,13 @@ def test_arguments_are_checked():
     with pytest.raises(fvx.FvxError):
         fvx.solve_batch([c.op, c.op], [B, B], amg=amg)  # batches: single solves only
     for kw in (dict(degree=1), dict(degree=9), dict(ratio=1.0), dict(beta=0.0), dict(coarse_max=0),
-               dict(coarse_max=4096), dict(max_levels=0), dict(max_levels=17)):
+               dict(coarse_max=4096), dict(max_levels=0), dict(max_levels=17), dict(mode_cells=-1),
+               dict(mode_cells=2049)):
         with pytest.raises(fvx.FvxError):
             fvx.Amg(c.op, **kw)
     big = Case(inputs.channel_base(40, 30), 4)          # 4800 unknowns
     with pytest.raises(fvx.FvxError):
-        fvx.Amg(big.op, max_levels=1)                   # coarsest level above 2048 unknowns
+        fvx.Amg(big.op, max_levels=1, mode_cells=0)     # coarsest level above 2048 unknowns
     m = fvx.Mesh.from_spec(inputs.channel_base(12, 10))
     s13 = fvx.Operator(m, 4, 0.5, fvx.PERIODIC_Z, stencil=13)
     with pytest.raises(fvx.FvxError):

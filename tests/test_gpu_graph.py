@@ -69,7 +69,7 @@ def test_graph_equals_phases(spec, k, coupling, kw, name, poll):
 def test_graph_multigrid():
     c = Case(inputs.channel_base(32, 24), 8, with_f32=True)
     fvx = c.fvx
-    amg = fvx.Amg(c.op, coarse_max=64)
+    amg = fvx.Amg(c.op, coarse_max=64, mode_cells=0)
     b = inputs.rhs_uniform(23, c.m3.N)
     B = c.op.to_rows(b)
     for kw in ({}, {"precision": fvx.MIXED, "inner_rtol": 1e-4}):
@@ -77,8 +77,10 @@ def test_graph_multigrid():
         for _ in range(2):
             _same(phases, c.op.solve(B, rtol=1e-10, amg=amg, poll_every=4, launch=fvx.LAUNCH_GRAPH, **kw))
         assert _relres(c, c.op.to_planes(phases[0]), b) <= 1.05e-10
-    # a new hierarchy of the same operator (a new serial) is not served from the old one's graphs
-    amg2 = fvx.Amg(c.op, coarse_max=20, degree=3)
+    # a new hierarchy of the same operator (a new serial) is not served from
+    # the old one's graphs; its coarsest level is solved per plane mode
+    amg2 = fvx.Amg(c.op, coarse_max=20, degree=3, mode_cells=50)
+    assert amg2.n_levels >= 3
     phases = c.op.solve(B, rtol=1e-10, amg=amg2, poll_every=4, launch=fvx.LAUNCH_PHASES)
     _same(phases, c.op.solve(B, rtol=1e-10, amg=amg2, poll_every=4, launch=fvx.LAUNCH_GRAPH))
 

@@ -321,3 +321,60 @@ def test_galerkin_level_of_a_uniform_periodic_box_is_the_closed_form_stencil():
     A1 = np.zeros_like(E)
     A1[np.ix_(perm, perm)] = h.levels[1].A.toarray()
     np.testing.assert_allclose(A1, E, rtol=0, atol=1e-13 * np.abs(E).max())
+
+
+def test_mode_rule_stops_at_the_first_level_with_few_base_cells():
+    m3, A = _case(inputs.channel_base(32, 24), 8)
+    full = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40))
+    for cells in (1000, 200, 50):
+        h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40, mode_cells=cells))
+        first = next(i for i, lv in enumerate(full.levels) if lv.n_b <= cells)
+        assert len(h.levels) == first + 1
+        for a, b in zip(h.levels, full.levels):
+            assert (a.n_b, a.k) == (b.n_b, b.k)
+            assert (a.A != b.A).nnz == 0
+    # within mode_cells but above the mode terms: coarsening goes on
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40, mode_cells=2048), solve_coarsest=False)
+    sizes = [(lv.n_b, lv.k) for lv in h.levels]
+    last = next(i for i, lv in enumerate(full.levels) if (lv.k // 2 + 1) * lv.n_b ** 2 <= amg.MODE_TERMS)
+    assert sizes == [(lv.n_b, lv.k) for lv in full.levels[:last + 1]] and h.pinv is None
+    assert (m3.k // 2 + 1) * m3.n_b ** 2 <= amg.MODE_TERMS              # this case: level 0 within both
+    m32, A32 = _case(inputs.channel_base(32, 24), 32)                   # 17 modes of 768^2 > 2^23 terms
+    h32 = amg.build(A32, m32.n_b, 32, True, amg.AmgOpts(coarse_max=40, mode_cells=2048), solve_coarsest=False)
+    assert [(lv.n_b, lv.k) for lv in h32.levels][0] == (768, 32) and len(h32.levels) >= 2
+    assert (h32.levels[-1].k // 2 + 1) * h32.levels[-1].n_b ** 2 <= amg.MODE_TERMS
+    assert 17 * 768 ** 2 > amg.MODE_TERMS
+    # independent planes: the rule is for coupled planes only
+    n_b = m3.n_b
+    A0 = A[:n_b, :n_b].tocsr()
+    ha = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20), columns=8)
+    hb = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20, mode_cells=2000), columns=8)
+    assert [lv.n_b for lv in ha.levels] == [lv.n_b for lv in hb.levels]
+
+
+@pytest.mark.parametrize("k,dirichlet", [(8, False), (5, False), (6, True), (2, False)])
+def test_coarsest_pinv_is_blockwise_by_plane_modes(k, dirichlet):
+    """The coarsest level of coupled planes is block circulant over the
+    planes, so its pseudo-inverse is the inverse discrete Fourier transform
+    (numpy's FFT over the plane offset) of the pseudo-inverses of the mode
+    blocks sum_d C_d exp(-2 pi i m d / k) -- the closed form the library's
+    per-mode solve relies on, here pinned against the oracle's
+    eigen-decomposition of the whole level."""
+    m3, A = _case(inputs.channel_base(12, 10), k, dirichlet=dirichlet)
+    h = amg.build(A, m3.n_b, m3.k, True, amg.AmgOpts(coarse_max=40, mode_cells=40))
+    lv = h.levels[-1]
+    n = lv.n_b
+    assert lv.k == k and n <= 40 and len(h.levels) >= 2
+    B = lv.A.toarray()
+    C = np.stack([B[:n, d * n:(d + 1) * n] for d in range(k)])      # block (0, d) = C_d
+    for l in range(k):                                                # block (l, l + d) = C_d
+        for d in range(k):
+            assert np.array_equal(B[l * n:(l + 1) * n, ((l + d) % k) * n:((l + d) % k + 1) * n], C[d])
+    Mhat = np.fft.fft(C, axis=0)                                      # mode m: sum_d C_d e^{-2 pi i m d / k}
+    Phat = np.stack([np.linalg.pinv(Mhat[m], rcond=1e-10) for m in range(k)])
+    Pd = np.fft.ifft(Phat, axis=0)                                    # offset d block of the pseudo-inverse
+    assert np.abs(Pd.imag).max() <= 1e-12 * np.abs(Pd.real).max()
+    for l in range(k):
+        for d in range(k):
+            got = h.pinv[l * n:(l + 1) * n, ((l + d) % k) * n:((l + d) % k + 1) * n]
+            assert np.allclose(got, Pd[d].real, rtol=0, atol=1e-9 * np.abs(Pd.real).max())
