@@ -703,11 +703,12 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_fwd(const CgState *__
     mr[int64_t(j) * n_b + i] = s;
 }
 
-// Mode solves: row i of mode m's pseudo-inverse times the mode's right-hand
+// Mode solves: rows i of mode m's pseudo-inverse times the mode's right-hand
 // sides, basis functions 2m - 1 (cosine) and 2m (sine; mode 0 has basis
 // function 0 alone, mode k/2 of even k basis function k - 1 alone).  One
-// wavefront per (mode, row), 8 terms per lane in flight, the row read once
-// for both right-hand sides.
+// wavefront per mode and pair of rows (2p, 2p + 1), 8 terms of each row per
+// lane in flight, the right-hand sides read once for both rows and each row
+// once for both right-hand sides.
 template <typename T>
 __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *__restrict__ st,
                                                                  const T *__restrict__ pinv, int n_b, int k,
@@ -715,32 +716,43 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *
                                                                  double *__restrict__ mz) {
     if (st->done) return;
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (row >= int64_t(modes) * n_b) return;  // uniform over the wavefront
-    const int m = int(row / n_b);
-    const int64_t i = row - int64_t(m) * n_b;
+    const int64_t pair = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t pairs = (n_b + 1) / 2;
+    if (pair >= int64_t(modes) * pairs) return;  // uniform over the wavefront
+    const int m = int(pair / pairs);
+    const int64_t i = 2 * (pair - int64_t(m) * pairs);
+    const bool two = i + 1 < n_b;
     const int jc = m == 0 ? 0 : 2 * m - 1;
     const bool has_s = m > 0 && 2 * m < k;
     const int js = has_s ? 2 * m : jc;
-    const T *prow = pinv + row * n_b;
+    const T *p0 = pinv + (int64_t(m) * n_b + i) * n_b;
+    const T *p1 = two ? p0 + n_b : p0;
     const double *rc = mr + int64_t(jc) * n_b, *rs = mr + int64_t(js) * n_b;
-    double sc = 0.0, ss = 0.0;
+    double c0 = 0.0, s0 = 0.0, c1 = 0.0, s1 = 0.0;
     for (int t0 = lane; t0 < n_b; t0 += 64 * 8) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int t = t0 + 64 * u;
             if (t < n_b) {
-                const double p = double(prow[t]);
-                sc += p * rc[t];
-                ss += p * rs[t];
+                const double a = double(p0[t]), b = double(p1[t]), x = rc[t], y = rs[t];
+                c0 += a * x;
+                s0 += a * y;
+                c1 += b * x;
+                s1 += b * y;
             }
         }
     }
-    sc = wave_sum(sc);
-    ss = wave_sum(ss);
+    c0 = wave_sum(c0);
+    s0 = wave_sum(s0);
+    c1 = wave_sum(c1);
+    s1 = wave_sum(s1);
     if (lane == 0) {
-        mz[int64_t(jc) * n_b + i] = sc;
-        if (has_s) mz[int64_t(js) * n_b + i] = ss;
+        mz[int64_t(jc) * n_b + i] = c0;
+        if (has_s) mz[int64_t(js) * n_b + i] = s0;
+        if (two) {
+            mz[int64_t(jc) * n_b + i + 1] = c1;
+            if (has_s) mz[int64_t(js) * n_b + i + 1] = s1;
+        }
     }
 }
 
@@ -984,7 +996,7 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
         const int64_t outs = op->n_b * int64_t(op->k);
         if (h->modes) {
             const dim3 tgrid(unsigned(ceil_div(outs, kDenseBlock)));
-            const dim3 sgrid(unsigned(ceil_div(int64_t(h->modes) * op->n_b, kDenseBlock / 64)));
+            const dim3 sgrid(unsigned(ceil_div(int64_t(h->modes) * ((op->n_b + 1) / 2), kDenseBlock / 64)));
             hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t, int(op->n_b),
                                op->k, op->ld, rhs(nl - 1), w.mr);
             hipLaunchKernelGGL(k_amg_modes_solve<T>, sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
