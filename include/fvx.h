@@ -488,11 +488,14 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   most coarse_max unknowns (n_b k, all planes) is the coarsest; it is
  *   solved with its dense pseudo-inverse (inverse with Dirichlet walls) per
  *   independent system, formed on the host in FP64.
- *   Plane modes (coupled planes, mode_cells > 0): a level with at most
- *   mode_cells base cells whose mode systems (below) hold at most 2^23
- *   terms in all, (floor(k/2) + 1) n_b^2 <= 2^23 (64 MiB in FP64, read once
- *   per cycle), is also the coarsest, and a coarsest level within both
- *   limits is solved per plane mode.  Its planes are coupled
+ *   Plane modes (mode_cells > 0): a level with at most mode_cells base
+ *   cells whose solve per plane (below) multiplies at most 2^23
+ *   pseudo-inverse terms per cycle, u n_b^2 <= 2^23 with u = floor(k/2) + 1
+ *   for coupled planes and u = ceil(k/2) for independent ones, is also the
+ *   coarsest, and a coarsest level within both limits and above coarse_max
+ *   unknowns is solved per plane: independent planes by the one n_b x n_b
+ *   pseudo-inverse, two planes per row read; coupled planes per mode.
+ *   Coupled planes are coupled
  *   periodically, so the real discrete Fourier basis along the planes splits
  *   it exactly into floor(k/2) + 1 systems A_b + (2 - 2 cos(2 pi m / k)) W of
  *   n_b unknowns (mode m; one right-hand side for m = 0 and m = k/2, a cosine
@@ -520,8 +523,8 @@ typedef struct fvx_amg_opts {
     double z_rule;       /* plane-merging threshold (>= 0) */
     int32_t coarse_max;  /* coarsest level size n_b k (1..2048) */
     int32_t max_levels;  /* 1..16 */
-    int32_t mode_cells;  /* coupled planes: coarsest at <= mode_cells base cells (and <= 2^23 mode
-                            terms), solved per plane mode (0: off; 0..2048) */
+    int32_t mode_cells;  /* coarsest at <= mode_cells base cells (and <= 2^23 terms per cycle),
+                            solved per plane mode (0: off; 0..2048) */
 } fvx_amg_opts;
 
 /* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 2048, max_levels 16, mode_cells 2048. */
@@ -548,8 +551,10 @@ int fvx_amg_level(const fvx_amg *amg, int32_t level, int64_t *n_b, int32_t *k, i
                   const fvx_op **op);
 /* Base cell -> aggregate of a level of kind 1 (host int32 [n_b]). */
 int fvx_amg_aggregates(const fvx_amg *amg, int32_t level, int32_t *agg);
-/* Plane modes of the coarsest level's solve: floor(k/2) + 1 when it is
- * solved per plane mode, 0 when by one dense pseudo-inverse (host int32). */
+/* Systems of the coarsest level's solve per plane: floor(k/2) + 1 plane
+ * modes (coupled planes) or 1 shared by the planes (independent planes); 0
+ * when it is solved by one dense pseudo-inverse over its unknowns (host
+ * int32). */
 int fvx_amg_coarsest_modes(const fvx_amg *amg, int32_t *modes);
 
 /* One V-cycle Z = M^-1 R (device [n_b][ld] of the fine op, precision dtype

@@ -28,11 +28,12 @@ with no block reuse:
   its assembled operator: t_ij = -a_ij within plane 0, w_i = -a_i,(plane 1, i)
   (halved for two planes, whose two plane neighbours coincide).
 * Coarsest level (at most coarse_max unknowns, counted over all planes;
-  independent planes share one hierarchy; with coupled planes and
-  mode_cells > 0 also a level of at most mode_cells base cells whose plane
-  modes hold at most MODE_TERMS terms, (k // 2 + 1) n_b^2, which the
-  library solves per plane mode -- here it is solved like any other
-  coarsest level, as one matrix): the pseudo-inverse, from the
+  independent planes share one hierarchy; with mode_cells > 0 also a level
+  of at most mode_cells base cells whose solve per plane multiplies at most
+  MODE_TERMS pseudo-inverse terms, u n_b^2 with u = k // 2 + 1 plane modes
+  of coupled planes or u = ceil(columns / 2) plane pairs of independent
+  ones, which the library solves per plane (mode) -- here it is solved like
+  any other coarsest level, as one matrix): the pseudo-inverse, from the
   eigen-decomposition with the eigenvalues below 1e-10 of the Galerkin scale
   dropped (the largest row sum of |P|^T |A| |P| carried down the levels: a
   one-cell Neumann level is zero up to the rounding of its sums).
@@ -186,8 +187,8 @@ def build(A0: sp.csr_matrix, n_b: int, k: int, coupled: bool, opts: AmgOpts | No
         h.levels.append(lev)
         if lev.n_b * lev.k * columns <= opts.coarse_max or len(h.levels) >= opts.max_levels:
             break
-        if (coupled and opts.mode_cells > 0 and lev.n_b <= opts.mode_cells
-                and (lev.k // 2 + 1) * lev.n_b ** 2 <= MODE_TERMS):
+        units = lev.k // 2 + 1 if coupled else (columns + 1) // 2
+        if opts.mode_cells > 0 and lev.n_b <= opts.mode_cells and units * lev.n_b ** 2 <= MODE_TERMS:
             break
         T, w = couplings(lev.A, lev.n_b, lev.k)
         tmax = np.zeros(lev.n_b)

@@ -27,10 +27,11 @@ struct fvx_amg {
     fvx_amg_opts o{};
     bool coupled = false;                    // planes coupled (one system); else k independent systems
     int n_d = 0;                             // unknowns of the coarsest dense solve per system
-    int modes = 0;                           // > 0: coarsest solved per plane mode (modes systems of n_d = n_b)
+    int modes = 0;                           // > 0: coarsest solved per plane (mode): coupled planes floor(k/2) + 1
+                                             //   mode systems of n_d = n_b; independent planes 1, shared
     const double *pinv64 = nullptr;          // [n_d][n_d] coarsest pseudo-inverse (AoS order: cell, plane),
     const float *pinv32 = nullptr;           //   or [modes][n_d][n_d], one per plane mode
-    const double *phi = nullptr;             // modes: [k][k] real Fourier basis, row j = basis function j
+    const double *phi = nullptr;             // coupled modes: [k][k] real Fourier basis, row j = basis function j
     const double *phi_t = nullptr;           //   and its transpose
     double inv_theta = 1.0;
     double c1[fvx::kMaxAmgDegree] = {}, c2[fvx::kMaxAmgDegree] = {};  // smoother step j uses c1[j], c2[j]

@@ -202,13 +202,15 @@ double plane_dominance(const HostLevel &L) {
     return ratio[m];
 }
 
-// Terms of the plane-mode pseudo-inverses of a coupled level: floor(k/2) + 1
-// modes of n x n.  A level is solved per mode only within kModeTerms (64 MiB
-// in FP64, read once per cycle).
+// Pseudo-inverse terms one cycle multiplies when a level is solved per plane
+// (mode): coupled planes, floor(k/2) + 1 modes of n x n, each read once for
+// its cosine and sine right-hand sides; independent planes, the one n x n
+// pseudo-inverse once per pair of planes.  A level is solved that way only
+// within kModeTerms (64 MiB of FP64 terms per cycle).
 constexpr int64_t kModeTerms = int64_t(1) << 23;
-int64_t mode_terms(const HostLevel &L) { return int64_t(L.k / 2 + 1) * L.n * L.n; }
+int64_t mode_units(const HostLevel &L, bool coupled) { return coupled ? L.k / 2 + 1 : (L.k + 1) / 2; }
 bool by_modes(const HostLevel &L, bool coupled, const fvx_amg_opts &o) {
-    return coupled && o.mode_cells > 0 && L.n <= o.mode_cells && mode_terms(L) <= kModeTerms;
+    return o.mode_cells > 0 && L.n <= o.mode_cells && mode_units(L, coupled) * L.n * L.n <= kModeTerms;
 }
 
 std::vector<HostLevel> build_levels(HostLevel L0, bool coupled, const fvx_amg_opts &o) {
@@ -429,10 +431,10 @@ struct Plan {
     std::vector<fvx_op_desc> descs;
     std::vector<size_t> op_bytes;
     std::vector<double> pinv;
-    std::vector<double> phi;  // plane modes: the Fourier basis of the coarsest level's planes
+    std::vector<double> phi;  // plane modes of coupled planes: the Fourier basis of the coarsest level's planes
     bool coupled = false;
     int n_d = 0;
-    int modes = 0;
+    int modes = 0;  // coarsest per plane (mode): coupled floor(k/2) + 1 systems; independent planes 1, shared
 };
 
 void check_amg_opts(const fvx_amg_opts *o) {
@@ -457,11 +459,18 @@ Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
     P.coupled = op->zfaces;
     P.L = build_levels(fine_level(*m, op, dirichlet), P.coupled, *o);
     const HostLevel &last = P.L.back();
-    if (by_modes(last, P.coupled, *o)) {
+    // A level within coarse_max keeps the dense solve (one launch; the solve
+    // per plane takes three).
+    if (last.n * last.k > o->coarse_max && by_modes(last, P.coupled, *o)) {
         P.n_d = int(last.n);
-        P.modes = last.k / 2 + 1;
-        P.pinv = mode_pinvs(last, op->singular, P.modes);
-        P.phi = fourier_basis(last.k);
+        if (P.coupled) {
+            P.modes = last.k / 2 + 1;
+            P.pinv = mode_pinvs(last, op->singular, P.modes);
+            P.phi = fourier_basis(last.k);
+        } else {
+            P.modes = 1;
+            P.pinv = coarsest_pinv(last, false, op->singular);
+        }
     } else {
         const int64_t nd = last.n * (P.coupled ? last.k : 1);
         FVX_REQUIRE(nd <= kMaxAmgCoarse, FVX_E_UNSUPPORTED,
@@ -680,9 +689,10 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_dense(const CgState *__rest
     if (lane == 0) z[i * ld + l] = T(s);
 }
 
-// Coarsest level per plane mode (coupled planes).  The level's vectors are
-// [n_b][ld] (cell, plane); the mode vectors are [k][n_b] (basis function,
-// cell), one contiguous right-hand side per basis function.
+// Coarsest level per plane mode.  The level's vectors are [n_b][ld] (cell,
+// plane); the mode vectors are [k][n_b] (basis function, cell), one
+// contiguous right-hand side per basis function.  Independent planes take
+// the identity for the basis (phi, phi_t NULL: the transforms transpose).
 // Forward transform mr[j][i] = sum_l phi[j][l] r[i][l]: one thread per
 // (cell, basis function), the lanes of a cell reading the transposed table
 // along its rows and the cell's planes by broadcast.
@@ -698,41 +708,49 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_fwd(const CgState *__
     const int j = int(o - i * k);
     const T *ri = r + i * ld;
     double s = 0.0;
+    if (phi_t) {
 #pragma unroll 8
-    for (int l = 0; l < k; ++l) s += phi_t[int64_t(l) * k + j] * double(ri[l]);
+        for (int l = 0; l < k; ++l) s += phi_t[int64_t(l) * k + j] * double(ri[l]);
+    } else {
+        s = double(ri[j]);
+    }
     mr[int64_t(j) * n_b + i] = s;
 }
 
-// Mode solves: rows i of mode m's pseudo-inverse times the mode's right-hand
-// sides, basis functions 2m - 1 (cosine) and 2m (sine; mode 0 has basis
-// function 0 alone, mode k/2 of even k basis function k - 1 alone).  One
-// wavefront per mode and pair of rows (2p, 2p + 1), 8 terms of each row per
-// lane in flight, the right-hand sides read once for both rows and each row
-// once for both right-hand sides.
+// Mode solves: rows i of a pseudo-inverse times two right-hand sides.
+// Coupled planes, unit u = mode m: mode m's pseudo-inverse, basis functions
+// 2m - 1 (cosine) and 2m (sine; mode 0 has basis function 0 alone, mode k/2
+// of even k basis function k - 1 alone).  Independent planes (shared), unit
+// u: the one pseudo-inverse, planes 2u and 2u + 1 (< k).  One wavefront per
+// unit and pair of rows (2p, 2p + 1), 8 terms of each row per lane in
+// flight, the right-hand sides read once for both rows and each row once for
+// both right-hand sides.
 template <typename T>
 __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *__restrict__ st,
                                                                  const T *__restrict__ pinv, int n_b, int k,
-                                                                 int modes, const double *__restrict__ mr,
+                                                                 int units, int shared,
+                                                                 const double *__restrict__ mr,
                                                                  double *__restrict__ mz) {
     if (st->done) return;
     const int lane = threadIdx.x & 63;
     const int64_t pair = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t pairs = (n_b + 1) / 2;
-    if (pair >= int64_t(modes) * pairs) return;  // uniform over the wavefront
-    const int m = int(pair / pairs);
-    const int64_t i = 2 * (pair - int64_t(m) * pairs);
+    if (pair >= int64_t(units) * pairs) return;  // uniform over the wavefront
+    const int u = int(pair / pairs);
+    const int64_t i = 2 * (pair - int64_t(u) * pairs);
     const bool two = i + 1 < n_b;
-    const int jc = m == 0 ? 0 : 2 * m - 1;
-    const bool has_s = m > 0 && 2 * m < k;
-    const int js = has_s ? 2 * m : jc;
+    const int m = shared ? 0 : u;
+    const int jc = shared ? 2 * u : (m == 0 ? 0 : 2 * m - 1);
+    const bool has_s = shared ? 2 * u + 1 < k : (m > 0 && 2 * m < k);
+    const int js = has_s ? jc + 1 : jc;
     const T *p0 = pinv + (int64_t(m) * n_b + i) * n_b;
     const T *p1 = two ? p0 + n_b : p0;
     const double *rc = mr + int64_t(jc) * n_b, *rs = mr + int64_t(js) * n_b;
     double c0 = 0.0, s0 = 0.0, c1 = 0.0, s1 = 0.0;
     for (int t0 = lane; t0 < n_b; t0 += 64 * 8) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + 64 * u;
+        for (int v = 0; v < 8; ++v) {
+            const int t = t0 + 64 * v;
             if (t < n_b) {
                 const double a = double(p0[t]), b = double(p1[t]), x = rc[t], y = rs[t];
                 c0 += a * x;
@@ -768,8 +786,12 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_inv(const CgState *__
     const int64_t i = o / k;
     const int l = int(o - i * k);
     double s = 0.0;
+    if (phi) {
 #pragma unroll 8
-    for (int j = 0; j < k; ++j) s += phi[int64_t(j) * k + l] * mz[int64_t(j) * n_b + i];
+        for (int j = 0; j < k; ++j) s += phi[int64_t(j) * k + l] * mz[int64_t(j) * n_b + i];
+    } else {
+        s = mz[int64_t(l) * n_b + i];
+    }
     z[i * ld + l] = T(s);
 }
 
@@ -996,11 +1018,12 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
         const int64_t outs = op->n_b * int64_t(op->k);
         if (h->modes) {
             const dim3 tgrid(unsigned(ceil_div(outs, kDenseBlock)));
-            const dim3 sgrid(unsigned(ceil_div(int64_t(h->modes) * ((op->n_b + 1) / 2), kDenseBlock / 64)));
+            const int units = h->coupled ? h->modes : (op->k + 1) / 2;
+            const dim3 sgrid(unsigned(ceil_div(int64_t(units) * ((op->n_b + 1) / 2), kDenseBlock / 64)));
             hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t, int(op->n_b),
                                op->k, op->ld, rhs(nl - 1), w.mr);
             hipLaunchKernelGGL(k_amg_modes_solve<T>, sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
-                               int(op->n_b), op->k, h->modes, static_cast<const double *>(w.mr), w.mz);
+                               int(op->n_b), op->k, units, int(!h->coupled), static_cast<const double *>(w.mr), w.mz);
             hipLaunchKernelGGL(k_amg_modes_inv<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi, int(op->n_b),
                                op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
         } else {
@@ -1163,7 +1186,7 @@ int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, v
             h->pinv32 = reinterpret_cast<const float *>(q);
         }
         std::vector<double> phi_t;
-        if (P.modes) {
+        if (!P.phi.empty()) {
             const int kc = P.L.back().k;
             phi_t.resize(P.phi.size());
             for (int j = 0; j < kc; ++j)

@@ -39,10 +39,12 @@ MODE_CASES = [
     (inputs.channel_base(16, 12), 6, None, 1, True, 30, 60),
     (inputs.channel_base(17, 13), 5, 0.05, 1, False, 25, 60),    # odd k: every mode > 0 has a sine
     (inputs.unit_square_triangles(8), 4, None, 1, False, 30, 40),
-    (inputs.channel_base(20, 16), 5, None, 0, False, 20, 100),   # independent planes: no modes
+    (inputs.channel_base(20, 16), 5, None, 0, False, 20, 100),   # independent planes: one shared system
+    (inputs.channel_base(24, 20), 8, None, 0, False, 20, 100),   # independent planes, an even count
+    (inputs.channel_base(17, 13), 1, None, 1, False, 20, 400),   # one plane: a single mode, 221 cells
 ]
 MODE_IDS = ["channel-modes", "channel-z-modes", "k2-modes", "dirichlet-modes", "odd-k-modes", "triangles-modes",
-            "independent-modes"]
+            "independent-modes", "independent-8-modes", "k1-modes"]
 ALL, ALL_IDS = CASES + MODE_CASES, IDS + MODE_IDS
 
 
@@ -72,8 +74,10 @@ def test_levels_and_aggregates_equal_the_oracle(case):
         if lv.kind == "xy":
             assert np.array_equal(amg.aggregates(l), lv.agg), l
     last, cells = h.levels[-1], (case[6] if len(case) > 6 else 0)
-    by_modes = coupled and 0 < last.n_b <= cells and (last.k // 2 + 1) * last.n_b ** 2 <= oamg.MODE_TERMS
-    assert amg.coarsest_modes == (last.k // 2 + 1 if by_modes else 0)
+    units = last.k // 2 + 1 if coupled else (c.k + 1) // 2
+    above = last.n_b * (last.k if coupled else c.k) > case[5]       # within coarse_max: the dense solve
+    by_modes = above and 0 < last.n_b <= cells and units * last.n_b ** 2 <= oamg.MODE_TERMS
+    assert amg.coarsest_modes == ((last.k // 2 + 1 if coupled else 1) if by_modes else 0)
 
 
 @pytest.mark.parametrize("case", ALL, ids=ALL_IDS)

@@ -344,12 +344,19 @@ def test_mode_rule_stops_at_the_first_level_with_few_base_cells():
     assert [(lv.n_b, lv.k) for lv in h32.levels][0] == (768, 32) and len(h32.levels) >= 2
     assert (h32.levels[-1].k // 2 + 1) * h32.levels[-1].n_b ** 2 <= amg.MODE_TERMS
     assert 17 * 768 ** 2 > amg.MODE_TERMS
-    # independent planes: the rule is for coupled planes only
+    # independent planes: the planes counted in pairs, n_b^2 per pair
     n_b = m3.n_b
     A0 = A[:n_b, :n_b].tocsr()
     ha = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20), columns=8)
-    hb = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20, mode_cells=2000), columns=8)
-    assert [lv.n_b for lv in ha.levels] == [lv.n_b for lv in hb.levels]
+    for cols, cells in ((8, 2000), (8, 100), (64, 2000), (1, 2000)):
+        hb = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20, mode_cells=cells), columns=cols,
+                       solve_coarsest=False)
+        full = amg.build(A0, n_b, 1, False, amg.AmgOpts(coarse_max=20), columns=cols, solve_coarsest=False)
+        first = next(i for i, lv in enumerate(full.levels)
+                     if lv.n_b <= cells and (cols + 1) // 2 * lv.n_b ** 2 <= amg.MODE_TERMS)
+        assert [lv.n_b for lv in hb.levels] == [lv.n_b for lv in full.levels[:first + 1]]
+        assert all(lv.k == 1 for lv in hb.levels)
+    assert (64 + 1) // 2 * 768 ** 2 > amg.MODE_TERMS >= 4 * 768 ** 2     # 64 planes coarsen further than 8
 
 
 @pytest.mark.parametrize("k,dirichlet", [(8, False), (5, False), (6, True), (2, False)])
