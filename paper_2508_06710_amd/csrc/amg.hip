@@ -826,12 +826,17 @@ __global__ void k_amg_clear_state(CgState *st) {
 // V-cycle driver
 // ---------------------------------------------------------------------------
 
-// Launch tile of a level's kernels: 2 elements per lane when the row stride
-// allows, enough lanes per row to cover k in one pass (at most 64), 256
+// Launch tile of a level's kernels over n_rows rows: 2 elements per lane
+// when the row stride allows; 4 in FP32 over at least 2^18 elements (16-byte
+// lanes where the launch streams; on smaller launches, which wait on
+// latency, the wider lanes left too few threads and were slower), not on a
+// level whose planes are merged (its restriction takes one plane pair per
+// lane); enough lanes per row to cover k in one pass (at most 64), 256
 // threads, XCD-aware order, one row tile per workgroup.
-fvx_tile level_tile(const fvx_op *op) {
+fvx_tile level_tile(const fvx_op *op, int64_t n_rows, size_t es, bool merge) {
     fvx_tile t{};
-    t.vec = op->ld % 2 == 0 ? 2 : 1;
+    const bool wide = es == 4 && !merge && op->ld % 4 == 0 && n_rows * op->ld >= (int64_t(1) << 18);
+    t.vec = wide ? 4 : (op->ld % 2 == 0 ? 2 : 1);
     t.lanes_per_row = std::min(64, next_pow2(int(ceil_div(op->k, t.vec))));
     t.block = 256;
     t.xcd_remap = 1;
@@ -847,9 +852,9 @@ struct LevelLaunch {
 };
 
 template <typename T>
-LevelLaunch<T> level_launch(const fvx_op *op, int64_t n_rows) {
+LevelLaunch<T> level_launch(const fvx_op *op, int64_t n_rows, bool merge) {
     LevelLaunch<T> L;
-    const fvx_tile t = level_tile(op);
+    const fvx_tile t = level_tile(op, n_rows, sizeof(T), merge);
     RowGrid g;
     L.a = row_args<T>(op, n_rows, g, t);
     L.grid = dim3(unsigned(g.n_blocks));
@@ -977,7 +982,7 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
     // Down: pre-smooth, restrict.
     for (int l = 0; l + 1 < nl; ++l) {
         const fvx_op *op = h->lv[l].op;
-        const LevelLaunch<T> L = level_launch<T>(op, op->n_b);
+        const LevelLaunch<T> L = level_launch<T>(op, op->n_b, h->lv[l].kind == 2);
         const T *r = rhs(l);
         const auto &v = w.lv[l];
         for (int j = 1; j < deg; ++j)
@@ -986,7 +991,7 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
         const T *zs = v.s[(deg - 2) & 1];
         const fvx_op *nop = h->lv[l + 1].op;
         if (h->lv[l].kind == 1) {
-            const LevelLaunch<T> R = level_launch<T>(op, nop->n_b);
+            const LevelLaunch<T> R = level_launch<T>(op, nop->n_b, false);
             by_vec<T>(R.vec, op->zfaces, [&](auto Vt, auto Zt) {
                 constexpr int V = decltype(Vt)::value;
                 constexpr bool Z = decltype(Zt)::value;
@@ -1043,7 +1048,7 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
     // Up: prolongate + first post step, remaining post steps.
     for (int l = nl - 2; l >= 0; --l) {
         const fvx_op *op = h->lv[l].op;
-        const LevelLaunch<T> L = level_launch<T>(op, op->n_b);
+        const LevelLaunch<T> L = level_launch<T>(op, op->n_b, h->lv[l].kind == 2);
         const T *r = rhs(l);
         const auto &v = w.lv[l];
         const fvx_op *nop = h->lv[l + 1].op;

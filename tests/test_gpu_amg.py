@@ -132,6 +132,23 @@ def test_fp32_cycle_is_close_to_the_fp64_cycle(case):
     assert np.linalg.norm(z32 - ref) <= 1e-3 * np.linalg.norm(ref)
 
 
+def test_fp32_cycle_with_wide_lanes():
+    """An FP32 cycle whose finest levels stream (16384 and 4096 cells x 64
+    planes: 4 elements per lane in the smoother, the restriction and the
+    prolongation; 2 on the coarser and plane-merged levels) against the
+    oracle's FP64 cycle, and the mixed-precision solve with it."""
+    c, amg, h, coupled = _setup(inputs.channel_base(128, 128), 64, None, 1, False, 2048)
+    assert [lv.n_b for lv in h.levels[:2]] == [16384, 4096] and h.levels[2].kind == "z"
+    r = oracle.project_mean(inputs.rhs_uniform(123, c.m3.N), 1)
+    z32 = c.op.to_planes(amg.apply(c.op.to_rows(r, dtype=c.fvx.F32)), dtype=c.fvx.F32).astype(np.float64)
+    ref = oamg.vcycle(h, r)
+    assert np.linalg.norm(z32 - ref) <= 1e-3 * np.linalg.norm(ref)
+    b = inputs.rhs_uniform(124, c.m3.N)
+    X, st = c.op.solve(c.op.to_rows(b), rtol=1e-10, precision=c.fvx.MIXED, amg=amg)
+    assert st["status"] == 0
+    assert _true_relres(c, c.op.to_planes(X), b) <= 1e-10 * 1.05
+
+
 def test_one_level_is_the_exact_pseudo_inverse():
     import paper_2508_06710_amd as fvx
     c = Case(inputs.channel_base(10, 8), 4)
