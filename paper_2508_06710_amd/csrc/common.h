@@ -67,6 +67,10 @@ struct OpDev {
     // coefficient (13-point); NULL otherwise.
     const T *ell_v1 = nullptr;
     const T *w2 = nullptr;
+    // The same operators with their entries in the fixed direction order: per
+    // row one record of srec_width(stencil) coefficients (8 in-plane entries,
+    // diagonal, w, then 8 neighbouring-plane entries or w2); NULL otherwise.
+    const T *srec = nullptr;
     // Jacobi scaling of the SPD form -L: 1 / (-diag) per base row (1 where
     // the diagonal vanishes), shared by the k planes.
     const T *dinv = nullptr;
@@ -144,6 +148,10 @@ inline int next_pow2(int v) {
 // Row stride of multivectors for k planes: k itself when k <= 2 or a multiple
 // of 4, else k rounded up to a multiple of 4 (so 16-byte vector loads stay
 // aligned for both precisions).
+// Coefficients per row of a structured operator's packed record (13-point:
+// 11, padded to 12 for 16-byte records).
+constexpr int srec_width(int stencil) { return stencil == 27 ? 18 : 12; }
+
 inline int32_t ld_for_k(int32_t k) { return (k <= 2 || k % 4 == 0) ? k : (k + 3) / 4 * 4; }
 
 // ELL widths the kernels are compiled for (all gathers of a row issue before

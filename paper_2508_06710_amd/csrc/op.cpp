@@ -32,6 +32,10 @@ struct HostOp {
     // stored in the fixed direction order of stencil_dirs (an absent
     // neighbour, past a wall, being the row itself with value 0)
     int sdir = 0;
+    // and then each row's coefficients packed [n_b][srec_width]: the 8 entries,
+    // diagonal, w, then the 8 neighbouring-plane entries (27-point) or w2 and a
+    // pad (13-point), so that a row's coefficients are one contiguous record
+    std::vector<double> srec;
 };
 
 // One axis of a Cartesian base: cell centres and, when periodic, the period.
@@ -223,6 +227,20 @@ HostOp build_host_stencil(const fvx_mesh &m, const fvx_op_desc &d) {
     h.py = m.periodic_y;
     h.diag32.assign(nb, 0.0f);
     for (int64_t i = 0; i < nb; ++i) h.diag32[i] = float(h.diag[i]);
+    if (h.sdir) {
+        const int wd = fvx::srec_width(d.stencil);
+        h.srec.assign(size_t(wd) * nb, 0.0);
+        for (int64_t r = 0; r < nb; ++r) {
+            double *o = &h.srec[size_t(r) * wd];
+            for (int e = 0; e < 8; ++e) o[e] = h.ell_val[size_t(e) * nb + r];
+            o[8] = h.diag[r];
+            o[9] = h.w[r];
+            if (d.stencil == 27)
+                for (int e = 0; e < 8; ++e) o[10 + e] = h.ell_v1[size_t(e) * nb + r];
+            else
+                o[10] = h.w2[r];
+        }
+    }
     return h;
 }
 
@@ -354,7 +372,7 @@ struct Layout {
 
 struct Offsets {
     size_t ell_col, cf_face, f_c1, f_c2, cart[2];
-    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2], dinv[2];
+    size_t diag[2], ell_val[2], w[2], cf_coef[2], area[2], f_invd[2], ell_v1[2], w2[2], dinv[2], srec[2];
     size_t fnx[2], fny[2], gsx[2], gsy[2], inv_area[2];
     size_t total;
 };
@@ -384,6 +402,7 @@ Offsets layout(const HostOp &h, bool f32) {
         o.gsy[p] = L.take(v * h.gsy.size());
         o.inv_area[p] = L.take(v * h.inv_area.size());
         o.cart[p] = L.take(v * h.cart.size());
+        o.srec[p] = L.take(v * h.srec.size());
     }
     o.total = L.off;
     return o;
@@ -626,16 +645,23 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
         }
         put(o.dinv[0], dinv.data(), 8 * nb);
         put(o.cart[0], h.cart.data(), 8 * h.cart.size());
+        put(o.srec[0], h.srec.data(), 8 * h.srec.size());
         for (auto pr : {std::make_pair(o.fnx[0], &h.fnx), std::make_pair(o.fny[0], &h.fny),
                         std::make_pair(o.gsx[0], &h.gsx), std::make_pair(o.gsy[0], &h.gsy),
                         std::make_pair(o.inv_area[0], &h.inv_area)})
             put(pr.first, pr.second->data(), 8 * pr.second->size());
         std::vector<float> nv32[5];
-        std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232, cart32;
+        std::vector<float> ev32, w32, cf32, ar32, fi32, v132, w232, cart32, srec32;
         if (f32) {
             cart32 = fvx::cast<float>(h.cart);
             for (size_t r = 0; r < cart32.size() / 8; ++r) cart32[r * 8] = h.diag32[r];  // the FP32 diagonal
             put(o.cart[1], cart32.data(), 4 * cart32.size());
+            srec32 = fvx::cast<float>(h.srec);
+            if (!h.srec.empty()) {
+                const size_t wd = h.srec.size() / nb;
+                for (size_t r = 0; r < nb; ++r) srec32[r * wd + 8] = h.diag32[r];  // the FP32 diagonal
+            }
+            put(o.srec[1], srec32.data(), 4 * srec32.size());
             v132 = fvx::cast<float>(h.ell_v1);
             w232 = fvx::cast<float>(h.w2);
             put(o.ell_v1[1], v132.data(), 4 * v132.size());
@@ -697,6 +723,7 @@ int fvx_op_create(const fvx_mesh *m, const fvx_op_desc *d, void *dev_mem, size_t
             D.inv_dz = T(1.0 / d->dz);
             D.ell_v1 = h.ell_v1.empty() ? nullptr : reinterpret_cast<const T *>(base + o.ell_v1[p]);
             D.w2 = h.w2.empty() ? nullptr : reinterpret_cast<const T *>(base + o.w2[p]);
+            D.srec = h.srec.empty() ? nullptr : reinterpret_cast<const T *>(base + o.srec[p]);
             D.dinv = reinterpret_cast<const T *>(base + o.dinv[p]);
             if (!h.cart.empty()) {
                 D.cart = reinterpret_cast<const T *>(base + o.cart[p]);

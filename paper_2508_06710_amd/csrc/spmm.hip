@@ -350,7 +350,10 @@ __global__ __launch_bounds__(512) void k_lap_stencil_passes(RowArgs<T> a, const 
 // loaded value are formed once and serve every line that reads it.  A
 // neighbour past a wall is read at the clamped cell, with coefficient 0 (the
 // ELL row holds the row itself there), so each term and the order of the
-// terms are those of stencil_apply: bitwise k_lap_stencil.
+// terms are those of stencil_apply: bitwise k_lap_stencil.  A row's
+// coefficients come from its packed record (a few wide scalar loads in place
+// of one per coefficient array): row 0's with the strip's loads, row q + 1's
+// while row q is computed.
 template <typename T, int V, bool E1, bool S2, bool NT, int R>
 __global__ __launch_bounds__(512) void k_stencil_lines(RowArgs<T> a, const T *__restrict__ X, T *__restrict__ Y,
                                                         int nx, int ny, int px, int py, uint32_t n_xtiles,
@@ -377,6 +380,14 @@ __global__ __launch_bounds__(512) void k_stencil_lines(RowArgs<T> a, const T *__
         const bool in_x = i_raw < uint32_t(nx);  // uniform over the wavefront
         const int i = in_x ? int(i_raw) : nx - 1;
         const int j0 = int(tj) * R;
+        constexpr int NC = E1 ? 18 : 11, NCP = srec_width(E1 ? 27 : 13);
+        T cf[2][NC];
+        auto load_coef = [&](int q, T(&c)[NC]) {
+            const int64_t base = (int64_t(min(j0 + q, ny - 1)) * nx + i) * NCP;
+#pragma unroll
+            for (int e = 0; e < NC; ++e) c[e] = ld_meta<true>(A.srec, base + e);
+        };
+        load_coef(0, cf[0]);
         vt acc[R];
         if constexpr (E1) {
             // 27-point: columns iW, i, iE of the lines j0 - 1 .. j0 + R
@@ -399,15 +410,16 @@ __global__ __launch_bounds__(512) void k_stencil_lines(RowArgs<T> a, const T *__
             }
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int64_t row = int64_t(min(j0 + q, ny - 1)) * nx + i;
+                if (q + 1 < R) load_coef(q + 1, cf[(q + 1) & 1]);
+                const T(&c)[NC] = cf[q & 1];
                 const vt *xs[8] = {&xw[q], &xc[q], &xe[q], &xw[q + 1], &xe[q + 1], &xw[q + 2], &xc[q + 2], &xe[q + 2]};
                 const vt *ss[8] = {&sw[q], &sc[q], &se[q], &sw[q + 1], &se[q + 1], &sw[q + 2], &sc[q + 2], &se[q + 2]};
-                vt s_ = ld_meta<true>(A.diag, row) * xc[q + 1];
+                vt s_ = c[8] * xc[q + 1];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_val, e * a.n_b + row), *xs[e], s_);
-                fma_into(ld_meta<true>(A.w, row), sc[q + 1], s_);
+                for (int e = 0; e < 8; ++e) fma_into(c[e], *xs[e], s_);
+                fma_into(c[9], sc[q + 1], s_);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_v1, e * a.n_b + row), *ss[e], s_);
+                for (int e = 0; e < 8; ++e) fma_into(c[10 + e], *ss[e], s_);
                 acc[q] = s_;
             }
         } else {
@@ -429,14 +441,15 @@ __global__ __launch_bounds__(512) void k_stencil_lines(RowArgs<T> a, const T *__
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int64_t row = int64_t(min(j0 + q, ny - 1)) * nx + i;
+                if (q + 1 < R) load_coef(q + 1, cf[(q + 1) & 1]);
+                const T(&c)[NC] = cf[q & 1];
                 const vt &xo = xc[q + 2];
                 const vt *xs[8] = {&xc[q], &xc[q + 1], &xww[q], &xw[q], &xe[q], &xee[q], &xc[q + 3], &xc[q + 4]};
-                vt s_ = ld_meta<true>(A.diag, row) * xo;
+                vt s_ = c[8] * xo;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) fma_into(ld_meta<true>(A.ell_val, e * a.n_b + row), *xs[e], s_);
-                fma_into(ld_meta<true>(A.w, row), shifts(xo, std::integral_constant<int, 1>{}), s_);
-                fma_into(ld_meta<true>(A.w2, row), shifts(xo, std::integral_constant<int, 2>{}), s_);
+                for (int e = 0; e < 8; ++e) fma_into(c[e], *xs[e], s_);
+                fma_into(c[9], shifts(xo, std::integral_constant<int, 1>{}), s_);
+                fma_into(c[10], shifts(xo, std::integral_constant<int, 2>{}), s_);
                 acc[q] = s_;
             }
         }
