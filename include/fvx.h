@@ -532,7 +532,8 @@ int fvx_amg_opts_default(fvx_amg_opts *opts);
 
 /* Builds the hierarchy of op (which must have been built from mesh m with
  * the finite-volume stencil, 7) on the host and returns the device bytes it
- * needs.  FVX_E_UNSUPPORTED for the 13/27-point operators. */
+ * needs (the coarsest pseudo-inverses are sized here and formed by
+ * fvx_amg_create).  FVX_E_UNSUPPORTED for the 13/27-point operators. */
 int fvx_amg_bytes(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *opts, size_t *bytes);
 /* Builds the hierarchy into dev_mem (256-byte aligned, >= fvx_amg_bytes);
  * the coarse operators carry FP32 copies when op does.  Copies on `stream`

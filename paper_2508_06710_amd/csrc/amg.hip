@@ -432,6 +432,7 @@ struct Plan {
     std::vector<size_t> op_bytes;
     std::vector<double> pinv;
     std::vector<double> phi;  // plane modes of coupled planes: the Fourier basis of the coarsest level's planes
+    size_t pinv_terms = 0, phi_terms = 0;  // their sizes (also when they are not formed)
     bool coupled = false;
     int n_d = 0;
     int modes = 0;  // coarsest per plane (mode): coupled floor(k/2) + 1 systems; independent planes 1, shared
@@ -448,7 +449,9 @@ void check_amg_opts(const fvx_amg_opts *o) {
     FVX_REQUIRE(o->mode_cells >= 0 && o->mode_cells <= kMaxAmgCoarse, FVX_E_ARG, "mode_cells must be 0..2048");
 }
 
-Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
+// form: compute the coarsest pseudo-inverses (false: their sizes only, for
+// fvx_amg_bytes).
+Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, bool form) {
     FVX_REQUIRE(m && op, FVX_E_ARG, "NULL mesh or operator");
     check_amg_opts(o);
     FVX_REQUIRE(op->stencil == 7, FVX_E_UNSUPPORTED, "the multigrid needs the 7-point finite-volume operator");
@@ -463,12 +466,13 @@ Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
     // per plane takes three).
     if (last.n * last.k > o->coarse_max && by_modes(last, P.coupled, *o)) {
         P.n_d = int(last.n);
-        if (P.coupled) {
-            P.modes = last.k / 2 + 1;
+        P.modes = P.coupled ? last.k / 2 + 1 : 1;
+        P.pinv_terms = size_t(P.modes) * size_t(last.n) * size_t(last.n);
+        P.phi_terms = P.coupled ? size_t(last.k) * size_t(last.k) : 0;
+        if (form && P.coupled) {
             P.pinv = mode_pinvs(last, op->singular, P.modes);
             P.phi = fourier_basis(last.k);
-        } else {
-            P.modes = 1;
+        } else if (form) {
             P.pinv = coarsest_pinv(last, false, op->singular);
         }
     } else {
@@ -476,7 +480,8 @@ Plan make_plan(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o) {
         FVX_REQUIRE(nd <= kMaxAmgCoarse, FVX_E_UNSUPPORTED,
                     "coarsening stopped above 2048 unknowns (raise max_levels or coarse_max)");
         P.n_d = int(nd);
-        P.pinv = coarsest_pinv(last, P.coupled, op->singular);
+        P.pinv_terms = size_t(nd) * size_t(nd);
+        if (form) P.pinv = coarsest_pinv(last, P.coupled, op->singular);
     }
     for (size_t l = 1; l < P.L.size(); ++l) {
         P.meshes.push_back(level_mesh(P.L[l], P.coupled));
@@ -497,9 +502,9 @@ size_t plan_bytes(const Plan &P, bool f32) {
     for (size_t b : P.op_bytes) off += align256(b);
     for (const auto &L : P.L)
         if (L.kind == 1) off += align256(4 * size_t(L.n)) * 2 + align256(4 * size_t(L.nc + 1));
-    off += align256(8 * P.pinv.size());
-    if (f32) off += align256(4 * P.pinv.size());
-    off += 2 * align256(8 * P.phi.size());
+    off += align256(8 * P.pinv_terms);
+    if (f32) off += align256(4 * P.pinv_terms);
+    off += 2 * align256(8 * P.phi_terms);
     return off;
 }
 
@@ -1115,7 +1120,7 @@ int fvx_amg_opts_default(fvx_amg_opts *o) {
 int fvx_amg_bytes(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, size_t *bytes) {
     return guard([&] {
         FVX_REQUIRE(bytes, FVX_E_ARG, "NULL bytes");
-        const fvx::Plan P = fvx::make_plan(m, op, o);
+        const fvx::Plan P = fvx::make_plan(m, op, o, false);
         *bytes = fvx::plan_bytes(P, op->has_f32);
         return FVX_OK;
     });
@@ -1127,7 +1132,9 @@ int fvx_amg_create(const fvx_mesh *m, const fvx_op *op, const fvx_amg_opts *o, v
         FVX_REQUIRE(out && dev_mem, FVX_E_ARG, "NULL output or device buffer");
         FVX_REQUIRE(reinterpret_cast<uintptr_t>(dev_mem) % 256 == 0, FVX_E_ARG,
                     "device buffer must be 256-byte aligned");
-        const fvx::Plan P = fvx::make_plan(m, op, o);
+        const fvx::Plan P = fvx::make_plan(m, op, o, true);
+        FVX_REQUIRE(P.pinv.size() == P.pinv_terms && P.phi.size() == P.phi_terms, FVX_E_ARG,
+                    "coarsest solve sizes disagree with the plan");
         const bool f32 = op->has_f32;
         const size_t need = fvx::plan_bytes(P, f32);
         FVX_REQUIRE(bytes >= need, FVX_E_NOMEM, "multigrid buffer too small: need " + std::to_string(need));
