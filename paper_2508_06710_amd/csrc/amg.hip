@@ -722,6 +722,60 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_fwd(const CgState *__
     mr[int64_t(j) * n_b + i] = s;
 }
 
+// The same transforms for at most kModeLdsK coupled planes with the basis
+// (32 KiB at 64 planes) and the block's cells staged in LDS: one round of
+// global loads per block, then the sums from LDS in the same order as above
+// (the same results bit for bit).  A block takes kDenseBlock / k cells.
+constexpr int kModeLdsK = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kDenseBlock) void k_amg_modes_fwd_lds(const CgState *__restrict__ st,
+                                                                   const double *__restrict__ phi_t, int n_b, int k,
+                                                                   int ld, const T *__restrict__ r,
+                                                                   double *__restrict__ mr) {
+    if (st->done) return;
+    __shared__ double sphi[kModeLdsK * kModeLdsK];
+    __shared__ double sx[kDenseBlock];
+    const int t = int(threadIdx.x), cpb = kDenseBlock / k;
+    const int64_t c0 = int64_t(blockIdx.x) * cpb;
+#pragma unroll 16
+    for (int u = t; u < k * k; u += kDenseBlock) sphi[u] = phi_t[u];
+    const int cc = t / k, q = t - cc * k;  // the block's cell, and the plane it loads / basis function it sums
+    const bool live = cc < cpb && c0 + cc < n_b;
+    if (live) sx[t] = double(r[(c0 + cc) * ld + q]);
+    __syncthreads();
+    if (!live) return;
+    const double *xc = sx + cc * k;
+    double s = 0.0;
+    for (int l = 0; l < k; ++l) s += sphi[l * k + q] * xc[l];
+    mr[int64_t(q) * n_b + c0 + cc] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kDenseBlock) void k_amg_modes_inv_lds(const CgState *__restrict__ st,
+                                                                   const double *__restrict__ phi, int n_b, int k,
+                                                                   int ld, const double *__restrict__ mz,
+                                                                   T *__restrict__ z) {
+    if (st->done) return;
+    __shared__ double sphi[kModeLdsK * kModeLdsK];
+    __shared__ double sx[kDenseBlock];
+    const int t = int(threadIdx.x), cpb = kDenseBlock / k;
+    const int64_t c0 = int64_t(blockIdx.x) * cpb;
+#pragma unroll 16
+    for (int u = t; u < k * k; u += kDenseBlock) sphi[u] = phi[u];
+    for (int u = t; u < cpb * k; u += kDenseBlock) {  // mz[j][c0 + cc] into sx[cc][j], consecutive cells per thread run
+        const int j = u / cpb, cc = u - j * cpb;
+        if (c0 + cc < n_b) sx[cc * k + j] = mz[int64_t(j) * n_b + c0 + cc];
+    }
+    __syncthreads();
+    const int cc = t / k, q = t - cc * k;  // the block's cell and the plane it writes
+    if (cc >= cpb || c0 + cc >= n_b) return;
+    const double *mc = sx + cc * k;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += sphi[j * k + q] * mc[j];
+    z[(c0 + cc) * ld + q] = T(s);
+}
+
 // Mode solves: rows i of a pseudo-inverse times two right-hand sides.
 // Coupled planes, unit u = mode m: mode m's pseudo-inverse, basis functions
 // 2m - 1 (cosine) and 2m (sine; mode 0 has basis function 0 alone, mode k/2
@@ -1030,12 +1084,22 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
             const dim3 tgrid(unsigned(ceil_div(outs, kDenseBlock)));
             const int units = h->coupled ? h->modes : (op->k + 1) / 2;
             const dim3 sgrid(unsigned(ceil_div(int64_t(units) * ((op->n_b + 1) / 2), kDenseBlock / 64)));
-            hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t, int(op->n_b),
-                               op->k, op->ld, rhs(nl - 1), w.mr);
+            const bool lds = h->phi && op->k <= kModeLdsK;
+            const dim3 lgrid(lds ? unsigned(ceil_div(op->n_b, kDenseBlock / op->k)) : 1u);
+            if (lds)
+                hipLaunchKernelGGL(k_amg_modes_fwd_lds<T>, lgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t,
+                                   int(op->n_b), op->k, op->ld, rhs(nl - 1), w.mr);
+            else
+                hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t,
+                                   int(op->n_b), op->k, op->ld, rhs(nl - 1), w.mr);
             hipLaunchKernelGGL(k_amg_modes_solve<T>, sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
                                int(op->n_b), op->k, units, int(!h->coupled), static_cast<const double *>(w.mr), w.mz);
-            hipLaunchKernelGGL(k_amg_modes_inv<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi, int(op->n_b),
-                               op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
+            if (lds)
+                hipLaunchKernelGGL(k_amg_modes_inv_lds<T>, lgrid, dim3(kDenseBlock), 0, s, d.st, h->phi,
+                                   int(op->n_b), op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
+            else
+                hipLaunchKernelGGL(k_amg_modes_inv<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi,
+                                   int(op->n_b), op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
         } else {
             const unsigned dense_grid = unsigned(h->coupled ? outs : ceil_div(outs, kDenseBlock / 64));
             hipLaunchKernelGGL(k_amg_dense<T>, dim3(dense_grid), dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
