@@ -777,6 +777,8 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_inv_lds(const CgState
 }
 
 // Mode solves: rows i of a pseudo-inverse times two right-hand sides.
+// PAIR (n_b even, so every row and right-hand side starts 16-byte aligned in
+// FP64): each lane takes two neighbouring terms per load.
 // Coupled planes, unit u = mode m: mode m's pseudo-inverse, basis functions
 // 2m - 1 (cosine) and 2m (sine; mode 0 has basis function 0 alone, mode k/2
 // of even k basis function k - 1 alone).  Independent planes (shared), unit
@@ -784,7 +786,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_inv_lds(const CgState
 // unit and pair of rows (2p, 2p + 1), 8 terms of each row per lane in
 // flight, the right-hand sides read once for both rows and each row once for
 // both right-hand sides.
-template <typename T>
+template <typename T, bool PAIR>
 __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *__restrict__ st,
                                                                  const T *__restrict__ pinv, int n_b, int k,
                                                                  int units, int shared,
@@ -806,16 +808,39 @@ __global__ __launch_bounds__(kDenseBlock) void k_amg_modes_solve(const CgState *
     const T *p1 = two ? p0 + n_b : p0;
     const double *rc = mr + int64_t(jc) * n_b, *rs = mr + int64_t(js) * n_b;
     double c0 = 0.0, s0 = 0.0, c1 = 0.0, s1 = 0.0;
-    for (int t0 = lane; t0 < n_b; t0 += 64 * 8) {
+    if constexpr (PAIR) {
+        using t2 = vec_t<T, 2>;
+        using d2 = vec_t<double, 2>;
+        const int h = n_b / 2;
+        for (int t0 = lane; t0 < h; t0 += 64 * 4) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int t = t0 + 64 * v;
-            if (t < n_b) {
-                const double a = double(p0[t]), b = double(p1[t]), x = rc[t], y = rs[t];
-                c0 += a * x;
-                s0 += a * y;
-                c1 += b * x;
-                s1 += b * y;
+            for (int v = 0; v < 4; ++v) {
+                const int t = t0 + 64 * v;
+                if (t < h) {
+                    const t2 a = reinterpret_cast<const t2 *>(p0)[t], b = reinterpret_cast<const t2 *>(p1)[t];
+                    const d2 x = reinterpret_cast<const d2 *>(rc)[t], y = reinterpret_cast<const d2 *>(rs)[t];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        c0 += double(a[e]) * x[e];
+                        s0 += double(a[e]) * y[e];
+                        c1 += double(b[e]) * x[e];
+                        s1 += double(b[e]) * y[e];
+                    }
+                }
+            }
+        }
+    } else {
+        for (int t0 = lane; t0 < n_b; t0 += 64 * 8) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int t = t0 + 64 * v;
+                if (t < n_b) {
+                    const double a = double(p0[t]), b = double(p1[t]), x = rc[t], y = rs[t];
+                    c0 += a * x;
+                    s0 += a * y;
+                    c1 += b * x;
+                    s1 += b * y;
+                }
             }
         }
     }
@@ -1092,8 +1117,14 @@ void amg_vcycle(const fvx_amg *h, const T *r0, const AmgWork<T> &w, const CgDev 
             else
                 hipLaunchKernelGGL(k_amg_modes_fwd<T>, tgrid, dim3(kDenseBlock), 0, s, d.st, h->phi_t,
                                    int(op->n_b), op->k, op->ld, rhs(nl - 1), w.mr);
-            hipLaunchKernelGGL(k_amg_modes_solve<T>, sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
-                               int(op->n_b), op->k, units, int(!h->coupled), static_cast<const double *>(w.mr), w.mz);
+            if (op->n_b % 2 == 0)
+                hipLaunchKernelGGL((k_amg_modes_solve<T, true>), sgrid, dim3(kDenseBlock), 0, s, d.st, pinv_of<T>(h),
+                                   int(op->n_b), op->k, units, int(!h->coupled), static_cast<const double *>(w.mr),
+                                   w.mz);
+            else
+                hipLaunchKernelGGL((k_amg_modes_solve<T, false>), sgrid, dim3(kDenseBlock), 0, s, d.st,
+                                   pinv_of<T>(h), int(op->n_b), op->k, units, int(!h->coupled),
+                                   static_cast<const double *>(w.mr), w.mz);
             if (lds)
                 hipLaunchKernelGGL(k_amg_modes_inv_lds<T>, lgrid, dim3(kDenseBlock), 0, s, d.st, h->phi,
                                    int(op->n_b), op->k, op->ld, static_cast<const double *>(w.mz), w.lv[nl - 1].q[0]);
