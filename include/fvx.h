@@ -494,10 +494,10 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   for coupled planes and u = ceil(k/2) for independent ones, is also the
  *   coarsest, and a coarsest level within both limits and above coarse_max
  *   unknowns is solved per plane: independent planes by the one n_b x n_b
- *   pseudo-inverse, two planes per row read; coupled planes per mode.
- *   Coupled planes are coupled
- *   periodically, so the real discrete Fourier basis along the planes splits
- *   it exactly into floor(k/2) + 1 systems A_b + (2 - 2 cos(2 pi m / k)) W of
+ *   pseudo-inverse, two planes per row read; coupled planes per mode.  Their
+ *   planes are coupled periodically, so the real discrete Fourier basis
+ *   along the planes splits the level exactly into floor(k/2) + 1 systems
+ *   A_b + (2 - 2 cos(2 pi m / k)) W of
  *   n_b unknowns (mode m; one right-hand side for m = 0 and m = k/2, a cosine
  *   and a sine one otherwise).  It is solved by the transform to the modes,
  *   the dense pseudo-inverse of every mode system (formed on the host in
@@ -514,8 +514,9 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   degree 2 on the way down); every one returns at once once the solve
  *   using the cycle has converged.
  * Ownership: dev_mem (fvx_amg_bytes) holds every coarse operator, the
- * aggregate maps and the coarsest pseudo-inverse; the caller keeps it and the
- * fine op alive until fvx_amg_destroy.  The hierarchy is immutable. */
+ * aggregate maps and the coarsest pseudo-inverse (or the plane modes'
+ * pseudo-inverses and the Fourier basis); the caller keeps it and the fine
+ * op alive until fvx_amg_destroy.  The hierarchy is immutable. */
 typedef struct fvx_amg_opts {
     int32_t degree;      /* Chebyshev smoothing steps before and after the coarse correction (2..8) */
     double ratio;        /* smoother interval [2 / ratio, 2] (> 1) */
