@@ -497,9 +497,9 @@ int fvx_poisson_solve_batch(int n, const fvx_op *const *ops, const double *const
  *   pseudo-inverse, two planes per row read; coupled planes per mode.  Their
  *   planes are coupled periodically, so the real discrete Fourier basis
  *   along the planes splits the level exactly into floor(k/2) + 1 systems
- *   A_b + (2 - 2 cos(2 pi m / k)) W of
- *   n_b unknowns (mode m; one right-hand side for m = 0 and m = k/2, a cosine
- *   and a sine one otherwise).  It is solved by the transform to the modes,
+ *   A_b + (2 - 2 cos(2 pi m / k)) W of n_b unknowns (mode m; one right-hand
+ *   side for m = 0 and m = k/2, a cosine and a sine one otherwise).  It is
+ *   solved by the transform to the modes,
  *   the dense pseudo-inverse of every mode system (formed on the host in
  *   FP64) and the transform back: the same pseudo-inverse of the whole level,
  *   in three launches and (floor(k/2) + 1) n_b^2 stored terms instead of
