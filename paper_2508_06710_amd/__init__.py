@@ -507,7 +507,11 @@ class Operator:
 class Amg:
     """Aggregation multigrid hierarchy of an operator (fvx_amg_*): every
     level an operator of the same repeated-block form.  Pass it to
-    Operator.solve(amg=...) to precondition CG with one V-cycle."""
+    Operator.solve(amg=...) to precondition CG with one V-cycle.
+    mode_cells (None: the library's default, 2048; 0: off) lets coarsening
+    stop at the first level of at most that many base cells whose solve per
+    plane mode fits the library's term budget; coarsest_modes reports how
+    that level is solved (0: one dense pseudo-inverse)."""
 
     def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=2048, max_levels=16,
                  mode_cells=None, stream=None):
