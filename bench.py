@@ -1353,7 +1353,7 @@ def pcg_leg(fvx, torch, op, D, rtol, err_of=None):
 def amg_leg(fvx, torch, inputs, op, D, rtol, err_of=None):
     """CG preconditioned by one V-cycle of the aggregation multigrid (default
     options: Chebyshev degree 2 on [2/8, 2], pairwise aggregation with beta
-    0.25, plane merging when the plane coupling dominates, coarsest level at
+    0.75, plane merging when the plane coupling dominates, coarsest level at
     most 2048 unknowns, or solved per plane mode at the first level whose
     modes hold at most 2^23 terms) on the benchmark's projection right-hand side, FP64 and
     mixed precision, the best of 3 timed solves each; the time of one V-cycle

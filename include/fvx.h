@@ -528,7 +528,7 @@ typedef struct fvx_amg_opts {
                             solved per plane mode (0: off; 0..2048) */
 } fvx_amg_opts;
 
-/* degree 2, ratio 8, beta 0.25, z_rule 1, coarse_max 2048, max_levels 16, mode_cells 2048. */
+/* degree 2, ratio 8, beta 0.75, z_rule 1, coarse_max 2048, max_levels 16, mode_cells 2048. */
 int fvx_amg_opts_default(fvx_amg_opts *opts);
 
 /* Builds the hierarchy of op (which must have been built from mesh m with

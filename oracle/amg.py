@@ -59,7 +59,7 @@ MODE_TERMS = 2 ** 23   # plane-mode pseudo-inverse terms a coarsest level may ho
 class AmgOpts:
     degree: int = 2
     ratio: float = 8.0
-    beta: float = 0.25
+    beta: float = 0.75
     z_rule: float = 1.0
     coarse_max: int = 2048
     max_levels: int = 16

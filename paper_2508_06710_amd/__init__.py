@@ -513,7 +513,7 @@ class Amg:
     plane mode fits the library's term budget; coarsest_modes reports how
     that level is solved (0: one dense pseudo-inverse)."""
 
-    def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.25, z_rule=1.0, coarse_max=2048, max_levels=16,
+    def __init__(self, op: Operator, degree=2, ratio=8.0, beta=0.75, z_rule=1.0, coarse_max=2048, max_levels=16,
                  mode_cells=None, stream=None):
         torch = _torch()
         if op.mesh is None:

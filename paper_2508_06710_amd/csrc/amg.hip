@@ -1204,7 +1204,7 @@ int fvx_amg_opts_default(fvx_amg_opts *o) {
     if (!o) return FVX_E_ARG;
     o->degree = 2;
     o->ratio = 8.0;
-    o->beta = 0.25;
+    o->beta = 0.75;
     o->z_rule = 1.0;
     o->coarse_max = 2048;
     o->max_levels = 16;
