@@ -222,3 +222,19 @@ def test_mesh_in_hilbert_order_renumbers_cells(fvx):
     e0 = sorted(tuple(sorted(e)) for e in zip(inv[f10], inv[f20]))
     e1 = sorted(tuple(sorted(e)) for e in zip(f11, f21))
     assert e0 == e1
+
+
+def test_multigrid_defaults(fvx):
+    """fvx_amg_opts_default against the values the header states, and the
+    oracle's defaults for the options both sides share (the oracle leaves
+    the plane-mode rule off unless asked: comparisons pass it)."""
+    from paper_2508_06710_amd import _lib
+    from oracle import amg as oamg
+    o = _lib.AmgOpts()
+    assert fvx.lib().fvx_amg_opts_default(C.byref(o)) == 0
+    got = (o.degree, o.ratio, o.beta, o.z_rule, o.coarse_max, o.max_levels, o.mode_cells)
+    assert got == (2, 8.0, 0.75, 1.0, 2048, 16, 2048)
+    d = oamg.AmgOpts()
+    assert (d.degree, d.ratio, d.beta, d.z_rule, d.coarse_max, d.max_levels) == got[:6]
+    assert d.mode_cells == 0
+    assert fvx.lib().fvx_amg_opts_default(None) != 0
