@@ -123,7 +123,7 @@ def test_one_v_cycle_matches_the_oracle(case, degree):
     assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("case", [CASES[0], MODE_CASES[0]], ids=["dense", "modes"])
+@pytest.mark.parametrize("case", [CASES[0], MODE_CASES[0], MODE_CASES[4]], ids=["dense", "modes", "modes-odd-cells"])
 def test_fp32_cycle_is_close_to_the_fp64_cycle(case):
     c, amg, h, coupled = _setup(*case)
     r = oracle.project_mean(inputs.rhs_uniform(111, c.m3.N), 1)
@@ -236,7 +236,8 @@ def test_amg_pcg_matches_dense_solve_and_repeats_bitwise():
     assert np.max(np.abs(x - xd)) <= 1e-9 * np.max(np.abs(xd))
 
 
-@pytest.mark.parametrize("case", [CASES[0], CASES[4], MODE_CASES[0]], ids=["coupled", "independent", "modes"])
+@pytest.mark.parametrize("case", [CASES[0], CASES[4], MODE_CASES[0], MODE_CASES[4], MODE_CASES[6]],
+                         ids=["coupled", "independent", "modes", "modes-odd-cells", "modes-independent"])
 def test_mixed_precision_with_amg(case):
     c, amg, h, coupled = _setup(*case)
     b = inputs.rhs_uniform(116, c.m3.N)
